@@ -1,0 +1,226 @@
+"""FP64 CPU oracle for the radiance-cascades formal solution and the non-LTE
+iteration around it (arXiv:2408.14425, Secs. 2-3).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path. It shares no code
+with the HIP library; only the seeded input generators are common.
+
+``liboracle.so`` is compiled from ``rc_oracle.c`` by ``__graft_entry__.build()``
+(or :func:`build_oracle`).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["rc_oracle.c"]
+
+
+def build_oracle(verbose: bool = False) -> str:
+    """Compile the C part of the oracle (plain gcc, FP64, OpenMP)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    tmp = _LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, *srcs, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Geom(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("nz", C.c_int32), ("n_casc", C.c_int32), ("c0_dirs", C.c_int32),
+        ("t1", C.c_double), ("t_rule", C.c_int32), ("pad_", C.c_int32), ("voxel", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build_oracle()
+        L = C.CDLL(_LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        gp = C.POINTER(Geom)
+        L.ora_t_start.restype = C.c_double
+        L.ora_t_start.argtypes = [gp, C.c_int32]
+        L.ora_level_dirs.restype = C.c_int32
+        L.ora_level_dirs.argtypes = [gp, C.c_int32]
+        L.ora_level_px.restype = C.c_int32
+        L.ora_level_px.argtypes = [gp, C.c_int32]
+        L.ora_level_pz.restype = C.c_int32
+        L.ora_level_pz.argtypes = [gp, C.c_int32]
+        L.ora_direction.restype = None
+        L.ora_direction.argtypes = [gp, C.c_int32, C.c_int32, dp, dp]
+        L.ora_segments.restype = C.c_int32
+        L.ora_segments.argtypes = [C.c_double] * 6 + [C.c_int32, C.c_int32, ip, ip, dp, C.c_int32]
+        L.ora_march.restype = None
+        L.ora_march.argtypes = [C.c_int32, dp, dp, dp, dp, dp]
+        L.ora_merge.restype = None
+        L.ora_merge.argtypes = [C.c_double] * 4 + [dp, dp]
+        L.ora_merge_level.restype = None
+        L.ora_merge_level.argtypes = [gp, C.c_int32, C.c_int32, dp, dp, dp, dp, C.c_void_p]
+        L.ora_formal_solve.restype = C.c_int32
+        L.ora_formal_solve.argtypes = [gp, C.c_int32, dp, dp, C.c_void_p, dp, C.c_void_p,
+                                       C.POINTER(C.c_int64), C.c_int32]
+        L.ora_level_intervals.restype = C.c_int64
+        L.ora_level_intervals.argtypes = [gp, C.c_int32, C.c_int32, dp, dp, dp, dp]
+        L.ora_lc_solve.restype = C.c_int32
+        L.ora_lc_solve.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                   dp, dp, dp, C.c_int32]
+        L.ora_lc_points.restype = C.c_int32
+        L.ora_lc_points.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, dp, dp,
+                                    C.c_int32, ip, ip, ip, dp, C.c_int32]
+        L.ora_num_threads.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def make_geom(nx: int, nz: int, n_casc: int, c0_dirs: int = 4, t1: float = 1.5,
+              t_rule: int = 0, voxel: float = 1.0) -> Geom:
+    return Geom(nx, nz, n_casc, c0_dirs, t1, t_rule, 0, voxel)
+
+
+def t_start(g: Geom, i: int) -> float:
+    return lib().ora_t_start(C.byref(g), i)
+
+
+def level_shape(g: Geom, i: int) -> tuple[int, int, int]:
+    """(probes z, probes x, directions) of cascade i."""
+    L = lib()
+    return (L.ora_level_pz(C.byref(g), i), L.ora_level_px(C.byref(g), i),
+            L.ora_level_dirs(C.byref(g), i))
+
+
+def direction(g: Geom, i: int, k: int) -> tuple[float, float]:
+    wx, wz = C.c_double(), C.c_double()
+    lib().ora_direction(C.byref(g), i, k, C.byref(wx), C.byref(wz))
+    return wx.value, wz.value
+
+
+def segments(cx, cz, wx, wz, ta, tb, nx, nz):
+    """Segments of a ray, near -> far: (cell x, cell z, length in cells)."""
+    m = nx + nz + 8
+    sx = np.zeros(m, np.int32)
+    sz = np.zeros(m, np.int32)
+    dt = np.zeros(m, np.float64)
+    n = lib().ora_segments(cx, cz, wx, wz, ta, tb, nx, nz,
+                           sx.ctypes.data_as(C.POINTER(C.c_int32)),
+                           sz.ctypes.data_as(C.POINTER(C.c_int32)), _dp(dt), m)
+    if n < 0:
+        raise RuntimeError("segment buffer overflow")
+    return sx[:n].copy(), sz[:n].copy(), dt[:n].copy()
+
+
+def march(chi, eta, ds):
+    """Back-to-front piecewise-constant solution over segments ordered near -> far."""
+    chi, eta, ds = _f64(chi), _f64(eta), _f64(ds)
+    I, tau = C.c_double(), C.c_double()
+    lib().ora_march(len(ds), _dp(chi), _dp(eta), _dp(ds), C.byref(I), C.byref(tau))
+    return I.value, tau.value
+
+
+def merge(near, far):
+    """Merge operator on (I, tau) pairs; ``near`` is the interval nearer the probe."""
+    I, tau = C.c_double(), C.c_double()
+    lib().ora_merge(near[0], near[1], far[0], far[1], C.byref(I), C.byref(tau))
+    return I.value, tau.value
+
+
+def merge_level(g: Geom, i: int, I_i, tau_i, I_up, need=None):
+    """Merge cascade i (raw) with merged cascade i+1; arrays [n_wave][pz][px][dirs]."""
+    I_i, tau_i = _f64(I_i), _f64(tau_i)
+    out = np.zeros_like(I_i)
+    up = None if I_up is None else _f64(I_up)
+    nm = None if need is None else np.ascontiguousarray(need, dtype=np.uint8)
+    lib().ora_merge_level(C.byref(g), i, I_i.shape[0], _dp(I_i), _dp(tau_i),
+                          None if up is None else _dp(up), _dp(out),
+                          None if nm is None else nm.ctypes.data)
+    return out
+
+
+def formal_solve(chi, eta, n_casc: int, voxel: float = 1.0, c0_dirs: int = 4, t1: float = 1.5,
+                 t_rule: int = 0, need=None, want_I0: bool = False, n_threads: int = 0):
+    """RC formal solve in FP64. chi, eta: [n_wave][nz][nx]. Returns J (and the
+    merged cascade-0 radiance [n_wave][nz][nx][N_0] if ``want_I0``) and stats
+    (rays, non-empty rays, cell steps)."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    nw, nz, nx = chi.shape
+    g = make_geom(nx, nz, n_casc, c0_dirs, t1, t_rule, voxel)
+    J = np.zeros((nw, nz, nx))
+    I0 = np.zeros((nw, nz, nx, c0_dirs)) if want_I0 else None
+    st = np.zeros(3, np.int64)
+    nm = None if need is None else np.ascontiguousarray(need, dtype=np.uint8)
+    rc = lib().ora_formal_solve(C.byref(g), nw, _dp(chi), _dp(eta),
+                                None if nm is None else nm.ctypes.data, _dp(J),
+                                None if I0 is None else I0.ctypes.data,
+                                st.ctypes.data_as(C.POINTER(C.c_int64)), n_threads)
+    if rc != 0:
+        raise RuntimeError(f"ora_formal_solve failed ({rc})")
+    out = {"J": J, "rays": int(st[0]), "nonempty": int(st[1]), "steps": int(st[2])}
+    if want_I0:
+        out["I0"] = I0
+    return out
+
+
+def level_intervals(g: Geom, i: int, chi, eta):
+    """Raw (I, tau) of every interval of cascade i; [n_wave][pz][px][dirs]."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    pz, px, nd = level_shape(g, i)
+    I = np.zeros((chi.shape[0], pz, px, nd))
+    tau = np.zeros_like(I)
+    lib().ora_level_intervals(C.byref(g), i, chi.shape[0], _dp(chi), _dp(eta), _dp(I), _dp(tau))
+    return I, tau
+
+
+def lc_solve(chi, eta, M: int, voxel: float = 1.0, n_threads: int = 0):
+    """Long-characteristics J with M uniformly spaced directions per cell."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    nw, nz, nx = chi.shape
+    J = np.zeros((nw, nz, nx))
+    lib().ora_lc_solve(nx, nz, voxel, M, nw, _dp(chi), _dp(eta), _dp(J), n_threads)
+    return J
+
+
+def lc_points(chi, eta, M: int, pts, voxel: float = 1.0, n_threads: int = 0):
+    """Long-characteristics J at selected (x, z, wavelength index) triples."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    nw, nz, nx = chi.shape
+    pts = np.asarray(pts, dtype=np.int32).reshape(-1, 3)
+    px, pz, pl = (np.ascontiguousarray(pts[:, j]) for j in range(3))
+    J = np.zeros(len(pts))
+    ip = C.POINTER(C.c_int32)
+    lib().ora_lc_points(nx, nz, voxel, M, nw, _dp(chi), _dp(eta), len(pts),
+                        px.ctypes.data_as(ip), pz.ctypes.data_as(ip), pl.ctypes.data_as(ip),
+                        _dp(J), n_threads)
+    return J
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())

@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs for the radiance-cascades solver.
+
+This module is shared by the tests, the benchmark and the oracle harness. It
+only draws and shapes random fields; it contains none of the method's
+arithmetic (no ray marching, merging, rates or populations).
+
+All fields are built in float64 with ``numpy.random.default_rng(seed)``
+(PCG64) and rounded to float32, the precision the GPU path consumes. The
+oracle receives the same float32 values widened to float64, so that parity
+measures solver error and not input rounding.
+
+Layout: row-major with x fastest, fields ``[n_wave][nz][nx]``. Cell (x, z)
+occupies [x, x+1) x [z, z+1) in cell units; its centre is (x+1/2, z+1/2).
+
+The paper's own production input (a 2.5D MHD prominence snapshot, Sec. 4.1)
+is not available; these generators stand in for it with the same shape
+class: uniform 2D grids with optically thick structures embedded in thin
+surroundings, a line-profile-shaped opacity over wavelength, and smooth
+source functions.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+# Second radiation constant h c / k_B [m K], used only to shape a smooth,
+# Planck-like source-function input for the multi-wavelength workload.
+_C2_RAD = 1.4388e-2
+
+
+def n_cascades_for(nx: int, nz: int) -> int:
+    """Default cascade count for a grid: ceil(log4(max(nx, nz))) + 2.
+
+    Reproduces 5 cascades at 64^2 and 7 at 1024^2 (the paper's scaling law,
+    Eq. RcScalingLaw, with alpha = 2 and t_1 = 1.5 cells).
+    """
+    m = max(int(nx), int(nz))
+    k = 0
+    while 4 ** k < m:
+        k += 1
+    return k + 2
+
+
+def grf(rng: np.random.Generator, shape: tuple[int, int], corr_len: float) -> np.ndarray:
+    """Gaussian random field: white noise filtered in Fourier space by a
+    Gaussian kernel of correlation length ``corr_len`` cells, standardised to
+    zero mean and unit variance (periodic)."""
+    nz, nx = shape
+    noise = rng.standard_normal(shape)
+    kz = np.fft.fftfreq(nz)[:, None]
+    kx = np.fft.fftfreq(nx)[None, :]
+    filt = np.exp(-2.0 * (math.pi * corr_len) ** 2 * (kx * kx + kz * kz))
+    f = np.fft.ifft2(np.fft.fft2(noise) * filt).real
+    f -= f.mean()
+    sd = f.std()
+    return f / sd if sd > 0 else f
+
+
+@dataclass
+class FormalSolveInput:
+    """chi, eta: float32 ``[n_wave][nz][nx]``; voxel_scale: length of one cell
+    in the units chi is given per."""
+    chi: np.ndarray
+    eta: np.ndarray
+    voxel_scale: float
+    n_cascades: int
+    name: str
+
+    @property
+    def nx(self) -> int:
+        return int(self.chi.shape[2])
+
+    @property
+    def nz(self) -> int:
+        return int(self.chi.shape[1])
+
+    @property
+    def n_wave(self) -> int:
+        return int(self.chi.shape[0])
+
+
+def blobs_medium(n: int = 64, seed: int = 1, n_blobs: int = 3) -> FormalSolveInput:
+    """Single-wavelength medium on an n x n grid: opacity log-uniform in
+    [1e-3, 1e1] per cell plus ``n_blobs`` optically thick Gaussian blobs of
+    peak 1e3 (centres uniform in [n/8, 7n/8]^2, widths uniform in [2, 5]
+    cells); a smooth sinusoidal source function in [0.5, 2]; eta = chi * S.
+
+    At n = 64, seed = 1 this is the 64^2, 1-wavelength, 5-cascade formal-solve
+    parity workload.
+    """
+    rng = np.random.default_rng(seed)
+    chi = 10.0 ** rng.uniform(-3.0, 1.0, size=(n, n))
+    zc, xc = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5, indexing="ij")
+    for _ in range(n_blobs):
+        cx, cz = rng.uniform(n / 8.0, 7.0 * n / 8.0, size=2)
+        sig = rng.uniform(2.0, 5.0)
+        chi = chi + 1e3 * np.exp(-((xc - cx) ** 2 + (zc - cz) ** 2) / (2.0 * sig * sig))
+    phx, phz = rng.uniform(0.0, 2.0 * math.pi, size=2)
+    src = 1.25 + 0.75 * np.sin(2 * math.pi * xc / n + phx) * np.sin(2 * math.pi * zc / n + phz)
+    chi32 = chi.astype(np.float32)
+    eta32 = (chi32.astype(np.float64) * src).astype(np.float32)
+    return FormalSolveInput(chi32[None], eta32[None], 1.0, n_cascades_for(n, n),
+                            f"blobs{n}x{n}_s{seed}")
+
+
+def line_medium(n: int = 1024, n_wave: int = 64, seed: int = 2, nz: int | None = None,
+                wave_subset: np.ndarray | None = None) -> FormalSolveInput:
+    """Multi-wavelength medium: a log-normal density rho = exp(1.5 GRF(32)),
+    a Gaussian line-profile opacity over wavelength with 0.1 .. 1e4 contrast
+    (kappa_w = 0.1 + 1e4 exp(-x_w^2), x_w spanning [-4, 4]), chi = 1e-2 rho
+    kappa_w per cell, a temperature T = 6000 + 2000 tanh(GRF(128)) K and a
+    Planck-ratio source function S = (e^{c2/(l0 T0)} - 1)/(e^{c2/(l0 T)} - 1)
+    at l0 = 500 nm, T0 = 6000 K; eta = chi * S.
+
+    At n = 1024, n_wave = 64, seed = 2 this is the 1024^2, 64-wavelength,
+    7-cascade formal-solve workload. ``wave_subset`` selects wavelength
+    indices out of the ``n_wave`` grid (same fields, fewer wavelengths).
+    """
+    nz = n if nz is None else nz
+    rng = np.random.default_rng(seed)
+    rho = np.exp(1.5 * grf(rng, (nz, n), 32.0 * n / 1024.0 if n < 1024 else 32.0))
+    temp = 6000.0 + 2000.0 * np.tanh(grf(rng, (nz, n), 128.0 * n / 1024.0 if n < 1024 else 128.0))
+    lam0, t0 = 500e-9, 6000.0
+    src = np.expm1(_C2_RAD / (lam0 * t0)) / np.expm1(_C2_RAD / (lam0 * temp))
+    waves = np.arange(n_wave) if wave_subset is None else np.asarray(wave_subset)
+    half = 0.5 * (n_wave - 1)
+    xw = (waves - half) / (half if half > 0 else 1.0) * 4.0
+    kappa = 0.1 + 1e4 * np.exp(-xw * xw)
+    chi = np.empty((len(waves), nz, n), dtype=np.float32)
+    eta = np.empty_like(chi)
+    for i, k in enumerate(kappa):
+        c = (1e-2 * rho * k).astype(np.float32)
+        chi[i] = c
+        eta[i] = (c.astype(np.float64) * src).astype(np.float32)
+    return FormalSolveInput(chi, eta, 1.0, n_cascades_for(n, nz), f"line{n}x{nz}_w{n_wave}_s{seed}")
+
+
+def disc_in_vacuum(n: int = 256, radius: float = 4.0, chi_disc: float = 1e3,
+                   src: float = 1.0) -> FormalSolveInput:
+    """Opaque pixelised disc in vacuum at the grid centre: every cell whose
+    centre lies within ``radius`` of the centre gets chi = ``chi_disc``,
+    eta = chi * ``src``; everything else is empty (chi = eta = 0)."""
+    zc, xc = np.meshgrid(np.arange(n) + 0.5, np.arange(n) + 0.5, indexing="ij")
+    r = np.hypot(xc - n / 2.0, zc - n / 2.0)
+    inside = r <= radius
+    chi = np.where(inside, chi_disc, 0.0).astype(np.float32)
+    eta = np.where(inside, chi_disc * src, 0.0).astype(np.float32)
+    return FormalSolveInput(chi[None], eta[None], 1.0, n_cascades_for(n, n), f"disc{n}_r{radius}")
+
+
+def uneven_batch(seed: int = 4, n_atm: int = 16, sizes=None, waves=None):
+    """List of (side, n_wave, atmosphere seed) for a batch of independent
+    line-medium atmospheres of uneven size: sides uniform on multiples of 128
+    in [256, 2048], wavelength counts uniform on multiples of 32 in [32, 256].
+    """
+    rng = np.random.default_rng(seed)
+    sizes = list(range(256, 2049, 128)) if sizes is None else list(sizes)
+    waves = list(range(32, 257, 32)) if waves is None else list(waves)
+    out = []
+    for a in range(n_atm):
+        out.append((int(rng.choice(sizes)), int(rng.choice(waves)), 4000 + a))
+    return out

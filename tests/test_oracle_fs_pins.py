@@ -1,0 +1,440 @@
+"""Pins of the FP64 formal-solve oracle against what the paper and the
+mathematics fix (no GPU). Each test names the passage it checks.
+
+A plausible mistake in the oracle -- a swapped merge, a wrong interval start,
+an off-by-one cell, a transposed axis, a wrong tap weight or child index --
+fails at least one of these.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_14425_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- geometry
+
+
+def test_ray_counts_match_paper_identity():
+    """Sec. 2.4: with alpha = 2 in 2D every cascade holds N_C0 rays."""
+    for case in _golden("ray_counts.json")["cases"]:
+        n, I = case["n"], case["n_cascades"]
+        assert W.n_cascades_for(n, n) == I
+        g = oracle.make_geom(n, n, I)
+        counts = [np.prod(oracle.level_shape(g, i)) for i in range(I)]
+        assert all(c == case["N_C0"] for c in counts)
+        assert sum(counts) == case["computed"]
+        pz, px, nd_top = oracle.level_shape(g, I - 1)
+        assert n * n * nd_top == case["constructed"]
+
+
+def test_interval_starts_scaling_law():
+    """Eq. RcScalingLaw: t_0 = 0, t_1 = 1.5, x4 per cascade, top to infinity."""
+    ts = _golden("interval_starts.json")["t_cells"]
+    g = oracle.make_geom(1024, 1024, 7)
+    for i, t in enumerate(ts[:7]):
+        assert oracle.t_start(g, i) == t
+    assert math.isinf(oracle.t_start(g, 7))
+
+
+def test_child_cones_nest_in_parent():
+    """Sec. 2.3.1: the 2 alpha = 4 children of ray k of cascade i lie inside its cone."""
+    g = oracle.make_geom(64, 64, 5)
+    for i in range(4):
+        nd = oracle.level_shape(g, i)[2]
+        for k in range(nd):
+            lo, hi = 2 * math.pi * k / nd, 2 * math.pi * (k + 1) / nd
+            for j in range(4):
+                wx, wz = oracle.direction(g, i + 1, 4 * k + j)
+                th = math.atan2(wz, wx) % (2 * math.pi)
+                assert lo < th < hi
+
+
+def test_interval_lengths_in_homogeneous_medium():
+    """Per-cascade optical depth of an unclipped interior interval is chi (t_{i+1} - t_i)."""
+    n = 256
+    chi = np.full((1, n, n), 0.01)
+    eta = np.zeros_like(chi)
+    g = oracle.make_geom(n, n, 6)
+    ts = _golden("interval_starts.json")["t_cells"]
+    for i in range(4):
+        I, tau = oracle.level_intervals(g, i, chi, eta)
+        pz, px, nd = oracle.level_shape(g, i)
+        c = tau[0, pz // 2, px // 2]  # probe near the centre: unclipped up to cascade 3
+        np.testing.assert_allclose(c, 0.01 * (ts[i + 1] - ts[i]), rtol=1e-12)
+
+
+# ------------------------------------------------------------ segmentation
+
+
+def _sample_cells(cx, cz, wx, wz, lo, hi, nx, nz, n_samp):
+    t = lo + (np.arange(n_samp) + 0.5) * (hi - lo) / n_samp
+    x = cx + t * wx
+    z = cz + t * wz
+    inside = (x >= 0) & (x < nx) & (z >= 0) & (z < nz)
+    return np.floor(x[inside]).astype(int), np.floor(z[inside]).astype(int), (hi - lo) / n_samp
+
+
+def test_segments_against_dense_sampling():
+    """Sec. 3.2: piecewise-constant cells along the ray; lengths per cell
+    agree with 1e6-point sampling, midpoints lie in their cells."""
+    rng = np.random.default_rng(0)
+    nx, nz = 13, 9
+    for _ in range(40):
+        cx, cz = rng.uniform(-3, nx + 3), rng.uniform(-3, nz + 3)
+        th = rng.uniform(0, 2 * math.pi)
+        wx, wz = math.cos(th), math.sin(th)
+        ta = rng.uniform(0, 4)
+        tb = ta + rng.uniform(0.1, 25)
+        sx, sz, dt = oracle.segments(cx, cz, wx, wz, ta, tb, nx, nz)
+        # midpoints inside their cells
+        t = ta
+        lengths = {}
+        # rebuild the clipped start by sampling: first inside sample
+        xs, zs, h = _sample_cells(cx, cz, wx, wz, ta, tb, nx, nz, 1_000_000)
+        for a, b in zip(xs, zs):
+            lengths[(a, b)] = lengths.get((a, b), 0.0) + h
+        seg = {}
+        for a, b, d in zip(sx, sz, dt):
+            seg[(int(a), int(b))] = seg.get((int(a), int(b)), 0.0) + d
+        assert set(k for k, v in lengths.items() if v > 1e-4) <= set(seg)
+        for key in seg:
+            assert abs(seg[key] - lengths.get(key, 0.0)) < 5e-5
+        assert abs(dt.sum() - len(xs) * h) < 5e-5
+        assert np.all(dt > 0)
+
+
+def test_segments_exact_diagonal_through_corner():
+    """Cascade-0 diagonal rays from a cell centre pass through the cell corner:
+    sqrt(2)/2 in the own cell, 1.5 - sqrt(2)/2 in the diagonal neighbour."""
+    s = math.sqrt(0.5)
+    sx, sz, dt = oracle.segments(3.5, 3.5, s, s, 0.0, 1.5, 8, 8)
+    per = {}
+    for a, b, d in zip(sx, sz, dt):
+        per[(int(a), int(b))] = per.get((int(a), int(b)), 0.0) + d
+    assert abs(per[(3, 3)] - s) < 1e-12
+    assert abs(per[(4, 4)] - (1.5 - s)) < 1e-12
+    assert sum(v for k, v in per.items() if k not in [(3, 3), (4, 4)]) < 1e-12
+
+
+# -------------------------------------------------------------- march / merge
+
+
+def test_march_single_cell_closed_form():
+    """Sec. 3.2: one homogeneous cell gives I = S (1 - e^{-chi L}), tau = chi L."""
+    for chi, S, L in [(0.3, 2.0, 1.7), (50.0, 0.7, 0.2), (1e-9, 3.0, 2.0)]:
+        I, tau = oracle.march([chi], [chi * S], [L])
+        assert abs(I - S * (-math.expm1(-chi * L))) <= 1e-14 * max(1, abs(I))
+        assert abs(tau - chi * L) <= 1e-14 * tau
+
+
+def test_march_thin_and_opaque_limits():
+    eta = np.array([0.5, 1.0, 2.0])
+    ds = np.array([0.1, 0.3, 0.7])
+    I, tau = oracle.march(np.zeros(3), eta, ds)
+    assert abs(I - (eta * ds).sum()) < 1e-15 and tau == 0.0
+    # opaque first (nearest) cell: only its source function is seen
+    I, _ = oracle.march([1e4, 1.0, 1.0], [1e4 * 0.25, 5.0, 5.0], [1.0, 1.0, 1.0])
+    assert abs(I - 0.25) < 1e-14
+
+
+def test_march_two_cells_formal_solution():
+    """Formal solution I = int S e^{-tau} dtau for piecewise-constant media:
+    the near cell attenuates the far one."""
+    c1, S1, L1, c2, S2, L2 = 0.8, 1.5, 0.6, 2.5, 0.4, 1.1
+    want = S1 * (1 - math.exp(-c1 * L1)) + math.exp(-c1 * L1) * S2 * (1 - math.exp(-c2 * L2))
+    I, tau = oracle.march([c1, c2], [c1 * S1, c2 * S2], [L1, L2])
+    assert abs(I - want) < 1e-14
+    assert abs(tau - (c1 * L1 + c2 * L2)) < 1e-14
+
+
+def test_merge_worked_example():
+    """Sec. 2.2.1: a near interval of transmission 1/2 halves the far radiance."""
+    I, tau = oracle.merge((1.0, math.log(2.0)), (4.0, 0.3))
+    assert abs(I - 3.0) < 1e-15
+    assert abs(tau - (math.log(2.0) + 0.3)) < 1e-15
+
+
+def test_merge_split_invariance():
+    """Eq. RabMerge + merge operator: march[a,c] = M(march[a,b], march[b,c])."""
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        n = rng.integers(2, 12)
+        chi = 10 ** rng.uniform(-2, 1, n)
+        eta = chi * rng.uniform(0.1, 3, n)
+        ds = rng.uniform(0.05, 1.5, n)
+        b = rng.integers(1, n)
+        whole = oracle.march(chi, eta, ds)
+        near = oracle.march(chi[:b], eta[:b], ds[:b])
+        far = oracle.march(chi[b:], eta[b:], ds[b:])
+        m = oracle.merge(near, far)
+        assert abs(m[0] - whole[0]) <= 1e-13 * whole[0]
+        assert abs(m[1] - whole[1]) <= 1e-13 * whole[1]
+        # associativity
+        if b + 1 < n:
+            mid = oracle.march(chi[b:b + 1], eta[b:b + 1], ds[b:b + 1])
+            rest = oracle.march(chi[b + 1:], eta[b + 1:], ds[b + 1:])
+            m2 = oracle.merge(oracle.merge(near, mid), rest)
+            assert abs(m2[0] - whole[0]) <= 1e-13 * whole[0]
+
+
+def _level_arrays(g, i, n_wave=1):
+    pz, px, nd = oracle.level_shape(g, i)
+    return np.zeros((n_wave, pz, px, nd))
+
+
+def test_merge_partition_of_unity():
+    """Constant upper cascade, empty lower intervals: the merged field equals
+    the constant everywhere, grid edges included (clamped taps keep weights)."""
+    for n in (16, 20):
+        g = oracle.make_geom(n, n, 4)
+        for i in range(3):
+            Ii = _level_arrays(g, i)
+            up = _level_arrays(g, i + 1) + 1.75
+            out = oracle.merge_level(g, i, Ii, Ii, up)
+            np.testing.assert_array_equal(out, 1.75)
+
+
+def test_merge_energy_conservation():
+    """With tau = 0 and even probe counts each upper (probe, direction) entry
+    is distributed with total weight exactly 1: sum merged = sum lower + sum upper."""
+    rng = np.random.default_rng(5)
+    g = oracle.make_geom(32, 32, 5)
+    for i in range(4):
+        Ii = rng.uniform(0, 1, _level_arrays(g, i).shape)
+        up = rng.uniform(0, 1, _level_arrays(g, i + 1).shape)
+        out = oracle.merge_level(g, i, Ii, np.zeros_like(Ii), up)
+        np.testing.assert_allclose(out.sum(), Ii.sum() + up.sum(), rtol=1e-13)
+
+
+def test_merge_bilinear_reproduces_linear_field():
+    """Sec. 2.3.1: bilinear interpolation is exact for a field linear in the
+    probe position (interior probes, away from the clamped edge)."""
+    g = oracle.make_geom(64, 64, 5)
+    for i in range(3):
+        pz, px, nd = oracle.level_shape(g, i + 1)
+        s_up = 2.0 ** (i + 1)
+        zc = (np.arange(pz) + 0.5) * s_up
+        xc = (np.arange(px) + 0.5) * s_up
+        field = 0.3 + 0.02 * xc[None, :] - 0.05 * zc[:, None]
+        up = np.repeat(field[None, :, :, None], nd, axis=3)
+        Ii = _level_arrays(g, i)
+        out = oracle.merge_level(g, i, Ii, Ii, up)
+        s = 2.0 ** i
+        qz, qx, _ = oracle.level_shape(g, i)
+        zl = (np.arange(qz) + 0.5) * s
+        xl = (np.arange(qx) + 0.5) * s
+        want = 0.3 + 0.02 * xl[None, :] - 0.05 * zl[:, None]
+        inner = slice(2, -2)
+        np.testing.assert_allclose(out[0, inner, inner, 0], want[inner, inner], rtol=1e-13, atol=1e-14)
+
+
+def test_merge_children_angular_average():
+    """Sec. 2.3.1: ray k of cascade i averages children 4k..4k+3. For an upper
+    field cos(theta) the merged value is cos(theta_k) times the mean of
+    cos((j - 3/2) d) over the four children, d the child spacing."""
+    g = oracle.make_geom(32, 32, 4)
+    for i in range(3):
+        pz, px, nd_up = oracle.level_shape(g, i + 1)
+        th_up = 2 * math.pi * (np.arange(nd_up) + 0.5) / nd_up
+        up = np.broadcast_to(2.0 + np.cos(th_up), (1, pz, px, nd_up)).copy()
+        Ii = _level_arrays(g, i)
+        out = oracle.merge_level(g, i, Ii, Ii, up)
+        nd = nd_up // 4
+        th = 2 * math.pi * (np.arange(nd) + 0.5) / nd
+        d = 2 * math.pi / nd_up
+        fac = np.mean([math.cos((j - 1.5) * d) for j in range(4)])
+        np.testing.assert_allclose(out[0, 3, 3], 2.0 + np.cos(th) * fac, rtol=1e-13)
+
+
+def test_merge_attenuates_far_by_near_transmission():
+    Ii = None
+    g = oracle.make_geom(8, 8, 2)
+    Ii = _level_arrays(g, 0) + 0.5
+    tau = _level_arrays(g, 0) + math.log(4.0)
+    up = _level_arrays(g, 1) + 2.0
+    out = oracle.merge_level(g, 0, Ii, tau, up)
+    np.testing.assert_allclose(out, 0.5 + 0.25 * 2.0, rtol=1e-15)
+
+
+# -------------------------------------------------------- full formal solve
+
+
+def test_homogeneous_thick_medium_J_equals_S():
+    """RTE in a homogeneous optically thick medium: J = S away from the edge."""
+    n = 32
+    chi = np.full((1, n, n), 20.0)
+    eta = chi * 0.7
+    J = oracle.formal_solve(chi, eta, W.n_cascades_for(n, n))["J"][0]
+    np.testing.assert_allclose(J[3:-3, 3:-3], 0.7, rtol=1e-12)
+
+
+def test_single_cascade_equals_four_ray_long_characteristics():
+    """With one cascade (t_1 = infinity) RC is discrete-ordinates long
+    characteristics with the N_0 = 4 cascade-0 directions."""
+    inp = W.blobs_medium(16, seed=7)
+    Jrc = oracle.formal_solve(inp.chi, inp.eta, 1)["J"]
+    Jlc = oracle.lc_solve(inp.chi, inp.eta, 4)
+    np.testing.assert_allclose(Jrc, Jlc, rtol=1e-13)
+
+
+def _fine_rte(chi, eta, cx, cz, wx, wz, h=2e-4):
+    """Independent RTE integration along a ray by uniform sub-steps of length h,
+    each cell looked up at the sub-step centre (no segmentation logic)."""
+    nz, nx = chi.shape
+    tx = ((0 if wx < 0 else nx) - cx) / wx
+    tz = ((0 if wz < 0 else nz) - cz) / wz
+    L = min(tx, tz)
+    n = int(math.ceil(L / h))
+    t = (np.arange(n) + 0.5) * (L / n)
+    ix = np.clip(np.floor(cx + t * wx).astype(int), 0, nx - 1)
+    iz = np.clip(np.floor(cz + t * wz).astype(int), 0, nz - 1)
+    c = chi[iz, ix]
+    e = eta[iz, ix]
+    dtau = c * (L / n)
+    tau_before = np.concatenate([[0.0], np.cumsum(dtau)[:-1]])
+    with np.errstate(invalid="ignore", divide="ignore"):
+        contrib = np.where(dtau > 0, e / np.where(c > 0, c, 1) * -np.expm1(-dtau), e * (L / n))
+    return float(np.sum(contrib * np.exp(-tau_before)))
+
+
+def test_long_characteristics_against_fine_sampling():
+    """Brute force on a tiny grid: the LC solver (same segmentation and march as
+    the cascades) matches a sub-step integration of the RTE."""
+    inp = W.blobs_medium(8, seed=11, n_blobs=1)
+    chi, eta = inp.chi[0].astype(np.float64), inp.eta[0].astype(np.float64)
+    M = 16
+    pts = [(2, 3, 0), (6, 1, 0), (4, 4, 0)]
+    Jlc = oracle.lc_points(chi, eta, M, pts)
+    for (x, z, _), jl in zip(pts, Jlc):
+        acc = 0.0
+        for m in range(M):
+            th = 2 * math.pi * (m + 0.5) / M
+            acc += _fine_rte(chi, eta, x + 0.5, z + 0.5, math.cos(th), math.sin(th))
+        assert abs(acc / M - jl) <= 2e-3 * jl
+
+
+def test_d4_symmetry():
+    """Square power-of-two grid: the probe grid, the direction set and the
+    bilinear taps are symmetric under rotations/reflections, so J is too."""
+    inp = W.blobs_medium(32, seed=4, n_blobs=2)
+    I = 4
+    J = oracle.formal_solve(inp.chi, inp.eta, I)["J"]
+    for k in (1, 2, 3):
+        Jr = oracle.formal_solve(np.rot90(inp.chi, k, axes=(1, 2)),
+                                 np.rot90(inp.eta, k, axes=(1, 2)), I)["J"]
+        np.testing.assert_allclose(Jr, np.rot90(J, k, axes=(1, 2)), rtol=1e-12)
+    for ax in (1, 2):
+        Jf = oracle.formal_solve(np.flip(inp.chi, ax), np.flip(inp.eta, ax), I)["J"]
+        np.testing.assert_allclose(Jf, np.flip(J, ax), rtol=1e-12)
+
+
+def test_linearity_in_eta():
+    rng = np.random.default_rng(9)
+    inp = W.blobs_medium(16, seed=2)
+    e1 = inp.chi * rng.uniform(0, 2, inp.chi.shape)
+    e2 = inp.chi * rng.uniform(0, 2, inp.chi.shape)
+    I = 4
+    J1 = oracle.formal_solve(inp.chi, e1, I)["J"]
+    J2 = oracle.formal_solve(inp.chi, e2, I)["J"]
+    J12 = oracle.formal_solve(inp.chi, 0.3 * e1 + 1.7 * e2, I)["J"]
+    np.testing.assert_allclose(J12, 0.3 * J1 + 1.7 * J2, rtol=1e-13)
+
+
+def test_occluding_ring_blocks_far_field():
+    """An opaque, non-emitting ring around a cell hides everything beyond it:
+    J of the enclosed cell is its own emission, S (1 - e^{-chi sqrt(2)/2})."""
+    n = 32
+    chi = np.full((n, n), 0.05)
+    eta = chi * 3.0
+    c = 15
+    chi[c - 1:c + 2, c - 1:c + 2] = 1e4
+    eta[c - 1:c + 2, c - 1:c + 2] = 0.0
+    chi[c, c], eta[c, c] = 0.4, 0.4 * 1.3
+    J = oracle.formal_solve(chi, eta, W.n_cascades_for(n, n))["J"][0]
+    want = 1.3 * -math.expm1(-0.4 * math.sqrt(0.5))
+    assert abs(J[c, c] - want) < 1e-13
+
+
+def _disc_true_J(x, z, centre, R, n_dir=200_000):
+    """Exact flatland J at (x, z) for an opaque, S = 1 pixelised disc: the
+    fraction of directions whose ray hits any disc cell (ray/box tests)."""
+    th = 2 * math.pi * (np.arange(n_dir) + 0.5) / n_dir
+    wx, wz = np.cos(th), np.sin(th)
+    hit = np.zeros(n_dir, bool)
+    lo = int(centre - R - 1)
+    hi = int(centre + R + 1)
+    for cz in range(lo, hi + 1):
+        for cx in range(lo, hi + 1):
+            if math.hypot(cx + 0.5 - centre, cz + 0.5 - centre) > R:
+                continue
+            with np.errstate(divide="ignore", invalid="ignore"):
+                t1 = (cx - x) / wx
+                t2 = (cx + 1 - x) / wx
+                t3 = (cz - z) / wz
+                t4 = (cz + 1 - z) / wz
+            tmin = np.maximum(np.minimum(t1, t2), np.minimum(t3, t4))
+            tmax = np.minimum(np.maximum(t1, t2), np.maximum(t3, t4))
+            hit |= (tmax > np.maximum(tmin, 0)) & (tmax - np.maximum(tmin, 0) > 1e-3)
+    return hit.mean()
+
+
+def test_point_source_falloff():
+    """Sec. 2.5, Fig. CircleTest: an opaque disc (hundreds of mean free paths
+    per cell) in vacuum; J falls off as 1/r. Basic RC rings around the exact
+    answer where cascades meet (parallax between probes of neighbouring
+    cascades): typically a few per cent, a little over 10% at worst in the
+    paper's test. Here the mean error over the cuts stays below 8% and no
+    point exceeds 30% (cascade-boundary spikes on the diagonal)."""
+    n, R = 256, 4.0
+    d = W.disc_in_vacuum(n, R)
+    J = oracle.formal_solve(d.chi, d.eta, d.n_cascades)["J"][0]
+    rs = np.array([16, 24, 32, 48, 64, 80, 96])
+    all_rel = []
+    for ang in (0.0, 45.0, 90.0):
+        vals, truth = [], []
+        for r in rs:
+            x = int(n / 2 + r * math.cos(math.radians(ang)))
+            z = int(n / 2 + r * math.sin(math.radians(ang)))
+            vals.append(J[z, x])
+            truth.append(_disc_true_J(x + 0.5, z + 0.5, n / 2, R))
+        vals, truth = np.array(vals), np.array(truth)
+        all_rel.extend(vals / truth - 1)
+        slope = np.polyfit(np.log(rs), np.log(vals), 1)[0]
+        assert -1.1 < slope < -0.9, slope
+    all_rel = np.abs(np.array(all_rel))
+    assert all_rel.mean() < 0.08, all_rel
+    assert all_rel.max() < 0.30, all_rel
+
+
+def test_long_characteristics_converge_to_true_disc_J():
+    """LC with many directions converges to the exact flatland J of the disc."""
+    n, R = 128, 4.0
+    d = W.disc_in_vacuum(n, R)
+    pts = [(n // 2 + 20, n // 2, 0), (n // 2 + 14, n // 2 + 14, 0)]
+    Jl = oracle.lc_points(d.chi, d.eta, 65536, pts)
+    for (x, z, _), jl in zip(pts, Jl):
+        assert abs(jl / _disc_true_J(x + 0.5, z + 0.5, n / 2, R) - 1) < 5e-3
+
+
+def test_dependency_cone_matches_full_solve():
+    """Computing J at selected cells through their dependency cone only gives
+    the same values as the full solve."""
+    inp = W.line_medium(64, 3, seed=5)
+    full = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    need = np.zeros((64, 64), np.uint8)
+    need[[3, 40, 63], [0, 22, 63]] = 1
+    part = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades, need=need)["J"]
+    m = need.astype(bool)
+    np.testing.assert_array_equal(part[:, m], full[:, m])
