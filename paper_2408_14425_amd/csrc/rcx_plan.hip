@@ -1,0 +1,341 @@
+// rcx_plan.hip -- host side of librcx: plans, cascade geometry, work counts
+// and the orchestration of one formal solve (Osborne & Sannikov,
+// arXiv:2408.14425, Secs. 2.3-2.4 and 3.2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rcx_internal.h"
+
+namespace rcx {
+
+namespace {
+thread_local int32_t g_last_code = RCX_OK;
+thread_local char g_last_msg[512] = "";
+}  // namespace
+
+int32_t fail(int32_t code, const std::string& msg)
+{
+    g_last_code = code;
+    std::snprintf(g_last_msg, sizeof(g_last_msg), "%s", msg.c_str());
+    return code;
+}
+
+int32_t hip_fail(hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+    return fail(RCX_E_HIP, m);
+}
+
+static int32_t ok()
+{
+    g_last_code = RCX_OK;
+    g_last_msg[0] = 0;
+    return RCX_OK;
+}
+
+}  // namespace rcx
+
+using namespace rcx;
+
+struct rcx_plan {
+    rcx_grid grid;
+    rcx_params prm;
+    int32_t max_wave;
+    int32_t n_casc;
+    int32_t top_skipped;
+    std::vector<LevelDesc> levels;
+    std::vector<int32_t> dir_off;  // offset of cascade i's directions in the table
+    std::vector<double4> dirs_host;
+    double4* dirs_dev = nullptr;
+    void* ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    bool work_done = false;
+    rcx_work work;
+};
+
+namespace {
+
+double t_start(const rcx_params& p, int32_t n_casc, int32_t i)
+{
+    if (i <= 0) return 0.0;
+    if (i >= n_casc) return INFINITY;
+    if (p.t_rule == RCX_T_LENGTH_X4) return p.c0_t1 * (std::ldexp(1.0, 2 * i) - 1.0) / 3.0;
+    return p.c0_t1 * std::ldexp(1.0, 2 * (i - 1));
+}
+
+int32_t auto_cascades(int32_t nx, int32_t nz)
+{
+    int32_t m = std::max(nx, nz), k = 0;
+    while ((int64_t(1) << (2 * k)) < m) ++k;
+    return k + 2;
+}
+
+int64_t level_entries(const LevelDesc& L) { return (int64_t)L.px * L.pz * L.nd; }
+
+// Largest distance from any probe of a cascade to any corner of the domain:
+// a cascade whose interval starts beyond it has only empty rays.
+double max_probe_corner_distance(const rcx_grid& g, const LevelDesc& L)
+{
+    double best = 0.0;
+    const double us[2] = {0.5 * L.s, (L.px - 0.5) * L.s};
+    const double vs[2] = {0.5 * L.s, (L.pz - 0.5) * L.s};
+    const double xs[2] = {0.0, (double)g.nx};
+    const double zs[2] = {0.0, (double)g.nz};
+    for (double u : us)
+        for (double v : vs)
+            for (double x : xs)
+                for (double z : zs) best = std::max(best, std::hypot(u - x, v - z));
+    return best;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct WsLayout {
+    size_t F, casc_a, casc_b, total;
+};
+
+WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
+{
+    WsLayout w{};
+    const int64_t ncell = (int64_t)p->grid.nx * p->grid.nz;
+    int64_t max_entries = 0;
+    for (const auto& L : p->levels) max_entries = std::max(max_entries, level_entries(L));
+    w.F = 0;
+    w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_wave);
+    w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * n_wave);
+    w.total = w.casc_b + align256(sizeof(float) * (size_t)max_entries * n_wave);
+    return w;
+}
+
+// Exact per-ray work on the host: number of segments the kernel's cell walk
+// produces = plane crossings strictly inside the clipped interval + 1.
+void count_work(rcx_plan* p)
+{
+    rcx_work& w = p->work;
+    std::memset(&w, 0, sizeof(w));
+    w.n_cascades = p->n_casc;
+    w.top_skipped = p->top_skipped;
+    const int32_t nx = p->grid.nx, nz = p->grid.nz;
+    for (int32_t i = 0; i < p->n_casc; ++i) {
+        const LevelDesc& L = p->levels[i];
+        int64_t rays = level_entries(L), nonempty = 0, steps = 0;
+        if (!(p->top_skipped && i == p->n_casc - 1)) {
+            for (int32_t v = 0; v < L.pz; ++v)
+                for (int32_t u = 0; u < L.px; ++u) {
+                    const double cx = (u + 0.5) * L.s, cz = (v + 0.5) * L.s;
+                    for (int32_t k = 0; k < L.nd; ++k) {
+                        const double4 d = p->dirs_host[p->dir_off[i] + k];
+                        double ax = (0.0 - cx) * d.z, bx = ((double)nx - cx) * d.z;
+                        double az = (0.0 - cz) * d.w, bz = ((double)nz - cz) * d.w;
+                        double lo = std::max(L.ta, std::max(std::min(ax, bx), std::min(az, bz)));
+                        double hi = std::min(L.tb, std::min(std::max(ax, bx), std::max(az, bz)));
+                        if (!(lo < hi)) continue;
+                        ++nonempty;
+                        double x0 = cx + lo * d.x, x1 = cx + hi * d.x;
+                        double z0 = cz + lo * d.y, z1 = cz + hi * d.y;
+                        int64_t nxc = d.x > 0 ? (int64_t)std::ceil(x1) - 1 - (int64_t)std::floor(x0)
+                                              : (int64_t)std::ceil(x0) - 1 - (int64_t)std::floor(x1);
+                        int64_t nzc = d.y > 0 ? (int64_t)std::ceil(z1) - 1 - (int64_t)std::floor(z0)
+                                              : (int64_t)std::ceil(z0) - 1 - (int64_t)std::floor(z1);
+                        steps += std::max<int64_t>(nxc, 0) + std::max<int64_t>(nzc, 0) + 1;
+                    }
+                }
+        }
+        if (i < 16) {
+            w.level_rays[i] = rays;
+            w.level_steps[i] = steps;
+        }
+        w.rays_all += rays;
+        w.rays_nonempty += nonempty;
+        w.cell_steps += steps;
+    }
+    p->work_done = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rcx_params_default(rcx_params* p)
+{
+    if (!p) return fail(RCX_E_INVALID, "rcx_params_default: null");
+    p->n_cascades = 0;
+    p->c0_dirs = 4;
+    p->c0_t1 = 1.5;
+    p->t_rule = RCX_T_GEOMETRIC;
+    p->storage = RCX_STORE_F32;
+    p->n_incl = 1;
+    p->flags = 0;
+    return ok();
+}
+
+int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wave, rcx_plan** out)
+{
+    if (out) *out = nullptr;
+    if (!g || !prm || !out) return fail(RCX_E_INVALID, "rcx_plan_create: null argument");
+    if (g->nx <= 0 || g->nz <= 0 || max_wave <= 0)
+        return fail(RCX_E_INVALID, "rcx_plan_create: nx, nz and max_wave must be positive");
+    if (!(g->voxel_scale > 0.0)) return fail(RCX_E_INVALID, "rcx_plan_create: voxel_scale must be > 0");
+    if (prm->c0_dirs <= 0 || !(prm->c0_t1 > 0.0))
+        return fail(RCX_E_INVALID, "rcx_plan_create: c0_dirs and c0_t1 must be positive");
+    if (prm->t_rule != RCX_T_GEOMETRIC && prm->t_rule != RCX_T_LENGTH_X4)
+        return fail(RCX_E_INVALID, "rcx_plan_create: unknown t_rule");
+    if (prm->storage != RCX_STORE_F32) return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
+    if (prm->n_incl != 1) return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: only n_incl = 1 (flatland)");
+    int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
+    if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
+    if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: too many directions on the top cascade");
+
+    rcx_plan* p = new (std::nothrow) rcx_plan();
+    if (!p) return fail(RCX_E_NOMEM, "rcx_plan_create: host allocation");
+    p->grid = *g;
+    p->prm = *prm;
+    p->prm.n_cascades = n_casc;
+    p->max_wave = max_wave;
+    p->n_casc = n_casc;
+    p->levels.resize(n_casc);
+    p->dir_off.resize(n_casc);
+    int32_t off = 0;
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        const int32_t s = 1 << i;
+        L.px = (g->nx + s - 1) / s;
+        L.pz = (g->nz + s - 1) / s;
+        L.nd = prm->c0_dirs << (2 * i);
+        L.s = (double)s;
+        L.ta = t_start(*prm, n_casc, i);
+        L.tb = t_start(*prm, n_casc, i + 1);
+        L.max_steps = g->nx + g->nz + 4;
+        p->dir_off[i] = off;
+        // Cone centres theta = 2 pi (k + 1/2) / N_i (children 4k..4k+3 nest).
+        for (int32_t k = 0; k < L.nd; ++k) {
+            const double th = 2.0 * M_PI * (k + 0.5) / (double)L.nd;
+            const double wx = std::cos(th), wz = std::sin(th);
+            p->dirs_host.push_back(make_double4(wx, wz, 1.0 / wx, 1.0 / wz));
+        }
+        off += L.nd;
+    }
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        if (i + 1 < n_casc) {
+            L.qx = p->levels[i + 1].px;
+            L.qz = p->levels[i + 1].pz;
+            L.nd_up = p->levels[i + 1].nd;
+        }
+    }
+    const LevelDesc& top = p->levels[n_casc - 1];
+    p->top_skipped = (n_casc > 1 && top.ta >= max_probe_corner_distance(*g, top)) ? 1 : 0;
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        L.has_up = (i + 1 < n_casc) && !(p->top_skipped && i + 1 == n_casc - 1);
+    }
+
+    hipError_t e = hipMalloc(&p->dirs_dev, sizeof(double4) * p->dirs_host.size());
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc(directions)");
+    }
+    e = hipMemcpy(p->dirs_dev, p->dirs_host.data(), sizeof(double4) * p->dirs_host.size(),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rcx_plan_destroy(p);
+        return hip_fail(e, "hipMemcpy(directions)");
+    }
+    p->ws_own_bytes = ws_layout(p, max_wave).total;
+    e = hipMalloc(&p->ws_own, p->ws_own_bytes);
+    if (e != hipSuccess) {
+        p->ws_own = nullptr;
+        rcx_plan_destroy(p);
+        return fail(RCX_E_NOMEM, std::string("rcx_plan_create: workspace hipMalloc: ") + hipGetErrorName(e));
+    }
+    *out = p;
+    return ok();
+}
+
+int32_t rcx_plan_workspace_bytes(const rcx_plan* p, int32_t n_wave, size_t* bytes)
+{
+    if (!p || !bytes) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: null argument");
+    if (n_wave <= 0) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: n_wave must be positive");
+    *bytes = ws_layout(p, n_wave).total;
+    return ok();
+}
+
+int32_t rcx_plan_work(rcx_plan* p, rcx_work* out)
+{
+    if (!p || !out) return fail(RCX_E_INVALID, "rcx_plan_work: null argument");
+    if (!p->work_done) count_work(p);
+    *out = p->work;
+    return ok();
+}
+
+int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                         void* workspace, size_t ws_bytes, hipStream_t st)
+{
+    if (!p || !chi || !eta || !J) return fail(RCX_E_INVALID, "rcx_formal_solve: null argument");
+    if (n_wave <= 0 || n_wave > p->max_wave)
+        return fail(RCX_E_INVALID, "rcx_formal_solve: n_wave must be in [1, max_wave]");
+    const WsLayout w = ws_layout(p, n_wave);
+    char* ws = (char*)workspace;
+    if (!ws) {
+        ws = (char*)p->ws_own;
+    } else if (ws_bytes < w.total) {
+        return fail(RCX_E_WORKSPACE, "rcx_formal_solve: workspace smaller than rcx_plan_workspace_bytes");
+    }
+    const int32_t nx = p->grid.nx, nz = p->grid.nz;
+    const int64_t ncell = (int64_t)nx * nz;
+    float2* F = (float2*)(ws + w.F);
+    float* bufs[2] = {(float*)(ws + w.casc_a), (float*)(ws + w.casc_b)};
+
+    RCX_HIP_TRY(launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, st));
+    int cur = 0;
+    const float* up = nullptr;
+    for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+        if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
+        const LevelDesc& L = p->levels[i];
+        float* outb = bufs[cur];
+        RCX_HIP_TRY(launch_march_merge(L, nx, nz, n_wave, F, p->dirs_dev + p->dir_off[i],
+                                       L.has_up ? up : nullptr, outb, st));
+        up = outb;
+        cur ^= 1;
+    }
+    RCX_HIP_TRY(launch_j(up, J, n_wave, ncell, p->prm.c0_dirs, st));
+    return ok();
+}
+
+int32_t rcx_plan_destroy(rcx_plan* p)
+{
+    if (!p) return ok();
+    if (p->dirs_dev) (void)hipFree(p->dirs_dev);
+    if (p->ws_own) (void)hipFree(p->ws_own);
+    delete p;
+    return ok();
+}
+
+const char* rcx_error_string(int32_t code)
+{
+    switch (code) {
+    case RCX_OK: return "ok";
+    case RCX_W_NOT_CONVERGED: return "not converged within the iteration limit";
+    case RCX_E_INVALID: return "invalid argument";
+    case RCX_E_UNSUPPORTED: return "unsupported configuration";
+    case RCX_E_NOMEM: return "out of memory";
+    case RCX_E_HIP: return "HIP runtime error";
+    case RCX_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status code";
+    }
+}
+
+int32_t rcx_last_error(char* buf, size_t n)
+{
+    if (buf && n > 0) std::snprintf(buf, n, "%s", g_last_msg);
+    return g_last_code;
+}
+
+}  // extern "C"

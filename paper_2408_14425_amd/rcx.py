@@ -1,0 +1,204 @@
+"""ctypes binding of librcx (``include/rcx.h``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels. Device arrays are passed as ``torch.Tensor`` (their ``data_ptr()``)
+and work is enqueued on the tensor's current HIP stream. Loading fails loudly
+when ``librcx.so`` has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librcx.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rcx.h")
+
+RCX_OK = 0
+RCX_W_NOT_CONVERGED = 1
+RCX_E_INVALID = -1
+RCX_E_UNSUPPORTED = -2
+RCX_E_NOMEM = -3
+RCX_E_HIP = -4
+RCX_E_WORKSPACE = -5
+RCX_T_GEOMETRIC = 0
+RCX_T_LENGTH_X4 = 1
+RCX_STORE_F32 = 0
+
+
+class rcx_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nz", C.c_int32), ("voxel_scale", C.c_double)]
+
+
+class rcx_params(C.Structure):
+    _fields_ = [("n_cascades", C.c_int32), ("c0_dirs", C.c_int32), ("c0_t1", C.c_double),
+                ("t_rule", C.c_int32), ("storage", C.c_int32), ("n_incl", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class rcx_work(C.Structure):
+    _fields_ = [("n_cascades", C.c_int32), ("top_skipped", C.c_int32), ("rays_all", C.c_int64),
+                ("rays_nonempty", C.c_int64), ("cell_steps", C.c_int64),
+                ("level_rays", C.c_int64 * 16), ("level_steps", C.c_int64 * 16)]
+
+
+class RcxError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load librcx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, sz = C.c_void_p, C.c_int32, C.c_size_t
+    L.rcx_params_default.argtypes = [C.POINTER(rcx_params)]
+    L.rcx_plan_create.argtypes = [C.POINTER(rcx_grid), C.POINTER(rcx_params), i32, C.POINTER(vp)]
+    L.rcx_plan_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+    L.rcx_plan_work.argtypes = [vp, C.POINTER(rcx_work)]
+    L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
+    L.rcx_plan_destroy.argtypes = [vp]
+    L.rcx_error_string.argtypes = [i32]
+    L.rcx_error_string.restype = C.c_char_p
+    L.rcx_last_error.argtypes = [C.c_char_p, sz]
+    for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
+                 "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error"):
+        getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        buf = C.create_string_buffer(512)
+        load().rcx_last_error(buf, 512)
+        raise RcxError(rc, where, buf.value.decode() or load().rcx_error_string(rc).decode())
+    return rc
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype_name: str, what: str) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != dtype_name:
+        raise ValueError(f"{what} must be a contiguous {dtype_name} tensor on the GPU")
+    return int(t.data_ptr())
+
+
+# ------------------------------------------------------------- raw C names
+
+
+def rcx_params_default() -> rcx_params:
+    p = rcx_params()
+    _check(load().rcx_params_default(C.byref(p)), "rcx_params_default")
+    return p
+
+
+def rcx_plan_create(grid: rcx_grid, params: rcx_params, max_wave: int) -> int:
+    h = C.c_void_p()
+    _check(load().rcx_plan_create(C.byref(grid), C.byref(params), int(max_wave), C.byref(h)),
+           "rcx_plan_create")
+    return h.value
+
+
+def rcx_plan_workspace_bytes(plan: int, n_wave: int) -> int:
+    b = C.c_size_t()
+    _check(load().rcx_plan_workspace_bytes(plan, int(n_wave), C.byref(b)), "rcx_plan_workspace_bytes")
+    return int(b.value)
+
+
+def rcx_plan_work(plan: int) -> rcx_work:
+    w = rcx_work()
+    _check(load().rcx_plan_work(plan, C.byref(w)), "rcx_plan_work")
+    return w
+
+
+def rcx_formal_solve(plan: int, n_wave: int, chi, eta, J, workspace=None, stream=None) -> int:
+    ws_ptr = _dev_ptr(workspace, "torch.uint8", "workspace")
+    ws_bytes = 0 if workspace is None else workspace.numel()
+    return _check(load().rcx_formal_solve(plan, int(n_wave), _dev_ptr(chi, "torch.float32", "chi"),
+                                          _dev_ptr(eta, "torch.float32", "eta"),
+                                          _dev_ptr(J, "torch.float32", "J"), ws_ptr or None,
+                                          ws_bytes, _stream_ptr(stream)), "rcx_formal_solve")
+
+
+def rcx_plan_destroy(plan: int) -> int:
+    return _check(load().rcx_plan_destroy(plan), "rcx_plan_destroy")
+
+
+def rcx_error_string(code: int) -> str:
+    return load().rcx_error_string(int(code)).decode()
+
+
+def rcx_last_error() -> tuple[int, str]:
+    buf = C.create_string_buffer(512)
+    code = load().rcx_last_error(buf, 512)
+    return code, buf.value.decode()
+
+
+# ------------------------------------------------------------ convenience
+
+
+@dataclass
+class Work:
+    n_cascades: int
+    top_skipped: bool
+    rays_all: int
+    rays_nonempty: int
+    cell_steps: int
+    level_rays: list
+    level_steps: list
+
+
+class Plan:
+    """Owns an ``rcx_plan`` for one grid and up to ``max_wave`` wavelengths."""
+
+    def __init__(self, nx: int, nz: int, max_wave: int, voxel_scale: float = 1.0,
+                 n_cascades: int = 0, c0_dirs: int = 4, c0_t1: float = 1.5,
+                 t_rule: int = RCX_T_GEOMETRIC, storage: int = RCX_STORE_F32):
+        p = rcx_params_default()
+        p.n_cascades, p.c0_dirs, p.c0_t1, p.t_rule, p.storage = n_cascades, c0_dirs, c0_t1, t_rule, storage
+        self.nx, self.nz, self.max_wave = nx, nz, max_wave
+        self.handle = rcx_plan_create(rcx_grid(nx, nz, voxel_scale), p, max_wave)
+
+    def work(self) -> Work:
+        w = rcx_plan_work(self.handle)
+        n = w.n_cascades
+        return Work(n, bool(w.top_skipped), w.rays_all, w.rays_nonempty, w.cell_steps,
+                    list(w.level_rays[:n]), list(w.level_steps[:n]))
+
+    def workspace_bytes(self, n_wave: int) -> int:
+        return rcx_plan_workspace_bytes(self.handle, n_wave)
+
+    def formal_solve(self, chi, eta, J=None, workspace=None, stream=None):
+        import torch
+        n_wave = chi.shape[0]
+        if J is None:
+            J = torch.empty_like(chi)
+        rcx_formal_solve(self.handle, n_wave, chi, eta, J, workspace, stream)
+        return J
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rcx_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,61 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the GPU."""
+import ctypes as C
+import re
+
+import pytest
+
+from paper_2408_14425_amd import rcx
+
+
+def _declared_functions():
+    text = open(rcx.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(rcx_[a-z0-9_]+|nlte_[a-z0-9_]+|mlp_[a-z0-9_]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rcx.load()
+    names = _declared_functions()
+    assert "rcx_formal_solve" in names and "rcx_plan_create" in names
+    for n in names:
+        assert hasattr(L, n), f"librcx.so does not export {n}"
+
+
+def test_error_strings():
+    assert rcx.rcx_error_string(0) == "ok"
+    assert "invalid" in rcx.rcx_error_string(rcx.RCX_E_INVALID)
+    assert rcx.rcx_error_string(-99) == "unknown status code"
+
+
+@pytest.mark.parametrize("nx,nz,mw", [(0, 8, 1), (8, -1, 1), (8, 8, 0)])
+def test_plan_create_rejects_bad_sizes(nx, nz, mw):
+    p = rcx.rcx_params_default()
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(nx, nz, 1.0), p, mw)
+    assert e.value.code == rcx.RCX_E_INVALID
+
+
+def test_plan_create_rejects_unsupported():
+    p = rcx.rcx_params_default()
+    p.n_incl = 8
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(8, 8, 1.0), p, 1)
+    assert e.value.code == rcx.RCX_E_UNSUPPORTED
+    p = rcx.rcx_params_default()
+    p.n_cascades = 17
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(8, 8, 1.0), p, 1)
+    assert e.value.code == rcx.RCX_E_INVALID
+    code, msg = rcx.rcx_last_error()
+    assert code == rcx.RCX_E_INVALID and "n_cascades" in msg
+
+
+def test_null_arguments_are_rejected():
+    L = rcx.load()
+    assert L.rcx_plan_create(None, None, 1, None) == rcx.RCX_E_INVALID
+    assert L.rcx_formal_solve(None, 1, None, None, None, None, 0, None) == rcx.RCX_E_INVALID
+    assert L.rcx_plan_destroy(None) == rcx.RCX_OK
+    assert L.rcx_params_default(None) == rcx.RCX_E_INVALID

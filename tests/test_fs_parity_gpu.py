@@ -1,0 +1,141 @@
+"""GPU formal solve vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerance: 1e-4 relative per cell on J for the FP32 path (every term of the
+march and merge is non-negative once 1 - e^{-x} is evaluated stably, so FP32
+error grows at most linearly in the number of steps: ~1e-5 for the longest
+rays here).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_14425_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-4
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gpu_solve(inp, n_cascades=0, t_rule=0, workspace=False):
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    print(f"[gpu] formal solve {inp.name} n_cascades={n_cascades or inp.n_cascades} t_rule={t_rule}",
+          flush=True)
+    plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, voxel_scale=inp.voxel_scale, n_cascades=n_cascades,
+                    t_rule=t_rule)
+    chi = torch.from_numpy(inp.chi).cuda()
+    eta = torch.from_numpy(inp.eta).cuda()
+    ws = None
+    if workspace:
+        ws = torch.empty(plan.workspace_bytes(inp.n_wave), dtype=torch.uint8, device="cuda")
+    J = plan.formal_solve(chi, eta, workspace=ws)
+    torch.cuda.synchronize()
+    out = J.cpu().numpy().astype(np.float64)
+    plan.close()
+    return out
+
+
+def _assert_rel(Jg, Jo, rtol=RTOL):
+    rel = np.abs(Jg - Jo) / np.maximum(np.abs(Jo), 1e-300)
+    worst = np.unravel_index(np.argmax(rel), rel.shape)
+    assert rel.max() <= rtol, f"max rel err {rel.max():.3e} at {worst}: gpu {Jg[worst]} oracle {Jo[worst]}"
+    return rel.max()
+
+
+def test_blobs_64_single_wavelength_full_field():
+    """64^2, 1 wavelength, 5 cascades: every cell."""
+    inp = W.blobs_medium(64, seed=1)
+    Jg = _gpu_solve(inp)
+    Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    print("max rel", _assert_rel(Jg, Jo))
+
+
+def test_line_medium_256_eight_wavelengths_full_field():
+    """Reduced multi-wavelength workload: 256^2, 8 wavelengths spanning the
+    line profile (0.1 .. 1e4 opacity contrast), 6 cascades, every cell."""
+    inp = W.line_medium(256, 64, seed=2, wave_subset=np.arange(0, 64, 8))
+    Jg = _gpu_solve(inp)
+    Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    _assert_rel(Jg, Jo)
+
+
+@pytest.mark.parametrize("nx,nz,nw,seed", [(37, 53, 3, 1), (100, 64, 67, 2), (1, 1, 1, 3), (2, 7, 5, 4)])
+def test_ragged_grids_and_wavelength_counts(nx, nz, nw, seed):
+    """Sizes that are not multiples of the probe spacing (probes outside the
+    domain, clamped taps) and wavelength counts that do not fill a wavefront."""
+    rng = np.random.default_rng(seed)
+    chi = (10 ** rng.uniform(-2, 2, (nw, nz, nx))).astype(np.float32)
+    eta = (chi * rng.uniform(0.2, 3.0, (nw, nz, nx))).astype(np.float32)
+    inp = W.FormalSolveInput(chi, eta, 1.0, W.n_cascades_for(nx, nz), f"rand{nx}x{nz}w{nw}")
+    Jg = _gpu_solve(inp, workspace=True)
+    Jo = oracle.formal_solve(chi, eta, inp.n_cascades)["J"]
+    _assert_rel(Jg, Jo)
+
+
+def test_vacuum_disc_zero_opacity_cells():
+    """chi = eta = 0 outside an opaque disc: exercises the chi -> 0 limit."""
+    inp = W.disc_in_vacuum(128, 4.0)
+    Jg = _gpu_solve(inp)
+    Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    _assert_rel(Jg, Jo)
+
+
+def test_voxel_scale_and_interval_rule():
+    inp = W.blobs_medium(48, seed=6)
+    inp.chi[...] = (inp.chi * 1e-3).astype(np.float32)
+    inp.eta[...] = (inp.eta * 1e-3).astype(np.float32)
+    inp.voxel_scale = 250.0
+    for t_rule in (0, 1):
+        Jg = _gpu_solve(inp, t_rule=t_rule)
+        Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades, voxel=250.0, t_rule=t_rule)["J"]
+        _assert_rel(Jg, Jo)
+
+
+def test_single_and_two_cascades():
+    inp = W.blobs_medium(32, seed=8)
+    for nc in (1, 2):
+        Jg = _gpu_solve(inp, n_cascades=nc)
+        Jo = oracle.formal_solve(inp.chi, inp.eta, nc)["J"]
+        _assert_rel(Jg, Jo)
+
+
+def test_deterministic_bitwise():
+    inp = W.line_medium(128, 64, seed=3, wave_subset=np.arange(0, 64, 4))
+    a = _gpu_solve(inp)
+    b = _gpu_solve(inp)
+    assert np.array_equal(a, b)
+
+
+def test_full_size_1024_64_wavelengths_sampled():
+    """The benchmark workload (1024^2, 64 wavelengths, 7 cascades) in the
+    benchmark's launch configuration; J compared at sampled (cell, wavelength)
+    points that the oracle computes through their dependency cones."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.line_medium(1024, 64, seed=2)
+    print("[gpu] full-size 1024^2 x 64 formal solve", flush=True)
+    plan = rcx.Plan(1024, 1024, 64)
+    chi = torch.from_numpy(inp.chi).cuda()
+    eta = torch.from_numpy(inp.eta).cuda()
+    J = plan.formal_solve(chi, eta)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy()
+    plan.close()
+    assert np.all(np.isfinite(Jg)) and Jg.min() > 0
+    rng = np.random.default_rng(123)
+    cells = [(0, 0), (1023, 1023), (0, 1023), (511, 512)] + [tuple(rng.integers(0, 1024, 2)) for _ in range(2)]
+    need = np.zeros((1024, 1024), np.uint8)
+    for x, z in cells:
+        need[z, x] = 1
+    for lam in (0, 21, 31, 32, 47, 63):
+        Jo = oracle.formal_solve(inp.chi[lam:lam + 1], inp.eta[lam:lam + 1], 7, need=need)["J"][0]
+        for x, z in cells:
+            g, o = float(Jg[lam, z, x]), Jo[z, x]
+            assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
