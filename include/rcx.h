@@ -117,6 +117,16 @@ int32_t rcx_plan_work(rcx_plan* plan, rcx_work* out_host);
 int32_t rcx_formal_solve(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta,
                          float* J, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* Kernel timing for measurement: when enabled, every solve records HIP
+ * events on its stream around each cascade's march+merge launch and around
+ * the other launches (prep, J). rcx_plan_get_timing() synchronises on the
+ * recorded events and returns the accumulated milliseconds per cascade
+ * (ms_level_host[n_cascades]), the accumulated prep + J time, the number of
+ * march+merge launches and of solves since the last get, then resets. */
+int32_t rcx_plan_set_timing(rcx_plan* plan, int32_t enable);
+int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_other_host,
+                            int64_t* n_march_launches_host, int64_t* n_solves_host);
+
 /* Release a plan and its device memory. NULL is accepted. */
 int32_t rcx_plan_destroy(rcx_plan* plan);
 

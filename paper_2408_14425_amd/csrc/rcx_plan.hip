@@ -57,6 +57,14 @@ struct rcx_plan {
     size_t ws_own_bytes = 0;
     bool work_done = false;
     rcx_work work;
+    // measurement: events recorded around launches when timing is enabled
+    struct Timed {
+        int32_t level;  // cascade index, or -1 for prep / J
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    int64_t n_solves = 0;
 };
 
 namespace {
@@ -156,6 +164,26 @@ void count_work(rcx_plan* p)
         w.cell_steps += steps;
     }
     p->work_done = true;
+}
+
+// Run `launch` between two recorded events when timing is enabled.
+template <class F>
+hipError_t timed(rcx_plan* p, int32_t level, hipStream_t st, F&& launch)
+{
+    if (!p->timing) return launch();
+    rcx_plan::Timed t{level, nullptr, nullptr};
+    hipError_t e = hipEventCreate(&t.a);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&t.b);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(t.a);
+        return e;
+    }
+    (void)hipEventRecord(t.a, st);
+    e = launch();
+    (void)hipEventRecord(t.b, st);
+    p->pending.push_back(t);
+    return e;
 }
 
 }  // namespace
@@ -293,25 +321,70 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     float2* F = (float2*)(ws + w.F);
     float* bufs[2] = {(float*)(ws + w.casc_a), (float*)(ws + w.casc_b)};
 
-    RCX_HIP_TRY(launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, st));
+    if (p->timing) ++p->n_solves;
+    RCX_HIP_TRY(timed(p, -1, st, [&] {
+        return launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, st);
+    }));
     int cur = 0;
     const float* up = nullptr;
     for (int32_t i = p->n_casc - 1; i >= 0; --i) {
         if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
         const LevelDesc& L = p->levels[i];
         float* outb = bufs[cur];
-        RCX_HIP_TRY(launch_march_merge(L, nx, nz, n_wave, F, p->dirs_dev + p->dir_off[i],
-                                       L.has_up ? up : nullptr, outb, st));
+        RCX_HIP_TRY(timed(p, i, st, [&] {
+            return launch_march_merge(L, nx, nz, n_wave, F, p->dirs_dev + p->dir_off[i],
+                                      L.has_up ? up : nullptr, outb, st);
+        }));
         up = outb;
         cur ^= 1;
     }
-    RCX_HIP_TRY(launch_j(up, J, n_wave, ncell, p->prm.c0_dirs, st));
+    RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_j(up, J, n_wave, ncell, p->prm.c0_dirs, st); }));
     return ok();
+}
+
+int32_t rcx_plan_set_timing(rcx_plan* p, int32_t enable)
+{
+    if (!p) return fail(RCX_E_INVALID, "rcx_plan_set_timing: null plan");
+    p->timing = enable != 0;
+    return ok();
+}
+
+int32_t rcx_plan_get_timing(rcx_plan* p, double* ms_level, double* ms_other, int64_t* n_launch,
+                            int64_t* n_solves)
+{
+    if (!p || !ms_level || !ms_other || !n_launch || !n_solves)
+        return fail(RCX_E_INVALID, "rcx_plan_get_timing: null argument");
+    for (int32_t i = 0; i < p->n_casc; ++i) ms_level[i] = 0.0;
+    *ms_other = 0.0;
+    *n_launch = 0;
+    int32_t rc = RCX_OK;
+    for (auto& t : p->pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && rc == RCX_OK) rc = hip_fail(e, "rcx_plan_get_timing");
+        if (t.level >= 0) {
+            ms_level[t.level] += ms;
+            ++*n_launch;
+        } else {
+            *ms_other += ms;
+        }
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    p->pending.clear();
+    *n_solves = p->n_solves;
+    p->n_solves = 0;
+    return rc == RCX_OK ? ok() : rc;
 }
 
 int32_t rcx_plan_destroy(rcx_plan* p)
 {
     if (!p) return ok();
+    for (auto& t : p->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
     if (p->dirs_dev) (void)hipFree(p->dirs_dev);
     if (p->ws_own) (void)hipFree(p->ws_own);
     delete p;

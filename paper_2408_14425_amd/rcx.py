@@ -67,11 +67,15 @@ def load() -> C.CDLL:
     L.rcx_plan_work.argtypes = [vp, C.POINTER(rcx_work)]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.rcx_plan_destroy.argtypes = [vp]
+    L.rcx_plan_set_timing.argtypes = [vp, i32]
+    L.rcx_plan_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.rcx_error_string.argtypes = [i32]
     L.rcx_error_string.restype = C.c_char_p
     L.rcx_last_error.argtypes = [C.c_char_p, sz]
     for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
-                 "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error"):
+                 "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error", "rcx_plan_set_timing",
+                 "rcx_plan_get_timing"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -136,6 +140,20 @@ def rcx_formal_solve(plan: int, n_wave: int, chi, eta, J, workspace=None, stream
                                           ws_bytes, _stream_ptr(stream)), "rcx_formal_solve")
 
 
+def rcx_plan_set_timing(plan: int, enable: bool) -> int:
+    return _check(load().rcx_plan_set_timing(plan, int(bool(enable))), "rcx_plan_set_timing")
+
+
+def rcx_plan_get_timing(plan: int, n_cascades: int):
+    """(ms per cascade, ms prep + J, march launches, solves) since the last call."""
+    ms = (C.c_double * max(n_cascades, 1))()
+    other = C.c_double()
+    nl, ns = C.c_int64(), C.c_int64()
+    _check(load().rcx_plan_get_timing(plan, ms, C.byref(other), C.byref(nl), C.byref(ns)),
+           "rcx_plan_get_timing")
+    return list(ms[:n_cascades]), other.value, nl.value, ns.value
+
+
 def rcx_plan_destroy(plan: int) -> int:
     return _check(load().rcx_plan_destroy(plan), "rcx_plan_destroy")
 
@@ -180,6 +198,12 @@ class Plan:
         n = w.n_cascades
         return Work(n, bool(w.top_skipped), w.rays_all, w.rays_nonempty, w.cell_steps,
                     list(w.level_rays[:n]), list(w.level_steps[:n]))
+
+    def set_timing(self, enable: bool):
+        rcx_plan_set_timing(self.handle, enable)
+
+    def get_timing(self):
+        return rcx_plan_get_timing(self.handle, self.work().n_cascades)
 
     def workspace_bytes(self, n_wave: int) -> int:
         return rcx_plan_workspace_bytes(self.handle, n_wave)
