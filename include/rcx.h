@@ -110,6 +110,7 @@ int32_t rcx_plan_work(rcx_plan* plan, rcx_work* out_host);
  * (device, float32), the flatland mean intensity (1/N_0) sum_k I_0(k) of the
  * merged cascade 0. Free-space boundary (Sec. 3.4). chi must be >= 0;
  * cells with chi * voxel_scale < 1e-20 are treated as having that opacity.
+ * Grids are limited to nx * nz <= 2^24 cells (RCX_E_UNSUPPORTED beyond).
  * workspace: device buffer of at least rcx_plan_workspace_bytes(n_wave)
  * bytes, or NULL to use the plan's own.
  * Errors: RCX_E_INVALID (null arrays, n_wave <= 0 or > max_wave);

@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["rc_oracle.c"]
+_SOURCES = ["rc_oracle.c", "nlte_oracle.c"]
 
 
 def build_oracle(verbose: bool = False) -> str:

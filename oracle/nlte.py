@@ -1,0 +1,322 @@
+"""FP64 CPU oracle of the non-LTE iteration (arXiv:2408.14425, Sec. 3.3).
+
+TEST INFRASTRUCTURE ONLY: used by the tests and the benchmark's CPU
+baseline, never by the product path; shares no code with the HIP library.
+
+One iteration, in the paper's order:
+  1. opacities and emissivities from the current populations (lines with
+     Doppler-shifted Voigt profiles evaluated per ray step, Sec. 3.2);
+  2. the radiance-cascades formal solution per wavelength (``rc_oracle.c``);
+  3. at cascade 0: the diagonal operator Psi* of the piecewise-constant
+     solver, the effective intensity I_eff = I - Psi* eta_t and the
+     preconditioned rates of the "same-preconditioning" MALI scheme, where
+     only a transition's own emissivity is treated implicitly (Sec. 3.3);
+  4. the rate matrix Gamma: off-diagonal terms from radiative + collisional
+     rates, the diagonal from conservation (column sums vanish), one row
+     replaced by particle conservation, solved in FP64 (Sec. 3.3, 3.5);
+  5. the maximum relative change of the populations (Sec. 4.2).
+
+Readings (listed in the design notes):
+  - The directional operator is Lambda* = 1 - exp(-tau), with tau the
+    optical depth from the cell centre to its edge along the ray, and
+    Psi* = Lambda* / chi (the printed exp(-tau) makes Psi* diverge as
+    chi -> 0). Psi* is exactly dI_probe / d eta_cell of the march.
+  - I_eff = I - Psi* n_j U_ji (the population factor makes it an
+    emissivity); the downward coefficient is
+    sum W w [V_ji I_eff + U_ji (1 - chi_t Psi*)], chi_t the transition's own
+    opacity at the previous populations.
+  - The conservation row replaces the equation of the most populated level.
+  - Convergence: max over cells and levels of |n_new - n_old| / n_new.
+  - Rate integrals: W = 4 pi dnu / (h nu) with the input frequency weights;
+    flatland angular weights 1/N_0.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _dp, lib, make_geom
+
+# CODATA 2018, SI
+H_PLANCK = 6.62607015e-34
+C_LIGHT = 2.99792458e8
+K_BOLTZ = 1.380649e-23
+M_ELEC = 9.1093837015e-31
+Q_ELEC = 1.602176634e-19
+EPS0 = 8.8541878128e-12
+AMU = 1.66053906660e-27
+EV = Q_ELEC
+
+
+class NlteFields(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("nz", C.c_int32), ("n_wave", C.c_int32), ("n_lines", C.c_int32),
+        ("line", C.c_void_p), ("u", C.c_void_p), ("chi_c", C.c_void_p), ("eta_c", C.c_void_p),
+        ("kappa", C.c_void_p), ("eps", C.c_void_p), ("adamp", C.c_void_p), ("inv_vth", C.c_void_p),
+        ("vx", C.c_void_p), ("vz", C.c_void_p),
+    ]
+
+
+def _bind():
+    L = lib()
+    if not hasattr(L, "_nlte_bound"):
+        L.ora_voigt_H_vec.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.ora_voigt_H_vec.restype = None
+        L.ora_nlte_formal_solve.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_int32]
+        L.ora_nlte_formal_solve.restype = C.c_int32
+        L.ora_nlte_local.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_void_p, C.c_void_p]
+        L.ora_nlte_local.restype = None
+        L._nlte_bound = True
+    return L
+
+
+def voigt_H(a, x):
+    """Voigt function H(a, x) = Re w(x + i a) (Weideman's series, FP64)."""
+    a = np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), np.broadcast(a, x).shape))
+    x = np.ascontiguousarray(np.broadcast_to(np.asarray(x, np.float64), a.shape))
+    out = np.empty_like(a)
+    _bind().ora_voigt_H_vec(a.size, a.ctypes.data, x.ctypes.data, out.ctypes.data)
+    return out
+
+
+# ------------------------------------------------------------------- atom
+
+
+@dataclass
+class Transition:
+    kind: str      # "line" or "cont"
+    i: int         # lower level
+    j: int         # upper level
+    nu0: float     # line centre or edge frequency [Hz]
+    sigma: float   # line: integrated cross-section [m^2 Hz]; cont: cross-section at the edge [m^2]
+    A: float       # line: spontaneous emission rate [1/s]
+    q: float       # collisional de-excitation coefficient [m^3/s]
+
+
+class Atom:
+    """The model atom, with the line quantities of classical radiation theory:
+    integrated cross-section sigma = e^2 f / (4 eps0 m_e c), Einstein
+    A_ji = 2 pi e^2 nu^2 g_i f / (eps0 m_e c^3 g_j), natural damping
+    Gamma = sum of A out of the upper and lower levels."""
+
+    def __init__(self, d: dict):
+        self.E = np.array(d["E_eV"], np.float64) * EV
+        self.g = np.array(d["g"], np.float64)
+        self.mass = d["mass_amu"] * AMU
+        self.n_levels = len(self.E)
+        self.trans: list[Transition] = []
+        for (i, j, lam0, f), q in zip(d["lines"], d["q_coll"]):
+            nu0 = C_LIGHT / (lam0 * 1e-9)
+            sigma = Q_ELEC ** 2 * f / (4.0 * EPS0 * M_ELEC * C_LIGHT)
+            A = 2.0 * math.pi * Q_ELEC ** 2 * nu0 ** 2 * self.g[i] * f / (EPS0 * M_ELEC * C_LIGHT ** 3 * self.g[j])
+            self.trans.append(Transition("line", i, j, nu0, sigma, A, q))
+        for (i, j, ledge, a0), q in zip(d["continua"], d["q_coll"][len(d["lines"]):]):
+            self.trans.append(Transition("cont", i, j, C_LIGHT / (ledge * 1e-9), a0, 0.0, q))
+        self.lines = [t for t in self.trans if t.kind == "line"]
+        # natural damping of each line
+        self.gamma = []
+        for t in self.lines:
+            out_up = sum(s.A for s in self.lines if s.j == t.j)
+            out_lo = sum(s.A for s in self.lines if s.j == t.i)
+            self.gamma.append(out_up + out_lo)
+
+
+def lte_populations(atom: Atom, T, ne, ntot):
+    """Saha-Boltzmann populations [n_levels][cells]: bound levels relative to
+    the ground level by Boltzmann, the continuum (last level) by Saha with the
+    free-electron partition factor 2 (2 pi m_e k T / h^2)^{3/2} / n_e;
+    normalised to ntot."""
+    T = np.asarray(T, np.float64)
+    kT = K_BOLTZ * T
+    rel = np.empty((atom.n_levels,) + T.shape)
+    for l in range(atom.n_levels - 1):
+        rel[l] = atom.g[l] / atom.g[0] * np.exp(-(atom.E[l] - atom.E[0]) / kT)
+    saha = 2.0 * (2.0 * math.pi * M_ELEC * kT / H_PLANCK ** 2) ** 1.5 / ne
+    c = atom.n_levels - 1
+    rel[c] = atom.g[c] / atom.g[0] * saha * np.exp(-(atom.E[c] - atom.E[0]) / kT)
+    return rel / rel.sum(axis=0) * ntot
+
+
+# -------------------------------------------------------------- problem
+
+
+class Problem:
+    """Static (population-independent) data of one non-LTE problem."""
+
+    def __init__(self, inp, n_casc: int | None = None):
+        from paper_2408_14425_amd.workloads import n_cascades_for
+        self.inp = inp
+        self.atom = Atom(inp.atom)
+        self.nx, self.nz = inp.nx, inp.nz
+        self.ncell = inp.nx * inp.nz
+        self.T = inp.T.reshape(-1).astype(np.float64)
+        self.ne = inp.ne.reshape(-1).astype(np.float64)
+        self.ntot = inp.ntot.reshape(-1).astype(np.float64)
+        self.vx = inp.vel[0].reshape(-1).astype(np.float64)
+        self.vz = inp.vel[1].reshape(-1).astype(np.float64)
+        self.nu = C_LIGHT / (inp.lambda_nm.astype(np.float64) * 1e-9)
+        self.trans_of = inp.trans.astype(np.int32)
+        self.W = 4.0 * math.pi * inp.dnu / (H_PLANCK * self.nu)
+        self.n_casc = n_cascades_for(self.nx, self.nz) if n_casc is None else n_casc
+        self.geom = make_geom(self.nx, self.nz, self.n_casc, voxel=inp.voxel)
+        self.n0 = 4
+        self.lte = lte_populations(self.atom, self.T, self.ne, self.ntot)
+        # thermal speed and line quantities per cell
+        self.vth = np.sqrt(2.0 * K_BOLTZ * self.T / self.atom.mass)
+        self.line_index = np.full(len(self.nu), -1, np.int32)
+        self.u = np.zeros(len(self.nu))
+        for lam, t in enumerate(self.trans_of):
+            tr = self.atom.trans[t]
+            if tr.kind == "line":
+                self.line_index[lam] = self.atom.lines.index(tr)
+                self.u[lam] = C_LIGHT * (self.nu[lam] - tr.nu0) / tr.nu0
+        self.dnuD = [t.nu0 * self.vth / C_LIGHT for t in self.atom.lines]
+        self.adamp = np.array([g / (4.0 * math.pi * d) for g, d in zip(self.atom.gamma, self.dnuD)])
+        # collisional rates: down C_ji = ne q (T/1e4)^-1/2, up by detailed balance
+        self.Cdown = np.array([self.ne * t.q * (self.T / 1e4) ** -0.5 for t in self.atom.trans])
+        self.Cup = np.array([cd * self.lte[t.j] / self.lte[t.i] for cd, t in zip(self.Cdown, self.atom.trans)])
+        # c0 directions and the distance from the cell centre to its edge along each
+        self.dirs = [(math.cos(2 * math.pi * (k + 0.5) / self.n0), math.sin(2 * math.pi * (k + 0.5) / self.n0))
+                     for k in range(self.n0)]
+        self.ell = np.array([0.5 / max(abs(wx), abs(wz)) for wx, wz in self.dirs]) * inp.voxel
+
+    # -- per-transition coefficients at wavelength index lam
+    def cont_coeffs(self, lam: int):
+        """Bound-free V_ic, V_ci, U_ci per cell: alpha (nu_edge/nu)^3, times the
+        LTE ratio n_i*/n_c* and exp(-h nu / k T) for the downward terms."""
+        tr = self.atom.trans[self.trans_of[lam]]
+        nu = self.nu[lam]
+        alpha = tr.sigma * (tr.nu0 / nu) ** 3 if nu >= tr.nu0 else 0.0
+        Vic = np.full(self.ncell, alpha)
+        Vci = alpha * self.lte[tr.i] / self.lte[tr.j] * np.exp(-H_PLANCK * nu / (K_BOLTZ * self.T))
+        Uci = 2.0 * H_PLANCK * nu ** 3 / C_LIGHT ** 2 * Vci
+        return tr, Vic, Vci, Uci
+
+    def line_coeffs(self, lam: int, H):
+        """Line V_ij, V_ji, U_ji for profile values H (same shape as cells x ...):
+        phi = H / (sqrt(pi) dnu_D)."""
+        li = self.line_index[lam]
+        tr = self.atom.lines[li]
+        phi = H / (math.sqrt(math.pi) * self.dnuD[li][:, None])
+        Vij = tr.sigma * phi
+        Vji = self.atom.g[tr.i] / self.atom.g[tr.j] * Vij
+        Uji = 2.0 * H_PLANCK * tr.nu0 ** 3 / C_LIGHT ** 2 * Vji
+        return tr, Vij, Vji, Uji
+
+    def fields(self, pops):
+        """Opacity fields for the formal solve at populations pops [levels][cells]."""
+        nw = len(self.nu)
+        chi_c = np.zeros((nw, self.ncell))
+        eta_c = np.zeros((nw, self.ncell))
+        nl = len(self.atom.lines)
+        kappa = np.zeros((nl, self.ncell))
+        eps = np.zeros((nl, self.ncell))
+        for lam in range(nw):
+            tr = self.atom.trans[self.trans_of[lam]]
+            if tr.kind == "cont":
+                _, Vic, Vci, Uci = self.cont_coeffs(lam)
+                chi_c[lam] = pops[tr.i] * Vic - pops[tr.j] * Vci
+                eta_c[lam] = pops[tr.j] * Uci
+        for li, tr in enumerate(self.atom.lines):
+            norm = tr.sigma / (math.sqrt(math.pi) * self.dnuD[li])
+            gr = self.atom.g[tr.i] / self.atom.g[tr.j]
+            kappa[li] = norm * (pops[tr.i] - gr * pops[tr.j])
+            eps[li] = norm * gr * pops[tr.j] * 2.0 * H_PLANCK * tr.nu0 ** 3 / C_LIGHT ** 2
+        return chi_c, eta_c, kappa, eps
+
+    def _cfields(self, chi_c, eta_c, kappa, eps):
+        keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
+                (self.u, chi_c, eta_c, kappa, eps, self.adamp, 1.0 / self.vth, self.vx, self.vz)]
+        line = np.ascontiguousarray(self.line_index, dtype=np.int32)
+        keep.append(line)
+        f = NlteFields(self.nx, self.nz, len(self.nu), len(self.atom.lines), line.ctypes.data,
+                       *[k.ctypes.data for k in keep[:9]])
+        return f, keep
+
+    def formal_solve(self, pops):
+        """J [n_wave][cells] and merged cascade-0 radiance I0 [n_wave][cells][N_0],
+        plus the local directional opacity chi [n_wave][cells][N_0] and line
+        profile H at each cell."""
+        chi_c, eta_c, kappa, eps = self.fields(pops)
+        f, keep = self._cfields(chi_c, eta_c, kappa, eps)
+        nw = len(self.nu)
+        J = np.zeros((nw, self.ncell))
+        I0 = np.zeros((nw, self.ncell, self.n0))
+        st = np.zeros(3, np.int64)
+        L = _bind()
+        rc = L.ora_nlte_formal_solve(C.byref(self.geom), C.byref(f), J.ctypes.data, I0.ctypes.data,
+                                     st.ctypes.data, 0)
+        if rc != 0:
+            raise RuntimeError("ora_nlte_formal_solve failed")
+        chi_loc = np.zeros((nw, self.ncell, self.n0))
+        H_loc = np.zeros((nw, self.ncell, self.n0))
+        L.ora_nlte_local(C.byref(self.geom), C.byref(f), chi_loc.ctypes.data, H_loc.ctypes.data)
+        del keep
+        return J, I0, chi_loc, H_loc, st
+
+    def rates(self, pops, I0, chi_loc, H_loc):
+        """Preconditioned radiative rate coefficients per transition and cell:
+        Rup (multiplies n_i) and Rdown (multiplies n_j)."""
+        nt = len(self.atom.trans)
+        Rup = np.zeros((nt, self.ncell))
+        Rdn = np.zeros((nt, self.ncell))
+        w = 1.0 / self.n0
+        for lam in range(len(self.nu)):
+            t = self.trans_of[lam]
+            tr = self.atom.trans[t]
+            chi = chi_loc[lam]                                   # [cells][k]
+            psi = -np.expm1(-chi * self.ell[None, :]) / chi      # Psi* = (1 - e^{-chi l}) / chi
+            if tr.kind == "line":
+                _, Vij, Vji, Uji = self.line_coeffs(lam, H_loc[lam])
+            else:
+                _, Vic, Vci, Uci = self.cont_coeffs(lam)
+                Vij, Vji, Uji = Vic[:, None], Vci[:, None], Uci[:, None]
+            eta_t = pops[tr.j][:, None] * Uji
+            chi_t = pops[tr.i][:, None] * Vij - pops[tr.j][:, None] * Vji
+            Ieff = I0[lam] - psi * eta_t
+            Rup[t] += self.W[lam] * w * np.sum(Vij * Ieff, axis=1)
+            Rdn[t] += self.W[lam] * w * np.sum(Vji * Ieff + Uji * (1.0 - chi_t * psi), axis=1)
+        return Rup, Rdn
+
+    def gamma(self, Rup, Rdn):
+        """Rate matrix [cells][levels][levels]: Gamma[j][i] = rate i -> j
+        (i != j), diagonal = minus the column sum (conservation)."""
+        nlv = self.atom.n_levels
+        G = np.zeros((self.ncell, nlv, nlv))
+        for t, tr in enumerate(self.atom.trans):
+            G[:, tr.j, tr.i] += Rup[t] + self.Cup[t]
+            G[:, tr.i, tr.j] += Rdn[t] + self.Cdown[t]
+        for l in range(nlv):
+            G[:, l, l] = -(G.sum(axis=1)[:, l] - G[:, l, l])
+        return G
+
+    def stat_eq(self, pops, Rup, Rdn):
+        """Solve Gamma n = 0 with the most populated level's row replaced by
+        sum(n) = ntot. Returns new populations and max |dn| / n_new."""
+        G = self.gamma(Rup, Rdn)
+        nlv = self.atom.n_levels
+        r = np.argmax(pops, axis=0)
+        A = G.copy()
+        b = np.zeros((self.ncell, nlv))
+        A[np.arange(self.ncell), r, :] = 1.0
+        b[np.arange(self.ncell), r] = self.ntot
+        new = np.linalg.solve(A, b[..., None])[..., 0].T
+        change = float(np.max(np.abs(new - pops) / np.abs(new)))
+        return new, change
+
+    def iterate(self, pops, n_iter: int, tol: float | None = None):
+        """Plain iteration (no acceleration). Stops after n_iter iterations or
+        once the max relative change drops below tol."""
+        changes = []
+        for _ in range(n_iter):
+            J, I0, chi_loc, H_loc, _ = self.formal_solve(pops)
+            Rup, Rdn = self.rates(pops, I0, chi_loc, H_loc)
+            pops, ch = self.stat_eq(pops, Rup, Rdn)
+            changes.append(ch)
+            if tol is not None and ch < tol:
+                break
+        return pops, changes

@@ -51,15 +51,12 @@
 #include <omp.h>
 #endif
 
-typedef struct {
-    int32_t nx, nz;      /* grid size in cells */
-    int32_t n_casc;      /* number of cascades I */
-    int32_t c0_dirs;     /* directions on cascade 0 (N_0) */
-    double t1;           /* start of cascade 1 (= length of cascade-0 intervals), cells */
-    int32_t t_rule;      /* 0: t_i = t1 4^{i-1};  1: t_i = t1 (4^i - 1)/3 */
-    int32_t pad_;
-    double voxel;        /* physical length of one cell, in the units chi is per */
-} ora_geom;
+#include "rc_oracle.h"
+
+/* ora_geom fields: grid size in cells (nx, nz); number of cascades I
+ * (n_casc); directions on cascade 0 (c0_dirs); start of cascade 1 in cells
+ * (t1); interval rule (t_rule: 0 geometric t_i = t1 4^{i-1}, 1 lengths x4
+ * t_i = t1 (4^i - 1)/3); physical length of one cell (voxel). */
 
 /* ---------------------------------------------------------------- geometry */
 
@@ -197,10 +194,8 @@ void ora_merge(double I_near, double tau_near, double I_far, double tau_far,
     *tau_out = tau_near + tau_far;
 }
 
-/* Opacity/emissivity provider: the value a ray sees in a cell for wavelength
- * index lam when looking along (wx, wz). */
-typedef void (*ora_opac_fn)(const void* ctx, int32_t lam, int32_t cx, int32_t cz,
-                            double wx, double wz, double* chi, double* eta);
+/* ora_opac_fn: opacity/emissivity a ray sees in a cell for wavelength index
+ * lam when looking along (wx, wz) (declared in rc_oracle.h). */
 
 typedef struct {
     const double* chi;  /* [n_wave][nz][nx] per unit length */

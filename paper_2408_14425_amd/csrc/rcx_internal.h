@@ -36,10 +36,13 @@ int32_t hip_fail(hipError_t e, const char* what);
 // launch status.
 hipError_t launch_prep(const float* chi, const float* eta, float2* F, int32_t n_wave, int64_t ncell,
                        float voxel, hipStream_t st);
-hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, int32_t n_wave,
-                              const float2* F, const double4* dirs, const float* up, float* out,
-                              hipStream_t st);
-hipError_t launch_j(const float* I0, float* J, int32_t n_wave, int64_t ncell, int32_t n0,
+// Wavelengths per batch of the field and cascade layouts.
+int32_t batch_width();
+// Fb: the batch's slice of F ([ncell][batch_width] float2); up/out: cascade
+// buffers [rays][batch_width].
+hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
+                              const double4* dirs, const float* up, float* out, hipStream_t st);
+hipError_t launch_j(const float* I0, float* J, int32_t n_wave, int32_t batch, int64_t ncell, int32_t n0,
                     hipStream_t st);
 
 }  // namespace rcx

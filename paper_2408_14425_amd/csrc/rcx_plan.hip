@@ -114,10 +114,12 @@ WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
     const int64_t ncell = (int64_t)p->grid.nx * p->grid.nz;
     int64_t max_entries = 0;
     for (const auto& L : p->levels) max_entries = std::max(max_entries, level_entries(L));
+    const int64_t lb = batch_width();
+    const int64_t n_batch = (n_wave + lb - 1) / lb;
     w.F = 0;
-    w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_wave);
-    w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * n_wave);
-    w.total = w.casc_b + align256(sizeof(float) * (size_t)max_entries * n_wave);
+    w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_batch * lb);
+    w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * lb);
+    w.total = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb);
     return w;
 }
 
@@ -210,6 +212,8 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
     if (g->nx <= 0 || g->nz <= 0 || max_wave <= 0)
         return fail(RCX_E_INVALID, "rcx_plan_create: nx, nz and max_wave must be positive");
     if (!(g->voxel_scale > 0.0)) return fail(RCX_E_INVALID, "rcx_plan_create: voxel_scale must be > 0");
+    if ((int64_t)g->nx * g->nz > (int64_t(1) << 24))
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: nx * nz must be at most 2^24 cells");
     if (prm->c0_dirs <= 0 || !(prm->c0_t1 > 0.0))
         return fail(RCX_E_INVALID, "rcx_plan_create: c0_dirs and c0_t1 must be positive");
     if (prm->t_rule != RCX_T_GEOMETRIC && prm->t_rule != RCX_T_LENGTH_X4)
@@ -325,20 +329,25 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     RCX_HIP_TRY(timed(p, -1, st, [&] {
         return launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, st);
     }));
-    int cur = 0;
-    const float* up = nullptr;
-    for (int32_t i = p->n_casc - 1; i >= 0; --i) {
-        if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
-        const LevelDesc& L = p->levels[i];
-        float* outb = bufs[cur];
-        RCX_HIP_TRY(timed(p, i, st, [&] {
-            return launch_march_merge(L, nx, nz, n_wave, F, p->dirs_dev + p->dir_off[i],
-                                      L.has_up ? up : nullptr, outb, st);
-        }));
-        up = outb;
-        cur ^= 1;
+    const int32_t lb = batch_width();
+    const int32_t n_batch = (n_wave + lb - 1) / lb;
+    for (int32_t b = 0; b < n_batch; ++b) {
+        const float2* Fb = F + (size_t)b * ncell * lb;
+        int cur = 0;
+        const float* up = nullptr;
+        for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+            if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
+            const LevelDesc& L = p->levels[i];
+            float* outb = bufs[cur];
+            RCX_HIP_TRY(timed(p, i, st, [&] {
+                return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], L.has_up ? up : nullptr,
+                                          outb, st);
+            }));
+            up = outb;
+            cur ^= 1;
+        }
+        RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_j(up, J, n_wave, b, ncell, p->prm.c0_dirs, st); }));
     }
-    RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_j(up, J, n_wave, ncell, p->prm.c0_dirs, st); }));
     return ok();
 }
 

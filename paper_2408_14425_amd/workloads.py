@@ -162,3 +162,130 @@ def uneven_batch(seed: int = 4, n_atm: int = 16, sizes=None, waves=None):
     for a in range(n_atm):
         out.append((int(rng.choice(sizes)), int(rng.choice(waves)), 4000 + a))
     return out
+
+
+# ------------------------------------------------------------------ non-LTE
+
+# Synthetic hydrogen-like model atom: 3 bound levels + continuum. Level data
+# (energies [eV], statistical weights), two lines (lower, upper, rest
+# wavelength [nm], oscillator strength), one bound-free continuum (lower,
+# upper, edge wavelength [nm], cross-section at the edge [m^2], scaling as
+# lambda^3 below the edge), atomic mass [amu], and per-transition collisional
+# de-excitation coefficients q [m^3/s] (downward rate n_e q (T/1e4 K)^-1/2).
+# This is input data, in the role of an atomic-model file.
+SYNTH_ATOM = {
+    # energies consistent with the line and edge wavelengths (E = h c / lambda)
+    "E_eV": [0.0, 10.1985850483837, 12.0877817088518, 13.5977405607809],
+    "g": [2.0, 8.0, 18.0, 1.0],
+    "mass_amu": 1.008,
+    "lines": [(0, 1, 121.57, 0.4164), (1, 2, 656.28, 0.6407)],
+    "continua": [(0, 3, 91.18, 6.3e-22)],
+    # transitions in order: lines, then continua
+    "q_coll": [2.6e-11, 2.4e-10, 1.0e-12],
+}
+
+
+@dataclass
+class NlteInput:
+    """A non-LTE problem: atmosphere on an nx x nz grid and a wavelength grid.
+
+    T, ne, ntot: [nz][nx] float64 (K, m^-3, m^-3; ntot = all hydrogen
+    particles, neutral and ionised); vel: [2][nz][nx] float32 (vx, vz, m/s);
+    lambda_nm: [n_wave] float64; trans: [n_wave] int32 index of the
+    transition each wavelength belongs to (lines first, then continua), grouped
+    by transition; dnu: [n_wave] float64 frequency quadrature weights [Hz]
+    (trapezoid in frequency within each transition's sub-grid); voxel: cell
+    size [m]."""
+    T: np.ndarray
+    ne: np.ndarray
+    ntot: np.ndarray
+    vel: np.ndarray
+    lambda_nm: np.ndarray
+    trans: np.ndarray
+    dnu: np.ndarray
+    voxel: float
+    atom: dict
+    name: str
+
+    @property
+    def nx(self) -> int:
+        return int(self.T.shape[1])
+
+    @property
+    def nz(self) -> int:
+        return int(self.T.shape[0])
+
+    @property
+    def n_wave(self) -> int:
+        return int(len(self.lambda_nm))
+
+
+_C_LIGHT = 2.99792458e8
+
+
+def nlte_wavelength_grid(atom: dict, n_line: int = 64, n_cont: int = 32, vmax: float = 150e3,
+                         stretch: float = 3.0):
+    """Per line: n_line points over +-vmax in Doppler velocity, sinh-stretched
+    towards the core; per continuum: n_cont points log-spaced over
+    [0.5, 1] x the edge wavelength. Returns (lambda_nm, trans, dnu)."""
+    lams, trans, dnus = [], [], []
+    t = 0
+    for (_, _, lam0, _) in atom["lines"]:
+        s = np.linspace(-1.0, 1.0, n_line)
+        v = vmax * np.sinh(stretch * s) / np.sinh(stretch)
+        lam = lam0 * (1.0 + v / _C_LIGHT)
+        lams.append(lam)
+        trans.append(np.full(n_line, t))
+        t += 1
+    for (_, _, ledge, _) in atom["continua"]:
+        lam = ledge * np.logspace(np.log10(0.5), 0.0, n_cont)
+        lams.append(lam)
+        trans.append(np.full(n_cont, t))
+        t += 1
+    for lam in lams:
+        nu = _C_LIGHT / (lam * 1e-9)
+        w = np.zeros_like(nu)
+        d = np.abs(np.diff(nu))
+        w[:-1] += 0.5 * d
+        w[1:] += 0.5 * d
+        dnus.append(w)
+    return (np.concatenate(lams), np.concatenate(trans).astype(np.int32), np.concatenate(dnus))
+
+
+def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 32,
+                    n0: float = 5e16, voxel: float = 1e3, nz: int | None = None) -> NlteInput:
+    """Synthetic prominence-like atmosphere: a hot (1e5 K), tenuous
+    background with cool blobs, log10 T = 5 - sum_b (5 - log10 T_b)
+    exp(-r^2 / 2 sigma_b^2) clipped to [log10 5e3, 5], 24 blobs per 1024^2
+    (count scaled by area, at least 3), widths uniform in [20, 80] x
+    max(n, 256)/1024 cells, blob temperatures log-uniform in [5e3, 3e4] K;
+    hydrogen density
+    ntot = n0 (1e4 K / T); a prescribed ionisation fraction
+    x(T) = 1e-4 + (1 - 1e-4) / (1 + (6540 K / T)^16) (shaped like a hydrogen
+    ionisation curve at these densities: about 1% at 5000 K, 75% at 7000 K),
+    ne = x ntot; velocities
+    uniform in +-20 km/s on a 32 x 32 coarse grid, bilinearly upsampled."""
+    nz = n if nz is None else nz
+    rng = np.random.default_rng(seed)
+    zc, xc = np.meshgrid(np.arange(nz) + 0.5, np.arange(n) + 0.5, indexing="ij")
+    n_blobs = max(3, int(round(24 * n * nz / 1024.0 ** 2)))
+    logt = np.full((nz, n), 5.0)
+    for _ in range(n_blobs):
+        cx, cz = rng.uniform(0, n), rng.uniform(0, nz)
+        sig = rng.uniform(20.0, 80.0) * max(n, 256) / 1024.0
+        tb = 10 ** rng.uniform(np.log10(5e3), np.log10(3e4))
+        logt -= (5.0 - np.log10(tb)) * np.exp(-((xc - cx) ** 2 + (zc - cz) ** 2) / (2 * sig * sig))
+    T = 10 ** np.clip(logt, np.log10(5e3), 5.0)
+    ntot = n0 * (1e4 / T)
+    xion = 1e-4 + (1.0 - 1e-4) / (1.0 + (6540.0 / T) ** 16)
+    ne = xion * ntot
+    coarse = rng.uniform(-20e3, 20e3, size=(2, 32, 32))
+    vel = np.empty((2, nz, n))
+    gz = (np.arange(nz) + 0.5) / nz * 32 - 0.5
+    gx = (np.arange(n) + 0.5) / n * 32 - 0.5
+    for d in range(2):
+        rows = np.array([np.interp(gx, np.arange(32), coarse[d, j]) for j in range(32)])
+        vel[d] = np.array([np.interp(gz, np.arange(32), rows[:, i]) for i in range(n)]).T
+    lam, trans, dnu = nlte_wavelength_grid(SYNTH_ATOM, n_line, n_cont)
+    return NlteInput(T, ne, ntot, vel.astype(np.float32), lam, trans, dnu, voxel, SYNTH_ATOM,
+                     f"nlte{n}x{nz}_w{len(lam)}_s{seed}")

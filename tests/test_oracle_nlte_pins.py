@@ -1,0 +1,184 @@
+"""Pins of the FP64 non-LTE oracle (no GPU) against what physics and the
+paper fix: textbook atomic constants, Kirchhoff / detailed balance at LTE,
+the collision-dominated limit, profile normalisation, the cascade-0 operator
+as the derivative of the march, rate-matrix conservation and the fixed point
+of the preconditioned iteration."""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import wofz
+
+import oracle
+from oracle import nlte
+from paper_2408_14425_amd import workloads as W
+
+
+@pytest.fixture(scope="module")
+def small():
+    inp = W.nlte_atmosphere(16, seed=5, n_line=24, n_cont=8)
+    return nlte.Problem(inp)
+
+
+def test_voigt_matches_faddeeva():
+    """H(a, x) = Re w(x + i a) against scipy's Faddeeva function."""
+    rng = np.random.default_rng(0)
+    a = 10 ** rng.uniform(-5, 0.5, 50000)
+    x = rng.uniform(-30, 30, 50000)
+    ref = wofz(x + 1j * a).real
+    np.testing.assert_allclose(nlte.voigt_H(a, x), ref, rtol=1e-7)
+
+
+def test_einstein_A_textbook_values():
+    """Oscillator strengths 0.4164 (Ly-alpha) and 0.6407 (H-alpha) give the
+    textbook n-averaged hydrogen rates 4.699e8 and 4.410e7 1/s."""
+    atom = nlte.Atom(W.SYNTH_ATOM)
+    assert abs(atom.lines[0].A / 4.699e8 - 1) < 2e-3
+    assert abs(atom.lines[1].A / 4.410e7 - 1) < 2e-3
+    # Einstein relation between spontaneous and stimulated emission:
+    # A_ji = (2 h nu^3 / c^2) B_ji with B_ji = (g_i/g_j) 4 pi sigma / (h nu)
+    for t in atom.lines:
+        Bji = atom.g[t.i] / atom.g[t.j] * 4 * math.pi * t.sigma / (nlte.H_PLANCK * t.nu0)
+        assert abs(t.A / (2 * nlte.H_PLANCK * t.nu0 ** 3 / nlte.C_LIGHT ** 2 * Bji) - 1) < 1e-12
+
+
+def test_saha_boltzmann_constants():
+    """Boltzmann ratio of level 1 to 0 is (g1/g0) e^{-E1/kT} (E1 = hc / 121.57 nm); the Saha
+    factor (2 pi m_e k T / h^2)^{3/2} is 2.4147e21 T^{3/2} m^-3."""
+    atom = nlte.Atom(W.SYNTH_ATOM)
+    T = np.array([6000.0, 2e4])
+    ne = np.array([1e16, 1e17])
+    n = nlte.lte_populations(atom, T, ne, np.array([1.0, 1.0]))
+    kT_eV = nlte.K_BOLTZ * T / nlte.EV
+    np.testing.assert_allclose(n[1] / n[0], 4.0 * np.exp(-1239.8419843320025 / 121.57 / kT_eV), rtol=1e-9)
+    saha = 2.4147e21 * T ** 1.5 / ne * 2 * (1.0 / 2.0) * np.exp(-1239.8419843320025 / 91.18 / kT_eV)
+    np.testing.assert_allclose(n[3] / n[0], saha, rtol=2e-4)
+    np.testing.assert_allclose(n.sum(axis=0), 1.0, rtol=1e-14)
+
+
+def test_line_profile_normalised_on_grid(small):
+    """sum_lambda phi dnu over a line's sub-grid is 1 up to the truncated
+    far wings (phi = H / (sqrt(pi) dnu_D))."""
+    P = small
+    for li, tr in enumerate(P.atom.lines):
+        lams = np.where(P.line_index == li)[0]
+        # on a fine uniform grid the normalisation is exact to the wings
+        u = np.linspace(-150e3, 150e3, 20001)
+        for c in (0, P.ncell // 2):
+            x = u / P.vth[c]
+            H = nlte.voigt_H(P.adamp[li][c], x)
+            integral = np.trapezoid(H / math.sqrt(math.pi), x)
+            assert abs(integral - 1) < 5e-3
+        assert len(lams) > 0
+
+
+def test_rates_vanish_at_lte_for_planck_field(small):
+    """Kirchhoff: with LTE populations and the LTE source function in every
+    direction (B at the line centre for line wavelengths, complete
+    redistribution; B_nu for the continuum), every transition's
+    preconditioned net rate vanishes (eta_t = chi_t S, Psi* terms cancel), so
+    the statistical-equilibrium solve returns the LTE populations."""
+    P = small
+    pops = P.lte.copy()
+    nu_eval = P.nu.copy()
+    for lam, t in enumerate(P.trans_of):
+        if P.atom.trans[t].kind == "line":
+            nu_eval[lam] = P.atom.trans[t].nu0
+    nu = nu_eval[:, None]
+    B = 2 * nlte.H_PLANCK * nu ** 3 / nlte.C_LIGHT ** 2 / np.expm1(nlte.H_PLANCK * nu / (nlte.K_BOLTZ * P.T[None, :]))
+    I0 = np.repeat(B[:, :, None], P.n0, axis=2)
+    _, _, chi_loc, H_loc, _ = P.formal_solve(pops)
+    Rup, Rdn = P.rates(pops, I0, chi_loc, H_loc)
+    for t, tr in enumerate(P.atom.trans):
+        lams = np.where(P.trans_of == t)[0]
+        gross = np.zeros(P.ncell)
+        for lam in lams:
+            if tr.kind == "line":
+                _, Vij, _, _ = P.line_coeffs(lam, H_loc[lam])
+            else:
+                _, Vic, _, _ = P.cont_coeffs(lam)
+                Vij = Vic[:, None]
+            gross += P.W[lam] / P.n0 * np.sum(Vij * I0[lam], axis=1) * pops[tr.i]
+        net = pops[tr.i] * Rup[t] - pops[tr.j] * Rdn[t]
+        assert np.max(np.abs(net) / gross) < 1e-8, t
+    new, ch = P.stat_eq(pops, Rup, Rdn)
+    assert ch < 1e-7
+
+
+def test_collision_dominated_limit_is_lte():
+    """Collisions far above radiative rates force Saha-Boltzmann populations."""
+    d = dict(W.SYNTH_ATOM)
+    d["q_coll"] = [q * 1e12 for q in W.SYNTH_ATOM["q_coll"]]
+    inp = W.nlte_atmosphere(16, seed=6, n_line=16, n_cont=8)
+    inp.atom = d
+    P = nlte.Problem(inp)
+    pops, changes = P.iterate(P.lte.copy(), 3)
+    np.testing.assert_allclose(pops, P.lte, rtol=1e-6)
+
+
+def test_gamma_columns_sum_to_zero_and_solution_unique(small):
+    P = small
+    pops = P.lte.copy()
+    J, I0, chi_loc, H_loc, _ = P.formal_solve(pops)
+    Rup, Rdn = P.rates(pops, I0, chi_loc, H_loc)
+    G = P.gamma(Rup, Rdn)
+    colsum = np.abs(G.sum(axis=1)).max(axis=1) / np.abs(G).max(axis=(1, 2))
+    assert colsum.max() < 1e-13
+    new, _ = P.stat_eq(pops, Rup, Rdn)
+    np.testing.assert_allclose(new.sum(axis=0), P.ntot, rtol=1e-12)
+    # The solution of Gamma n = 0, sum n = ntot does not depend on which
+    # equation the conservation row replaces: check against the
+    # least-squares solution of the full over-determined system.
+    for c in range(0, P.ncell, 37):
+        A = np.vstack([G[c], np.ones(P.atom.n_levels)])
+        b = np.zeros(P.atom.n_levels + 1)
+        b[-1] = P.ntot[c]
+        sol, *_ = np.linalg.lstsq(A, b, rcond=None)
+        np.testing.assert_allclose(new[:, c], sol, rtol=1e-8, atol=1e-12 * P.ntot[c])
+
+
+def test_cascade0_operator_is_derivative_of_march():
+    """Psi*(k) = (1 - e^{-chi l_k}) / chi equals dI_0(k)/d eta of the cell
+    itself, l_k the distance from the cell centre to its edge along w_k (one
+    cascade, so no other interval passes the cell)."""
+    rng = np.random.default_rng(2)
+    n = 9
+    chi = 10 ** rng.uniform(-2, 1.5, (1, n, n))
+    eta = chi * rng.uniform(0.5, 2.0, (1, n, n))
+    c = (4, 5)
+    base = oracle.formal_solve(chi, eta, 1, want_I0=True)["I0"][0, c[0], c[1]]
+    h = 1e-3 * eta[0, c[0], c[1]]
+    eta2 = eta.copy()
+    eta2[0, c[0], c[1]] += h
+    pert = oracle.formal_solve(chi, eta2, 1, want_I0=True)["I0"][0, c[0], c[1]]
+    fd = (pert - base) / h
+    ell = math.sqrt(0.5)
+    psi = -math.expm1(-chi[0, c[0], c[1]] * ell) / chi[0, c[0], c[1]]
+    np.testing.assert_allclose(fd, psi, rtol=1e-7)
+
+
+def test_fixed_point_balances_unpreconditioned_rates():
+    """At convergence the preconditioning terms cancel: the plain rates
+    (I, no Psi*) balance the populations to about the stopping tolerance."""
+    inp = W.nlte_atmosphere(16, seed=5, n_line=24, n_cont=8)
+    P = nlte.Problem(inp)
+    pops, changes = P.iterate(P.lte.copy(), 200, tol=1e-9)
+    assert changes[-1] < 1e-9
+    J, I0, chi_loc, H_loc, _ = P.formal_solve(pops)
+    nt = len(P.atom.trans)
+    Rup = np.zeros((nt, P.ncell))
+    Rdn = np.zeros((nt, P.ncell))
+    for lam in range(len(P.nu)):
+        t = P.trans_of[lam]
+        tr = P.atom.trans[t]
+        if tr.kind == "line":
+            _, Vij, Vji, Uji = P.line_coeffs(lam, H_loc[lam])
+        else:
+            _, Vic, Vci, Uci = P.cont_coeffs(lam)
+            Vij, Vji, Uji = Vic[:, None], Vci[:, None], Uci[:, None]
+        Rup[t] += P.W[lam] / P.n0 * np.sum(Vij * I0[lam], axis=1)
+        Rdn[t] += P.W[lam] / P.n0 * np.sum(Uji + Vji * I0[lam], axis=1)
+    G = P.gamma(Rup, Rdn)
+    res = np.einsum("cij,jc->ic", G, pops)
+    scale = np.einsum("cij,jc->ic", np.abs(G), pops)
+    assert np.max(np.abs(res) / scale) < 1e-6
