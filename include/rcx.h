@@ -42,8 +42,12 @@ extern "C" {
 #define RCX_T_GEOMETRIC 0  /* t_0 = 0, t_i = c0_t1 * 4^(i-1)                    */
 #define RCX_T_LENGTH_X4 1  /* t_i = c0_t1 * (4^i - 1) / 3 (lengths x4)          */
 
-/* Storage of merged cascade radiance between levels. */
+/* Storage of merged cascade radiance between levels. F16_SCALED stores
+ * cascades >= 1 as FP16 with a per-wavelength power-of-two scale
+ * 2^(15 - ceil(log2 max S)), valid because no merged radiance exceeds the
+ * largest source function along its path; cascade 0 stays FP32. */
 #define RCX_STORE_F32 0
+#define RCX_STORE_F16_SCALED 1
 
 /* Uniform 2D grid. chi is per unit of voxel_scale length: the optical depth
  * of a path of dt cells is chi * dt * voxel_scale (Sec. 3.2). */
@@ -58,7 +62,7 @@ typedef struct {
  *               the cone centres theta = 2 pi (k + 1/2) / N_i.
  *   c0_t1:      end of the cascade-0 interval = start of cascade 1, in cells.
  *   t_rule:     RCX_T_GEOMETRIC or RCX_T_LENGTH_X4.
- *   storage:    RCX_STORE_F32.
+ *   storage:    RCX_STORE_F32 or RCX_STORE_F16_SCALED.
  *   n_incl:     inclination rays per flatland ray; must be 1 (flatland J).
  *   flags:      reserved, 0. */
 typedef struct {
@@ -130,6 +134,119 @@ int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_ot
 
 /* Release a plan and its device memory. NULL is accepted. */
 int32_t rcx_plan_destroy(rcx_plan* plan);
+
+/* ================================================================ non-LTE
+ * The non-LTE iteration of Sec. 3.3: opacities and emissivities from level
+ * populations, the radiance-cascades formal solution per wavelength with
+ * Doppler-shifted Voigt lines evaluated per ray step (Sec. 3.2), the
+ * diagonal cascade-0 operator and the "same-preconditioning" MALI rates
+ * (Rybicki & Hummer 1992, as adapted in Sec. 3.3), and the per-cell rate
+ * matrix Gamma solved in FP64 with its diagonal from conservation.
+ *
+ * Model: one atom, levels 0..n_levels-1 with the last level the continuum
+ * (ionised stage); every wavelength belongs to exactly one transition (its
+ * governing transition, Sec. 3.3), wavelengths are grouped by transition in
+ * the order lines then continua; no background opacity; flatland angular
+ * quadrature (weights 1/N_0); free-space boundary; electron density fixed. */
+
+#define RCX_NLTE_MAX_LEVELS 6
+#define RCX_NLTE_MAX_LINES 8
+#define RCX_NLTE_MAX_CONTS 4
+
+/* Atomic model (host struct). Energies in eV from the ground level;
+ * statistical weights; lines (lower, upper, rest wavelength [nm], oscillator
+ * strength f); bound-free continua (lower, upper = n_levels-1, edge
+ * wavelength [nm], cross-section at the edge [m^2], scaling as lambda^3
+ * below the edge); atomic mass [amu]; collisional de-excitation coefficients
+ * q_coll [m^3/s] per transition (lines first, then continua): the downward
+ * rate is n_e q (T / 1e4 K)^-1/2, the upward one follows by detailed
+ * balance. Natural damping of a line is the sum of the Einstein A of all
+ * lines leaving its upper and its lower level. */
+typedef struct {
+    int32_t n_levels, n_lines, n_conts, pad_;
+    double E_eV[RCX_NLTE_MAX_LEVELS];
+    double g[RCX_NLTE_MAX_LEVELS];
+    double mass_amu;
+    int32_t line_lower[RCX_NLTE_MAX_LINES], line_upper[RCX_NLTE_MAX_LINES];
+    double line_lambda_nm[RCX_NLTE_MAX_LINES], line_f[RCX_NLTE_MAX_LINES];
+    int32_t cont_lower[RCX_NLTE_MAX_CONTS], cont_upper[RCX_NLTE_MAX_CONTS];
+    double cont_edge_nm[RCX_NLTE_MAX_CONTS], cont_alpha0[RCX_NLTE_MAX_CONTS];
+    double q_coll[RCX_NLTE_MAX_LINES + RCX_NLTE_MAX_CONTS];
+} rcx_atom;
+
+typedef struct rcx_nlte rcx_nlte;
+
+/* Create a non-LTE solver for grid g (voxel_scale in metres) and the
+ * cascade parameters p, with n_wave wavelengths: lambda_nm_host[n_wave],
+ * trans_host[n_wave] (transition index of each wavelength, grouped and
+ * ordered as described above) and dnu_host[n_wave] (frequency quadrature
+ * weights of the rate integrals, Hz). All host arrays are copied.
+ * Errors: RCX_E_INVALID (nulls, sizes, ungrouped or out-of-range
+ * transitions, a wavelength outside its continuum's edge);
+ * RCX_E_UNSUPPORTED (more levels/lines/continua than the maxima);
+ * RCX_E_NOMEM; RCX_E_HIP. */
+int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* atom, int32_t n_wave,
+                        const double* lambda_nm_host, const int32_t* trans_host, const double* dnu_host,
+                        rcx_nlte** out);
+
+/* Atmosphere (device arrays, [nz][nx]): temperature T [K], electron
+ * density ne [m^-3], total atom density ntot [m^-3] (all levels incl. the
+ * ionised stage), velocity vel [2][nz][nx] float32 (vx, vz) [m/s]. Computes
+ * on the device in FP64 the Saha-Boltzmann populations, collisional rates,
+ * thermal widths and damping, and fills the Voigt table H(a, x) in FP64
+ * (Fourier-integral form of the Voigt function, Gauss-Legendre panels) for
+ * the damping range present. Synchronises the stream once (damping range). */
+int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, const double* ntot,
+                                const float* vel, hipStream_t stream);
+
+/* LTE (Saha-Boltzmann) populations [n_levels][nz][nx] float64 (device). */
+int32_t rcx_nlte_lte_populations(rcx_nlte* s, double* pops, hipStream_t stream);
+
+/* One formal solution at populations pops [n_levels][nz][nx] (device,
+ * float64): opacity synthesis, every cascade top-down per wavelength batch,
+ * and at cascade 0 the preconditioned rate coefficients. rates (device,
+ * float32, [n_trans][2][nz][nx]) receives, per transition t, the upward
+ * coefficient (multiplies n_lower) and the downward coefficient (multiplies
+ * n_upper):
+ *   up   = sum_{lambda,k} W w_k V_ij I_eff,
+ *   down = sum_{lambda,k} W w_k [V_ji I_eff + U_ji (1 - chi_t Psi*)],
+ *   I_eff = I - Psi* eta_t,  Psi* = (1 - e^{-chi l_k}) / chi,
+ * with W = 4 pi dnu / (h nu), w_k = 1/N_0, l_k the distance from the cell
+ * centre to its edge along direction k, chi_t and eta_t the transition's own
+ * opacity and emissivity at pops. J (device float32 [n_wave][nz][nx]) may
+ * be NULL. */
+int32_t rcx_nlte_formal_solve_rates(rcx_nlte* s, const double* pops, float* rates, float* J,
+                                    hipStream_t stream);
+
+/* Statistical equilibrium (Sec. 3.3): per cell, Gamma[j][i] = upward rate
+ * i->j plus collisions, Gamma[i][j] = downward, diagonal = minus the column
+ * sum (FP64), the row of the most populated level replaced by sum n = ntot,
+ * solved with partial pivoting in FP64; pops_inout updated in place.
+ * *max_rel_change_host = max over cells and levels of |n_new - n_old| /
+ * n_new (synchronises the stream). */
+int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops_inout,
+                         double* max_rel_change_host, hipStream_t stream);
+
+/* Plain iteration (no acceleration, Sec. 3.3) from pops_inout until the max
+ * relative change drops below tol or max_iter iterations: formal solution
+ * with rates, statistical equilibrium, repeat. Returns RCX_OK when
+ * converged, RCX_W_NOT_CONVERGED when max_iter was reached. *iters_host and
+ * *last_change_host report the iterations run and the last change.
+ * Synchronises the stream once per iteration (8 bytes). */
+int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, double tol,
+                         int32_t* iters_host, double* last_change_host, hipStream_t stream);
+
+/* Evaluate the device Voigt table (bilinear in (a, |x|), asymptotic series
+ * beyond its x range) at n points: a, x, out device float32 arrays. For
+ * checking the table against a reference. */
+int32_t rcx_nlte_voigt_eval(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out,
+                            hipStream_t stream);
+
+/* Number of transitions and of levels of the solver's atom. */
+int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* n_levels_host, int32_t* n_trans_host);
+
+/* Release the solver. NULL is accepted. */
+int32_t rcx_nlte_destroy(rcx_nlte* s);
 
 /* Static description of a status code. */
 const char* rcx_error_string(int32_t code);

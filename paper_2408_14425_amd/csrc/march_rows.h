@@ -1,0 +1,288 @@
+// march_rows.h -- the radiance-interval march + merge kernel (Osborne &
+// Sannikov, arXiv:2408.14425, Secs. 2.2-2.3 and 3.2), templated on how a ray
+// step obtains its opacity and source function (Op) and on what happens with
+// the merged radiance (Epi).
+//
+// A wavefront holds 4 rays x 16 wavelengths: each 16-lane row is one ray of
+// one 16-wavelength batch. The cell walk is cooperative per row: lane j
+// computes the one or two segments of the j-th grid column the ray crosses
+// along its major axis (plane crossings in FP64, so cell boundaries are
+// exact), the row compacts them into LDS, and all 16 wavelength lanes then
+// step through the list with the FP32 radiative update
+//   I += T S (1 - 2^{-y}),  T *= 2^{-y},  y = optical depth in log2 units,
+// front to back, which equals the back-to-front piecewise-constant solution
+// of Sec. 3.2. The merge with the cascade above (Sec. 2.3.1) follows:
+//   Itilde = I + T * sum_taps w_x w_z (1/4) sum_j Itilde_up(tap, 4k + j).
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "rcx_internal.h"
+
+namespace rcx {
+namespace march {
+
+constexpr int kBlock = 256;                       // 4 wavefronts
+constexpr int kRaysPerBlock = (kBlock / 64) * 4;  // 4 rows of 16 lanes per wavefront
+constexpr int kLB = 16;                           // wavelengths per batch = lanes per row
+constexpr unsigned kXcds = 8;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
+// contiguous range of logical blocks so rays that share cells share an L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    unsigned per = nb / kXcds, rem = nb % kXcds;
+    unsigned x = b % kXcds, slot = b / kXcds;
+    unsigned start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+    return start + slot;
+}
+
+// 1 - 2^{-y} for y >= 0 (y = optical depth in log2 units) without
+// cancellation: with x = y ln2, the series x - x^2/2 + x^3/6 below x = 1/64
+// (truncation < 2e-7 relative), the direct form above (< 4e-6 relative).
+__device__ __forceinline__ float one_minus_exp2_neg(float y, float e)
+{
+    constexpr float c1 = 0.6931471805599453f;  // ln 2
+    constexpr float c2 = 0.2402265069591007f;  // (ln 2)^2 / 2
+    constexpr float c3 = 0.0555041086648216f;  // (ln 2)^3 / 6
+    const float ser = y * (c1 - y * (c2 - y * c3));
+    return y < (1.0f / 64.0f) / c1 ? ser : 1.0f - e;
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Geometry of the ray a row marches.
+struct RayInfo {
+    int32_t k, u, v;  // direction, probe coordinates
+    int64_t ray;      // ray index within the cascade
+    double wx, wz;    // direction
+    bool active;
+};
+
+// Readers of the merged cascade above: FP32, or FP16 with a per-wavelength
+// power-of-two scale (value = stored * inv_scale).
+struct UpF32 {
+    const float* p;
+    __device__ __forceinline__ void init(int) {}
+    __device__ __forceinline__ float get(int64_t i) const { return p[i]; }
+};
+struct UpF16 {
+    const __half* p;
+    const float* inv_scale_b;  // [16] of this batch
+    float inv;
+    __device__ __forceinline__ void init(int l) { inv = inv_scale_b[l]; }
+    __device__ __forceinline__ float get(int64_t i) const { return __half2float(p[i]) * inv; }
+};
+
+template <class Op, class Epi, class Up>
+__global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
+                                                        const double4* __restrict__ dirs, Up up, int64_t total)
+{
+    // per wave, per row: (cell index, ds) entries
+    __shared__ uint4 seg[kBlock / 64][4][16];
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int row = lane >> 4;
+    const int l = lane & 15;
+    const uint64_t row_bits = 0xFFFFull << (16 * row);
+    const uint64_t lt_bits = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    op.init(l);
+    epi.init(l);
+    up.init(l);
+    {
+        uint4* sw = &seg[w][0][0];
+        sw[lane] = make_uint4(0u, 0u, 0u, 0u);
+        wave_sync();
+    }
+
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
+    for (int64_t base = ((int64_t)lb * (kBlock / 64) + w) * 4; base < total; base += stride) {
+        RayInfo ri;
+        ri.ray = base + row;
+        ri.active = ri.ray < total;
+        const int64_t rr = ri.active ? ri.ray : total - 1;
+        ri.k = (int32_t)(rr % L.nd);
+        const int32_t p = (int32_t)(rr / L.nd);
+        ri.u = p % L.px;
+        ri.v = p / L.px;
+
+        const double cx = (ri.u + 0.5) * L.s, cz = (ri.v + 0.5) * L.s;
+        const double4 d = dirs[ri.k];  // {wx, wz, 1/wx, 1/wz}
+        ri.wx = d.x;
+        ri.wz = d.y;
+        op.begin_ray(d.x, d.y);
+        // Plane crossings t(X) = X / w - c / w, evaluated with one FMA so the
+        // crossing of the domain's exit plane equals the clip bound exactly.
+        const double offx = -cx * d.z, offz = -cz * d.w;
+        const double ax = offx, bx = fma((double)nx, d.z, offx);
+        const double az = offz, bz = fma((double)nz, d.w, offz);
+        double lo = fmax(L.ta, fmax(fmin(ax, bx), fmin(az, bz)));
+        double hi = fmin(L.tb, fmin(fmax(ax, bx), fmax(az, bz)));
+        if (!ri.active) {
+            lo = 1.0;
+            hi = 0.0;
+        }
+
+        // Major axis m (the one crossed at least as often), minor axis n.
+        const bool xmaj = fabs(d.x) >= fabs(d.y);
+        const double wm = xmaj ? d.x : d.y, wn = xmaj ? d.y : d.x;
+        const double cm = xmaj ? cx : cz, cn = xmaj ? cz : cx;
+        const double im_ = xmaj ? d.z : d.w, in_ = xmaj ? d.w : d.z;
+        const double offm = xmaj ? offx : offz, offn = xmaj ? offz : offx;
+        const int nm = xmaj ? nx : nz, nn = xmaj ? nz : nx;
+        const int strm = xmaj ? 1 : nx, strn = xmaj ? nx : 1;
+        const int sm = wm > 0.0 ? 1 : -1, sn = wn > 0.0 ? 1 : -1;
+
+        const double pm0 = cm + lo * wm;
+        int im0 = wm > 0.0 ? (int)floor(pm0) : (int)ceil(pm0) - 1;
+        im0 = min(max(im0, 0), nm - 1);
+        const int mfirst = wm > 0.0 ? im0 + 1 : im0;  // first m-plane crossed
+
+        float I = 0.0f, T = 1.0f;
+        const int max_chunks = (nm + 2 + 15) / 16 + 1;
+        for (int chunk = 0; chunk < max_chunks; ++chunk) {
+            // ---- column j of this row's ray: one or two segments
+            const int j = chunk * 16 + l;
+            const double ta = (j == 0) ? lo : fma((double)(mfirst + (j - 1) * sm), im_, offm);
+            const double tb_ = fmin(fma((double)(mfirst + j * sm), im_, offm), hi);
+            const bool valid = ta < hi;
+            const int im = min(max(im0 + j * sm, 0), nm - 1);
+            const double pn = cn + ta * wn;
+            int in0 = wn > 0.0 ? (int)floor(pn) : (int)ceil(pn) - 1;
+            in0 = min(max(in0, 0), nn - 1);
+            const int nnext = wn > 0.0 ? in0 + 1 : in0;
+            const double tn = fma((double)nnext, in_, offn);
+            const bool two = valid && tn < tb_;
+            const double tmid = fmax(tn, ta);
+            const uint32_t cell1 = (uint32_t)(im * strm + in0 * strn);
+            const int in1 = min(max(in0 + sn, 0), nn - 1);
+            const uint32_t cell2 = (uint32_t)(im * strm + in1 * strn);
+            const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
+            const float ds2 = (float)fmax(tb_ - tmid, 0.0);
+
+            const uint64_t b1 = __ballot(valid);
+            if (b1 == 0) break;
+            const uint64_t b2 = __ballot(two);
+            const int pos = __popcll(b1 & row_bits & lt_bits) + __popcll(b2 & row_bits & lt_bits);
+            const int n_row = __popcll(b1 & row_bits) + __popcll(b2 & row_bits);
+            int n_max = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t rb = 0xFFFFull << (16 * q);
+                n_max = max(n_max, __popcll(b1 & rb) + __popcll(b2 & rb));
+            }
+            uint2* srow = reinterpret_cast<uint2*>(&seg[w][row][0]);
+            if (valid) srow[pos] = make_uint2(cell1, __float_as_uint(ds1));
+            if (two) srow[pos + 1] = make_uint2(cell2, __float_as_uint(ds2));
+            wave_sync();
+
+            // ---- step through the row's segments, 4 at a time. Positions past
+            // the row's count are steps with no opacity and no emission.
+            for (int s = 0; s < n_max; s += 4) {
+                const uint4 e01 = seg[w][row][s >> 1];
+                const uint4 e23 = seg[w][row][(s >> 1) + 1];
+                const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
+                const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
+                                      __uint_as_float(e23.w)};
+                typename Op::Raw raw[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float2 f = op.resolve(raw[q]);  // {optical depth per cell, log2 units; S}
+                    const float y = f.x * dsv[q];
+                    const float e = __builtin_amdgcn_exp2f(-y);
+                    I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
+                    T *= e;
+                }
+            }
+            wave_sync();
+        }
+
+        if (ri.active && L.has_up) {
+            // Bilinear taps on the cascade above: q = (u + 1/2)/2 - 1/2, so
+            // even u -> taps (u/2 - 1, u/2) with weights (1/4, 3/4), odd u ->
+            // taps ((u-1)/2, (u+1)/2) with weights (3/4, 1/4); clamped.
+            const int bx0 = (ri.u - 1) >> 1, bz0 = (ri.v - 1) >> 1;
+            const float fx = (ri.u & 1) ? 0.25f : 0.75f;
+            const float fz = (ri.v & 1) ? 0.25f : 0.75f;
+            const int txs[2] = {min(max(bx0, 0), L.qx - 1), min(max(bx0 + 1, 0), L.qx - 1)};
+            const int tzs[2] = {min(max(bz0, 0), L.qz - 1), min(max(bz0 + 1, 0), L.qz - 1)};
+            const float wxs[2] = {1.0f - fx, fx};
+            const float wzs[2] = {1.0f - fz, fz};
+            float far = 0.0f;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int64_t bi = (((int64_t)tzs[a] * L.qx + txs[bb]) * L.nd_up + 4 * (int64_t)ri.k) * kLB + l;
+                    const float c4 = up.get(bi) + up.get(bi + kLB) + up.get(bi + 2 * kLB) + up.get(bi + 3 * kLB);
+                    far = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far);
+                }
+            I = fmaf(T, far, I);
+        }
+        epi.finish(ri, l, lane, I, op);
+    }
+}
+
+// Epilogue that stores the merged radiance of every ray: out[ray][16].
+struct StoreEpi {
+    float* out;
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish(const RayInfo& ri, int l, int lane, float I, const Op&)
+    {
+        (void)lane;
+        if (ri.active) out[ri.ray * kLB + l] = I;
+    }
+};
+
+// Epilogue storing FP16 with a per-wavelength power-of-two scale
+// (stored = value * scale; the scale keeps the largest source function of
+// the wavelength below 2^15, and no merged radiance exceeds it).
+struct StoreF16Epi {
+    __half* out;
+    const float* scale_b;  // [16] of this batch
+    float sc;
+    __device__ __forceinline__ void init(int l) { sc = scale_b[l]; }
+    template <class Op>
+    __device__ __forceinline__ void finish(const RayInfo& ri, int l, int lane, float I, const Op&)
+    {
+        (void)lane;
+        if (ri.active) out[ri.ray * kLB + l] = __float2half_rn(I * sc);
+    }
+};
+
+// Opacity from a per-batch field F[c][16] = {optical depth per cell in log2
+// units, S}, read with buffer loads: an out-of-range offset returns 0.
+struct FieldOp {
+    const float2* Fb;
+    uint32_t fb_bytes;
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;
+    using Raw = float2;
+    __device__ __forceinline__ void init(int l)
+    {
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)Fb, 0, (int)fb_bytes, 0x00020000);
+        lane_off = (uint32_t)l * 8u;
+    }
+    __device__ __forceinline__ void begin_ray(double, double) {}
+    __device__ __forceinline__ void fetch(uint32_t cell, bool ok, Raw& r) const
+    {
+        const uint32_t off = ok ? cell * (uint32_t)(kLB * 8) + lane_off : 0x80000000u;
+        r = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+    }
+    __device__ __forceinline__ float2 resolve(const Raw& r) const { return r; }
+};
+
+}  // namespace march
+}  // namespace rcx

@@ -1,0 +1,966 @@
+// nlte.hip -- the non-LTE iteration around the radiance-cascades formal
+// solution (Osborne & Sannikov, arXiv:2408.14425, Sec. 3.3) on gfx950.
+//
+// Per iteration:
+//   k_synth      populations (FP64) -> per-cell line records and continuum
+//                fields (FP32) for the march, and per-cell records for the
+//                rate epilogue;
+//   march        every cascade top-down per 16-wavelength batch; line batches
+//                evaluate the Doppler-shifted Voigt opacity per ray step
+//                (Sec. 3.2: velocity-dependent terms per ray, observer frame);
+//   cascade 0    the march kernel with a rate epilogue: Psi*, I_eff and the
+//                preconditioned rate coefficients per (cell, direction,
+//                wavelength), reduced over the wavefront (16 wavelengths x 4
+//                directions of one cell) without atomics;
+//   k_rates_sum  per-transition sums over its batches, in a fixed order;
+//   k_stat_eq    Gamma per cell in FP64, diagonal from conservation, one row
+//                replaced by particle conservation, Gaussian elimination with
+//                partial pivoting; the max relative change is reduced with an
+//                integer atomic max on the (non-negative) FP64 bit pattern.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "march_rows.h"
+
+namespace rcx {
+namespace nl {
+
+using march::kBlock;
+using march::kLB;
+
+// CODATA 2018, SI
+constexpr double kH = 6.62607015e-34;
+constexpr double kC = 2.99792458e8;
+constexpr double kKB = 1.380649e-23;
+constexpr double kMe = 9.1093837015e-31;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kEps0 = 8.8541878128e-12;
+constexpr double kAmu = 1.66053906660e-27;
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kLog2eD = 1.4426950408889634074;
+
+constexpr int kMaxL = RCX_NLTE_MAX_LEVELS;
+constexpr int kMaxT = RCX_NLTE_MAX_LINES + RCX_NLTE_MAX_CONTS;
+
+// One transition as the device kernels see it.
+struct Trans {
+    int32_t kind;   // 0 line, 1 continuum
+    int32_t i, j;   // lower, upper level
+    int32_t line;   // line index (kind 0) or continuum index (kind 1)
+    double nu0;     // line centre / edge frequency [Hz]
+    double sigma;   // line: e^2 f / (4 eps0 m_e c) [m^2 Hz]; continuum: alpha at the edge [m^2]
+    double gr;      // g_i / g_j
+    double U0;      // line: 2 h nu0^3 / c^2
+    double gamma;   // line: natural damping [1/s]
+    double q;       // collisional de-excitation coefficient [m^3/s]
+};
+
+struct AtomDev {
+    int32_t nl, nt, n_lines, n_conts;
+    double E[kMaxL];  // [J]
+    double g[kMaxL];
+    double mass;      // [kg]
+    Trans t[kMaxT];
+};
+
+// ---------------------------------------------------------------- Voigt table
+// H(a, x) on a uniform grid a in [0, a_max] (kNa nodes), x in [0, kXTab]
+// (kNx nodes); each entry holds the pair {H(x_i), H(x_{i+1})} so one 8-byte
+// load gives both x neighbours. Beyond kXTab the asymptotic series
+// H ~ a / (sqrt(pi) x^2) (1 + 3/(2x^2) + 15/(4x^4) + 105/(8x^6) + 945/(16x^8))
+// is used (relative truncation < 1e-7 there; exp(-x^2) < 1e-27).
+constexpr int kNa = 41;
+constexpr double kXTab = 8.0;
+constexpr int kNx = 4097;  // dx = 1/512
+
+struct VoigtTab {
+    const float2* tab;
+    float inv_da;
+    float inv_dx;
+};
+
+__device__ __forceinline__ float voigt_lookup(const VoigtTab& V, float a, float ax)
+{
+    const float fa = fminf(fmaxf(a * V.inv_da, 0.0f), (float)(kNa - 1) - 1e-3f);
+    const int ia = (int)fa;
+    const float wa = fa - (float)ia;
+    const float fx = fminf(fmaxf(ax * V.inv_dx, 0.0f), (float)(kNx - 1) - 1e-3f);
+    const int ix = (int)fx;
+    const float wx = fx - (float)ix;
+    const float2 p0 = V.tab[ia * kNx + ix];
+    const float2 p1 = V.tab[(ia + 1) * kNx + ix];
+    const float h0 = fmaf(wx, p0.y - p0.x, p0.x);
+    const float h1 = fmaf(wx, p1.y - p1.x, p1.x);
+    const float ht = fmaf(wa, h1 - h0, h0);
+    const float r = 1.0f / fmaxf(ax * ax, 1.0f);
+    const float ser = 1.0f + r * (1.5f + r * (3.75f + r * (13.125f + r * 59.0625f)));
+    const float hs = a * 0.5641895835477563f * r * ser;  // a / sqrt(pi) / x^2 * series
+    return ax < (float)kXTab ? ht : hs;
+}
+
+// Fill: H(a, x) = pi^{-1/2} int_0^inf exp(-a t - t^2/4) cos(x t) dt (the
+// Fourier form of the Voigt function), integrated over [0, 13] (the
+// integrand is below 1e-18 beyond) with 8-point Gauss-Legendre on 104
+// panels of width 1/8, in FP64.
+__device__ double voigt_fourier(double a, double x)
+{
+    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double h = 0.125;
+    double acc = 0.0;
+    for (int p = 0; p < 104; ++p) {
+        const double c = (p + 0.5) * h;
+        for (int q = 0; q < 4; ++q) {
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double t = c + sgn * 0.5 * h * gx[q];
+                acc += gw[q] * exp(-a * t - 0.25 * t * t) * cos(x * t);
+            }
+        }
+    }
+    return acc * 0.5 * h / sqrt(kPi);
+}
+
+__global__ void k_voigt_fill(float2* tab, double da, double dx)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)kNa * kNx) return;
+    const int ia = (int)(idx / kNx), ix = (int)(idx % kNx);
+    const double a = ia * da;
+    const double h0 = voigt_fourier(a, ix * dx);
+    const double h1 = (ix + 1 < kNx) ? voigt_fourier(a, (ix + 1) * dx) : h0;
+    tab[idx] = make_float2((float)h0, (float)h1);
+}
+
+__global__ void k_voigt_eval(VoigtTab V, int32_t n, const float* a, const float* x, float* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = voigt_lookup(V, a[i], fabsf(x[i]));
+}
+
+// ------------------------------------------------------------ static data
+// Per cell, from T, ne, ntot (FP64): Saha-Boltzmann populations, collisional
+// rates, 1/v_th, line damping a and sigma/(sqrt(pi) dnu_D), and for each
+// continuum log2(n_i*/n_c*) and h/(k T) log2(e).
+struct StaticOut {
+    double* lte;       // [nl][ncell]
+    double* cup;       // [nt][ncell]
+    double* cdn;       // [nt][ncell]
+    float* inv_vth;    // [ncell]
+    float* adamp;      // [n_lines][ncell]
+    float* sphi;       // [n_lines][ncell]
+    float* lratio;     // [n_conts][ncell]
+    float* hkt2;       // [ncell]
+    unsigned int* amax_bits;  // max damping over cells and lines (float bits)
+};
+
+__global__ void k_static(AtomDev A, int64_t ncell, const double* __restrict__ T, const double* __restrict__ ne,
+                         const double* __restrict__ ntot, StaticOut o)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float amax = 0.0f;
+    if (c < ncell) {
+        const double t = T[c], e = ne[c], n = ntot[c];
+        const double kT = kKB * t;
+        double rel[kMaxL];
+        double sum = 0.0;
+        const int cl = A.nl - 1;  // continuum level
+        for (int l = 0; l < cl; ++l) {
+            rel[l] = A.g[l] / A.g[0] * exp(-(A.E[l] - A.E[0]) / kT);
+            sum += rel[l];
+        }
+        const double saha = 2.0 * pow(2.0 * kPi * kMe * kT / (kH * kH), 1.5) / e;
+        rel[cl] = A.g[cl] / A.g[0] * saha * exp(-(A.E[cl] - A.E[0]) / kT);
+        sum += rel[cl];
+        for (int l = 0; l < A.nl; ++l) o.lte[(int64_t)l * ncell + c] = rel[l] / sum * n;
+        const double vth = sqrt(2.0 * kKB * t / A.mass);
+        o.inv_vth[c] = (float)(1.0 / vth);
+        for (int k = 0; k < A.nt; ++k) {
+            const Trans& tr = A.t[k];
+            const double cd = e * tr.q / sqrt(t / 1e4);
+            o.cdn[(int64_t)k * ncell + c] = cd;
+            o.cup[(int64_t)k * ncell + c] = cd * rel[tr.j] / rel[tr.i];
+            if (tr.kind == 0) {
+                const double dnuD = tr.nu0 * vth / kC;
+                const float a = (float)(tr.gamma / (4.0 * kPi * dnuD));
+                o.adamp[(int64_t)tr.line * ncell + c] = a;
+                o.sphi[(int64_t)tr.line * ncell + c] = (float)(tr.sigma / (sqrt(kPi) * dnuD));
+                amax = fmaxf(amax, a);
+            } else {
+                o.lratio[(int64_t)tr.line * ncell + c] = (float)log2(rel[tr.i] / rel[tr.j]);
+            }
+        }
+        o.hkt2[c] = (float)(kH / kT * kLog2eD);
+    }
+    // block max of the damping, then one atomic per block (non-negative floats
+    // order like their bit patterns)
+    __shared__ float red[256];
+    red[threadIdx.x] = amax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(o.amax_bits, __float_as_uint(red[0]));
+}
+
+// -------------------------------------------------------------- synthesis
+// Lines: rec[line][c] = {kappa (optical depth per cell at H = 1, log2 units),
+// S_line, a, 1/v_th}, with kappa = sigma/(sqrt(pi) dnu_D) (n_i - g_i/g_j n_j)
+// voxel and S_line = U0 (g_i/g_j) n_j / (n_i - g_i/g_j n_j) (complete
+// redistribution: eta and chi share the profile); epi[line][c] = {n_i, n_j,
+// sigma/(sqrt(pi) dnu_D), 0}. Continua: epi[cont][c] = {n_i, n_c,
+// log2(n_i*/n_c*), h/(kT) log2 e}; their per-wavelength fields come from
+// k_synth_cont.
+constexpr float kChiFloor = 1e-20f;  // optical depth per cell, natural units
+
+struct SynthArgs {
+    const double* pops;  // [nl][ncell]
+    const float* inv_vth;
+    const float* adamp;
+    const float* sphi;
+    const float* lratio;
+    const float* hkt2;
+    float4* line_rec;    // [n_lines][ncell]
+    float4* epi_rec;     // [n_trans][ncell]
+    double voxel;
+};
+
+__global__ void k_synth(AtomDev A, int64_t ncell, SynthArgs s)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    for (int k = 0; k < A.nt; ++k) {
+        const Trans& tr = A.t[k];
+        const double ni = s.pops[(int64_t)tr.i * ncell + c];
+        const double nj = s.pops[(int64_t)tr.j * ncell + c];
+        if (tr.kind == 0) {
+            const double sp = s.sphi[(int64_t)tr.line * ncell + c];
+            const double dn = ni - tr.gr * nj;
+            double kap = sp * dn * s.voxel;  // natural units per cell
+            double S = tr.U0 * tr.gr * nj / dn;
+            if (!(kap >= kChiFloor)) {  // no (or inverted) line opacity: keep the emission finite
+                S = tr.U0 * tr.gr * nj * sp * s.voxel / kChiFloor;
+                kap = kChiFloor;
+            }
+            s.line_rec[(int64_t)tr.line * ncell + c] =
+                make_float4((float)(kap * kLog2eD), (float)S, s.adamp[(int64_t)tr.line * ncell + c], s.inv_vth[c]);
+            s.epi_rec[(int64_t)k * ncell + c] = make_float4((float)ni, (float)nj, (float)sp, 0.0f);
+        } else {
+            s.epi_rec[(int64_t)k * ncell + c] =
+                make_float4((float)ni, (float)nj, s.lratio[(int64_t)tr.line * ncell + c], s.hkt2[c]);
+        }
+    }
+}
+
+// Continuum batch b: F[b][c][l] = {kappa (log2 units per cell), S} with
+// chi = alpha (n_i - n_c (n_i*/n_c*) e^{-h nu/kT}), eta = (2 h nu^3/c^2) alpha
+// n_c (n_i*/n_c*) e^{-h nu/kT}, alpha = alpha0 (nu_edge/nu)^3 (FP64).
+struct ContBatch {
+    int32_t trans;
+    int32_t n;        // valid wavelengths in the batch
+    double nu[kLB];
+};
+
+__global__ void k_synth_cont(AtomDev A, int64_t ncell, const double* __restrict__ pops, const double* __restrict__ T,
+                             ContBatch cb, const float* lratio, double voxel, float2* __restrict__ Fb)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= ncell * kLB) return;
+    const int64_t c = idx / kLB;
+    const int l = (int)(idx % kLB);
+    float2 v = make_float2(0.0f, 0.0f);
+    if (l < cb.n) {
+        const Trans& tr = A.t[cb.trans];
+        const double ni = pops[(int64_t)tr.i * ncell + c];
+        const double nc = pops[(int64_t)tr.j * ncell + c];
+        const double nu = cb.nu[l];
+        const double alpha = tr.sigma * pow(tr.nu0 / nu, 3.0);
+        const double lr = lratio[(int64_t)tr.line * ncell + c];
+        const double stim = exp2(lr - kH * nu / (kKB * T[c]) * kLog2eD);  // (n_i*/n_c*) e^{-h nu / kT}
+        const double chi = alpha * (ni - nc * stim) * voxel;
+        const double eta = 2.0 * kH * nu * nu * nu / (kC * kC) * alpha * nc * stim * voxel;
+        if (chi >= kChiFloor)
+            v = make_float2((float)(chi * kLog2eD), (float)(eta / chi));
+        else
+            v = make_float2(kChiFloor * (float)kLog2eD, (float)(eta / kChiFloor));
+    }
+    Fb[idx] = v;
+}
+
+// ------------------------------------------------------------ line march op
+// Opacity of a line batch at one ray step: x = (u_l + w . v) / v_th (the
+// profile of a ray looking along w, photons travelling along -w, in the
+// observer's frame), chi = kappa H(a, |x|), S = S_line.
+struct LineOp {
+    const float4* rec;  // [ncell]
+    const float2* vel;  // [ncell]
+    VoigtTab vt;
+    const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
+    float u, wx, wz;
+    struct Raw {
+        float4 r;
+        float2 v;
+        bool ok;
+    };
+    __device__ __forceinline__ void init(int l) { u = u_b[l]; }
+    __device__ __forceinline__ void begin_ray(double dwx, double dwz)
+    {
+        wx = (float)dwx;
+        wz = (float)dwz;
+    }
+    __device__ __forceinline__ void fetch(uint32_t cell, bool ok, Raw& raw) const
+    {
+        const uint32_t c = ok ? cell : 0u;
+        raw.r = rec[c];
+        raw.v = vel[c];
+        raw.ok = ok;
+    }
+    __device__ __forceinline__ float profile(const float4& r, const float2& v) const
+    {
+        const float x = (u + wx * v.x + wz * v.y) * r.w;
+        return voigt_lookup(vt, r.z, fabsf(x));
+    }
+    __device__ __forceinline__ float2 resolve(const Raw& raw) const
+    {
+        const float H = profile(raw.r, raw.v);
+        return make_float2(raw.ok ? raw.r.x * H : 0.0f, raw.r.y);
+    }
+};
+
+// ----------------------------------------------------------- rate epilogue
+// At cascade 0 every wavefront holds the 4 directions (rows) x 16
+// wavelengths of one cell. Each lane forms, with I the merged radiance,
+//   Psi* = l (1 - e^{-tau}) / tau,  tau = chi_t l  (l = distance from the
+//          cell centre to its edge along the ray, m)
+//   I_eff = I - Psi* eta_t
+//   up   = W V_ij I_eff,   down = W (V_ji I_eff + U_ji (1 - chi_t Psi*))
+// (W = 4 pi dnu/(h nu) / N_0 per lane, 0 on padding lanes); the wavefront sum
+// goes to part[c] = {up, down}.
+struct RatesEpi {
+    float* out;             // merged cascade 0 [rays][16] (for J)
+    float2* part;           // [ncell] this batch's rate contributions
+    const float4* epi_rec;  // [ncell] of the batch's transition
+    const float* W;         // [16]
+    const float* nu;        // [16] (continuum batches)
+    const float* alpha;     // [16] alpha(nu) (continuum batches)
+    const float* U0c;       // [16] 2 h nu^3 / c^2 (continuum batches)
+    float gr, U0;           // line: g_i/g_j, 2 h nu0^3 / c^2
+    float ell_cells, voxel; // l in cells (the same for all N_0 directions), cell size [m]
+    int32_t kind;           // 0 line, 1 continuum
+
+    __device__ __forceinline__ void init(int) {}
+
+    template <class Op>
+    __device__ __forceinline__ void finish(const march::RayInfo& ri, int l, int lane, float I, const Op& op)
+    {
+        if (ri.active) out[ri.ray * kLB + l] = I;
+        const int64_t cell = ri.ray / 4;  // cascade 0: ray = cell * 4 + direction
+        float up = 0.0f, dn = 0.0f;
+        if (ri.active) {
+            const float4 e = epi_rec[cell];
+            float Vij, Vji, Uji;
+            if (kind == 0) {
+                const float H = line_profile(op, (uint32_t)cell);
+                Vij = e.z * H;
+                Vji = gr * Vij;
+                Uji = U0 * Vji;
+            } else {
+                Vij = alpha[l];
+                Vji = Vij * __builtin_amdgcn_exp2f(fminf(e.z - nu[l] * e.w, 126.0f));
+                Uji = U0c[l] * Vji;
+            }
+            const float eta_t = e.y * Uji;
+            const float chi_t = e.x * Vij - e.y * Vji;   // [1/m]
+            const float ellm = ell_cells * voxel;
+            const float tau = fmaxf(chi_t * ellm, 0.0f);
+            // phi1 = (1 - e^{-tau}) / tau: series below 1/64, direct above
+            const float ser = 1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f)));
+            const float phi1 = tau < (1.0f / 64.0f) ? ser : (1.0f - __builtin_amdgcn_exp2f(-tau * march::kLog2e)) / tau;
+            const float psi = ellm * phi1;
+            const float ieff = I - psi * eta_t;
+            const float wv = W[l];
+            up = (wv * Vij) * ieff;
+            dn = (wv * Vji) * ieff + (wv * Uji) * (1.0f - chi_t * psi);
+        }
+        // wavefront sum (fixed butterfly order: deterministic)
+        for (int m = 32; m >= 1; m >>= 1) {
+            up += __shfl_xor(up, m);
+            dn += __shfl_xor(dn, m);
+        }
+        if (lane == 0 && ri.active) part[cell] = make_float2(up, dn);
+    }
+
+    // H at the cell itself along the ray (only a LineOp has a profile).
+    __device__ __forceinline__ float line_profile(const LineOp& op, uint32_t cell) const
+    {
+        return op.profile(op.rec[cell], op.vel[cell]);
+    }
+    __device__ __forceinline__ float line_profile(const march::FieldOp&, uint32_t) const { return 0.0f; }
+};
+
+// ------------------------------------------------------------- rate sums
+// rates[t][0|1][c] = sum over the batches of transition t (fixed order).
+__global__ void k_rates_sum(int64_t ncell, int32_t nt, const int32_t* __restrict__ tb0, const int32_t* __restrict__ tb1,
+                            const float2* __restrict__ part, float* __restrict__ rates)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    for (int t = 0; t < nt; ++t) {
+        double u = 0.0, d = 0.0;
+        for (int b = tb0[t]; b < tb1[t]; ++b) {
+            const float2 p = part[(int64_t)b * ncell + c];
+            u += p.x;
+            d += p.y;
+        }
+        rates[((int64_t)t * 2 + 0) * ncell + c] = (float)u;
+        rates[((int64_t)t * 2 + 1) * ncell + c] = (float)d;
+    }
+}
+
+// ------------------------------------------------- statistical equilibrium
+template <int NL>
+__global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const float* __restrict__ rates,
+                                                  const double* __restrict__ cup, const double* __restrict__ cdn,
+                                                  const double* __restrict__ ntot, double* __restrict__ pops,
+                                                  unsigned long long* __restrict__ max_change)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double change = 0.0;
+    if (c < ncell) {
+        double n[NL], G[NL][NL + 1];
+        for (int l = 0; l < NL; ++l) {
+            n[l] = pops[(int64_t)l * ncell + c];
+            for (int m = 0; m <= NL; ++m) G[l][m] = 0.0;
+        }
+        for (int k = 0; k < A.nt; ++k) {
+            const Trans& tr = A.t[k];
+            const double up = (double)rates[((int64_t)k * 2 + 0) * ncell + c] + cup[(int64_t)k * ncell + c];
+            const double dn = (double)rates[((int64_t)k * 2 + 1) * ncell + c] + cdn[(int64_t)k * ncell + c];
+            G[tr.j][tr.i] += up;
+            G[tr.i][tr.j] += dn;
+        }
+        for (int m = 0; m < NL; ++m) {  // diagonal: minus the column sum
+            double s = 0.0;
+            for (int l = 0; l < NL; ++l)
+                if (l != m) s += G[l][m];
+            G[m][m] = -s;
+        }
+        int r = 0;
+        for (int l = 1; l < NL; ++l)
+            if (n[l] > n[r]) r = l;
+        for (int m = 0; m < NL; ++m) G[r][m] = 1.0;
+        G[r][NL] = ntot[c];
+        // Gaussian elimination with partial pivoting on the augmented matrix
+        for (int col = 0; col < NL; ++col) {
+            int piv = col;
+            for (int l = col + 1; l < NL; ++l)
+                if (fabs(G[l][col]) > fabs(G[piv][col])) piv = l;
+            if (piv != col)
+                for (int m = 0; m <= NL; ++m) {
+                    const double t = G[col][m];
+                    G[col][m] = G[piv][m];
+                    G[piv][m] = t;
+                }
+            const double inv = 1.0 / G[col][col];
+            for (int l = col + 1; l < NL; ++l) {
+                const double f = G[l][col] * inv;
+                for (int m = col; m <= NL; ++m) G[l][m] -= f * G[col][m];
+            }
+        }
+        double x[NL];
+        for (int l = NL - 1; l >= 0; --l) {
+            double s = G[l][NL];
+            for (int m = l + 1; m < NL; ++m) s -= G[l][m] * x[m];
+            x[l] = s / G[l][l];
+        }
+        for (int l = 0; l < NL; ++l) {
+            change = fmax(change, fabs(x[l] - n[l]) / fabs(x[l]));
+            pops[(int64_t)l * ncell + c] = x[l];
+        }
+        if (!(change == change)) change = INFINITY;  // NaN: report as non-convergence
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = change;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(max_change, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+}  // namespace nl
+}  // namespace rcx
+
+// ====================================================================== host
+
+using namespace rcx;
+using namespace rcx::nl;
+
+struct rcx_nlte {
+    rcx_plan* plan = nullptr;
+    AtomDev atom{};
+    int32_t n_wave = 0;
+    int64_t ncell = 0;
+    double voxel = 1.0;
+    std::vector<double> lam_nm, dnu;
+    std::vector<int32_t> trans;
+    struct Batch {
+        int32_t trans, lam0, n, cont_slot;  // cont_slot: index of the continuum field slice, or -1
+    };
+    std::vector<Batch> batches;
+    std::vector<int32_t> tb0, tb1;  // batch range of each transition
+    int32_t n_cont_batches = 0;
+    // device
+    float* bconst = nullptr;  // [n_batch][5][16]: W/N0, u, nu, alpha, 2 h nu^3 / c^2
+    int32_t* d_tb = nullptr;  // [2][nt]
+    double *lte = nullptr, *cup = nullptr, *cdn = nullptr, *T = nullptr, *ntot = nullptr;
+    float *inv_vth = nullptr, *adamp = nullptr, *sphi = nullptr, *lratio = nullptr, *hkt2 = nullptr;
+    float2* vel = nullptr;
+    float4* line_rec = nullptr;
+    float4* epi_rec = nullptr;
+    float2* Fcont = nullptr;
+    float* casc[2] = {nullptr, nullptr};
+    float2* part = nullptr;
+    float* rates = nullptr;
+    unsigned long long* d_max = nullptr;
+    unsigned int* d_amax = nullptr;
+    float2* vtab = nullptr;
+    float v_inv_da = 0.0f;
+    bool atm_set = false;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int32_t nlte_fail(int32_t code, const std::string& m) { return rcx::fail(code, m); }
+
+template <class P>
+hipError_t dmalloc(rcx_nlte* s, P** p, size_t bytes)
+{
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes < 256 ? 256 : bytes);
+    if (e == hipSuccess) s->allocs.push_back(q);
+    *p = (P*)q;
+    return e;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_zero_u32(unsigned int* p) { *p = 0u; }
+
+// [2][ncell] planar velocity -> interleaved {vx, vz}
+__global__ void k_pack_vel(int64_t ncell, const float* __restrict__ v, float2* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncell) out[c] = make_float2(v[c], v[ncell + c]);
+}
+
+unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <class Op, class Epi>
+hipError_t launch_level(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+                        const float* up, hipStream_t st)
+{
+    const int64_t total = (int64_t)L.px * L.pz * L.nd;
+    const march::UpF32 u{up};
+    hipLaunchKernelGGL((march::k_march_rows<Op, Epi, march::UpF32>), march_grid(total), dim3(kBlock), 0, st, L, nx,
+                       nz, op, epi, dirs, u, total);
+    return hipGetLastError();
+}
+
+template <int NL>
+hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_stat_eq<NL>, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->atom, s->ncell, rates,
+                       s->cup, s->cdn, s->ntot, pops, s->d_max);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* atom, int32_t n_wave,
+                        const double* lambda_nm_host, const int32_t* trans_host, const double* dnu_host, rcx_nlte** out)
+{
+    if (out) *out = nullptr;
+    if (!g || !p || !atom || !lambda_nm_host || !trans_host || !dnu_host || !out)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: null argument");
+    if (n_wave <= 0) return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: n_wave must be positive");
+    if (atom->n_levels < 2 || atom->n_levels > RCX_NLTE_MAX_LEVELS || atom->n_lines < 0 ||
+        atom->n_lines > RCX_NLTE_MAX_LINES || atom->n_conts < 0 || atom->n_conts > RCX_NLTE_MAX_CONTS)
+        return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: atom exceeds the supported sizes");
+    if (p->c0_dirs != 4) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: the rate epilogue needs c0_dirs = 4");
+    const int32_t nt = atom->n_lines + atom->n_conts;
+    if (nt < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: no transitions");
+    for (int32_t k = 0; k < atom->n_lines; ++k)
+        if (atom->line_lower[k] < 0 || atom->line_upper[k] >= atom->n_levels ||
+            atom->line_lower[k] >= atom->line_upper[k] || !(atom->line_lambda_nm[k] > 0) || !(atom->line_f[k] > 0))
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: bad line definition");
+    for (int32_t k = 0; k < atom->n_conts; ++k)
+        if (atom->cont_lower[k] < 0 || atom->cont_upper[k] != atom->n_levels - 1 || !(atom->cont_edge_nm[k] > 0))
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: bad continuum definition (upper must be the last level)");
+    // wavelengths grouped by transition, in transition order
+    for (int32_t l = 0; l < n_wave; ++l) {
+        if (trans_host[l] < 0 || trans_host[l] >= nt)
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: transition index out of range");
+        if (l > 0 && trans_host[l] < trans_host[l - 1])
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: wavelengths must be grouped by ascending transition");
+        if (!(lambda_nm_host[l] > 0) || !(dnu_host[l] >= 0))
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: bad wavelength or weight");
+        const int32_t t = trans_host[l];
+        if (t >= atom->n_lines && lambda_nm_host[l] > atom->cont_edge_nm[t - atom->n_lines] * (1 + 1e-12))
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: continuum wavelength beyond its edge");
+    }
+
+    rcx_nlte* s = new (std::nothrow) rcx_nlte();
+    if (!s) return nlte_fail(RCX_E_NOMEM, "rcx_nlte_create: host allocation");
+    int32_t rc = rcx_plan_create(g, p, kLB, &s->plan);
+    if (rc != RCX_OK) {
+        delete s;
+        return rc;
+    }
+    s->n_wave = n_wave;
+    s->ncell = (int64_t)g->nx * g->nz;
+    s->voxel = g->voxel_scale;
+    s->lam_nm.assign(lambda_nm_host, lambda_nm_host + n_wave);
+    s->dnu.assign(dnu_host, dnu_host + n_wave);
+    s->trans.assign(trans_host, trans_host + n_wave);
+
+    // atom in SI
+    AtomDev& A = s->atom;
+    A.nl = atom->n_levels;
+    A.nt = nt;
+    A.n_lines = atom->n_lines;
+    A.n_conts = atom->n_conts;
+    for (int l = 0; l < A.nl; ++l) {
+        A.E[l] = atom->E_eV[l] * kQe;
+        A.g[l] = atom->g[l];
+    }
+    A.mass = atom->mass_amu * kAmu;
+    for (int k = 0; k < atom->n_lines; ++k) {
+        Trans& t = A.t[k];
+        t.kind = 0;
+        t.i = atom->line_lower[k];
+        t.j = atom->line_upper[k];
+        t.line = k;
+        t.nu0 = kC / (atom->line_lambda_nm[k] * 1e-9);
+        t.sigma = kQe * kQe * atom->line_f[k] / (4.0 * kEps0 * kMe * kC);
+        t.gr = A.g[t.i] / A.g[t.j];
+        t.U0 = 2.0 * kH * t.nu0 * t.nu0 * t.nu0 / (kC * kC);
+        t.q = atom->q_coll[k];
+    }
+    std::vector<double> Aein(atom->n_lines);
+    for (int k = 0; k < atom->n_lines; ++k) {
+        const Trans& t = A.t[k];
+        Aein[k] = 2.0 * kPi * kQe * kQe * t.nu0 * t.nu0 * A.g[t.i] * atom->line_f[k] /
+                  (kEps0 * kMe * kC * kC * kC * A.g[t.j]);
+    }
+    for (int k = 0; k < atom->n_lines; ++k) {  // natural damping: A out of the upper and the lower level
+        double gsum = 0.0;
+        for (int m = 0; m < atom->n_lines; ++m)
+            if (A.t[m].j == A.t[k].j || A.t[m].j == A.t[k].i) gsum += Aein[m];
+        A.t[k].gamma = gsum;
+    }
+    for (int k = 0; k < atom->n_conts; ++k) {
+        Trans& t = A.t[atom->n_lines + k];
+        t.kind = 1;
+        t.i = atom->cont_lower[k];
+        t.j = atom->cont_upper[k];
+        t.line = k;
+        t.nu0 = kC / (atom->cont_edge_nm[k] * 1e-9);
+        t.sigma = atom->cont_alpha0[k];
+        t.gr = A.g[t.i] / A.g[t.j];
+        t.q = atom->q_coll[atom->n_lines + k];
+    }
+
+    // batches of <= 16 wavelengths within each transition's group
+    s->tb0.assign(nt, 0);
+    s->tb1.assign(nt, 0);
+    int32_t l = 0;
+    for (int32_t t = 0; t < nt; ++t) {
+        s->tb0[t] = (int32_t)s->batches.size();
+        while (l < n_wave && s->trans[l] == t) {
+            int32_t n = 0;
+            while (n < kLB && l + n < n_wave && s->trans[l + n] == t) ++n;
+            const int32_t slot = A.t[t].kind == 1 ? s->n_cont_batches++ : -1;
+            s->batches.push_back({t, l, n, slot});
+            l += n;
+        }
+        s->tb1[t] = (int32_t)s->batches.size();
+    }
+    const int32_t nb = (int32_t)s->batches.size();
+    std::vector<float> bc((size_t)nb * 5 * kLB, 0.0f);
+    for (int32_t b = 0; b < nb; ++b) {
+        const auto& B = s->batches[b];
+        const Trans& t = A.t[B.trans];
+        for (int32_t q = 0; q < B.n; ++q) {
+            const int32_t lam = B.lam0 + q;
+            const double nu = kC / (s->lam_nm[lam] * 1e-9);
+            float* row = &bc[(size_t)b * 5 * kLB];
+            row[0 * kLB + q] = (float)(4.0 * kPi * s->dnu[lam] / (kH * nu) / 4.0);
+            if (t.kind == 0) {
+                row[1 * kLB + q] = (float)(kC * (nu - t.nu0) / t.nu0);
+            } else {
+                row[2 * kLB + q] = (float)nu;
+                row[3 * kLB + q] = (float)(t.sigma * std::pow(t.nu0 / nu, 3.0));
+                row[4 * kLB + q] = (float)(2.0 * kH * nu * nu * nu / (kC * kC));
+            }
+        }
+    }
+    const int64_t nc = s->ncell;
+    int64_t max_entries = 0;
+    for (const auto& L : s->plan->levels) max_entries = std::max<int64_t>(max_entries, (int64_t)L.px * L.pz * L.nd);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) {
+        if (r != hipSuccess && e == hipSuccess) e = r;
+    };
+    chk(dmalloc(s, &s->bconst, bc.size() * sizeof(float)));
+    chk(dmalloc(s, &s->d_tb, sizeof(int32_t) * 2 * nt));
+    chk(dmalloc(s, &s->lte, sizeof(double) * A.nl * nc));
+    chk(dmalloc(s, &s->cup, sizeof(double) * nt * nc));
+    chk(dmalloc(s, &s->cdn, sizeof(double) * nt * nc));
+    chk(dmalloc(s, &s->T, sizeof(double) * nc));
+    chk(dmalloc(s, &s->ntot, sizeof(double) * nc));
+    chk(dmalloc(s, &s->inv_vth, sizeof(float) * nc));
+    chk(dmalloc(s, &s->adamp, sizeof(float) * std::max(1, A.n_lines) * nc));
+    chk(dmalloc(s, &s->sphi, sizeof(float) * std::max(1, A.n_lines) * nc));
+    chk(dmalloc(s, &s->lratio, sizeof(float) * std::max(1, A.n_conts) * nc));
+    chk(dmalloc(s, &s->hkt2, sizeof(float) * nc));
+    chk(dmalloc(s, &s->vel, sizeof(float2) * nc));
+    chk(dmalloc(s, &s->line_rec, sizeof(float4) * std::max(1, A.n_lines) * nc));
+    chk(dmalloc(s, &s->epi_rec, sizeof(float4) * nt * nc));
+    chk(dmalloc(s, &s->Fcont, sizeof(float2) * std::max(1, s->n_cont_batches) * nc * kLB));
+    chk(dmalloc(s, &s->casc[0], sizeof(float) * max_entries * kLB));
+    chk(dmalloc(s, &s->casc[1], sizeof(float) * max_entries * kLB));
+    chk(dmalloc(s, &s->part, sizeof(float2) * nb * nc));
+    chk(dmalloc(s, &s->rates, sizeof(float) * 2 * nt * nc));
+    chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
+    chk(dmalloc(s, &s->d_amax, sizeof(unsigned int)));
+    chk(dmalloc(s, &s->vtab, sizeof(float2) * kNa * kNx));
+    if (e != hipSuccess) {
+        rcx_nlte_destroy(s);
+        return nlte_fail(RCX_E_NOMEM, std::string("rcx_nlte_create: hipMalloc: ") + hipGetErrorName(e));
+    }
+    std::vector<int32_t> tb(2 * nt);
+    for (int t = 0; t < nt; ++t) {
+        tb[t] = s->tb0[t];
+        tb[nt + t] = s->tb1[t];
+    }
+    chk(hipMemcpy(s->bconst, bc.data(), bc.size() * sizeof(float), hipMemcpyHostToDevice));
+    chk(hipMemcpy(s->d_tb, tb.data(), tb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (e != hipSuccess) {
+        rcx_nlte_destroy(s);
+        return rcx::hip_fail(e, "rcx_nlte_create: hipMemcpy");
+    }
+    *out = s;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, const double* ntot, const float* vel,
+                                hipStream_t st)
+{
+    if (!s || !T || !ne || !ntot || !vel) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_atmosphere: null argument");
+    const int64_t nc = s->ncell;
+    RCX_HIP_TRY(hipMemcpyAsync(s->T, T, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    RCX_HIP_TRY(hipMemcpyAsync(s->ntot, ntot, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_pack_vel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, vel, s->vel);
+    RCX_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, s->d_amax);
+    RCX_HIP_TRY(hipGetLastError());
+    StaticOut o{s->lte, s->cup, s->cdn, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->d_amax};
+    hipLaunchKernelGGL(k_static, dim3(blocks_for(nc, 256)), dim3(256), 0, st, s->atom, nc, s->T, ne, s->ntot, o);
+    RCX_HIP_TRY(hipGetLastError());
+    unsigned int bits = 0;
+    RCX_HIP_TRY(hipMemcpyAsync(&bits, s->d_amax, sizeof(bits), hipMemcpyDeviceToHost, st));
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    float amax;
+    std::memcpy(&amax, &bits, sizeof(amax));
+    if (!(amax == amax)) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_atmosphere: damping is not finite (check T)");
+    const double a_top = std::max(1.02 * (double)amax, 1e-8);
+    const double da = a_top / (kNa - 1);
+    s->v_inv_da = (float)(1.0 / da);
+    hipLaunchKernelGGL(k_voigt_fill, dim3(blocks_for((int64_t)kNa * kNx, 128)), dim3(128), 0, st, s->vtab, da,
+                       kXTab / (kNx - 1));
+    RCX_HIP_TRY(hipGetLastError());
+    s->atm_set = true;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_lte_populations(rcx_nlte* s, double* pops, hipStream_t st)
+{
+    if (!s || !pops) return nlte_fail(RCX_E_INVALID, "rcx_nlte_lte_populations: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_lte_populations: set the atmosphere first");
+    RCX_HIP_TRY(hipMemcpyAsync(pops, s->lte, sizeof(double) * s->atom.nl * s->ncell, hipMemcpyDeviceToDevice, st));
+    return RCX_OK;
+}
+
+static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates, float* J, hipStream_t st)
+{
+    const rcx_plan* P = s->plan;
+    const int32_t nx = P->grid.nx, nz = P->grid.nz;
+    const int64_t nc = s->ncell;
+    const AtomDev& A = s->atom;
+    SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel};
+    hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
+    RCX_HIP_TRY(hipGetLastError());
+    const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
+    for (size_t b = 0; b < s->batches.size(); ++b) {
+        const auto& B = s->batches[b];
+        const Trans& tr = A.t[B.trans];
+        const float* bc = s->bconst + b * 5 * kLB;
+        float2* Fb = s->Fcont + (size_t)std::max(B.cont_slot, 0) * nc * kLB;
+        if (tr.kind == 1) {
+            ContBatch cb{};
+            cb.trans = B.trans;
+            cb.n = B.n;
+            for (int q = 0; q < B.n; ++q) cb.nu[q] = kC / (s->lam_nm[B.lam0 + q] * 1e-9);
+            hipLaunchKernelGGL(k_synth_cont, dim3(blocks_for(nc * kLB, 256)), dim3(256), 0, st, A, nc, pops, s->T, cb,
+                               s->lratio, s->voxel, Fb);
+            RCX_HIP_TRY(hipGetLastError());
+        }
+        march::FieldOp fop{};
+        fop.Fb = Fb;
+        fop.fb_bytes = (uint32_t)(nc * kLB * sizeof(float2));
+        LineOp lop{};
+        if (tr.kind == 0) {
+            lop.rec = s->line_rec + (size_t)tr.line * nc;
+            lop.vel = s->vel;
+            lop.vt = vt;
+            lop.u_b = bc + 1 * kLB;
+        }
+        RatesEpi re{};
+        re.part = s->part + b * nc;
+        re.epi_rec = s->epi_rec + (size_t)B.trans * nc;
+        re.W = bc;
+        re.nu = bc + 2 * kLB;
+        re.alpha = bc + 3 * kLB;
+        re.U0c = bc + 4 * kLB;
+        re.gr = (float)tr.gr;
+        re.U0 = (float)tr.U0;
+        re.ell_cells = (float)std::sqrt(0.5);
+        re.voxel = (float)s->voxel;
+        re.kind = tr.kind;
+        int cur = 0;
+        const float* up = nullptr;
+        for (int32_t i = P->n_casc - 1; i >= 0; --i) {
+            if (P->top_skipped && i == P->n_casc - 1) continue;
+            const LevelDesc& L = P->levels[i];
+            const double4* dirs = P->dirs_dev + P->dir_off[i];
+            float* outb = s->casc[cur];
+            const float* upl = L.has_up ? up : nullptr;
+            hipError_t e;
+            if (i > 0) {
+                march::StoreEpi se{outb};
+                e = tr.kind == 0 ? launch_level(L, nx, nz, lop, se, dirs, upl, st)
+                                 : launch_level(L, nx, nz, fop, se, dirs, upl, st);
+            } else {
+                re.out = outb;
+                e = tr.kind == 0 ? launch_level(L, nx, nz, lop, re, dirs, upl, st)
+                                 : launch_level(L, nx, nz, fop, re, dirs, upl, st);
+            }
+            RCX_HIP_TRY(e);
+            up = outb;
+            cur ^= 1;
+        }
+        if (J) RCX_HIP_TRY(launch_j(up, J, B.lam0, B.n, nc, 4, st));
+    }
+    hipLaunchKernelGGL(k_rates_sum, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, A.nt, s->d_tb, s->d_tb + A.nt,
+                       s->part, rates);
+    RCX_HIP_TRY(hipGetLastError());
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_formal_solve_rates(rcx_nlte* s, const double* pops, float* rates, float* J, hipStream_t st)
+{
+    if (!s || !pops || !rates) return nlte_fail(RCX_E_INVALID, "rcx_nlte_formal_solve_rates: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_formal_solve_rates: set the atmosphere first");
+    return formal_solve_rates(s, pops, rates, J, st);
+}
+
+static int32_t stat_eq(rcx_nlte* s, const float* rates, double* pops, double* change_host, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, s->d_max);
+    RCX_HIP_TRY(hipGetLastError());
+    hipError_t e = hipErrorInvalidValue;
+    switch (s->atom.nl) {
+    case 2: e = launch_se<2>(s, rates, pops, st); break;
+    case 3: e = launch_se<3>(s, rates, pops, st); break;
+    case 4: e = launch_se<4>(s, rates, pops, st); break;
+    case 5: e = launch_se<5>(s, rates, pops, st); break;
+    case 6: e = launch_se<6>(s, rates, pops, st); break;
+    default: return nlte_fail(RCX_E_UNSUPPORTED, "stat_eq: level count");
+    }
+    RCX_HIP_TRY(e);
+    unsigned long long bits = 0;
+    RCX_HIP_TRY(hipMemcpyAsync(&bits, s->d_max, sizeof(bits), hipMemcpyDeviceToHost, st));
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    double ch;
+    std::memcpy(&ch, &bits, sizeof(ch));
+    *change_host = ch;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops, double* change_host, hipStream_t st)
+{
+    if (!s || !rates || !pops || !change_host) return nlte_fail(RCX_E_INVALID, "rcx_nlte_stat_eq: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_stat_eq: set the atmosphere first");
+    return stat_eq(s, rates, pops, change_host, st);
+}
+
+int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops, int32_t max_iter, double tol, int32_t* iters_host,
+                         double* last_change_host, hipStream_t st)
+{
+    if (!s || !pops || !iters_host || !last_change_host)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_iterate: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_iterate: set the atmosphere first");
+    if (max_iter < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_iterate: max_iter must be >= 1");
+    *iters_host = 0;
+    *last_change_host = INFINITY;
+    for (int32_t it = 0; it < max_iter; ++it) {
+        int32_t rc = formal_solve_rates(s, pops, s->rates, nullptr, st);
+        if (rc != RCX_OK) return rc;
+        double ch = 0.0;
+        rc = stat_eq(s, s->rates, pops, &ch, st);
+        if (rc != RCX_OK) return rc;
+        *iters_host = it + 1;
+        *last_change_host = ch;
+        if (ch < tol) return RCX_OK;
+    }
+    return RCX_W_NOT_CONVERGED;
+}
+
+int32_t rcx_nlte_voigt_eval(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out, hipStream_t st)
+{
+    if (!s || !a || !x || !out || n < 0) return nlte_fail(RCX_E_INVALID, "rcx_nlte_voigt_eval: bad argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_voigt_eval: set the atmosphere first");
+    if (n == 0) return RCX_OK;
+    const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
+    hipLaunchKernelGGL(k_voigt_eval, dim3(blocks_for(n, 256)), dim3(256), 0, st, vt, n, a, x, out);
+    RCX_HIP_TRY(hipGetLastError());
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* nl, int32_t* nt)
+{
+    if (!s || !nl || !nt) return nlte_fail(RCX_E_INVALID, "rcx_nlte_dims: null argument");
+    *nl = s->atom.nl;
+    *nt = s->atom.nt;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_destroy(rcx_nlte* s)
+{
+    if (!s) return RCX_OK;
+    for (void* p : s->allocs) (void)hipFree(p);
+    if (s->plan) rcx_plan_destroy(s->plan);
+    delete s;
+    return RCX_OK;
+}
+
+}  // extern "C"

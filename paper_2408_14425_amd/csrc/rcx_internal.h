@@ -34,15 +34,60 @@ int32_t hip_fail(hipError_t e, const char* what);
 
 // Kernel launchers (fs_kernels.hip). All enqueue on `st` and return the
 // launch status.
+// smax_bits (nullable): [n_batch * batch_width] per-wavelength max of S (float bits).
 hipError_t launch_prep(const float* chi, const float* eta, float2* F, int32_t n_wave, int64_t ncell,
-                       float voxel, hipStream_t st);
+                       float voxel, unsigned int* smax_bits, hipStream_t st);
+// FP16 storage scales from the per-wavelength max S.
+hipError_t launch_scales(int32_t n, const unsigned int* smax_bits, float* scale, float* inv_scale, hipStream_t st);
+
+// Cascade buffers of one march launch: the merged cascade above (read) and
+// this cascade (written), each FP32 or FP16-with-scale.
+struct CascIO {
+    const void* up;
+    void* out;
+    bool up_f16, out_f16;
+    const float* scale_b;      // [batch_width] stored = value * scale
+    const float* inv_scale_b;  // [batch_width]
+};
 // Wavelengths per batch of the field and cascade layouts.
 int32_t batch_width();
+// Grid of a march launch over `rays` rays.
+dim3 march_grid(int64_t rays);
 // Fb: the batch's slice of F ([ncell][batch_width] float2); up/out: cascade
 // buffers [rays][batch_width].
-hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
-                              const double4* dirs, const float* up, float* out, hipStream_t st);
-hipError_t launch_j(const float* I0, float* J, int32_t n_wave, int32_t batch, int64_t ncell, int32_t n0,
+hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                              const CascIO& io, hipStream_t st);
+// J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
+hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
                     hipStream_t st);
 
 }  // namespace rcx
+
+#include <vector>
+
+// A formal-solve plan: grid, cascade geometry and the device direction table.
+struct rcx_plan {
+    rcx_grid grid;
+    rcx_params prm;
+    int32_t max_wave;
+    int32_t n_casc;
+    int32_t top_skipped;
+    std::vector<rcx::LevelDesc> levels;
+    std::vector<int32_t> dir_off;  // offset of cascade i's directions in the table
+    std::vector<double4> dirs_host;
+    double4* dirs_dev = nullptr;
+    void* ws_own = nullptr;
+    size_t ws_own_bytes = 0;
+    bool work_done = false;
+    rcx_work work;
+    // measurement: events recorded around launches when timing is enabled
+    struct Timed {
+        int32_t level;  // cascade index, or -1 for prep / J
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
+    int64_t n_solves = 0;
+};
+
+

@@ -43,30 +43,6 @@ static int32_t ok()
 
 using namespace rcx;
 
-struct rcx_plan {
-    rcx_grid grid;
-    rcx_params prm;
-    int32_t max_wave;
-    int32_t n_casc;
-    int32_t top_skipped;
-    std::vector<LevelDesc> levels;
-    std::vector<int32_t> dir_off;  // offset of cascade i's directions in the table
-    std::vector<double4> dirs_host;
-    double4* dirs_dev = nullptr;
-    void* ws_own = nullptr;
-    size_t ws_own_bytes = 0;
-    bool work_done = false;
-    rcx_work work;
-    // measurement: events recorded around launches when timing is enabled
-    struct Timed {
-        int32_t level;  // cascade index, or -1 for prep / J
-        hipEvent_t a, b;
-    };
-    bool timing = false;
-    std::vector<Timed> pending;
-    int64_t n_solves = 0;
-};
-
 namespace {
 
 double t_start(const rcx_params& p, int32_t n_casc, int32_t i)
@@ -105,7 +81,7 @@ double max_probe_corner_distance(const rcx_grid& g, const LevelDesc& L)
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t F, casc_a, casc_b, total;
+    size_t F, casc_a, casc_b, smax, scale, inv_scale, total;
 };
 
 WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
@@ -119,7 +95,10 @@ WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
     w.F = 0;
     w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_batch * lb);
     w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * lb);
-    w.total = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb);
+    w.smax = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb);
+    w.scale = w.smax + align256(sizeof(float) * (size_t)n_batch * lb);
+    w.inv_scale = w.scale + align256(sizeof(float) * (size_t)n_batch * lb);
+    w.total = w.inv_scale + align256(sizeof(float) * (size_t)n_batch * lb);
     return w;
 }
 
@@ -218,7 +197,8 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
         return fail(RCX_E_INVALID, "rcx_plan_create: c0_dirs and c0_t1 must be positive");
     if (prm->t_rule != RCX_T_GEOMETRIC && prm->t_rule != RCX_T_LENGTH_X4)
         return fail(RCX_E_INVALID, "rcx_plan_create: unknown t_rule");
-    if (prm->storage != RCX_STORE_F32) return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
+    if (prm->storage != RCX_STORE_F32 && prm->storage != RCX_STORE_F16_SCALED)
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
     if (prm->n_incl != 1) return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: only n_incl = 1 (flatland)");
     int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
     if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
@@ -326,27 +306,43 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     float* bufs[2] = {(float*)(ws + w.casc_a), (float*)(ws + w.casc_b)};
 
     if (p->timing) ++p->n_solves;
-    RCX_HIP_TRY(timed(p, -1, st, [&] {
-        return launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, st);
-    }));
+    const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
+    unsigned int* smax = (unsigned int*)(ws + w.smax);
+    float* scale = (float*)(ws + w.scale);
+    float* inv_scale = (float*)(ws + w.inv_scale);
     const int32_t lb = batch_width();
     const int32_t n_batch = (n_wave + lb - 1) / lb;
+    RCX_HIP_TRY(timed(p, -1, st, [&] {
+        hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
+        if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
+        return e;
+    }));
     for (int32_t b = 0; b < n_batch; ++b) {
         const float2* Fb = F + (size_t)b * ncell * lb;
         int cur = 0;
-        const float* up = nullptr;
+        const void* up = nullptr;
+        bool up_f16 = false;
         for (int32_t i = p->n_casc - 1; i >= 0; --i) {
             if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
             const LevelDesc& L = p->levels[i];
-            float* outb = bufs[cur];
+            CascIO io;
+            io.up = L.has_up ? up : nullptr;
+            io.up_f16 = up_f16;
+            io.out = bufs[cur];
+            io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
+            io.scale_b = scale + (size_t)b * lb;
+            io.inv_scale_b = inv_scale + (size_t)b * lb;
             RCX_HIP_TRY(timed(p, i, st, [&] {
-                return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], L.has_up ? up : nullptr,
-                                          outb, st);
+                return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
             }));
-            up = outb;
+            up = bufs[cur];
+            up_f16 = io.out_f16;
             cur ^= 1;
         }
-        RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_j(up, J, n_wave, b, ncell, p->prm.c0_dirs, st); }));
+        const int32_t nvalid = std::min(lb, n_wave - b * lb);
+        RCX_HIP_TRY(timed(p, -1, st, [&] {
+            return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
+        }));
     }
     return ok();
 }

@@ -25,6 +25,7 @@ RCX_E_WORKSPACE = -5
 RCX_T_GEOMETRIC = 0
 RCX_T_LENGTH_X4 = 1
 RCX_STORE_F32 = 0
+RCX_STORE_F16_SCALED = 1
 
 
 class rcx_grid(C.Structure):
@@ -219,6 +220,181 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             rcx_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ non-LTE
+
+MAXL, MAXLINE, MAXCONT = 6, 8, 4
+
+
+class rcx_atom(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("n_lines", C.c_int32), ("n_conts", C.c_int32), ("pad_", C.c_int32),
+                ("E_eV", C.c_double * MAXL), ("g", C.c_double * MAXL), ("mass_amu", C.c_double),
+                ("line_lower", C.c_int32 * MAXLINE), ("line_upper", C.c_int32 * MAXLINE),
+                ("line_lambda_nm", C.c_double * MAXLINE), ("line_f", C.c_double * MAXLINE),
+                ("cont_lower", C.c_int32 * MAXCONT), ("cont_upper", C.c_int32 * MAXCONT),
+                ("cont_edge_nm", C.c_double * MAXCONT), ("cont_alpha0", C.c_double * MAXCONT),
+                ("q_coll", C.c_double * (MAXLINE + MAXCONT))]
+
+
+def atom_from_dict(d: dict) -> rcx_atom:
+    a = rcx_atom()
+    a.n_levels = len(d["E_eV"])
+    a.n_lines = len(d["lines"])
+    a.n_conts = len(d["continua"])
+    for i, (e, g) in enumerate(zip(d["E_eV"], d["g"])):
+        a.E_eV[i] = e
+        a.g[i] = g
+    a.mass_amu = d["mass_amu"]
+    for k, (lo, hi, lam, f) in enumerate(d["lines"]):
+        a.line_lower[k], a.line_upper[k], a.line_lambda_nm[k], a.line_f[k] = lo, hi, lam, f
+    for k, (lo, hi, edge, a0) in enumerate(d["continua"]):
+        a.cont_lower[k], a.cont_upper[k], a.cont_edge_nm[k], a.cont_alpha0[k] = lo, hi, edge, a0
+    for k, q in enumerate(d["q_coll"]):
+        a.q_coll[k] = q
+    return a
+
+
+def _load_nlte():
+    L = load()
+    if getattr(L, "_nlte_bound", False):
+        return L
+    vp, i32 = C.c_void_p, C.c_int32
+    L.rcx_nlte_create.argtypes = [C.POINTER(rcx_grid), C.POINTER(rcx_params), C.POINTER(rcx_atom), i32,
+                                  vp, vp, vp, C.POINTER(vp)]
+    L.rcx_nlte_set_atmosphere.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
+    L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
+    L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.rcx_nlte_iterate.argtypes = [vp, vp, i32, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double), vp]
+    L.rcx_nlte_voigt_eval.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.rcx_nlte_dims.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.rcx_nlte_destroy.argtypes = [vp]
+    for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
+              "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
+              "rcx_nlte_dims", "rcx_nlte_destroy"):
+        getattr(L, n).restype = i32
+    L._nlte_bound = True
+    return L
+
+
+def rcx_nlte_create(grid: rcx_grid, params: rcx_params, atom: rcx_atom, lambda_nm, trans, dnu) -> int:
+    import numpy as np
+    lam = np.ascontiguousarray(lambda_nm, np.float64)
+    tr = np.ascontiguousarray(trans, np.int32)
+    dn = np.ascontiguousarray(dnu, np.float64)
+    h = C.c_void_p()
+    _check(_load_nlte().rcx_nlte_create(C.byref(grid), C.byref(params), C.byref(atom), len(lam), lam.ctypes.data,
+                                        tr.ctypes.data, dn.ctypes.data, C.byref(h)), "rcx_nlte_create")
+    return h.value
+
+
+def rcx_nlte_set_atmosphere(s: int, T, ne, ntot, vel, stream=None) -> int:
+    return _check(_load_nlte().rcx_nlte_set_atmosphere(
+        s, _dev_ptr(T, "torch.float64", "T"), _dev_ptr(ne, "torch.float64", "ne"),
+        _dev_ptr(ntot, "torch.float64", "ntot"), _dev_ptr(vel, "torch.float32", "vel"), _stream_ptr(stream)),
+        "rcx_nlte_set_atmosphere")
+
+
+def rcx_nlte_lte_populations(s: int, pops, stream=None) -> int:
+    return _check(_load_nlte().rcx_nlte_lte_populations(s, _dev_ptr(pops, "torch.float64", "pops"),
+                                                        _stream_ptr(stream)), "rcx_nlte_lte_populations")
+
+
+def rcx_nlte_formal_solve_rates(s: int, pops, rates, J=None, stream=None) -> int:
+    return _check(_load_nlte().rcx_nlte_formal_solve_rates(
+        s, _dev_ptr(pops, "torch.float64", "pops"), _dev_ptr(rates, "torch.float32", "rates"),
+        _dev_ptr(J, "torch.float32", "J") or None, _stream_ptr(stream)), "rcx_nlte_formal_solve_rates")
+
+
+def rcx_nlte_stat_eq(s: int, rates, pops, stream=None) -> float:
+    ch = C.c_double()
+    _check(_load_nlte().rcx_nlte_stat_eq(s, _dev_ptr(rates, "torch.float32", "rates"),
+                                         _dev_ptr(pops, "torch.float64", "pops"), C.byref(ch), _stream_ptr(stream)),
+           "rcx_nlte_stat_eq")
+    return ch.value
+
+
+def rcx_nlte_iterate(s: int, pops, max_iter: int, tol: float, stream=None):
+    """Returns (status, iterations, last change); status RCX_OK or RCX_W_NOT_CONVERGED."""
+    it, ch = C.c_int32(), C.c_double()
+    rc = _check(_load_nlte().rcx_nlte_iterate(s, _dev_ptr(pops, "torch.float64", "pops"), int(max_iter), float(tol),
+                                              C.byref(it), C.byref(ch), _stream_ptr(stream)), "rcx_nlte_iterate")
+    return rc, it.value, ch.value
+
+
+def rcx_nlte_voigt_eval(s: int, a, x, out, stream=None) -> int:
+    return _check(_load_nlte().rcx_nlte_voigt_eval(s, a.numel(), _dev_ptr(a, "torch.float32", "a"),
+                                                   _dev_ptr(x, "torch.float32", "x"),
+                                                   _dev_ptr(out, "torch.float32", "out"), _stream_ptr(stream)),
+                  "rcx_nlte_voigt_eval")
+
+
+def rcx_nlte_dims(s: int):
+    nl, nt = C.c_int32(), C.c_int32()
+    _check(_load_nlte().rcx_nlte_dims(s, C.byref(nl), C.byref(nt)), "rcx_nlte_dims")
+    return nl.value, nt.value
+
+
+def rcx_nlte_destroy(s: int) -> int:
+    return _check(_load_nlte().rcx_nlte_destroy(s), "rcx_nlte_destroy")
+
+
+class Nlte:
+    """Owns an ``rcx_nlte`` solver for one non-LTE problem (a
+    ``workloads.NlteInput``); arrays live on ``cuda:0``."""
+
+    def __init__(self, inp, n_cascades: int = 0):
+        import torch
+        p = rcx_params_default()
+        p.n_cascades = n_cascades
+        self.inp = inp
+        self.handle = rcx_nlte_create(rcx_grid(inp.nx, inp.nz, inp.voxel), p, atom_from_dict(inp.atom),
+                                      inp.lambda_nm, inp.trans, inp.dnu)
+        self.n_levels, self.n_trans = rcx_nlte_dims(self.handle)
+        dev = torch.device("cuda:0")
+        self.T = torch.from_numpy(inp.T.astype("float64")).to(dev)
+        self.ne = torch.from_numpy(inp.ne.astype("float64")).to(dev)
+        self.ntot = torch.from_numpy(inp.ntot.astype("float64")).to(dev)
+        self.vel = torch.from_numpy(inp.vel.astype("float32")).to(dev).contiguous()
+        rcx_nlte_set_atmosphere(self.handle, self.T, self.ne, self.ntot, self.vel)
+
+    def lte(self):
+        import torch
+        pops = torch.empty((self.n_levels, self.inp.nz, self.inp.nx), dtype=torch.float64, device="cuda:0")
+        rcx_nlte_lte_populations(self.handle, pops)
+        return pops
+
+    def formal_solve_rates(self, pops, want_J: bool = False):
+        import torch
+        rates = torch.empty((self.n_trans, 2, self.inp.nz, self.inp.nx), dtype=torch.float32, device="cuda:0")
+        J = torch.empty((self.inp.n_wave, self.inp.nz, self.inp.nx), dtype=torch.float32,
+                        device="cuda:0") if want_J else None
+        rcx_nlte_formal_solve_rates(self.handle, pops, rates, J)
+        return rates, J
+
+    def stat_eq(self, rates, pops) -> float:
+        return rcx_nlte_stat_eq(self.handle, rates, pops)
+
+    def iterate(self, pops, max_iter: int, tol: float):
+        return rcx_nlte_iterate(self.handle, pops, max_iter, tol)
+
+    def voigt(self, a, x):
+        import torch
+        out = torch.empty_like(a)
+        rcx_nlte_voigt_eval(self.handle, a, x, out)
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rcx_nlte_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

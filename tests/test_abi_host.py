@@ -59,3 +59,42 @@ def test_null_arguments_are_rejected():
     assert L.rcx_formal_solve(None, 1, None, None, None, None, 0, None) == rcx.RCX_E_INVALID
     assert L.rcx_plan_destroy(None) == rcx.RCX_OK
     assert L.rcx_params_default(None) == rcx.RCX_E_INVALID
+
+
+def _nlte_args():
+    from paper_2408_14425_amd import workloads as W
+    inp = W.nlte_atmosphere(8, seed=1, n_line=4, n_cont=4)
+    return inp, rcx.atom_from_dict(inp.atom)
+
+
+def test_nlte_create_rejects_bad_wavelength_grouping():
+    inp, atom = _nlte_args()
+    tr = inp.trans.copy()
+    tr[0], tr[-1] = tr[-1], tr[0]
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_nlte_create(rcx.rcx_grid(8, 8, inp.voxel), rcx.rcx_params_default(), atom, inp.lambda_nm, tr, inp.dnu)
+    assert e.value.code == rcx.RCX_E_INVALID
+
+
+def test_nlte_create_rejects_unsupported_atom_and_geometry():
+    inp, atom = _nlte_args()
+    atom.n_levels = 7
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_nlte_create(rcx.rcx_grid(8, 8, inp.voxel), rcx.rcx_params_default(), atom, inp.lambda_nm,
+                            inp.trans, inp.dnu)
+    assert e.value.code == rcx.RCX_E_UNSUPPORTED
+    inp, atom = _nlte_args()
+    p = rcx.rcx_params_default()
+    p.c0_dirs = 8
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_nlte_create(rcx.rcx_grid(8, 8, inp.voxel), p, atom, inp.lambda_nm, inp.trans, inp.dnu)
+    assert e.value.code == rcx.RCX_E_UNSUPPORTED
+
+
+def test_nlte_create_rejects_continuum_wavelength_beyond_edge():
+    inp, atom = _nlte_args()
+    lam = inp.lambda_nm.copy()
+    lam[-1] = 95.0  # continuum edge is 91.18 nm
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_nlte_create(rcx.rcx_grid(8, 8, inp.voxel), rcx.rcx_params_default(), atom, lam, inp.trans, inp.dnu)
+    assert e.value.code == rcx.RCX_E_INVALID

@@ -139,3 +139,25 @@ def test_full_size_1024_64_wavelengths_sampled():
         for x, z in cells:
             g, o = float(Jg[lam, z, x]), Jo[z, x]
             assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
+
+
+@pytest.mark.parametrize("which", ["blobs64", "line256"])
+def test_fp16_storage_error_is_bounded(which):
+    """FP16 cascade storage with per-wavelength power-of-two scaling: each
+    stored value carries at most 2^-12 relative rounding error within range,
+    accumulated over at most 6 stored cascades; the error against the FP64
+    oracle is reported and bounded by 2e-3."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.blobs_medium(64, seed=1) if which == "blobs64" else \
+        W.line_medium(256, 64, seed=2, wave_subset=np.arange(0, 64, 8))
+    print(f"[gpu] fp16 storage {inp.name}", flush=True)
+    plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, storage=rcx.RCX_STORE_F16_SCALED)
+    J = plan.formal_solve(torch.from_numpy(inp.chi).cuda(), torch.from_numpy(inp.eta).cuda())
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().astype(np.float64)
+    plan.close()
+    Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    rel = np.abs(Jg - Jo) / Jo
+    print(f"fp16 storage {which}: max rel {rel.max():.3e} mean {rel.mean():.3e}")
+    assert rel.max() < 2e-3

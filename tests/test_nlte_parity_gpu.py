@@ -1,0 +1,116 @@
+"""GPU non-LTE iteration vs the FP64 oracle, through the C ABI.
+
+Tolerances: populations 1e-3 relative (compared after the same number of
+iterations, the oracle's stopping count for converged runs); J 5e-4 relative
+(the FP32 march plus the device Voigt table's interpolation error, below
+5e-5 relative); LTE populations 1e-12 (same FP64 formula)."""
+import numpy as np
+import pytest
+
+from paper_2408_14425_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def case32():
+    inp = W.nlte_atmosphere(32, seed=3, n_line=32, n_cont=16)
+    from oracle import nlte
+    return inp, nlte.Problem(inp)
+
+
+def _solver(inp):
+    from paper_2408_14425_amd import rcx
+    print(f"[gpu] nlte solver {inp.name}", flush=True)
+    return rcx.Nlte(inp)
+
+
+def test_voigt_table_matches_reference(case32):
+    torch = _torch()
+    from oracle import nlte
+    inp, P = case32
+    s = _solver(inp)
+    rng = np.random.default_rng(1)
+    a = rng.uniform(0, P.adamp.max(), 200000)
+    x = np.concatenate([rng.uniform(0, 8, 100000), rng.uniform(8, 40, 100000)])
+    got = s.voigt(torch.tensor(a, dtype=torch.float32, device="cuda"),
+                  torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    s.close()
+    ref = nlte.voigt_H(a.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
+    rel = np.abs(got - ref) / ref
+    print("voigt table max rel", rel.max())
+    assert rel.max() < 5e-5
+
+
+def test_lte_populations(case32):
+    _torch()
+    inp, P = case32
+    s = _solver(inp)
+    pops = s.lte().cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    np.testing.assert_allclose(pops, P.lte, rtol=1e-12)
+
+
+def test_formal_solve_J_and_first_update(case32):
+    torch = _torch()
+    inp, P = case32
+    s = _solver(inp)
+    pops = s.lte()
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    ch = s.stat_eq(rates, pops)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    po = P.lte.copy()
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(po)
+    Rup, Rdn = P.rates(po, I0, chi_loc, H_loc)
+    new, cho = P.stat_eq(po, Rup, Rdn)
+    relJ = np.abs(Jg - Jo) / np.abs(Jo)
+    print("J max rel", relJ.max(), "first change gpu/oracle", ch, cho)
+    assert relJ.max() < 5e-4
+    relp = np.abs(pg - new) / np.abs(new)
+    print("pops after one update max rel", relp.max())
+    assert relp.max() < 1e-3
+    assert abs(ch / cho - 1) < 1e-3
+
+
+def test_three_iterations(case32):
+    _torch()
+    inp, P = case32
+    s = _solver(inp)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, 3, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    po, changes = P.iterate(P.lte.copy(), 3)
+    relp = np.abs(pg - po) / np.abs(po)
+    print("3 iterations: max rel", relp.max(), "changes", ch, changes[-1])
+    assert it == 3 and rc == 1
+    assert relp.max() < 1e-3
+
+
+def test_converged_at_oracle_iteration_count(case32):
+    """The oracle iterates to max change < 1e-3; the GPU runs the same number
+    of iterations; populations agree to 1e-3 and the GPU's own stopping test
+    fires at the same count."""
+    _torch()
+    inp, P = case32
+    po, changes = P.iterate(P.lte.copy(), 200, tol=1e-3)
+    K = len(changes)
+    s = _solver(inp)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, K, 1e-3)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"converged: oracle {K} iterations (last change {changes[-1]:.3e}); gpu {it} ({ch:.3e}); max rel {relp.max():.3e}")
+    assert it == K and rc == 0
+    assert relp.max() < 1e-3
