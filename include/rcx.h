@@ -135,6 +135,43 @@ int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_ot
 /* Release a plan and its device memory. NULL is accepted. */
 int32_t rcx_plan_destroy(rcx_plan* plan);
 
+/* ================================================================ batches
+ * Many formal solutions in one persistent launch (the GPU analogue of
+ * solving several atmospheres and wavelength batches at once, Secs. 2.3 and
+ * 3.2): work items (atmosphere, 16-wavelength batch, cascade, probe tile)
+ * are queued from the top cascade down; a grid sized to the resident
+ * capacity pops them, each waits (bounded) on the completion counter of its
+ * cascade above, marches, merges and publishes; cascade 0 writes J.
+ * Solves are enqueued as a captured HIP graph, re-captured when the input
+ * or output pointers change. */
+typedef struct rcx_batch rcx_batch;
+
+/* n_atm atmospheres with grids[a] and n_wave[a] wavelengths. p as for
+ * rcx_plan_create, with n_cascades = 0 (automatic per atmosphere) and
+ * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
+int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
+                         rcx_batch** out);
+/* Probe-tile size of a work item in rays (>= 16; default 4096). */
+int32_t rcx_batch_set_tiling(rcx_batch* b, int32_t rays_per_item);
+/* Enqueue through a captured graph (1, default) or by direct launches (0). */
+int32_t rcx_batch_set_graph(rcx_batch* b, int32_t enable);
+/* chi_host[a], eta_host[a], J_host[a]: host arrays of n_atm device pointers
+ * to [n_wave[a]][nz][nx] float32, as for rcx_formal_solve. Synchronises the
+ * stream. RCX_E_HIP if a work item timed out waiting (the launch still
+ * drains; J is then invalid). */
+int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
+                        float* const* J_host, hipStream_t stream);
+/* Work summed over atmospheres and wavelengths (rcx_work semantics). */
+int32_t rcx_batch_work(const rcx_batch* b, int64_t* rays_nonempty_host, int64_t* cell_steps_host);
+/* Time each candidate tile size {1024, 4096, 16384, 65536} rays on these
+ * inputs and keep the fastest (*best_rays_host). cache_path (or NULL): a
+ * text file of JSON lines keyed by the batch's shapes; a hit skips timing,
+ * a miss appends the result. */
+int32_t rcx_batch_autotune(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
+                           float* const* J_host, const char* cache_path, int32_t* best_rays_host,
+                           hipStream_t stream);
+int32_t rcx_batch_destroy(rcx_batch* b);
+
 /* ================================================================ non-LTE
  * The non-LTE iteration of Sec. 3.3: opacities and emissivities from level
  * populations, the radiance-cascades formal solution per wavelength with
@@ -247,6 +284,59 @@ int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* n_levels_host, int32_t* n_tran
 
 /* Release the solver. NULL is accepted. */
 int32_t rcx_nlte_destroy(rcx_nlte* s);
+
+/* ===================================================== learned warm start
+ * A small multilayer perceptron x [B][n_in] -> (Linear, SiLU) x depth ->
+ * Linear -> y [B][n_out], trained by Adam on an MSE loss with BF16 MFMA
+ * products (FP32 accumulation) and FP32 master weights. It predicts
+ * warm-start level populations for the non-LTE iteration; the plain
+ * iteration from its prediction remains the judge of convergence.
+ * Parameters are one flat FP32 array, layer by layer: W [fan_in][fan_out]
+ * row-major, then b [fan_out]. Initial values come from the caller. */
+typedef struct rcx_mlp rcx_mlp;
+
+/* Create a network for batches up to max_batch. Supports 1 <= n_in <= 16,
+ * 1 <= n_out <= 64, 1 <= depth <= 16, width a multiple of 64 in [64, 512]
+ * (RCX_E_UNSUPPORTED otherwise). Parameters start at zero. */
+int32_t rcx_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t max_batch, rcx_mlp** out);
+int32_t rcx_mlp_n_params(const rcx_mlp* m, int64_t* n_host);
+/* Copy parameters in/out (host arrays of rcx_mlp_n_params floats; both
+ * synchronise the device). set_params also resets the Adam moments. */
+int32_t rcx_mlp_set_params(rcx_mlp* m, const float* flat_host, int64_t n);
+int32_t rcx_mlp_get_params(const rcx_mlp* m, float* flat_host, int64_t n);
+/* Inference: x [batch][n_in], y [batch][n_out] (device FP32); any batch size
+ * (processed in chunks of max_batch). */
+int32_t rcx_mlp_forward(rcx_mlp* m, const float* x, float* y, int32_t batch, hipStream_t stream);
+/* Loss (mean squared error over samples and outputs, to *loss_host) and its
+ * gradient with respect to the flat parameters (grad: device FP32, may be
+ * NULL). batch <= max_batch. Synchronises the stream. */
+int32_t rcx_mlp_gradients(rcx_mlp* m, const float* x, const float* y_ref, int32_t batch, float* grad,
+                          float* loss_host, hipStream_t stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) at
+ * learning rate lr on a batch; *loss_host gets the loss before the step. */
+int32_t rcx_mlp_train_step(rcx_mlp* m, const float* x, const float* y_ref, int32_t batch, float lr,
+                           float* loss_host, hipStream_t stream);
+int32_t rcx_mlp_destroy(rcx_mlp* m);
+
+/* Warm-start features of every cell at populations pops (device FP64):
+ * one formal solution with J, then feat [nz*nx][6] (device FP32) =
+ * {log10 T, log10 ne, |v| [km/s], log10 chi_0 (line 0's centre opacity
+ * [1/m]), log10 Jbar_0, log10 Jbar_1} with Jbar_t the profile-weighted mean
+ * intensity of line t; each standardised as (f - mean)/std with
+ * norm_host[2][6] = {means, stds} (NULL: no standardisation). Synchronises. */
+int32_t rcx_nlte_features(rcx_nlte* s, const double* pops, const float* norm_host, float* feat, hipStream_t stream);
+/* out [nz*nx][n_levels] (device FP32) = (log10(n_l/ntot) - mean_l)/std_l,
+ * norm_host[2][n_levels] (NULL: none). Synchronises. */
+int32_t rcx_nlte_log_fractions(rcx_nlte* s, const double* pops, const float* norm_host, float* out,
+                               hipStream_t stream);
+/* Learned warm start: LTE populations, one formal solution, features,
+ * network inference, and populations n_l = ntot 10^{z_l} / sum_m 10^{z_m}
+ * with z the de-standardised prediction (targ_norm_host[2][n_levels]);
+ * pops_out [n_levels][nz][nx] device FP64. The plain iteration started
+ * from it remains the judge of convergence. Synchronises. */
+int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_host, const float* targ_norm_host,
+                            double* pops_out, hipStream_t stream);
+
 
 /* Static description of a status code. */
 const char* rcx_error_string(int32_t code);

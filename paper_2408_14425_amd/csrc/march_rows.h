@@ -81,156 +81,184 @@ struct UpF16 {
     __device__ __forceinline__ float get(int64_t i) const { return __half2float(p[i]) * inv; }
 };
 
+// Lane state shared by the kernels that march rows of rays.
+struct RowCtx {
+    int lane, w, row, l;
+    uint64_t row_bits, lt_bits;
+};
+
+__device__ __forceinline__ RowCtx row_ctx()
+{
+    RowCtx c;
+    c.lane = threadIdx.x & 63;
+    c.w = threadIdx.x >> 6;
+    c.row = c.lane >> 4;
+    c.l = c.lane & 15;
+    c.row_bits = 0xFFFFull << (16 * c.row);
+    c.lt_bits = (c.lane == 0) ? 0ull : (~0ull >> (64 - c.lane));
+    return c;
+}
+
+// March, merge and finish one ray per row. ray = output index of the ray
+// in its cascade, (u, v, k) its probe and direction; active false for rows
+// past the end (they still take part in the wavefront-wide ballots).
+template <class Op, class Epi, class Up>
+__device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
+                                          const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[16],
+                                          const RowCtx& cx_, int64_t ray, int32_t u, int32_t v, int32_t k,
+                                          bool active)
+{
+    const int lane = cx_.lane, row = cx_.row, l = cx_.l;
+    const uint64_t row_bits = cx_.row_bits, lt_bits = cx_.lt_bits;
+    RayInfo ri;
+    ri.ray = ray;
+    ri.active = active;
+    ri.k = k;
+    ri.u = u;
+    ri.v = v;
+
+    const double cx = (ri.u + 0.5) * L.s, cz = (ri.v + 0.5) * L.s;
+    const double4 d = dirs[ri.k];  // {wx, wz, 1/wx, 1/wz}
+    ri.wx = d.x;
+    ri.wz = d.y;
+    op.begin_ray(d.x, d.y);
+    // Plane crossings t(X) = X / w - c / w, evaluated with one FMA so the
+    // crossing of the domain's exit plane equals the clip bound exactly.
+    const double offx = -cx * d.z, offz = -cz * d.w;
+    const double ax = offx, bx = fma((double)nx, d.z, offx);
+    const double az = offz, bz = fma((double)nz, d.w, offz);
+    double lo = fmax(L.ta, fmax(fmin(ax, bx), fmin(az, bz)));
+    double hi = fmin(L.tb, fmin(fmax(ax, bx), fmax(az, bz)));
+    if (!ri.active) {
+        lo = 1.0;
+        hi = 0.0;
+    }
+
+    // Major axis m (the one crossed at least as often), minor axis n.
+    const bool xmaj = fabs(d.x) >= fabs(d.y);
+    const double wm = xmaj ? d.x : d.y, wn = xmaj ? d.y : d.x;
+    const double cm = xmaj ? cx : cz, cn = xmaj ? cz : cx;
+    const double im_ = xmaj ? d.z : d.w, in_ = xmaj ? d.w : d.z;
+    const double offm = xmaj ? offx : offz, offn = xmaj ? offz : offx;
+    const int nm = xmaj ? nx : nz, nn = xmaj ? nz : nx;
+    const int strm = xmaj ? 1 : nx, strn = xmaj ? nx : 1;
+    const int sm = wm > 0.0 ? 1 : -1, sn = wn > 0.0 ? 1 : -1;
+
+    const double pm0 = cm + lo * wm;
+    int im0 = wm > 0.0 ? (int)floor(pm0) : (int)ceil(pm0) - 1;
+    im0 = min(max(im0, 0), nm - 1);
+    const int mfirst = wm > 0.0 ? im0 + 1 : im0;  // first m-plane crossed
+
+    float I = 0.0f, T = 1.0f;
+    const int max_chunks = (nm + 2 + 15) / 16 + 1;
+    for (int chunk = 0; chunk < max_chunks; ++chunk) {
+        // ---- column j of this row's ray: one or two segments
+        const int j = chunk * 16 + l;
+        const double ta = (j == 0) ? lo : fma((double)(mfirst + (j - 1) * sm), im_, offm);
+        const double tb_ = fmin(fma((double)(mfirst + j * sm), im_, offm), hi);
+        const bool valid = ta < hi;
+        const int im = min(max(im0 + j * sm, 0), nm - 1);
+        const double pn = cn + ta * wn;
+        int in0 = wn > 0.0 ? (int)floor(pn) : (int)ceil(pn) - 1;
+        in0 = min(max(in0, 0), nn - 1);
+        const int nnext = wn > 0.0 ? in0 + 1 : in0;
+        const double tn = fma((double)nnext, in_, offn);
+        const bool two = valid && tn < tb_;
+        const double tmid = fmax(tn, ta);
+        const uint32_t cell1 = (uint32_t)(im * strm + in0 * strn);
+        const int in1 = min(max(in0 + sn, 0), nn - 1);
+        const uint32_t cell2 = (uint32_t)(im * strm + in1 * strn);
+        const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
+        const float ds2 = (float)fmax(tb_ - tmid, 0.0);
+
+        const uint64_t b1 = __ballot(valid);
+        if (b1 == 0) break;
+        const uint64_t b2 = __ballot(two);
+        const int pos = __popcll(b1 & row_bits & lt_bits) + __popcll(b2 & row_bits & lt_bits);
+        const int n_row = __popcll(b1 & row_bits) + __popcll(b2 & row_bits);
+        int n_max = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t rb = 0xFFFFull << (16 * q);
+            n_max = max(n_max, __popcll(b1 & rb) + __popcll(b2 & rb));
+        }
+        uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
+        if (valid) srow[pos] = make_uint2(cell1, __float_as_uint(ds1));
+        if (two) srow[pos + 1] = make_uint2(cell2, __float_as_uint(ds2));
+        wave_sync();
+
+        // ---- step through the row's segments, 4 at a time. Positions past
+        // the row's count are steps with no opacity and no emission.
+        for (int s = 0; s < n_max; s += 4) {
+            const uint4 e01 = seg[row][s >> 1];
+            const uint4 e23 = seg[row][(s >> 1) + 1];
+            const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
+            const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
+                                  __uint_as_float(e23.w)};
+            typename Op::Raw raw[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float2 f = op.resolve(raw[q]);  // {optical depth per cell, log2 units; S}
+                const float y = f.x * dsv[q];
+                const float e = __builtin_amdgcn_exp2f(-y);
+                I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
+                T *= e;
+            }
+        }
+        wave_sync();
+    }
+
+    if (ri.active && L.has_up) {
+        // Bilinear taps on the cascade above: q = (u + 1/2)/2 - 1/2, so
+        // even u -> taps (u/2 - 1, u/2) with weights (1/4, 3/4), odd u ->
+        // taps ((u-1)/2, (u+1)/2) with weights (3/4, 1/4); clamped.
+        const int bx0 = (ri.u - 1) >> 1, bz0 = (ri.v - 1) >> 1;
+        const float fx = (ri.u & 1) ? 0.25f : 0.75f;
+        const float fz = (ri.v & 1) ? 0.25f : 0.75f;
+        const int txs[2] = {min(max(bx0, 0), L.qx - 1), min(max(bx0 + 1, 0), L.qx - 1)};
+        const int tzs[2] = {min(max(bz0, 0), L.qz - 1), min(max(bz0 + 1, 0), L.qz - 1)};
+        const float wxs[2] = {1.0f - fx, fx};
+        const float wzs[2] = {1.0f - fz, fz};
+        float far = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                const int64_t bi = (((int64_t)tzs[a] * L.qx + txs[bb]) * L.nd_up + 4 * (int64_t)ri.k) * kLB + l;
+                const float c4 = up.get(bi) + up.get(bi + kLB) + up.get(bi + 2 * kLB) + up.get(bi + 3 * kLB);
+                far = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far);
+            }
+        I = fmaf(T, far, I);
+    }
+    epi.finish(ri, l, lane, I, op);
+}
+
 template <class Op, class Epi, class Up>
 __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
 {
     // per wave, per row: (cell index, ds) entries
     __shared__ uint4 seg[kBlock / 64][4][16];
-
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int row = lane >> 4;
-    const int l = lane & 15;
-    const uint64_t row_bits = 0xFFFFull << (16 * row);
-    const uint64_t lt_bits = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    op.init(l);
-    epi.init(l);
-    up.init(l);
+    const RowCtx c = row_ctx();
+    op.init(c.l);
+    epi.init(c.l);
+    up.init(c.l);
     {
-        uint4* sw = &seg[w][0][0];
-        sw[lane] = make_uint4(0u, 0u, 0u, 0u);
+        uint4* sw = &seg[c.w][0][0];
+        sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
         wave_sync();
     }
-
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
-    for (int64_t base = ((int64_t)lb * (kBlock / 64) + w) * 4; base < total; base += stride) {
-        RayInfo ri;
-        ri.ray = base + row;
-        ri.active = ri.ray < total;
-        const int64_t rr = ri.active ? ri.ray : total - 1;
-        ri.k = (int32_t)(rr % L.nd);
+    for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
+        const int64_t ray = base + c.row;
+        const bool active = ray < total;
+        const int64_t rr = active ? ray : total - 1;
+        const int32_t k = (int32_t)(rr % L.nd);
         const int32_t p = (int32_t)(rr / L.nd);
-        ri.u = p % L.px;
-        ri.v = p / L.px;
-
-        const double cx = (ri.u + 0.5) * L.s, cz = (ri.v + 0.5) * L.s;
-        const double4 d = dirs[ri.k];  // {wx, wz, 1/wx, 1/wz}
-        ri.wx = d.x;
-        ri.wz = d.y;
-        op.begin_ray(d.x, d.y);
-        // Plane crossings t(X) = X / w - c / w, evaluated with one FMA so the
-        // crossing of the domain's exit plane equals the clip bound exactly.
-        const double offx = -cx * d.z, offz = -cz * d.w;
-        const double ax = offx, bx = fma((double)nx, d.z, offx);
-        const double az = offz, bz = fma((double)nz, d.w, offz);
-        double lo = fmax(L.ta, fmax(fmin(ax, bx), fmin(az, bz)));
-        double hi = fmin(L.tb, fmin(fmax(ax, bx), fmax(az, bz)));
-        if (!ri.active) {
-            lo = 1.0;
-            hi = 0.0;
-        }
-
-        // Major axis m (the one crossed at least as often), minor axis n.
-        const bool xmaj = fabs(d.x) >= fabs(d.y);
-        const double wm = xmaj ? d.x : d.y, wn = xmaj ? d.y : d.x;
-        const double cm = xmaj ? cx : cz, cn = xmaj ? cz : cx;
-        const double im_ = xmaj ? d.z : d.w, in_ = xmaj ? d.w : d.z;
-        const double offm = xmaj ? offx : offz, offn = xmaj ? offz : offx;
-        const int nm = xmaj ? nx : nz, nn = xmaj ? nz : nx;
-        const int strm = xmaj ? 1 : nx, strn = xmaj ? nx : 1;
-        const int sm = wm > 0.0 ? 1 : -1, sn = wn > 0.0 ? 1 : -1;
-
-        const double pm0 = cm + lo * wm;
-        int im0 = wm > 0.0 ? (int)floor(pm0) : (int)ceil(pm0) - 1;
-        im0 = min(max(im0, 0), nm - 1);
-        const int mfirst = wm > 0.0 ? im0 + 1 : im0;  // first m-plane crossed
-
-        float I = 0.0f, T = 1.0f;
-        const int max_chunks = (nm + 2 + 15) / 16 + 1;
-        for (int chunk = 0; chunk < max_chunks; ++chunk) {
-            // ---- column j of this row's ray: one or two segments
-            const int j = chunk * 16 + l;
-            const double ta = (j == 0) ? lo : fma((double)(mfirst + (j - 1) * sm), im_, offm);
-            const double tb_ = fmin(fma((double)(mfirst + j * sm), im_, offm), hi);
-            const bool valid = ta < hi;
-            const int im = min(max(im0 + j * sm, 0), nm - 1);
-            const double pn = cn + ta * wn;
-            int in0 = wn > 0.0 ? (int)floor(pn) : (int)ceil(pn) - 1;
-            in0 = min(max(in0, 0), nn - 1);
-            const int nnext = wn > 0.0 ? in0 + 1 : in0;
-            const double tn = fma((double)nnext, in_, offn);
-            const bool two = valid && tn < tb_;
-            const double tmid = fmax(tn, ta);
-            const uint32_t cell1 = (uint32_t)(im * strm + in0 * strn);
-            const int in1 = min(max(in0 + sn, 0), nn - 1);
-            const uint32_t cell2 = (uint32_t)(im * strm + in1 * strn);
-            const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
-            const float ds2 = (float)fmax(tb_ - tmid, 0.0);
-
-            const uint64_t b1 = __ballot(valid);
-            if (b1 == 0) break;
-            const uint64_t b2 = __ballot(two);
-            const int pos = __popcll(b1 & row_bits & lt_bits) + __popcll(b2 & row_bits & lt_bits);
-            const int n_row = __popcll(b1 & row_bits) + __popcll(b2 & row_bits);
-            int n_max = 0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t rb = 0xFFFFull << (16 * q);
-                n_max = max(n_max, __popcll(b1 & rb) + __popcll(b2 & rb));
-            }
-            uint2* srow = reinterpret_cast<uint2*>(&seg[w][row][0]);
-            if (valid) srow[pos] = make_uint2(cell1, __float_as_uint(ds1));
-            if (two) srow[pos + 1] = make_uint2(cell2, __float_as_uint(ds2));
-            wave_sync();
-
-            // ---- step through the row's segments, 4 at a time. Positions past
-            // the row's count are steps with no opacity and no emission.
-            for (int s = 0; s < n_max; s += 4) {
-                const uint4 e01 = seg[w][row][s >> 1];
-                const uint4 e23 = seg[w][row][(s >> 1) + 1];
-                const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
-                const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
-                                      __uint_as_float(e23.w)};
-                typename Op::Raw raw[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float2 f = op.resolve(raw[q]);  // {optical depth per cell, log2 units; S}
-                    const float y = f.x * dsv[q];
-                    const float e = __builtin_amdgcn_exp2f(-y);
-                    I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
-                    T *= e;
-                }
-            }
-            wave_sync();
-        }
-
-        if (ri.active && L.has_up) {
-            // Bilinear taps on the cascade above: q = (u + 1/2)/2 - 1/2, so
-            // even u -> taps (u/2 - 1, u/2) with weights (1/4, 3/4), odd u ->
-            // taps ((u-1)/2, (u+1)/2) with weights (3/4, 1/4); clamped.
-            const int bx0 = (ri.u - 1) >> 1, bz0 = (ri.v - 1) >> 1;
-            const float fx = (ri.u & 1) ? 0.25f : 0.75f;
-            const float fz = (ri.v & 1) ? 0.25f : 0.75f;
-            const int txs[2] = {min(max(bx0, 0), L.qx - 1), min(max(bx0 + 1, 0), L.qx - 1)};
-            const int tzs[2] = {min(max(bz0, 0), L.qz - 1), min(max(bz0 + 1, 0), L.qz - 1)};
-            const float wxs[2] = {1.0f - fx, fx};
-            const float wzs[2] = {1.0f - fz, fz};
-            float far = 0.0f;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int bb = 0; bb < 2; ++bb) {
-                    const int64_t bi = (((int64_t)tzs[a] * L.qx + txs[bb]) * L.nd_up + 4 * (int64_t)ri.k) * kLB + l;
-                    const float c4 = up.get(bi) + up.get(bi + kLB) + up.get(bi + 2 * kLB) + up.get(bi + 3 * kLB);
-                    far = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far);
-                }
-            I = fmaf(T, far, I);
-        }
-        epi.finish(ri, l, lane, I, op);
+        march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], c, ray, p % L.px, p / L.px, k, active);
     }
 }
 
@@ -259,6 +287,23 @@ struct StoreF16Epi {
     {
         (void)lane;
         if (ri.active) out[ri.ray * kLB + l] = __float2half_rn(I * sc);
+    }
+};
+
+// Cascade-0 epilogue writing J directly: with N_0 = 4 directions the 4 rows
+// of a wavefront are the 4 directions of one cell (ray = cell * 4 + k), so
+// J = (1/4) sum over the rows, J[lam0 + l][cell] for l < n_valid.
+struct JEpi {
+    float* J;
+    int32_t lam0, n_valid;
+    int64_t ncell;
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish(const RayInfo& ri, int l, int lane, float I, const Op&)
+    {
+        float s = I + __shfl_xor(I, 16);
+        s += __shfl_xor(s, 32);
+        if (ri.active && (lane >> 4) == 0 && l < n_valid) J[(int64_t)(lam0 + l) * ncell + ri.ray / 4] = 0.25f * s;
     }
 };
 

@@ -494,6 +494,84 @@ __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const
     if (threadIdx.x == 0) atomicMax(max_change, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+
+// ------------------------------------------------------ warm-start features
+// Per cell: {log10 T, log10 ne, |v| [km/s], log10 chi_0 (opacity of line 0 at
+// its centre [1/m]), log10 Jbar_t for the first two lines}, Jbar_t the
+// profile-weighted mean intensity of line t, sum H(a, u/v_th) dnu J / sum
+// H dnu over the line's wavelengths (static profile at the cell); each
+// feature standardised with (mean, std).
+struct FeatArgs {
+    const float* J;        // [n_wave][ncell]
+    const double* T;
+    const double* ne;
+    const float2* vel;
+    const float* inv_vth;
+    const float* adamp;    // [n_lines][ncell]
+    const float4* line_rec;
+    const float* u_all;    // [n_wave] velocity offsets (lines)
+    const float* dnu_all;  // [n_wave]
+    int32_t lam0[2], lam1[2];  // wavelength ranges of lines 0 and 1
+    int32_t n_lines;
+    float voxel;
+    const float* norm;     // [2][6] mean, std
+    float* out;            // [ncell][6]
+};
+
+__global__ void k_features(int64_t ncell, VoigtTab vt, FeatArgs f)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    float v[6];
+    v[0] = log10f((float)f.T[c]);
+    v[1] = log10f((float)f.ne[c]);
+    const float2 w = f.vel[c];
+    v[2] = sqrtf(w.x * w.x + w.y * w.y) * 1e-3f;
+    const float kap = f.n_lines > 0 ? f.line_rec[c].x / (f.voxel * march::kLog2e) : 1e-30f;
+    v[3] = log10f(fmaxf(kap, 1e-30f));
+    for (int t = 0; t < 2; ++t) {
+        float num = 0.0f, den = 0.0f;
+        if (t < f.n_lines) {
+            const float a = f.adamp[(int64_t)t * ncell + c];
+            for (int l = f.lam0[t]; l < f.lam1[t]; ++l) {
+                const float h = voigt_lookup(vt, a, fabsf(f.u_all[l] * f.inv_vth[c])) * f.dnu_all[l];
+                num += h * f.J[(int64_t)l * ncell + c];
+                den += h;
+            }
+        }
+        v[4 + t] = log10f(fmaxf(den > 0.0f ? num / den : 0.0f, 1e-35f));
+    }
+    for (int q = 0; q < 6; ++q) f.out[c * 6 + q] = (v[q] - f.norm[q]) / f.norm[6 + q];
+}
+
+// log10(n_l / ntot) per cell, standardised: out[c][l] = (log10 frac - mean_l) / std_l.
+__global__ void k_log_fractions(int64_t ncell, int32_t nl, const double* __restrict__ pops,
+                                const double* __restrict__ ntot, const float* __restrict__ norm, float* __restrict__ out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    for (int l = 0; l < nl; ++l) {
+        const double fr = fmax(pops[(int64_t)l * ncell + c] / ntot[c], 1e-300);
+        out[c * nl + l] = ((float)log10(fr) - norm[l]) / norm[nl + l];
+    }
+}
+
+// Populations from predicted standardised log fractions y [c][l]:
+// n_l = ntot 10^{z_l} / sum_m 10^{z_m}, z = y std + mean (FP64).
+__global__ void k_pops_from_pred(int64_t ncell, int32_t nl, const float* __restrict__ y, const float* __restrict__ norm,
+                                 const double* __restrict__ ntot, double* __restrict__ pops)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    double z[kMaxL], zmax = -1e300, sum = 0.0;
+    for (int l = 0; l < nl; ++l) {
+        z[l] = (double)y[c * nl + l] * norm[nl + l] + norm[l];
+        zmax = fmax(zmax, z[l]);
+    }
+    for (int l = 0; l < nl; ++l) sum += exp10(z[l] - zmax);
+    for (int l = 0; l < nl; ++l) pops[(int64_t)l * ncell + c] = ntot[c] * exp10(z[l] - zmax) / sum;
+}
+
 }  // namespace nl
 }  // namespace rcx
 
@@ -519,7 +597,7 @@ struct rcx_nlte {
     // device
     float* bconst = nullptr;  // [n_batch][5][16]: W/N0, u, nu, alpha, 2 h nu^3 / c^2
     int32_t* d_tb = nullptr;  // [2][nt]
-    double *lte = nullptr, *cup = nullptr, *cdn = nullptr, *T = nullptr, *ntot = nullptr;
+    double *lte = nullptr, *cup = nullptr, *cdn = nullptr, *T = nullptr, *ntot = nullptr, *ne_copy = nullptr;
     float *inv_vth = nullptr, *adamp = nullptr, *sphi = nullptr, *lratio = nullptr, *hkt2 = nullptr;
     float2* vel = nullptr;
     float4* line_rec = nullptr;
@@ -533,6 +611,12 @@ struct rcx_nlte {
     float2* vtab = nullptr;
     float v_inv_da = 0.0f;
     bool atm_set = false;
+    float* u_all = nullptr;    // [n_wave]
+    float* dnu_all = nullptr;  // [n_wave]
+    float* Jtmp = nullptr;     // [n_wave][ncell] (warm start)
+    float* feat = nullptr;     // [ncell][6]
+    float* pred = nullptr;     // [ncell][n_levels]
+    float* norms = nullptr;    // [12 + 2 n_levels]
     std::vector<void*> allocs;
 };
 
@@ -727,6 +811,7 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->cdn, sizeof(double) * nt * nc));
     chk(dmalloc(s, &s->T, sizeof(double) * nc));
     chk(dmalloc(s, &s->ntot, sizeof(double) * nc));
+    chk(dmalloc(s, &s->ne_copy, sizeof(double) * nc));
     chk(dmalloc(s, &s->inv_vth, sizeof(float) * nc));
     chk(dmalloc(s, &s->adamp, sizeof(float) * std::max(1, A.n_lines) * nc));
     chk(dmalloc(s, &s->sphi, sizeof(float) * std::max(1, A.n_lines) * nc));
@@ -743,6 +828,9 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
     chk(dmalloc(s, &s->d_amax, sizeof(unsigned int)));
     chk(dmalloc(s, &s->vtab, sizeof(float2) * kNa * kNx));
+    chk(dmalloc(s, &s->u_all, sizeof(float) * n_wave));
+    chk(dmalloc(s, &s->dnu_all, sizeof(float) * n_wave));
+    chk(dmalloc(s, &s->norms, sizeof(float) * (12 + 2 * kMaxL)));
     if (e != hipSuccess) {
         rcx_nlte_destroy(s);
         return nlte_fail(RCX_E_NOMEM, std::string("rcx_nlte_create: hipMalloc: ") + hipGetErrorName(e));
@@ -754,6 +842,17 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     }
     chk(hipMemcpy(s->bconst, bc.data(), bc.size() * sizeof(float), hipMemcpyHostToDevice));
     chk(hipMemcpy(s->d_tb, tb.data(), tb.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    {
+        std::vector<float> u(n_wave, 0.0f), d(n_wave);
+        for (int32_t q = 0; q < n_wave; ++q) {
+            const Trans& t = A.t[s->trans[q]];
+            const double nu = kC / (s->lam_nm[q] * 1e-9);
+            if (t.kind == 0) u[q] = (float)(kC * (nu - t.nu0) / t.nu0);
+            d[q] = (float)s->dnu[q];
+        }
+        chk(hipMemcpy(s->u_all, u.data(), sizeof(float) * n_wave, hipMemcpyHostToDevice));
+        chk(hipMemcpy(s->dnu_all, d.data(), sizeof(float) * n_wave, hipMemcpyHostToDevice));
+    }
     if (e != hipSuccess) {
         rcx_nlte_destroy(s);
         return rcx::hip_fail(e, "rcx_nlte_create: hipMemcpy");
@@ -769,6 +868,7 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     const int64_t nc = s->ncell;
     RCX_HIP_TRY(hipMemcpyAsync(s->T, T, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     RCX_HIP_TRY(hipMemcpyAsync(s->ntot, ntot, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
+    RCX_HIP_TRY(hipMemcpyAsync(s->ne_copy, ne, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_pack_vel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, vel, s->vel);
     RCX_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, s->d_amax);
@@ -960,6 +1060,104 @@ int32_t rcx_nlte_destroy(rcx_nlte* s)
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->plan) rcx_plan_destroy(s->plan);
     delete s;
+    return RCX_OK;
+}
+
+}  // extern "C"
+
+static int32_t ensure_warm_buffers(rcx_nlte* s)
+{
+    if (s->Jtmp) return RCX_OK;
+    if (dmalloc(s, &s->Jtmp, sizeof(float) * s->n_wave * s->ncell) != hipSuccess ||
+        dmalloc(s, &s->feat, sizeof(float) * 6 * s->ncell) != hipSuccess ||
+        dmalloc(s, &s->pred, sizeof(float) * kMaxL * s->ncell) != hipSuccess)
+        return nlte_fail(RCX_E_NOMEM, "warm start buffers");
+    return RCX_OK;
+}
+
+static int32_t features(rcx_nlte* s, const float* J, const float* norm_host, float* out, hipStream_t st)
+{
+    std::vector<float> nrm(12);
+    for (int q = 0; q < 12; ++q) nrm[q] = norm_host ? norm_host[q] : (q < 6 ? 0.0f : 1.0f);
+    RCX_HIP_TRY(hipMemcpyAsync(s->norms, nrm.data(), sizeof(float) * 12, hipMemcpyHostToDevice, st));
+    FeatArgs f{};
+    f.J = J;
+    f.T = s->T;
+    f.ne = s->ne_copy;
+    f.vel = s->vel;
+    f.inv_vth = s->inv_vth;
+    f.adamp = s->adamp;
+    f.line_rec = s->line_rec;
+    f.u_all = s->u_all;
+    f.dnu_all = s->dnu_all;
+    f.n_lines = s->atom.n_lines;
+    for (int t = 0; t < 2; ++t) {
+        f.lam0[t] = f.lam1[t] = 0;
+        if (t < s->atom.n_lines) {
+            f.lam0[t] = s->batches[s->tb0[t]].lam0;
+            const auto& last = s->batches[s->tb1[t] - 1];
+            f.lam1[t] = last.lam0 + last.n;
+        }
+    }
+    f.voxel = (float)s->voxel;
+    f.norm = s->norms;
+    f.out = out;
+    const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
+    hipLaunchKernelGGL(k_features, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, vt, f);
+    RCX_HIP_TRY(hipGetLastError());
+    // norms must not be overwritten before the kernel has read them
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    return RCX_OK;
+}
+
+extern "C" {
+
+int32_t rcx_nlte_features(rcx_nlte* s, const double* pops, const float* norm_host, float* feat, hipStream_t st)
+{
+    if (!s || !pops || !feat) return nlte_fail(RCX_E_INVALID, "rcx_nlte_features: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_features: set the atmosphere first");
+    int32_t rc = ensure_warm_buffers(s);
+    if (rc != RCX_OK) return rc;
+    rc = formal_solve_rates(s, pops, s->rates, s->Jtmp, st);
+    if (rc != RCX_OK) return rc;
+    return features(s, s->Jtmp, norm_host, feat, st);
+}
+
+int32_t rcx_nlte_log_fractions(rcx_nlte* s, const double* pops, const float* norm_host, float* out, hipStream_t st)
+{
+    if (!s || !pops || !out) return nlte_fail(RCX_E_INVALID, "rcx_nlte_log_fractions: null argument");
+    const int nl = s->atom.nl;
+    std::vector<float> nrm(2 * nl);
+    for (int q = 0; q < 2 * nl; ++q) nrm[q] = norm_host ? norm_host[q] : (q < nl ? 0.0f : 1.0f);
+    RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, nrm.data(), sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_log_fractions, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, pops, s->ntot,
+                       s->norms + 12, out);
+    RCX_HIP_TRY(hipGetLastError());
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_host, const float* targ_norm_host,
+                            double* pops_out, hipStream_t st)
+{
+    if (!s || !net || !feat_norm_host || !targ_norm_host || !pops_out)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_warm_start: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_warm_start: set the atmosphere first");
+    int32_t rc = ensure_warm_buffers(s);
+    if (rc != RCX_OK) return rc;
+    const int nl = s->atom.nl;
+    RCX_HIP_TRY(hipMemcpyAsync(pops_out, s->lte, sizeof(double) * nl * s->ncell, hipMemcpyDeviceToDevice, st));
+    rc = formal_solve_rates(s, pops_out, s->rates, s->Jtmp, st);
+    if (rc != RCX_OK) return rc;
+    rc = features(s, s->Jtmp, feat_norm_host, s->feat, st);
+    if (rc != RCX_OK) return rc;
+    rc = rcx_mlp_forward(net, s->feat, s->pred, (int32_t)s->ncell, st);
+    if (rc != RCX_OK) return rc;
+    RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, targ_norm_host, sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pops_from_pred, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, s->pred,
+                       s->norms + 12, s->ntot, pops_out);
+    RCX_HIP_TRY(hipGetLastError());
+    RCX_HIP_TRY(hipStreamSynchronize(st));
     return RCX_OK;
 }
 

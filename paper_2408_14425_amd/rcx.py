@@ -277,6 +277,11 @@ def _load_nlte():
     L.rcx_nlte_voigt_eval.argtypes = [vp, i32, vp, vp, vp, vp]
     L.rcx_nlte_dims.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.rcx_nlte_destroy.argtypes = [vp]
+    L.rcx_nlte_features.argtypes = [vp, vp, vp, vp, vp]
+    L.rcx_nlte_log_fractions.argtypes = [vp, vp, vp, vp, vp]
+    L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
+    for n in ("rcx_nlte_features", "rcx_nlte_log_fractions", "rcx_nlte_warm_start"):
+        getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
               "rcx_nlte_dims", "rcx_nlte_destroy"):
@@ -392,9 +397,228 @@ class Nlte:
         rcx_nlte_voigt_eval(self.handle, a, x, out)
         return out
 
+    def features(self, pops, norm=None):
+        """Warm-start features [cells][6] (device FP32) at populations pops."""
+        import numpy as np
+        import torch
+        out = torch.empty((self.inp.nx * self.inp.nz, 6), dtype=torch.float32, device="cuda:0")
+        nrm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        _check(_load_nlte().rcx_nlte_features(self.handle, _dev_ptr(pops, "torch.float64", "pops"),
+                                              None if nrm is None else nrm.ctypes.data,
+                                              _dev_ptr(out, "torch.float32", "feat"), _stream_ptr(None)),
+               "rcx_nlte_features")
+        return out
+
+    def log_fractions(self, pops, norm=None):
+        import numpy as np
+        import torch
+        out = torch.empty((self.inp.nx * self.inp.nz, self.n_levels), dtype=torch.float32, device="cuda:0")
+        nrm = None if norm is None else np.ascontiguousarray(norm, np.float32)
+        _check(_load_nlte().rcx_nlte_log_fractions(self.handle, _dev_ptr(pops, "torch.float64", "pops"),
+                                                   None if nrm is None else nrm.ctypes.data,
+                                                   _dev_ptr(out, "torch.float32", "out"), _stream_ptr(None)),
+               "rcx_nlte_log_fractions")
+        return out
+
+    def warm_start(self, net, feat_norm, targ_norm):
+        """Populations predicted by the network (device FP64 [levels][nz][nx])."""
+        import numpy as np
+        import torch
+        pops = torch.empty((self.n_levels, self.inp.nz, self.inp.nx), dtype=torch.float64, device="cuda:0")
+        fn = np.ascontiguousarray(feat_norm, np.float32)
+        tn = np.ascontiguousarray(targ_norm, np.float32)
+        _check(_load_nlte().rcx_nlte_warm_start(self.handle, net.handle, fn.ctypes.data, tn.ctypes.data,
+                                                _dev_ptr(pops, "torch.float64", "pops"), _stream_ptr(None)),
+               "rcx_nlte_warm_start")
+        return pops
+
     def close(self):
         if getattr(self, "handle", None):
             rcx_nlte_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ MLP
+
+
+def _load_mlp():
+    L = load()
+    if getattr(L, "_mlp_bound", False):
+        return L
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.rcx_mlp_create.argtypes = [i32, i32, i32, i32, i32, C.POINTER(vp)]
+    L.rcx_mlp_n_params.argtypes = [vp, C.POINTER(i64)]
+    L.rcx_mlp_set_params.argtypes = [vp, vp, i64]
+    L.rcx_mlp_get_params.argtypes = [vp, vp, i64]
+    L.rcx_mlp_forward.argtypes = [vp, vp, vp, i32, vp]
+    L.rcx_mlp_gradients.argtypes = [vp, vp, vp, i32, vp, C.POINTER(C.c_float), vp]
+    L.rcx_mlp_train_step.argtypes = [vp, vp, vp, i32, C.c_float, C.POINTER(C.c_float), vp]
+    L.rcx_mlp_destroy.argtypes = [vp]
+    for n in ("rcx_mlp_create", "rcx_mlp_n_params", "rcx_mlp_set_params", "rcx_mlp_get_params", "rcx_mlp_forward",
+              "rcx_mlp_gradients", "rcx_mlp_train_step", "rcx_mlp_destroy"):
+        getattr(L, n).restype = i32
+    L._mlp_bound = True
+    return L
+
+
+def rcx_mlp_create(n_in: int, width: int, depth: int, n_out: int, max_batch: int) -> int:
+    h = C.c_void_p()
+    _check(_load_mlp().rcx_mlp_create(n_in, width, depth, n_out, max_batch, C.byref(h)), "rcx_mlp_create")
+    return h.value
+
+
+class Mlp:
+    """Owns an ``rcx_mlp``."""
+
+    def __init__(self, n_in=6, width=128, depth=4, n_out=4, max_batch=65536):
+        self.n_in, self.n_out = n_in, n_out
+        self.handle = rcx_mlp_create(n_in, width, depth, n_out, max_batch)
+        n = C.c_int64()
+        _check(_load_mlp().rcx_mlp_n_params(self.handle, C.byref(n)), "rcx_mlp_n_params")
+        self.n_params = n.value
+
+    def set_params(self, flat):
+        import numpy as np
+        f = np.ascontiguousarray(flat, np.float32)
+        _check(_load_mlp().rcx_mlp_set_params(self.handle, f.ctypes.data, len(f)), "rcx_mlp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        f = np.empty(self.n_params, np.float32)
+        _check(_load_mlp().rcx_mlp_get_params(self.handle, f.ctypes.data, len(f)), "rcx_mlp_get_params")
+        return f
+
+    def forward(self, x, stream=None):
+        import torch
+        y = torch.empty((x.shape[0], self.n_out), dtype=torch.float32, device=x.device)
+        _check(_load_mlp().rcx_mlp_forward(self.handle, _dev_ptr(x, "torch.float32", "x"),
+                                           _dev_ptr(y, "torch.float32", "y"), x.shape[0], _stream_ptr(stream)),
+               "rcx_mlp_forward")
+        return y
+
+    def gradients(self, x, y_ref, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        loss = C.c_float()
+        _check(_load_mlp().rcx_mlp_gradients(self.handle, _dev_ptr(x, "torch.float32", "x"),
+                                             _dev_ptr(y_ref, "torch.float32", "y_ref"), x.shape[0],
+                                             _dev_ptr(g, "torch.float32", "grad"), C.byref(loss),
+                                             _stream_ptr(stream)), "rcx_mlp_gradients")
+        return loss.value, g
+
+    def train_step(self, x, y_ref, lr: float, stream=None) -> float:
+        loss = C.c_float()
+        _check(_load_mlp().rcx_mlp_train_step(self.handle, _dev_ptr(x, "torch.float32", "x"),
+                                              _dev_ptr(y_ref, "torch.float32", "y_ref"), x.shape[0], float(lr),
+                                              C.byref(loss), _stream_ptr(stream)), "rcx_mlp_train_step")
+        return loss.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load_mlp().rcx_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batches
+
+
+def _load_batch():
+    L = load()
+    if getattr(L, "_batch_bound", False):
+        return L
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.rcx_batch_create.argtypes = [i32, C.POINTER(rcx_grid), C.POINTER(i32), C.POINTER(rcx_params), C.POINTER(vp)]
+    L.rcx_batch_set_tiling.argtypes = [vp, i32]
+    L.rcx_batch_set_graph.argtypes = [vp, i32]
+    L.rcx_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+    L.rcx_batch_work.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+    L.rcx_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_char_p, C.POINTER(i32), vp]
+    L.rcx_batch_destroy.argtypes = [vp]
+    for n in ("rcx_batch_create", "rcx_batch_set_tiling", "rcx_batch_set_graph", "rcx_batch_solve",
+              "rcx_batch_work", "rcx_batch_autotune", "rcx_batch_destroy"):
+        getattr(L, n).restype = i32
+    L._batch_bound = True
+    return L
+
+
+def _ptr_array(ts, what: str):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = _dev_ptr(t, "torch.float32", f"{what}[{i}]")
+    return arr
+
+
+class Batch:
+    """Owns an ``rcx_batch``: formal solutions of several atmospheres (grids
+    ``shapes[a] = (nx, nz)``, ``n_wave[a]`` wavelengths) in one persistent
+    launch."""
+
+    def __init__(self, shapes, n_wave, voxel_scale=1.0, storage: int = RCX_STORE_F32, c0_t1: float = 1.5,
+                 t_rule: int = RCX_T_GEOMETRIC):
+        n = len(shapes)
+        if len(n_wave) != n:
+            raise ValueError("shapes and n_wave differ in length")
+        vs = voxel_scale if hasattr(voxel_scale, "__len__") else [voxel_scale] * n
+        grids = (rcx_grid * n)(*[rcx_grid(int(nx), int(nz), float(v)) for (nx, nz), v in zip(shapes, vs)])
+        nw = (C.c_int32 * n)(*[int(w) for w in n_wave])
+        p = rcx_params_default()
+        p.storage, p.c0_t1, p.t_rule = storage, c0_t1, t_rule
+        h = C.c_void_p()
+        _check(_load_batch().rcx_batch_create(n, grids, nw, C.byref(p), C.byref(h)), "rcx_batch_create")
+        self.handle = h.value
+        self.shapes, self.n_wave = [tuple(s) for s in shapes], list(n_wave)
+
+    def set_tiling(self, rays_per_item: int):
+        _check(_load_batch().rcx_batch_set_tiling(self.handle, int(rays_per_item)), "rcx_batch_set_tiling")
+
+    def set_graph(self, enable: bool):
+        _check(_load_batch().rcx_batch_set_graph(self.handle, int(bool(enable))), "rcx_batch_set_graph")
+
+    def work(self):
+        r, c = C.c_int64(), C.c_int64()
+        _check(_load_batch().rcx_batch_work(self.handle, C.byref(r), C.byref(c)), "rcx_batch_work")
+        return r.value, c.value
+
+    def _arrays(self, chi, eta, J):
+        import torch
+        if J is None:
+            J = [torch.empty_like(c) for c in chi]
+        if not (len(chi) == len(eta) == len(J) == len(self.shapes)):
+            raise ValueError("one chi, eta and J per atmosphere")
+        for a, (c, (nx, nz), nw) in enumerate(zip(chi, self.shapes, self.n_wave)):
+            if tuple(c.shape) != (nw, nz, nx) or tuple(eta[a].shape) != (nw, nz, nx) or \
+                    tuple(J[a].shape) != (nw, nz, nx):
+                raise ValueError(f"atmosphere {a}: arrays must be [{nw}][{nz}][{nx}]")
+        return J, _ptr_array(chi, "chi"), _ptr_array(eta, "eta"), _ptr_array(J, "J")
+
+    def solve(self, chi, eta, J=None, stream=None):
+        J, pc, pe, pj = self._arrays(chi, eta, J)
+        _check(_load_batch().rcx_batch_solve(self.handle, pc, pe, pj, _stream_ptr(stream)), "rcx_batch_solve")
+        return J
+
+    def autotune(self, chi, eta, J=None, cache_path=None, stream=None) -> int:
+        J, pc, pe, pj = self._arrays(chi, eta, J)
+        best = C.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _check(_load_batch().rcx_batch_autotune(self.handle, pc, pe, pj, path, C.byref(best), _stream_ptr(stream)),
+               "rcx_batch_autotune")
+        return best.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _load_batch().rcx_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,140 @@
+"""Learned warm start for the non-LTE iteration: training data from
+converged runs of the method itself, training of the network on the GPU, and
+the comparison of iterations and wall time to convergence from the LTE start
+and from the network's prediction. Every numerical step runs in librcx
+(formal solutions, iterations, features, network training and inference);
+this module only orchestrates and keeps the bookkeeping.
+
+    python -m paper_2408_14425_amd.warmstart --train-n 256 --train-runs 16 --eval-n 512
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import rcx, workloads as W
+
+
+def converged_run(n: int, seed: int, n_line: int, n_cont: int, tol: float, max_iter: int):
+    """Features at LTE and converged log fractions of one seeded atmosphere."""
+    inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
+    s = rcx.Nlte(inp)
+    pops = s.lte()
+    feat = s.features(pops).cpu().numpy()
+    rc, it, ch = s.iterate(pops, max_iter, tol)
+    targ = s.log_fractions(pops).cpu().numpy()
+    s.close()
+    return feat, targ, it, ch
+
+
+def dataset(n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 500):
+    X, Y, info = [], [], []
+    for seed in seeds:
+        f, t, it, ch = converged_run(n, seed, n_line, n_cont, tol, max_iter)
+        X.append(f)
+        Y.append(t)
+        info.append({"seed": int(seed), "iterations": it, "last_change": ch})
+    return np.concatenate(X), np.concatenate(Y), info
+
+
+def norms(a: np.ndarray) -> np.ndarray:
+    mu = a.mean(axis=0)
+    sd = a.std(axis=0)
+    sd = np.where(sd > 1e-6, sd, 1.0)
+    return np.stack([mu, sd]).astype(np.float32)
+
+
+def train(X, Y, epochs: int = 20, batch: int = 8192, lr: float = 2e-3, seed: int = 0, width: int = 128,
+          depth: int = 4):
+    import torch
+    fn, tn = norms(X), norms(Y)
+    Xs = ((X - fn[0]) / fn[1]).astype(np.float32)
+    Ys = ((Y - tn[0]) / tn[1]).astype(np.float32)
+    net = rcx.Mlp(X.shape[1], width, depth, Y.shape[1], max_batch=batch)
+    net.set_params(W.mlp_init_params(X.shape[1], width, depth, Y.shape[1], seed=seed))
+    rng = np.random.default_rng(seed)
+    xt = torch.from_numpy(Xs).cuda()
+    yt = torch.from_numpy(Ys).cuda()
+    losses = []
+    n = len(Xs)
+    for ep in range(epochs):
+        perm = torch.from_numpy(rng.permutation(n)).cuda()
+        lr_ep = lr * (0.5 * (1 + np.cos(np.pi * ep / epochs)))
+        tot = 0.0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            tot += net.train_step(xt[idx].contiguous(), yt[idx].contiguous(), lr_ep)
+        losses.append(tot / max(1, n // batch))
+    return net, fn, tn, losses
+
+
+def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 1000,
+             ref_tol: float = 1e-6):
+    """For each seed: iterations and wall time to max change < tol from the
+    LTE start and from the warm start, and the largest relative difference of
+    both results from a reference iterated to ref_tol."""
+    import torch
+    out = []
+    for seed in seeds:
+        inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
+        s = rcx.Nlte(inp)
+        ref = s.lte()
+        rc_r, it_r, ch_r = s.iterate(ref, 5 * max_iter, ref_tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p_lte = s.lte()
+        rc0, it0, ch0 = s.iterate(p_lte, max_iter, tol)
+        torch.cuda.synchronize()
+        t_lte = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        p_ws = s.warm_start(net, fn, tn)
+        p_pred = p_ws.clone()
+        rc1, it1, ch1 = s.iterate(p_ws, max_iter, tol)
+        torch.cuda.synchronize()
+        t_ws = time.perf_counter() - t0
+        err = lambda p: float(((p - ref).abs() / ref.abs()).max())
+        out.append({
+            "seed": int(seed), "n": n, "reference_iterations": it_r, "reference_change": ch_r,
+            "lte_iterations": it0, "lte_seconds": t_lte, "lte_error_vs_reference": err(p_lte),
+            "warm_iterations": it1, "warm_seconds": t_ws, "warm_error_vs_reference": err(p_ws),
+            "prediction_error_vs_reference": err(p_pred),
+            "converged": bool(rc0 == 0 and rc1 == 0),
+        })
+        s.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-n", type=int, default=128)
+    ap.add_argument("--train-runs", type=int, default=16)
+    ap.add_argument("--eval-n", type=int, default=256)
+    ap.add_argument("--eval-seeds", type=int, nargs="+", default=[6000, 6001])
+    ap.add_argument("--n-line", type=int, default=64)
+    ap.add_argument("--n-cont", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    t0 = time.perf_counter()
+    X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, fn, tn, losses = train(X, Y, epochs=a.epochs)
+    t_train = time.perf_counter() - t0
+    ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont)
+    rep = {"train": {"n": a.train_n, "runs": a.train_runs, "samples": len(X), "data_seconds": t_data,
+                     "train_seconds": t_train, "epochs": a.epochs, "loss_first": losses[0], "loss_last": losses[-1],
+                     "runs_info": info},
+           "eval": ev}
+    s = json.dumps(rep)
+    print(s, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(s + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -289,3 +289,17 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
     lam, trans, dnu = nlte_wavelength_grid(SYNTH_ATOM, n_line, n_cont)
     return NlteInput(T, ne, ntot, vel.astype(np.float32), lam, trans, dnu, voxel, SYNTH_ATOM,
                      f"nlte{n}x{nz}_w{len(lam)}_s{seed}")
+
+
+def mlp_init_params(n_in: int = 6, width: int = 128, depth: int = 4, n_out: int = 4, seed: int = 0):
+    """Seeded initial parameters of the warm-start network, flat FP32, layer
+    by layer W [fan_in][fan_out] then b [fan_out], each uniform in
+    +-1/sqrt(fan_in) (the common default for linear layers)."""
+    rng = np.random.default_rng(seed)
+    dims = [n_in] + [width] * depth + [n_out]
+    out = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        lim = 1.0 / np.sqrt(a)
+        out.append(rng.uniform(-lim, lim, a * b))
+        out.append(rng.uniform(-lim, lim, b))
+    return np.concatenate(out).astype(np.float32)

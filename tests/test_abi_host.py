@@ -98,3 +98,22 @@ def test_nlte_create_rejects_continuum_wavelength_beyond_edge():
     with pytest.raises(rcx.RcxError) as e:
         rcx.rcx_nlte_create(rcx.rcx_grid(8, 8, inp.voxel), rcx.rcx_params_default(), atom, lam, inp.trans, inp.dnu)
     assert e.value.code == rcx.RCX_E_INVALID
+
+
+def test_batch_create_rejects_bad_arguments():
+    L = rcx._load_batch()
+    h = C.c_void_p()
+    g = (rcx.rcx_grid * 1)(rcx.rcx_grid(16, 16, 1.0))
+    nw = (C.c_int32 * 1)(4)
+    p = rcx.rcx_params_default()
+    assert L.rcx_batch_create(0, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_INVALID
+    assert L.rcx_batch_create(1, None, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_INVALID
+    p.c0_dirs = 8
+    assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
+    p = rcx.rcx_params_default()
+    p.n_cascades = 3
+    assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
+    assert h.value is None
+    assert L.rcx_batch_solve(None, None, None, None, None) == rcx.RCX_E_INVALID
+    assert L.rcx_batch_set_tiling(None, 4096) == rcx.RCX_E_INVALID
+    assert L.rcx_batch_destroy(None) == rcx.RCX_OK

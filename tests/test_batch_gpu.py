@@ -1,0 +1,162 @@
+"""Batched persistent formal solve vs the FP64 oracle and vs per-atmosphere
+plan solves, through the C ABI.
+
+Tolerances: 1e-4 relative on J against the oracle (FP32 path, as for the
+single-plan solve); against the single-plan GPU solve 1e-6 relative (the
+same per-ray arithmetic; only the order of the four cascade-0 direction sums
+differs); bitwise across tile sizes, graph on/off and repeated replays (the
+per-ray arithmetic does not depend on which work item computes it).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_14425_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-4
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rand_atm(nx, nz, nw, seed):
+    rng = np.random.default_rng(seed)
+    chi = (10 ** rng.uniform(-2, 2, (nw, nz, nx))).astype(np.float32)
+    eta = (chi * rng.uniform(0.2, 3.0, (nw, nz, nx))).astype(np.float32)
+    return chi, eta
+
+
+# uneven sizes (ragged against the probe spacing, wavelength counts that do
+# not fill a 16-wide batch, more batches than buffer slots)
+CASES = [(64, 64, 3, 1), (37, 53, 20, 2), (128, 96, 1, 3), (1, 1, 2, 4), (200, 256, 70, 5)]
+
+
+def _inputs(cases):
+    torch = _torch()
+    host = [_rand_atm(nx, nz, nw, sd) for nx, nz, nw, sd in cases]
+    chi = [torch.from_numpy(c).cuda() for c, _ in host]
+    eta = [torch.from_numpy(e).cuda() for _, e in host]
+    return host, chi, eta
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def test_uneven_batch_matches_oracle_and_plans():
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    print("[gpu] batch uneven", CASES, flush=True)
+    host, chi, eta = _inputs(CASES)
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in CASES], [nw for _, _, nw, _ in CASES])
+    J = B.solve(chi, eta)
+    torch.cuda.synchronize()
+    for a, (nx, nz, nw, _) in enumerate(CASES):
+        Jg = J[a].cpu().numpy().astype(np.float64)
+        plan = rcx.Plan(nx, nz, nw)
+        Jp = plan.formal_solve(chi[a], eta[a]).cpu().numpy().astype(np.float64)
+        plan.close()
+        assert _rel(Jg, Jp) <= 1e-6, (a, _rel(Jg, Jp))
+        lam = np.unique(np.linspace(0, nw - 1, min(nw, 4)).astype(int))
+        Jo = oracle.formal_solve(host[a][0][lam], host[a][1][lam], W.n_cascades_for(nx, nz))["J"]
+        r = _rel(Jg[lam], Jo)
+        print(f"atm {a} {nx}x{nz} w{nw}: vs plan {_rel(Jg, Jp):.2e} vs oracle {r:.2e}")
+        assert r <= RTOL
+    B.close()
+
+
+def test_tiling_and_graph_do_not_change_results():
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    host, chi, eta = _inputs(CASES)
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in CASES], [nw for _, _, nw, _ in CASES])
+    ref = [j.cpu().numpy() for j in B.solve(chi, eta)]
+    J = [torch.empty_like(c) for c in chi]
+    for rays in (16, 1024, 65536):
+        for graph in (False, True):
+            print(f"[gpu] batch tiling {rays} graph {graph}", flush=True)
+            B.set_tiling(rays)
+            B.set_graph(graph)
+            for rep in range(3):  # graph replays with eager work in between
+                for j in J:
+                    j.fill_(-1.0)
+                B.solve(chi, eta, J)
+                torch.cuda.synchronize()
+                for a in range(len(CASES)):
+                    assert np.array_equal(J[a].cpu().numpy(), ref[a]), (rays, graph, rep, a)
+                _ = (chi[0] * 2.0).sum().item()
+    B.close()
+
+
+def test_fp16_batch_error_is_bounded():
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    cases = [(64, 64, 3, 1), (100, 80, 33, 7)]
+    print("[gpu] batch fp16", cases, flush=True)
+    host, chi, eta = _inputs(cases)
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in cases], [nw for _, _, nw, _ in cases],
+                  storage=rcx.RCX_STORE_F16_SCALED)
+    J = B.solve(chi, eta)
+    torch.cuda.synchronize()
+    for a, (nx, nz, nw, _) in enumerate(cases):
+        Jg = J[a].cpu().numpy().astype(np.float64)
+        lam = np.array([0, nw - 1])
+        Jo = oracle.formal_solve(host[a][0][lam], host[a][1][lam], W.n_cascades_for(nx, nz))["J"]
+        r = _rel(Jg[lam], Jo)
+        print(f"fp16 batch atm {a}: max rel {r:.3e}")
+        assert r < 2e-3
+    B.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    cases = CASES[:3]
+    host, chi, eta = _inputs(cases)
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in cases], [nw for _, _, nw, _ in cases])
+    ref = [j.cpu().numpy() for j in B.solve(chi, eta)]
+    path = str(tmp_path / "tiles.jsonl")
+    print("[gpu] batch autotune", flush=True)
+    best = B.autotune(chi, eta, cache_path=path)
+    assert best in (1024, 4096, 16384, 65536)
+    assert open(path).read().count("\n") == 1
+    assert B.autotune(chi, eta, cache_path=path) == best  # cache hit: no new line
+    assert open(path).read().count("\n") == 1
+    J = B.solve(chi, eta)
+    torch.cuda.synchronize()
+    for a in range(len(cases)):
+        assert np.array_equal(J[a].cpu().numpy(), ref[a])
+    B.close()
+
+
+def test_line_medium_batch_sampled_against_oracle():
+    """Three line-medium atmospheres (config-2 type) at 256^2, 384^2 and
+    512^2 with 32, 48 and 64 wavelengths in one launch; sampled cells checked
+    against the oracle through their dependency cones."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    specs = [(256, 32, 11), (384, 48, 12), (512, 64, 13)]
+    inps = [W.line_medium(side, nw, seed=sd) for side, nw, sd in specs]
+    print("[gpu] batch line media", specs, flush=True)
+    chi = [torch.from_numpy(i.chi).cuda() for i in inps]
+    eta = [torch.from_numpy(i.eta).cuda() for i in inps]
+    B = rcx.Batch([(i.nx, i.nz) for i in inps], [i.n_wave for i in inps])
+    J = [j.cpu().numpy() for j in B.solve(chi, eta)]
+    B.close()
+    rng = np.random.default_rng(5)
+    for inp, Jg in zip(inps, J):
+        n = inp.nx
+        cells = [(0, 0), (n - 1, n - 1)] + [tuple(rng.integers(0, n, 2)) for _ in range(3)]
+        need = np.zeros((n, n), np.uint8)
+        for x, z in cells:
+            need[z, x] = 1
+        for lam in (0, inp.n_wave // 2, inp.n_wave - 1):
+            Jo = oracle.formal_solve(inp.chi[lam:lam + 1], inp.eta[lam:lam + 1], inp.n_cascades, need=need)["J"][0]
+            for x, z in cells:
+                assert abs(float(Jg[lam, z, x]) - Jo[z, x]) <= RTOL * Jo[z, x], (inp.name, lam, x, z)
