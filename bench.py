@@ -1,10 +1,14 @@
-"""Benchmark: radiance-cascades formal solve on one MI355X.
+"""Benchmark: radiance-cascades formal solve and non-LTE iteration on one MI355X.
 
 A step is one formal solve of the 1024 x 1024, 64-wavelength, 7-cascade line
 medium (seed 2): prep, every cascade's fused march + merge, J. Inputs are
-resident in HBM before the timed region. Prints one JSON line.
+resident in HBM before the timed region. The same line also reports the
+FP16-storage variant of that solve and the seconds per converged non-LTE
+solve (1024 x 1024, 160 wavelengths, max relative change < 1e-3) from the
+LTE start with FP32 and FP16 cascade storage, and from the learned warm
+start when a trained network is present. Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-nlte]
 """
 from __future__ import annotations
 
@@ -20,6 +24,12 @@ if ROOT not in sys.path:
 
 METRIC = "ray-intervals/s + s per converged non-LTE solve, plain vs learned/FP16"
 HBM_PEAK_GBS = 8000.0
+# Vector lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (78.6 TFLOP/s of unpacked FP32 FMA). The march needs about 8 lane-op slots
+# per cell step and wavelength (optical depth, exp2 at quarter rate, 1 - e,
+# the I update, the transmission update).
+VALU_LANE_OPS = 39.3e12
+VALU_OPS_PER_STEP = 8
 # Algorithmic bytes per cell step and wavelength: chi and S, FP32 each.
 BYTES_PER_STEP = 8
 
@@ -37,6 +47,12 @@ def parse():
                          "to scale hardware byte counters")
     ap.add_argument("--cpu-waves", type=int, default=1,
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
+    ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--nlte-n", type=int, default=1024)
+    ap.add_argument("--nlte-max-iter", type=int, default=300)
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "warmstart_mlp.npz"),
+                    help="trained warm-start network (skipped when absent)")
     return ap.parse_args()
 
 
@@ -56,19 +72,28 @@ def algorithmic_bytes(work, n_wave):
     return b
 
 
-def measured_traffic(kernel_file: str, profile: str):
+KERNEL_SOURCES = ("march_rows.h", "fs_kernels.hip", "rcx_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2408_14425_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(profile: str):
     """HBM bytes per launch of the march kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since."""
-    import hashlib
     import re
     try:
         text = open(os.path.join(ROOT, "profiles", profile)).read()
-        src = open(os.path.join(ROOT, "paper_2408_14425_amd", "csrc", kernel_file), "rb").read()
     except OSError:
         return None
     h = re.search(r"kernel_source_sha256: ([0-9a-f]+)", text)
     t = re.search(r"traffic_bytes_per_launch: ([0-9.eE+-]+)", text)
-    if not h or not t or h.group(1) != hashlib.sha256(src).hexdigest():
+    if not h or not t or h.group(1) != kernel_source_hash():
         return None
     return float(t.group(1))
 
@@ -91,6 +116,76 @@ def cpu_baseline(inp, n_waves: int):
         "sample": f"FP64 oracle full formal solve of {n_waves} of the 64 wavelengths "
                   f"({r['nonempty']} non-empty ray intervals, {r['steps']} cell steps) in {dt:.1f} s",
     }
+
+
+def time_solves(plan, chi, eta, J, steps: int, warmup: int):
+    """Wall time of `steps` formal solves after `warmup`, and the per-cascade
+    kernel times from the plan's HIP events over the timed solves."""
+    import torch
+    for _ in range(warmup):
+        plan.formal_solve(chi, eta, J)
+    torch.cuda.synchronize()
+    plan.get_timing()  # discard anything pending
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.formal_solve(chi, eta, J)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan.set_timing(False)
+    return dt, plan.get_timing()
+
+
+def nlte_solves(args):
+    """Seconds to a converged non-LTE solve (max relative change < 1e-3)
+    from the LTE start with FP32 and FP16 cascade storage, and from the
+    learned warm start when trained weights are present."""
+    import numpy as np
+    import torch
+
+    from paper_2408_14425_amd import rcx, warmstart, workloads
+    inp = workloads.nlte_atmosphere(args.nlte_n, seed=3, n_line=64, n_cont=32)
+    out = {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz} grid, {inp.n_wave} wavelengths "
+                       f"(2 lines x 64 + 32 continuum), synthetic 3-level + continuum atom, seed 3, "
+                       f"stop at max relative change < 1e-3",
+           "tol": 1e-3}
+    net = None
+    if os.path.exists(args.weights):
+        net, fn, tn = warmstart.load(args.weights)
+    runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False)]
+    if net is not None:
+        runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True)]
+    final = {}
+    for name, storage, learned in runs:
+        s = rcx.Nlte(inp, storage=storage)
+        # one untimed iteration from LTE warms the kernels up
+        p = s.lte()
+        s.iterate(p, 1, 0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = s.warm_start(net, fn, tn) if learned else s.lte()
+        it, rc, ch = 0, 1, float("inf")
+        while rc != 0 and it < args.nlte_max_iter:
+            # chunks of the same iteration, so that progress is visible
+            rc, k, ch = s.iterate(p, min(5, args.nlte_max_iter - it), 1e-3)
+            it += k
+            print(f"[bench] non-LTE {name}: {it} iterations, change {ch:.3e}, "
+                  f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        final[name] = p
+        s.close()
+        out[name] = {"seconds": dt, "iterations": it, "last_change": ch, "converged": rc == 0,
+                     "s_per_iteration": dt / max(it, 1)}
+        print(f"[bench] non-LTE {name}: {it} iterations, {dt:.2f} s", file=sys.stderr, flush=True)
+    ref = final["plain_fp32"]
+    for name in final:
+        if name != "plain_fp32":
+            out[name]["max_rel_diff_vs_plain_fp32"] = float(((final[name] - ref).abs() / ref.abs()).max())
+    if net is not None:
+        net.close()
+    return out
 
 
 def main():
@@ -119,21 +214,22 @@ def main():
     J = torch.empty_like(chi)
     plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
     work = plan.work()
-    for _ in range(args.warmup):
-        plan.formal_solve(chi, eta, J)
-    torch.cuda.synchronize()
-    plan.get_timing()  # discard anything pending
-    plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.formal_solve(chi, eta, J)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    plan.set_timing(False)
-    ms_level, ms_other, n_launch, n_solves = plan.get_timing()
+    dt, (ms_level, ms_other, n_launch, n_solves) = time_solves(plan, chi, eta, J, args.steps, args.warmup)
     ok = bool(torch.isfinite(J).all().item())
     plan.close()
+
+    fp16 = None
+    if not args.no_fp16:
+        # the same solve with FP16 cascade storage
+        plan16 = rcx.Plan(inp.nx, inp.nz, inp.n_wave, storage=rcx.RCX_STORE_F16_SCALED)
+        J16 = torch.empty_like(chi)
+        dt16, _ = time_solves(plan16, chi, eta, J16, args.steps, args.warmup)
+        plan16.close()
+        fp16 = {
+            "ms_per_step": dt16 / args.steps * 1e3,
+            "value": work.rays_nonempty * inp.n_wave / (dt16 / args.steps),
+            "max_rel_diff_vs_fp32": float(((J16 - J).abs() / J.abs()).max().item()),
+        }
 
     ms_step = dt / args.steps * 1e3
     rays = work.rays_nonempty * inp.n_wave
@@ -167,17 +263,21 @@ def main():
             "kernel_ms_prep_and_J": ms_other / max(n_solves, 1),
             "finite": ok,
         },
+        "fp16_storage": fp16,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_march_merge",
+            "kernel": "k_march_rows",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("fs_kernels.hip", "k_march_merge_line1024_w64.md"),
+            "traffic": measured_traffic("k_march_rows_line1024_w64.md"),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "valu_frac": work.cell_steps * inp.n_wave * VALU_OPS_PER_STEP / (dt / args.steps) / VALU_LANE_OPS,
         },
     }
+    if not args.no_nlte:
+        out["nonlte"] = nlte_solves(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_waves)
     print(json.dumps(out), flush=True)

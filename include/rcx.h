@@ -136,14 +136,15 @@ int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_ot
 int32_t rcx_plan_destroy(rcx_plan* plan);
 
 /* ================================================================ batches
- * Many formal solutions in one persistent launch (the GPU analogue of
- * solving several atmospheres and wavelength batches at once, Secs. 2.3 and
- * 3.2): work items (atmosphere, 16-wavelength batch, cascade, probe tile)
- * are queued from the top cascade down; a grid sized to the resident
- * capacity pops them, each waits (bounded) on the completion counter of its
- * cascade above, marches, merges and publishes; cascade 0 writes J.
- * Solves are enqueued as a captured HIP graph, re-captured when the input
- * or output pointers change. */
+ * Many formal solutions at once (several atmospheres, each with its
+ * wavelength batches; every one an independent formal solution, Secs. 2.3
+ * and 3.2): work items (atmosphere, 16-wavelength batch, cascade, probe
+ * tile) are grouped into generations by their distance from the
+ * atmosphere's top cascade, and each generation is one launch over all
+ * atmospheres and batches; stream order provides every dependency, so no
+ * workgroup waits on another. Cascade 0 writes J directly. The sequence of
+ * launches is captured into a HIP graph and replayed, re-captured when the
+ * input or output pointers change. */
 typedef struct rcx_batch rcx_batch;
 
 /* n_atm atmospheres with grids[a] and n_wave[a] wavelengths. p as for
@@ -151,14 +152,16 @@ typedef struct rcx_batch rcx_batch;
  * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
 int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
                          rcx_batch** out);
-/* Probe-tile size of a work item in rays (>= 16; default 4096). */
+/* Probe-tile size of a work item in rays (>= 16; default 4096): one
+ * workgroup marches one tile. */
 int32_t rcx_batch_set_tiling(rcx_batch* b, int32_t rays_per_item);
-/* Enqueue through a captured graph (1, default) or by direct launches (0). */
+/* Enqueue through the captured graph (1, default) or by direct launches (0). */
 int32_t rcx_batch_set_graph(rcx_batch* b, int32_t enable);
 /* chi_host[a], eta_host[a], J_host[a]: host arrays of n_atm device pointers
- * to [n_wave[a]][nz][nx] float32, as for rcx_formal_solve. Synchronises the
- * stream. RCX_E_HIP if a work item timed out waiting (the launch still
- * drains; J is then invalid). */
+ * to [n_wave[a]][nz][nx] float32, as for rcx_formal_solve; the pointers are
+ * recorded in the graph and must stay valid while they are in use.
+ * Synchronises the stream. Errors: RCX_E_INVALID (null arguments);
+ * RCX_E_HIP. */
 int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
                         float* const* J_host, hipStream_t stream);
 /* Work summed over atmospheres and wavelengths (rcx_work semantics). */
@@ -218,6 +221,10 @@ typedef struct rcx_nlte rcx_nlte;
  * trans_host[n_wave] (transition index of each wavelength, grouped and
  * ordered as described above) and dnu_host[n_wave] (frequency quadrature
  * weights of the rate integrals, Hz). All host arrays are copied.
+ * p->storage = RCX_STORE_F16_SCALED stores cascades >= 1 of every
+ * formal solution as FP16 with a per-wavelength power-of-two scale from the
+ * largest source function of that wavelength (lines: S_line; continua:
+ * eta/chi); cascade 0, the rates and the rate matrix stay FP32/FP64.
  * Errors: RCX_E_INVALID (nulls, sizes, ungrouped or out-of-range
  * transitions, a wavelength outside its continuum's edge);
  * RCX_E_UNSUPPORTED (more levels/lines/continua than the maxima);
@@ -325,13 +332,15 @@ int32_t rcx_mlp_destroy(rcx_mlp* m);
  * intensity of line t; each standardised as (f - mean)/std with
  * norm_host[2][6] = {means, stds} (NULL: no standardisation). Synchronises. */
 int32_t rcx_nlte_features(rcx_nlte* s, const double* pops, const float* norm_host, float* feat, hipStream_t stream);
-/* out [nz*nx][n_levels] (device FP32) = (log10(n_l/ntot) - mean_l)/std_l,
+/* Log departure coefficients, the warm start's targets:
+ * out [nz*nx][n_levels] (device FP32) = (log10(n_l / n_l^LTE) - mean_l)/std_l
+ * with n^LTE the Saha-Boltzmann populations of the atmosphere,
  * norm_host[2][n_levels] (NULL: none). Synchronises. */
-int32_t rcx_nlte_log_fractions(rcx_nlte* s, const double* pops, const float* norm_host, float* out,
-                               hipStream_t stream);
+int32_t rcx_nlte_log_departures(rcx_nlte* s, const double* pops, const float* norm_host, float* out,
+                                hipStream_t stream);
 /* Learned warm start: LTE populations, one formal solution, features,
- * network inference, and populations n_l = ntot 10^{z_l} / sum_m 10^{z_m}
- * with z the de-standardised prediction (targ_norm_host[2][n_levels]);
+ * network inference, and populations n_l = ntot b_l n_l^LTE / sum_m b_m n_m^LTE
+ * with log10 b the de-standardised prediction (targ_norm_host[2][n_levels]);
  * pops_out [n_levels][nz][nx] device FP64. The plain iteration started
  * from it remains the judge of convergence. Synchronises. */
 int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_host, const float* targ_norm_host,

@@ -1,20 +1,19 @@
-// batch.hip -- many atmospheres and wavelength batches in one persistent
-// launch across all cascade levels (the radiance-cascades formal solution of
-// Osborne & Sannikov, arXiv:2408.14425, Secs. 2.3 and 3.2, batched).
+// batch.hip -- formal solutions of many atmospheres and wavelength batches
+// (the radiance-cascades formal solution of Osborne & Sannikov,
+// arXiv:2408.14425, Secs. 2.3 and 3.2), batched.
 //
 // Work item = (atmosphere, 16-wavelength batch, cascade, probe tile). Each
 // atmosphere has a few buffer slots (a pair of cascade buffers each); batch
-// b uses slot b mod K and starts after batch b - K has finished. Items sit
-// in a device queue ordered by (b div K, distance from the atmosphere's top
-// cascade), so every item's dependencies (all items of the cascade above of
-// the same batch, or the last cascade of batch b - K) come earlier in the
-// queue. A persistent grid pops items in order; an item waits on the
-// completion counter of its dependency (acquire at agent scope, a spin
-// bounded in wall-clock time that raises an error flag and lets the wave
-// go on), marches its rays with the same march_ray as the per-level
-// kernels, then publishes (release at agent scope). A workgroup only waits
-// for items already taken by running workgroups, which in turn wait only
-// for earlier items, so the queue drains. Cascade 0 writes J directly.
+// b uses slot b mod K and runs in round b div K. A generation is the set of
+// items with the same (round, distance from the atmosphere's top cascade):
+// every dependency of an item (the cascade above of the same batch, or the
+// last cascade of the batch that used the slot before) lies in an earlier
+// generation, so one grouped launch per generation, in stream order, needs
+// no waiting between workgroups. Within a launch the workgroups take items
+// in order; each marches its probe tile with the same march_ray as the
+// per-level kernels. Cascade 0 writes J directly. The whole sequence (input
+// prep for every atmosphere + all generations) is captured into a HIP graph
+// and replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,96 +60,56 @@ struct Item {
 
 constexpr int32_t kMaxSlots = 4;
 
+// One generation: workgroup g processes items begin + g, begin + g + grid, ...
 template <bool F16>
-__global__ __launch_bounds__(kBlock) void k_batch(const Task* __restrict__ tasks, const Item* __restrict__ items,
-                                                  uint32_t n_items, unsigned int* __restrict__ head,
-                                                  unsigned int* __restrict__ done, unsigned int* __restrict__ err,
-                                                  uint64_t spin_ticks)
+__global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ tasks, const Item* __restrict__ items,
+                                                      uint32_t begin, uint32_t end)
 {
     __shared__ uint4 seg[kBlock / 64][4][16];
-    __shared__ uint32_t s_item;
-    __shared__ uint32_t s_skip;
     const march::RowCtx c = march::row_ctx();
     {
         uint4* sw = &seg[c.w][0][0];
         sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
         march::wave_sync();
     }
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(head, 1u);
-        __syncthreads();
-        const uint32_t it = s_item;
-        if (it >= n_items) break;
+    for (uint32_t it = begin + blockIdx.x; it < end; it += gridDim.x) {
         const Item item = items[it];
         const Task& T = tasks[item.task];
-        if (threadIdx.x == 0) {
-            uint32_t skip = 0;
-            if (T.dep >= 0) {
-                const uint32_t need = tasks[T.dep].n_items;
-                const uint64_t t0 = wall_clock64();
-                while (__hip_atomic_load(&done[T.dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                    __builtin_amdgcn_s_sleep(8);
-                    if (wall_clock64() - t0 > spin_ticks) {
-                        atomicOr(err, 1u);
-                        skip = 1;
-                        break;
-                    }
-                }
-            }
-            s_skip = skip;
-        }
-        __syncthreads();
-        __threadfence();  // every wave's reads of the cascade above come after the acquire
-        if (!s_skip) {
-            march::FieldOp op{};
-            op.Fb = T.Fb;
-            op.fb_bytes = T.fb_bytes;
-            op.init(c.l);
-            const int32_t N = T.L.nd;
-            const int64_t n_rays = (int64_t)T.tx * T.tz * N;
-            for (int64_t base = (int64_t)c.w * 4; base < n_rays; base += march::kRaysPerBlock) {
-                const int64_t r = base + c.row;
-                const int32_t k = (int32_t)(r % N);
-                const int32_t pl = (int32_t)(r / N);
-                const int32_t u = item.u0 + pl % T.tx, v = item.v0 + pl / T.tx;
-                const bool active = r < n_rays && u < T.L.px && v < T.L.pz;
-                const int64_t ray = ((int64_t)v * T.L.px + u) * N + k;
-                if (F16) {
-                    march::UpF16 up{(const __half*)T.up, T.inv_scale_b, 0.0f};
-                    up.init(c.l);
-                    if (T.level == 0) {
-                        march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                        march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
-                    } else {
-                        march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
-                        epi.init(c.l);
-                        march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
-                    }
+        march::FieldOp op{};
+        op.Fb = T.Fb;
+        op.fb_bytes = T.fb_bytes;
+        op.init(c.l);
+        const int32_t N = T.L.nd;
+        const int64_t n_rays = (int64_t)T.tx * T.tz * N;
+        for (int64_t base = (int64_t)c.w * 4; base < n_rays; base += march::kRaysPerBlock) {
+            const int64_t r = base + c.row;
+            const int32_t k = (int32_t)(r % N);
+            const int32_t pl = (int32_t)(r / N);
+            const int32_t u = item.u0 + pl % T.tx, v = item.v0 + pl / T.tx;
+            const bool active = r < n_rays && u < T.L.px && v < T.L.pz;
+            const int64_t ray = ((int64_t)v * T.L.px + u) * N + k;
+            if (F16) {
+                march::UpF16 up{(const __half*)T.up, T.inv_scale_b, 0.0f};
+                up.init(c.l);
+                if (T.level == 0) {
+                    march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
                 } else {
-                    march::UpF32 up{(const float*)T.up};
-                    if (T.level == 0) {
-                        march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                        march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
-                    } else {
-                        march::StoreEpi epi{(float*)T.out};
-                        march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
-                    }
+                    march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
+                    epi.init(c.l);
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                }
+            } else {
+                march::UpF32 up{(const float*)T.up};
+                if (T.level == 0) {
+                    march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                } else {
+                    march::StoreEpi epi{(float*)T.out};
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
                 }
             }
         }
-        __threadfence();  // this wave's stores reach device scope before the item is published
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[item.task], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
-}
-
-__global__ void k_reset(unsigned int* head, unsigned int* done, uint32_t n_tasks, unsigned int* err)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_tasks) done[i] = 0u;
-    if (i == 0) {
-        *head = 0u;
-        *err = 0u;
     }
 }
 
@@ -172,24 +131,20 @@ struct rcx_batch {
     std::vector<size_t> casc_half;     // bytes of one of the two buffers
     std::vector<int32_t> casc_index;   // first slot of atmosphere a
     std::vector<int32_t> n_slots;      // slots of atmosphere a
-    uint64_t spin_ticks = 0;           // bound on one wait, in wall-clock ticks
     int32_t rays_per_item = 4096;
     std::vector<Task> tasks_h;
     std::vector<Item> items_h;
     Task* tasks_d = nullptr;
     Item* items_d = nullptr;
     size_t tasks_cap = 0, items_cap = 0;
-    unsigned int *head = nullptr, *done = nullptr, *err = nullptr;
-    size_t done_cap = 0;
-    int grid = 0;
+    std::vector<uint32_t> gen_begin;  // item range of each generation: [gen_begin[g], gen_begin[g + 1])
+    int grid_cap = 0;                 // workgroups per launch at most (resident capacity)
     std::vector<float*> J_bound;  // J pointers the tasks were built for
     // graph
     bool use_graph = true;
     hipStream_t cap = nullptr;  // capture stream (the legacy default stream cannot be captured)
     hipGraphExec_t gexec = nullptr;
     std::vector<const float*> g_chi, g_eta;
-    std::vector<float*> g_J;
-    int32_t g_rays = -1;
     std::vector<void*> allocs;
 };
 
@@ -219,8 +174,9 @@ void tile_for(int32_t rays, int32_t N, int32_t px, int32_t pz, int32_t* tx, int3
     *tz = std::min(a, pz);
 }
 
-// Build the task and item lists for the current J pointers and tile size.
-// Returns false if the queue order would let an item wait for a later one.
+// Build the task and item lists for the current J pointers and tile size,
+// grouped into generations. Returns false if a dependency would not precede
+// its dependent (an internal error).
 bool build_work(rcx_batch* s, float* const* J)
 {
     s->tasks_h.clear();
@@ -285,23 +241,23 @@ bool build_work(rcx_batch* s, float* const* J)
         const Task& b = s->tasks_h[y.task];
         return (int64_t)a.L.px * a.L.pz * a.L.nd > (int64_t)b.L.px * b.L.pz * b.L.nd;
     });
-    for (const auto& o : order) {
+    s->gen_begin.clear();
+    std::vector<int32_t> gen_of(s->tasks_h.size(), -1);
+    for (size_t q = 0; q < order.size(); ++q) {
+        const auto& o = order[q];
+        if (q == 0 || o.round != order[q - 1].round || o.top_dist != order[q - 1].top_dist)
+            s->gen_begin.push_back((uint32_t)s->items_h.size());
+        gen_of[o.task] = (int32_t)s->gen_begin.size() - 1;
         const Task& T = s->tasks_h[o.task];
         for (int32_t v0 = 0; v0 < T.L.pz; v0 += T.tz)
             for (int32_t u0 = 0; u0 < T.L.px; u0 += T.tx) s->items_h.push_back({o.task, u0, v0});
     }
-    // every dependency's items precede all of the dependent task's items
-    std::vector<int64_t> first(s->tasks_h.size(), -1), lastpos(s->tasks_h.size(), -1), count(s->tasks_h.size(), 0);
-    for (size_t q = 0; q < s->items_h.size(); ++q) {
-        const int32_t t = s->items_h[q].task;
-        if (first[t] < 0) first[t] = (int64_t)q;
-        lastpos[t] = (int64_t)q;
-        ++count[t];
-    }
+    s->gen_begin.push_back((uint32_t)s->items_h.size());
+    // every dependency lies in an earlier generation
     for (size_t t = 0; t < s->tasks_h.size(); ++t) {
         const Task& T = s->tasks_h[t];
-        if (count[t] != (int64_t)T.n_items) return false;
-        if (T.dep >= 0 && !(T.dep != (int32_t)t && lastpos[T.dep] < first[t])) return false;
+        if (gen_of[t] < 0) return false;
+        if (T.dep >= 0 && !(gen_of[T.dep] >= 0 && gen_of[T.dep] < gen_of[t])) return false;
     }
     return true;
 }
@@ -321,12 +277,6 @@ hipError_t upload_work(rcx_batch* s)
         e = hipMalloc(&s->items_d, sizeof(Item) * s->items_cap);
         if (e != hipSuccess) return e;
     }
-    if (s->tasks_h.size() > s->done_cap) {
-        if (s->done) (void)hipFree(s->done);
-        s->done_cap = s->tasks_h.size();
-        e = hipMalloc(&s->done, sizeof(unsigned int) * s->done_cap);
-        if (e != hipSuccess) return e;
-    }
     e = hipMemcpy(s->tasks_d, s->tasks_h.data(), sizeof(Task) * s->tasks_h.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(s->items_d, s->items_h.data(), sizeof(Item) * s->items_h.size(), hipMemcpyHostToDevice);
@@ -344,17 +294,17 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
         if (e == hipSuccess && s->f16) e = launch_scales(s->n_batch[a] * kLB, s->smax[a], s->scale[a], s->inv_scale[a], st);
         if (e != hipSuccess) return e;
     }
-    const uint32_t nt = (uint32_t)s->tasks_h.size();
-    hipLaunchKernelGGL(k_reset, dim3((nt + 255) / 256 + 1), dim3(256), 0, st, s->head, s->done, nt, s->err);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (s->f16)
-        hipLaunchKernelGGL(k_batch<true>, dim3(s->grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d,
-                           (uint32_t)s->items_h.size(), s->head, s->done, s->err, s->spin_ticks);
-    else
-        hipLaunchKernelGGL(k_batch<false>, dim3(s->grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d,
-                           (uint32_t)s->items_h.size(), s->head, s->done, s->err, s->spin_ticks);
-    return hipGetLastError();
+    for (size_t g = 0; g + 1 < s->gen_begin.size(); ++g) {
+        const uint32_t b = s->gen_begin[g], e = s->gen_begin[g + 1];
+        const unsigned grid = (unsigned)std::min<uint32_t>(e - b, (uint32_t)s->grid_cap);
+        if (s->f16)
+            hipLaunchKernelGGL(k_batch_gen<true>, dim3(grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d, b, e);
+        else
+            hipLaunchKernelGGL(k_batch_gen<false>, dim3(grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d, b, e);
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
 }
 
 void drop_graph(rcx_batch* s)
@@ -430,32 +380,23 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
         if (e != hipSuccess) break;
     }
     chk(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
-    chk(balloc(s, &s->head, sizeof(unsigned int)));
-    chk(balloc(s, &s->err, sizeof(unsigned int)));
     if (e != hipSuccess) {
         rcx_batch_destroy(s);
         return bfail(RCX_E_NOMEM, std::string("rcx_batch_create: hipMalloc: ") + hipGetErrorName(e));
     }
-    // persistent grid: resident capacity (both kernel variants have the same footprint)
+    // workgroups per generation launch: at most the resident capacity
     int dev = 0, n_cu = 0, per_cu = 0;
     chk(hipGetDevice(&dev));
     chk(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     if (s->f16)
-        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, kBlock, 0));
+        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_gen<true>, kBlock, 0));
     else
-        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, kBlock, 0));
+        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_gen<false>, kBlock, 0));
     if (e != hipSuccess || n_cu < 1 || per_cu < 1) {
         rcx_batch_destroy(s);
         return rcx::hip_fail(e == hipSuccess ? hipErrorInvalidValue : e, "rcx_batch_create: occupancy query");
     }
-    s->grid = n_cu * per_cu;
-    int clock_khz = 0;
-    chk(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
-    if (e != hipSuccess || clock_khz < 1) {
-        rcx_batch_destroy(s);
-        return rcx::hip_fail(e == hipSuccess ? hipErrorInvalidValue : e, "rcx_batch_create: wall clock rate");
-    }
-    s->spin_ticks = (uint64_t)clock_khz * 1000ull * 20ull;  // 20 s
+    s->grid_cap = n_cu * per_cu;
     *out = s;
     return RCX_OK;
 }
@@ -515,10 +456,7 @@ int32_t rcx_batch_solve(rcx_batch* s, const float* const* chi_host, const float*
     } else {
         RCX_HIP_TRY(enqueue(s, chi_host, eta_host, st));
     }
-    unsigned int err = 0;
-    RCX_HIP_TRY(hipMemcpyAsync(&err, s->err, sizeof(err), hipMemcpyDeviceToHost, st));
     RCX_HIP_TRY(hipStreamSynchronize(st));
-    if (err) return bfail(RCX_E_HIP, "rcx_batch_solve: a work item timed out waiting for the cascade above");
     return RCX_OK;
 }
 
@@ -598,7 +536,6 @@ int32_t rcx_batch_destroy(rcx_batch* s)
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->tasks_d) (void)hipFree(s->tasks_d);
     if (s->items_d) (void)hipFree(s->items_d);
-    if (s->done) (void)hipFree(s->done);
     for (rcx_plan* P : s->plans) rcx_plan_destroy(P);
     if (s->cap) (void)hipStreamDestroy(s->cap);
     delete s;

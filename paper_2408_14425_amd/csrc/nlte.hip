@@ -267,14 +267,15 @@ struct ContBatch {
 };
 
 __global__ void k_synth_cont(AtomDev A, int64_t ncell, const double* __restrict__ pops, const double* __restrict__ T,
-                             ContBatch cb, const float* lratio, double voxel, float2* __restrict__ Fb)
+                             ContBatch cb, const float* lratio, double voxel, float2* __restrict__ Fb,
+                             unsigned int* __restrict__ smax_b)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= ncell * kLB) return;
-    const int64_t c = idx / kLB;
+    const bool in = idx < ncell * kLB;  // no early return: the block reduces below
+    const int64_t c = in ? idx / kLB : 0;
     const int l = (int)(idx % kLB);
     float2 v = make_float2(0.0f, 0.0f);
-    if (l < cb.n) {
+    if (in && l < cb.n) {
         const Trans& tr = A.t[cb.trans];
         const double ni = pops[(int64_t)tr.i * ncell + c];
         const double nc = pops[(int64_t)tr.j * ncell + c];
@@ -289,7 +290,46 @@ __global__ void k_synth_cont(AtomDev A, int64_t ncell, const double* __restrict_
         else
             v = make_float2(kChiFloor * (float)kLog2eD, (float)(eta / kChiFloor));
     }
-    Fb[idx] = v;
+    if (in) Fb[idx] = v;
+    if (smax_b) {
+        // per-wavelength max of S over the 16 cells of this block (lanes l,
+        // l + 16, ... hold wavelength l), then one atomic per wavelength
+        float m = v.y;
+        m = fmaxf(m, __shfl_xor(m, 16));
+        m = fmaxf(m, __shfl_xor(m, 32));
+        __shared__ float red[256 / 64][kLB];
+        const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        if (lane < kLB) red[w][lane] = m;
+        __syncthreads();
+        if (threadIdx.x < kLB) {
+            float r = red[0][threadIdx.x];
+            for (int q = 1; q < (int)(blockDim.x >> 6); ++q) r = fmaxf(r, red[q][threadIdx.x]);
+            atomicMax(&smax_b[threadIdx.x], __float_as_uint(r));
+        }
+    }
+}
+
+// Max over cells of a line's source function (every wavelength of a line
+// batch shares S_line), into all 16 entries of the batch's smax.
+__global__ void k_smax_line(int64_t ncell, const float4* __restrict__ rec, unsigned int* __restrict__ smax_b)
+{
+    __shared__ float red[256];
+    float m = 0.0f;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, rec[c].y);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x < kLB) atomicMax(&smax_b[threadIdx.x], __float_as_uint(red[0]));
+}
+
+__global__ void k_zero_u32n(unsigned int* p, int32_t n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // ------------------------------------------------------------ line march op
@@ -545,31 +585,33 @@ __global__ void k_features(int64_t ncell, VoigtTab vt, FeatArgs f)
 }
 
 // log10(n_l / ntot) per cell, standardised: out[c][l] = (log10 frac - mean_l) / std_l.
-__global__ void k_log_fractions(int64_t ncell, int32_t nl, const double* __restrict__ pops,
-                                const double* __restrict__ ntot, const float* __restrict__ norm, float* __restrict__ out)
+__global__ void k_log_departures(int64_t ncell, int32_t nl, const double* __restrict__ pops,
+                                 const double* __restrict__ lte, const float* __restrict__ norm, float* __restrict__ out)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     for (int l = 0; l < nl; ++l) {
-        const double fr = fmax(pops[(int64_t)l * ncell + c] / ntot[c], 1e-300);
-        out[c * nl + l] = ((float)log10(fr) - norm[l]) / norm[nl + l];
+        const double b = fmax(pops[(int64_t)l * ncell + c], 1e-300) / fmax(lte[(int64_t)l * ncell + c], 1e-300);
+        out[c * nl + l] = ((float)log10(b) - norm[l]) / norm[nl + l];
     }
 }
 
-// Populations from predicted standardised log fractions y [c][l]:
-// n_l = ntot 10^{z_l} / sum_m 10^{z_m}, z = y std + mean (FP64).
+// Populations from predicted standardised log departure coefficients
+// y [c][l]: n_l = n_l^LTE 10^{z_l}, z = y std + mean, renormalised to
+// sum_l n_l = ntot (FP64).
 __global__ void k_pops_from_pred(int64_t ncell, int32_t nl, const float* __restrict__ y, const float* __restrict__ norm,
-                                 const double* __restrict__ ntot, double* __restrict__ pops)
+                                 const double* __restrict__ lte, const double* __restrict__ ntot,
+                                 double* __restrict__ pops)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    double z[kMaxL], zmax = -1e300, sum = 0.0;
+    double n[kMaxL], sum = 0.0;
     for (int l = 0; l < nl; ++l) {
-        z[l] = (double)y[c * nl + l] * norm[nl + l] + norm[l];
-        zmax = fmax(zmax, z[l]);
+        const double z = (double)y[c * nl + l] * norm[nl + l] + norm[l];
+        n[l] = lte[(int64_t)l * ncell + c] * exp10(fmin(z, 30.0));
+        sum += n[l];
     }
-    for (int l = 0; l < nl; ++l) sum += exp10(z[l] - zmax);
-    for (int l = 0; l < nl; ++l) pops[(int64_t)l * ncell + c] = ntot[c] * exp10(z[l] - zmax) / sum;
+    for (int l = 0; l < nl; ++l) pops[(int64_t)l * ncell + c] = ntot[c] * n[l] / sum;
 }
 
 }  // namespace nl
@@ -604,6 +646,9 @@ struct rcx_nlte {
     float4* epi_rec = nullptr;
     float2* Fcont = nullptr;
     float* casc[2] = {nullptr, nullptr};
+    bool f16 = false;                 // cascades >= 1 stored as scaled FP16
+    unsigned int* smax = nullptr;     // [n_batch][16] max S (float bits)
+    float *scale = nullptr, *inv_scale = nullptr;  // [n_batch][16]
     float2* part = nullptr;
     float* rates = nullptr;
     unsigned long long* d_max = nullptr;
@@ -646,15 +691,24 @@ __global__ void k_pack_vel(int64_t ncell, const float* __restrict__ v, float2* _
 
 unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <class Op, class Epi>
+template <class Op, class Epi, class Up>
 hipError_t launch_level(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
-                        const float* up, hipStream_t st)
+                        const Up& up, hipStream_t st)
 {
     const int64_t total = (int64_t)L.px * L.pz * L.nd;
-    const march::UpF32 u{up};
-    hipLaunchKernelGGL((march::k_march_rows<Op, Epi, march::UpF32>), march_grid(total), dim3(kBlock), 0, st, L, nx,
-                       nz, op, epi, dirs, u, total);
+    hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
+                       dirs, up, total);
     return hipGetLastError();
+}
+
+// One cascade of one batch: the opacity op (line or field), the epilogue
+// (store FP32 / FP16, or the cascade-0 rates) and the reader of the cascade
+// above (FP32 or FP16).
+template <class Epi, class Up>
+hipError_t launch_level_op(int32_t kind, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
+                           const march::FieldOp& fop, const Epi& epi, const double4* dirs, const Up& up, hipStream_t st)
+{
+    return kind == 0 ? launch_level(L, nx, nz, lop, epi, dirs, up, st) : launch_level(L, nx, nz, fop, epi, dirs, up, st);
 }
 
 template <int NL>
@@ -831,6 +885,10 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->u_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->dnu_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->norms, sizeof(float) * (12 + 2 * kMaxL)));
+    s->f16 = p->storage == RCX_STORE_F16_SCALED;
+    chk(dmalloc(s, &s->smax, sizeof(unsigned int) * nb * kLB));
+    chk(dmalloc(s, &s->scale, sizeof(float) * nb * kLB));
+    chk(dmalloc(s, &s->inv_scale, sizeof(float) * nb * kLB));
     if (e != hipSuccess) {
         rcx_nlte_destroy(s);
         return nlte_fail(RCX_E_NOMEM, std::string("rcx_nlte_create: hipMalloc: ") + hipGetErrorName(e));
@@ -910,22 +968,38 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
     hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
     RCX_HIP_TRY(hipGetLastError());
     const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
-    for (size_t b = 0; b < s->batches.size(); ++b) {
+    const int32_t nb = (int32_t)s->batches.size();
+    if (s->f16) {
+        hipLaunchKernelGGL(k_zero_u32n, dim3(blocks_for((int64_t)nb * kLB, 256)), dim3(256), 0, st, s->smax, nb * kLB);
+        RCX_HIP_TRY(hipGetLastError());
+    }
+    // continuum fields (and the per-wavelength max S of every batch)
+    for (int32_t b = 0; b < nb; ++b) {
         const auto& B = s->batches[b];
         const Trans& tr = A.t[B.trans];
-        const float* bc = s->bconst + b * 5 * kLB;
-        float2* Fb = s->Fcont + (size_t)std::max(B.cont_slot, 0) * nc * kLB;
+        unsigned int* smax_b = s->f16 ? s->smax + (size_t)b * kLB : nullptr;
         if (tr.kind == 1) {
             ContBatch cb{};
             cb.trans = B.trans;
             cb.n = B.n;
             for (int q = 0; q < B.n; ++q) cb.nu[q] = kC / (s->lam_nm[B.lam0 + q] * 1e-9);
+            float2* Fb = s->Fcont + (size_t)B.cont_slot * nc * kLB;
             hipLaunchKernelGGL(k_synth_cont, dim3(blocks_for(nc * kLB, 256)), dim3(256), 0, st, A, nc, pops, s->T, cb,
-                               s->lratio, s->voxel, Fb);
+                               s->lratio, s->voxel, Fb, smax_b);
+            RCX_HIP_TRY(hipGetLastError());
+        } else if (smax_b) {
+            hipLaunchKernelGGL(k_smax_line, dim3(std::min<unsigned>(blocks_for(nc, 256), 1024u)), dim3(256), 0, st, nc,
+                               s->line_rec + (size_t)tr.line * nc, smax_b);
             RCX_HIP_TRY(hipGetLastError());
         }
+    }
+    if (s->f16) RCX_HIP_TRY(launch_scales(nb * kLB, s->smax, s->scale, s->inv_scale, st));
+    for (int32_t b = 0; b < nb; ++b) {
+        const auto& B = s->batches[b];
+        const Trans& tr = A.t[B.trans];
+        const float* bc = s->bconst + b * 5 * kLB;
         march::FieldOp fop{};
-        fop.Fb = Fb;
+        fop.Fb = s->Fcont + (size_t)std::max(B.cont_slot, 0) * nc * kLB;
         fop.fb_bytes = (uint32_t)(nc * kLB * sizeof(float2));
         LineOp lop{};
         if (tr.kind == 0) {
@@ -946,29 +1020,41 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         re.ell_cells = (float)std::sqrt(0.5);
         re.voxel = (float)s->voxel;
         re.kind = tr.kind;
+        const float* sc_b = s->scale + (size_t)b * kLB;
+        const float* isc_b = s->inv_scale + (size_t)b * kLB;
         int cur = 0;
-        const float* up = nullptr;
+        const void* up = nullptr;
         for (int32_t i = P->n_casc - 1; i >= 0; --i) {
             if (P->top_skipped && i == P->n_casc - 1) continue;
             const LevelDesc& L = P->levels[i];
             const double4* dirs = P->dirs_dev + P->dir_off[i];
             float* outb = s->casc[cur];
-            const float* upl = L.has_up ? up : nullptr;
+            const void* upl = L.has_up ? up : nullptr;
             hipError_t e;
-            if (i > 0) {
-                march::StoreEpi se{outb};
-                e = tr.kind == 0 ? launch_level(L, nx, nz, lop, se, dirs, upl, st)
-                                 : launch_level(L, nx, nz, fop, se, dirs, upl, st);
+            if (s->f16) {
+                // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
+                const march::UpF16 u16{(const __half*)upl, isc_b, 0.0f};
+                if (i > 0) {
+                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, march::StoreF16Epi{(__half*)outb, sc_b, 0.0f},
+                                        dirs, u16, st);
+                } else {
+                    re.out = outb;
+                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, re, dirs, u16, st);
+                }
             } else {
-                re.out = outb;
-                e = tr.kind == 0 ? launch_level(L, nx, nz, lop, re, dirs, upl, st)
-                                 : launch_level(L, nx, nz, fop, re, dirs, upl, st);
+                const march::UpF32 u32{(const float*)upl};
+                if (i > 0) {
+                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, march::StoreEpi{outb}, dirs, u32, st);
+                } else {
+                    re.out = outb;
+                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, re, dirs, u32, st);
+                }
             }
             RCX_HIP_TRY(e);
             up = outb;
             cur ^= 1;
         }
-        if (J) RCX_HIP_TRY(launch_j(up, J, B.lam0, B.n, nc, 4, st));
+        if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, st));
     }
     hipLaunchKernelGGL(k_rates_sum, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, A.nt, s->d_tb, s->d_tb + A.nt,
                        s->part, rates);
@@ -1123,14 +1209,15 @@ int32_t rcx_nlte_features(rcx_nlte* s, const double* pops, const float* norm_hos
     return features(s, s->Jtmp, norm_host, feat, st);
 }
 
-int32_t rcx_nlte_log_fractions(rcx_nlte* s, const double* pops, const float* norm_host, float* out, hipStream_t st)
+int32_t rcx_nlte_log_departures(rcx_nlte* s, const double* pops, const float* norm_host, float* out, hipStream_t st)
 {
-    if (!s || !pops || !out) return nlte_fail(RCX_E_INVALID, "rcx_nlte_log_fractions: null argument");
+    if (!s || !pops || !out) return nlte_fail(RCX_E_INVALID, "rcx_nlte_log_departures: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_log_departures: set the atmosphere first");
     const int nl = s->atom.nl;
     std::vector<float> nrm(2 * nl);
     for (int q = 0; q < 2 * nl; ++q) nrm[q] = norm_host ? norm_host[q] : (q < nl ? 0.0f : 1.0f);
     RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, nrm.data(), sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_log_fractions, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, pops, s->ntot,
+    hipLaunchKernelGGL(k_log_departures, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, pops, s->lte,
                        s->norms + 12, out);
     RCX_HIP_TRY(hipGetLastError());
     RCX_HIP_TRY(hipStreamSynchronize(st));
@@ -1155,7 +1242,7 @@ int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_ho
     if (rc != RCX_OK) return rc;
     RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, targ_norm_host, sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_pops_from_pred, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, s->pred,
-                       s->norms + 12, s->ntot, pops_out);
+                       s->norms + 12, s->lte, s->ntot, pops_out);
     RCX_HIP_TRY(hipGetLastError());
     RCX_HIP_TRY(hipStreamSynchronize(st));
     return RCX_OK;

@@ -278,9 +278,9 @@ def _load_nlte():
     L.rcx_nlte_dims.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.rcx_nlte_destroy.argtypes = [vp]
     L.rcx_nlte_features.argtypes = [vp, vp, vp, vp, vp]
-    L.rcx_nlte_log_fractions.argtypes = [vp, vp, vp, vp, vp]
+    L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
-    for n in ("rcx_nlte_features", "rcx_nlte_log_fractions", "rcx_nlte_warm_start"):
+    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start"):
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
@@ -356,10 +356,11 @@ class Nlte:
     """Owns an ``rcx_nlte`` solver for one non-LTE problem (a
     ``workloads.NlteInput``); arrays live on ``cuda:0``."""
 
-    def __init__(self, inp, n_cascades: int = 0):
+    def __init__(self, inp, n_cascades: int = 0, storage: int = RCX_STORE_F32):
         import torch
         p = rcx_params_default()
         p.n_cascades = n_cascades
+        p.storage = storage
         self.inp = inp
         self.handle = rcx_nlte_create(rcx_grid(inp.nx, inp.nz, inp.voxel), p, atom_from_dict(inp.atom),
                                       inp.lambda_nm, inp.trans, inp.dnu)
@@ -409,15 +410,15 @@ class Nlte:
                "rcx_nlte_features")
         return out
 
-    def log_fractions(self, pops, norm=None):
+    def log_departures(self, pops, norm=None):
         import numpy as np
         import torch
         out = torch.empty((self.inp.nx * self.inp.nz, self.n_levels), dtype=torch.float32, device="cuda:0")
         nrm = None if norm is None else np.ascontiguousarray(norm, np.float32)
-        _check(_load_nlte().rcx_nlte_log_fractions(self.handle, _dev_ptr(pops, "torch.float64", "pops"),
+        _check(_load_nlte().rcx_nlte_log_departures(self.handle, _dev_ptr(pops, "torch.float64", "pops"),
                                                    None if nrm is None else nrm.ctypes.data,
                                                    _dev_ptr(out, "torch.float32", "out"), _stream_ptr(None)),
-               "rcx_nlte_log_fractions")
+               "rcx_nlte_log_departures")
         return out
 
     def warm_start(self, net, feat_norm, targ_norm):
@@ -477,7 +478,7 @@ class Mlp:
     """Owns an ``rcx_mlp``."""
 
     def __init__(self, n_in=6, width=128, depth=4, n_out=4, max_batch=65536):
-        self.n_in, self.n_out = n_in, n_out
+        self.n_in, self.n_out, self.width, self.depth = n_in, n_out, width, depth
         self.handle = rcx_mlp_create(n_in, width, depth, n_out, max_batch)
         n = C.c_int64()
         _check(_load_mlp().rcx_mlp_n_params(self.handle, C.byref(n)), "rcx_mlp_n_params")

@@ -19,13 +19,13 @@ from . import rcx, workloads as W
 
 
 def converged_run(n: int, seed: int, n_line: int, n_cont: int, tol: float, max_iter: int):
-    """Features at LTE and converged log fractions of one seeded atmosphere."""
+    """Features at LTE and converged log departure coefficients of one seeded atmosphere."""
     inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
     s = rcx.Nlte(inp)
     pops = s.lte()
     feat = s.features(pops).cpu().numpy()
     rc, it, ch = s.iterate(pops, max_iter, tol)
-    targ = s.log_fractions(pops).cpu().numpy()
+    targ = s.log_departures(pops).cpu().numpy()
     s.close()
     return feat, targ, it, ch
 
@@ -37,6 +37,7 @@ def dataset(n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter
         X.append(f)
         Y.append(t)
         info.append({"seed": int(seed), "iterations": it, "last_change": ch})
+        print(f"converged run {n}^2 seed {seed}: {it} iterations (change {ch:.2e})", flush=True)
     return np.concatenate(X), np.concatenate(Y), info
 
 
@@ -71,18 +72,40 @@ def train(X, Y, epochs: int = 20, batch: int = 8192, lr: float = 2e-3, seed: int
     return net, fn, tn, losses
 
 
+def save(net, fn, tn, path: str, info: dict | None = None):
+    """Trained parameters and the feature/target standardisation, as a
+    plain npz (no pickled objects)."""
+    import os
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    np.savez(path, params=net.get_params(), feat_norm=fn, targ_norm=tn,
+             shape=np.array([net.n_in, net.width, net.depth, net.n_out], np.int64),
+             info=np.array(json.dumps(info or {})))
+
+
+def load(path: str, max_batch: int = 65536):
+    """(net, feat_norm, targ_norm) from a file written by save()."""
+    d = np.load(path)  # allow_pickle stays False
+    n_in, width, depth, n_out = (int(v) for v in d["shape"])
+    net = rcx.Mlp(n_in, width, depth, n_out, max_batch=max_batch)
+    net.set_params(d["params"])
+    return net, d["feat_norm"].astype(np.float32), d["targ_norm"].astype(np.float32)
+
+
 def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 1000,
-             ref_tol: float = 1e-6):
+             ref_tol: float = 1e-5, ref_max_iter: int = 2000, storage: int = rcx.RCX_STORE_F32):
     """For each seed: iterations and wall time to max change < tol from the
-    LTE start and from the warm start, and the largest relative difference of
-    both results from a reference iterated to ref_tol."""
+    LTE start and from the warm start, the largest relative difference of
+    the starting guesses and of both converged results from a reference
+    iterated further (to ref_tol, or ref_max_iter iterations: the FP32 rates
+    put a floor of a few 1e-4 under the attainable change), and the
+    difference between the two converged results."""
     import torch
     out = []
     for seed in seeds:
         inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
-        s = rcx.Nlte(inp)
+        s = rcx.Nlte(inp, storage=storage)
         ref = s.lte()
-        rc_r, it_r, ch_r = s.iterate(ref, 5 * max_iter, ref_tol)
+        rc_r, it_r, ch_r = s.iterate(ref, ref_max_iter, ref_tol)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p_lte = s.lte()
@@ -95,12 +118,16 @@ def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 
         rc1, it1, ch1 = s.iterate(p_ws, max_iter, tol)
         torch.cuda.synchronize()
         t_ws = time.perf_counter() - t0
-        err = lambda p: float(((p - ref).abs() / ref.abs()).max())
+        err = lambda p, r=ref: float(((p - r).abs() / r.abs()).max())
+        med = lambda p, r=ref: float(((p - r).abs() / r.abs()).median())
+        p_lte0 = s.lte()
         out.append({
             "seed": int(seed), "n": n, "reference_iterations": it_r, "reference_change": ch_r,
             "lte_iterations": it0, "lte_seconds": t_lte, "lte_error_vs_reference": err(p_lte),
             "warm_iterations": it1, "warm_seconds": t_ws, "warm_error_vs_reference": err(p_ws),
-            "prediction_error_vs_reference": err(p_pred),
+            "lte_start_error_vs_reference": err(p_lte0), "lte_start_median_error": med(p_lte0),
+            "prediction_error_vs_reference": err(p_pred), "prediction_median_error": med(p_pred),
+            "warm_vs_lte_converged": err(p_ws, p_lte),
             "converged": bool(rc0 == 0 and rc1 == 0),
         })
         s.close()
@@ -117,6 +144,7 @@ def main():
     ap.add_argument("--n-cont", type=int, default=32)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--save", default=None, help="write the trained network (npz)")
     a = ap.parse_args()
     t0 = time.perf_counter()
     X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont)
@@ -124,6 +152,10 @@ def main():
     t0 = time.perf_counter()
     net, fn, tn, losses = train(X, Y, epochs=a.epochs)
     t_train = time.perf_counter() - t0
+    print(f"trained on {len(X)} samples in {t_train:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}", flush=True)
+    if a.save:
+        save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "epochs": a.epochs,
+                                   "n_line": a.n_line, "n_cont": a.n_cont, "loss_last": losses[-1]})
     ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont)
     rep = {"train": {"n": a.train_n, "runs": a.train_runs, "samples": len(X), "data_seconds": t_data,
                      "train_seconds": t_train, "epochs": a.epochs, "loss_first": losses[0], "loss_last": losses[-1],
