@@ -49,6 +49,10 @@ def parse():
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
     ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--nlte-only", action="store_true",
+                    help="only the converged non-LTE solves (for profiling; prints their object)")
+    ap.add_argument("--nlte-variants", default="plain_fp32,plain_fp16,learned_fp32,learned_fp16",
+                    help="comma-separated subset of the non-LTE runs")
     ap.add_argument("--nlte-n", type=int, default=1024)
     ap.add_argument("--nlte-max-iter", type=int, default=300)
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "warmstart_mlp.npz"),
@@ -156,6 +160,8 @@ def nlte_solves(args):
     runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False)]
     if net is not None:
         runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True)]
+    wanted = set(args.nlte_variants.split(","))
+    runs = [r for r in runs if r[0] in wanted]
     final = {}
     for name, storage, learned in runs:
         s = rcx.Nlte(inp, storage=storage)
@@ -179,9 +185,9 @@ def nlte_solves(args):
         out[name] = {"seconds": dt, "iterations": it, "last_change": ch, "converged": rc == 0,
                      "s_per_iteration": dt / max(it, 1)}
         print(f"[bench] non-LTE {name}: {it} iterations, {dt:.2f} s", file=sys.stderr, flush=True)
-    ref = final["plain_fp32"]
+    ref = final.get("plain_fp32")
     for name in final:
-        if name != "plain_fp32":
+        if ref is not None and name != "plain_fp32":
             out[name]["max_rel_diff_vs_plain_fp32"] = float(((final[name] - ref).abs() / ref.abs()).max())
     if net is not None:
         net.close()
@@ -205,6 +211,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "repeats": 3}), flush=True)
+        return
+
+    if args.nlte_only:
+        print(json.dumps(nlte_solves(args)), flush=True)
         return
 
     inp = workloads.line_medium(args.n, args.waves, seed=2)
