@@ -210,7 +210,7 @@ __global__ void k_static(AtomDev A, int64_t ncell, const double* __restrict__ T,
 
 // -------------------------------------------------------------- synthesis
 // Lines: rec[line][c] = {kappa (optical depth per cell at H = 1, log2 units),
-// S_line, a, 1/v_th}, with kappa = sigma/(sqrt(pi) dnu_D) (n_i - g_i/g_j n_j)
+// S_line, a in Voigt-table units (a / da), 1/v_th}, with kappa = sigma/(sqrt(pi) dnu_D) (n_i - g_i/g_j n_j)
 // voxel and S_line = U0 (g_i/g_j) n_j / (n_i - g_i/g_j n_j) (complete
 // redistribution: eta and chi share the profile); epi[line][c] = {n_i, n_j,
 // sigma/(sqrt(pi) dnu_D), 0}. Continua: epi[cont][c] = {n_i, n_c,
@@ -228,6 +228,7 @@ struct SynthArgs {
     float4* line_rec;    // [n_lines][ncell]
     float4* epi_rec;     // [n_trans][ncell]
     double voxel;
+    float inv_da;        // 1 / (damping step of the Voigt table)
 };
 
 __global__ void k_synth(AtomDev A, int64_t ncell, SynthArgs s)
@@ -247,8 +248,8 @@ __global__ void k_synth(AtomDev A, int64_t ncell, SynthArgs s)
                 S = tr.U0 * tr.gr * nj * sp * s.voxel / kChiFloor;
                 kap = kChiFloor;
             }
-            s.line_rec[(int64_t)tr.line * ncell + c] =
-                make_float4((float)(kap * kLog2eD), (float)S, s.adamp[(int64_t)tr.line * ncell + c], s.inv_vth[c]);
+            const float fa = fminf(s.adamp[(int64_t)tr.line * ncell + c] * s.inv_da, (float)(kNa - 1) - 1e-3f);
+            s.line_rec[(int64_t)tr.line * ncell + c] = make_float4((float)(kap * kLog2eD), (float)S, fa, s.inv_vth[c]);
             s.epi_rec[(int64_t)k * ncell + c] = make_float4((float)ni, (float)nj, (float)sp, 0.0f);
         } else {
             s.epi_rec[(int64_t)k * ncell + c] =
@@ -341,34 +342,61 @@ struct LineOp {
     const float2* vel;  // [ncell]
     VoigtTab vt;
     const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
+    uint32_t ncell;
+    float da_sqrtpi;    // damping step of the table / sqrt(pi)
     float u, wx, wz;
+    __amdgpu_buffer_rsrc_t r_rec, r_vel, r_tab;
     struct Raw {
         float4 r;
         float2 v;
-        bool ok;
     };
-    __device__ __forceinline__ void init(int l) { u = u_b[l]; }
+    __device__ __forceinline__ void init(int l)
+    {
+        u = u_b[l];
+        r_rec = __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(ncell * 16u), 0x00020000);
+        r_vel = __builtin_amdgcn_make_buffer_rsrc((void*)vel, 0, (int)(ncell * 8u), 0x00020000);
+        r_tab = __builtin_amdgcn_make_buffer_rsrc((void*)vt.tab, 0, (int)(kNa * kNx * 8), 0x00020000);
+    }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
         wx = (float)dwx;
         wz = (float)dwz;
     }
+    // An out-of-range offset reads zeros: kappa = 0, so a step past the
+    // row's segment count has no opacity (and S = 0).
     __device__ __forceinline__ void fetch(uint32_t cell, bool ok, Raw& raw) const
     {
-        const uint32_t c = ok ? cell : 0u;
-        raw.r = rec[c];
-        raw.v = vel[c];
-        raw.ok = ok;
+        // cell < 2^24, so valid offsets stay below 2^28
+        raw.r = __builtin_bit_cast(float4,
+                                   __builtin_amdgcn_raw_buffer_load_b128(r_rec, ok ? cell * 16u : 0x80000000u, 0, 0));
+        raw.v = __builtin_bit_cast(float2,
+                                   __builtin_amdgcn_raw_buffer_load_b64(r_vel, ok ? cell * 8u : 0x80000000u, 0, 0));
     }
+    // H(a, |x|), x = (u + w . v) / v_th, from the table (bilinear; the record
+    // holds a in table units, always inside the table) or, beyond kXTab, the
+    // asymptotic series.
     __device__ __forceinline__ float profile(const float4& r, const float2& v) const
     {
-        const float x = (u + wx * v.x + wz * v.y) * r.w;
-        return voigt_lookup(vt, r.z, fabsf(x));
+        const float ax = fabsf((u + wx * v.x + wz * v.y) * r.w);
+        const int ia = (int)r.z;  // r.z >= 0
+        const float wa = __builtin_amdgcn_fractf(r.z);
+        const float fx = fminf(ax * vt.inv_dx, (float)(kNx - 1) - 1e-3f);
+        const int ix = (int)fx;
+        const float wxi = __builtin_amdgcn_fractf(fx);
+        const uint32_t off = (uint32_t)(ia * kNx + ix) * 8u;
+        const float2 p0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r_tab, off, 0, 0));
+        const float2 p1 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r_tab, off + kNx * 8u, 0, 0));
+        const float h0 = fmaf(wxi, p0.y - p0.x, p0.x);
+        const float h1 = fmaf(wxi, p1.y - p1.x, p1.x);
+        const float ht = fmaf(wa, h1 - h0, h0);
+        const float q = __builtin_amdgcn_rcpf(ax * ax);
+        const float ser = fmaf(q, fmaf(q, fmaf(q, fmaf(q, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
+        const float hs = (r.z * da_sqrtpi) * q * ser;  // a / sqrt(pi) / x^2 * series
+        return ax < (float)kXTab ? ht : hs;
     }
     __device__ __forceinline__ float2 resolve(const Raw& raw) const
     {
-        const float H = profile(raw.r, raw.v);
-        return make_float2(raw.ok ? raw.r.x * H : 0.0f, raw.r.y);
+        return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);
     }
 };
 
@@ -964,7 +992,8 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
     const int32_t nx = P->grid.nx, nz = P->grid.nz;
     const int64_t nc = s->ncell;
     const AtomDev& A = s->atom;
-    SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel};
+    SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel,
+                 s->v_inv_da};
     hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
     RCX_HIP_TRY(hipGetLastError());
     const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
@@ -1007,6 +1036,8 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             lop.vel = s->vel;
             lop.vt = vt;
             lop.u_b = bc + 1 * kLB;
+            lop.ncell = (uint32_t)nc;
+            lop.da_sqrtpi = (float)(1.0 / (s->v_inv_da * std::sqrt(kPi)));
         }
         RatesEpi re{};
         re.part = s->part + b * nc;
