@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
     ap.add_argument("--nlte-only", action="store_true",
                     help="only the converged non-LTE solves (for profiling; prints their object)")
-    ap.add_argument("--nlte-variants", default="plain_fp32,plain_fp16,learned_fp32,learned_fp16",
+    ap.add_argument("--nlte-variants", default="plain_fp32,learned_fp16",
                     help="comma-separated subset of the non-LTE runs")
     ap.add_argument("--nlte-n", type=int, default=1024)
     ap.add_argument("--nlte-max-iter", type=int, default=300)
@@ -172,10 +172,12 @@ def nlte_solves(args):
         t0 = time.perf_counter()
         p = s.warm_start(net, fn, tn) if learned else s.lte()
         it, rc, ch = 0, 1, float("inf")
+        hist = []  # (iterations, change) after each chunk
         while rc != 0 and it < args.nlte_max_iter:
             # chunks of the same iteration, so that progress is visible
             rc, k, ch = s.iterate(p, min(5, args.nlte_max_iter - it), 1e-3)
             it += k
+            hist.append((it, ch))
             print(f"[bench] non-LTE {name}: {it} iterations, change {ch:.3e}, "
                   f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -184,11 +186,22 @@ def nlte_solves(args):
         s.close()
         out[name] = {"seconds": dt, "iterations": it, "last_change": ch, "converged": rc == 0,
                      "s_per_iteration": dt / max(it, 1)}
+        # distance to the fixed point estimated from the contraction rate of
+        # the last chunks: rho per iteration, error ~ change * rho / (1 - rho)
+        if len(hist) >= 3 and hist[-3][1] > 0 and ch > 0:
+            rho = (ch / hist[-3][1]) ** (1.0 / max(it - hist[-3][0], 1))
+            if rho < 1.0:
+                out[name]["contraction_per_iteration"] = rho
+                out[name]["error_estimate"] = ch * rho / (1.0 - rho)
         print(f"[bench] non-LTE {name}: {it} iterations, {dt:.2f} s", file=sys.stderr, flush=True)
     ref = final.get("plain_fp32")
     for name in final:
         if ref is not None and name != "plain_fp32":
             out[name]["max_rel_diff_vs_plain_fp32"] = float(((final[name] - ref).abs() / ref.abs()).max())
+    if "plain_fp32" in out:
+        for name in final:
+            if name != "plain_fp32":
+                out[name]["speedup_vs_plain_fp32"] = out["plain_fp32"]["seconds"] / out[name]["seconds"]
     if net is not None:
         net.close()
     return out

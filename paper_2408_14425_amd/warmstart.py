@@ -49,7 +49,7 @@ def norms(a: np.ndarray) -> np.ndarray:
 
 
 def train(X, Y, epochs: int = 20, batch: int = 8192, lr: float = 2e-3, seed: int = 0, width: int = 128,
-          depth: int = 4):
+          depth: int = 4, verbose: bool = False):
     import torch
     fn, tn = norms(X), norms(Y)
     Xs = ((X - fn[0]) / fn[1]).astype(np.float32)
@@ -69,6 +69,8 @@ def train(X, Y, epochs: int = 20, batch: int = 8192, lr: float = 2e-3, seed: int
             idx = perm[b0:b0 + batch]
             tot += net.train_step(xt[idx].contiguous(), yt[idx].contiguous(), lr_ep)
         losses.append(tot / max(1, n // batch))
+        if verbose and (ep % 5 == 0 or ep == epochs - 1):
+            print(f"epoch {ep}: loss {losses[-1]:.4g}", flush=True)
     return net, fn, tn, losses
 
 
@@ -105,7 +107,11 @@ def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 
         inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
         s = rcx.Nlte(inp, storage=storage)
         ref = s.lte()
-        rc_r, it_r, ch_r = s.iterate(ref, ref_max_iter, ref_tol)
+        it_r, rc_r, ch_r = 0, 1, float("inf")
+        while rc_r != 0 and it_r < ref_max_iter:
+            rc_r, k, ch_r = s.iterate(ref, min(50, ref_max_iter - it_r), ref_tol)
+            it_r += k
+            print(f"reference {n}^2 seed {seed}: {it_r} iterations, change {ch_r:.2e}", flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         p_lte = s.lte()
@@ -145,18 +151,22 @@ def main():
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained network (npz)")
+    ap.add_argument("--ref-max-iter", type=int, default=300)
     a = ap.parse_args()
     t0 = time.perf_counter()
     X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont)
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    net, fn, tn, losses = train(X, Y, epochs=a.epochs)
+    print(f"training on {len(X)} samples", flush=True)
+    net, fn, tn, losses = train(X, Y, epochs=a.epochs, verbose=True)
     t_train = time.perf_counter() - t0
     print(f"trained on {len(X)} samples in {t_train:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}", flush=True)
     if a.save:
         save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "epochs": a.epochs,
                                    "n_line": a.n_line, "n_cont": a.n_cont, "loss_last": losses[-1]})
-    ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont)
+    ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont, ref_max_iter=a.ref_max_iter)
+    for e in ev:
+        print(json.dumps(e), flush=True)
     rep = {"train": {"n": a.train_n, "runs": a.train_runs, "samples": len(X), "data_seconds": t_data,
                      "train_seconds": t_train, "epochs": a.epochs, "loss_first": losses[0], "loss_last": losses[-1],
                      "runs_info": info},
