@@ -285,6 +285,14 @@ int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, doub
  * checking the table against a reference. */
 int32_t rcx_nlte_voigt_eval(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out,
                             hipStream_t stream);
+/* The same for the profile the line march uses: a compact table (cubic
+ * Hermite in x on [0, 8] at spacing 1/32, linear in a on at most 9 nodes
+ * over the atmosphere's damping range, filled in FP64 from the Fourier
+ * integrals of H and of the Faraday-Voigt function) that every march
+ * workgroup copies into LDS, and the same asymptotic series beyond x = 8.
+ * a is clamped to the atmosphere's damping range. */
+int32_t rcx_nlte_voigt_eval_march(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out,
+                                  hipStream_t stream);
 
 /* Number of transitions and of levels of the solver's atom. */
 int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* n_levels_host, int32_t* n_trans_host);

@@ -93,20 +93,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ t
                 up.init(c.l);
                 if (T.level == 0) {
                     march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
                 } else {
                     march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
                     epi.init(c.l);
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
                 }
             } else {
                 march::UpF32 up{(const float*)T.up};
                 if (T.level == 0) {
                     march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
                 } else {
                     march::StoreEpi epi{(float*)T.out};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], c, ray, u, v, k, active);
+                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
                 }
             }
         }

@@ -99,14 +99,23 @@ __device__ __forceinline__ RowCtx row_ctx()
     return c;
 }
 
+// Segments per row and chunk: 16 columns, at most two segments each.
+constexpr int kSegs = 32;
+
 // March, merge and finish one ray per row. ray = output index of the ray
 // in its cascade, (u, v, k) its probe and direction; active false for rows
 // past the end (they still take part in the wavefront-wide ballots).
+// An Op whose step data depends on the cell only (the same for all 16
+// wavelength lanes of a row) sets kStaged: the lane that finds a segment
+// loads that data once (Op::stage) while the row's segment list is built,
+// and the step loop reads it back from LDS (stg, this wavefront's
+// [4 rows][kSegs] entries) instead of issuing a dependent global load per
+// step.
 template <class Op, class Epi, class Up>
 __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
                                           const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[16],
-                                          const RowCtx& cx_, int64_t ray, int32_t u, int32_t v, int32_t k,
-                                          bool active)
+                                          typename Op::Stage (*stg)[kSegs], const RowCtx& cx_, int64_t ray,
+                                          int32_t u, int32_t v, int32_t k, bool active)
 {
     const int lane = cx_.lane, row = cx_.row, l = cx_.l;
     const uint64_t row_bits = cx_.row_bits, lt_bits = cx_.lt_bits;
@@ -170,6 +179,11 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         const uint32_t cell2 = (uint32_t)(im * strm + in1 * strn);
         const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
         const float ds2 = (float)fmax(tb_ - tmid, 0.0);
+        typename Op::Stage st1{}, st2{};
+        if constexpr (Op::kStaged) {
+            if (valid) st1 = op.stage(cell1);
+            if (two) st2 = op.stage(cell2);
+        }
 
         const uint64_t b1 = __ballot(valid);
         if (b1 == 0) break;
@@ -185,6 +199,10 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
         if (valid) srow[pos] = make_uint2(cell1, __float_as_uint(ds1));
         if (two) srow[pos + 1] = make_uint2(cell2, __float_as_uint(ds2));
+        if constexpr (Op::kStaged) {
+            if (valid) stg[row][pos] = st1;
+            if (two) stg[row][pos + 1] = st2;
+        }
         wave_sync();
 
         // ---- step through the row's segments, 4 at a time. Positions past
@@ -197,7 +215,12 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
                                   __uint_as_float(e23.w)};
             typename Op::Raw raw[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (Op::kStaged)
+                    op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
+                else
+                    op.fetch(cells[q], (s + q) < n_row, raw[q]);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float2 f = op.resolve(raw[q]);  // {optical depth per cell, log2 units; S}
@@ -239,8 +262,15 @@ template <class Op, class Epi, class Up>
 __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
 {
-    // per wave, per row: (cell index, ds) entries
+    // per wave, per row: (cell index, ds) entries, and staged step data
     __shared__ uint4 seg[kBlock / 64][4][16];
+    __shared__ typename Op::Stage stg[Op::kStaged ? kBlock / 64 : 1][4][kSegs];
+    // block-wide tables of the Op (e.g. a line profile), copied once
+    __shared__ float2 op_smem[Op::kSmemBytes > 0 ? Op::kSmemBytes / 8 : 2];
+    if constexpr (Op::kSmemBytes > 0) {
+        op.init_shared(op_smem);
+        __syncthreads();
+    }
     const RowCtx c = row_ctx();
     op.init(c.l);
     epi.init(c.l);
@@ -248,6 +278,14 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
     {
         uint4* sw = &seg[c.w][0][0];
         sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (Op::kStaged) {
+            // positions past a row's segment count are read (with zero
+            // opacity): they must hold zeros or a real record, never garbage
+            static_assert(sizeof(typename Op::Stage) % 16 == 0, "stage entries are written as uint4");
+            uint4* gw = reinterpret_cast<uint4*>(&stg[c.w][0][0]);
+            constexpr int n16 = 4 * kSegs * (int)sizeof(typename Op::Stage) / 16;
+            for (int i = c.lane; i < n16; i += 64) gw[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
         wave_sync();
     }
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
@@ -258,7 +296,8 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
         const int64_t rr = active ? ray : total - 1;
         const int32_t k = (int32_t)(rr % L.nd);
         const int32_t p = (int32_t)(rr / L.nd);
-        march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], c, ray, p % L.px, p / L.px, k, active);
+        march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[Op::kStaged ? c.w : 0], c, ray, p % L.px, p / L.px, k,
+                  active);
     }
 }
 
@@ -315,6 +354,10 @@ struct FieldOp {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t lane_off;
     using Raw = float2;
+    static constexpr bool kStaged = false;  // per-lane data: nothing to stage
+    struct Stage {};
+    static constexpr int kSmemBytes = 0;
+    __device__ __forceinline__ void init_shared(float2*) {}
     __device__ __forceinline__ void init(int l)
     {
         rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)Fb, 0, (int)fb_bytes, 0x00020000);

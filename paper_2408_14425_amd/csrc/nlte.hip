@@ -142,6 +142,92 @@ __global__ void k_voigt_eval(VoigtTab V, int32_t n, const float* a, const float*
     if (i < n) out[i] = voigt_lookup(V, a[i], fabsf(x[i]));
 }
 
+// Compact profile table for the march, copied into LDS by every workgroup:
+// {H(a_k, x_i), dH/dx(a_k, x_i) * dxc} at a_k = k da (k < n_a <= kNacMax)
+// and x_i = i dxc, dxc = 1/32 on [0, kXTab]; cubic Hermite in x (error
+// below 3e-8 of H(0, 0)), linear in a (error below da^2 / 4 of H(0, 0)).
+// dH/dx = 2 (a L - x H) with L(a, x) = Im w(x + i a) the Faraday-Voigt
+// function, from the same Fourier integral:
+// L = pi^{-1/2} int_0^inf exp(-a t - t^2/4) sin(x t) dt.
+constexpr int kNxc = 257;
+constexpr int kNacMax = 9;
+constexpr float kInvDxc = 32.0f;
+constexpr int kCompactBytes = kNacMax * kNxc * 8;
+
+__device__ void voigt_fourier2(double a, double x, double& H, double& L)
+{
+    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double h = 0.125;
+    double ac = 0.0, as = 0.0;
+    for (int p = 0; p < 104; ++p) {
+        const double c = (p + 0.5) * h;
+        for (int q = 0; q < 4; ++q) {
+            for (int sgn = -1; sgn <= 1; sgn += 2) {
+                const double t = c + sgn * 0.5 * h * gx[q];
+                const double e = gw[q] * exp(-a * t - 0.25 * t * t);
+                double sn, cs;
+                sincos(x * t, &sn, &cs);
+                ac += e * cs;
+                as += e * sn;
+            }
+        }
+    }
+    H = ac * 0.5 * h / sqrt(kPi);
+    L = as * 0.5 * h / sqrt(kPi);
+}
+
+__global__ void k_voigt_fill_compact(float2* tab, int32_t n_a, double da)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_a * kNxc) return;
+    const int ia = idx / kNxc, ix = idx % kNxc;
+    const double a = ia * da, x = ix / (double)kInvDxc;
+    double H, L;
+    voigt_fourier2(a, x, H, L);
+    tab[idx] = make_float2((float)H, (float)(2.0 * (a * L - x * H) / (double)kInvDxc));
+}
+
+// H(a, ax) from the LDS table; fa = a / da (inside [0, n_a - 1)),
+// a_sqrtpi = a / sqrt(pi) for the asymptotic series beyond kXTab.
+__device__ __forceinline__ float voigt_compact(const float2* __restrict__ tab, float fa, float a_sqrtpi, float ax)
+{
+    const int ia = (int)fa;
+    const float wa = __builtin_amdgcn_fractf(fa);
+    const float fx = fminf(ax * kInvDxc, (float)(kNxc - 1) - 1e-3f);
+    const int ix = (int)fx;
+    const float t = __builtin_amdgcn_fractf(fx);
+    const float2* p = tab + ia * kNxc + ix;
+    const float2 q00 = p[0], q01 = p[1], q10 = p[kNxc], q11 = p[kNxc + 1];
+    const float t2 = t * t;
+    const float h01 = t2 * fmaf(-2.0f, t, 3.0f);       // t^2 (3 - 2t)
+    const float h00 = 1.0f - h01;
+    const float tm1 = t - 1.0f;
+    const float h10 = t * tm1 * tm1;                   // t (t - 1)^2
+    const float h11 = t2 * tm1;                        // t^2 (t - 1)
+    const float H0 = fmaf(h00, q00.x, fmaf(h10, q00.y, fmaf(h01, q01.x, h11 * q01.y)));
+    const float H1 = fmaf(h00, q10.x, fmaf(h10, q10.y, fmaf(h01, q11.x, h11 * q11.y)));
+    const float ht = fmaf(wa, H1 - H0, H0);
+    const float q = __builtin_amdgcn_rcpf(ax * ax);
+    const float ser = fmaf(q, fmaf(q, fmaf(q, fmaf(q, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
+    return ax < (float)kXTab ? ht : a_sqrtpi * q * ser;
+}
+
+// The march's profile at arbitrary (a, x), for checking the compact table.
+__global__ __launch_bounds__(256) void k_voigt_eval_compact(const float2* __restrict__ tabc, int32_t n_a, float inv_da,
+                                                            float da_sqrtpi, int32_t n, const float* a, const float* x,
+                                                            float* out)
+{
+    __shared__ float2 tab[kNacMax * kNxc];
+    for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) tab[i] = tabc[i];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const float fa = fminf(a[i] * inv_da, (float)(n_a - 1) - 1e-3f);
+        out[i] = voigt_compact(tab, fa, fa * da_sqrtpi, fabsf(x[i]));
+    }
+}
+
 // ------------------------------------------------------------ static data
 // Per cell, from T, ne, ntot (FP64): Saha-Boltzmann populations, collisional
 // rates, 1/v_th, line damping a and sigma/(sqrt(pi) dnu_D), and for each
@@ -228,7 +314,8 @@ struct SynthArgs {
     float4* line_rec;    // [n_lines][ncell]
     float4* epi_rec;     // [n_trans][ncell]
     double voxel;
-    float inv_da;        // 1 / (damping step of the Voigt table)
+    float inv_da;        // 1 / (damping step of the march's profile table)
+    int32_t n_a;         // damping nodes of that table
 };
 
 __global__ void k_synth(AtomDev A, int64_t ncell, SynthArgs s)
@@ -248,7 +335,7 @@ __global__ void k_synth(AtomDev A, int64_t ncell, SynthArgs s)
                 S = tr.U0 * tr.gr * nj * sp * s.voxel / kChiFloor;
                 kap = kChiFloor;
             }
-            const float fa = fminf(s.adamp[(int64_t)tr.line * ncell + c] * s.inv_da, (float)(kNa - 1) - 1e-3f);
+            const float fa = fminf(s.adamp[(int64_t)tr.line * ncell + c] * s.inv_da, (float)(s.n_a - 1) - 1e-3f);
             s.line_rec[(int64_t)tr.line * ncell + c] = make_float4((float)(kap * kLog2eD), (float)S, fa, s.inv_vth[c]);
             s.epi_rec[(int64_t)k * ncell + c] = make_float4((float)ni, (float)nj, (float)sp, 0.0f);
         } else {
@@ -340,59 +427,57 @@ __global__ void k_zero_u32n(unsigned int* p, int32_t n)
 struct LineOp {
     const float4* rec;  // [ncell]
     const float2* vel;  // [ncell]
-    VoigtTab vt;
+    const float2* tabc; // compact profile table [n_a][kNxc] (global; copied to LDS)
+    int32_t n_a;
     const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
     uint32_t ncell;
     float da_sqrtpi;    // damping step of the table / sqrt(pi)
     float u, wx, wz;
-    __amdgpu_buffer_rsrc_t r_rec, r_vel, r_tab;
+    const float2* tab;  // the LDS copy
     struct Raw {
         float4 r;
         float2 v;
     };
-    __device__ __forceinline__ void init(int l)
+    // the cell record and velocity are the same for all wavelength lanes
+    static constexpr bool kStaged = true;
+    struct Stage {
+        float4 r;
+        float2 v;
+        float2 pad;
+    };
+    static constexpr int kSmemBytes = kCompactBytes;
+    __device__ __forceinline__ void init_shared(float2* smem)
     {
-        u = u_b[l];
-        r_rec = __builtin_amdgcn_make_buffer_rsrc((void*)rec, 0, (int)(ncell * 16u), 0x00020000);
-        r_vel = __builtin_amdgcn_make_buffer_rsrc((void*)vel, 0, (int)(ncell * 8u), 0x00020000);
-        r_tab = __builtin_amdgcn_make_buffer_rsrc((void*)vt.tab, 0, (int)(kNa * kNx * 8), 0x00020000);
+        for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) smem[i] = tabc[i];
+        tab = smem;
     }
+    __device__ __forceinline__ Stage stage(uint32_t cell) const
+    {
+        Stage st;
+        st.r = rec[cell];
+        st.v = vel[cell];
+        st.pad = make_float2(0.0f, 0.0f);
+        return st;
+    }
+    // positions past the row's segment count: no opacity
+    __device__ __forceinline__ void from_stage(const Stage& st, bool ok, Raw& raw) const
+    {
+        raw.r = st.r;
+        raw.r.x = ok ? st.r.x : 0.0f;
+        raw.v = st.v;
+    }
+    __device__ __forceinline__ void init(int l) { u = u_b[l]; }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
         wx = (float)dwx;
         wz = (float)dwz;
     }
-    // An out-of-range offset reads zeros: kappa = 0, so a step past the
-    // row's segment count has no opacity (and S = 0).
-    __device__ __forceinline__ void fetch(uint32_t cell, bool ok, Raw& raw) const
-    {
-        // cell < 2^24, so valid offsets stay below 2^28
-        raw.r = __builtin_bit_cast(float4,
-                                   __builtin_amdgcn_raw_buffer_load_b128(r_rec, ok ? cell * 16u : 0x80000000u, 0, 0));
-        raw.v = __builtin_bit_cast(float2,
-                                   __builtin_amdgcn_raw_buffer_load_b64(r_vel, ok ? cell * 8u : 0x80000000u, 0, 0));
-    }
-    // H(a, |x|), x = (u + w . v) / v_th, from the table (bilinear; the record
-    // holds a in table units, always inside the table) or, beyond kXTab, the
-    // asymptotic series.
+    // H(a, |x|), x = (u + w . v) / v_th; the record holds a in table units
+    // (always inside the table)
     __device__ __forceinline__ float profile(const float4& r, const float2& v) const
     {
         const float ax = fabsf((u + wx * v.x + wz * v.y) * r.w);
-        const int ia = (int)r.z;  // r.z >= 0
-        const float wa = __builtin_amdgcn_fractf(r.z);
-        const float fx = fminf(ax * vt.inv_dx, (float)(kNx - 1) - 1e-3f);
-        const int ix = (int)fx;
-        const float wxi = __builtin_amdgcn_fractf(fx);
-        const uint32_t off = (uint32_t)(ia * kNx + ix) * 8u;
-        const float2 p0 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r_tab, off, 0, 0));
-        const float2 p1 = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r_tab, off + kNx * 8u, 0, 0));
-        const float h0 = fmaf(wxi, p0.y - p0.x, p0.x);
-        const float h1 = fmaf(wxi, p1.y - p1.x, p1.x);
-        const float ht = fmaf(wa, h1 - h0, h0);
-        const float q = __builtin_amdgcn_rcpf(ax * ax);
-        const float ser = fmaf(q, fmaf(q, fmaf(q, fmaf(q, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
-        const float hs = (r.z * da_sqrtpi) * q * ser;  // a / sqrt(pi) / x^2 * series
-        return ax < (float)kXTab ? ht : hs;
+        return voigt_compact(tab, r.z, r.z * da_sqrtpi, ax);
     }
     __device__ __forceinline__ float2 resolve(const Raw& raw) const
     {
@@ -683,6 +768,9 @@ struct rcx_nlte {
     unsigned int* d_amax = nullptr;
     float2* vtab = nullptr;
     float v_inv_da = 0.0f;
+    float2* vtabc = nullptr;  // compact table of the march
+    int32_t n_ac = 2;
+    double da_c = 1.0;
     bool atm_set = false;
     float* u_all = nullptr;    // [n_wave]
     float* dnu_all = nullptr;  // [n_wave]
@@ -910,6 +998,7 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
     chk(dmalloc(s, &s->d_amax, sizeof(unsigned int)));
     chk(dmalloc(s, &s->vtab, sizeof(float2) * kNa * kNx));
+    chk(dmalloc(s, &s->vtabc, sizeof(float2) * kNacMax * kNxc));
     chk(dmalloc(s, &s->u_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->dnu_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->norms, sizeof(float) * (12 + 2 * kMaxL)));
@@ -974,6 +1063,13 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     hipLaunchKernelGGL(k_voigt_fill, dim3(blocks_for((int64_t)kNa * kNx, 128)), dim3(128), 0, st, s->vtab, da,
                        kXTab / (kNx - 1));
     RCX_HIP_TRY(hipGetLastError());
+    // compact table: a step of at most 2e-3 (linear-in-a error below 1e-6),
+    // at most kNacMax nodes
+    s->n_ac = (int32_t)std::min<double>(kNacMax, std::max(2.0, std::ceil(a_top / 2e-3) + 1.0));
+    s->da_c = a_top / (s->n_ac - 1);
+    hipLaunchKernelGGL(k_voigt_fill_compact, dim3(blocks_for((int64_t)s->n_ac * kNxc, 64)), dim3(64), 0, st, s->vtabc,
+                       s->n_ac, s->da_c);
+    RCX_HIP_TRY(hipGetLastError());
     s->atm_set = true;
     return RCX_OK;
 }
@@ -993,10 +1089,9 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
     const int64_t nc = s->ncell;
     const AtomDev& A = s->atom;
     SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel,
-                 s->v_inv_da};
+                 (float)(1.0 / s->da_c), s->n_ac};
     hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
     RCX_HIP_TRY(hipGetLastError());
-    const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
     const int32_t nb = (int32_t)s->batches.size();
     if (s->f16) {
         hipLaunchKernelGGL(k_zero_u32n, dim3(blocks_for((int64_t)nb * kLB, 256)), dim3(256), 0, st, s->smax, nb * kLB);
@@ -1034,10 +1129,11 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         if (tr.kind == 0) {
             lop.rec = s->line_rec + (size_t)tr.line * nc;
             lop.vel = s->vel;
-            lop.vt = vt;
+            lop.tabc = s->vtabc;
+            lop.n_a = s->n_ac;
             lop.u_b = bc + 1 * kLB;
             lop.ncell = (uint32_t)nc;
-            lop.da_sqrtpi = (float)(1.0 / (s->v_inv_da * std::sqrt(kPi)));
+            lop.da_sqrtpi = (float)(s->da_c / std::sqrt(kPi));
         }
         RatesEpi re{};
         re.part = s->part + b * nc;
@@ -1159,6 +1255,17 @@ int32_t rcx_nlte_voigt_eval(rcx_nlte* s, int32_t n, const float* a, const float*
     if (n == 0) return RCX_OK;
     const VoigtTab vt{s->vtab, s->v_inv_da, (float)((kNx - 1) / kXTab)};
     hipLaunchKernelGGL(k_voigt_eval, dim3(blocks_for(n, 256)), dim3(256), 0, st, vt, n, a, x, out);
+    RCX_HIP_TRY(hipGetLastError());
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_voigt_eval_march(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out, hipStream_t st)
+{
+    if (!s || !a || !x || !out || n < 0) return nlte_fail(RCX_E_INVALID, "rcx_nlte_voigt_eval_march: bad argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_voigt_eval_march: set the atmosphere first");
+    if (n == 0) return RCX_OK;
+    hipLaunchKernelGGL(k_voigt_eval_compact, dim3(blocks_for(n, 256)), dim3(256), 0, st, s->vtabc, s->n_ac,
+                       (float)(1.0 / s->da_c), (float)(s->da_c / std::sqrt(kPi)), n, a, x, out);
     RCX_HIP_TRY(hipGetLastError());
     return RCX_OK;
 }

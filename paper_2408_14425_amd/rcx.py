@@ -275,6 +275,7 @@ def _load_nlte():
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
     L.rcx_nlte_iterate.argtypes = [vp, vp, i32, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double), vp]
     L.rcx_nlte_voigt_eval.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.rcx_nlte_voigt_eval_march.argtypes = [vp, i32, vp, vp, vp, vp]
     L.rcx_nlte_dims.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.rcx_nlte_destroy.argtypes = [vp]
     L.rcx_nlte_features.argtypes = [vp, vp, vp, vp, vp]
@@ -284,6 +285,7 @@ def _load_nlte():
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
+              "rcx_nlte_voigt_eval_march",
               "rcx_nlte_dims", "rcx_nlte_destroy"):
         getattr(L, n).restype = i32
     L._nlte_bound = True
@@ -392,10 +394,18 @@ class Nlte:
     def iterate(self, pops, max_iter: int, tol: float):
         return rcx_nlte_iterate(self.handle, pops, max_iter, tol)
 
-    def voigt(self, a, x):
+    def voigt(self, a, x, march: bool = False):
+        """H(a, x) from the solver's tables: the full table (features), or
+        with march=True the compact table the line march uses."""
         import torch
         out = torch.empty_like(a)
-        rcx_nlte_voigt_eval(self.handle, a, x, out)
+        if march:
+            _check(_load_nlte().rcx_nlte_voigt_eval_march(self.handle, a.numel(), _dev_ptr(a, "torch.float32", "a"),
+                                                          _dev_ptr(x, "torch.float32", "x"),
+                                                          _dev_ptr(out, "torch.float32", "out"), _stream_ptr(None)),
+                   "rcx_nlte_voigt_eval_march")
+        else:
+            rcx_nlte_voigt_eval(self.handle, a, x, out)
         return out
 
     def features(self, pops, norm=None):

@@ -49,6 +49,26 @@ def test_voigt_table_matches_reference(case32):
     assert rel.max() < 5e-5
 
 
+def test_march_profile_table_matches_reference(case32):
+    """The compact LDS table of the line march (Hermite in x, linear in a)
+    against the oracle's Voigt function over the atmosphere's damping range,
+    in the core and across the table/series boundary at x = 8."""
+    torch = _torch()
+    from oracle import nlte
+    inp, P = case32
+    s = _solver(inp)
+    rng = np.random.default_rng(2)
+    a = rng.uniform(0, P.adamp.max(), 200000)
+    x = np.concatenate([rng.uniform(0, 8, 100000), rng.uniform(7.9, 40, 100000)])
+    got = s.voigt(torch.tensor(a, dtype=torch.float32, device="cuda"),
+                  torch.tensor(x, dtype=torch.float32, device="cuda"), march=True).cpu().numpy().astype(np.float64)
+    s.close()
+    ref = nlte.voigt_H(a.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
+    rel = np.abs(got - ref) / ref
+    print("march profile table max rel", rel.max())
+    assert rel.max() < 2e-5
+
+
 def test_lte_populations(case32):
     _torch()
     inp, P = case32
