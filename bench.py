@@ -62,14 +62,16 @@ def parse():
 
 def algorithmic_bytes(work, n_wave):
     """Bytes the fused march+merge kernels touch per solve: chi and S per cell
-    step, the cascade above read once, the merged cascade written once."""
+    step, the cascade above read once, the merged cascade written once
+    (cascade 0 writes J instead: one value per cell, its 4 directions summed
+    in the kernel)."""
     b = 0
     n = work.n_cascades
     for i in range(n):
         if work.top_skipped and i == n - 1:
             continue
         b += work.level_steps[i] * n_wave * BYTES_PER_STEP
-        b += work.level_rays[i] * n_wave * 4  # write merged cascade i
+        b += (work.level_rays[i] // 4 if i == 0 else work.level_rays[i]) * n_wave * 4  # cascade i or J
         up_read = i + 1 < n and not (work.top_skipped and i + 1 == n - 1)
         if up_read:
             b += work.level_rays[i + 1] * n_wave * 4

@@ -186,6 +186,17 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
     return launch_fs(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
 }
 
+hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, hipStream_t st)
+{
+    march::FieldOp op{};
+    op.Fb = Fb;
+    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    const march::JEpi epi{J, lam0, n_valid, (int64_t)nx * nz};
+    if (!io.up_f16) return launch_fs(L, nx, nz, op, epi, dirs, march::UpF32{(const float*)io.up}, st);
+    return launch_fs(L, nx, nz, op, epi, dirs, march::UpF16{(const __half*)io.up, io.inv_scale_b, 0.0f}, st);
+}
+
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
                     hipStream_t st)
 {

@@ -57,6 +57,10 @@ dim3 march_grid(int64_t rays);
 // buffers [rays][batch_width].
 hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                               const CascIO& io, hipStream_t st);
+// Cascade 0 with 4 directions: march, merge and J in one launch (no stored
+// cascade 0): J[lam0 + l][c] for l < n_valid.
+hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, hipStream_t st);
 // J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
                     hipStream_t st);

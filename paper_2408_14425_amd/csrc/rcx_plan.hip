@@ -312,6 +312,7 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     float* inv_scale = (float*)(ws + w.inv_scale);
     const int32_t lb = batch_width();
     const int32_t n_batch = (n_wave + lb - 1) / lb;
+    const bool fuse_j = p->prm.c0_dirs == 4;
     RCX_HIP_TRY(timed(p, -1, st, [&] {
         hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
         if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
@@ -332,6 +333,15 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
             io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
             io.scale_b = scale + (size_t)b * lb;
             io.inv_scale_b = inv_scale + (size_t)b * lb;
+            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            if (i == 0 && fuse_j) {
+                // cascade 0 writes J directly (the 4 rows of a wavefront are
+                // the 4 directions of one cell)
+                RCX_HIP_TRY(timed(p, i, st, [&] {
+                    return launch_march_merge_j(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb, nvalid, st);
+                }));
+                continue;
+            }
             RCX_HIP_TRY(timed(p, i, st, [&] {
                 return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
             }));
@@ -339,10 +349,12 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
             up_f16 = io.out_f16;
             cur ^= 1;
         }
-        const int32_t nvalid = std::min(lb, n_wave - b * lb);
-        RCX_HIP_TRY(timed(p, -1, st, [&] {
-            return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
-        }));
+        if (!fuse_j) {
+            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            RCX_HIP_TRY(timed(p, -1, st, [&] {
+                return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
+            }));
+        }
     }
     return ok();
 }
