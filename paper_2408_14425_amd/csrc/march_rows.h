@@ -102,6 +102,16 @@ __device__ __forceinline__ RowCtx row_ctx()
 // Segments per row and chunk: 16 columns, at most two segments each.
 constexpr int kSegs = 32;
 
+// One front-to-back step: f = {optical depth per cell in log2 units, S},
+// ds the segment length in cells.
+__device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
+{
+    const float y = f.x * ds;
+    const float e = __builtin_amdgcn_exp2f(-y);
+    I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
+    T *= e;
+}
+
 // March, merge and finish one ray per row. ray = output index of the ray
 // in its cascade, (u, v, k) its probe and direction; active false for rows
 // past the end (they still take part in the wavefront-wide ballots).
@@ -207,27 +217,34 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
 
         // ---- step through the row's segments, 4 at a time. Positions past
         // the row's count are steps with no opacity and no emission.
-        for (int s = 0; s < n_max; s += 4) {
-            const uint4 e01 = seg[row][s >> 1];
-            const uint4 e23 = seg[row][(s >> 1) + 1];
-            const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
-            const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
-                                  __uint_as_float(e23.w)};
-            typename Op::Raw raw[4];
+        if constexpr (Op::kStaged) {
+            // step data in LDS: no global loads to overlap
+            for (int s = 0; s < n_max; s += 4) {
+                const uint4 e01 = seg[row][s >> 1];
+                const uint4 e23 = seg[row][(s >> 1) + 1];
+                const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
+                                      __uint_as_float(e23.w)};
+                typename Op::Raw raw[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if constexpr (Op::kStaged)
-                    op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
-                else
-                    op.fetch(cells[q], (s + q) < n_row, raw[q]);
+                for (int q = 0; q < 4; ++q) op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I, T);
             }
+        } else {
+            // per-lane data: the 4 loads of a group are issued together (a
+            // software pipeline across groups measured no faster: the upper
+            // cascades are bound by HBM bandwidth)
+            for (int s = 0; s < n_max; s += 4) {
+                const uint4 e01 = seg[row][s >> 1];
+                const uint4 e23 = seg[row][(s >> 1) + 1];
+                const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
+                const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
+                                      __uint_as_float(e23.w)};
+                typename Op::Raw raw[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float2 f = op.resolve(raw[q]);  // {optical depth per cell, log2 units; S}
-                const float y = f.x * dsv[q];
-                const float e = __builtin_amdgcn_exp2f(-y);
-                I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
-                T *= e;
+                for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I, T);
             }
         }
         wave_sync();
@@ -291,13 +308,30 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
     for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
-        const int64_t ray = base + c.row;
-        const bool active = ray < total;
-        const int64_t rr = active ? ray : total - 1;
-        const int32_t k = (int32_t)(rr % L.nd);
-        const int32_t p = (int32_t)(rr / L.nd);
-        march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[Op::kStaged ? c.w : 0], c, ray, p % L.px, p / L.px, k,
-                  active);
+        const int64_t r = base + c.row;
+        bool active = r < total;
+        const int64_t rr = active ? r : total - 1;
+        int32_t k, u, v;
+        if (L.tile_p <= 0) {
+            k = (int32_t)(rr % L.nd);
+            const int32_t p = (int32_t)(rr / L.nd);
+            u = p % L.px;
+            v = p / L.px;
+        } else {
+            // group g = (probe tile, direction wedge), wedge fastest; within
+            // a group, direction fastest
+            const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
+            const int64_t g = rr / per, r_in = rr % per;
+            const int32_t nw = L.nd / L.tile_d;
+            const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
+            const int32_t pl = (int32_t)(r_in / L.tile_d);
+            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
+            u = (t % ntx) * L.tile_p + pl % L.tile_p;
+            v = (t / ntx) * L.tile_p + pl / L.tile_p;
+            active = active && u < L.px && v < L.pz;
+        }
+        const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;  // output index
+        march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[Op::kStaged ? c.w : 0], c, ray, u, v, k, active);
     }
 }
 

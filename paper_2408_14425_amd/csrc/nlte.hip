@@ -811,7 +811,7 @@ template <class Op, class Epi, class Up>
 hipError_t launch_level(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
                         const Up& up, hipStream_t st)
 {
-    const int64_t total = (int64_t)L.px * L.pz * L.nd;
+    const int64_t total = level_launch_rays(L);
     hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
                        dirs, up, total);
     return hipGetLastError();

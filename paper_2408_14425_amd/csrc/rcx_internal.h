@@ -20,7 +20,20 @@ struct LevelDesc {
     int32_t max_steps;  // bound on cells a ray can cross
     double s;           // probe spacing, cells
     double ta, tb;      // interval [ta, tb) in cells; tb = +inf on the top cascade
+    // Launch order of the rays: 0 = probe-major (direction fastest); else
+    // groups of tile_p x tile_p probes x tile_d directions, so the rays a
+    // launch runs at one time cross a compact band of cells.
+    int32_t tile_p, tile_d;
 };
+
+// Rays a march launch covers (the tiled order pads the probe grid to whole
+// tiles; padding rays are inactive).
+inline int64_t level_launch_rays(const LevelDesc& L)
+{
+    if (L.tile_p <= 0) return (int64_t)L.px * L.pz * L.nd;
+    const int64_t tx = (L.px + L.tile_p - 1) / L.tile_p, tz = (L.pz + L.tile_p - 1) / L.tile_p;
+    return tx * tz * L.tile_p * L.tile_p * L.nd;
+}
 
 // Error plumbing: set the thread-local message and return the code.
 int32_t fail(int32_t code, const std::string& msg);

@@ -14,6 +14,11 @@
 
 namespace rcx {
 
+// Ray order of the upper cascades (see LevelDesc::tile_p).
+constexpr int32_t kTileMinDirs = 256;
+constexpr int32_t kTileProbes = 4;
+constexpr int32_t kTileDirs = 32;
+
 namespace {
 thread_local int32_t g_last_code = RCX_OK;
 thread_local char g_last_msg[512] = "";
@@ -247,6 +252,16 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
     for (int32_t i = 0; i < n_casc; ++i) {
         LevelDesc& L = p->levels[i];
         L.has_up = (i + 1 < n_casc) && !(p->top_skipped && i + 1 == n_casc - 1);
+        // long upper-cascade rays: run them in (4 x 4 probe tile x 32
+        // direction wedge) groups, so the few groups one XCD holds at a time
+        // cross a band of cells that fits its L2 (probe-major order spreads
+        // them over full 360-degree fans)
+        L.tile_p = 0;
+        L.tile_d = 0;
+        if (L.nd >= kTileMinDirs && L.nd % kTileDirs == 0) {
+            L.tile_p = kTileProbes;
+            L.tile_d = kTileDirs;
+        }
     }
 
     hipError_t e = hipMalloc(&p->dirs_dev, sizeof(double4) * p->dirs_host.size());
