@@ -138,13 +138,13 @@ int32_t rcx_plan_destroy(rcx_plan* plan);
 /* ================================================================ batches
  * Many formal solutions at once (several atmospheres, each with its
  * wavelength batches; every one an independent formal solution, Secs. 2.3
- * and 3.2): work items (atmosphere, 16-wavelength batch, cascade, probe
- * tile) are grouped into generations by their distance from the
- * atmosphere's top cascade, and each generation is one launch over all
- * atmospheres and batches; stream order provides every dependency, so no
- * workgroup waits on another. Cascade 0 writes J directly. The sequence of
- * launches is captured into a HIP graph and replayed, re-captured when the
- * input or output pointers change. */
+ * and 3.2). Tasks (atmosphere, 16-wavelength batch, cascade) are grouped
+ * into generations by their distance from the atmosphere's top cascade;
+ * each generation is one launch that sweeps the rays of all its tasks, and
+ * stream order provides every dependency, so no workgroup waits on another.
+ * Cascade 0 writes J directly. The sequence of launches is captured into a
+ * HIP graph and replayed, re-captured when the input or output pointers
+ * change. */
 typedef struct rcx_batch rcx_batch;
 
 /* n_atm atmospheres with grids[a] and n_wave[a] wavelengths. p as for
@@ -152,9 +152,10 @@ typedef struct rcx_batch rcx_batch;
  * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
 int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
                          rcx_batch** out);
-/* Probe-tile size of a work item in rays (>= 16; default 4096): one
- * workgroup marches one tile. */
-int32_t rcx_batch_set_tiling(rcx_batch* b, int32_t rays_per_item);
+/* Launch order of the cascades with >= 256 directions: groups of
+ * tile_probes x tile_probes probes x 32 directions (default 4), or 0 for
+ * probe-major order. Results do not depend on it. */
+int32_t rcx_batch_set_order(rcx_batch* b, int32_t tile_probes);
 /* Enqueue through the captured graph (1, default) or by direct launches (0). */
 int32_t rcx_batch_set_graph(rcx_batch* b, int32_t enable);
 /* chi_host[a], eta_host[a], J_host[a]: host arrays of n_atm device pointers
@@ -166,13 +167,12 @@ int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float*
                         float* const* J_host, hipStream_t stream);
 /* Work summed over atmospheres and wavelengths (rcx_work semantics). */
 int32_t rcx_batch_work(const rcx_batch* b, int64_t* rays_nonempty_host, int64_t* cell_steps_host);
-/* Time each candidate tile size {1024, 4096, 16384, 65536} rays on these
- * inputs and keep the fastest (*best_rays_host). cache_path (or NULL): a
+/* Time each candidate launch order {0, 2, 4, 8} (rcx_batch_set_order) on
+ * these inputs and keep the fastest (*best_host). cache_path (or NULL): a
  * text file of JSON lines keyed by the batch's shapes; a hit skips timing,
  * a miss appends the result. */
 int32_t rcx_batch_autotune(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
-                           float* const* J_host, const char* cache_path, int32_t* best_rays_host,
-                           hipStream_t stream);
+                           float* const* J_host, const char* cache_path, int32_t* best_host, hipStream_t stream);
 int32_t rcx_batch_destroy(rcx_batch* b);
 
 /* ================================================================ non-LTE

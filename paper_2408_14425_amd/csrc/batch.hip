@@ -2,17 +2,21 @@
 // (the radiance-cascades formal solution of Osborne & Sannikov,
 // arXiv:2408.14425, Secs. 2.3 and 3.2), batched.
 //
-// Work item = (atmosphere, 16-wavelength batch, cascade, probe tile). Each
-// atmosphere has a few buffer slots (a pair of cascade buffers each); batch
-// b uses slot b mod K and runs in round b div K. A generation is the set of
-// items with the same (round, distance from the atmosphere's top cascade):
-// every dependency of an item (the cascade above of the same batch, or the
-// last cascade of the batch that used the slot before) lies in an earlier
-// generation, so one grouped launch per generation, in stream order, needs
-// no waiting between workgroups. Within a launch the workgroups take items
-// in order; each marches its probe tile with the same march_ray as the
-// per-level kernels. Cascade 0 writes J directly. The whole sequence (input
-// prep for every atmosphere + all generations) is captured into a HIP graph
+// Task = (atmosphere, 16-wavelength batch, cascade); the tasks of one
+// (atmosphere, batch) form a chain from the top cascade down. Each
+// atmosphere has a few buffer slots (a pair of cascade buffers each); chain
+// b uses slot b mod K. Launches are formed by a list schedule: a set of
+// active chains advances one cascade per launch, and chains are activated
+// (in order, at most K per atmosphere) until a launch holds enough rays to
+// fill the GPU. A large atmosphere then runs one chain at a time, so its
+// batch's field data stays in the Infinity Cache across its cascades as in
+// the per-cascade path, while small atmospheres share launches. Every
+// dependency (the cascade above in the same chain, or the chain that used
+// the slot before) lies in an earlier launch, and stream order provides it:
+// no workgroup waits on another. A launch sweeps the concatenated rays of
+// its tasks, each in the same order as the per-cascade kernels, with the
+// same march_ray. Cascade 0 writes J directly. The whole sequence (input
+// prep for every atmosphere + all launches) is captured into a HIP graph
 // and replayed.
 #include <hip/hip_runtime.h>
 
@@ -47,23 +51,20 @@ struct Task {
     float* J;
     int32_t lam0, n_valid;
     int64_t ncell;
-    int32_t dep;      // task this one waits for, or -1
-    uint32_t n_items;
+    int32_t dep;      // task this one depends on, or -1
     int32_t level;
-    int32_t tx, tz;   // probe tile
-};
-
-struct Item {
-    int32_t task;
-    int32_t u0, v0;
+    int64_t ray0;     // first ray of the task in its generation's sweep
+    int64_t n_rays;   // rays the task launches (level_launch_rays, a multiple of 4)
 };
 
 constexpr int32_t kMaxSlots = 4;
 
-// One generation: workgroup g processes items begin + g, begin + g + grid, ...
+// One generation: tasks [t0, t0 + nt) sorted by ray0, total rays in all.
+// Grid-stride over the rays like the per-cascade kernel; the 4 rays of a
+// wavefront belong to one task (every task's ray count is a multiple of 4).
 template <bool F16>
-__global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ tasks, const Item* __restrict__ items,
-                                                      uint32_t begin, uint32_t end)
+__global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ tasks, int32_t t0, int32_t nt,
+                                                      int64_t total)
 {
     __shared__ uint4 seg[kBlock / 64][4][16];
     const march::RowCtx c = march::row_ctx();
@@ -72,42 +73,64 @@ __global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ t
         sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
         march::wave_sync();
     }
-    for (uint32_t it = begin + blockIdx.x; it < end; it += gridDim.x) {
-        const Item item = items[it];
-        const Task& T = tasks[item.task];
+    const unsigned lb = march::xcd_block_chunked(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * march::kRaysPerBlock;
+    for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
+        // the task holding ray `base` (the same for the whole wavefront:
+        // made explicit so the descriptor is read with scalar loads)
+        const int64_t wbase = (int64_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32 |
+                              (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+        int32_t lo = t0, hi = t0 + nt - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (tasks[mid].ray0 <= wbase) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const Task T = tasks[lo];  // by value: kept in registers for the march
+        const int64_t rr = wbase - T.ray0 + c.row;  // < T.n_rays
+        const LevelDesc L = T.L;
+        int32_t k, u, v;
+        if (L.tile_p <= 0) {
+            k = (int32_t)(rr % L.nd);
+            const int32_t p = (int32_t)(rr / L.nd);
+            u = p % L.px;
+            v = p / L.px;
+        } else {
+            const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
+            const int64_t g = rr / per, r_in = rr % per;
+            const int32_t nw = L.nd / L.tile_d;
+            const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
+            const int32_t pl = (int32_t)(r_in / L.tile_d);
+            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
+            u = (t % ntx) * L.tile_p + pl % L.tile_p;
+            v = (t / ntx) * L.tile_p + pl / L.tile_p;
+        }
+        const bool active = u < L.px && v < L.pz;
+        const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;
         march::FieldOp op{};
         op.Fb = T.Fb;
         op.fb_bytes = T.fb_bytes;
         op.init(c.l);
-        const int32_t N = T.L.nd;
-        const int64_t n_rays = (int64_t)T.tx * T.tz * N;
-        for (int64_t base = (int64_t)c.w * 4; base < n_rays; base += march::kRaysPerBlock) {
-            const int64_t r = base + c.row;
-            const int32_t k = (int32_t)(r % N);
-            const int32_t pl = (int32_t)(r / N);
-            const int32_t u = item.u0 + pl % T.tx, v = item.v0 + pl / T.tx;
-            const bool active = r < n_rays && u < T.L.px && v < T.L.pz;
-            const int64_t ray = ((int64_t)v * T.L.px + u) * N + k;
-            if (F16) {
-                march::UpF16 up{(const __half*)T.up, T.inv_scale_b, 0.0f};
-                up.init(c.l);
-                if (T.level == 0) {
-                    march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
-                } else {
-                    march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
-                    epi.init(c.l);
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
-                }
+        if (F16) {
+            march::UpF16 up{(const __half*)T.up, T.inv_scale_b, 0.0f};
+            up.init(c.l);
+            if (T.level == 0) {
+                march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
+                march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
             } else {
-                march::UpF32 up{(const float*)T.up};
-                if (T.level == 0) {
-                    march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
-                } else {
-                    march::StoreEpi epi{(float*)T.out};
-                    march::march_ray(T.L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
-                }
+                march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
+                epi.init(c.l);
+                march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
+            }
+        } else {
+            march::UpF32 up{(const float*)T.up};
+            if (T.level == 0) {
+                march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
+                march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
+            } else {
+                march::StoreEpi epi{(float*)T.out};
+                march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
             }
         }
     }
@@ -131,14 +154,13 @@ struct rcx_batch {
     std::vector<size_t> casc_half;     // bytes of one of the two buffers
     std::vector<int32_t> casc_index;   // first slot of atmosphere a
     std::vector<int32_t> n_slots;      // slots of atmosphere a
-    int32_t rays_per_item = 4096;
-    std::vector<Task> tasks_h;
-    std::vector<Item> items_h;
+    int32_t tile_probes = 4;          // launch order of the upper cascades (0: probe-major)
+    int64_t fill_rays = 1 << 19;      // rays a launch gathers before it stops activating chains
+    std::vector<Task> tasks_h;        // grouped by generation, each group sorted by ray0
     Task* tasks_d = nullptr;
-    Item* items_d = nullptr;
-    size_t tasks_cap = 0, items_cap = 0;
-    std::vector<uint32_t> gen_begin;  // item range of each generation: [gen_begin[g], gen_begin[g + 1])
-    int grid_cap = 0;                 // workgroups per launch at most (resident capacity)
+    size_t tasks_cap = 0;
+    std::vector<int32_t> gen_task;    // task range of each generation: [gen_task[g], gen_task[g + 1])
+    std::vector<int64_t> gen_rays;    // rays of each generation
     std::vector<float*> J_bound;  // J pointers the tasks were built for
     // graph
     bool use_graph = true;
@@ -162,52 +184,40 @@ hipError_t balloc(rcx_batch* s, P** p, size_t bytes)
     return e;
 }
 
-// Probe tile with about `rays` rays for a cascade of N directions.
-void tile_for(int32_t rays, int32_t N, int32_t px, int32_t pz, int32_t* tx, int32_t* tz)
-{
-    int64_t probes = std::max<int64_t>(1, rays / N);
-    int32_t a = 1;
-    while ((int64_t)(a * 2) * (a * 2) <= probes) a *= 2;
-    int32_t b = a;
-    if ((int64_t)a * b * 2 <= probes) b *= 2;
-    *tx = std::min(b, px);
-    *tz = std::min(a, pz);
-}
-
-// Build the task and item lists for the current J pointers and tile size,
-// grouped into generations. Returns false if a dependency would not precede
-// its dependent (an internal error).
+// Build the task list for the current J pointers and launch order, grouped
+// into launches by the list schedule. Returns false if a dependency would
+// not precede its dependent (an internal error).
 bool build_work(rcx_batch* s, float* const* J)
 {
-    s->tasks_h.clear();
-    s->items_h.clear();
-    struct Pending {
-        int32_t round, top_dist, task;
+    // chains in order: atmosphere-major, batches in order
+    struct Chain {
+        int32_t atm;
+        std::vector<Task> tasks;  // top cascade first
     };
-    std::vector<Pending> order;
+    std::vector<Chain> chains;
     for (int32_t a = 0; a < s->n_atm; ++a) {
         const rcx_plan* P = s->plans[a];
         const int64_t ncell = (int64_t)P->grid.nx * P->grid.nz;
         const int32_t K = s->n_slots[a];
-        std::vector<int32_t> last(s->n_batch[a], -1);  // cascade-0 task of each batch
         for (int32_t b = 0; b < s->n_batch[a]; ++b) {
+            Chain ch;
+            ch.atm = a;
             const int32_t slot = s->casc_index[a] + b % K;
             char* buf0 = (char*)s->casc[slot];
             char* bufs[2] = {buf0, buf0 + s->casc_half[slot]};
             int cur = 0;
-            int32_t prev = -1;
             const void* up = nullptr;
             for (int32_t i = P->n_casc - 1; i >= 0; --i) {
                 if (P->top_skipped && i == P->n_casc - 1) continue;
-                const LevelDesc& L = P->levels[i];
                 Task T{};
-                T.L = L;
+                T.L = P->levels[i];
+                if (T.L.tile_p > 0) T.L.tile_p = s->tile_probes;  // 0: probe-major
                 T.nx = P->grid.nx;
                 T.nz = P->grid.nz;
                 T.dirs = P->dirs_dev + P->dir_off[i];
                 T.Fb = s->F[a] + (size_t)b * ncell * kLB;
                 T.fb_bytes = (uint32_t)(ncell * kLB * sizeof(float2));
-                T.up = L.has_up ? up : nullptr;
+                T.up = T.L.has_up ? up : nullptr;
                 T.out = bufs[cur];
                 T.scale_b = s->f16 ? s->scale[a] + b * kLB : nullptr;
                 T.inv_scale_b = s->f16 ? s->inv_scale[a] + b * kLB : nullptr;
@@ -215,72 +225,97 @@ bool build_work(rcx_batch* s, float* const* J)
                 T.lam0 = b * kLB;
                 T.n_valid = std::min(kLB, s->n_wave[a] - b * kLB);
                 T.ncell = ncell;
-                // the cascade above, or for the batch's first cascade the
-                // batch that used this slot before
-                T.dep = L.has_up ? prev : (prev < 0 && b >= K ? last[b - K] : -1);
                 T.level = i;
-                tile_for(s->rays_per_item, L.nd, L.px, L.pz, &T.tx, &T.tz);
-                const int32_t ntx = (L.px + T.tx - 1) / T.tx, ntz = (L.pz + T.tz - 1) / T.tz;
-                T.n_items = (uint32_t)ntx * ntz;
-                const int32_t ti = (int32_t)s->tasks_h.size();
-                s->tasks_h.push_back(T);
-                order.push_back({b / K, P->n_casc - 1 - i, ti});
-                prev = ti;
+                T.n_rays = level_launch_rays(T.L);
+                T.dep = -1;
+                if (T.n_rays % 4 != 0) return false;
+                ch.tasks.push_back(T);
                 up = bufs[cur];
                 cur ^= 1;
             }
-            last[b] = prev;
+            chains.push_back(std::move(ch));
         }
     }
-    // Slot rounds, then top-down; among equal keys larger tasks first (they
-    // bound the makespan). Every dependency sorts strictly earlier.
-    std::stable_sort(order.begin(), order.end(), [&](const Pending& x, const Pending& y) {
-        if (x.round != y.round) return x.round < y.round;
-        if (x.top_dist != y.top_dist) return x.top_dist < y.top_dist;
-        const Task& a = s->tasks_h[x.task];
-        const Task& b = s->tasks_h[y.task];
-        return (int64_t)a.L.px * a.L.pz * a.L.nd > (int64_t)b.L.px * b.L.pz * b.L.nd;
-    });
-    s->gen_begin.clear();
-    std::vector<int32_t> gen_of(s->tasks_h.size(), -1);
-    for (size_t q = 0; q < order.size(); ++q) {
-        const auto& o = order[q];
-        if (q == 0 || o.round != order[q - 1].round || o.top_dist != order[q - 1].top_dist)
-            s->gen_begin.push_back((uint32_t)s->items_h.size());
-        gen_of[o.task] = (int32_t)s->gen_begin.size() - 1;
-        const Task& T = s->tasks_h[o.task];
-        for (int32_t v0 = 0; v0 < T.L.pz; v0 += T.tz)
-            for (int32_t u0 = 0; u0 < T.L.px; u0 += T.tx) s->items_h.push_back({o.task, u0, v0});
+    // list schedule
+    s->tasks_h.clear();
+    s->gen_task.clear();
+    s->gen_rays.clear();
+    std::vector<int32_t> active_of(s->n_atm, 0);
+    struct Active {
+        int32_t chain, pos;
+    };
+    std::vector<Active> active;
+    size_t next = 0;  // first chain not yet activated
+    std::vector<char> started(chains.size(), 0);
+    while (next < chains.size() || !active.empty()) {
+        int64_t rays = 0;
+        for (const auto& a : active) rays += chains[a.chain].tasks[a.pos].n_rays;
+        for (size_t c = next; c < chains.size() && rays < s->fill_rays; ++c) {
+            if (started[c] || active_of[chains[c].atm] >= s->n_slots[chains[c].atm]) continue;
+            // chains of one atmosphere start in order (their slots rotate)
+            bool earlier_waiting = false;
+            for (size_t d = next; d < c; ++d)
+                if (!started[d] && chains[d].atm == chains[c].atm) earlier_waiting = true;
+            if (earlier_waiting) continue;
+            started[c] = 1;
+            ++active_of[chains[c].atm];
+            active.push_back({(int32_t)c, 0});
+            rays += chains[c].tasks[0].n_rays;
+        }
+        while (next < chains.size() && started[next]) ++next;
+        if (active.empty()) return false;  // cannot happen: some chain can always start
+        // one launch: the next task of every active chain, larger first
+        std::vector<Task> gen;
+        for (auto& a : active) gen.push_back(chains[a.chain].tasks[a.pos]);
+        std::stable_sort(gen.begin(), gen.end(), [](const Task& x, const Task& y) { return x.n_rays > y.n_rays; });
+        s->gen_task.push_back((int32_t)s->tasks_h.size());
+        int64_t ray0 = 0;
+        for (Task T : gen) {
+            T.ray0 = ray0;
+            ray0 += T.n_rays;
+            s->tasks_h.push_back(T);
+        }
+        s->gen_rays.push_back(ray0);
+        // advance; retire finished chains
+        std::vector<Active> still;
+        for (auto a : active) {
+            if (++a.pos < (int32_t)chains[a.chain].tasks.size()) still.push_back(a);
+            else --active_of[chains[a.chain].atm];
+        }
+        active.swap(still);
     }
-    s->gen_begin.push_back((uint32_t)s->items_h.size());
-    // every dependency lies in an earlier generation
+    s->gen_task.push_back((int32_t)s->tasks_h.size());
+    // Check: the task that wrote a task's input cascade (same batch, the
+    // cascade above) sits in an earlier launch, and no task in between
+    // overwrote that buffer.
+    std::vector<int32_t> gen_of(s->tasks_h.size());
+    for (size_t g = 0; g + 1 < s->gen_task.size(); ++g)
+        for (int32_t t = s->gen_task[g]; t < s->gen_task[g + 1]; ++t) gen_of[t] = (int32_t)g;
     for (size_t t = 0; t < s->tasks_h.size(); ++t) {
         const Task& T = s->tasks_h[t];
-        if (gen_of[t] < 0) return false;
-        if (T.dep >= 0 && !(gen_of[T.dep] >= 0 && gen_of[T.dep] < gen_of[t])) return false;
+        if (!T.up) continue;
+        int32_t writer = -1;
+        for (size_t w = 0; w < s->tasks_h.size(); ++w)
+            if (s->tasks_h[w].level == T.level + 1 && s->tasks_h[w].lam0 == T.lam0 && s->tasks_h[w].Fb == T.Fb)
+                writer = (int32_t)w;
+        if (writer < 0 || s->tasks_h[writer].out != T.up || !(gen_of[writer] < gen_of[t])) return false;
+        for (size_t w = 0; w < s->tasks_h.size(); ++w)
+            if ((int32_t)w != writer && s->tasks_h[w].out == T.up && gen_of[w] >= gen_of[writer] && gen_of[w] <= gen_of[t])
+                return false;
     }
     return true;
 }
 
 hipError_t upload_work(rcx_batch* s)
 {
-    hipError_t e = hipSuccess;
     if (s->tasks_h.size() > s->tasks_cap) {
         if (s->tasks_d) (void)hipFree(s->tasks_d);
+        s->tasks_d = nullptr;
         s->tasks_cap = s->tasks_h.size();
-        e = hipMalloc(&s->tasks_d, sizeof(Task) * s->tasks_cap);
+        hipError_t e = hipMalloc(&s->tasks_d, sizeof(Task) * s->tasks_cap);
         if (e != hipSuccess) return e;
     }
-    if (s->items_h.size() > s->items_cap) {
-        if (s->items_d) (void)hipFree(s->items_d);
-        s->items_cap = s->items_h.size();
-        e = hipMalloc(&s->items_d, sizeof(Item) * s->items_cap);
-        if (e != hipSuccess) return e;
-    }
-    e = hipMemcpy(s->tasks_d, s->tasks_h.data(), sizeof(Task) * s->tasks_h.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
-        e = hipMemcpy(s->items_d, s->items_h.data(), sizeof(Item) * s->items_h.size(), hipMemcpyHostToDevice);
-    return e;
+    return hipMemcpy(s->tasks_d, s->tasks_h.data(), sizeof(Task) * s->tasks_h.size(), hipMemcpyHostToDevice);
 }
 
 // Enqueue one batch solve (no synchronisation).
@@ -294,13 +329,14 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
         if (e == hipSuccess && s->f16) e = launch_scales(s->n_batch[a] * kLB, s->smax[a], s->scale[a], s->inv_scale[a], st);
         if (e != hipSuccess) return e;
     }
-    for (size_t g = 0; g + 1 < s->gen_begin.size(); ++g) {
-        const uint32_t b = s->gen_begin[g], e = s->gen_begin[g + 1];
-        const unsigned grid = (unsigned)std::min<uint32_t>(e - b, (uint32_t)s->grid_cap);
+    for (size_t g = 0; g + 1 < s->gen_task.size(); ++g) {
+        const int32_t t0 = s->gen_task[g], nt = s->gen_task[g + 1] - t0;
+        const int64_t total = s->gen_rays[g];
+        const dim3 grid = march_grid(total);
         if (s->f16)
-            hipLaunchKernelGGL(k_batch_gen<true>, dim3(grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d, b, e);
+            hipLaunchKernelGGL(k_batch_gen<true>, grid, dim3(kBlock), 0, st, s->tasks_d, t0, nt, total);
         else
-            hipLaunchKernelGGL(k_batch_gen<false>, dim3(grid), dim3(kBlock), 0, st, s->tasks_d, s->items_d, b, e);
+            hipLaunchKernelGGL(k_batch_gen<false>, grid, dim3(kBlock), 0, st, s->tasks_d, t0, nt, total);
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
     }
@@ -384,28 +420,15 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
         rcx_batch_destroy(s);
         return bfail(RCX_E_NOMEM, std::string("rcx_batch_create: hipMalloc: ") + hipGetErrorName(e));
     }
-    // workgroups per generation launch: at most the resident capacity
-    int dev = 0, n_cu = 0, per_cu = 0;
-    chk(hipGetDevice(&dev));
-    chk(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    if (s->f16)
-        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_gen<true>, kBlock, 0));
-    else
-        chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_gen<false>, kBlock, 0));
-    if (e != hipSuccess || n_cu < 1 || per_cu < 1) {
-        rcx_batch_destroy(s);
-        return rcx::hip_fail(e == hipSuccess ? hipErrorInvalidValue : e, "rcx_batch_create: occupancy query");
-    }
-    s->grid_cap = n_cu * per_cu;
     *out = s;
     return RCX_OK;
 }
 
-int32_t rcx_batch_set_tiling(rcx_batch* s, int32_t rays_per_item)
+int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes)
 {
-    if (!s || rays_per_item < 16) return bfail(RCX_E_INVALID, "rcx_batch_set_tiling: bad argument");
-    s->rays_per_item = rays_per_item;
-    s->J_bound.clear();  // rebuild the work lists on the next solve
+    if (!s || tile_probes < 0 || tile_probes > 64) return bfail(RCX_E_INVALID, "rcx_batch_set_order: bad argument");
+    s->tile_probes = tile_probes;
+    s->J_bound.clear();  // rebuild the task list on the next solve
     drop_graph(s);
     return RCX_OK;
 }
@@ -494,20 +517,20 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
             const size_t pos = line.find(pre);
             if (pos != std::string::npos) {
                 const int32_t r = std::atoi(line.c_str() + pos + pre.size());
-                if (r >= 16) {
+                if (r >= 0 && r <= 64) {
                     *best_rays_host = r;
-                    return rcx_batch_set_tiling(s, r);
+                    return rcx_batch_set_order(s, r);
                 }
             }
         }
     }
-    const int32_t cands[] = {1024, 4096, 16384, 65536};
+    const int32_t cands[] = {0, 2, 4, 8};
     double best_ms = 1e300;
     int32_t best = cands[0];
     const bool g = s->use_graph;
     s->use_graph = false;
     for (int32_t cnd : cands) {
-        int32_t rc = rcx_batch_set_tiling(s, cnd);
+        int32_t rc = rcx_batch_set_order(s, cnd);
         if (rc != RCX_OK) return rc;
         rc = rcx_batch_solve(s, chi, eta, J, st);  // warm-up and work-list build
         if (rc != RCX_OK) return rc;
@@ -526,7 +549,7 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
         f << "{\"" << k << "\": " << best << ", \"ms\": " << best_ms << "}\n";
     }
     *best_rays_host = best;
-    return rcx_batch_set_tiling(s, best);
+    return rcx_batch_set_order(s, best);
 }
 
 int32_t rcx_batch_destroy(rcx_batch* s)
@@ -535,7 +558,6 @@ int32_t rcx_batch_destroy(rcx_batch* s)
     drop_graph(s);
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->tasks_d) (void)hipFree(s->tasks_d);
-    if (s->items_d) (void)hipFree(s->items_d);
     for (rcx_plan* P : s->plans) rcx_plan_destroy(P);
     if (s->cap) (void)hipStreamDestroy(s->cap);
     delete s;

@@ -29,14 +29,19 @@ constexpr unsigned kXcds = 8;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
-// Workgroups are dispatched round-robin over the 8 XCDs; give every XCD a
-// contiguous range of logical blocks so rays that share cells share an L2.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+// Workgroups are dispatched round-robin over the 8 XCDs. XCD x takes
+// chunks of kXcdChunk consecutive logical blocks, chunk i on XCD i mod 8:
+// all XCDs advance through the ray order together (they share the field data
+// in the Infinity Cache) while each works on compact groups of rays (shared
+// in its own L2). The tail that does not fill 8 whole chunks keeps the
+// identity order.
+constexpr unsigned kXcdChunk = 128;
+__device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb)
 {
-    unsigned per = nb / kXcds, rem = nb % kXcds;
-    unsigned x = b % kXcds, slot = b / kXcds;
-    unsigned start = (x < rem) ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
-    return start + slot;
+    const unsigned full = nb / (kXcds * kXcdChunk) * (kXcds * kXcdChunk);
+    if (b >= full) return b;
+    const unsigned x = b % kXcds, slot = b / kXcds;
+    return (slot / kXcdChunk) * (kXcds * kXcdChunk) + x * kXcdChunk + slot % kXcdChunk;
 }
 
 // 1 - 2^{-y} for y >= 0 (y = optical depth in log2 units) without
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
         }
         wave_sync();
     }
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
     for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
         const int64_t r = base + c.row;

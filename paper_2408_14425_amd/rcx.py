@@ -551,13 +551,13 @@ def _load_batch():
         return L
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.rcx_batch_create.argtypes = [i32, C.POINTER(rcx_grid), C.POINTER(i32), C.POINTER(rcx_params), C.POINTER(vp)]
-    L.rcx_batch_set_tiling.argtypes = [vp, i32]
+    L.rcx_batch_set_order.argtypes = [vp, i32]
     L.rcx_batch_set_graph.argtypes = [vp, i32]
     L.rcx_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.rcx_batch_work.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     L.rcx_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_char_p, C.POINTER(i32), vp]
     L.rcx_batch_destroy.argtypes = [vp]
-    for n in ("rcx_batch_create", "rcx_batch_set_tiling", "rcx_batch_set_graph", "rcx_batch_solve",
+    for n in ("rcx_batch_create", "rcx_batch_set_order", "rcx_batch_set_graph", "rcx_batch_solve",
               "rcx_batch_work", "rcx_batch_autotune", "rcx_batch_destroy"):
         getattr(L, n).restype = i32
     L._batch_bound = True
@@ -591,8 +591,8 @@ class Batch:
         self.handle = h.value
         self.shapes, self.n_wave = [tuple(s) for s in shapes], list(n_wave)
 
-    def set_tiling(self, rays_per_item: int):
-        _check(_load_batch().rcx_batch_set_tiling(self.handle, int(rays_per_item)), "rcx_batch_set_tiling")
+    def set_order(self, tile_probes: int):
+        _check(_load_batch().rcx_batch_set_order(self.handle, int(tile_probes)), "rcx_batch_set_order")
 
     def set_graph(self, enable: bool):
         _check(_load_batch().rcx_batch_set_graph(self.handle, int(bool(enable))), "rcx_batch_set_graph")
