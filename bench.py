@@ -49,6 +49,9 @@ def parse():
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
     ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--c4", action="store_true",
+                    help="also run the batched formal solve of 16 uneven atmospheres (256^2..2048^2, "
+                         "32..256 wavelengths; ~190 GB of device memory, a few minutes)")
     ap.add_argument("--nlte-only", action="store_true",
                     help="only the converged non-LTE solves (for profiling; prints their object)")
     ap.add_argument("--nlte-variants", default="plain_fp32,learned_fp16",
@@ -209,6 +212,71 @@ def nlte_solves(args):
     return out
 
 
+def c4_batched(args):
+    """The 16-atmosphere uneven batch in one batched solve (HIP graph), FP32
+    and FP16 cascade storage: time per solve, ray intervals per second, and
+    J at sampled cells of a wing and a core wavelength of every atmosphere
+    against the FP64 oracle (through the cells' dependency cones)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2408_14425_amd import rcx, workloads
+    specs = workloads.uneven_batch()
+    rng = np.random.default_rng(7)
+    chi, eta, J, samples = [], [], [], []
+    t0 = time.perf_counter()
+    for side, nw, seed in specs:
+        inp = workloads.line_medium(side, nw, seed=seed)
+        chi.append(torch.from_numpy(inp.chi).cuda())
+        eta.append(torch.from_numpy(inp.eta).cuda())
+        J.append(torch.empty_like(chi[-1]))
+        lam = [0, nw // 2]  # line wing and line core
+        cells = [(0, 0), (side - 1, side - 1)] + [tuple(int(c) for c in rng.integers(0, side, 2)) for _ in range(2)]
+        samples.append((inp.chi[lam].copy(), inp.eta[lam].copy(), lam, cells, inp.n_cascades))
+        del inp
+        print(f"[bench] c4 atmosphere {side}^2 x {nw} ready ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+              flush=True)
+    out = {"workload": "16 line-medium atmospheres, sides " + ",".join(str(s_[0]) for s_ in specs)
+                       + "; wavelengths " + ",".join(str(s_[1]) for s_ in specs),
+           "atmospheres": len(specs)}
+    got = {}
+    for name, storage in (("fp32", rcx.RCX_STORE_F32), ("fp16", rcx.RCX_STORE_F16_SCALED)):
+        B = rcx.Batch([(s_[0], s_[0]) for s_ in specs], [s_[1] for s_ in specs], storage=storage)
+        B.solve(chi, eta, J)  # builds the schedule and captures the graph
+        torch.cuda.synchronize()
+        reps = 2
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            B.solve(chi, eta, J)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / reps
+        rays, steps = B.work()
+        B.close()
+        got[name] = [[J[a][l, z, x].item() for l in smp[2] for (x, z) in smp[3]] for a, smp in enumerate(samples)]
+        out[name] = {"s_per_solve": dt, "ray_intervals_per_s": rays / dt, "cell_steps_per_s": steps / dt}
+        print(f"[bench] c4 {name}: {dt:.2f} s per batched solve", file=sys.stderr, flush=True)
+    del chi, eta, J
+    torch.cuda.empty_cache()
+    ref = []
+    for c_, e_, lam, cells, nc in samples:
+        side = c_.shape[-1]
+        need = np.zeros((side, side), np.uint8)
+        for x, z in cells:
+            need[z, x] = 1
+        vals = []
+        for i in range(len(lam)):
+            Jo = oracle.formal_solve(c_[i:i + 1], e_[i:i + 1], nc, need=need)["J"][0]
+            vals += [Jo[z, x] for (x, z) in cells]
+        ref.append(vals)
+    for name in ("fp32", "fp16"):
+        rel = [abs(g - o) / o for ga, ra in zip(got[name], ref) for g, o in zip(ga, ra)]
+        out[name]["max_rel_error_vs_oracle"] = max(rel)
+        out[name]["samples"] = len(rel)
+    out["rays_per_solve"] = rays
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -303,6 +371,8 @@ def main():
     }
     if not args.no_nlte:
         out["nonlte"] = nlte_solves(args)
+    if args.c4:
+        out["batched"] = c4_batched(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_waves)
     print(json.dumps(out), flush=True)

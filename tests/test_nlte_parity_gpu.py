@@ -177,3 +177,23 @@ def test_fp16_storage_converged_populations(case32):
     assert np.all(np.isfinite(J16))
     assert rdiff < 1e-4
     assert relp.max() < 1e-3
+
+
+def test_converged_64_at_oracle_iteration_count():
+    """The same at 64^2 (the oracle's iteration count, populations to 1e-3)."""
+    _torch()
+    from oracle import nlte
+    inp = W.nlte_atmosphere(64, seed=4, n_line=32, n_cont=16)
+    P = nlte.Problem(inp)
+    po, changes = P.iterate(P.lte.copy(), 200, tol=1e-3)
+    K = len(changes)
+    s = _solver(inp)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, K, 0.0)  # exactly the oracle's iteration count
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"64^2 converged: oracle {K} iterations (last change {changes[-1]:.3e}); gpu {it} ({ch:.3e}); "
+          f"max rel {relp.max():.3e}")
+    assert it == K
+    assert relp.max() < 1e-3
