@@ -175,23 +175,30 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
 
     float I = 0.0f, T = 1.0f;
     const int max_chunks = (nm + 2 + 15) / 16 + 1;
+    // Minor-axis cell of a crossing at pn: floor(pn) if sn > 0, else
+    // ceil(pn) - 1 = ~floor(-pn); both as floor(sn * pn) ^ nflip (sn * pn is
+    // exact). The products below stay within 24 bits (cell < 2^24).
+    const double snd = (double)sn;
+    const int nflip = sn > 0 ? 0 : -1, nadd = sn > 0 ? 1 : 0;
     for (int chunk = 0; chunk < max_chunks; ++chunk) {
         // ---- column j of this row's ray: one or two segments
         const int j = chunk * 16 + l;
-        const double ta = (j == 0) ? lo : fma((double)(mfirst + (j - 1) * sm), im_, offm);
-        const double tb_ = fmin(fma((double)(mfirst + j * sm), im_, offm), hi);
+        const int pj = mfirst + __mul24(j - 1, sm);  // m-plane entering column j
+        const double ta = (j == 0) ? lo : fma((double)pj, im_, offm);
+        const double tb_ = fmin(fma((double)(pj + sm), im_, offm), hi);
         const bool valid = ta < hi;
-        const int im = min(max(im0 + j * sm, 0), nm - 1);
+        const int im = min(max(im0 + __mul24(j, sm), 0), nm - 1);
         const double pn = cn + ta * wn;
-        int in0 = wn > 0.0 ? (int)floor(pn) : (int)ceil(pn) - 1;
+        int in0 = (int)floor(snd * pn) ^ nflip;
         in0 = min(max(in0, 0), nn - 1);
-        const int nnext = wn > 0.0 ? in0 + 1 : in0;
+        const int nnext = in0 + nadd;
         const double tn = fma((double)nnext, in_, offn);
         const bool two = valid && tn < tb_;
         const double tmid = fmax(tn, ta);
-        const uint32_t cell1 = (uint32_t)(im * strm + in0 * strn);
         const int in1 = min(max(in0 + sn, 0), nn - 1);
-        const uint32_t cell2 = (uint32_t)(im * strm + in1 * strn);
+        const int cm_ = __mul24(im, strm);
+        const uint32_t cell1 = (uint32_t)(cm_ + __mul24(in0, strn));
+        const uint32_t cell2 = (uint32_t)(cm_ + __mul24(in1, strn));
         const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
         const float ds2 = (float)fmax(tb_ - tmid, 0.0);
         typename Op::Stage st1{}, st2{};
@@ -203,20 +210,35 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         const uint64_t b1 = __ballot(valid);
         if (b1 == 0) break;
         const uint64_t b2 = __ballot(two);
-        const int pos = __popcll(b1 & row_bits & lt_bits) + __popcll(b2 & row_bits & lt_bits);
-        const int n_row = __popcll(b1 & row_bits) + __popcll(b2 & row_bits);
+        const int pos = (int)__popcll(b1 & row_bits & lt_bits) + (int)__popcll(b2 & row_bits & lt_bits);
+        // longest list of the 4 rows, from the wave-uniform ballots
         int n_max = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint64_t rb = 0xFFFFull << (16 * q);
-            n_max = max(n_max, __popcll(b1 & rb) + __popcll(b2 & rb));
+            n_max = max(n_max, (int)__popcll(b1 & rb) + (int)__popcll(b2 & rb));
         }
+        n_max = __builtin_amdgcn_readfirstlane(n_max);
         uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
-        if (valid) srow[pos] = make_uint2(cell1, __float_as_uint(ds1));
-        if (two) srow[pos + 1] = make_uint2(cell2, __float_as_uint(ds2));
+        // entries: the Op's key of the cell (a byte offset for per-lane
+        // fields) and ds; positions past the row's count hold a null entry
+        // (no data, ds = 0), so the step loop needs no bounds test
+        int n_row = 0;
         if constexpr (Op::kStaged) {
+            n_row = (int)__popcll(b1 & row_bits) + (int)__popcll(b2 & row_bits);
+            if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
+            if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
+            if (n_row + l < kSegs) srow[n_row + l] = make_uint2(Op::kNullKey, 0u);
+            if (n_row + l + 16 < kSegs) srow[n_row + l + 16] = make_uint2(Op::kNullKey, 0u);
             if (valid) stg[row][pos] = st1;
             if (two) stg[row][pos + 1] = st2;
+        } else {
+            // null entries everywhere, then the row's segments over them (the
+            // LDS executes one wavefront's writes in issue order)
+            srow[l] = make_uint2(Op::kNullKey, 0u);
+            srow[l + 16] = make_uint2(Op::kNullKey, 0u);
+            if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
+            if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
         }
         wave_sync();
 
@@ -237,9 +259,10 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a
-            // software pipeline across groups measured no faster: the upper
-            // cascades are bound by HBM bandwidth)
-            for (int s = 0; s < n_max; s += 4) {
+            // software pipeline across groups measured no faster)
+#pragma unroll
+            for (int s = 0; s < kSegs; s += 4) {
+                if (s >= n_max) break;
                 const uint4 e01 = seg[row][s >> 1];
                 const uint4 e23 = seg[row][(s >> 1) + 1];
                 const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
@@ -247,7 +270,7 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
                                       __uint_as_float(e23.w)};
                 typename Op::Raw raw[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) op.fetch(cells[q], (s + q) < n_row, raw[q]);
+                for (int q = 0; q < 4; ++q) op.fetch_key(cells[q], raw[q]);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I, T);
             }
@@ -403,10 +426,13 @@ struct FieldOp {
         lane_off = (uint32_t)l * 8u;
     }
     __device__ __forceinline__ void begin_ray(double, double) {}
-    __device__ __forceinline__ void fetch(uint32_t cell, bool ok, Raw& r) const
+    // key of a cell: the byte offset of its 16 wavelengths (cell < 2^24, so
+    // below 2^28); the null key lies beyond every buffer and reads zeros
+    static constexpr uint32_t kNullKey = 0x80000000u;
+    __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell * (uint32_t)(kLB * 8); }
+    __device__ __forceinline__ void fetch_key(uint32_t k, Raw& r) const
     {
-        const uint32_t off = ok ? cell * (uint32_t)(kLB * 8) + lane_off : 0x80000000u;
-        r = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, off, 0, 0));
+        r = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, k + lane_off, 0, 0));
     }
     __device__ __forceinline__ float2 resolve(const Raw& r) const { return r; }
 };

@@ -451,6 +451,10 @@ struct LineOp {
         for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) smem[i] = tabc[i];
         tab = smem;
     }
+    // segment entries keep the cell index (the step loop reads the staged
+    // record); a null entry has ds = 0
+    static constexpr uint32_t kNullKey = 0u;
+    __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell; }
     __device__ __forceinline__ Stage stage(uint32_t cell) const
     {
         Stage st;
