@@ -66,11 +66,10 @@ template <bool F16>
 __global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ tasks, int32_t t0, int32_t nt,
                                                       int64_t total)
 {
-    __shared__ uint4 seg[kBlock / 64][4][16];
+    __shared__ uint4 seg[kBlock / 64][4][march::kSegRow];
     const march::RowCtx c = march::row_ctx();
     {
-        uint4* sw = &seg[c.w][0][0];
-        sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
+        seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
         march::wave_sync();
     }
     const unsigned lb = march::xcd_block_chunked(blockIdx.x, gridDim.x);

@@ -106,6 +106,12 @@ __device__ __forceinline__ RowCtx row_ctx()
 
 // Segments per row and chunk: 16 columns, at most two segments each.
 constexpr int kSegs = 32;
+// LDS rows of the segment lists (16 uint4 = 32 entries) and of the staged
+// data, each padded by one element: the 4 rows of a wavefront read 4
+// different addresses in the same instruction, and unpadded (256 or 1024
+// bytes apart) they would fall in the same banks.
+constexpr int kSegRow = 17;
+constexpr int kStgRow = kSegs + 1;
 
 // One front-to-back step: f = {optical depth per cell in log2 units, S},
 // ds the segment length in cells.
@@ -122,14 +128,15 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
 // past the end (they still take part in the wavefront-wide ballots).
 // An Op whose step data depends on the cell only (the same for all 16
 // wavelength lanes of a row) sets kStaged: the lane that finds a segment
-// loads that data once (Op::stage) while the row's segment list is built,
+// loads that data once (Op::stage_load, then Op::stage_make forms the
+// entry) while the row's segment list is built,
 // and the step loop reads it back from LDS (stg, this wavefront's
 // [4 rows][kSegs] entries) instead of issuing a dependent global load per
 // step.
 template <class Op, class Epi, class Up>
 __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
-                                          const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[16],
-                                          typename Op::Stage (*stg)[kSegs], const RowCtx& cx_, int64_t ray,
+                                          const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[kSegRow],
+                                          typename Op::Stage (*stg)[kStgRow], const RowCtx& cx_, int64_t ray,
                                           int32_t u, int32_t v, int32_t k, bool active)
 {
     const int lane = cx_.lane, row = cx_.row, l = cx_.l;
@@ -201,10 +208,11 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         const uint32_t cell2 = (uint32_t)(cm_ + __mul24(in1, strn));
         const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
         const float ds2 = (float)fmax(tb_ - tmid, 0.0);
-        typename Op::Stage st1{}, st2{};
+        // staged data: loads issued here, used after the compaction below
+        typename Op::StageIn st1{}, st2{};
         if constexpr (Op::kStaged) {
-            if (valid) st1 = op.stage(cell1);
-            if (two) st2 = op.stage(cell2);
+            if (valid) st1 = op.stage_load(cell1);
+            if (two) st2 = op.stage_load(cell2);
         }
 
         const uint64_t b1 = __ballot(valid);
@@ -230,8 +238,8 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
             if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
             if (n_row + l < kSegs) srow[n_row + l] = make_uint2(Op::kNullKey, 0u);
             if (n_row + l + 16 < kSegs) srow[n_row + l + 16] = make_uint2(Op::kNullKey, 0u);
-            if (valid) stg[row][pos] = st1;
-            if (two) stg[row][pos + 1] = st2;
+            if (valid) stg[row][pos] = op.stage_make(st1);
+            if (two) stg[row][pos + 1] = op.stage_make(st2);
         } else {
             // null entries everywhere, then the row's segments over them (the
             // LDS executes one wavefront's writes in issue order)
@@ -308,8 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
 {
     // per wave, per row: (cell index, ds) entries, and staged step data
-    __shared__ uint4 seg[kBlock / 64][4][16];
-    __shared__ typename Op::Stage stg[Op::kStaged ? kBlock / 64 : 1][4][kSegs];
+    __shared__ uint4 seg[kBlock / 64][4][kSegRow];
+    __shared__ typename Op::Stage stg[Op::kStaged ? kBlock / 64 : 1][4][kStgRow];
     // block-wide tables of the Op (e.g. a line profile), copied once
     __shared__ float2 op_smem[Op::kSmemBytes > 0 ? Op::kSmemBytes / 8 : 2];
     if constexpr (Op::kSmemBytes > 0) {
@@ -321,14 +329,13 @@ __global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, 
     epi.init(c.l);
     up.init(c.l);
     {
-        uint4* sw = &seg[c.w][0][0];
-        sw[c.lane] = make_uint4(0u, 0u, 0u, 0u);
+        seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
         if constexpr (Op::kStaged) {
             // positions past a row's segment count are read (with zero
             // opacity): they must hold zeros or a real record, never garbage
             static_assert(sizeof(typename Op::Stage) % 16 == 0, "stage entries are written as uint4");
             uint4* gw = reinterpret_cast<uint4*>(&stg[c.w][0][0]);
-            constexpr int n16 = 4 * kSegs * (int)sizeof(typename Op::Stage) / 16;
+            constexpr int n16 = 4 * kStgRow * (int)sizeof(typename Op::Stage) / 16;
             for (int i = c.lane; i < n16; i += 64) gw[i] = make_uint4(0u, 0u, 0u, 0u);
         }
         wave_sync();
@@ -418,6 +425,7 @@ struct FieldOp {
     using Raw = float2;
     static constexpr bool kStaged = false;  // per-lane data: nothing to stage
     struct Stage {};
+    struct StageIn {};
     static constexpr int kSmemBytes = 0;
     __device__ __forceinline__ void init_shared(float2*) {}
     __device__ __forceinline__ void init(int l)

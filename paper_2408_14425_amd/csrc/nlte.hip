@@ -188,6 +188,25 @@ __global__ void k_voigt_fill_compact(float2* tab, int32_t n_a, double da)
     tab[idx] = make_float2((float)H, (float)(2.0 * (a * L - x * H) / (double)kInvDxc));
 }
 
+// Cubic Hermite at fraction t between nodes q0, q1 = {value, derivative * dxc}.
+__device__ __forceinline__ float hermite(float t, float2 q0, float2 q1)
+{
+    const float t2 = t * t;
+    const float h01 = t2 * fmaf(-2.0f, t, 3.0f);  // t^2 (3 - 2t)
+    const float h00 = 1.0f - h01;
+    const float tm1 = t - 1.0f;
+    const float h10 = t * tm1 * tm1;              // t (t - 1)^2
+    const float h11 = t2 * tm1;                   // t^2 (t - 1)
+    return fmaf(h00, q0.x, fmaf(h10, q0.y, fmaf(h01, q1.x, h11 * q1.y)));
+}
+
+// The asymptotic series of H beyond kXTab, without its factor a / sqrt(pi):
+// q (1 + 3/2 q + 15/4 q^2 + 105/8 q^3 + 945/16 q^4), q = 1 / x^2.
+__device__ __forceinline__ float voigt_wing_series(float q)
+{
+    return q * fmaf(q, fmaf(q, fmaf(q, fmaf(q, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
+}
+
 // H(a, ax) from the LDS table; fa = a / da (inside [0, n_a - 1)),
 // a_sqrtpi = a / sqrt(pi) for the asymptotic series beyond kXTab.
 __device__ __forceinline__ float voigt_compact(const float2* __restrict__ tab, float fa, float a_sqrtpi, float ax)
@@ -198,33 +217,64 @@ __device__ __forceinline__ float voigt_compact(const float2* __restrict__ tab, f
     const int ix = (int)fx;
     const float t = __builtin_amdgcn_fractf(fx);
     const float2* p = tab + ia * kNxc + ix;
-    const float2 q00 = p[0], q01 = p[1], q10 = p[kNxc], q11 = p[kNxc + 1];
-    const float t2 = t * t;
-    const float h01 = t2 * fmaf(-2.0f, t, 3.0f);       // t^2 (3 - 2t)
-    const float h00 = 1.0f - h01;
-    const float tm1 = t - 1.0f;
-    const float h10 = t * tm1 * tm1;                   // t (t - 1)^2
-    const float h11 = t2 * tm1;                        // t^2 (t - 1)
-    const float H0 = fmaf(h00, q00.x, fmaf(h10, q00.y, fmaf(h01, q01.x, h11 * q01.y)));
-    const float H1 = fmaf(h00, q10.x, fmaf(h10, q10.y, fmaf(h01, q11.x, h11 * q11.y)));
+    const float H0 = hermite(t, p[0], p[1]);
+    const float H1 = hermite(t, p[kNxc], p[kNxc + 1]);
     const float ht = fmaf(wa, H1 - H0, H0);
-    const float q = __builtin_amdgcn_rcpf(ax * ax);
-    const float ser = fmaf(q, fmaf(q, fmaf(q, fmaf(q, 59.0625f, 13.125f), 3.75f), 1.5f), 1.0f);
-    return ax < (float)kXTab ? ht : a_sqrtpi * q * ser;
+    return ax < (float)kXTab ? ht : a_sqrtpi * voigt_wing_series(__builtin_amdgcn_rcpf(ax * ax));
+}
+
+// Small damping. H is harmonic in (x, a), so about a = 0
+//   H(a, x) = e^{-x^2} (1 + a^2 (1 - 2 x^2)) - (2 a / sqrt(pi)) g(x) + R,
+//   g(x) = 1 - 2 x F(x) = F'(x), F = Dawson's function,
+// from H(0, x) = e^{-x^2}, dH/da(0, x) = -(2/sqrt(pi)) g(x) and
+// d2H/da2 = -d2H/dx2; the remainder R = (a^3/3 sqrt(pi)) g''(x) + O(a^4)
+// is below 0.76 a^3 of H(0, 0) and below about a^2 / 4 of H at any x (its
+// relative size peaks where e^{-x^2} and the a term are equal, near x = 3).
+// Used when every cell has a <= kSmallAMax (remainder below 7e-6 of H). The
+// table holds {g, g' dxc} at x_i = i dxc on [0, kXTab] (g' = -2F - 2xg);
+// beyond it g is -1/2 times the series above.
+constexpr double kSmallAMax = 5e-3;
+
+__device__ __forceinline__ float voigt_small_a(const float2* __restrict__ gtab, float a2, float ca, float ax)
+{
+    const float x2 = ax * ax;
+    const float e = __builtin_amdgcn_exp2f(-x2 * march::kLog2e);
+    const float fx = fminf(ax * kInvDxc, (float)(kNxc - 1) - 1e-3f);
+    const int ix = (int)fx;
+    const float2* p = gtab + ix;
+    const float gt = hermite(__builtin_amdgcn_fractf(fx), p[0], p[1]);
+    const float g = ax < (float)kXTab ? gt : -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2));
+    return fmaf(e, fmaf(a2, fmaf(-2.0f, x2, 1.0f), 1.0f), -ca * g);
+}
+
+__global__ void k_dawson_fill(float2* tab)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNxc) return;
+    const double x = i / (double)kInvDxc;
+    double H, L;
+    voigt_fourier2(0.0, x, H, L);  // L(0, x) = (2 / sqrt(pi)) F(x)
+    const double F = 0.5 * sqrt(kPi) * L;
+    const double g = 1.0 - 2.0 * x * F;
+    tab[i] = make_float2((float)g, (float)((-2.0 * F - 2.0 * x * g) / (double)kInvDxc));
 }
 
 // The march's profile at arbitrary (a, x), for checking the compact table.
 __global__ __launch_bounds__(256) void k_voigt_eval_compact(const float2* __restrict__ tabc, int32_t n_a, float inv_da,
-                                                            float da_sqrtpi, int32_t n, const float* a, const float* x,
-                                                            float* out)
+                                                            float da_sqrtpi, int32_t small_a, int32_t n, const float* a,
+                                                            const float* x, float* out)
 {
     __shared__ float2 tab[kNacMax * kNxc];
     for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) tab[i] = tabc[i];
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        const float fa = fminf(a[i] * inv_da, (float)(n_a - 1) - 1e-3f);
-        out[i] = voigt_compact(tab, fa, fa * da_sqrtpi, fabsf(x[i]));
+        if (small_a) {
+            out[i] = voigt_small_a(tab, a[i] * a[i], (float)(2.0 / sqrt(kPi)) * a[i], fabsf(x[i]));
+        } else {
+            const float fa = fminf(a[i] * inv_da, (float)(n_a - 1) - 1e-3f);
+            out[i] = voigt_compact(tab, fa, fa * da_sqrtpi, fabsf(x[i]));
+        }
     }
 }
 
@@ -423,29 +473,34 @@ __global__ void k_zero_u32n(unsigned int* p, int32_t n)
 // ------------------------------------------------------------ line march op
 // Opacity of a line batch at one ray step: x = (u_l + w . v) / v_th (the
 // profile of a ray looking along w, photons travelling along -w, in the
-// observer's frame), chi = kappa H(a, |x|), S = S_line.
-struct LineOp {
+// observer's frame), chi = kappa H(a, |x|), S = S_line. kSmallA selects the
+// profile: the expansion in a (voigt_small_a, record z = a) or the compact
+// table in (a, x) (voigt_compact, record z = a / da).
+template <bool kSmallA>
+struct LineOpT {
     const float4* rec;  // [ncell]
     const float2* vel;  // [ncell]
-    const float2* tabc; // compact profile table [n_a][kNxc] (global; copied to LDS)
+    const float2* tabc; // profile table [n_a][kNxc] (global; copied to LDS)
     int32_t n_a;
     const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
     uint32_t ncell;
     float da_sqrtpi;    // damping step of the table / sqrt(pi)
     float u, wx, wz;
     const float2* tab;  // the LDS copy
-    struct Raw {
-        float4 r;
-        float2 v;
-    };
-    // the cell record and velocity are the same for all wavelength lanes
+    // the cell record and velocity are the same for all wavelength lanes;
+    // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)}
     static constexpr bool kStaged = true;
     struct Stage {
         float4 r;
         float2 v;
-        float2 pad;
+        float2 p;
     };
-    static constexpr int kSmemBytes = kCompactBytes;
+    using Raw = Stage;
+    struct StageIn {
+        float4 r;
+        float2 v;
+    };
+    static constexpr int kSmemBytes = kSmallA ? kNxc * 8 : kCompactBytes;
     __device__ __forceinline__ void init_shared(float2* smem)
     {
         for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) smem[i] = tabc[i];
@@ -455,20 +510,20 @@ struct LineOp {
     // record); a null entry has ds = 0
     static constexpr uint32_t kNullKey = 0u;
     __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell; }
-    __device__ __forceinline__ Stage stage(uint32_t cell) const
+    __device__ __forceinline__ StageIn stage_load(uint32_t cell) const { return StageIn{rec[cell], vel[cell]}; }
+    __device__ __forceinline__ Stage stage_make(const StageIn& in) const
     {
         Stage st;
-        st.r = rec[cell];
-        st.v = vel[cell];
-        st.pad = make_float2(0.0f, 0.0f);
+        st.r = in.r;
+        st.v = in.v;
+        st.p = kSmallA ? make_float2(in.r.z * in.r.z, (float)(2.0 / sqrt(kPi)) * in.r.z) : make_float2(0.0f, 0.0f);
         return st;
     }
     // positions past the row's segment count: no opacity
     __device__ __forceinline__ void from_stage(const Stage& st, bool ok, Raw& raw) const
     {
-        raw.r = st.r;
+        raw = st;
         raw.r.x = ok ? st.r.x : 0.0f;
-        raw.v = st.v;
     }
     __device__ __forceinline__ void init(int l) { u = u_b[l]; }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
@@ -476,18 +531,24 @@ struct LineOp {
         wx = (float)dwx;
         wz = (float)dwz;
     }
-    // H(a, |x|), x = (u + w . v) / v_th; the record holds a in table units
-    // (always inside the table)
+    // H(a, |x|), x = (u + w . v) / v_th, from a record and a velocity
     __device__ __forceinline__ float profile(const float4& r, const float2& v) const
     {
         const float ax = fabsf((u + wx * v.x + wz * v.y) * r.w);
+        if constexpr (kSmallA) return voigt_small_a(tab, r.z * r.z, (float)(2.0 / sqrt(kPi)) * r.z, ax);
         return voigt_compact(tab, r.z, r.z * da_sqrtpi, ax);
     }
     __device__ __forceinline__ float2 resolve(const Raw& raw) const
     {
+        if constexpr (kSmallA) {
+            const float ax = fabsf((u + wx * raw.v.x + wz * raw.v.y) * raw.r.w);
+            return make_float2(raw.r.x * voigt_small_a(tab, raw.p.x, raw.p.y, ax), raw.r.y);
+        }
         return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);
     }
 };
+using LineOp = LineOpT<false>;
+using LineOpSmallA = LineOpT<true>;
 
 // ----------------------------------------------------------- rate epilogue
 // At cascade 0 every wavefront holds the 4 directions (rows) x 16
@@ -552,8 +613,9 @@ struct RatesEpi {
         if (lane == 0 && ri.active) part[cell] = make_float2(up, dn);
     }
 
-    // H at the cell itself along the ray (only a LineOp has a profile).
-    __device__ __forceinline__ float line_profile(const LineOp& op, uint32_t cell) const
+    // H at the cell itself along the ray (only a line op has a profile).
+    template <bool K>
+    __device__ __forceinline__ float line_profile(const LineOpT<K>& op, uint32_t cell) const
     {
         return op.profile(op.rec[cell], op.vel[cell]);
     }
@@ -772,9 +834,10 @@ struct rcx_nlte {
     unsigned int* d_amax = nullptr;
     float2* vtab = nullptr;
     float v_inv_da = 0.0f;
-    float2* vtabc = nullptr;  // compact table of the march
-    int32_t n_ac = 2;
+    float2* vtabc = nullptr;  // profile table of the line march
+    int32_t n_ac = 2;         // its damping rows (1 with small_a)
     double da_c = 1.0;
+    bool small_a = false;     // every a <= kSmallAMax: expansion in a
     bool atm_set = false;
     float* u_all = nullptr;    // [n_wave]
     float* dnu_all = nullptr;  // [n_wave]
@@ -825,10 +888,22 @@ hipError_t launch_level(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op
 // (store FP32 / FP16, or the cascade-0 rates) and the reader of the cascade
 // above (FP32 or FP16).
 template <class Epi, class Up>
-hipError_t launch_level_op(int32_t kind, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
+hipError_t launch_level_op(int32_t kind, bool small_a, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
                            const march::FieldOp& fop, const Epi& epi, const double4* dirs, const Up& up, hipStream_t st)
 {
-    return kind == 0 ? launch_level(L, nx, nz, lop, epi, dirs, up, st) : launch_level(L, nx, nz, fop, epi, dirs, up, st);
+    if (kind != 0) return launch_level(L, nx, nz, fop, epi, dirs, up, st);
+    if (small_a) {
+        LineOpSmallA sop{};
+        sop.rec = lop.rec;
+        sop.vel = lop.vel;
+        sop.tabc = lop.tabc;
+        sop.n_a = lop.n_a;
+        sop.u_b = lop.u_b;
+        sop.ncell = lop.ncell;
+        sop.da_sqrtpi = lop.da_sqrtpi;
+        return launch_level(L, nx, nz, sop, epi, dirs, up, st);
+    }
+    return launch_level(L, nx, nz, lop, epi, dirs, up, st);
 }
 
 template <int NL>
@@ -1067,12 +1142,20 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     hipLaunchKernelGGL(k_voigt_fill, dim3(blocks_for((int64_t)kNa * kNx, 128)), dim3(128), 0, st, s->vtab, da,
                        kXTab / (kNx - 1));
     RCX_HIP_TRY(hipGetLastError());
-    // compact table: a step of at most 2e-3 (linear-in-a error below 1e-6),
-    // at most kNacMax nodes
-    s->n_ac = (int32_t)std::min<double>(kNacMax, std::max(2.0, std::ceil(a_top / 2e-3) + 1.0));
-    s->da_c = a_top / (s->n_ac - 1);
-    hipLaunchKernelGGL(k_voigt_fill_compact, dim3(blocks_for((int64_t)s->n_ac * kNxc, 64)), dim3(64), 0, st, s->vtabc,
-                       s->n_ac, s->da_c);
+    s->small_a = a_top <= kSmallAMax;
+    if (s->small_a) {
+        // the expansion in a: one row, g(x) = 1 - 2x F(x) and g'
+        s->n_ac = 1;
+        s->da_c = 1.0;
+        hipLaunchKernelGGL(k_dawson_fill, dim3(blocks_for(kNxc, 64)), dim3(64), 0, st, s->vtabc);
+    } else {
+        // compact table: a step of at most 2e-3 (linear-in-a error below
+        // 1e-6), at most kNacMax nodes
+        s->n_ac = (int32_t)std::min<double>(kNacMax, std::max(2.0, std::ceil(a_top / 2e-3) + 1.0));
+        s->da_c = a_top / (s->n_ac - 1);
+        hipLaunchKernelGGL(k_voigt_fill_compact, dim3(blocks_for((int64_t)s->n_ac * kNxc, 64)), dim3(64), 0, st,
+                           s->vtabc, s->n_ac, s->da_c);
+    }
     RCX_HIP_TRY(hipGetLastError());
     s->atm_set = true;
     return RCX_OK;
@@ -1092,8 +1175,9 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
     const int32_t nx = P->grid.nx, nz = P->grid.nz;
     const int64_t nc = s->ncell;
     const AtomDev& A = s->atom;
+    // record z: a itself for the expansion, a / da on the compact table
     SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel,
-                 (float)(1.0 / s->da_c), s->n_ac};
+                 s->small_a ? 1.0f : (float)(1.0 / s->da_c), s->small_a ? (1 << 24) : s->n_ac};
     hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
     RCX_HIP_TRY(hipGetLastError());
     const int32_t nb = (int32_t)s->batches.size();
@@ -1166,19 +1250,19 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
                 // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
                 const march::UpF16 u16{(const __half*)upl, isc_b, 0.0f};
                 if (i > 0) {
-                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, march::StoreF16Epi{(__half*)outb, sc_b, 0.0f},
+                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, march::StoreF16Epi{(__half*)outb, sc_b, 0.0f},
                                         dirs, u16, st);
                 } else {
                     re.out = outb;
-                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, re, dirs, u16, st);
+                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, re, dirs, u16, st);
                 }
             } else {
                 const march::UpF32 u32{(const float*)upl};
                 if (i > 0) {
-                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, march::StoreEpi{outb}, dirs, u32, st);
+                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, march::StoreEpi{outb}, dirs, u32, st);
                 } else {
                     re.out = outb;
-                    e = launch_level_op(tr.kind, L, nx, nz, lop, fop, re, dirs, u32, st);
+                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, re, dirs, u32, st);
                 }
             }
             RCX_HIP_TRY(e);
@@ -1269,7 +1353,7 @@ int32_t rcx_nlte_voigt_eval_march(rcx_nlte* s, int32_t n, const float* a, const 
     if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_voigt_eval_march: set the atmosphere first");
     if (n == 0) return RCX_OK;
     hipLaunchKernelGGL(k_voigt_eval_compact, dim3(blocks_for(n, 256)), dim3(256), 0, st, s->vtabc, s->n_ac,
-                       (float)(1.0 / s->da_c), (float)(s->da_c / std::sqrt(kPi)), n, a, x, out);
+                       (float)(1.0 / s->da_c), (float)(s->da_c / std::sqrt(kPi)), (int32_t)s->small_a, n, a, x, out);
     RCX_HIP_TRY(hipGetLastError());
     return RCX_OK;
 }
