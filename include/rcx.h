@@ -280,16 +280,31 @@ int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops_inout,
 int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, double tol,
                          int32_t* iters_host, double* last_change_host, hipStream_t stream);
 
+/* Line profile of the march (the Voigt function H(a, x) of Sec. 4.1's line
+ * opacity), chosen at rcx_nlte_set_atmosphere:
+ *   RCX_PROFILE_AUTO   the expansion about a = 0 when every cell has damping
+ *                      a <= 5e-3 (H = e^{-x^2} (1 + a^2 (1 - 2x^2))
+ *                      - (2a/sqrt(pi)) (1 - 2x F(x)), F Dawson's function
+ *                      from a one-row LDS table; relative error below 7e-6),
+ *                      else the compact table;
+ *   RCX_PROFILE_TABLE  always the compact (a, x) table.
+ * Takes effect at the next rcx_nlte_set_atmosphere. RCX_E_INVALID for
+ * another mode. */
+#define RCX_PROFILE_AUTO 0
+#define RCX_PROFILE_TABLE 1
+int32_t rcx_nlte_set_line_profile(rcx_nlte* s, int32_t mode);
+
 /* Evaluate the device Voigt table (bilinear in (a, |x|), asymptotic series
  * beyond its x range) at n points: a, x, out device float32 arrays. For
  * checking the table against a reference. */
 int32_t rcx_nlte_voigt_eval(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out,
                             hipStream_t stream);
-/* The same for the profile the line march uses: a compact table (cubic
- * Hermite in x on [0, 8] at spacing 1/32, linear in a on at most 9 nodes
- * over the atmosphere's damping range, filled in FP64 from the Fourier
- * integrals of H and of the Faraday-Voigt function) that every march
- * workgroup copies into LDS, and the same asymptotic series beyond x = 8.
+/* The same for the profile the line march uses (rcx_nlte_set_line_profile):
+ * the expansion about a = 0, or the compact table (cubic Hermite in x on
+ * [0, 8] at spacing 1/32, linear in a on at most 9 nodes over the
+ * atmosphere's damping range, filled in FP64 from the Fourier integrals of
+ * H and of the Faraday-Voigt function); every march workgroup copies its
+ * table into LDS; the same asymptotic series beyond x = 8. With the table,
  * a is clamped to the atmosphere's damping range. */
 int32_t rcx_nlte_voigt_eval_march(rcx_nlte* s, int32_t n, const float* a, const float* x, float* out,
                                   hipStream_t stream);

@@ -838,6 +838,7 @@ struct rcx_nlte {
     int32_t n_ac = 2;         // its damping rows (1 with small_a)
     double da_c = 1.0;
     bool small_a = false;     // every a <= kSmallAMax: expansion in a
+    int32_t profile_mode = RCX_PROFILE_AUTO;
     bool atm_set = false;
     float* u_all = nullptr;    // [n_wave]
     float* dnu_all = nullptr;  // [n_wave]
@@ -1115,6 +1116,15 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     return RCX_OK;
 }
 
+int32_t rcx_nlte_set_line_profile(rcx_nlte* s, int32_t mode)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_line_profile: null solver");
+    if (mode != RCX_PROFILE_AUTO && mode != RCX_PROFILE_TABLE)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_line_profile: mode must be RCX_PROFILE_AUTO or RCX_PROFILE_TABLE");
+    s->profile_mode = mode;
+    return RCX_OK;
+}
+
 int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, const double* ntot, const float* vel,
                                 hipStream_t st)
 {
@@ -1142,7 +1152,7 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     hipLaunchKernelGGL(k_voigt_fill, dim3(blocks_for((int64_t)kNa * kNx, 128)), dim3(128), 0, st, s->vtab, da,
                        kXTab / (kNx - 1));
     RCX_HIP_TRY(hipGetLastError());
-    s->small_a = a_top <= kSmallAMax;
+    s->small_a = s->profile_mode == RCX_PROFILE_AUTO && a_top <= kSmallAMax;
     if (s->small_a) {
         // the expansion in a: one row, g(x) = 1 - 2x F(x) and g'
         s->n_ac = 1;

@@ -26,6 +26,8 @@ RCX_T_GEOMETRIC = 0
 RCX_T_LENGTH_X4 = 1
 RCX_STORE_F32 = 0
 RCX_STORE_F16_SCALED = 1
+RCX_PROFILE_AUTO = 0
+RCX_PROFILE_TABLE = 1
 
 
 class rcx_grid(C.Structure):
@@ -270,6 +272,7 @@ def _load_nlte():
     L.rcx_nlte_create.argtypes = [C.POINTER(rcx_grid), C.POINTER(rcx_params), C.POINTER(rcx_atom), i32,
                                   vp, vp, vp, C.POINTER(vp)]
     L.rcx_nlte_set_atmosphere.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.rcx_nlte_set_line_profile.argtypes = [vp, i32]
     L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
     L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -301,6 +304,10 @@ def rcx_nlte_create(grid: rcx_grid, params: rcx_params, atom: rcx_atom, lambda_n
     _check(_load_nlte().rcx_nlte_create(C.byref(grid), C.byref(params), C.byref(atom), len(lam), lam.ctypes.data,
                                         tr.ctypes.data, dn.ctypes.data, C.byref(h)), "rcx_nlte_create")
     return h.value
+
+
+def rcx_nlte_set_line_profile(s: int, mode: int) -> int:
+    return _check(_load_nlte().rcx_nlte_set_line_profile(s, int(mode)), "rcx_nlte_set_line_profile")
 
 
 def rcx_nlte_set_atmosphere(s: int, T, ne, ntot, vel, stream=None) -> int:
@@ -358,7 +365,8 @@ class Nlte:
     """Owns an ``rcx_nlte`` solver for one non-LTE problem (a
     ``workloads.NlteInput``); arrays live on ``cuda:0``."""
 
-    def __init__(self, inp, n_cascades: int = 0, storage: int = RCX_STORE_F32):
+    def __init__(self, inp, n_cascades: int = 0, storage: int = RCX_STORE_F32,
+                 line_profile: int = RCX_PROFILE_AUTO):
         import torch
         p = rcx_params_default()
         p.n_cascades = n_cascades
@@ -366,6 +374,7 @@ class Nlte:
         self.inp = inp
         self.handle = rcx_nlte_create(rcx_grid(inp.nx, inp.nz, inp.voxel), p, atom_from_dict(inp.atom),
                                       inp.lambda_nm, inp.trans, inp.dnu)
+        rcx_nlte_set_line_profile(self.handle, line_profile)
         self.n_levels, self.n_trans = rcx_nlte_dims(self.handle)
         dev = torch.device("cuda:0")
         self.T = torch.from_numpy(inp.T.astype("float64")).to(dev)

@@ -59,6 +59,8 @@ def test_null_arguments_are_rejected():
     assert L.rcx_formal_solve(None, 1, None, None, None, None, 0, None) == rcx.RCX_E_INVALID
     assert L.rcx_plan_destroy(None) == rcx.RCX_OK
     assert L.rcx_params_default(None) == rcx.RCX_E_INVALID
+    rcx._load_nlte()
+    assert L.rcx_nlte_set_line_profile(None, rcx.RCX_PROFILE_AUTO) == rcx.RCX_E_INVALID
 
 
 def _nlte_args():

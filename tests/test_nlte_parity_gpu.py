@@ -26,10 +26,15 @@ def case32():
     return inp, nlte.Problem(inp)
 
 
-def _solver(inp):
+def _solver(inp, line_profile=0):
     from paper_2408_14425_amd import rcx
-    print(f"[gpu] nlte solver {inp.name}", flush=True)
-    return rcx.Nlte(inp)
+    print(f"[gpu] nlte solver {inp.name} profile {line_profile}", flush=True)
+    return rcx.Nlte(inp, line_profile=line_profile)
+
+
+# the line march's profile: the expansion about a = 0 (chosen automatically
+# for this atmosphere's small damping) and the compact (a, x) table
+PROFILES = [pytest.param(0, id="auto"), pytest.param(1, id="table")]
 
 
 def test_voigt_table_matches_reference(case32):
@@ -49,14 +54,17 @@ def test_voigt_table_matches_reference(case32):
     assert rel.max() < 5e-5
 
 
-def test_march_profile_table_matches_reference(case32):
-    """The compact LDS table of the line march (Hermite in x, linear in a)
-    against the oracle's Voigt function over the atmosphere's damping range,
-    in the core and across the table/series boundary at x = 8."""
+@pytest.mark.parametrize("profile", PROFILES)
+def test_march_profile_table_matches_reference(case32, profile):
+    """The line march's profile (the expansion about a = 0 with Dawson's
+    function from its LDS table, or the compact LDS table, Hermite in x and
+    linear in a) against the oracle's Voigt function over the atmosphere's
+    damping range, in the core and across the table/series boundary at
+    x = 8."""
     torch = _torch()
     from oracle import nlte
     inp, P = case32
-    s = _solver(inp)
+    s = _solver(inp, profile)
     rng = np.random.default_rng(2)
     a = rng.uniform(0, P.adamp.max(), 200000)
     x = np.concatenate([rng.uniform(0, 8, 100000), rng.uniform(7.9, 40, 100000)])
@@ -102,10 +110,11 @@ def test_formal_solve_J_and_first_update(case32):
     assert abs(ch / cho - 1) < 1e-3
 
 
-def test_three_iterations(case32):
+@pytest.mark.parametrize("profile", PROFILES)
+def test_three_iterations(case32, profile):
     _torch()
     inp, P = case32
-    s = _solver(inp)
+    s = _solver(inp, profile)
     pops = s.lte()
     rc, it, ch = s.iterate(pops, 3, 0.0)
     pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
