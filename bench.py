@@ -5,8 +5,8 @@ medium (seed 2): prep, every cascade's fused march + merge, J. Inputs are
 resident in HBM before the timed region. The same line also reports the
 FP16-storage variant of that solve and the seconds per converged non-LTE
 solve (1024 x 1024, 160 wavelengths, max relative change < 1e-3) from the
-LTE start with FP32 and FP16 cascade storage, and from the learned warm
-start when a trained network is present. Prints one JSON line.
+LTE start with FP32 cascade storage and from the learned warm start with
+FP16 storage (when a trained network is present). Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-nlte]
 """
@@ -24,12 +24,14 @@ if ROOT not in sys.path:
 
 METRIC = "ray-intervals/s + s per converged non-LTE solve, plain vs learned/FP16"
 HBM_PEAK_GBS = 8000.0
-# Vector lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# (78.6 TFLOP/s of unpacked FP32 FMA). The march needs about 8 lane-op slots
-# per cell step and wavelength (optical depth, exp2 at quarter rate, 1 - e,
-# the I update, the transmission update).
+# Vector ALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12
+# lane operations per second (78.6 TFLOP/s of unpacked FP32 FMA; the 157.3
+# TFLOP/s figure counts two-wide packed FMAs, which this code does not use).
 VALU_LANE_OPS = 39.3e12
-VALU_OPS_PER_STEP = 8
+# Algorithmic VALU operations per cell step and wavelength of the march:
+# optical depth y = kappa ds, e = 2^-y, 1 - e, T S, I += T S (1 - e),
+# T *= e.
+ALU_OPS_PER_STEP = 6
 # Algorithmic bytes per cell step and wavelength: chi and S, FP32 each.
 BYTES_PER_STEP = 8
 
@@ -329,8 +331,14 @@ def main():
     value = rays / (dt / args.steps)
     march_ms = sum(ms_level)
     avg_launch_s = march_ms / 1e3 / max(n_launch, 1)
-    bytes_per_launch = algorithmic_bytes(work, inp.n_wave) / max(n_launch // max(n_solves, 1), 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9
+    launches_per_solve = max(n_launch // max(n_solves, 1), 1)
+    # ALU roofline (the bound the counters show): algorithmic lane operations
+    # per launch over the average launch duration
+    ops_per_launch = work.cell_steps * inp.n_wave * ALU_OPS_PER_STEP / launches_per_solve
+    alu_achieved = ops_per_launch / avg_launch_s / 1e12
+    # the cacheless byte count and the measured HBM traffic, for comparison
+    bytes_per_launch = algorithmic_bytes(work, inp.n_wave) / launches_per_solve
+    traffic = measured_traffic("k_march_rows_line1024_w64.md")
     out = {
         "metric": METRIC,
         "value": value,
@@ -358,15 +366,18 @@ def main():
         },
         "fp16_storage": fp16,
         "roofline": {
-            "bound": "hbm",
+            "bound": "alu",
             "kernel": "k_march_rows",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_march_rows_line1024_w64.md"),
+            "achieved": alu_achieved,
+            "peak": VALU_LANE_OPS / 1e12,
+            "unit": "T VALU lane-ops/s",
+            "frac": alu_achieved / (VALU_LANE_OPS / 1e12),
+            "ops_per_cell_step": ALU_OPS_PER_STEP,
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "valu_frac": work.cell_steps * inp.n_wave * VALU_OPS_PER_STEP / (dt / args.steps) / VALU_LANE_OPS,
+            "hbm_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
+            "hbm_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "cacheless_bytes_GBs": bytes_per_launch / avg_launch_s / 1e9,
         },
     }
     if not args.no_nlte:
