@@ -159,42 +159,66 @@ hipError_t launch_scales(int32_t n, const unsigned int* smax_bits, float* scale,
 }
 
 namespace {
-template <class Epi, class Up>
-hipError_t launch_fs(const LevelDesc& L, int32_t nx, int32_t nz, const march::FieldOp& op, const Epi& epi,
-                     const double4* dirs, const Up& up, hipStream_t st)
+template <class Op, class Epi, class Up>
+hipError_t launch_fs(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+                     const Up& up, hipStream_t st)
 {
     const int64_t total = level_launch_rays(L);
-    hipLaunchKernelGGL((march::k_march_rows<march::FieldOp, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L,
-                       nx, nz, op, epi, dirs, up, total);
+    hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
+                       dirs, up, total);
     return hipGetLastError();
+}
+
+// The reader of the cascade above, then the launch with it.
+template <class Op, class Epi>
+hipError_t launch_fs_up(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi,
+                        const double4* dirs, const CascIO& io, hipStream_t st)
+{
+    if (!io.up_f16) {
+        march::UpF32 up{(const float*)io.up};
+        up.stride = io.slot_stride;
+        return launch_fs(L, nx, nz, op, epi, dirs, up, st);
+    }
+    march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+    up.stride = io.slot_stride;
+    return launch_fs(L, nx, nz, op, epi, dirs, up, st);
 }
 }  // namespace
 
 hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                               const CascIO& io, hipStream_t st)
 {
+    const uint32_t fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    if (io.slot_stride != 0) {
+        march::FieldOp2 op{};
+        op.Fb = Fb;
+        op.fb_bytes = fb_bytes;
+        if (!io.out_f16) return launch_fs_up(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, io, st);
+        return launch_fs_up(L, nx, nz, op, march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f},
+                            dirs, io, st);
+    }
     march::FieldOp op{};
     op.Fb = Fb;
-    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
-    if (!io.up_f16) {
-        const march::UpF32 up{(const float*)io.up};
-        if (!io.out_f16) return launch_fs(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
-        return launch_fs(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
-    }
-    const march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
-    if (!io.out_f16) return launch_fs(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
-    return launch_fs(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
+    op.fb_bytes = fb_bytes;
+    if (!io.out_f16) return launch_fs_up(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, io, st);
+    return launch_fs_up(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, io, st);
 }
 
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
-                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, hipStream_t st)
+                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
+                                hipStream_t st)
 {
+    const uint32_t fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    if (io.slot_stride != 0) {
+        march::FieldOp2 op{};
+        op.Fb = Fb;
+        op.fb_bytes = fb_bytes;
+        return launch_fs_up(L, nx, nz, op, march::JEpi2{J, lam0, n_valid, n_valid1, (int64_t)nx * nz}, dirs, io, st);
+    }
     march::FieldOp op{};
     op.Fb = Fb;
-    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
-    const march::JEpi epi{J, lam0, n_valid, (int64_t)nx * nz};
-    if (!io.up_f16) return launch_fs(L, nx, nz, op, epi, dirs, march::UpF32{(const float*)io.up}, st);
-    return launch_fs(L, nx, nz, op, epi, dirs, march::UpF16{(const __half*)io.up, io.inv_scale_b, 0.0f}, st);
+    op.fb_bytes = fb_bytes;
+    return launch_fs_up(L, nx, nz, op, march::JEpi{J, lam0, n_valid, (int64_t)nx * nz}, dirs, io, st);
 }
 
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,

@@ -72,18 +72,30 @@ struct RayInfo {
 };
 
 // Readers of the merged cascade above: FP32, or FP16 with a per-wavelength
-// power-of-two scale (value = stored * inv_scale).
+// power-of-two scale (value = stored * inv_scale). Slot w = 1 (a second
+// wavelength batch marched by the same lanes) lies `stride` elements after
+// slot 0, with the next batch's scales.
 struct UpF32 {
     const float* p;
+    int64_t stride = 0;
     __device__ __forceinline__ void init(int) {}
-    __device__ __forceinline__ float get(int64_t i) const { return p[i]; }
+    __device__ __forceinline__ float get(int64_t i, int w) const { return p[i + w * stride]; }
 };
 struct UpF16 {
     const __half* p;
-    const float* inv_scale_b;  // [16] of this batch
+    const float* inv_scale_b;  // [16] of this batch (then [16] of the next when stride != 0)
     float inv;
-    __device__ __forceinline__ void init(int l) { inv = inv_scale_b[l]; }
-    __device__ __forceinline__ float get(int64_t i) const { return __half2float(p[i]) * inv; }
+    int64_t stride = 0;
+    float inv2 = 0.0f;
+    __device__ __forceinline__ void init(int l)
+    {
+        inv = inv_scale_b[l];
+        if (stride != 0) inv2 = inv_scale_b[l + kLB];
+    }
+    __device__ __forceinline__ float get(int64_t i, int w) const
+    {
+        return __half2float(p[i + w * stride]) * (w ? inv2 : inv);
+    }
 };
 
 // Lane state shared by the kernels that march rows of rays.
@@ -180,7 +192,16 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
     im0 = min(max(im0, 0), nm - 1);
     const int mfirst = wm > 0.0 ? im0 + 1 : im0;  // first m-plane crossed
 
-    float I = 0.0f, T = 1.0f;
+    // kW wavelength batches per lane (slot w of lane l is wavelength l of
+    // batch w): the walk and the segment list serve all of them
+    constexpr int W = Op::kW;
+    static_assert(!Op::kStaged || W == 1, "staged ops march one batch");
+    float I[W], T[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        I[w] = 0.0f;
+        T[w] = 1.0f;
+    }
     const int max_chunks = (nm + 2 + 15) / 16 + 1;
     // Minor-axis cell of a crossing at pn: floor(pn) if sn > 0, else
     // ceil(pn) - 1 = ~floor(-pn); both as floor(sn * pn) ^ nflip (sn * pn is
@@ -263,7 +284,7 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
 #pragma unroll
                 for (int q = 0; q < 4; ++q) op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I, T);
+                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I[0], T[0]);
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a
@@ -276,11 +297,13 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
                 const uint32_t cells[4] = {e01.x, e01.z, e23.x, e23.z};
                 const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
                                       __uint_as_float(e23.w)};
-                typename Op::Raw raw[4];
+                typename Op::Raw raw[4][W];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) op.fetch_key(cells[q], raw[q]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I, T);
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int w = 0; w < W; ++w) step(op.resolve(raw[q][w]), dsv[q], I[w], T[w]);
             }
         }
         wave_sync();
@@ -297,18 +320,29 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         const int tzs[2] = {min(max(bz0, 0), L.qz - 1), min(max(bz0 + 1, 0), L.qz - 1)};
         const float wxs[2] = {1.0f - fx, fx};
         const float wzs[2] = {1.0f - fz, fz};
-        float far = 0.0f;
+        float far[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) far[w] = 0.0f;
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int bb = 0; bb < 2; ++bb) {
                 const int64_t bi = (((int64_t)tzs[a] * L.qx + txs[bb]) * L.nd_up + 4 * (int64_t)ri.k) * kLB + l;
-                const float c4 = up.get(bi) + up.get(bi + kLB) + up.get(bi + 2 * kLB) + up.get(bi + 3 * kLB);
-                far = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far);
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const float c4 =
+                        up.get(bi, w) + up.get(bi + kLB, w) + up.get(bi + 2 * kLB, w) + up.get(bi + 3 * kLB, w);
+                    far[w] = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far[w]);
+                }
             }
-        I = fmaf(T, far, I);
+#pragma unroll
+        for (int w = 0; w < W; ++w) I[w] = fmaf(T[w], far[w], I[w]);
     }
-    epi.finish(ri, l, lane, I, op);
+    if constexpr (W == 1) {
+        epi.finish(ri, l, lane, I[0], op);
+    } else {
+        epi.finish2(ri, l, lane, I, op);
+    }
 }
 
 template <class Op, class Epi, class Up>
@@ -423,6 +457,7 @@ struct FieldOp {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t lane_off;
     using Raw = float2;
+    static constexpr int kW = 1;
     static constexpr bool kStaged = false;  // per-lane data: nothing to stage
     struct Stage {};
     struct StageIn {};
@@ -438,11 +473,97 @@ struct FieldOp {
     // below 2^28); the null key lies beyond every buffer and reads zeros
     static constexpr uint32_t kNullKey = 0x80000000u;
     __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell * (uint32_t)(kLB * 8); }
-    __device__ __forceinline__ void fetch_key(uint32_t k, Raw& r) const
+    __device__ __forceinline__ void fetch_key(uint32_t k, Raw (&r)[kW]) const
     {
-        r = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, k + lane_off, 0, 0));
+        r[0] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, k + lane_off, 0, 0));
     }
     __device__ __forceinline__ float2 resolve(const Raw& r) const { return r; }
+};
+
+// Two consecutive batches of the same field layout per lane (Fb and
+// Fb + ncell * 16): one segment list, one key, two buffer loads.
+struct FieldOp2 {
+    const float2* Fb;
+    uint32_t fb_bytes;  // bytes of one batch
+    __amdgpu_buffer_rsrc_t rsrc0, rsrc1;
+    uint32_t lane_off;
+    using Raw = float2;
+    static constexpr int kW = 2;
+    static constexpr bool kStaged = false;
+    struct Stage {};
+    struct StageIn {};
+    static constexpr int kSmemBytes = 0;
+    __device__ __forceinline__ void init_shared(float2*) {}
+    __device__ __forceinline__ void init(int l)
+    {
+        rsrc0 = __builtin_amdgcn_make_buffer_rsrc((void*)Fb, 0, (int)fb_bytes, 0x00020000);
+        rsrc1 = __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)Fb + fb_bytes), 0, (int)fb_bytes, 0x00020000);
+        lane_off = (uint32_t)l * 8u;
+    }
+    __device__ __forceinline__ void begin_ray(double, double) {}
+    static constexpr uint32_t kNullKey = 0x80000000u;
+    __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell * (uint32_t)(kLB * 8); }
+    __device__ __forceinline__ void fetch_key(uint32_t k, Raw (&r)[kW]) const
+    {
+        r[0] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc0, k + lane_off, 0, 0));
+        r[1] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc1, k + lane_off, 0, 0));
+    }
+    __device__ __forceinline__ float2 resolve(const Raw& r) const { return r; }
+};
+
+// Epilogues for two batches per lane: slot 1 is stored `stride` elements
+// after slot 0 (FP16 with the next batch's scales).
+struct StoreEpi2 {
+    float* out;
+    int64_t stride;
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
+    {
+        if (ri.active) {
+            out[ri.ray * kLB + l] = I[0];
+            out[stride + ri.ray * kLB + l] = I[1];
+        }
+    }
+};
+struct StoreF16Epi2 {
+    __half* out;
+    int64_t stride;
+    const float* scale_b;  // [32]: this batch's scales, then the next batch's
+    float sc0, sc1;
+    __device__ __forceinline__ void init(int l)
+    {
+        sc0 = scale_b[l];
+        sc1 = scale_b[l + kLB];
+    }
+    template <class Op>
+    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
+    {
+        if (ri.active) {
+            out[ri.ray * kLB + l] = __float2half_rn(I[0] * sc0);
+            out[stride + ri.ray * kLB + l] = __float2half_rn(I[1] * sc1);
+        }
+    }
+};
+// Cascade 0 with N_0 = 4: J of both batches (rows lam0 + l and
+// lam0 + 16 + l, for l below each batch's valid count).
+struct JEpi2 {
+    float* J;
+    int32_t lam0, n_valid0, n_valid1;
+    int64_t ncell;
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int lane, const float (&I)[2], const Op&)
+    {
+        float s0 = I[0] + __shfl_xor(I[0], 16);
+        float s1 = I[1] + __shfl_xor(I[1], 16);
+        s0 += __shfl_xor(s0, 32);
+        s1 += __shfl_xor(s1, 32);
+        if (ri.active && (lane >> 4) == 0) {
+            if (l < n_valid0) J[(int64_t)(lam0 + l) * ncell + ri.ray / 4] = 0.25f * s0;
+            if (l < n_valid1) J[(int64_t)(lam0 + kLB + l) * ncell + ri.ray / 4] = 0.25f * s1;
+        }
+    }
 };
 
 }  // namespace march

@@ -488,7 +488,9 @@ struct LineOpT {
     float u, wx, wz;
     const float2* tab;  // the LDS copy
     // the cell record and velocity are the same for all wavelength lanes;
-    // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)}
+    // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)} and holds
+    // (w . v) / v_th in place of the velocity's x component
+    static constexpr int kW = 1;
     static constexpr bool kStaged = true;
     struct Stage {
         float4 r;
@@ -517,6 +519,7 @@ struct LineOpT {
         st.r = in.r;
         st.v = in.v;
         st.p = kSmallA ? make_float2(in.r.z * in.r.z, (float)(2.0 / sqrt(kPi)) * in.r.z) : make_float2(0.0f, 0.0f);
+        if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
         return st;
     }
     // positions past the row's segment count: no opacity
@@ -541,7 +544,7 @@ struct LineOpT {
     __device__ __forceinline__ float2 resolve(const Raw& raw) const
     {
         if constexpr (kSmallA) {
-            const float ax = fabsf((u + wx * raw.v.x + wz * raw.v.y) * raw.r.w);
+            const float ax = fabsf(fmaf(u, raw.r.w, raw.v.x));
             return make_float2(raw.r.x * voigt_small_a(tab, raw.p.x, raw.p.y, ax), raw.r.y);
         }
         return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);

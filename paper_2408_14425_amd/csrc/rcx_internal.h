@@ -59,21 +59,26 @@ struct CascIO {
     const void* up;
     void* out;
     bool up_f16, out_f16;
-    const float* scale_b;      // [batch_width] stored = value * scale
-    const float* inv_scale_b;  // [batch_width]
+    const float* scale_b;      // [batch_width] stored = value * scale (2 x with pairs)
+    const float* inv_scale_b;  // [batch_width] (2 x with pairs)
+    int64_t slot_stride = 0;   // pairs of batches: elements from batch b's cascade to b+1's
 };
 // Wavelengths per batch of the field and cascade layouts.
 int32_t batch_width();
 // Grid of a march launch over `rays` rays.
 dim3 march_grid(int64_t rays);
 // Fb: the batch's slice of F ([ncell][batch_width] float2); up/out: cascade
-// buffers [rays][batch_width].
+// buffers [rays][batch_width]. With io.slot_stride != 0 the launch marches
+// batches b and b+1 together (the next slice of F; cascades slot_stride
+// elements further on).
 hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                               const CascIO& io, hipStream_t st);
 // Cascade 0 with 4 directions: march, merge and J in one launch (no stored
-// cascade 0): J[lam0 + l][c] for l < n_valid.
+// cascade 0): J[lam0 + l][c] for l < n_valid, and with a pair also
+// J[lam0 + batch_width + l][c] for l < n_valid1.
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
-                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, hipStream_t st);
+                                const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
+                                hipStream_t st);
 // J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
                     hipStream_t st);

@@ -16,6 +16,8 @@ namespace rcx {
 
 // Ray order of the upper cascades (see LevelDesc::tile_p).
 constexpr int32_t kTileMinDirs = 256;
+// Cascades marched two wavelength batches at a time (see rcx_formal_solve).
+constexpr int32_t kPairMaxDirs = 256;
 constexpr int32_t kTileProbes = 4;
 constexpr int32_t kTileDirs = 32;
 
@@ -87,6 +89,7 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct WsLayout {
     size_t F, casc_a, casc_b, smax, scale, inv_scale, total;
+    int64_t casc_slot;  // elements of one batch's slot in a cascade buffer
 };
 
 WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
@@ -97,10 +100,14 @@ WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
     for (const auto& L : p->levels) max_entries = std::max(max_entries, level_entries(L));
     const int64_t lb = batch_width();
     const int64_t n_batch = (n_wave + lb - 1) / lb;
+    // two batches are marched together when there are at least two: each
+    // cascade buffer then holds both (slot 1 at casc_slot elements)
+    const int64_t slots = n_batch >= 2 ? 2 : 1;
+    w.casc_slot = max_entries * lb;
     w.F = 0;
     w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_batch * lb);
-    w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * lb);
-    w.smax = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb);
+    w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * lb * slots);
+    w.smax = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb * slots);
     w.scale = w.smax + align256(sizeof(float) * (size_t)n_batch * lb);
     w.inv_scale = w.scale + align256(sizeof(float) * (size_t)n_batch * lb);
     w.total = w.inv_scale + align256(sizeof(float) * (size_t)n_batch * lb);
@@ -333,8 +340,16 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
         if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
         return e;
     }));
-    for (int32_t b = 0; b < n_batch; ++b) {
+    // batches b and b+1 marched together (one cell walk for 32 wavelengths)
+    // on the cascades with at most kPairMaxDirs directions; the wider ones
+    // (whose rays cross the most cells, and whose field reads rely on the
+    // Infinity Cache holding one batch) march each batch alone into the
+    // same two-slot layout. An odd last batch runs alone throughout.
+    for (int32_t b = 0; b < n_batch;) {
+        const bool pair = b + 1 < n_batch;
         const float2* Fb = F + (size_t)b * ncell * lb;
+        const int32_t nvalid = std::min(lb, n_wave - b * lb);
+        const int32_t nvalid1 = pair ? std::min(lb, n_wave - (b + 1) * lb) : 0;
         int cur = 0;
         const void* up = nullptr;
         bool up_f16 = false;
@@ -348,28 +363,47 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
             io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
             io.scale_b = scale + (size_t)b * lb;
             io.inv_scale_b = inv_scale + (size_t)b * lb;
-            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            const bool together = pair && L.nd <= kPairMaxDirs;
+            io.slot_stride = together ? w.casc_slot : 0;
             if (i == 0 && fuse_j) {
                 // cascade 0 writes J directly (the 4 rows of a wavefront are
-                // the 4 directions of one cell)
+                // the 4 directions of one cell); N_0 = 4: always together
                 RCX_HIP_TRY(timed(p, i, st, [&] {
-                    return launch_march_merge_j(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb, nvalid, st);
+                    return launch_march_merge_j(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb, nvalid,
+                                                nvalid1, st);
                 }));
                 continue;
             }
             RCX_HIP_TRY(timed(p, i, st, [&] {
                 return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
             }));
+            if (pair && !together) {
+                // batch b+1 into slot 1 (FP16 cascades: 2-byte elements)
+                CascIO io1 = io;
+                const size_t up_off = (size_t)w.casc_slot * (io.up_f16 ? (size_t)2 : sizeof(float));
+                const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
+                io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
+                io1.out = (void*)((char*)io.out + out_off);
+                io1.scale_b = io.scale_b + lb;
+                io1.inv_scale_b = io.inv_scale_b + lb;
+                RCX_HIP_TRY(timed(p, i, st, [&] {
+                    return launch_march_merge(L, nx, nz, Fb + (size_t)ncell * lb, p->dirs_dev + p->dir_off[i], io1,
+                                              st);
+                }));
+            }
             up = bufs[cur];
             up_f16 = io.out_f16;
             cur ^= 1;
         }
         if (!fuse_j) {
-            const int32_t nvalid = std::min(lb, n_wave - b * lb);
             RCX_HIP_TRY(timed(p, -1, st, [&] {
-                return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
+                hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
+                if (e == hipSuccess && pair)
+                    e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, st);
+                return e;
             }));
         }
+        b += pair ? 2 : 1;
     }
     return ok();
 }

@@ -141,7 +141,7 @@ def test_full_size_1024_64_wavelengths_sampled():
             assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
 
 
-@pytest.mark.parametrize("which", ["blobs64", "line256"])
+@pytest.mark.parametrize("which", ["blobs64", "line256", "line96_w40"])
 def test_fp16_storage_error_is_bounded(which):
     """FP16 cascade storage with per-wavelength power-of-two scaling: each
     stored value carries at most 2^-12 relative rounding error within range,
@@ -149,8 +149,13 @@ def test_fp16_storage_error_is_bounded(which):
     oracle is reported and bounded by 2e-3."""
     torch = _torch()
     from paper_2408_14425_amd import rcx
-    inp = W.blobs_medium(64, seed=1) if which == "blobs64" else \
-        W.line_medium(256, 64, seed=2, wave_subset=np.arange(0, 64, 8))
+    if which == "blobs64":
+        inp = W.blobs_medium(64, seed=1)
+    elif which == "line256":
+        inp = W.line_medium(256, 64, seed=2, wave_subset=np.arange(0, 64, 8))
+    else:
+        # three 16-wavelength batches: a pair marched together, then one alone
+        inp = W.line_medium(96, 64, seed=5, wave_subset=np.arange(0, 40))
     print(f"[gpu] fp16 storage {inp.name}", flush=True)
     plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, storage=rcx.RCX_STORE_F16_SCALED)
     J = plan.formal_solve(torch.from_numpy(inp.chi).cuda(), torch.from_numpy(inp.eta).cuda())
