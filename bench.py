@@ -378,6 +378,7 @@ def main():
             "hbm_GBs": traffic / avg_launch_s / 1e9 if traffic else None,
             "hbm_frac": traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS if traffic else None,
             "cacheless_bytes_GBs": bytes_per_launch / avg_launch_s / 1e9,
+            "cacheless_frac": bytes_per_launch / avg_launch_s / 1e9 / HBM_PEAK_GBS,
         },
     }
     if not args.no_nlte:
