@@ -4,7 +4,8 @@
 // the merged radiance (Epi).
 //
 // A wavefront holds 4 rays x 16 wavelengths: each 16-lane row is one ray of
-// one 16-wavelength batch. The cell walk is cooperative per row: lane j
+// one 16-wavelength batch (or of two batches, Op::kW = 2, each lane holding
+// wavelength l of both). The cell walk is cooperative per row: lane j
 // computes the one or two segments of the j-th grid column the ray crosses
 // along its major axis (plane crossings in FP64, so cell boundaries are
 // exact), the row compacts them into LDS, and all 16 wavelength lanes then
