@@ -145,7 +145,7 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
 // entry) while the row's segment list is built,
 // and the step loop reads it back from LDS (stg, this wavefront's
 // [4 rows][kSegs] entries) instead of issuing a dependent global load per
-// step.
+// step; Op::resolve4 turns a group of 4 staged steps into {chi, S}.
 template <class Op, class Epi, class Up>
 __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
                                           const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[kSegRow],
@@ -284,8 +284,10 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
                 typename Op::Raw raw[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
+                float2 f[4];
+                op.resolve4(raw, f);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step(op.resolve(raw[q]), dsv[q], I[0], T[0]);
+                for (int q = 0; q < 4; ++q) step(f[q], dsv[q], I[0], T[0]);
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a
@@ -359,7 +361,7 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
 }
 
 template <class Op, class Epi, class Up>
-__global__ __launch_bounds__(kBlock) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
+__global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
 {
     // per wave, per row: (cell index, ds) entries, and staged step data

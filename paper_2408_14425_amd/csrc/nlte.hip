@@ -231,32 +231,41 @@ __device__ __forceinline__ float voigt_compact(const float2* __restrict__ tab, f
 // is below 0.76 a^3 of H(0, 0) and below about a^2 / 4 of H at any x (its
 // relative size peaks where e^{-x^2} and the a term are equal, near x = 3).
 // Used when every cell has a <= kSmallAMax (remainder below 7e-6 of H). The
-// table holds {g, g' dxc} at x_i = i dxc on [0, kXTab] (g' = -2F - 2xg);
+// table holds {g_i, g_{i+1} - g_i} at x_i = i / kInvDg on [0, kXTab],
+// linear in x (error below 6e-6 of H where the a term matters, x > 2);
 // beyond it g is -1/2 times the series above.
 constexpr double kSmallAMax = 5e-3;
+constexpr float kInvDg = 256.0f;
+constexpr int kNg = 8 * 256 + 1;
+static_assert(kNg <= kNacMax * kNxc, "the g table shares the compact table's buffers");
 
+// kCore: the caller knows ax < kXTab (no series).
+template <bool kCore = false>
 __device__ __forceinline__ float voigt_small_a(const float2* __restrict__ gtab, float a2, float ca, float ax)
 {
     const float x2 = ax * ax;
     const float e = __builtin_amdgcn_exp2f(-x2 * march::kLog2e);
-    const float fx = fminf(ax * kInvDxc, (float)(kNxc - 1) - 1e-3f);
-    const int ix = (int)fx;
-    const float2* p = gtab + ix;
-    const float gt = hermite(__builtin_amdgcn_fractf(fx), p[0], p[1]);
-    const float g = ax < (float)kXTab ? gt : -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2));
+    const float fx = fminf(ax * kInvDg, (float)(kNg - 1) - 1e-3f);
+    const float2 q = gtab[(int)fx];
+    const float gt = fmaf(__builtin_amdgcn_fractf(fx), q.y, q.x);
+    const float g = (!kCore && ax >= (float)kXTab) ? -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2)) : gt;
     return fmaf(e, fmaf(a2, fmaf(-2.0f, x2, 1.0f), 1.0f), -ca * g);
+}
+
+// g(x) = 1 - 2x F(x), with L(0, x) = (2 / sqrt(pi)) F(x) from the Fourier integral.
+__device__ double dawson_g(double x)
+{
+    double H, L;
+    voigt_fourier2(0.0, x, H, L);
+    return 1.0 - x * sqrt(kPi) * L;
 }
 
 __global__ void k_dawson_fill(float2* tab)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= kNxc) return;
-    const double x = i / (double)kInvDxc;
-    double H, L;
-    voigt_fourier2(0.0, x, H, L);  // L(0, x) = (2 / sqrt(pi)) F(x)
-    const double F = 0.5 * sqrt(kPi) * L;
-    const double g = 1.0 - 2.0 * x * F;
-    tab[i] = make_float2((float)g, (float)((-2.0 * F - 2.0 * x * g) / (double)kInvDxc));
+    if (i >= kNg) return;
+    const double g0 = dawson_g(i / (double)kInvDg), g1 = dawson_g((i + 1) / (double)kInvDg);
+    tab[i] = make_float2((float)g0, (float)(g1 - g0));
 }
 
 // The march's profile at arbitrary (a, x), for checking the compact table.
@@ -265,7 +274,8 @@ __global__ __launch_bounds__(256) void k_voigt_eval_compact(const float2* __rest
                                                             const float* x, float* out)
 {
     __shared__ float2 tab[kNacMax * kNxc];
-    for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) tab[i] = tabc[i];
+    const int n_tab = small_a ? kNg : n_a * kNxc;
+    for (int i = threadIdx.x; i < n_tab; i += blockDim.x) tab[i] = tabc[i];
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
@@ -502,10 +512,11 @@ struct LineOpT {
         float4 r;
         float2 v;
     };
-    static constexpr int kSmemBytes = kSmallA ? kNxc * 8 : kCompactBytes;
+    static constexpr int kSmemBytes = kSmallA ? kNg * 8 : kCompactBytes;
     __device__ __forceinline__ void init_shared(float2* smem)
     {
-        for (int i = threadIdx.x; i < n_a * kNxc; i += blockDim.x) smem[i] = tabc[i];
+        const int n_tab = kSmallA ? kNg : n_a * kNxc;
+        for (int i = threadIdx.x; i < n_tab; i += blockDim.x) smem[i] = tabc[i];
         tab = smem;
     }
     // segment entries keep the cell index (the step loop reads the staged
@@ -548,6 +559,34 @@ struct LineOpT {
             return make_float2(raw.r.x * voigt_small_a(tab, raw.p.x, raw.p.y, ax), raw.r.y);
         }
         return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);
+    }
+    // {chi, S} of a group of 4 staged steps. With the expansion in a, the
+    // series beyond kXTab is evaluated only when a lane of the wavefront
+    // needs it (the line-core batches never do).
+    __device__ __forceinline__ void resolve4(const Raw (&raw)[4], float2 (&f)[4]) const
+    {
+        if constexpr (kSmallA) {
+            float ax[4];
+            bool wing = false;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                ax[q] = fabsf(fmaf(u, raw[q].r.w, raw[q].v.x));
+                wing = wing || ax[q] >= (float)kXTab;
+            }
+            if (__ballot(wing) != 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    f[q] = make_float2(raw[q].r.x * voigt_small_a(tab, raw[q].p.x, raw[q].p.y, ax[q]), raw[q].r.y);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    f[q] = make_float2(raw[q].r.x * voigt_small_a<true>(tab, raw[q].p.x, raw[q].p.y, ax[q]),
+                                       raw[q].r.y);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) f[q] = resolve(raw[q]);
+        }
     }
 };
 using LineOp = LineOpT<false>;
@@ -1157,10 +1196,10 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     RCX_HIP_TRY(hipGetLastError());
     s->small_a = s->profile_mode == RCX_PROFILE_AUTO && a_top <= kSmallAMax;
     if (s->small_a) {
-        // the expansion in a: one row, g(x) = 1 - 2x F(x) and g'
+        // the expansion in a: the g(x) = 1 - 2x F(x) table
         s->n_ac = 1;
         s->da_c = 1.0;
-        hipLaunchKernelGGL(k_dawson_fill, dim3(blocks_for(kNxc, 64)), dim3(64), 0, st, s->vtabc);
+        hipLaunchKernelGGL(k_dawson_fill, dim3(blocks_for(kNg, 64)), dim3(64), 0, st, s->vtabc);
     } else {
         // compact table: a step of at most 2e-3 (linear-in-a error below
         // 1e-6), at most kNacMax nodes
