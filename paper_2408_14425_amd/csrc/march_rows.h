@@ -252,23 +252,18 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
         // entries: the Op's key of the cell (a byte offset for per-lane
         // fields) and ds; positions past the row's count hold a null entry
-        // (no data, ds = 0), so the step loop needs no bounds test
-        int n_row = 0;
+        // (no data, ds = 0), so the step loop needs no bounds test. Null
+        // entries are written everywhere first and the row's segments over
+        // them (the LDS executes one wavefront's writes in issue order).
+        srow[l] = make_uint2(Op::kNullKey, 0u);
+        srow[l + 16] = make_uint2(Op::kNullKey, 0u);
+        if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
+        if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
         if constexpr (Op::kStaged) {
-            n_row = (int)__popcll(b1 & row_bits) + (int)__popcll(b2 & row_bits);
-            if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
-            if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
-            if (n_row + l < kSegs) srow[n_row + l] = make_uint2(Op::kNullKey, 0u);
-            if (n_row + l + 16 < kSegs) srow[n_row + l + 16] = make_uint2(Op::kNullKey, 0u);
+            // staged entries past the row's count keep an earlier record (or
+            // the zeros of the kernel's start): finite, and met with ds = 0
             if (valid) stg[row][pos] = op.stage_make(st1);
             if (two) stg[row][pos + 1] = op.stage_make(st2);
-        } else {
-            // null entries everywhere, then the row's segments over them (the
-            // LDS executes one wavefront's writes in issue order)
-            srow[l] = make_uint2(Op::kNullKey, 0u);
-            srow[l + 16] = make_uint2(Op::kNullKey, 0u);
-            if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
-            if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
         }
         wave_sync();
 
@@ -283,7 +278,7 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
                                       __uint_as_float(e23.w)};
                 typename Op::Raw raw[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) op.from_stage(stg[row][s + q], (s + q) < n_row, raw[q]);
+                for (int q = 0; q < 4; ++q) raw[q] = stg[row][s + q];
                 float2 f[4];
                 op.resolve4(raw, f);
 #pragma unroll
@@ -380,8 +375,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t n
     {
         seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
         if constexpr (Op::kStaged) {
-            // positions past a row's segment count are read (with zero
-            // opacity): they must hold zeros or a real record, never garbage
+            // positions past a row's segment count are read (with ds = 0):
+            // they must hold zeros or a real record, never garbage
             static_assert(sizeof(typename Op::Stage) % 16 == 0, "stage entries are written as uint4");
             uint4* gw = reinterpret_cast<uint4*>(&stg[c.w][0][0]);
             constexpr int n16 = 4 * kStgRow * (int)sizeof(typename Op::Stage) / 16;

@@ -533,12 +533,6 @@ struct LineOpT {
         if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
         return st;
     }
-    // positions past the row's segment count: no opacity
-    __device__ __forceinline__ void from_stage(const Stage& st, bool ok, Raw& raw) const
-    {
-        raw = st;
-        raw.r.x = ok ? st.r.x : 0.0f;
-    }
     __device__ __forceinline__ void init(int l) { u = u_b[l]; }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
