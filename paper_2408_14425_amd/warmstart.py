@@ -144,6 +144,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-n", type=int, default=128)
     ap.add_argument("--train-runs", type=int, default=16)
+    ap.add_argument("--train-n2", type=int, default=0, help="a second training size (0: none)")
+    ap.add_argument("--train-runs2", type=int, default=0, help="converged runs at the second size (seeds 5100..)")
     ap.add_argument("--eval-n", type=int, default=256)
     ap.add_argument("--eval-seeds", type=int, nargs="+", default=[6000, 6001])
     ap.add_argument("--n-line", type=int, default=64)
@@ -155,6 +157,10 @@ def main():
     a = ap.parse_args()
     t0 = time.perf_counter()
     X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont)
+    if a.train_n2 > 0 and a.train_runs2 > 0:
+        X2, Y2, info2 = dataset(a.train_n2, range(5100, 5100 + a.train_runs2), a.n_line, a.n_cont)
+        X, Y = np.concatenate([X, X2]), np.concatenate([Y, Y2])
+        info += [dict(i, n=a.train_n2) for i in info2]
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
     print(f"training on {len(X)} samples", flush=True)
@@ -162,12 +168,14 @@ def main():
     t_train = time.perf_counter() - t0
     print(f"trained on {len(X)} samples in {t_train:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}", flush=True)
     if a.save:
-        save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "epochs": a.epochs,
+        save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "train_n2": a.train_n2,
+                                   "train_runs2": a.train_runs2, "epochs": a.epochs,
                                    "n_line": a.n_line, "n_cont": a.n_cont, "loss_last": losses[-1]})
     ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont, ref_max_iter=a.ref_max_iter)
     for e in ev:
         print(json.dumps(e), flush=True)
-    rep = {"train": {"n": a.train_n, "runs": a.train_runs, "samples": len(X), "data_seconds": t_data,
+    rep = {"train": {"n": a.train_n, "runs": a.train_runs, "n2": a.train_n2, "runs2": a.train_runs2,
+                     "samples": len(X), "data_seconds": t_data,
                      "train_seconds": t_train, "epochs": a.epochs, "loss_first": losses[0], "loss_last": losses[-1],
                      "runs_info": info},
            "eval": ev}
