@@ -51,6 +51,8 @@ def parse():
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
     ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--no-incl", action="store_true",
+                    help="skip the 2D-invariant formal solve with 8 inclinations per flatland ray")
     ap.add_argument("--c4", action="store_true",
                     help="also run the batched formal solve of 16 uneven atmospheres (256^2..2048^2, "
                          "32..256 wavelengths; ~190 GB of device memory, a few minutes)")
@@ -326,6 +328,25 @@ def main():
             "max_rel_diff_vs_fp32": float(((J16 - J).abs() / J.abs()).max().item()),
         }
 
+    incl = None
+    if not args.no_incl:
+        # the same solve with the paper's 8 inclinations per flatland ray
+        # (2D invariance): 8 x the ray intervals, J the hemisphere average
+        planI = rcx.Plan(inp.nx, inp.nz, inp.n_wave, n_incl=8)
+        workI = planI.work()
+        JI = torch.empty_like(chi)
+        stepsI = max(1, min(args.steps, 3))
+        dtI, _ = time_solves(planI, chi, eta, JI, stepsI, 1)
+        planI.close()
+        incl = {
+            "n_incl": 8,
+            "ms_per_step": dtI / stepsI * 1e3,
+            "value": workI.rays_nonempty * inp.n_wave / (dtI / stepsI),
+            "unit": "ray-intervals/s",
+            "ray_intervals_nonempty_per_step": workI.rays_nonempty * inp.n_wave,
+            "steps": stepsI,
+        }
+
     ms_step = dt / args.steps * 1e3
     rays = work.rays_nonempty * inp.n_wave
     value = rays / (dt / args.steps)
@@ -365,6 +386,7 @@ def main():
             "finite": ok,
         },
         "fp16_storage": fp16,
+        "inclined": incl,
         "roofline": {
             "bound": "alu",
             "kernel": "k_march_rows",

@@ -63,7 +63,15 @@ typedef struct {
  *   c0_t1:      end of the cascade-0 interval = start of cascade 1, in cells.
  *   t_rule:     RCX_T_GEOMETRIC or RCX_T_LENGTH_X4.
  *   storage:    RCX_STORE_F32 or RCX_STORE_F16_SCALED.
- *   n_incl:     inclination rays per flatland ray; must be 1 (flatland J).
+ *   n_incl:     inclination rays per flatland ray, in [1, 16] (Sec. 4.1, 2D
+ *               invariance): rays with the same x-z projection inclined to
+ *               the invariant y axis, mu = cos(inclination) on a Gauss-Radau
+ *               rule over [0, 1] with the node mu = 0 (the in-plane ray)
+ *               fixed; J = sum_m w_m J_m, J_m the flatland J with the path
+ *               per projected cell scaled by 1/sqrt(1 - mu_m^2). 1 = flatland
+ *               (the default); the paper uses 8. Only the formal solve
+ *               (rcx_formal_solve) supports n_incl > 1; batches and the
+ *               non-LTE solver return RCX_E_UNSUPPORTED for it.
  *   flags:      reserved, 0. */
 typedef struct {
     int32_t n_cascades;

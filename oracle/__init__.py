@@ -183,6 +183,42 @@ def formal_solve(chi, eta, n_casc: int, voxel: float = 1.0, c0_dirs: int = 4, t1
     return out
 
 
+def radau_inclinations(n: int):
+    """Gauss-Radau rule on mu = cos(angle to the invariant y axis) in [0, 1]
+    with the node mu = 0 (the in-plane ray) fixed (Sec. 4.1: eight
+    inclined rays per flatland ray integrate one hemisphere, the other being
+    its mirror image in a y-invariant model). Nodes: 0 and the roots of
+    (P_{n-1} + P_n)(x) / (1 + x), x = 2 mu - 1; weights 2/n^2 and
+    (1 - x) / (n^2 P_{n-1}(x)^2), halved for [0, 1]. n = 1 is flatland."""
+    from numpy.polynomial import legendre as leg
+    if n == 1:
+        return np.array([0.0]), np.array([1.0])
+    c = np.zeros(n + 1)
+    c[n - 1] = c[n] = 1.0
+    r = np.sort(np.real(leg.legroots(c)))
+    r = r[np.abs(r + 1.0) > 1e-9]
+    dc = leg.legder(c)
+    for _ in range(3):  # polish the companion-matrix roots
+        r = r - leg.legval(r, c) / leg.legval(r, dc)
+    pn1 = leg.legval(r, np.eye(n)[n - 1])
+    x = np.concatenate([[-1.0], r])
+    w = np.concatenate([[2.0 / n ** 2], (1.0 - r) / (n ** 2 * pn1 ** 2)])
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def formal_solve_inclined(chi, eta, n_casc: int, n_incl: int, voxel: float = 1.0, **kw):
+    """J of the 2D-invariant formal solution: sum over the inclinations of
+    the flatland solution whose path per projected cell is 1/sin(theta)
+    = 1/sqrt(1 - mu^2) times longer (the same x-z projection), weighted by
+    the Gauss-Radau weights."""
+    mu, w = radau_inclinations(n_incl)
+    J = None
+    for m in range(n_incl):
+        Jm = formal_solve(chi, eta, n_casc, voxel=voxel / np.sqrt(1.0 - mu[m] ** 2), **kw)["J"]
+        J = w[m] * Jm if J is None else J + w[m] * Jm
+    return J
+
+
 def level_intervals(g: Geom, i: int, chi, eta):
     """Raw (I, tau) of every interval of cascade i; [n_wave][pz][px][dirs]."""
     chi, eta = _f64(chi), _f64(eta)

@@ -99,12 +99,13 @@ __global__ void k_fill_u32(unsigned int* p, int32_t n, unsigned int v)
 // J[lam0 + l][c] = (1/N_0) sum_k Itilde_0[(c * N_0 + k)][l] for one batch,
 // through a 64-cell x 16-wavelength LDS tile.
 __global__ __launch_bounds__(256) void k_j(const float* __restrict__ I0, float* __restrict__ J,
-                                           int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0)
+                                           int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
+                                           int32_t acc_j)
 {
     __shared__ float tile[kLB][65];
     const int t = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * 64;
-    const float inv = 1.0f / (float)n0;
+    const float inv = w / (float)n0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int l = t & 15;
@@ -121,7 +122,10 @@ __global__ __launch_bounds__(256) void k_j(const float* __restrict__ I0, float* 
         const int l = (t >> 6) + 4 * r;
         const int cc = t & 63;
         const int64_t c = c0 + cc;
-        if (l < n_valid && c < ncell) J[(int64_t)(lam0 + l) * ncell + c] = tile[l][cc];
+        if (l < n_valid && c < ncell) {
+            float* j = &J[(int64_t)(lam0 + l) * ncell + c];
+            *j = acc_j ? *j + tile[l][cc] : tile[l][cc];
+        }
     }
 }
 
@@ -206,26 +210,27 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
 
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                                 const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
-                                hipStream_t st)
+                                float w, bool acc, hipStream_t st)
 {
     const uint32_t fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
     if (io.slot_stride != 0) {
         march::FieldOp2 op{};
         op.Fb = Fb;
         op.fb_bytes = fb_bytes;
-        return launch_fs_up(L, nx, nz, op, march::JEpi2{J, lam0, n_valid, n_valid1, (int64_t)nx * nz}, dirs, io, st);
+        return launch_fs_up(L, nx, nz, op, march::JEpi2{J, lam0, n_valid, n_valid1, (int64_t)nx * nz, w, acc}, dirs,
+                            io, st);
     }
     march::FieldOp op{};
     op.Fb = Fb;
     op.fb_bytes = fb_bytes;
-    return launch_fs_up(L, nx, nz, op, march::JEpi{J, lam0, n_valid, (int64_t)nx * nz}, dirs, io, st);
+    return launch_fs_up(L, nx, nz, op, march::JEpi{J, lam0, n_valid, (int64_t)nx * nz, w, acc}, dirs, io, st);
 }
 
-hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
-                    hipStream_t st)
+hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
+                    bool acc, hipStream_t st)
 {
     dim3 grid((unsigned)((ncell + 63) / 64));
-    hipLaunchKernelGGL(k_j, grid, dim3(256), 0, st, I0, J, lam0, n_valid, ncell, n0);
+    hipLaunchKernelGGL(k_j, grid, dim3(256), 0, st, I0, J, lam0, n_valid, ncell, n0, w, (int32_t)acc);
     return hipGetLastError();
 }
 

@@ -228,8 +228,8 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         const int cm_ = __mul24(im, strm);
         const uint32_t cell1 = (uint32_t)(cm_ + __mul24(in0, strn));
         const uint32_t cell2 = (uint32_t)(cm_ + __mul24(in1, strn));
-        const float ds1 = (float)fmax((two ? tmid : tb_) - ta, 0.0);
-        const float ds2 = (float)fmax(tb_ - tmid, 0.0);
+        const float ds1 = (float)(fmax((two ? tmid : tb_) - ta, 0.0) * L.ds_scale);
+        const float ds2 = (float)(fmax(tb_ - tmid, 0.0) * L.ds_scale);
         // staged data: loads issued here, used after the compaction below
         typename Op::StageIn st1{}, st2{};
         if constexpr (Op::kStaged) {
@@ -445,17 +445,25 @@ struct StoreF16Epi {
 // Cascade-0 epilogue writing J directly: with N_0 = 4 directions the 4 rows
 // of a wavefront are the 4 directions of one cell (ray = cell * 4 + k), so
 // J = (1/4) sum over the rows, J[lam0 + l][cell] for l < n_valid.
+// With an inclination quadrature, pass m writes w_m J_m (acc false) or adds
+// it (acc true); flatland: w = 1, acc false.
 struct JEpi {
     float* J;
     int32_t lam0, n_valid;
     int64_t ncell;
+    float w = 1.0f;
+    bool acc = false;
     __device__ __forceinline__ void init(int) {}
     template <class Op>
     __device__ __forceinline__ void finish(const RayInfo& ri, int l, int lane, float I, const Op&)
     {
         float s = I + __shfl_xor(I, 16);
         s += __shfl_xor(s, 32);
-        if (ri.active && (lane >> 4) == 0 && l < n_valid) J[(int64_t)(lam0 + l) * ncell + ri.ray / 4] = 0.25f * s;
+        if (ri.active && (lane >> 4) == 0 && l < n_valid) {
+            float* j = &J[(int64_t)(lam0 + l) * ncell + ri.ray / 4];
+            const float v = (0.25f * w) * s;
+            *j = acc ? *j + v : v;
+        }
     }
 };
 
@@ -561,6 +569,8 @@ struct JEpi2 {
     float* J;
     int32_t lam0, n_valid0, n_valid1;
     int64_t ncell;
+    float w = 1.0f;
+    bool acc = false;
     __device__ __forceinline__ void init(int) {}
     template <class Op>
     __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int lane, const float (&I)[2], const Op&)
@@ -570,8 +580,15 @@ struct JEpi2 {
         s0 += __shfl_xor(s0, 32);
         s1 += __shfl_xor(s1, 32);
         if (ri.active && (lane >> 4) == 0) {
-            if (l < n_valid0) J[(int64_t)(lam0 + l) * ncell + ri.ray / 4] = 0.25f * s0;
-            if (l < n_valid1) J[(int64_t)(lam0 + kLB + l) * ncell + ri.ray / 4] = 0.25f * s1;
+            const float q = 0.25f * w;
+            if (l < n_valid0) {
+                float* j = &J[(int64_t)(lam0 + l) * ncell + ri.ray / 4];
+                *j = acc ? *j + q * s0 : q * s0;
+            }
+            if (l < n_valid1) {
+                float* j = &J[(int64_t)(lam0 + kLB + l) * ncell + ri.ray / 4];
+                *j = acc ? *j + q * s1 : q * s1;
+            }
         }
     }
 };

@@ -966,6 +966,7 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
         atom->n_lines > RCX_NLTE_MAX_LINES || atom->n_conts < 0 || atom->n_conts > RCX_NLTE_MAX_CONTS)
         return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: atom exceeds the supported sizes");
     if (p->c0_dirs != 4) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: the rate epilogue needs c0_dirs = 4");
+    if (p->n_incl != 1) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: flatland only (n_incl = 1)");
     const int32_t nt = atom->n_lines + atom->n_conts;
     if (nt < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: no transitions");
     for (int32_t k = 0; k < atom->n_lines; ++k)
@@ -1315,7 +1316,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             up = outb;
             cur ^= 1;
         }
-        if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, st));
+        if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, 1.0f, false, st));
     }
     hipLaunchKernelGGL(k_rates_sum, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, A.nt, s->d_tb, s->d_tb + A.nt,
                        s->part, rates);

@@ -24,6 +24,9 @@ struct LevelDesc {
     // groups of tile_p x tile_p probes x tile_d directions, so the rays a
     // launch runs at one time cross a compact band of cells.
     int32_t tile_p, tile_d;
+    // path length per unit of projected (x-z) length: 1 / sin(theta) for a
+    // ray inclined at theta to the invariant y axis; 1 in flatland
+    double ds_scale = 1.0;
 };
 
 // Rays a march launch covers (the tiled order pads the probe grid to whole
@@ -78,10 +81,12 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
 // J[lam0 + batch_width + l][c] for l < n_valid1.
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                                 const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
-                                hipStream_t st);
+                                float w, bool acc, hipStream_t st);
 // J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
-hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0,
-                    hipStream_t st);
+// The J writers take a weight w and acc: J = w * value, or J += w * value
+// (inclination quadrature: one pass per inclination).
+hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
+                    bool acc, hipStream_t st);
 
 }  // namespace rcx
 
@@ -95,6 +100,9 @@ struct rcx_plan {
     int32_t n_casc;
     int32_t top_skipped;
     std::vector<rcx::LevelDesc> levels;
+    // inclination quadrature (Gauss-Radau in mu = cos(angle to y) on [0, 1],
+    // fixed node mu = 0): path scale 1/sqrt(1 - mu^2) and weight per node
+    std::vector<double> incl_scale, incl_w;
     std::vector<int32_t> dir_off;  // offset of cascade i's directions in the table
     std::vector<double4> dirs_host;
     double4* dirs_dev = nullptr;

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "incl_quadrature.h"
 #include "rcx_internal.h"
 
 namespace rcx {
@@ -148,16 +149,19 @@ void count_work(rcx_plan* p)
                     }
                 }
         }
+        // every flatland ray interval is marched once per inclination
+        const int64_t ni = p->prm.n_incl;
         if (i < 16) {
-            w.level_rays[i] = rays;
-            w.level_steps[i] = steps;
+            w.level_rays[i] = rays * ni;
+            w.level_steps[i] = steps * ni;
         }
-        w.rays_all += rays;
-        w.rays_nonempty += nonempty;
-        w.cell_steps += steps;
+        w.rays_all += rays * ni;
+        w.rays_nonempty += nonempty * ni;
+        w.cell_steps += steps * ni;
     }
     p->work_done = true;
 }
+
 
 // Run `launch` between two recorded events when timing is enabled.
 template <class F>
@@ -211,7 +215,8 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
         return fail(RCX_E_INVALID, "rcx_plan_create: unknown t_rule");
     if (prm->storage != RCX_STORE_F32 && prm->storage != RCX_STORE_F16_SCALED)
         return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
-    if (prm->n_incl != 1) return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: only n_incl = 1 (flatland)");
+    if (prm->n_incl < 1 || prm->n_incl > 16)
+        return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
     int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
     if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
     if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
@@ -224,6 +229,12 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
     p->prm.n_cascades = n_casc;
     p->max_wave = max_wave;
     p->n_casc = n_casc;
+    {
+        std::vector<double> mu;
+        radau_nodes(prm->n_incl, mu, p->incl_w);
+        p->incl_scale.resize(prm->n_incl);
+        for (int32_t m = 0; m < prm->n_incl; ++m) p->incl_scale[m] = 1.0 / std::sqrt(1.0 - mu[m] * mu[m]);
+    }
     p->levels.resize(n_casc);
     p->dir_off.resize(n_casc);
     int32_t off = 0;
@@ -340,70 +351,80 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
         if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
         return e;
     }));
-    // batches b and b+1 marched together (one cell walk for 32 wavelengths)
-    // on the cascades with at most kPairMaxDirs directions; the wider ones
-    // (whose rays cross the most cells, and whose field reads rely on the
-    // Infinity Cache holding one batch) march each batch alone into the
-    // same two-slot layout. An odd last batch runs alone throughout.
-    for (int32_t b = 0; b < n_batch;) {
-        const bool pair = b + 1 < n_batch;
-        const float2* Fb = F + (size_t)b * ncell * lb;
-        const int32_t nvalid = std::min(lb, n_wave - b * lb);
-        const int32_t nvalid1 = pair ? std::min(lb, n_wave - (b + 1) * lb) : 0;
-        int cur = 0;
-        const void* up = nullptr;
-        bool up_f16 = false;
-        for (int32_t i = p->n_casc - 1; i >= 0; --i) {
-            if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
-            const LevelDesc& L = p->levels[i];
-            CascIO io;
-            io.up = L.has_up ? up : nullptr;
-            io.up_f16 = up_f16;
-            io.out = bufs[cur];
-            io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
-            io.scale_b = scale + (size_t)b * lb;
-            io.inv_scale_b = inv_scale + (size_t)b * lb;
-            const bool together = pair && L.nd <= kPairMaxDirs;
-            io.slot_stride = together ? w.casc_slot : 0;
-            if (i == 0 && fuse_j) {
-                // cascade 0 writes J directly (the 4 rows of a wavefront are
-                // the 4 directions of one cell); N_0 = 4: always together
+    // one pass per inclination (Gauss-Radau in mu, the path length per
+    // projected cell scaled by 1/sin): J = sum_m w_m J_m, written by the first
+    // pass and accumulated by the others
+    const int32_t n_incl = p->prm.n_incl;
+    for (int32_t m = 0; m < n_incl; ++m) {
+        const float jw = (float)p->incl_w[m];
+        const bool jacc = m > 0;
+        // batches b and b+1 marched together (one cell walk for 32 wavelengths)
+        // on the cascades with at most kPairMaxDirs directions; the wider ones
+        // (whose rays cross the most cells, and whose field reads rely on the
+        // Infinity Cache holding one batch) march each batch alone into the
+        // same two-slot layout. An odd last batch runs alone throughout.
+        for (int32_t b = 0; b < n_batch;) {
+            const bool pair = b + 1 < n_batch;
+            const float2* Fb = F + (size_t)b * ncell * lb;
+            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            const int32_t nvalid1 = pair ? std::min(lb, n_wave - (b + 1) * lb) : 0;
+            int cur = 0;
+            const void* up = nullptr;
+            bool up_f16 = false;
+            for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+                if (p->top_skipped && i == p->n_casc - 1) continue;  // all rays empty: nothing to merge
+                LevelDesc L = p->levels[i];
+                L.ds_scale = p->incl_scale[m];
+                CascIO io;
+                io.up = L.has_up ? up : nullptr;
+                io.up_f16 = up_f16;
+                io.out = bufs[cur];
+                io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
+                io.scale_b = scale + (size_t)b * lb;
+                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                const bool together = pair && L.nd <= kPairMaxDirs;
+                io.slot_stride = together ? w.casc_slot : 0;
+                if (i == 0 && fuse_j) {
+                    // cascade 0 writes J directly (the 4 rows of a wavefront are
+                    // the 4 directions of one cell); N_0 = 4: always together
+                    RCX_HIP_TRY(timed(p, i, st, [&] {
+                        return launch_march_merge_j(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb, nvalid,
+                                                    nvalid1, jw, jacc, st);
+                    }));
+                    continue;
+                }
                 RCX_HIP_TRY(timed(p, i, st, [&] {
-                    return launch_march_merge_j(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb, nvalid,
-                                                nvalid1, st);
+                    return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
                 }));
-                continue;
+                if (pair && !together) {
+                    // batch b+1 into slot 1 (FP16 cascades: 2-byte elements)
+                    CascIO io1 = io;
+                    const size_t up_off = (size_t)w.casc_slot * (io.up_f16 ? (size_t)2 : sizeof(float));
+                    const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
+                    io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
+                    io1.out = (void*)((char*)io.out + out_off);
+                    io1.scale_b = io.scale_b + lb;
+                    io1.inv_scale_b = io.inv_scale_b + lb;
+                    RCX_HIP_TRY(timed(p, i, st, [&] {
+                        return launch_march_merge(L, nx, nz, Fb + (size_t)ncell * lb, p->dirs_dev + p->dir_off[i], io1,
+                                                  st);
+                    }));
+                }
+                up = bufs[cur];
+                up_f16 = io.out_f16;
+                cur ^= 1;
             }
-            RCX_HIP_TRY(timed(p, i, st, [&] {
-                return launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
-            }));
-            if (pair && !together) {
-                // batch b+1 into slot 1 (FP16 cascades: 2-byte elements)
-                CascIO io1 = io;
-                const size_t up_off = (size_t)w.casc_slot * (io.up_f16 ? (size_t)2 : sizeof(float));
-                const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
-                io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
-                io1.out = (void*)((char*)io.out + out_off);
-                io1.scale_b = io.scale_b + lb;
-                io1.inv_scale_b = io.inv_scale_b + lb;
-                RCX_HIP_TRY(timed(p, i, st, [&] {
-                    return launch_march_merge(L, nx, nz, Fb + (size_t)ncell * lb, p->dirs_dev + p->dir_off[i], io1,
-                                              st);
+            if (!fuse_j) {
+                RCX_HIP_TRY(timed(p, -1, st, [&] {
+                    hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, jw, jacc, st);
+                    if (e == hipSuccess && pair)
+                        e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, jw,
+                                 jacc, st);
+                    return e;
                 }));
             }
-            up = bufs[cur];
-            up_f16 = io.out_f16;
-            cur ^= 1;
+            b += pair ? 2 : 1;
         }
-        if (!fuse_j) {
-            RCX_HIP_TRY(timed(p, -1, st, [&] {
-                hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, st);
-                if (e == hipSuccess && pair)
-                    e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, st);
-                return e;
-            }));
-        }
-        b += pair ? 2 : 1;
     }
     return ok();
 }

@@ -1,6 +1,7 @@
 """Host-only checks of the C ABI: the library loads, exports every symbol the
 header declares, and rejects invalid arguments before touching the GPU."""
 import ctypes as C
+import os
 import re
 
 import pytest
@@ -38,12 +39,42 @@ def test_plan_create_rejects_bad_sizes(nx, nz, mw):
     assert e.value.code == rcx.RCX_E_INVALID
 
 
-def test_plan_create_rejects_unsupported():
+@pytest.mark.parametrize("n_incl", [0, 17])
+def test_plan_create_rejects_bad_inclination_counts(n_incl):
     p = rcx.rcx_params_default()
-    p.n_incl = 8
+    p.n_incl = n_incl
     with pytest.raises(rcx.RcxError) as e:
         rcx.rcx_plan_create(rcx.rcx_grid(8, 8, 1.0), p, 1)
-    assert e.value.code == rcx.RCX_E_UNSUPPORTED
+    assert e.value.code == rcx.RCX_E_INVALID
+
+
+def test_host_radau_rule_matches_oracle_and_is_exact(tmp_path):
+    """The library's inclination rule (host C++, Newton on Legendre
+    polynomials) against the oracle's (numpy's Legendre roots), and its
+    exactness for polynomials in mu up to degree 2n - 2."""
+    import subprocess
+    import numpy as np
+    import oracle
+    src = tmp_path / "radau.cpp"
+    src.write_text(
+        '#include "incl_quadrature.h"\n#include <cstdio>\n#include <cstdlib>\n'
+        "int main(int c, char** v) { std::vector<double> mu, w; rcx::radau_nodes(std::atoi(v[1]), mu, w);"
+        ' for (size_t i = 0; i < mu.size(); ++i) std::printf("%.17g %.17g\\n", mu[i], w[i]); return 0; }\n')
+    exe = tmp_path / "radau"
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2408_14425_amd", "csrc")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", csrc, "-o", str(exe), str(src)], check=True)
+    for n in (1, 2, 3, 8, 16):
+        out = subprocess.run([str(exe), str(n)], check=True, capture_output=True, text=True).stdout
+        got = np.array([[float(t) for t in ln.split()] for ln in out.strip().splitlines()])
+        mu, w = oracle.radau_inclinations(n)
+        np.testing.assert_allclose(got[:, 0], mu, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(got[:, 1], w, rtol=1e-10, atol=0)  # numpy roots: ~5e-12 at n = 16
+        assert got[0, 0] == 0.0
+        for d in range(2 * n - 1):
+            assert abs(np.dot(got[:, 1], got[:, 0] ** d) - 1.0 / (d + 1)) < 1e-12
+
+
+def test_plan_create_rejects_unsupported():
     p = rcx.rcx_params_default()
     p.n_cascades = 17
     with pytest.raises(rcx.RcxError) as e:

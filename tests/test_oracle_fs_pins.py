@@ -280,6 +280,50 @@ def test_homogeneous_thick_medium_J_equals_S():
     np.testing.assert_allclose(J[3:-3, 3:-3], 0.7, rtol=1e-12)
 
 
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 12])
+def test_radau_inclinations_exact_and_fixed_node(n):
+    """Gauss-Radau in mu on [0, 1]: the in-plane node mu = 0 fixed, the rule
+    exact for polynomials up to degree 2n - 2 (and, measurably for n <= 8,
+    not for 2n - 1)."""
+    mu, w = oracle.radau_inclinations(n)
+    assert mu[0] == 0.0 and np.all(np.diff(mu) > 0) and mu[-1] < 1.0
+    for d in range(2 * n - 1):
+        assert abs(np.dot(w, mu ** d) - 1.0 / (d + 1)) < 1e-12
+    if 1 < n <= 8:
+        assert abs(np.dot(w, mu ** (2 * n - 1)) - 1.0 / (2 * n)) > 1e-10
+
+
+def test_inclined_homogeneous_thick_medium_J_equals_S():
+    """2D invariance: every inclined ray in a homogeneous thick medium sees
+    I = S, so the weighted sum over the hemisphere gives J = S."""
+    n = 32
+    chi = np.full((1, n, n), 20.0)
+    J = oracle.formal_solve_inclined(chi, chi * 0.7, W.n_cascades_for(n, n), 8)[0]
+    np.testing.assert_allclose(J[3:-3, 3:-3], 0.7, rtol=1e-12)
+
+
+def test_inclined_one_node_is_flatland():
+    inp = W.blobs_medium(16, seed=7)
+    a = oracle.formal_solve_inclined(inp.chi, inp.eta, inp.n_cascades, 1)
+    b = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
+    assert np.array_equal(a, b)
+
+
+def test_inclined_thin_medium_scales_with_path_length():
+    """Optically thin limit: the intensity of a ray is the emissivity times
+    its path length, and an inclined ray with the same x-z projection is
+    1/sin(theta) = 1/sqrt(1 - mu^2) times longer, so the inclined J is the
+    flatland J times sum_m w_m / sqrt(1 - mu_m^2) (to first order in tau)."""
+    n = 24
+    chi = np.full((1, n, n), 1e-7)
+    eta = chi * 1.3
+    nc = W.n_cascades_for(n, n)
+    Jf = oracle.formal_solve(chi, eta, nc)["J"][0]
+    Ji = oracle.formal_solve_inclined(chi, eta, nc, 8)[0]
+    mu, w = oracle.radau_inclinations(8)
+    np.testing.assert_allclose(Ji, Jf * np.dot(w, 1.0 / np.sqrt(1.0 - mu ** 2)), rtol=1e-5)
+
+
 def test_single_cascade_equals_four_ray_long_characteristics():
     """With one cascade (t_1 = infinity) RC is discrete-ordinates long
     characteristics with the N_0 = 4 cascade-0 directions."""
