@@ -69,7 +69,9 @@ typedef struct {
  *               rule over [0, 1] with the node mu = 0 (the in-plane ray)
  *               fixed; J = sum_m w_m J_m, J_m the flatland J with the path
  *               per projected cell scaled by 1/sqrt(1 - mu_m^2). 1 = flatland
- *               (the default); the paper uses 8. Only the formal solve
+ *               (the default); the paper uses 8 (with FP32 cascades the 8
+ *               run as slots of one march: 8 x the cascade workspace). Only
+ *               the formal solve
  *               (rcx_formal_solve) supports n_incl > 1; batches and the
  *               non-LTE solver return RCX_E_UNSUPPORTED for it.
  *   flags:      reserved, 0. */

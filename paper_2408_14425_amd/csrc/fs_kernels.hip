@@ -226,6 +226,31 @@ hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, cons
     return launch_fs_up(L, nx, nz, op, march::JEpi{J, lam0, n_valid, (int64_t)nx * nz, w, acc}, dirs, io, st);
 }
 
+hipError_t launch_march_merge_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                   const CascIO& io, const float* sc, hipStream_t st)
+{
+    march::FieldOpIncl<kInclSlots> op{};
+    op.Fb = Fb;
+    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    for (int w = 0; w < kInclSlots; ++w) op.sc[w] = sc[w];
+    return launch_fs_up(L, nx, nz, op, march::StoreEpiSlots<kInclSlots>{(float*)io.out, io.slot_stride}, dirs, io, st);
+}
+
+hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
+                                     const double4* dirs, const CascIO& io, float* J, int32_t lam0, int32_t n_valid,
+                                     const float* sc, const float* wt, hipStream_t st)
+{
+    march::FieldOpIncl<kInclSlots> op{};
+    op.Fb = Fb;
+    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    march::JEpiIncl<kInclSlots> epi{J, lam0, n_valid, (int64_t)nx * nz, {}};
+    for (int w = 0; w < kInclSlots; ++w) {
+        op.sc[w] = sc[w];
+        epi.wt[w] = wt[w];
+    }
+    return launch_fs_up(L, nx, nz, op, epi, dirs, io, st);
+}
+
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
                     bool acc, hipStream_t st)
 {

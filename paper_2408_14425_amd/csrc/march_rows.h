@@ -351,7 +351,7 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
     if constexpr (W == 1) {
         epi.finish(ri, l, lane, I[0], op);
     } else {
-        epi.finish2(ri, l, lane, I, op);
+        epi.finish_slots(ri, l, lane, I, op);
     }
 }
 
@@ -462,7 +462,10 @@ struct JEpi {
         if (ri.active && (lane >> 4) == 0 && l < n_valid) {
             float* j = &J[(int64_t)(lam0 + l) * ncell + ri.ray / 4];
             const float v = (0.25f * w) * s;
-            *j = acc ? *j + v : v;
+            if (acc)
+                *j += v;
+            else
+                *j = v;
         }
     }
 };
@@ -536,7 +539,7 @@ struct StoreEpi2 {
     int64_t stride;
     __device__ __forceinline__ void init(int) {}
     template <class Op>
-    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
     {
         if (ri.active) {
             out[ri.ray * kLB + l] = I[0];
@@ -555,7 +558,7 @@ struct StoreF16Epi2 {
         sc1 = scale_b[l + kLB];
     }
     template <class Op>
-    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
     {
         if (ri.active) {
             out[ri.ray * kLB + l] = __float2half_rn(I[0] * sc0);
@@ -573,7 +576,7 @@ struct JEpi2 {
     bool acc = false;
     __device__ __forceinline__ void init(int) {}
     template <class Op>
-    __device__ __forceinline__ void finish2(const RayInfo& ri, int l, int lane, const float (&I)[2], const Op&)
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int lane, const float (&I)[2], const Op&)
     {
         float s0 = I[0] + __shfl_xor(I[0], 16);
         float s1 = I[1] + __shfl_xor(I[1], 16);
@@ -581,15 +584,89 @@ struct JEpi2 {
         s1 += __shfl_xor(s1, 32);
         if (ri.active && (lane >> 4) == 0) {
             const float q = 0.25f * w;
-            if (l < n_valid0) {
-                float* j = &J[(int64_t)(lam0 + l) * ncell + ri.ray / 4];
-                *j = acc ? *j + q * s0 : q * s0;
-            }
-            if (l < n_valid1) {
-                float* j = &J[(int64_t)(lam0 + kLB + l) * ncell + ri.ray / 4];
-                *j = acc ? *j + q * s1 : q * s1;
+            float* j0 = &J[(int64_t)(lam0 + l) * ncell + ri.ray / 4];
+            float* j1 = &J[(int64_t)(lam0 + kLB + l) * ncell + ri.ray / 4];
+            if (acc) {
+                if (l < n_valid0) *j0 += q * s0;
+                if (l < n_valid1) *j1 += q * s1;
+            } else {
+                if (l < n_valid0) *j0 = q * s0;
+                if (l < n_valid1) *j1 = q * s1;
             }
         }
+    }
+};
+
+
+// W inclination rays per lane (2D invariance): the rays of one wavelength
+// batch with the same x-z projection, inclined to the invariant y axis. One
+// field load per step serves all W; slot w scales the optical depth by its
+// path per projected cell, sc[w] = 1 / sin(inclination).
+template <int W>
+struct FieldOpIncl {
+    const float2* Fb;
+    uint32_t fb_bytes;
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;
+    float sc[W];
+    using Raw = float2;
+    static constexpr int kW = W;
+    static constexpr bool kStaged = false;
+    struct Stage {};
+    struct StageIn {};
+    static constexpr int kSmemBytes = 0;
+    __device__ __forceinline__ void init_shared(float2*) {}
+    __device__ __forceinline__ void init(int l)
+    {
+        rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)Fb, 0, (int)fb_bytes, 0x00020000);
+        lane_off = (uint32_t)l * 8u;
+    }
+    __device__ __forceinline__ void begin_ray(double, double) {}
+    static constexpr uint32_t kNullKey = 0x80000000u;
+    __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell * (uint32_t)(kLB * 8); }
+    __device__ __forceinline__ void fetch_key(uint32_t k, Raw (&r)[kW]) const
+    {
+        const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rsrc, k + lane_off, 0, 0));
+#pragma unroll
+        for (int w = 0; w < W; ++w) r[w] = make_float2(f.x * sc[w], f.y);
+    }
+    __device__ __forceinline__ float2 resolve(const Raw& r) const { return r; }
+};
+
+// Inclination slots stored `stride` elements apart.
+template <int W>
+struct StoreEpiSlots {
+    float* out;
+    int64_t stride;
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int, const float (&I)[W], const Op&)
+    {
+        if (ri.active) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) out[w * stride + ri.ray * kLB + l] = I[w];
+        }
+    }
+};
+
+// Cascade 0 with N_0 = 4 and W inclination slots: J = (1/4) sum over the
+// rows of sum_w wt[w] I_w (the quadrature weights sum to 1).
+template <int W>
+struct JEpiIncl {
+    float* J;
+    int32_t lam0, n_valid;
+    int64_t ncell;
+    float wt[W];
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int lane, const float (&I)[W], const Op&)
+    {
+        float v = 0.0f;
+#pragma unroll
+        for (int w = 0; w < W; ++w) v = fmaf(wt[w], I[w], v);
+        float s = v + __shfl_xor(v, 16);
+        s += __shfl_xor(s, 32);
+        if (ri.active && (lane >> 4) == 0 && l < n_valid) J[(int64_t)(lam0 + l) * ncell + ri.ray / 4] = 0.25f * s;
     }
 };
 

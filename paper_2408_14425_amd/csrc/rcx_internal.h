@@ -82,6 +82,15 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                                 const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
                                 float w, bool acc, hipStream_t st);
+// kInclSlots inclinations per lane in one launch (FP32 cascades, slot w
+// io.slot_stride * w elements on): sc[w] = path per projected cell, wt[w]
+// the quadrature weights (cascade 0 with 4 directions writes J).
+constexpr int kInclSlots = 8;
+hipError_t launch_march_merge_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                   const CascIO& io, const float* sc, hipStream_t st);
+hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
+                                     const double4* dirs, const CascIO& io, float* J, int32_t lam0, int32_t n_valid,
+                                     const float* sc, const float* wt, hipStream_t st);
 // J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
 // The J writers take a weight w and acc: J = w * value, or J += w * value
 // (inclination quadrature: one pass per inclination).

@@ -93,6 +93,11 @@ struct WsLayout {
     int64_t casc_slot;  // elements of one batch's slot in a cascade buffer
 };
 
+// The paper's 8 inclinations with FP32 cascades run as slots of one march
+// (one walk and one field load per step for all 8); other counts, or FP16
+// cascades, run one pass per inclination.
+bool incl_slots(const rcx_plan* p) { return p->prm.n_incl == kInclSlots && p->prm.storage == RCX_STORE_F32; }
+
 WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
 {
     WsLayout w{};
@@ -103,7 +108,7 @@ WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
     const int64_t n_batch = (n_wave + lb - 1) / lb;
     // two batches are marched together when there are at least two: each
     // cascade buffer then holds both (slot 1 at casc_slot elements)
-    const int64_t slots = n_batch >= 2 ? 2 : 1;
+    const int64_t slots = incl_slots(p) ? kInclSlots : (n_batch >= 2 ? 2 : 1);
     w.casc_slot = max_entries * lb;
     w.F = 0;
     w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_batch * lb);
@@ -351,6 +356,55 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
         if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
         return e;
     }));
+    if (incl_slots(p)) {
+        // the inclinations as slots of each lane: J = sum_m w_m J_m formed in
+        // the cascade-0 epilogue
+        float sc[kInclSlots], wt[kInclSlots];
+        for (int m = 0; m < kInclSlots; ++m) {
+            sc[m] = (float)p->incl_scale[m];
+            wt[m] = (float)p->incl_w[m];
+        }
+        for (int32_t b = 0; b < n_batch; ++b) {
+            const float2* Fb = F + (size_t)b * ncell * lb;
+            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            int cur = 0;
+            const void* up = nullptr;
+            for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+                if (p->top_skipped && i == p->n_casc - 1) continue;
+                const LevelDesc& L = p->levels[i];
+                CascIO io;
+                io.up = L.has_up ? up : nullptr;
+                io.up_f16 = false;
+                io.out = bufs[cur];
+                io.out_f16 = false;
+                io.scale_b = scale + (size_t)b * lb;
+                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                io.slot_stride = w.casc_slot;
+                if (i == 0 && fuse_j) {
+                    RCX_HIP_TRY(timed(p, i, st, [&] {
+                        return launch_march_merge_j_incl(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, J, b * lb,
+                                                         nvalid, sc, wt, st);
+                    }));
+                    continue;
+                }
+                RCX_HIP_TRY(timed(p, i, st, [&] {
+                    return launch_march_merge_incl(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, sc, st);
+                }));
+                up = bufs[cur];
+                cur ^= 1;
+            }
+            if (!fuse_j) {
+                RCX_HIP_TRY(timed(p, -1, st, [&] {
+                    hipError_t e = hipSuccess;
+                    for (int m = 0; m < kInclSlots && e == hipSuccess; ++m)
+                        e = launch_j((const float*)up + m * w.casc_slot, J, b * lb, nvalid, ncell, p->prm.c0_dirs,
+                                     wt[m], m > 0, st);
+                    return e;
+                }));
+            }
+        }
+        return ok();
+    }
     // one pass per inclination (Gauss-Radau in mu, the path length per
     // projected cell scaled by 1/sin): J = sum_m w_m J_m, written by the first
     // pass and accumulated by the others

@@ -168,22 +168,24 @@ def test_fp16_storage_error_is_bounded(which):
     assert rel.max() < 2e-3
 
 
-@pytest.mark.parametrize("case", ["blobs64_incl8", "ragged_w20_incl3", "line96_w40_incl8_fp16"])
+@pytest.mark.parametrize("case", ["blobs64_incl8", "ragged_w20_incl3", "ragged_w20_incl8", "line96_w40_incl8_fp16"])
 def test_inclined_formal_solve_matches_oracle(case):
     """2D invariance (Sec. 4.1): n_incl rays per flatland ray on a
     Gauss-Radau rule in mu = cos(inclination to y), each with the path per
     projected cell 1/sqrt(1 - mu^2) times longer; J the weighted sum. Cases:
     the paper's 8 inclinations on the 64^2 blobs, 3 on a ragged grid with a
-    pair and an odd 16-wavelength batch, and 8 with FP16 cascade storage
-    (bounded as in the FP16 test)."""
+    pair and an odd 16-wavelength batch (one pass per inclination), 8 on it
+    (the 8 inclinations as slots of one march), and 8 with FP16 cascade
+    storage (one pass per inclination; bounded as in the FP16 test)."""
     if case == "blobs64_incl8":
         inp, ni, st, tol = W.blobs_medium(64, seed=1), 8, 0, RTOL
-    elif case == "ragged_w20_incl3":
+    elif case.startswith("ragged_w20"):
         rng = np.random.default_rng(11)
         nx, nz, nw = 37, 53, 20
         chi = (10 ** rng.uniform(-2, 2, (nw, nz, nx))).astype(np.float32)
         eta = (chi * rng.uniform(0.2, 3.0, (nw, nz, nx))).astype(np.float32)
-        inp, ni, st, tol = W.FormalSolveInput(chi, eta, 1.0, W.n_cascades_for(nx, nz), "rand37x53w20"), 3, 0, RTOL
+        ni = 3 if case.endswith("incl3") else 8
+        inp, st, tol = W.FormalSolveInput(chi, eta, 1.0, W.n_cascades_for(nx, nz), "rand37x53w20"), 0, RTOL
     else:
         inp, ni, st, tol = W.line_medium(96, 64, seed=5, wave_subset=np.arange(0, 40)), 8, 1, 2e-3
     Jg = _gpu_solve(inp, n_incl=ni, storage=st)
