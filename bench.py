@@ -58,7 +58,7 @@ def parse():
                          "32..256 wavelengths; ~190 GB of device memory, a few minutes)")
     ap.add_argument("--nlte-only", action="store_true",
                     help="only the converged non-LTE solves (for profiling; prints their object)")
-    ap.add_argument("--nlte-variants", default="plain_fp32,learned_fp16",
+    ap.add_argument("--nlte-variants", default="plain_fp32,learned_fp16,ng_fp32,learned_ng_fp16",
                     help="comma-separated subset of the non-LTE runs")
     ap.add_argument("--nlte-n", type=int, default=1024)
     ap.add_argument("--nlte-max-iter", type=int, default=300)
@@ -166,9 +166,11 @@ def nlte_solves(args):
     net = None
     if os.path.exists(args.weights):
         net, fn, tn = warmstart.load(args.weights)
-    runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False)]
+    runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False),
+            ("ng_fp32", rcx.RCX_STORE_F32, False)]
     if net is not None:
-        runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True)]
+        runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True),
+                 ("learned_ng_fp16", rcx.RCX_STORE_F16_SCALED, True)]
     wanted = set(args.nlte_variants.split(","))
     runs = [r for r in runs if r[0] in wanted]
     final = {}
@@ -178,6 +180,10 @@ def nlte_solves(args):
         p = s.lte()
         s.iterate(p, 1, 0.0)
         torch.cuda.synchronize()
+        if "ng_" in name:
+            # Ng acceleration (not in the paper): order 2, first after 4
+            # iterations, then every 4
+            s.set_acceleration(2, 4, 4)
         t0 = time.perf_counter()
         p = s.warm_start(net, fn, tn) if learned else s.lte()
         it, rc, ch = 0, 1, float("inf")

@@ -281,14 +281,28 @@ int32_t rcx_nlte_formal_solve_rates(rcx_nlte* s, const double* pops, float* rate
 int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops_inout,
                          double* max_rel_change_host, hipStream_t stream);
 
-/* Plain iteration (no acceleration, Sec. 3.3) from pops_inout until the max
- * relative change drops below tol or max_iter iterations: formal solution
- * with rates, statistical equilibrium, repeat. Returns RCX_OK when
- * converged, RCX_W_NOT_CONVERGED when max_iter was reached. *iters_host and
- * *last_change_host report the iterations run and the last change.
- * Synchronises the stream once per iteration (8 bytes). */
+/* The iteration of Sec. 3.3 from pops_inout until the max relative change
+ * drops below tol or max_iter iterations: formal solution with rates,
+ * statistical equilibrium, repeat (the paper's plain iteration; with
+ * rcx_nlte_set_acceleration, Ng acceleration after the equilibrium step).
+ * Returns RCX_OK when converged, RCX_W_NOT_CONVERGED when max_iter was
+ * reached. *iters_host and *last_change_host report the iterations run and
+ * the last change (of the equilibrium step, before any extrapolation).
+ * Synchronises the stream once per iteration (8 bytes), and once more per
+ * Ng step. */
 int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, double tol,
                          int32_t* iters_host, double* last_change_host, hipStream_t stream);
+
+/* Ng acceleration of rcx_nlte_iterate (not used by the paper; off by
+ * default): order M in [1, 3] (0 = off) extrapolates from the last M + 2
+ * iterates, x = (1 - sum c_j) x_0 + sum c_j x_j with c the least-squares
+ * solution of sum w (d_0 - sum_j c_j (d_0 - d_j))^2, d_k = x_k - x_{k+1},
+ * w = 1/x_0^2 (Ng 1974; Auer 1987), first after `delay` iterations, then
+ * every `period`; the iterate history restarts after each extrapolation and
+ * at this call. Allocates (M_max + 2) x n_levels x ncell FP64 of device
+ * memory on first use. RCX_E_INVALID for order outside [0, 3], delay < 0
+ * or period < 1. */
+int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int32_t period);
 
 /* Line profile of the march (the Voigt function H(a, x) of Sec. 4.1's line
  * opacity), chosen at rcx_nlte_set_atmosphere:

@@ -144,6 +144,28 @@ def lte_populations(atom: Atom, T, ne, ntot):
 # -------------------------------------------------------------- problem
 
 
+def ng_extrapolate(xs, M: int):
+    """Ng acceleration (Ng 1974; least-squares form of Auer 1987) from the
+    iterates xs[0] (newest) .. xs[M + 1]: with d_k = x_k - x_{k+1} and
+    w = 1 / x_0^2, minimise sum w (d_0 - sum_j c_j (d_0 - d_j))^2 over c and
+    return (1 - sum c) x_0 + sum_j c_j x_j (None if the normal equations are
+    singular)."""
+    x = [np.asarray(v, dtype=np.float64).ravel() for v in xs]
+    d = [x[k] - x[k + 1] for k in range(M + 1)]
+    w = 1.0 / x[0] ** 2
+    e = [d[0] - d[j] for j in range(1, M + 1)]
+    A = np.array([[np.sum(w * e[a] * e[b]) for b in range(M)] for a in range(M)])
+    b = np.array([np.sum(w * d[0] * e[a]) for a in range(M)])
+    try:
+        c = np.linalg.solve(A, b)
+    except np.linalg.LinAlgError:
+        return None
+    if not np.all(np.isfinite(c)):
+        return None
+    out = (1.0 - c.sum()) * x[0] + sum(c[j - 1] * x[j] for j in range(1, M + 1))
+    return out.reshape(np.shape(xs[0]))
+
+
 class Problem:
     """Static (population-independent) data of one non-LTE problem."""
 
@@ -308,15 +330,26 @@ class Problem:
         change = float(np.max(np.abs(new - pops) / np.abs(new)))
         return new, change
 
-    def iterate(self, pops, n_iter: int, tol: float | None = None):
-        """Plain iteration (no acceleration). Stops after n_iter iterations or
-        once the max relative change drops below tol."""
+    def iterate(self, pops, n_iter: int, tol: float | None = None, ng: tuple | None = None):
+        """The iteration of Sec. 3.3: formal solution with rates, then the
+        equilibrium step. Stops after n_iter iterations or once the max
+        relative change drops below tol. ng = (order M, delay, period) adds Ng
+        acceleration after the equilibrium step (not used by the paper)."""
         changes = []
-        for _ in range(n_iter):
+        hist = []  # newest last
+        for it in range(1, n_iter + 1):
             J, I0, chi_loc, H_loc, _ = self.formal_solve(pops)
             Rup, Rdn = self.rates(pops, I0, chi_loc, H_loc)
             pops, ch = self.stat_eq(pops, Rup, Rdn)
             changes.append(ch)
             if tol is not None and ch < tol:
                 break
+            if ng is not None and ng[0] > 0:
+                M, delay, period = ng
+                hist = (hist + [pops.copy()])[-(M + 2):]
+                if len(hist) == M + 2 and it >= delay and (it - delay) % period == 0:
+                    acc = ng_extrapolate(hist[::-1], M)
+                    if acc is not None:
+                        pops = acc
+                        hist = [pops.copy()]
         return pops, changes

@@ -875,6 +875,13 @@ struct rcx_nlte {
     double da_c = 1.0;
     bool small_a = false;     // every a <= kSmallAMax: expansion in a
     int32_t profile_mode = RCX_PROFILE_AUTO;
+    // Ng acceleration: order M (0 = off), first after ng_delay iterations,
+    // then every ng_period; ring of the last M + 2 iterates
+    int32_t ng_order = 0, ng_delay = 0, ng_period = 1;
+    int32_t ng_count = 0, ng_head = 0, ng_iter = 0;
+    double* ng_hist = nullptr;   // [M + 2][nl][ncell]
+    double* ng_part = nullptr;   // [kNgBlocks][kNgSums] partial sums
+    double* ng_sums = nullptr;   // [kNgSums]
     bool atm_set = false;
     float* u_all = nullptr;    // [n_wave]
     float* dnu_all = nullptr;  // [n_wave]
@@ -1331,6 +1338,160 @@ int32_t rcx_nlte_formal_solve_rates(rcx_nlte* s, const double* pops, float* rate
     return formal_solve_rates(s, pops, rates, J, st);
 }
 
+// ---------------------------------------------------- Ng acceleration
+// Ng (1974), in the least-squares form of Auer (1987): with iterates x_0
+// (newest) .. x_{M+1} and differences d_k = x_k - x_{k+1}, choose c_1..c_M
+// minimising sum w (d_0 - sum_j c_j (d_0 - d_j))^2 with w = 1 / x_0^2, i.e.
+// A c = b, A_ij = sum w (d_0 - d_i)(d_0 - d_j), b_i = sum w d_0 (d_0 - d_i);
+// then x = (1 - sum_j c_j) x_0 + sum_j c_j x_j.
+constexpr int kNgMaxOrder = 3;
+constexpr int kNgSums = kNgMaxOrder * (kNgMaxOrder + 1) / 2 + kNgMaxOrder;
+constexpr int kNgBlocks = 512;
+
+struct NgPtrs {
+    const double* x[kNgMaxOrder + 2];  // x_0 newest
+};
+
+__global__ __launch_bounds__(256) void k_ng_sums(NgPtrs P, int32_t M, int64_t n, double* __restrict__ part)
+{
+    double acc[kNgSums];
+#pragma unroll
+    for (int k = 0; k < kNgSums; ++k) acc[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double x[kNgMaxOrder + 2], d[kNgMaxOrder + 1];
+        for (int k = 0; k < M + 2; ++k) x[k] = P.x[k][i];
+        for (int k = 0; k < M + 1; ++k) d[k] = x[k] - x[k + 1];
+        const double w = 1.0 / (x[0] * x[0]);
+        int q = 0;
+        for (int a = 1; a <= M; ++a)
+            for (int b = a; b <= M; ++b) acc[q++] += w * (d[0] - d[a]) * (d[0] - d[b]);
+        for (int a = 1; a <= M; ++a) acc[q++] += w * d[0] * (d[0] - d[a]);
+    }
+    // block sum in a fixed order (deterministic)
+    __shared__ double red[kNgSums][256];
+    for (int k = 0; k < kNgSums; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < kNgSums; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < kNgSums) part[(int64_t)blockIdx.x * kNgSums + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_ng_reduce(const double* __restrict__ part, int32_t nblocks, double* __restrict__ sums)
+{
+    if (threadIdx.x < kNgSums) {
+        double t = 0.0;
+        for (int b = 0; b < nblocks; ++b) t += part[(int64_t)b * kNgSums + threadIdx.x];
+        sums[threadIdx.x] = t;
+    }
+}
+
+struct NgCoef {
+    double c[kNgMaxOrder];
+};
+
+__global__ void k_ng_update(NgPtrs P, int32_t M, NgCoef C, int64_t n, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double csum = 0.0, v = 0.0;
+    for (int j = 1; j <= M; ++j) {
+        csum += C.c[j - 1];
+        v += C.c[j - 1] * P.x[j][i];
+    }
+    out[i] = (1.0 - csum) * P.x[0][i] + v;
+}
+
+// Solve the M x M system (partial pivoting); false if it is singular.
+static bool ng_solve(int M, double A[kNgMaxOrder][kNgMaxOrder], double b[kNgMaxOrder], double c[kNgMaxOrder])
+{
+    for (int k = 0; k < M; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < M; ++r)
+            if (std::fabs(A[r][k]) > std::fabs(A[piv][k])) piv = r;
+        if (!(std::fabs(A[piv][k]) > 0.0)) return false;
+        if (piv != k) {
+            for (int cc = 0; cc < M; ++cc) std::swap(A[k][cc], A[piv][cc]);
+            std::swap(b[k], b[piv]);
+        }
+        for (int r = k + 1; r < M; ++r) {
+            const double f = A[r][k] / A[k][k];
+            for (int cc = k; cc < M; ++cc) A[r][cc] -= f * A[k][cc];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = M - 1; k >= 0; --k) {
+        double t = b[k];
+        for (int cc = k + 1; cc < M; ++cc) t -= A[k][cc] * c[cc];
+        c[k] = t / A[k][k];
+        if (!std::isfinite(c[k])) return false;
+    }
+    return true;
+}
+
+// After an iteration: keep pops in the ring; when the schedule says so and
+// M + 2 iterates are held, replace pops by the extrapolation (the ring then
+// restarts from it).
+static int32_t ng_step(rcx_nlte* s, double* pops, hipStream_t st)
+{
+    const int32_t M = s->ng_order;
+    const int64_t n = (int64_t)s->atom.nl * s->ncell;
+    const int32_t slots = M + 2;
+    ++s->ng_iter;
+    RCX_HIP_TRY(hipMemcpyAsync(s->ng_hist + (size_t)s->ng_head * n, pops, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st));
+    s->ng_head = (s->ng_head + 1) % slots;
+    s->ng_count = std::min(s->ng_count + 1, slots);
+    if (s->ng_count < slots || s->ng_iter < s->ng_delay || (s->ng_iter - s->ng_delay) % s->ng_period != 0)
+        return RCX_OK;
+    NgPtrs P{};
+    for (int k = 0; k < slots; ++k)  // newest first
+        P.x[k] = s->ng_hist + (size_t)((s->ng_head - 1 - k + 2 * slots) % slots) * n;
+    hipLaunchKernelGGL(k_ng_sums, dim3(kNgBlocks), dim3(256), 0, st, P, M, n, s->ng_part);
+    RCX_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ng_reduce, dim3(1), dim3(64), 0, st, s->ng_part, kNgBlocks, s->ng_sums);
+    RCX_HIP_TRY(hipGetLastError());
+    double sums[kNgSums];
+    RCX_HIP_TRY(hipMemcpyAsync(sums, s->ng_sums, sizeof(sums), hipMemcpyDeviceToHost, st));
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    double A[kNgMaxOrder][kNgMaxOrder], b[kNgMaxOrder], c[kNgMaxOrder];
+    int q = 0;
+    for (int a = 0; a < M; ++a)
+        for (int bb = a; bb < M; ++bb) A[a][bb] = A[bb][a] = sums[q++];
+    for (int a = 0; a < M; ++a) b[a] = sums[q++];
+    if (!ng_solve(M, A, b, c)) return RCX_OK;  // degenerate: keep the plain iterate
+    NgCoef C{};
+    for (int j = 0; j < M; ++j) C.c[j] = c[j];
+    hipLaunchKernelGGL(k_ng_update, dim3(blocks_for(n, 256)), dim3(256), 0, st, P, M, C, n, pops);
+    RCX_HIP_TRY(hipGetLastError());
+    // restart the ring from the extrapolated iterate
+    RCX_HIP_TRY(hipMemcpyAsync(s->ng_hist, pops, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    s->ng_head = 1 % slots;
+    s->ng_count = 1;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int32_t period)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_acceleration: null solver");
+    if (order < 0 || order > kNgMaxOrder || delay < 0 || period < 1)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_acceleration: order in [0, 3], delay >= 0, period >= 1");
+    const int64_t n = (int64_t)s->atom.nl * s->ncell;
+    if (order > 0 && !s->ng_hist) {
+        if (dmalloc(s, &s->ng_hist, sizeof(double) * (kNgMaxOrder + 2) * n) != hipSuccess ||
+            dmalloc(s, &s->ng_part, sizeof(double) * kNgBlocks * kNgSums) != hipSuccess ||
+            dmalloc(s, &s->ng_sums, sizeof(double) * kNgSums) != hipSuccess)
+            return nlte_fail(RCX_E_NOMEM, "rcx_nlte_set_acceleration: device allocation");
+    }
+    s->ng_order = order;
+    s->ng_delay = delay;
+    s->ng_period = period;
+    s->ng_count = s->ng_head = s->ng_iter = 0;
+    return RCX_OK;
+}
+
 static int32_t stat_eq(rcx_nlte* s, const float* rates, double* pops, double* change_host, hipStream_t st)
 {
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, s->d_max);
@@ -1379,6 +1540,10 @@ int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops, int32_t max_iter, double tol
         *iters_host = it + 1;
         *last_change_host = ch;
         if (ch < tol) return RCX_OK;
+        if (s->ng_order > 0) {
+            rc = ng_step(s, pops, st);
+            if (rc != RCX_OK) return rc;
+        }
     }
     return RCX_W_NOT_CONVERGED;
 }

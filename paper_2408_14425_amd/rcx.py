@@ -274,6 +274,7 @@ def _load_nlte():
                                   vp, vp, vp, C.POINTER(vp)]
     L.rcx_nlte_set_atmosphere.argtypes = [vp, vp, vp, vp, vp, vp]
     L.rcx_nlte_set_line_profile.argtypes = [vp, i32]
+    L.rcx_nlte_set_acceleration.argtypes = [vp, i32, i32, i32]
     L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
     L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -305,6 +306,11 @@ def rcx_nlte_create(grid: rcx_grid, params: rcx_params, atom: rcx_atom, lambda_n
     _check(_load_nlte().rcx_nlte_create(C.byref(grid), C.byref(params), C.byref(atom), len(lam), lam.ctypes.data,
                                         tr.ctypes.data, dn.ctypes.data, C.byref(h)), "rcx_nlte_create")
     return h.value
+
+
+def rcx_nlte_set_acceleration(s: int, order: int, delay: int, period: int) -> int:
+    return _check(_load_nlte().rcx_nlte_set_acceleration(s, int(order), int(delay), int(period)),
+                  "rcx_nlte_set_acceleration")
 
 
 def rcx_nlte_set_line_profile(s: int, mode: int) -> int:
@@ -403,6 +409,10 @@ class Nlte:
 
     def iterate(self, pops, max_iter: int, tol: float):
         return rcx_nlte_iterate(self.handle, pops, max_iter, tol)
+
+    def set_acceleration(self, order: int, delay: int = 0, period: int = 1):
+        """Ng acceleration of iterate() (order 0 = off)."""
+        rcx_nlte_set_acceleration(self.handle, order, delay, period)
 
     def voigt(self, a, x, march: bool = False):
         """H(a, x) from the solver's tables: the full table (features), or

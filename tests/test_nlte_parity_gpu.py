@@ -153,6 +153,34 @@ def test_converged_at_oracle_iteration_count(case32):
     assert rc2 == 0 and abs(it2 - K) <= 1 and ch2 < 1e-3
 
 
+def test_ng_accelerated_iteration_matches_oracle(case32):
+    """Ng acceleration (order 2, first after 4 iterations, then every 4):
+    the oracle converges in fewer iterations than the plain iteration; the
+    GPU run for the same count agrees with it to 1e-3 and its own stopping
+    test fires within one iteration of that count."""
+    _torch()
+    inp, P = case32
+    _, plain = P.iterate(P.lte.copy(), 200, tol=1e-3)
+    po, changes = P.iterate(P.lte.copy(), 200, tol=1e-3, ng=(2, 4, 4))
+    K = len(changes)
+    s = _solver(inp)
+    s.set_acceleration(2, 4, 4)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, K, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.set_acceleration(2, 4, 4)
+    pops2 = s.lte()
+    rc2, it2, ch2 = s.iterate(pops2, K + 2, 1e-3)
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"ng: oracle {K} iterations (plain {len(plain)}); gpu after {it}: max rel {relp.max():.3e}; "
+          f"gpu stopping test: rc {rc2} at {it2} ({ch2:.3e})")
+    assert K < len(plain)
+    assert it == K
+    assert relp.max() < 1e-3
+    assert rc2 == 0 and abs(it2 - K) <= 1
+
+
 def test_fp16_storage_converged_populations(case32):
     """FP16 scaled cascade storage inside the non-LTE iteration. The storage
     is linear FP16 with one power-of-two scale per wavelength, set by the

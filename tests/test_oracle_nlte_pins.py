@@ -182,3 +182,24 @@ def test_fixed_point_balances_unpreconditioned_rates():
     res = np.einsum("cij,jc->ic", G, pops)
     scale = np.einsum("cij,jc->ic", np.abs(G), pops)
     assert np.max(np.abs(res) / scale) < 1e-6
+
+
+@pytest.mark.parametrize("M,rates", [(1, (0.9,)), (2, (0.93, 0.6)), (3, (0.95, 0.7, -0.4))])
+def test_ng_extrapolation_recovers_fixed_point_of_linear_iteration(M, rates):
+    """Ng of order M is exact when the error of the iterates spans M
+    geometric modes, x_k = x* + sum_m a_m r_m^k (minimal-polynomial
+    extrapolation): from the M + 2 newest iterates it returns x*."""
+    from oracle.nlte import ng_extrapolate
+    rng = np.random.default_rng(M)
+    xstar = rng.uniform(1.0, 2.0, (3, 40))
+    modes = [rng.normal(0.0, 0.05, xstar.shape) for _ in rates]
+    xs = [xstar + sum(a * r ** k for a, r in zip(modes, rates)) for k in range(6, 6 + M + 2)]
+    got = ng_extrapolate(xs[::-1], M)
+    np.testing.assert_allclose(got, xstar, rtol=1e-9, atol=0)
+
+
+def test_ng_extrapolation_of_converged_iterates_is_identity():
+    """Iterates that no longer change give a singular system: no step."""
+    from oracle.nlte import ng_extrapolate
+    x = np.full((2, 5), 1.5)
+    assert ng_extrapolate([x, x, x, x], 2) is None
