@@ -7,10 +7,13 @@
 // Wavelengths are processed in batches of 16 (kLB). Data layout in HBM, with
 // c = z * nx + x the cell index and l the wavelength within a batch:
 //   F       [batch][c][16]          float2 {chi * voxel * log2(e) (floored), S = eta/chi}
-//   cascade [(p * N_i + k)][16]     float  merged radiance of probe p, direction k
+//   cascade [slot][(p * N_i + k)][16] float merged radiance of probe p, direction k;
+//                                   slot 1 = the second batch of a pair, slots 0-7
+//                                   = the inclinations, a fixed stride apart
 //   J       [lambda][c]             float  (the caller's layout)
-// A batch of F is 128 MB at 1024^2 (half the 256 MB Infinity Cache); every
-// cascade of one batch is marched before the next batch starts.
+// A batch of F is 128 MB at 1024^2 (half the 256 MB Infinity Cache); the
+// cascades of a batch (or of a pair of batches) are marched top-down before
+// the next batch starts.
 #include "march_rows.h"
 
 #include <cmath>
