@@ -36,7 +36,7 @@ def build_oracle(verbose: bool = False) -> str:
 class Geom(C.Structure):
     _fields_ = [
         ("nx", C.c_int32), ("nz", C.c_int32), ("n_casc", C.c_int32), ("c0_dirs", C.c_int32),
-        ("t1", C.c_double), ("t_rule", C.c_int32), ("pad_", C.c_int32), ("voxel", C.c_double),
+        ("t1", C.c_double), ("t_rule", C.c_int32), ("bilinear_fix", C.c_int32), ("voxel", C.c_double),
     ]
 
 
@@ -95,8 +95,8 @@ def _f64(a) -> np.ndarray:
 
 
 def make_geom(nx: int, nz: int, n_casc: int, c0_dirs: int = 4, t1: float = 1.5,
-              t_rule: int = 0, voxel: float = 1.0) -> Geom:
-    return Geom(nx, nz, n_casc, c0_dirs, t1, t_rule, 0, voxel)
+              t_rule: int = 0, voxel: float = 1.0, bilinear_fix: bool = False) -> Geom:
+    return Geom(nx, nz, n_casc, c0_dirs, t1, t_rule, int(bool(bilinear_fix)), voxel)
 
 
 def t_start(g: Geom, i: int) -> float:
@@ -158,15 +158,18 @@ def merge_level(g: Geom, i: int, I_i, tau_i, I_up, need=None):
 
 
 def formal_solve(chi, eta, n_casc: int, voxel: float = 1.0, c0_dirs: int = 4, t1: float = 1.5,
-                 t_rule: int = 0, need=None, want_I0: bool = False, n_threads: int = 0):
+                 t_rule: int = 0, need=None, want_I0: bool = False, n_threads: int = 0,
+                 bilinear_fix: bool = False):
     """RC formal solve in FP64. chi, eta: [n_wave][nz][nx]. Returns J (and the
     merged cascade-0 radiance [n_wave][nz][nx][N_0] if ``want_I0``) and stats
-    (rays, non-empty rays, cell steps)."""
+    (rays, non-empty rays, cell steps). ``bilinear_fix``: every cascade below
+    the top traces each interval once per bilinear probe of the cascade
+    above, to the start of that probe's child cone (Sec. 2.5)."""
     chi, eta = _f64(chi), _f64(eta)
     if chi.ndim == 2:
         chi, eta = chi[None], eta[None]
     nw, nz, nx = chi.shape
-    g = make_geom(nx, nz, n_casc, c0_dirs, t1, t_rule, voxel)
+    g = make_geom(nx, nz, n_casc, c0_dirs, t1, t_rule, voxel, bilinear_fix)
     J = np.zeros((nw, nz, nx))
     I0 = np.zeros((nw, nz, nx, c0_dirs)) if want_I0 else None
     st = np.zeros(3, np.int64)

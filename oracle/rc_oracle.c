@@ -20,6 +20,8 @@
  *     clamped at the grid edge                                    (Sec. 2.3.1, Sec. 2.5)
  *   - each ray of cascade i merges with its 2*alpha = 4 children  (Sec. 2.3.1)
  *   - iterative top-down merge                                    (Sec. 2.3.1)
+ *   - optional bilinear fix: each merged interval traced once per
+ *     bilinear probe, to the start of that probe's child cone      (Sec. 2.5)
  *   - piecewise-constant integration per cell, back to front      (Sec. 3.2, RTE solution)
  *   - free-space boundary: nothing enters the domain              (Sec. 3.4)
  *   - J = angular average of the merged cascade-0 radiance        (Sec. 1, Eq. J; flatland)
@@ -42,6 +44,11 @@
  *   - chi -> 0 is handled by writing the emission term as eta ds phi1(chi ds),
  *     phi1(x) = (1 - e^{-x}) / x, phi1(0) = 1.
  *   - Flatland angular quadrature: J = (1/N_0) sum_k I_0(k).
+ *   - Bilinear fix: the child cone of direction k on a probe q of cascade
+ *     i+1 is the cone of k's four children, so its start is q + t_{i+1} w_k;
+ *     the top cascade has no cascade above and keeps its own rays; a probe
+ *     below a top cascade that lies wholly outside the domain still traces
+ *     its four intervals (merged with nothing).
  */
 #include <math.h>
 #include <stdint.h>
@@ -293,6 +300,84 @@ void ora_merge_level(const ora_geom* g, int32_t i, int32_t n_wave, const double*
     }
 }
 
+/* Bilinear fix (Sec. 2.5, the ringing artefact and its remedy): an
+ * interval of cascade i below the top is traced not along its own ray but,
+ * once for each of the four probes q of cascade i+1 it interpolates from,
+ * from its usual start p + t_i w_k to the start q + t_{i+1} w_k of the
+ * child cone on q (the cone of direction k holds the children 4k..4k+3, so
+ * its centre is w_k). Each of these four intervals is merged with the
+ * children of its own probe, and the four results are averaged with the
+ * usual bilinear weights:
+ *   Itilde_i(p,k) = sum_taps w_x w_z M( R(p + t_i w_k -> q + t_{i+1} w_k),
+ *                                       (1/4) sum_j Itilde_{i+1}(q, 4k+j) ).
+ * Iup == NULL means the upper cascade contributes nothing. Outputs
+ * [n_wave][pz][px][dirs] merged. Returns the cell steps; counts the
+ * non-empty traced rays into *n_nonempty. */
+static int64_t level_fix(const ora_geom* g, int32_t i, int32_t n_wave, ora_opac_fn opac, const void* ctx,
+                         const uint8_t* need, const double* Iup, double* Iout, int64_t* n_nonempty)
+{
+    int32_t px = ora_level_px(g, i), pz = ora_level_pz(g, i), nd = ora_level_dirs(g, i);
+    int32_t qx = ora_level_px(g, i + 1), qz = ora_level_pz(g, i + 1), nd_up = nd * 4;
+    double s = ora_level_spacing(i), s_up = ora_level_spacing(i + 1);
+    double ta = ora_t_start(g, i), tb = ora_t_start(g, i + 1);
+    int32_t max_seg = g->nx + g->nz + 8;
+    int64_t steps = 0, nonempty = 0;
+#pragma omp parallel reduction(+ : steps, nonempty)
+    {
+        int32_t* sx = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+        int32_t* sz = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+        double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)max_seg);
+        double *sdt = buf, *schi = buf + max_seg, *seta = buf + 2 * max_seg, *sds = buf + 3 * max_seg;
+        int64_t total = (int64_t)n_wave * pz * px * nd;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < total; ++r) {
+            int32_t k = (int32_t)(r % nd);
+            int64_t pr = r / nd;
+            int32_t u = (int32_t)(pr % px);
+            int32_t v = (int32_t)((pr / px) % pz);
+            int32_t lam = (int32_t)(pr / ((int64_t)px * pz));
+            if (need && !need[(size_t)v * px + u]) continue;
+            int32_t tx[2], tz[2];
+            double wxv[2], wzv[2];
+            bilinear_taps((u + 0.5) * s, s_up, qx, tx, wxv);
+            bilinear_taps((v + 0.5) * s, s_up, qz, tz, wzv);
+            double wx, wz;
+            ora_direction(g, i, k, &wx, &wz);
+            /* the interval's usual start */
+            double ax = (u + 0.5) * s + ta * wx, az = (v + 0.5) * s + ta * wz;
+            double acc = 0.0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    /* start of the child cone on tap probe (tx[b], tz[a]) */
+                    double ex = (tx[b] + 0.5) * s_up + tb * wx, ez = (tz[a] + 0.5) * s_up + tb * wz;
+                    double len = hypot(ex - ax, ez - az);
+                    double In = 0.0, tn = 0.0;
+                    if (len > 0.0) {
+                        int32_t n = march_ray(g, opac, ctx, lam, ax, az, (ex - ax) / len, (ez - az) / len, 0.0,
+                                              len, sx, sz, sdt, schi, seta, sds, max_seg, &In, &tn);
+                        steps += n;
+                        nonempty += (n > 0);
+                    }
+                    double far = 0.0;
+                    if (Iup) {
+                        size_t base = (((size_t)lam * qz + tz[a]) * qx + tx[b]) * nd_up + 4 * (size_t)k;
+                        for (int j = 0; j < 4; ++j) far += Iup[base + j];
+                        far *= 0.25;
+                    }
+                    double I, tau;
+                    ora_merge(In, tn, far, 0.0, &I, &tau);
+                    acc += wzv[a] * wxv[b] * I;
+                }
+            Iout[r] = acc;
+        }
+        free(sx);
+        free(sz);
+        free(buf);
+    }
+    if (n_nonempty) *n_nonempty += nonempty;
+    return steps;
+}
+
 /* Raw (unmerged) intervals of cascade i for the probes in need (nullable).
  * Outputs [n_wave][pz][px][dirs]. Returns the number of cell steps taken. */
 static int64_t level_raw(const ora_geom* g, int32_t i, int32_t n_wave, ora_opac_fn opac,
@@ -377,16 +462,24 @@ int32_t ora_rc_solve(const ora_geom* g, int32_t n_wave, ora_opac_fn opac, const 
     double* up = NULL; /* merged cascade i+1 */
     for (int32_t i = I - 1; i >= 0; --i) {
         size_t n = (size_t)n_wave * ora_level_px(g, i) * ora_level_pz(g, i) * ora_level_dirs(g, i);
-        double* raw_I = (double*)calloc(n, sizeof(double));
-        double* raw_tau = (double*)calloc(n, sizeof(double));
         double* merged = (double*)calloc(n, sizeof(double));
-        steps += level_raw(g, i, n_wave, opac, ctx, need[i], raw_I, raw_tau, &nonempty);
+        const int fix = g->bilinear_fix && i < I - 1;
         {
             int64_t cnt = 0;
             size_t np = (size_t)ora_level_px(g, i) * ora_level_pz(g, i);
             for (size_t p = 0; p < np; ++p) cnt += need[i][p];
-            rays += cnt * (int64_t)ora_level_dirs(g, i) * n_wave;
+            rays += cnt * (int64_t)ora_level_dirs(g, i) * n_wave * (fix ? 4 : 1);
         }
+        if (fix) {
+            /* four traced intervals per merged one (Sec. 2.5) */
+            steps += level_fix(g, i, n_wave, opac, ctx, need[i], up, merged, &nonempty);
+            free(up);
+            up = merged;
+            continue;
+        }
+        double* raw_I = (double*)calloc(n, sizeof(double));
+        double* raw_tau = (double*)calloc(n, sizeof(double));
+        steps += level_raw(g, i, n_wave, opac, ctx, need[i], raw_I, raw_tau, &nonempty);
         if (i == I - 1) {
             memcpy(merged, raw_I, n * sizeof(double)); /* top cascade: nothing beyond */
         } else {

@@ -10,7 +10,7 @@ typedef struct {
     int32_t c0_dirs;
     double t1;
     int32_t t_rule;
-    int32_t pad_;
+    int32_t bilinear_fix; /* 1: trace each merged interval to its 4 bilinear probes */
     double voxel;
 } ora_geom;
 
