@@ -51,6 +51,8 @@ def parse():
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
     ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--no-fix", action="store_true",
+                    help="skip the formal solve with the bilinear fix")
     ap.add_argument("--no-incl", action="store_true",
                     help="skip the 2D-invariant formal solve with 8 inclinations per flatland ray")
     ap.add_argument("--c4", action="store_true",
@@ -353,6 +355,26 @@ def main():
             "steps": stepsI,
         }
 
+    fix = None
+    if not args.no_fix:
+        # the same solve with the bilinear fix: 4 traced rays per interval on
+        # every cascade below the top
+        planF = rcx.Plan(inp.nx, inp.nz, inp.n_wave, bilinear_fix=True)
+        JF = torch.empty_like(chi)
+        stepsF = max(1, min(args.steps, 5))
+        dtF, (msF, _, _, nF) = time_solves(planF, chi, eta, JF, stepsF, 1)
+        planF.close()
+        top = work.n_cascades - 1
+        traced = (4 * sum(work.level_rays[:top]) + work.level_rays[top]) * inp.n_wave
+        fix = {
+            "ms_per_step": dtF / stepsF * 1e3,
+            "ray_intervals_traced_per_step": traced,
+            "traced_per_s": traced / (dtF / stepsF),
+            "kernel_ms_per_cascade": [m / max(nF, 1) for m in msF],
+            "max_rel_diff_vs_basic": float(((JF - J).abs() / J.abs()).max().item()),
+            "steps": stepsF,
+        }
+
     ms_step = dt / args.steps * 1e3
     rays = work.rays_nonempty * inp.n_wave
     value = rays / (dt / args.steps)
@@ -393,6 +415,7 @@ def main():
         },
         "fp16_storage": fp16,
         "inclined": incl,
+        "bilinear_fix": fix,
         "roofline": {
             "bound": "alu",
             "kernel": "k_march_rows",

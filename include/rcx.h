@@ -48,6 +48,8 @@ extern "C" {
  * largest source function along its path; cascade 0 stays FP32. */
 #define RCX_STORE_F32 0
 #define RCX_STORE_F16_SCALED 1
+/* rcx_params.flags */
+#define RCX_FLAG_BILINEAR_FIX 1u
 
 /* Uniform 2D grid. chi is per unit of voxel_scale length: the optical depth
  * of a path of dt cells is chi * dt * voxel_scale (Sec. 3.2). */
@@ -74,7 +76,16 @@ typedef struct {
  *               the formal solve
  *               (rcx_formal_solve) supports n_incl > 1; batches and the
  *               non-LTE solver return RCX_E_UNSUPPORTED for it.
- *   flags:      reserved, 0. */
+ *   flags:      RCX_FLAG_BILINEAR_FIX or 0 (other bits must be 0).
+ *               RCX_FLAG_BILINEAR_FIX (Sec. 2.5, the remedy for ringing and
+ *               for light leaking through thin occluders): every cascade
+ *               below the top traces each interval once per bilinear probe
+ *               q of the cascade above, from its start p + t_i w_k to the
+ *               start q + t_{i+1} w_k of the child cone on q, merges it with
+ *               q's children and sums the four results with the bilinear
+ *               weights (4 x the rays below the top cascade). Flatland only
+ *               (n_incl = 1), formal solve only: batches and the non-LTE
+ *               solver return RCX_E_UNSUPPORTED for it. */
 typedef struct {
     int32_t n_cascades;
     int32_t c0_dirs;
@@ -109,7 +120,8 @@ int32_t rcx_params_default(rcx_params* p);
  * direction tables on the device and allocates the plan-owned workspace
  * used when a call passes workspace == NULL.
  * Errors: RCX_E_INVALID (null, nx/nz/max_wave <= 0, c0_dirs <= 0,
- * c0_t1 <= 0, n_cascades outside [1, 16]); RCX_E_UNSUPPORTED (n_incl != 1,
+ * c0_t1 <= 0, n_cascades outside [1, 16], unknown flags); RCX_E_UNSUPPORTED
+ * (RCX_FLAG_BILINEAR_FIX with n_incl != 1,
  * unknown storage); RCX_E_NOMEM; RCX_E_HIP. On error *out is NULL. */
 int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* p, int32_t max_wave, rcx_plan** out);
 

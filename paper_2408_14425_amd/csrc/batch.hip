@@ -360,6 +360,7 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
     if (p->c0_dirs != 4) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: the fused J epilogue needs c0_dirs = 4");
     if (p->n_cascades != 0) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: cascades are chosen per atmosphere");
     if (p->n_incl != 1) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: flatland only (n_incl = 1)");
+    if (p->flags != 0) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: no flags (basic merge only)");
     rcx_batch* s = new (std::nothrow) rcx_batch();
     if (!s) return bfail(RCX_E_NOMEM, "rcx_batch_create: host allocation");
     s->n_atm = n_atm;

@@ -190,7 +190,36 @@ hipError_t launch_fs_up(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op
     up.stride = io.slot_stride;
     return launch_fs(L, nx, nz, op, epi, dirs, up, st);
 }
+
+// The bilinear-fix kernel: one interval per wavefront, so 4 x the
+// intervals' rows.
+template <class Op, class Epi, class Up>
+hipError_t launch_fix_k(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+                        const Up& up, hipStream_t st)
+{
+    const int64_t total = level_launch_rays(L);
+    hipLaunchKernelGGL((march::k_march_fix<Op, Epi, Up>), march_grid(4 * total), dim3(kBlock), 0, st, L, nx, nz, op,
+                       epi, dirs, up, total);
+    return hipGetLastError();
+}
 }  // namespace
+
+hipError_t launch_march_fix(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                            const CascIO& io, hipStream_t st)
+{
+    if (io.slot_stride != 0) return hipErrorInvalidValue;
+    march::FieldOp op{};
+    op.Fb = Fb;
+    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    if (!io.up_f16) {
+        const march::UpF32 up{(const float*)io.up};
+        if (!io.out_f16) return launch_fix_k(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
+        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
+    }
+    march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+    if (!io.out_f16) return launch_fix_k(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
+    return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
+}
 
 hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                               const CascIO& io, hipStream_t st)

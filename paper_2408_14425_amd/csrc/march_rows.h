@@ -136,9 +136,11 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
     T *= e;
 }
 
-// March, merge and finish one ray per row. ray = output index of the ray
-// in its cascade, (u, v, k) its probe and direction; active false for rows
-// past the end (they still take part in the wavefront-wide ballots).
+// Walk one ray per row: the segments of the line (cx, cz) + t (wx, wz),
+// t in [t_lo, t_hi), that lie in the domain (d = {wx, wz, 1/wx, 1/wz}),
+// stepped front to back into I and T (Op::kW slots per lane). Rows with walk
+// false step through nothing but still take part in the wavefront-wide
+// ballots.
 // An Op whose step data depends on the cell only (the same for all 16
 // wavelength lanes of a row) sets kStaged: the lane that finds a segment
 // loads that data once (Op::stage_load, then Op::stage_make forms the
@@ -146,34 +148,22 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
 // and the step loop reads it back from LDS (stg, this wavefront's
 // [4 rows][kSegs] entries) instead of issuing a dependent global load per
 // step; Op::resolve4 turns a group of 4 staged steps into {chi, S}.
-template <class Op, class Epi, class Up>
-__device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
-                                          const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[kSegRow],
-                                          typename Op::Stage (*stg)[kStgRow], const RowCtx& cx_, int64_t ray,
-                                          int32_t u, int32_t v, int32_t k, bool active)
+template <class Op>
+__device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, double cx, double cz,
+                                         const double4 d, double t_lo, double t_hi, bool walk,
+                                         uint4 (*seg)[kSegRow], typename Op::Stage (*stg)[kStgRow],
+                                         const RowCtx& cx_, float (&I)[Op::kW], float (&T)[Op::kW])
 {
-    const int lane = cx_.lane, row = cx_.row, l = cx_.l;
+    const int row = cx_.row, l = cx_.l;
     const uint64_t row_bits = cx_.row_bits, lt_bits = cx_.lt_bits;
-    RayInfo ri;
-    ri.ray = ray;
-    ri.active = active;
-    ri.k = k;
-    ri.u = u;
-    ri.v = v;
-
-    const double cx = (ri.u + 0.5) * L.s, cz = (ri.v + 0.5) * L.s;
-    const double4 d = dirs[ri.k];  // {wx, wz, 1/wx, 1/wz}
-    ri.wx = d.x;
-    ri.wz = d.y;
-    op.begin_ray(d.x, d.y);
     // Plane crossings t(X) = X / w - c / w, evaluated with one FMA so the
     // crossing of the domain's exit plane equals the clip bound exactly.
     const double offx = -cx * d.z, offz = -cz * d.w;
     const double ax = offx, bx = fma((double)nx, d.z, offx);
     const double az = offz, bz = fma((double)nz, d.w, offz);
-    double lo = fmax(L.ta, fmax(fmin(ax, bx), fmin(az, bz)));
-    double hi = fmin(L.tb, fmin(fmax(ax, bx), fmax(az, bz)));
-    if (!ri.active) {
+    double lo = fmax(t_lo, fmax(fmin(ax, bx), fmin(az, bz)));
+    double hi = fmin(t_hi, fmin(fmax(ax, bx), fmax(az, bz)));
+    if (!walk) {
         lo = 1.0;
         hi = 0.0;
     }
@@ -197,7 +187,6 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
     // batch w): the walk and the segment list serve all of them
     constexpr int W = Op::kW;
     static_assert(!Op::kStaged || W == 1, "staged ops march one batch");
-    float I[W], T[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         I[w] = 0.0f;
@@ -318,6 +307,33 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
         }
         wave_sync();
     }
+}
+
+// March, merge and finish one ray per row. ray = output index of the ray
+// in its cascade, (u, v, k) its probe and direction; active false for rows
+// past the end (they still take part in the wavefront-wide ballots).
+template <class Op, class Epi, class Up>
+__device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
+                                          const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[kSegRow],
+                                          typename Op::Stage (*stg)[kStgRow], const RowCtx& cx_, int64_t ray,
+                                          int32_t u, int32_t v, int32_t k, bool active)
+{
+    const int lane = cx_.lane, l = cx_.l;
+    RayInfo ri;
+    ri.ray = ray;
+    ri.active = active;
+    ri.k = k;
+    ri.u = u;
+    ri.v = v;
+
+    const double cx = (ri.u + 0.5) * L.s, cz = (ri.v + 0.5) * L.s;
+    const double4 d = dirs[ri.k];  // {wx, wz, 1/wx, 1/wz}
+    ri.wx = d.x;
+    ri.wz = d.y;
+    op.begin_ray(d.x, d.y);
+    constexpr int W = Op::kW;
+    float I[W], T[W];
+    walk_ray(L, nx, nz, op, cx, cz, d, L.ta, L.tb, ri.active, seg, stg, cx_, I, T);
 
     if (ri.active && L.has_up) {
         // Bilinear taps on the cascade above: q = (u + 1/2)/2 - 1/2, so
@@ -355,6 +371,33 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
     }
 }
 
+// Probe and direction of launch-order ray r (of total): probe-major, or
+// the tiled order of LevelDesc; active false past the end and on padding.
+__device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t r, int64_t total, int32_t& k, int32_t& u,
+                                           int32_t& v, bool& active)
+{
+    active = r < total;
+    const int64_t rr = active ? r : total - 1;
+    if (L.tile_p <= 0) {
+        k = (int32_t)(rr % L.nd);
+        const int32_t p = (int32_t)(rr / L.nd);
+        u = p % L.px;
+        v = p / L.px;
+    } else {
+        // group g = (probe tile, direction wedge), wedge fastest; within
+        // a group, direction fastest
+        const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
+        const int64_t g = rr / per, r_in = rr % per;
+        const int32_t nw = L.nd / L.tile_d;
+        const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
+        const int32_t pl = (int32_t)(r_in / L.tile_d);
+        k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
+        u = (t % ntx) * L.tile_p + pl % L.tile_p;
+        v = (t / ntx) * L.tile_p + pl / L.tile_p;
+        active = active && u < L.px && v < L.pz;
+    }
+}
+
 template <class Op, class Epi, class Up>
 __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
@@ -387,30 +430,103 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t n
     const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
     for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
-        const int64_t r = base + c.row;
-        bool active = r < total;
-        const int64_t rr = active ? r : total - 1;
         int32_t k, u, v;
-        if (L.tile_p <= 0) {
-            k = (int32_t)(rr % L.nd);
-            const int32_t p = (int32_t)(rr / L.nd);
-            u = p % L.px;
-            v = p / L.px;
-        } else {
-            // group g = (probe tile, direction wedge), wedge fastest; within
-            // a group, direction fastest
-            const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
-            const int64_t g = rr / per, r_in = rr % per;
-            const int32_t nw = L.nd / L.tile_d;
-            const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
-            const int32_t pl = (int32_t)(r_in / L.tile_d);
-            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
-            u = (t % ntx) * L.tile_p + pl % L.tile_p;
-            v = (t / ntx) * L.tile_p + pl / L.tile_p;
-            active = active && u < L.px && v < L.pz;
-        }
+        bool active;
+        ray_coords(L, base + c.row, total, k, u, v, active);
         const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;  // output index
         march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[Op::kStaged ? c.w : 0], c, ray, u, v, k, active);
+    }
+}
+
+// Bilinear fix (Sec. 2.5): the interval (u, v, k) of a cascade below the
+// top is traced once per bilinear probe q of the cascade above, from its
+// usual start p + t_a w_k to the start q + t_b w_k of the child cone on q
+// (the cone of k's four children, centred on w_k), merged with q's children
+// 4k..4k+3, and the four results are summed with the bilinear weights. The
+// 4 rows of a wavefront are the 4 taps of one interval (row = 2 * a + b for
+// tap z index a, x index b), so the sum is two cross-row shuffles; row 0
+// finishes the interval. Taps are clamped at the grid edge (as in the
+// basic merge) and keep their weights.
+template <class Op, class Epi, class Up>
+__device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
+                                              const double4* __restrict__ dirs, const Up& up, uint4 (*seg)[kSegRow],
+                                              typename Op::Stage (*stg)[kStgRow], const RowCtx& cx_, int64_t ray,
+                                              int32_t u, int32_t v, int32_t k, bool active)
+{
+    static_assert(Op::kW == 1, "the fix marches one batch per lane");
+    const int row = cx_.row, l = cx_.l;
+    const int ta_z = row >> 1, ta_x = row & 1;
+    // the same taps and weights as the basic merge
+    const int bx0 = (u - 1) >> 1, bz0 = (v - 1) >> 1;
+    const float fx = (u & 1) ? 0.25f : 0.75f;
+    const float fz = (v & 1) ? 0.25f : 0.75f;
+    const int tx = min(max(bx0 + ta_x, 0), L.qx - 1);
+    const int tz = min(max(bz0 + ta_z, 0), L.qz - 1);
+    const float wgt = (ta_x ? fx : 1.0f - fx) * (ta_z ? fz : 1.0f - fz);
+
+    const double4 dk = dirs[k];
+    const double s_up = 2.0 * L.s;
+    const double ax = (u + 0.5) * L.s + L.ta * dk.x, az = (v + 0.5) * L.s + L.ta * dk.y;
+    const double ex = (tx + 0.5) * s_up + L.tb * dk.x, ez = (tz + 0.5) * s_up + L.tb * dk.y;
+    const double dx = ex - ax, dz = ez - az;
+    const double len = sqrt(dx * dx + dz * dz);
+    // a zero-length ray walks nothing (any unit direction will do); an
+    // axis-parallel one gets a 1e-12 minor component, so its plane steps on
+    // that axis stay finite (its cells are unchanged)
+    double4 d = make_double4(0.6, 0.8, 1.0 / 0.6, 1.0 / 0.8);
+    if (len > 0.0) {
+        double wx = dx / len, wz = dz / len;
+        if (fabs(wx) < 1e-12) wx = wx < 0.0 ? -1e-12 : 1e-12;
+        if (fabs(wz) < 1e-12) wz = wz < 0.0 ? -1e-12 : 1e-12;
+        d = make_double4(wx, wz, 1.0 / wx, 1.0 / wz);
+    }
+    op.begin_ray(dk.x, dk.y);
+    float I[1], T[1];
+    walk_ray(L, nx, nz, op, ax, az, d, 0.0, len, active && len > 0.0, seg, stg, cx_, I, T);
+
+    float m = I[0];
+    if (active && L.has_up) {
+        const int64_t bi = (((int64_t)tz * L.qx + tx) * L.nd_up + 4 * (int64_t)k) * kLB + l;
+        const float c4 = up.get(bi, 0) + up.get(bi + kLB, 0) + up.get(bi + 2 * kLB, 0) + up.get(bi + 3 * kLB, 0);
+        m = fmaf(T[0], 0.25f * c4, m);
+    }
+    float sum = wgt * m;
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    RayInfo ri;
+    ri.ray = ray;
+    ri.active = active && row == 0;
+    ri.k = k;
+    ri.u = u;
+    ri.v = v;
+    ri.wx = dk.x;
+    ri.wz = dk.y;
+    epi.finish(ri, l, cx_.lane, sum, op);
+}
+
+// One interval per wavefront (its 4 taps on the 4 rows); total = intervals
+// of the launch (the tiled order of LevelDesc applies to intervals).
+template <class Op, class Epi, class Up>
+__global__ __launch_bounds__(kBlock, 4) void k_march_fix(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
+                                                       const double4* __restrict__ dirs, Up up, int64_t total)
+{
+    static_assert(!Op::kStaged && Op::kSmemBytes == 0, "the fix takes per-lane field ops");
+    __shared__ uint4 seg[kBlock / 64][4][kSegRow];
+    __shared__ typename Op::Stage stg[1][4][kStgRow];
+    const RowCtx c = row_ctx();
+    op.init(c.l);
+    epi.init(c.l);
+    up.init(c.l);
+    seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
+    wave_sync();
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x);
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t r = (int64_t)lb * (kBlock / 64) + c.w; r < total; r += stride) {
+        int32_t k, u, v;
+        bool active;
+        ray_coords(L, r, total, k, u, v, active);
+        const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;
+        march_fix_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[0], c, ray, u, v, k, active);
     }
 }
 

@@ -974,6 +974,7 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
         return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: atom exceeds the supported sizes");
     if (p->c0_dirs != 4) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: the rate epilogue needs c0_dirs = 4");
     if (p->n_incl != 1) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: flatland only (n_incl = 1)");
+    if (p->flags != 0) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: no flags (basic merge only)");
     const int32_t nt = atom->n_lines + atom->n_conts;
     if (nt < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: no transitions");
     for (int32_t k = 0; k < atom->n_lines; ++k)

@@ -222,6 +222,9 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
         return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
     if (prm->n_incl < 1 || prm->n_incl > 16)
         return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
+    if ((prm->flags & ~RCX_FLAG_BILINEAR_FIX) != 0) return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
+    if ((prm->flags & RCX_FLAG_BILINEAR_FIX) && prm->n_incl != 1)
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: the bilinear fix is flatland only (n_incl = 1)");
     int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
     if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
     if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
@@ -356,6 +359,41 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
         if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
         return e;
     }));
+    if (p->prm.flags & RCX_FLAG_BILINEAR_FIX) {
+        // bilinear fix: one batch at a time; the cascades below the top trace
+        // each interval once per bilinear probe; cascade 0 is stored, then
+        // averaged into J
+        for (int32_t b = 0; b < n_batch; ++b) {
+            const float2* Fb = F + (size_t)b * ncell * lb;
+            const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            int cur = 0;
+            const void* up = nullptr;
+            bool up_f16 = false;
+            for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+                if (p->top_skipped && i == p->n_casc - 1) continue;
+                const LevelDesc& L = p->levels[i];
+                CascIO io;
+                io.up = L.has_up ? up : nullptr;
+                io.up_f16 = up_f16;
+                io.out = bufs[cur];
+                io.out_f16 = f16 && i > 0;
+                io.scale_b = scale + (size_t)b * lb;
+                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                const bool fix = i + 1 < p->n_casc;
+                RCX_HIP_TRY(timed(p, i, st, [&] {
+                    return fix ? launch_march_fix(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st)
+                               : launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
+                }));
+                up = bufs[cur];
+                up_f16 = io.out_f16;
+                cur ^= 1;
+            }
+            RCX_HIP_TRY(timed(p, -1, st, [&] {
+                return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, 1.0f, false, st);
+            }));
+        }
+        return ok();
+    }
     if (incl_slots(p)) {
         // the inclinations as slots of each lane: J = sum_m w_m J_m formed in
         // the cascade-0 epilogue

@@ -26,6 +26,7 @@ RCX_T_GEOMETRIC = 0
 RCX_T_LENGTH_X4 = 1
 RCX_STORE_F32 = 0
 RCX_STORE_F16_SCALED = 1
+RCX_FLAG_BILINEAR_FIX = 1
 RCX_PROFILE_AUTO = 0
 RCX_PROFILE_TABLE = 1
 
@@ -190,10 +191,12 @@ class Plan:
 
     def __init__(self, nx: int, nz: int, max_wave: int, voxel_scale: float = 1.0,
                  n_cascades: int = 0, c0_dirs: int = 4, c0_t1: float = 1.5,
-                 t_rule: int = RCX_T_GEOMETRIC, storage: int = RCX_STORE_F32, n_incl: int = 1):
+                 t_rule: int = RCX_T_GEOMETRIC, storage: int = RCX_STORE_F32, n_incl: int = 1,
+                 bilinear_fix: bool = False):
         p = rcx_params_default()
         p.n_cascades, p.c0_dirs, p.c0_t1, p.t_rule, p.storage = n_cascades, c0_dirs, c0_t1, t_rule, storage
         p.n_incl = n_incl
+        p.flags = RCX_FLAG_BILINEAR_FIX if bilinear_fix else 0
         self.nx, self.nz, self.max_wave = nx, nz, max_wave
         self.handle = rcx_plan_create(rcx_grid(nx, nz, voxel_scale), p, max_wave)
 

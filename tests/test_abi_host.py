@@ -48,6 +48,18 @@ def test_plan_create_rejects_bad_inclination_counts(n_incl):
     assert e.value.code == rcx.RCX_E_INVALID
 
 
+@pytest.mark.parametrize("flags, n_incl, code", [(2, 1, "RCX_E_INVALID"), (0x80000000, 1, "RCX_E_INVALID"),
+                                                 (1, 8, "RCX_E_UNSUPPORTED")])
+def test_plan_create_rejects_bad_flags(flags, n_incl, code):
+    """Unknown flag bits are invalid; the bilinear fix is flatland only."""
+    p = rcx.rcx_params_default()
+    p.flags = flags
+    p.n_incl = n_incl
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(8, 8, 1.0), p, 1)
+    assert e.value.code == getattr(rcx, code)
+
+
 def test_host_radau_rule_matches_oracle_and_is_exact(tmp_path):
     """The library's inclination rule (host C++, Newton on Legendre
     polynomials) against the oracle's (numpy's Legendre roots), and its

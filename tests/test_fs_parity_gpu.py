@@ -23,13 +23,13 @@ def _torch():
     return torch
 
 
-def _gpu_solve(inp, n_cascades=0, t_rule=0, workspace=False, n_incl=1, storage=0):
+def _gpu_solve(inp, n_cascades=0, t_rule=0, workspace=False, n_incl=1, storage=0, bilinear_fix=False):
     torch = _torch()
     from paper_2408_14425_amd import rcx
     print(f"[gpu] formal solve {inp.name} n_cascades={n_cascades or inp.n_cascades} t_rule={t_rule} "
-          f"n_incl={n_incl} storage={storage}", flush=True)
+          f"n_incl={n_incl} storage={storage} bilinear_fix={bilinear_fix}", flush=True)
     plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, voxel_scale=inp.voxel_scale, n_cascades=n_cascades,
-                    t_rule=t_rule, n_incl=n_incl, storage=storage)
+                    t_rule=t_rule, n_incl=n_incl, storage=storage, bilinear_fix=bilinear_fix)
     chi = torch.from_numpy(inp.chi).cuda()
     eta = torch.from_numpy(inp.eta).cuda()
     ws = None
@@ -191,3 +191,86 @@ def test_inclined_formal_solve_matches_oracle(case):
     Jg = _gpu_solve(inp, n_incl=ni, storage=st)
     Jo = oracle.formal_solve_inclined(inp.chi, inp.eta, inp.n_cascades, ni, voxel=inp.voxel_scale)
     print(f"inclined {case}: max rel {_assert_rel(Jg, Jo, tol):.3e}")
+
+
+def _ragged_w20():
+    rng = np.random.default_rng(11)
+    nx, nz, nw = 37, 53, 20
+    chi = (10 ** rng.uniform(-2, 2, (nw, nz, nx))).astype(np.float32)
+    eta = (chi * rng.uniform(0.2, 3.0, (nw, nz, nx))).astype(np.float32)
+    return W.FormalSolveInput(chi, eta, 1.0, W.n_cascades_for(nx, nz), "rand37x53w20")
+
+
+@pytest.mark.parametrize("case", ["blobs64", "ragged_w20", "blobs32_nc2", "blobs32_nc3", "disc128",
+                                  "line96_w40_fp16"])
+def test_bilinear_fix_matches_oracle(case):
+    """Bilinear fix (Sec. 2.5): each interval of the cascades below the top
+    traced once per bilinear probe, to the start of that probe's child cone.
+    Cases: the 64^2 blobs; a ragged 37 x 53 grid with 20 wavelengths (two
+    batches, the last one partial; its top cascade lies outside the domain,
+    so the cascade below traces its four rays with nothing above); 2 and 3
+    cascades (the top cascade marched and merged); the opaque disc in vacuum
+    (zero-opacity cells); FP16 cascade storage (bounded as in the FP16
+    test)."""
+    tol, nc, st = RTOL, 0, 0
+    if case == "blobs64":
+        inp = W.blobs_medium(64, seed=1)
+    elif case == "ragged_w20":
+        inp = _ragged_w20()
+    elif case.startswith("blobs32_nc"):
+        inp, nc = W.blobs_medium(32, seed=8), int(case[-1])
+    elif case == "disc128":
+        inp = W.disc_in_vacuum(128, 4.0)
+    else:
+        inp, st, tol = W.line_medium(96, 64, seed=5, wave_subset=np.arange(0, 40)), 1, 2e-3
+    Jg = _gpu_solve(inp, n_cascades=nc, storage=st, bilinear_fix=True)
+    Jo = oracle.formal_solve(inp.chi, inp.eta, nc or inp.n_cascades, voxel=inp.voxel_scale, bilinear_fix=True)["J"]
+    if case == "disc128":
+        # cells no ray of any cascade reaches from the disc are exactly 0 on both sides
+        assert np.array_equal(Jg == 0, Jo == 0)
+        m = Jo > 0
+        print(f"bilinear fix {case}: max rel {_assert_rel(Jg[m], Jo[m], tol):.3e}")
+        return
+    print(f"bilinear fix {case}: max rel {_assert_rel(Jg, Jo, tol):.3e}")
+
+
+def test_bilinear_fix_thin_wall_is_opaque():
+    """Behind a one-cell opaque wall the fix lets nothing through: the GPU's
+    J there is exactly zero, like the oracle's, and the lit side agrees with
+    the oracle."""
+    n, x0 = 64, 30
+    chi = np.zeros((1, n, n), np.float32)
+    eta = np.zeros((1, n, n), np.float32)
+    chi[0, :, :x0 - 4] = 0.3
+    eta[0, :, :x0 - 4] = 0.3
+    chi[0, :, x0] = 1e4
+    inp = W.FormalSolveInput(chi, eta, 1.0, W.n_cascades_for(n, n), "wall64")
+    Jg = _gpu_solve(inp, bilinear_fix=True)[0]
+    Jo = oracle.formal_solve(chi, eta, inp.n_cascades, bilinear_fix=True)["J"][0]
+    assert np.all(Jg[:, x0 + 1:] == 0.0)
+    _assert_rel(Jg[:, :x0], Jo[:, :x0])
+
+
+def test_bilinear_fix_full_size_sampled():
+    """The benchmark workload (1024^2, 64 wavelengths, 7 cascades) with the
+    fix, sampled (cell, wavelength) points against the oracle's dependency
+    cones."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.line_medium(1024, 64, seed=2)
+    print("[gpu] full-size 1024^2 x 64 formal solve, bilinear fix", flush=True)
+    plan = rcx.Plan(1024, 1024, 64, bilinear_fix=True)
+    J = plan.formal_solve(torch.from_numpy(inp.chi).cuda(), torch.from_numpy(inp.eta).cuda())
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy()
+    plan.close()
+    assert np.all(np.isfinite(Jg)) and Jg.min() > 0
+    cells = [(0, 0), (1023, 1023), (511, 512), (700, 90)]
+    need = np.zeros((1024, 1024), np.uint8)
+    for x, z in cells:
+        need[z, x] = 1
+    for lam in (0, 31, 63):
+        Jo = oracle.formal_solve(inp.chi[lam:lam + 1], inp.eta[lam:lam + 1], 7, need=need, bilinear_fix=True)["J"][0]
+        for x, z in cells:
+            g, o = float(Jg[lam, z, x]), Jo[z, x]
+            assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
