@@ -365,7 +365,7 @@ def main():
         dtF, (msF, _, _, nF) = time_solves(planF, chi, eta, JF, stepsF, 1)
         planF.close()
         top = work.n_cascades - 1
-        traced = (4 * sum(work.level_rays[:top]) + work.level_rays[top]) * inp.n_wave
+        traced = (4 * sum(work.level_rays[:top]) + (0 if work.top_skipped else work.level_rays[top])) * inp.n_wave
         fix = {
             "ms_per_step": dtF / stepsF * 1e3,
             "ray_intervals_traced_per_step": traced,
