@@ -58,14 +58,14 @@ typedef struct {
     double voxel_scale;
 } rcx_grid;
 
-/* Cascade parameters (Sec. 2.3; Sec. 4.6 gives the defaults).
+/* Cascade parameters (Sec. 2.3; Sec. 4.5 gives the defaults).
  *   n_cascades: 0 = automatic, ceil(log4(max(nx, nz))) + 2.
  *   c0_dirs:    directions on cascade 0 (4); cascade i has c0_dirs * 4^i,
  *               the cone centres theta = 2 pi (k + 1/2) / N_i.
  *   c0_t1:      end of the cascade-0 interval = start of cascade 1, in cells.
  *   t_rule:     RCX_T_GEOMETRIC or RCX_T_LENGTH_X4.
  *   storage:    RCX_STORE_F32 or RCX_STORE_F16_SCALED.
- *   n_incl:     inclination rays per flatland ray, in [1, 16] (Sec. 4.1, 2D
+ *   n_incl:     inclination rays per flatland ray, in [1, 16] (Sec. 3.1, 2D
  *               invariance): rays with the same x-z projection inclined to
  *               the invariant y axis, mu = cos(inclination) on a Gauss-Radau
  *               rule over [0, 1] with the node mu = 0 (the in-plane ray)
@@ -131,7 +131,7 @@ int32_t rcx_plan_workspace_bytes(const rcx_plan* plan, int32_t n_wave, size_t* b
 /* Work counts of the plan's geometry (computed on the host, cached). */
 int32_t rcx_plan_work(rcx_plan* plan, rcx_work* out_host);
 
-/* GivenFs formal solution (Sec. 3.7 mode GivenFs; method Secs. 2.2-2.3, 3.2):
+/* GivenFs formal solution (Sec. 3.8 mode GivenFs; method Secs. 2.2-2.3, 3.2):
  * isotropic chi, eta [n_wave][nz][nx] (device, float32) -> J [n_wave][nz][nx]
  * (device, float32), the flatland mean intensity (1/N_0) sum_k I_0(k) of the
  * merged cascade 0. Free-space boundary (Sec. 3.4). chi must be >= 0;
@@ -316,7 +316,7 @@ int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, doub
  * or period < 1. */
 int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int32_t period);
 
-/* Line profile of the march (the Voigt function H(a, x) of Sec. 4.1's line
+/* Line profile of the march (the Voigt function H(a, x) of Sec. 3.3's line
  * opacity), chosen at rcx_nlte_set_atmosphere:
  *   RCX_PROFILE_AUTO   the expansion about a = 0 when every cell has damping
  *                      a <= 5e-3 (H = e^{-x^2} (1 + a^2 (1 - 2x^2))

@@ -188,7 +188,7 @@ def formal_solve(chi, eta, n_casc: int, voxel: float = 1.0, c0_dirs: int = 4, t1
 
 def radau_inclinations(n: int):
     """Gauss-Radau rule on mu = cos(angle to the invariant y axis) in [0, 1]
-    with the node mu = 0 (the in-plane ray) fixed (Sec. 4.1: eight
+    with the node mu = 0 (the in-plane ray) fixed (Sec. 3.1: eight
     inclined rays per flatland ray integrate one hemisphere, the other being
     its mirror image in a y-invariant model). Nodes: 0 and the roots of
     (P_{n-1} + P_n)(x) / (1 + x), x = 2 mu - 1; weights 2/n^2 and

@@ -1,5 +1,5 @@
 // incl_quadrature.h -- the inclination quadrature of the 2D-invariant
-// formal solution (Osborne & Sannikov, arXiv:2408.14425, Sec. 4.1): each
+// formal solution (Osborne & Sannikov, arXiv:2408.14425, Sec. 3.1): each
 // flatland ray stands for rays with the same x-z projection at inclinations
 // mu = cos(angle to the invariant y axis) in [0, 1] (one hemisphere; the
 // other is its mirror image), integrated with a Gauss-Radau rule. Plain C++

@@ -170,7 +170,7 @@ def test_fp16_storage_error_is_bounded(which):
 
 @pytest.mark.parametrize("case", ["blobs64_incl8", "ragged_w20_incl3", "ragged_w20_incl8", "line96_w40_incl8_fp16"])
 def test_inclined_formal_solve_matches_oracle(case):
-    """2D invariance (Sec. 4.1): n_incl rays per flatland ray on a
+    """2D invariance (Sec. 3.1): n_incl rays per flatland ray on a
     Gauss-Radau rule in mu = cos(inclination to y), each with the path per
     projected cell 1/sqrt(1 - mu^2) times longer; J the weighted sum. Cases:
     the paper's 8 inclinations on the 64^2 blobs, 3 on a ragged grid with a
