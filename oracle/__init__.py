@@ -186,6 +186,23 @@ def formal_solve(chi, eta, n_casc: int, voxel: float = 1.0, c0_dirs: int = 4, t1
     return out
 
 
+def formal_solve_sparse(chi, eta, n_casc: int, active, **kw):
+    """Sparse formal solve (Sec. 3.5): ``active`` [nz][nx] flags the cells
+    of interest, which are the flagged probes of cascade 0; the probes of
+    cascade i+1 that are bilinear parents of flagged probes of cascade i are
+    flagged in turn up to the top cascade (the dependency cone of the
+    flagged cells), only flagged probes' intervals are computed, and cells
+    not flagged are transparent with no emission. J is 0 at cells not
+    flagged. Returns the ``formal_solve`` dictionary."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    m = np.asarray(active, dtype=bool)
+    out = formal_solve(np.where(m, chi, 0.0), np.where(m, eta, 0.0), n_casc, need=m.astype(np.uint8), **kw)
+    out["J"][:, ~m] = 0.0
+    return out
+
+
 def radau_inclinations(n: int):
     """Gauss-Radau rule on mu = cos(angle to the invariant y axis) in [0, 1]
     with the node mu = 0 (the in-plane ray) fixed (Sec. 3.1: eight
