@@ -51,6 +51,8 @@ def parse():
                     help="wavelengths of the same workload the FP64 oracle solves for the CPU baseline")
     ap.add_argument("--no-nlte", action="store_true", help="skip the converged non-LTE solves")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-storage formal solve")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse formal solve (a quarter of the cells flagged)")
     ap.add_argument("--no-fix", action="store_true",
                     help="skip the formal solve with the bilinear fix")
     ap.add_argument("--no-incl", action="store_true",
@@ -375,6 +377,27 @@ def main():
             "steps": stepsF,
         }
 
+    sparse = None
+    if not args.no_sparse:
+        # the same solve with a quarter of the cells flagged (cool structure
+        # in a hot corona); the rest transparent and empty
+        act = workloads.active_cells(inp.nx, inp.nz, seed=7, frac=0.25)
+        planS = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
+        counts = planS.set_active(act)
+        JS = torch.empty_like(chi)
+        stepsS = max(1, min(args.steps, 5))
+        dtS, (msS, _, _, nS) = time_solves(planS, chi, eta, JS, stepsS, 1)
+        planS.close()
+        dense_probes = [L // (4 << (2 * i)) for i, L in enumerate(work.level_rays)]
+        sparse = {
+            "active_cells": float(act.mean()),
+            "flagged_share_per_cascade": [c / d for c, d in zip(counts, dense_probes)],
+            "ms_per_step": dtS / stepsS * 1e3,
+            "speedup_vs_dense": (dt / args.steps) / (dtS / stepsS),
+            "kernel_ms_per_cascade": [m / max(nS, 1) for m in msS],
+            "steps": stepsS,
+        }
+
     ms_step = dt / args.steps * 1e3
     rays = work.rays_nonempty * inp.n_wave
     value = rays / (dt / args.steps)
@@ -416,6 +439,7 @@ def main():
         "fp16_storage": fp16,
         "inclined": incl,
         "bilinear_fix": fix,
+        "sparse": sparse,
         "roofline": {
             "bound": "alu",
             "kernel": "k_march_rows",

@@ -125,6 +125,23 @@ int32_t rcx_params_default(rcx_params* p);
  * unknown storage); RCX_E_NOMEM; RCX_E_HIP. On error *out is NULL. */
 int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* p, int32_t max_wave, rcx_plan** out);
 
+/* Sparse solve (Sec. 3.5). active_host [nz][nx] (host, caller-owned, read
+ * during the call) flags the cells of interest, non-zero = flagged; they are
+ * the flagged probes of cascade 0, and every probe of cascade i+1 that is a
+ * bilinear tap (clamped at the grid edge) of a flagged probe of cascade i is
+ * flagged in turn, up to the top cascade. Later rcx_formal_solve calls on
+ * the plan march only the flagged probes' rays, treat unflagged cells as
+ * transparent with no emission, and write J = 0 at unflagged cells; with
+ * the bilinear fix the flagged probes trace their four rays each.
+ * active_host = NULL makes every probe active again (the dense solve).
+ * level_active_host (nullable) receives the number of flagged probes of
+ * each cascade [n_cascades]. Builds the flagged-probe lists on the host and
+ * copies them to plan-owned device memory (synchronous; memory the size of
+ * one int32 per flagged probe plus one byte per cell).
+ * Errors: RCX_E_INVALID (null plan); RCX_E_HIP (allocation or copy: the plan
+ * is then dense). */
+int32_t rcx_plan_set_active_host(rcx_plan* plan, const uint8_t* active_host, int64_t* level_active_host);
+
 /* Bytes of device workspace a solve of n_wave wavelengths needs. */
 int32_t rcx_plan_workspace_bytes(const rcx_plan* plan, int32_t n_wave, size_t* bytes_host);
 

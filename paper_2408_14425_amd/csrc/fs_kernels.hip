@@ -16,6 +16,7 @@
 // the next batch starts.
 #include "march_rows.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace rcx {
@@ -101,6 +102,27 @@ __global__ void k_fill_u32(unsigned int* p, int32_t n, unsigned int v)
 // ---------------------------------------------------------------- J
 // J[lam0 + l][c] = (1/N_0) sum_k Itilde_0[(c * N_0 + k)][l] for one batch,
 // through a 64-cell x 16-wavelength LDS tile.
+// Sparse solve: cells with mask 0 are transparent and emit nothing
+// (F = {0, 0} in every batch), and their J is 0. Grid-stride over
+// (batch or wavelength) x cell; F is written as 16 float2 per cell.
+__global__ __launch_bounds__(256) void k_mask_fields(float2* __restrict__ F, const uint8_t* __restrict__ mask,
+                                                     int64_t ncell, int32_t n_batch)
+{
+    const int64_t n = (int64_t)n_batch * ncell * kLB;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = (i / kLB) % ncell;
+        if (!mask[c]) F[i] = make_float2(0.0f, 0.0f);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mask_j(float* __restrict__ J, const uint8_t* __restrict__ mask, int64_t ncell,
+                                                int32_t n_wave)
+{
+    const int64_t n = (int64_t)n_wave * ncell;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (!mask[i % ncell]) J[i] = 0.0f;
+}
+
 __global__ __launch_bounds__(256) void k_j(const float* __restrict__ I0, float* __restrict__ J,
                                            int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
                                            int32_t acc_j)
@@ -281,6 +303,22 @@ hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz,
         epi.wt[w] = wt[w];
     }
     return launch_fs_up(L, nx, nz, op, epi, dirs, io, st);
+}
+
+hipError_t launch_mask_fields(float2* F, const uint8_t* mask, int64_t ncell, int32_t n_batch, hipStream_t st)
+{
+    const int64_t n = (int64_t)n_batch * ncell * kLB;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_mask_fields, dim3(blocks), dim3(256), 0, st, F, mask, ncell, n_batch);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_j(float* J, const uint8_t* mask, int64_t ncell, int32_t n_wave, hipStream_t st)
+{
+    const int64_t n = (int64_t)n_wave * ncell;
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_mask_j, dim3(blocks), dim3(256), 0, st, J, mask, ncell, n_wave);
+    return hipGetLastError();
 }
 
 hipError_t launch_j(const float* I0, float* J, int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,

@@ -378,6 +378,27 @@ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t r, int64_
 {
     active = r < total;
     const int64_t rr = active ? r : total - 1;
+    if (L.plist) {
+        // sparse: entry i of the flagged-probe list stands for probe i of
+        // the dense order (groups of tile_p^2 list entries when tiled)
+        int64_t i;
+        if (L.tile_p <= 0) {
+            k = (int32_t)(rr % L.nd);
+            i = rr / L.nd;
+        } else {
+            const int64_t tp2 = (int64_t)L.tile_p * L.tile_p;
+            const int64_t per = tp2 * L.tile_d;
+            const int64_t g = rr / per, r_in = rr % per;
+            const int32_t nw = L.nd / L.tile_d;
+            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
+            i = (g / nw) * tp2 + r_in / L.tile_d;
+        }
+        active = active && i < L.n_active;
+        const int32_t p = L.plist[i < L.n_active ? i : L.n_active - 1];
+        u = p % L.px;
+        v = p / L.px;
+        return;
+    }
     if (L.tile_p <= 0) {
         k = (int32_t)(rr % L.nd);
         const int32_t p = (int32_t)(rr / L.nd);

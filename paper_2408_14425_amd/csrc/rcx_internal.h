@@ -27,12 +27,21 @@ struct LevelDesc {
     // path length per unit of projected (x-z) length: 1 / sin(theta) for a
     // ray inclined at theta to the invariant y axis; 1 in flatland
     double ds_scale = 1.0;
+    // sparse solve: the flagged probes (v * px + u) whose rays are marched,
+    // n_active of them, in the launch order's probe order (tile by tile when
+    // tile_p > 0); nullptr = every probe
+    const int32_t* plist = nullptr;
+    int32_t n_active = 0;
 };
 
 // Rays a march launch covers (the tiled order pads the probe grid to whole
 // tiles; padding rays are inactive).
 inline int64_t level_launch_rays(const LevelDesc& L)
 {
+    if (L.plist) {
+        const int64_t per = L.tile_p > 0 ? (int64_t)L.tile_p * L.tile_p : 1;
+        return (L.n_active + per - 1) / per * per * L.nd;
+    }
     if (L.tile_p <= 0) return (int64_t)L.px * L.pz * L.nd;
     const int64_t tx = (L.px + L.tile_p - 1) / L.tile_p, tz = (L.pz + L.tile_p - 1) / L.tile_p;
     return tx * tz * L.tile_p * L.tile_p * L.nd;
@@ -97,6 +106,10 @@ hipError_t launch_march_merge_incl(const LevelDesc& L, int32_t nx, int32_t nz, c
 hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
                                      const double4* dirs, const CascIO& io, float* J, int32_t lam0, int32_t n_valid,
                                      const float* sc, const float* wt, hipStream_t st);
+// Sparse solve: zero the field batches F [n_batch][ncell][16] at cells
+// with mask 0 (transparent, no emission), and J [n_wave][ncell] there.
+hipError_t launch_mask_fields(float2* F, const uint8_t* mask, int64_t ncell, int32_t n_batch, hipStream_t st);
+hipError_t launch_mask_j(float* J, const uint8_t* mask, int64_t ncell, int32_t n_wave, hipStream_t st);
 // J[lam0 + l][c] = (1/n0) sum_k I0[(c * n0 + k)][l] for l < n_valid.
 // The J writers take a weight w and acc: J = w * value, or J += w * value
 // (inclination quadrature: one pass per inclination).
@@ -121,6 +134,10 @@ struct rcx_plan {
     std::vector<int32_t> dir_off;  // offset of cascade i's directions in the table
     std::vector<double4> dirs_host;
     double4* dirs_dev = nullptr;
+    // sparse solve (rcx_plan_set_active_host): cascade-0 mask and the
+    // flagged probe lists of every cascade (levels[i].plist points here)
+    uint8_t* mask_dev = nullptr;
+    int32_t* plist_dev = nullptr;
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
     bool work_done = false;

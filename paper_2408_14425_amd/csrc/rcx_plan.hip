@@ -188,177 +188,19 @@ hipError_t timed(rcx_plan* p, int32_t level, hipStream_t st, F&& launch)
     return e;
 }
 
-}  // namespace
-
-extern "C" {
-
-int32_t rcx_params_default(rcx_params* p)
+// The cascades of every batch, top-down (after the field preparation).
+int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, char* ws, hipStream_t st)
 {
-    if (!p) return fail(RCX_E_INVALID, "rcx_params_default: null");
-    p->n_cascades = 0;
-    p->c0_dirs = 4;
-    p->c0_t1 = 1.5;
-    p->t_rule = RCX_T_GEOMETRIC;
-    p->storage = RCX_STORE_F32;
-    p->n_incl = 1;
-    p->flags = 0;
-    return ok();
-}
-
-int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wave, rcx_plan** out)
-{
-    if (out) *out = nullptr;
-    if (!g || !prm || !out) return fail(RCX_E_INVALID, "rcx_plan_create: null argument");
-    if (g->nx <= 0 || g->nz <= 0 || max_wave <= 0)
-        return fail(RCX_E_INVALID, "rcx_plan_create: nx, nz and max_wave must be positive");
-    if (!(g->voxel_scale > 0.0)) return fail(RCX_E_INVALID, "rcx_plan_create: voxel_scale must be > 0");
-    if ((int64_t)g->nx * g->nz > (int64_t(1) << 24))
-        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: nx * nz must be at most 2^24 cells");
-    if (prm->c0_dirs <= 0 || !(prm->c0_t1 > 0.0))
-        return fail(RCX_E_INVALID, "rcx_plan_create: c0_dirs and c0_t1 must be positive");
-    if (prm->t_rule != RCX_T_GEOMETRIC && prm->t_rule != RCX_T_LENGTH_X4)
-        return fail(RCX_E_INVALID, "rcx_plan_create: unknown t_rule");
-    if (prm->storage != RCX_STORE_F32 && prm->storage != RCX_STORE_F16_SCALED)
-        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
-    if (prm->n_incl < 1 || prm->n_incl > 16)
-        return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
-    if ((prm->flags & ~RCX_FLAG_BILINEAR_FIX) != 0) return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
-    if ((prm->flags & RCX_FLAG_BILINEAR_FIX) && prm->n_incl != 1)
-        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: the bilinear fix is flatland only (n_incl = 1)");
-    int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
-    if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
-    if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
-        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: too many directions on the top cascade");
-
-    rcx_plan* p = new (std::nothrow) rcx_plan();
-    if (!p) return fail(RCX_E_NOMEM, "rcx_plan_create: host allocation");
-    p->grid = *g;
-    p->prm = *prm;
-    p->prm.n_cascades = n_casc;
-    p->max_wave = max_wave;
-    p->n_casc = n_casc;
-    {
-        std::vector<double> mu;
-        radau_nodes(prm->n_incl, mu, p->incl_w);
-        p->incl_scale.resize(prm->n_incl);
-        for (int32_t m = 0; m < prm->n_incl; ++m) p->incl_scale[m] = 1.0 / std::sqrt(1.0 - mu[m] * mu[m]);
-    }
-    p->levels.resize(n_casc);
-    p->dir_off.resize(n_casc);
-    int32_t off = 0;
-    for (int32_t i = 0; i < n_casc; ++i) {
-        LevelDesc& L = p->levels[i];
-        const int32_t s = 1 << i;
-        L.px = (g->nx + s - 1) / s;
-        L.pz = (g->nz + s - 1) / s;
-        L.nd = prm->c0_dirs << (2 * i);
-        L.s = (double)s;
-        L.ta = t_start(*prm, n_casc, i);
-        L.tb = t_start(*prm, n_casc, i + 1);
-        L.max_steps = g->nx + g->nz + 4;
-        p->dir_off[i] = off;
-        // Cone centres theta = 2 pi (k + 1/2) / N_i (children 4k..4k+3 nest).
-        for (int32_t k = 0; k < L.nd; ++k) {
-            const double th = 2.0 * M_PI * (k + 0.5) / (double)L.nd;
-            const double wx = std::cos(th), wz = std::sin(th);
-            p->dirs_host.push_back(make_double4(wx, wz, 1.0 / wx, 1.0 / wz));
-        }
-        off += L.nd;
-    }
-    for (int32_t i = 0; i < n_casc; ++i) {
-        LevelDesc& L = p->levels[i];
-        if (i + 1 < n_casc) {
-            L.qx = p->levels[i + 1].px;
-            L.qz = p->levels[i + 1].pz;
-            L.nd_up = p->levels[i + 1].nd;
-        }
-    }
-    const LevelDesc& top = p->levels[n_casc - 1];
-    p->top_skipped = (n_casc > 1 && top.ta >= max_probe_corner_distance(*g, top)) ? 1 : 0;
-    for (int32_t i = 0; i < n_casc; ++i) {
-        LevelDesc& L = p->levels[i];
-        L.has_up = (i + 1 < n_casc) && !(p->top_skipped && i + 1 == n_casc - 1);
-        // long upper-cascade rays: run them in (4 x 4 probe tile x 32
-        // direction wedge) groups, so the few groups one XCD holds at a time
-        // cross a band of cells that fits its L2 (probe-major order spreads
-        // them over full 360-degree fans)
-        L.tile_p = 0;
-        L.tile_d = 0;
-        if (L.nd >= kTileMinDirs && L.nd % kTileDirs == 0) {
-            L.tile_p = kTileProbes;
-            L.tile_d = kTileDirs;
-        }
-    }
-
-    hipError_t e = hipMalloc(&p->dirs_dev, sizeof(double4) * p->dirs_host.size());
-    if (e != hipSuccess) {
-        delete p;
-        return hip_fail(e, "hipMalloc(directions)");
-    }
-    e = hipMemcpy(p->dirs_dev, p->dirs_host.data(), sizeof(double4) * p->dirs_host.size(),
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        rcx_plan_destroy(p);
-        return hip_fail(e, "hipMemcpy(directions)");
-    }
-    p->ws_own_bytes = ws_layout(p, max_wave).total;
-    e = hipMalloc(&p->ws_own, p->ws_own_bytes);
-    if (e != hipSuccess) {
-        p->ws_own = nullptr;
-        rcx_plan_destroy(p);
-        return fail(RCX_E_NOMEM, std::string("rcx_plan_create: workspace hipMalloc: ") + hipGetErrorName(e));
-    }
-    *out = p;
-    return ok();
-}
-
-int32_t rcx_plan_workspace_bytes(const rcx_plan* p, int32_t n_wave, size_t* bytes)
-{
-    if (!p || !bytes) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: null argument");
-    if (n_wave <= 0) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: n_wave must be positive");
-    *bytes = ws_layout(p, n_wave).total;
-    return ok();
-}
-
-int32_t rcx_plan_work(rcx_plan* p, rcx_work* out)
-{
-    if (!p || !out) return fail(RCX_E_INVALID, "rcx_plan_work: null argument");
-    if (!p->work_done) count_work(p);
-    *out = p->work;
-    return ok();
-}
-
-int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
-                         void* workspace, size_t ws_bytes, hipStream_t st)
-{
-    if (!p || !chi || !eta || !J) return fail(RCX_E_INVALID, "rcx_formal_solve: null argument");
-    if (n_wave <= 0 || n_wave > p->max_wave)
-        return fail(RCX_E_INVALID, "rcx_formal_solve: n_wave must be in [1, max_wave]");
-    const WsLayout w = ws_layout(p, n_wave);
-    char* ws = (char*)workspace;
-    if (!ws) {
-        ws = (char*)p->ws_own;
-    } else if (ws_bytes < w.total) {
-        return fail(RCX_E_WORKSPACE, "rcx_formal_solve: workspace smaller than rcx_plan_workspace_bytes");
-    }
     const int32_t nx = p->grid.nx, nz = p->grid.nz;
     const int64_t ncell = (int64_t)nx * nz;
     float2* F = (float2*)(ws + w.F);
     float* bufs[2] = {(float*)(ws + w.casc_a), (float*)(ws + w.casc_b)};
-
-    if (p->timing) ++p->n_solves;
     const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
-    unsigned int* smax = (unsigned int*)(ws + w.smax);
     float* scale = (float*)(ws + w.scale);
     float* inv_scale = (float*)(ws + w.inv_scale);
     const int32_t lb = batch_width();
     const int32_t n_batch = (n_wave + lb - 1) / lb;
     const bool fuse_j = p->prm.c0_dirs == 4;
-    RCX_HIP_TRY(timed(p, -1, st, [&] {
-        hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
-        if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
-        return e;
-    }));
     if (p->prm.flags & RCX_FLAG_BILINEAR_FIX) {
         // bilinear fix: one batch at a time; the cascades below the top trace
         // each interval once per bilinear probe; cascade 0 is stored, then
@@ -521,6 +363,273 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     return ok();
 }
 
+}  // namespace
+
+extern "C" {
+
+int32_t rcx_params_default(rcx_params* p)
+{
+    if (!p) return fail(RCX_E_INVALID, "rcx_params_default: null");
+    p->n_cascades = 0;
+    p->c0_dirs = 4;
+    p->c0_t1 = 1.5;
+    p->t_rule = RCX_T_GEOMETRIC;
+    p->storage = RCX_STORE_F32;
+    p->n_incl = 1;
+    p->flags = 0;
+    return ok();
+}
+
+int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wave, rcx_plan** out)
+{
+    if (out) *out = nullptr;
+    if (!g || !prm || !out) return fail(RCX_E_INVALID, "rcx_plan_create: null argument");
+    if (g->nx <= 0 || g->nz <= 0 || max_wave <= 0)
+        return fail(RCX_E_INVALID, "rcx_plan_create: nx, nz and max_wave must be positive");
+    if (!(g->voxel_scale > 0.0)) return fail(RCX_E_INVALID, "rcx_plan_create: voxel_scale must be > 0");
+    if ((int64_t)g->nx * g->nz > (int64_t(1) << 24))
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: nx * nz must be at most 2^24 cells");
+    if (prm->c0_dirs <= 0 || !(prm->c0_t1 > 0.0))
+        return fail(RCX_E_INVALID, "rcx_plan_create: c0_dirs and c0_t1 must be positive");
+    if (prm->t_rule != RCX_T_GEOMETRIC && prm->t_rule != RCX_T_LENGTH_X4)
+        return fail(RCX_E_INVALID, "rcx_plan_create: unknown t_rule");
+    if (prm->storage != RCX_STORE_F32 && prm->storage != RCX_STORE_F16_SCALED)
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
+    if (prm->n_incl < 1 || prm->n_incl > 16)
+        return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
+    if ((prm->flags & ~RCX_FLAG_BILINEAR_FIX) != 0) return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
+    if ((prm->flags & RCX_FLAG_BILINEAR_FIX) && prm->n_incl != 1)
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: the bilinear fix is flatland only (n_incl = 1)");
+    int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
+    if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
+    if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
+        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: too many directions on the top cascade");
+
+    rcx_plan* p = new (std::nothrow) rcx_plan();
+    if (!p) return fail(RCX_E_NOMEM, "rcx_plan_create: host allocation");
+    p->grid = *g;
+    p->prm = *prm;
+    p->prm.n_cascades = n_casc;
+    p->max_wave = max_wave;
+    p->n_casc = n_casc;
+    {
+        std::vector<double> mu;
+        radau_nodes(prm->n_incl, mu, p->incl_w);
+        p->incl_scale.resize(prm->n_incl);
+        for (int32_t m = 0; m < prm->n_incl; ++m) p->incl_scale[m] = 1.0 / std::sqrt(1.0 - mu[m] * mu[m]);
+    }
+    p->levels.resize(n_casc);
+    p->dir_off.resize(n_casc);
+    int32_t off = 0;
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        const int32_t s = 1 << i;
+        L.px = (g->nx + s - 1) / s;
+        L.pz = (g->nz + s - 1) / s;
+        L.nd = prm->c0_dirs << (2 * i);
+        L.s = (double)s;
+        L.ta = t_start(*prm, n_casc, i);
+        L.tb = t_start(*prm, n_casc, i + 1);
+        L.max_steps = g->nx + g->nz + 4;
+        p->dir_off[i] = off;
+        // Cone centres theta = 2 pi (k + 1/2) / N_i (children 4k..4k+3 nest).
+        for (int32_t k = 0; k < L.nd; ++k) {
+            const double th = 2.0 * M_PI * (k + 0.5) / (double)L.nd;
+            const double wx = std::cos(th), wz = std::sin(th);
+            p->dirs_host.push_back(make_double4(wx, wz, 1.0 / wx, 1.0 / wz));
+        }
+        off += L.nd;
+    }
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        if (i + 1 < n_casc) {
+            L.qx = p->levels[i + 1].px;
+            L.qz = p->levels[i + 1].pz;
+            L.nd_up = p->levels[i + 1].nd;
+        }
+    }
+    const LevelDesc& top = p->levels[n_casc - 1];
+    p->top_skipped = (n_casc > 1 && top.ta >= max_probe_corner_distance(*g, top)) ? 1 : 0;
+    for (int32_t i = 0; i < n_casc; ++i) {
+        LevelDesc& L = p->levels[i];
+        L.has_up = (i + 1 < n_casc) && !(p->top_skipped && i + 1 == n_casc - 1);
+        // long upper-cascade rays: run them in (4 x 4 probe tile x 32
+        // direction wedge) groups, so the few groups one XCD holds at a time
+        // cross a band of cells that fits its L2 (probe-major order spreads
+        // them over full 360-degree fans)
+        L.tile_p = 0;
+        L.tile_d = 0;
+        if (L.nd >= kTileMinDirs && L.nd % kTileDirs == 0) {
+            L.tile_p = kTileProbes;
+            L.tile_d = kTileDirs;
+        }
+    }
+
+    hipError_t e = hipMalloc(&p->dirs_dev, sizeof(double4) * p->dirs_host.size());
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "hipMalloc(directions)");
+    }
+    e = hipMemcpy(p->dirs_dev, p->dirs_host.data(), sizeof(double4) * p->dirs_host.size(),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        rcx_plan_destroy(p);
+        return hip_fail(e, "hipMemcpy(directions)");
+    }
+    p->ws_own_bytes = ws_layout(p, max_wave).total;
+    e = hipMalloc(&p->ws_own, p->ws_own_bytes);
+    if (e != hipSuccess) {
+        p->ws_own = nullptr;
+        rcx_plan_destroy(p);
+        return fail(RCX_E_NOMEM, std::string("rcx_plan_create: workspace hipMalloc: ") + hipGetErrorName(e));
+    }
+    *out = p;
+    return ok();
+}
+
+int32_t rcx_plan_set_active_host(rcx_plan* p, const uint8_t* active_host, int64_t* level_active_host)
+{
+    if (!p) return fail(RCX_E_INVALID, "rcx_plan_set_active_host: null plan");
+    const int32_t nx = p->grid.nx, nz = p->grid.nz;
+    // drop any previous flags: every probe active
+    hipError_t e = hipSuccess;
+    if (p->mask_dev) e = hipFree(p->mask_dev);
+    if (p->plist_dev && e == hipSuccess) e = hipFree(p->plist_dev);
+    p->mask_dev = nullptr;
+    p->plist_dev = nullptr;
+    for (auto& L : p->levels) {
+        L.plist = nullptr;
+        L.n_active = 0;
+    }
+    if (e != hipSuccess) return hip_fail(e, "rcx_plan_set_active_host: hipFree");
+    if (!active_host) {
+        if (level_active_host)
+            for (int32_t i = 0; i < p->n_casc; ++i)
+                level_active_host[i] = (int64_t)p->levels[i].px * p->levels[i].pz;
+        return ok();
+    }
+    // flags: cascade 0 = the active cells; a probe of cascade i+1 is flagged
+    // when it is one of the (clamped) bilinear taps of a flagged probe of
+    // cascade i (Sec. 3.5)
+    std::vector<std::vector<uint8_t>> flag(p->n_casc);
+    flag[0].assign(active_host, active_host + (size_t)nx * nz);
+    for (auto& f : flag[0]) f = f ? 1 : 0;
+    for (int32_t i = 0; i + 1 < p->n_casc; ++i) {
+        const LevelDesc& L = p->levels[i];
+        const LevelDesc& U = p->levels[i + 1];
+        flag[i + 1].assign((size_t)U.px * U.pz, 0);
+        for (int32_t v = 0; v < L.pz; ++v)
+            for (int32_t u = 0; u < L.px; ++u) {
+                if (!flag[i][(size_t)v * L.px + u]) continue;
+                const int bx0 = (u - 1) >> 1, bz0 = (v - 1) >> 1;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const int tx = std::min(std::max(bx0 + b, 0), U.px - 1);
+                        const int tz = std::min(std::max(bz0 + a, 0), U.pz - 1);
+                        flag[i + 1][(size_t)tz * U.px + tx] = 1;
+                    }
+            }
+    }
+    // lists in the launch order's probe order: tile by tile (row-major
+    // tiles, row-major inside a tile) on tiled cascades, else probe-major
+    std::vector<int32_t> all;
+    std::vector<size_t> off(p->n_casc);
+    std::vector<int32_t> cnt(p->n_casc);
+    for (int32_t i = 0; i < p->n_casc; ++i) {
+        const LevelDesc& L = p->levels[i];
+        off[i] = all.size();
+        if (L.tile_p <= 0) {
+            for (int32_t q = 0; q < L.px * L.pz; ++q)
+                if (flag[i][q]) all.push_back(q);
+        } else {
+            const int32_t tp = L.tile_p, ntx = (L.px + tp - 1) / tp, ntz = (L.pz + tp - 1) / tp;
+            for (int32_t tz = 0; tz < ntz; ++tz)
+                for (int32_t tx = 0; tx < ntx; ++tx)
+                    for (int32_t j = 0; j < tp * tp; ++j) {
+                        const int32_t u = tx * tp + j % tp, v = tz * tp + j / tp;
+                        if (u < L.px && v < L.pz && flag[i][(size_t)v * L.px + u]) all.push_back(v * L.px + u);
+                    }
+        }
+        cnt[i] = (int32_t)(all.size() - off[i]);
+        if (level_active_host) level_active_host[i] = cnt[i];
+    }
+    e = hipMalloc(&p->mask_dev, (size_t)nx * nz);
+    if (e == hipSuccess) e = hipMemcpy(p->mask_dev, flag[0].data(), (size_t)nx * nz, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->plist_dev, sizeof(int32_t) * std::max<size_t>(all.size(), 1));
+    if (e == hipSuccess && !all.empty())
+        e = hipMemcpy(p->plist_dev, all.data(), sizeof(int32_t) * all.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (p->mask_dev) (void)hipFree(p->mask_dev);
+        if (p->plist_dev) (void)hipFree(p->plist_dev);
+        p->mask_dev = nullptr;
+        p->plist_dev = nullptr;
+        return hip_fail(e, "rcx_plan_set_active_host");
+    }
+    for (int32_t i = 0; i < p->n_casc; ++i) {
+        p->levels[i].plist = p->plist_dev + off[i];
+        p->levels[i].n_active = cnt[i];
+    }
+    return ok();
+}
+
+int32_t rcx_plan_workspace_bytes(const rcx_plan* p, int32_t n_wave, size_t* bytes)
+{
+    if (!p || !bytes) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: null argument");
+    if (n_wave <= 0) return fail(RCX_E_INVALID, "rcx_plan_workspace_bytes: n_wave must be positive");
+    *bytes = ws_layout(p, n_wave).total;
+    return ok();
+}
+
+int32_t rcx_plan_work(rcx_plan* p, rcx_work* out)
+{
+    if (!p || !out) return fail(RCX_E_INVALID, "rcx_plan_work: null argument");
+    if (!p->work_done) count_work(p);
+    *out = p->work;
+    return ok();
+}
+
+int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                         void* workspace, size_t ws_bytes, hipStream_t st)
+{
+    if (!p || !chi || !eta || !J) return fail(RCX_E_INVALID, "rcx_formal_solve: null argument");
+    if (n_wave <= 0 || n_wave > p->max_wave)
+        return fail(RCX_E_INVALID, "rcx_formal_solve: n_wave must be in [1, max_wave]");
+    const WsLayout w = ws_layout(p, n_wave);
+    char* ws = (char*)workspace;
+    if (!ws) {
+        ws = (char*)p->ws_own;
+    } else if (ws_bytes < w.total) {
+        return fail(RCX_E_WORKSPACE, "rcx_formal_solve: workspace smaller than rcx_plan_workspace_bytes");
+    }
+    const int64_t ncell = (int64_t)p->grid.nx * p->grid.nz;
+    float2* F = (float2*)(ws + w.F);
+
+    if (p->timing) ++p->n_solves;
+    const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
+    unsigned int* smax = (unsigned int*)(ws + w.smax);
+    float* scale = (float*)(ws + w.scale);
+    float* inv_scale = (float*)(ws + w.inv_scale);
+    const int32_t lb = batch_width();
+    const int32_t n_batch = (n_wave + lb - 1) / lb;
+    if (p->mask_dev && p->levels[0].n_active == 0) {
+        // sparse with nothing flagged: J = 0
+        RCX_HIP_TRY(launch_mask_j(J, p->mask_dev, ncell, n_wave, st));
+        return ok();
+    }
+    RCX_HIP_TRY(timed(p, -1, st, [&] {
+        hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
+        if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
+        // sparse: unflagged cells transparent and empty (Sec. 3.5)
+        if (e == hipSuccess && p->mask_dev) e = launch_mask_fields(F, p->mask_dev, ncell, n_batch, st);
+        return e;
+    }));
+    const int32_t rc = solve_batches(p, n_wave, J, w, ws, st);
+    if (rc != RCX_OK || !p->mask_dev) return rc;
+    // sparse: J = 0 at unflagged cells
+    RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_mask_j(J, p->mask_dev, ncell, n_wave, st); }));
+    return ok();
+}
+
 int32_t rcx_plan_set_timing(rcx_plan* p, int32_t enable)
 {
     if (!p) return fail(RCX_E_INVALID, "rcx_plan_set_timing: null plan");
@@ -566,6 +675,8 @@ int32_t rcx_plan_destroy(rcx_plan* p)
     }
     if (p->dirs_dev) (void)hipFree(p->dirs_dev);
     if (p->ws_own) (void)hipFree(p->ws_own);
+    if (p->mask_dev) (void)hipFree(p->mask_dev);
+    if (p->plist_dev) (void)hipFree(p->plist_dev);
     delete p;
     return ok();
 }

@@ -69,6 +69,7 @@ def load() -> C.CDLL:
     L.rcx_plan_create.argtypes = [C.POINTER(rcx_grid), C.POINTER(rcx_params), i32, C.POINTER(vp)]
     L.rcx_plan_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     L.rcx_plan_work.argtypes = [vp, C.POINTER(rcx_work)]
+    L.rcx_plan_set_active_host.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.rcx_plan_destroy.argtypes = [vp]
     L.rcx_plan_set_timing.argtypes = [vp, i32]
@@ -79,10 +80,15 @@ def load() -> C.CDLL:
     L.rcx_last_error.argtypes = [C.c_char_p, sz]
     for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
                  "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error", "rcx_plan_set_timing",
-                 "rcx_plan_get_timing"):
+                 "rcx_plan_get_timing", "rcx_plan_set_active_host"):
         getattr(L, name).restype = i32
     _lib = L
     return L
+
+
+def np_shape(a):
+    import numpy as np
+    return tuple(np.shape(a))
 
 
 def _check(rc: int, where: str) -> int:
@@ -127,6 +133,19 @@ def rcx_plan_workspace_bytes(plan: int, n_wave: int) -> int:
     b = C.c_size_t()
     _check(load().rcx_plan_workspace_bytes(plan, int(n_wave), C.byref(b)), "rcx_plan_workspace_bytes")
     return int(b.value)
+
+
+def rcx_plan_set_active_host(plan: int, active, n_cascades: int):
+    """Flag the active cells ([nz][nx] array, non-zero = active) or, with
+    None, make every probe active; returns the flagged probes per cascade."""
+    import numpy as np
+    counts = (C.c_int64 * max(n_cascades, 1))()
+    if active is None:
+        _check(load().rcx_plan_set_active_host(plan, None, counts), "rcx_plan_set_active_host")
+    else:
+        a = np.ascontiguousarray(np.asarray(active) != 0, dtype=np.uint8)
+        _check(load().rcx_plan_set_active_host(plan, a.ctypes.data, counts), "rcx_plan_set_active_host")
+    return list(counts[:n_cascades])
 
 
 def rcx_plan_work(plan: int) -> rcx_work:
@@ -205,6 +224,14 @@ class Plan:
         n = w.n_cascades
         return Work(n, bool(w.top_skipped), w.rays_all, w.rays_nonempty, w.cell_steps,
                     list(w.level_rays[:n]), list(w.level_steps[:n]))
+
+    def set_active(self, active):
+        """Sparse solve: flag the cells of interest ([nz][nx], non-zero =
+        active) or None for the dense solve; returns the flagged probes of
+        each cascade."""
+        if active is not None and np_shape(active) != (self.nz, self.nx):
+            raise ValueError(f"active must have shape ({self.nz}, {self.nx})")
+        return rcx_plan_set_active_host(self.handle, active, self.work().n_cascades)
 
     def set_timing(self, enable: bool):
         rcx_plan_set_timing(self.handle, enable)

@@ -150,6 +150,18 @@ def disc_in_vacuum(n: int = 256, radius: float = 4.0, chi_disc: float = 1e3,
     return FormalSolveInput(chi[None], eta[None], 1.0, n_cascades_for(n, n), f"disc{n}_r{radius}")
 
 
+def active_cells(nx: int, nz: int, seed: int = 7, frac: float = 0.25, corr_len: float | None = None) -> np.ndarray:
+    """Flags of a sparse solve: cool structure in a hot corona. A Gaussian
+    random field (correlation length ``corr_len``, default max(nx, nz) / 16)
+    thresholded at its (1 - frac) quantile marks ``frac`` of the cells as
+    active ([nz][nx] bool); the paper flags about 25% of its cells by a
+    temperature cut."""
+    rng = np.random.default_rng(seed)
+    cl = max(nx, nz) / 16.0 if corr_len is None else corr_len
+    f = grf(rng, (nz, nx), cl)
+    return f > np.quantile(f, 1.0 - frac)
+
+
 def uneven_batch(seed: int = 4, n_atm: int = 16, sizes=None, waves=None):
     """List of (side, n_wave, atmosphere seed) for a batch of independent
     line-medium atmospheres of uneven size: sides uniform on multiples of 128

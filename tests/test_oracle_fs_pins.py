@@ -577,16 +577,6 @@ def test_bilinear_fix_ray_counts_and_top_cascade():
 # ---------------------------------------------------------------- sparsity
 
 
-def _active_blobs(n, seed, frac=0.3):
-    """Active cells: a smooth random field thresholded at its (1 - frac)
-    quantile (cool structure in a hot corona)."""
-    rng = np.random.default_rng(seed)
-    f = rng.standard_normal((n, n))
-    k = np.fft.fftfreq(n)
-    f = np.real(np.fft.ifft2(np.fft.fft2(f) * np.exp(-(k[:, None] ** 2 + k[None, :] ** 2) * (n / 6.0) ** 2)))
-    return f > np.quantile(f, 1.0 - frac)
-
-
 def test_sparse_all_active_is_the_dense_solve():
     """Sec. 3.5: with every cell flagged nothing is skipped or emptied."""
     inp = W.line_medium(48, 4, seed=3)
@@ -603,7 +593,7 @@ def test_sparse_ignores_unflagged_cells():
     flagged."""
     n = 64
     inp = W.line_medium(n, 3, seed=4)
-    act = _active_blobs(n, 1)
+    act = W.active_cells(n, n, seed=1, frac=0.3)
     a = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act)["J"]
     rng = np.random.default_rng(2)
     chi2 = np.where(act, inp.chi, rng.uniform(0, 50, inp.chi.shape))
@@ -624,7 +614,7 @@ def test_sparse_computes_fewer_rays():
     holding the same number of rays when dense."""
     n = 128
     inp = W.line_medium(n, 1, seed=4)
-    act = _active_blobs(n, 3, frac=0.25)
+    act = W.active_cells(n, n, seed=3, frac=0.25)
     dense = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)
     sparse = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act)
     share = sparse["rays"] / dense["rays"]
