@@ -276,13 +276,13 @@ def test_bilinear_fix_full_size_sampled():
             assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
 
 
-def _gpu_sparse(inp, active, storage=0, bilinear_fix=False, also_dense=False):
+def _gpu_sparse(inp, active, storage=0, bilinear_fix=False, also_dense=False, n_incl=1):
     torch = _torch()
     from paper_2408_14425_amd import rcx
     print(f"[gpu] sparse formal solve {inp.name} active {active.mean():.3f} storage={storage} "
           f"bilinear_fix={bilinear_fix}", flush=True)
     plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, voxel_scale=inp.voxel_scale, storage=storage,
-                    bilinear_fix=bilinear_fix)
+                    bilinear_fix=bilinear_fix, n_incl=n_incl)
     chi = torch.from_numpy(inp.chi).cuda()
     eta = torch.from_numpy(inp.eta).cuda()
     dense = None
@@ -300,7 +300,8 @@ def _gpu_sparse(inp, active, storage=0, bilinear_fix=False, also_dense=False):
     return out, counts, dense, again
 
 
-@pytest.mark.parametrize("case", ["blobs64", "ragged_w20", "line96_w40_fp16", "line256_w16_fix", "one_cell"])
+@pytest.mark.parametrize("case", ["blobs64", "ragged_w20", "line96_w40_fp16", "line256_w16_fix", "one_cell",
+                                  "blobs64_incl8"])
 def test_sparse_matches_oracle(case):
     """Sparse solve (Sec. 3.5): only the flagged probes' rays (the flagged
     cells and their bilinear parents up to the top) are marched, unflagged
