@@ -308,8 +308,9 @@ def test_sparse_matches_oracle(case):
     cells are transparent and empty, J is zero there. Cases: 30% of the 64^2
     blobs; a ragged grid with two batches; FP16 cascades with a pair of
     batches; 256^2 with the bilinear fix (its wide cascades launch the
-    flagged probes tile by tile); a single flagged cell."""
-    tol, st, fix = RTOL, 0, False
+    flagged probes tile by tile); a single flagged cell; the 8 inclinations
+    as slots of one march."""
+    tol, st, fix, ni = RTOL, 0, False, 1
     if case == "blobs64":
         inp = W.blobs_medium(64, seed=1)
         act = W.active_cells(64, 64, seed=1, frac=0.3)
@@ -322,13 +323,22 @@ def test_sparse_matches_oracle(case):
     elif case == "line256_w16_fix":
         inp, fix = W.line_medium(256, 64, seed=2, wave_subset=np.arange(0, 64, 4)), True
         act = W.active_cells(256, 256, seed=4, frac=0.25)
-    else:
+    elif case == "one_cell":
         inp = W.blobs_medium(64, seed=1)
         act = np.zeros((64, 64), bool)
         act[40, 17] = True
-    Jg, counts, _, _ = _gpu_sparse(inp, act, storage=st, bilinear_fix=fix)
-    Jo = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act, voxel=inp.voxel_scale,
-                                    bilinear_fix=fix)["J"]
+    else:
+        inp, ni = W.blobs_medium(64, seed=1), 8
+        act = W.active_cells(64, 64, seed=5, frac=0.3)
+    Jg, counts, _, _ = _gpu_sparse(inp, act, storage=st, bilinear_fix=fix, n_incl=ni)
+    if ni == 1:
+        Jo = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act, voxel=inp.voxel_scale,
+                                        bilinear_fix=fix)["J"]
+    else:
+        mu, wt = oracle.radau_inclinations(ni)
+        Jo = sum(wt[m] * oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act,
+                                                    voxel=inp.voxel_scale / np.sqrt(1.0 - mu[m] ** 2))["J"]
+                 for m in range(ni))
     assert counts[0] == act.sum()
     assert np.all(Jg[:, ~act] == 0.0)
     rel = _assert_rel(Jg[:, act], Jo[:, act], tol)
