@@ -229,10 +229,31 @@ hipError_t launch_fix_k(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op
 hipError_t launch_march_fix(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                             const CascIO& io, hipStream_t st)
 {
-    if (io.slot_stride != 0) return hipErrorInvalidValue;
+    const uint32_t fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    if (io.slot_stride != 0) {
+        // two batches per lane (slot 1 io.slot_stride elements on)
+        march::FieldOp2 op{};
+        op.Fb = Fb;
+        op.fb_bytes = fb_bytes;
+        if (!io.up_f16) {
+            march::UpF32 up{(const float*)io.up};
+            up.stride = io.slot_stride;
+            if (!io.out_f16)
+                return launch_fix_k(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, up, st);
+            return launch_fix_k(L, nx, nz, op,
+                                march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f}, dirs,
+                                up, st);
+        }
+        march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+        up.stride = io.slot_stride;
+        if (!io.out_f16)
+            return launch_fix_k(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, up, st);
+        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f},
+                            dirs, up, st);
+    }
     march::FieldOp op{};
     op.Fb = Fb;
-    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    op.fb_bytes = fb_bytes;
     if (!io.up_f16) {
         const march::UpF32 up{(const float*)io.up};
         if (!io.out_f16) return launch_fix_k(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);

@@ -466,7 +466,8 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t n
 // 4k..4k+3, and the four results are summed with the bilinear weights. The
 // 4 rows of a wavefront are the 4 taps of one interval (row = 2 * a + b for
 // tap z index a, x index b), so the sum is two cross-row shuffles; row 0
-// finishes the interval. Taps are clamped at the grid edge (as in the
+// finishes the interval. With Op::kW = 2 each lane carries two wavelength
+// batches along the same four walks. Taps are clamped at the grid edge (as in the
 // basic merge) and keep their weights.
 template <class Op, class Epi, class Up>
 __device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
@@ -474,7 +475,7 @@ __device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, in
                                               typename Op::Stage (*stg)[kStgRow], const RowCtx& cx_, int64_t ray,
                                               int32_t u, int32_t v, int32_t k, bool active)
 {
-    static_assert(Op::kW == 1, "the fix marches one batch per lane");
+    constexpr int W = Op::kW;  // wavelength batches per lane
     const int row = cx_.row, l = cx_.l;
     const int ta_z = row >> 1, ta_x = row & 1;
     // the same taps and weights as the basic merge
@@ -502,18 +503,24 @@ __device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, in
         d = make_double4(wx, wz, 1.0 / wx, 1.0 / wz);
     }
     op.begin_ray(dk.x, dk.y);
-    float I[1], T[1];
+    float I[W], T[W];
     walk_ray(L, nx, nz, op, ax, az, d, 0.0, len, active && len > 0.0, seg, stg, cx_, I, T);
 
-    float m = I[0];
     if (active && L.has_up) {
         const int64_t bi = (((int64_t)tz * L.qx + tx) * L.nd_up + 4 * (int64_t)k) * kLB + l;
-        const float c4 = up.get(bi, 0) + up.get(bi + kLB, 0) + up.get(bi + 2 * kLB, 0) + up.get(bi + 3 * kLB, 0);
-        m = fmaf(T[0], 0.25f * c4, m);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const float c4 = up.get(bi, w) + up.get(bi + kLB, w) + up.get(bi + 2 * kLB, w) + up.get(bi + 3 * kLB, w);
+            I[w] = fmaf(T[w], 0.25f * c4, I[w]);
+        }
     }
-    float sum = wgt * m;
-    sum += __shfl_xor(sum, 16);
-    sum += __shfl_xor(sum, 32);
+    float sum[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        sum[w] = wgt * I[w];
+        sum[w] += __shfl_xor(sum[w], 16);
+        sum[w] += __shfl_xor(sum[w], 32);
+    }
     RayInfo ri;
     ri.ray = ray;
     ri.active = active && row == 0;
@@ -522,7 +529,11 @@ __device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, in
     ri.v = v;
     ri.wx = dk.x;
     ri.wz = dk.y;
-    epi.finish(ri, l, cx_.lane, sum, op);
+    if constexpr (W == 1) {
+        epi.finish(ri, l, cx_.lane, sum[0], op);
+    } else {
+        epi.finish_slots(ri, l, cx_.lane, sum, op);
+    }
 }
 
 // One interval per wavefront (its 4 taps on the 4 rows); total = intervals

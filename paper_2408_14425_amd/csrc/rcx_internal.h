@@ -91,7 +91,8 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                                 const CascIO& io, float* J, int32_t lam0, int32_t n_valid, int32_t n_valid1,
                                 float w, bool acc, hipStream_t st);
-// Bilinear fix (one batch, io.slot_stride = 0): interval (p, k) traced
+// Bilinear fix (io.slot_stride != 0: batches b and b+1 per lane, as in
+// launch_march_merge): interval (p, k) traced
 // once per bilinear probe q of the cascade above, to q + t_b w_k, merged
 // with q's children and summed with the bilinear weights; up/out as for
 // launch_march_merge. Needs a cascade above in the plan (qx, qz, nd_up).

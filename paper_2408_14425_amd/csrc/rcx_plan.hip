@@ -202,12 +202,15 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
     const int32_t n_batch = (n_wave + lb - 1) / lb;
     const bool fuse_j = p->prm.c0_dirs == 4;
     if (p->prm.flags & RCX_FLAG_BILINEAR_FIX) {
-        // bilinear fix: one batch at a time; the cascades below the top trace
-        // each interval once per bilinear probe; cascade 0 is stored, then
-        // averaged into J
-        for (int32_t b = 0; b < n_batch; ++b) {
+        // bilinear fix: the cascades below the top trace each interval once
+        // per bilinear probe; batches b and b+1 share the walks on the
+        // cascades with at most kPairMaxDirs directions (as in the basic
+        // solve); cascade 0 is stored, then averaged into J
+        for (int32_t b = 0; b < n_batch;) {
+            const bool pair = b + 1 < n_batch;
             const float2* Fb = F + (size_t)b * ncell * lb;
             const int32_t nvalid = std::min(lb, n_wave - b * lb);
+            const int32_t nvalid1 = pair ? std::min(lb, n_wave - (b + 1) * lb) : 0;
             int cur = 0;
             const void* up = nullptr;
             bool up_f16 = false;
@@ -221,18 +224,41 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                 io.out_f16 = f16 && i > 0;
                 io.scale_b = scale + (size_t)b * lb;
                 io.inv_scale_b = inv_scale + (size_t)b * lb;
+                const bool together = pair && L.nd <= kPairMaxDirs;
+                io.slot_stride = together ? w.casc_slot : 0;
                 const bool fix = i + 1 < p->n_casc;
+                const double4* dirs = p->dirs_dev + p->dir_off[i];
                 RCX_HIP_TRY(timed(p, i, st, [&] {
-                    return fix ? launch_march_fix(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st)
-                               : launch_march_merge(L, nx, nz, Fb, p->dirs_dev + p->dir_off[i], io, st);
+                    return fix ? launch_march_fix(L, nx, nz, Fb, dirs, io, st)
+                               : launch_march_merge(L, nx, nz, Fb, dirs, io, st);
                 }));
+                if (pair && !together) {
+                    // batch b+1 into slot 1 (FP16 cascades: 2-byte elements)
+                    CascIO io1 = io;
+                    const size_t up_off = (size_t)w.casc_slot * (io.up_f16 ? (size_t)2 : sizeof(float));
+                    const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
+                    io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
+                    io1.out = (void*)((char*)io.out + out_off);
+                    io1.scale_b = io.scale_b + lb;
+                    io1.inv_scale_b = io.inv_scale_b + lb;
+                    const float2* Fb1 = Fb + (size_t)ncell * lb;
+                    RCX_HIP_TRY(timed(p, i, st, [&] {
+                        return fix ? launch_march_fix(L, nx, nz, Fb1, dirs, io1, st)
+                                   : launch_march_merge(L, nx, nz, Fb1, dirs, io1, st);
+                    }));
+                }
                 up = bufs[cur];
                 up_f16 = io.out_f16;
                 cur ^= 1;
             }
             RCX_HIP_TRY(timed(p, -1, st, [&] {
-                return launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, 1.0f, false, st);
+                hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, 1.0f, false, st);
+                if (e == hipSuccess && pair)
+                    e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, 1.0f,
+                                 false, st);
+                return e;
             }));
+            b += pair ? 2 : 1;
         }
         return ok();
     }

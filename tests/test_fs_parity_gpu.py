@@ -384,3 +384,25 @@ def test_sparse_full_size_sampled():
             g, o = float(Jg[lam, z, x]), Jo[z, x]
             assert abs(g - o) <= RTOL * o, (lam, x, z, g, o)
     print("flagged per cascade", counts)
+
+
+@pytest.mark.parametrize("t_rule, c0_dirs", [(1, 4), (0, 8)])
+def test_bilinear_fix_interval_rule_and_directions(t_rule, c0_dirs):
+    """The fix with the lengths-x4 interval rule, and with 8 cascade-0
+    directions (cascade 0 stored and averaged by the J kernel), on 20
+    wavelengths (a pair of batches)."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    rng = np.random.default_rng(12)
+    nx, nz, nw = 48, 40, 20
+    chi = (10 ** rng.uniform(-1.5, 1.5, (nw, nz, nx))).astype(np.float32)
+    eta = (chi * rng.uniform(0.2, 3.0, (nw, nz, nx))).astype(np.float32)
+    ncas = W.n_cascades_for(nx, nz)
+    print(f"[gpu] bilinear fix t_rule={t_rule} c0_dirs={c0_dirs}", flush=True)
+    plan = rcx.Plan(nx, nz, nw, t_rule=t_rule, c0_dirs=c0_dirs, bilinear_fix=True)
+    J = plan.formal_solve(torch.from_numpy(chi).cuda(), torch.from_numpy(eta).cuda())
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().astype(np.float64)
+    plan.close()
+    Jo = oracle.formal_solve(chi, eta, ncas, t_rule=t_rule, c0_dirs=c0_dirs, bilinear_fix=True)["J"]
+    print(f"fix t_rule={t_rule} c0_dirs={c0_dirs}: max rel {_assert_rel(Jg, Jo):.3e}")
