@@ -14,7 +14,10 @@ One iteration, in the paper's order:
   4. the rate matrix Gamma: off-diagonal terms from radiative + collisional
      rates, the diagonal from conservation (column sums vanish), one row
      replaced by particle conservation, solved in FP64 (Sec. 3.3, 3.5);
-  5. the maximum relative change of the populations (Sec. 4.2).
+  5. the maximum relative change of the populations (Sec. 4.2);
+  6. optionally, charge conservation: one Newton-Raphson step on the
+     populations and the electron density after the equilibrium step,
+     hydrogen (this atom) the only electron donor (Sec. 3.3).
 
 Readings (listed in the design notes):
   - The directional operator is Lambda* = 1 - exp(-tau), with tau the
@@ -29,6 +32,14 @@ Readings (listed in the design notes):
   - Convergence: max over cells and levels of |n_new - n_old| / n_new.
   - Rate integrals: W = 4 pi dnu / (h nu) with the input frequency weights;
     flatland angular weights 1/N_0.
+  - Charge conservation: unknowns (n, n_e) per cell; equations Gamma(n_e) n
+    = 0 with the conservation row, and n_e = n_c (the continuum level). The
+    rates proportional to n_e are the collisional downward rates, the
+    bound-bound collisional upward rates (detailed balance with a Boltzmann
+    ratio) and the radiative recombination rates (through n_i*/n_c*, which
+    is proportional to n_e); dGamma/dn_e = (those rates) / n_e, all other
+    rates held fixed. The step is taken only if it leaves every population
+    and n_e positive. The change metric includes |dn_e| / n_e.
 """
 from __future__ import annotations
 
@@ -316,6 +327,56 @@ class Problem:
             G[:, l, l] = -(G.sum(axis=1)[:, l] - G[:, l, l])
         return G
 
+    def with_ne(self, ne):
+        """A copy of the problem at electron density ne: the LTE populations,
+        collisional rates and continuum coefficients follow n_e."""
+        import copy
+        P = copy.copy(self)
+        P.ne = np.asarray(ne, np.float64).copy()
+        P.lte = lte_populations(self.atom, self.T, P.ne, self.ntot)
+        P.Cdown = np.array([P.ne * t.q * (self.T / 1e4) ** -0.5 for t in self.atom.trans])
+        P.Cup = np.array([cd * P.lte[t.j] / P.lte[t.i] for cd, t in zip(P.Cdown, self.atom.trans)])
+        return P
+
+    def charge_step(self, pops, Rup, Rdn):
+        """One Newton-Raphson step for charge conservation at the populations
+        of the equilibrium step (readings in the module notes). Returns the
+        new populations, n_e and the max relative change of both."""
+        G = self.gamma(Rup, Rdn)
+        nlv = self.atom.n_levels
+        cl = nlv - 1
+        nc = self.ncell
+        ne = self.ne
+        # dGamma/dn_e applied to the populations
+        D = np.zeros((nc, nlv))
+        for t, tr in enumerate(self.atom.trans):
+            up = self.Cup[t] if tr.kind == "line" else np.zeros(nc)
+            dn = self.Cdown[t] + (Rdn[t] if tr.kind == "cont" else 0.0)
+            D[:, tr.j] += up / ne * pops[tr.i]
+            D[:, tr.i] -= up / ne * pops[tr.i]
+            D[:, tr.i] += dn / ne * pops[tr.j]
+            D[:, tr.j] -= dn / ne * pops[tr.j]
+        M = np.zeros((nc, nlv + 1, nlv + 1))
+        rhs = np.zeros((nc, nlv + 1))
+        M[:, :nlv, :nlv] = G
+        M[:, :nlv, nlv] = D
+        rhs[:, :nlv] = -np.einsum("clm,mc->cl", G, pops)
+        r = np.argmax(pops, axis=0)
+        idx = np.arange(nc)
+        M[idx, r, :] = 0.0
+        M[idx, r, :nlv] = 1.0
+        rhs[idx, r] = self.ntot - pops.sum(axis=0)
+        M[:, nlv, cl] = -1.0
+        M[:, nlv, nlv] = 1.0
+        rhs[:, nlv] = pops[cl] - ne
+        d = np.linalg.solve(M, rhs[..., None])[..., 0]
+        new = pops + d[:, :nlv].T
+        ne_new = ne + d[:, nlv]
+        ok = np.all(new > 0, axis=0) & (ne_new > 0)
+        new = np.where(ok[None, :], new, pops)
+        ne_new = np.where(ok, ne_new, ne)
+        return new, ne_new
+
     def stat_eq(self, pops, Rup, Rdn):
         """Solve Gamma n = 0 with the most populated level's row replaced by
         sum(n) = ntot. Returns new populations and max |dn| / n_new."""
@@ -330,17 +391,29 @@ class Problem:
         change = float(np.max(np.abs(new - pops) / np.abs(new)))
         return new, change
 
-    def iterate(self, pops, n_iter: int, tol: float | None = None, ng: tuple | None = None):
+    def iterate(self, pops, n_iter: int, tol: float | None = None, ng: tuple | None = None,
+                charge: bool = False):
         """The iteration of Sec. 3.3: formal solution with rates, then the
         equilibrium step. Stops after n_iter iterations or once the max
         relative change drops below tol. ng = (order M, delay, period) adds Ng
-        acceleration after the equilibrium step (not used by the paper)."""
+        acceleration after the equilibrium step (not used by the paper).
+        charge: one Newton-Raphson charge-conservation step after each
+        equilibrium step, n_e carried from iteration to iteration (the final
+        n_e is left in ``self.last_ne``)."""
         changes = []
         hist = []  # newest last
+        P = self
         for it in range(1, n_iter + 1):
-            J, I0, chi_loc, H_loc, _ = self.formal_solve(pops)
-            Rup, Rdn = self.rates(pops, I0, chi_loc, H_loc)
-            pops, ch = self.stat_eq(pops, Rup, Rdn)
+            J, I0, chi_loc, H_loc, _ = P.formal_solve(pops)
+            Rup, Rdn = P.rates(pops, I0, chi_loc, H_loc)
+            old = pops
+            pops, ch = P.stat_eq(pops, Rup, Rdn)
+            if charge:
+                pops, ne_new = P.charge_step(pops, Rup, Rdn)
+                ch = max(float(np.max(np.abs(pops - old) / np.abs(pops))),
+                         float(np.max(np.abs(ne_new - P.ne) / ne_new)))
+                P = self.with_ne(ne_new)
+                self.last_ne = P.ne
             changes.append(ch)
             if tol is not None and ch < tol:
                 break

@@ -203,3 +203,73 @@ def test_ng_extrapolation_of_converged_iterates_is_identity():
     from oracle.nlte import ng_extrapolate
     x = np.full((2, 5), 1.5)
     assert ng_extrapolate([x, x, x, x], 2) is None
+
+
+# ------------------------------------------------------ charge conservation
+
+
+def test_charge_conservation_collisional_limit_is_saha():
+    """Sec. 3.3 (charge conservation by a Newton-Raphson step, also used for
+    a self-consistent starting n_e from the collisional rates alone): with
+    the radiative rates switched off the equilibrium is LTE at the current
+    n_e, and repeated steps drive n_e to the Saha solution of a plasma whose
+    only electron donor is this atom, n_e^2 = Phi (n_tot - n_e) / U, with
+    Phi = n_c n_e / n_1 from the Saha equation and U the bound partition
+    function relative to the ground level; the convergence is quadratic, as
+    a Newton step with the right derivative must be."""
+    from oracle.nlte import H_PLANCK, K_BOLTZ, M_ELEC
+    inp = W.nlte_atmosphere(8, seed=3, n_line=8, n_cont=4)
+    P = nlte.Problem(inp)
+    A = P.atom
+    kT = K_BOLTZ * P.T
+    cl = A.n_levels - 1
+    U = sum(A.g[l] / A.g[0] * np.exp(-(A.E[l] - A.E[0]) / kT) for l in range(cl))
+    Phi = A.g[cl] / A.g[0] * 2.0 * (2.0 * np.pi * M_ELEC * kT / H_PLANCK ** 2) ** 1.5 * np.exp(-(A.E[cl] - A.E[0]) / kT)
+    Pp = Phi / U
+    ne_true = 0.5 * (-Pp + np.sqrt(Pp * Pp + 4.0 * Pp * P.ntot))
+    zero = np.zeros((len(A.trans), P.ncell))
+    Q = P.with_ne(1.3 * ne_true)
+    pops = Q.lte
+    errs = []
+    for _ in range(7):
+        pops, _ = Q.stat_eq(pops, zero, zero)
+        pops, ne = Q.charge_step(pops, zero, zero)
+        Q = P.with_ne(ne)
+        errs.append(float(np.max(np.abs(ne / ne_true - 1.0))))
+    assert errs[-1] < 1e-12, errs
+    k = next(i for i, e in enumerate(errs) if e < 1e-3)
+    assert errs[k + 1] < 10 * errs[k] ** 2 + 1e-14, errs       # quadratic
+    np.testing.assert_allclose(pops[cl], ne_true, rtol=1e-10)
+    pops_eq, _ = Q.stat_eq(pops, zero, zero)
+    np.testing.assert_allclose(pops_eq, Q.lte, rtol=1e-10)
+
+
+def test_charge_step_at_a_solution_is_zero():
+    """At populations in equilibrium with n_e = n_c the Newton-Raphson step
+    changes nothing."""
+    inp = W.nlte_atmosphere(8, seed=3, n_line=8, n_cont=4)
+    P = nlte.Problem(inp)
+    zero = np.zeros((len(P.atom.trans), P.ncell))
+    Q = P.with_ne(P.ne)
+    pops = Q.lte
+    for _ in range(8):
+        pops, _ = Q.stat_eq(pops, zero, zero)
+        pops, ne = Q.charge_step(pops, zero, zero)
+        Q = P.with_ne(ne)
+    pops, _ = Q.stat_eq(pops, zero, zero)
+    new, ne2 = Q.charge_step(pops, zero, zero)
+    np.testing.assert_allclose(new, pops, rtol=1e-12)
+    np.testing.assert_allclose(ne2, Q.ne, rtol=1e-12)
+
+
+def test_charge_conserving_iteration_converges_with_n_e_equal_n_c():
+    """The full iteration with charge conservation (radiation on) converges
+    to populations with n_e = n_c in every cell, in a number of iterations
+    comparable to the iteration at fixed n_e."""
+    inp = W.nlte_atmosphere(16, seed=3, n_line=16, n_cont=8)
+    P = nlte.Problem(inp)
+    _, plain = P.iterate(P.lte.copy(), 200, tol=1e-3)
+    pops, ch = P.iterate(P.lte.copy(), 200, tol=1e-3, charge=True)
+    cl = P.atom.n_levels - 1
+    assert ch[-1] < 1e-3 and len(ch) < 3 * len(plain)
+    np.testing.assert_allclose(P.last_ne, pops[cl], rtol=5e-3)
