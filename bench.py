@@ -171,7 +171,7 @@ def nlte_solves(args):
     if os.path.exists(args.weights):
         net, fn, tn = warmstart.load(args.weights)
     runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False),
-            ("ng_fp32", rcx.RCX_STORE_F32, False)]
+            ("ng_fp32", rcx.RCX_STORE_F32, False), ("charge_fp32", rcx.RCX_STORE_F32, False)]
     if net is not None:
         runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True),
                  ("learned_ng_fp16", rcx.RCX_STORE_F16_SCALED, True)]
@@ -188,6 +188,10 @@ def nlte_solves(args):
             # Ng acceleration (not in the paper): order 2, first after 4
             # iterations, then every 4
             s.set_acceleration(2, 4, 4)
+        if "charge" in name:
+            # charge conservation: a Newton-Raphson step on the populations
+            # and n_e after each equilibrium step
+            s.set_charge_conservation(True)
         t0 = time.perf_counter()
         p = s.warm_start(net, fn, tn) if learned else s.lte()
         it, rc, ch = 0, 1, float("inf")

@@ -333,6 +333,27 @@ int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, doub
  * or period < 1. */
 int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int32_t period);
 
+/* Charge conservation (Sec. 3.3; off by default): after each equilibrium
+ * step of rcx_nlte_stat_eq / rcx_nlte_iterate, one Newton-Raphson step per
+ * cell on the populations and the electron density, with the equations
+ * Gamma(n_e) n = 0 (one row replaced by particle conservation, the most
+ * populated level's after the equilibrium step) and n_e = n_c (the
+ * continuum level: this atom, taken as hydrogen, is the only electron
+ * donor). dGamma/dn_e takes the rates proportional to n_e (collisional
+ * downward, bound-bound collisional upward, radiative recombination)
+ * divided by n_e; the other rates are held. The step is skipped in a cell
+ * where it would make a population or n_e non-positive. The solver's n_e
+ * (initially the one given to rcx_nlte_set_atmosphere) is updated in place,
+ * and the LTE populations, collisional rates and continuum LTE ratios are
+ * recomputed from it; the reported change includes |dn_e| / n_e. Setting the
+ * atmosphere again restores the given n_e. */
+int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable);
+
+/* The solver's current electron density [ncell] (device, FP64) into ne
+ * (device, caller-owned), enqueued on the stream. RCX_E_INVALID for a null
+ * argument or before rcx_nlte_set_atmosphere. */
+int32_t rcx_nlte_get_ne(rcx_nlte* s, double* ne, hipStream_t stream);
+
 /* Line profile of the march (the Voigt function H(a, x) of Sec. 3.3's line
  * opacity), chosen at rcx_nlte_set_atmosphere:
  *   RCX_PROFILE_AUTO   the expansion about a = 0 when every cell has damping

@@ -682,7 +682,8 @@ template <int NL>
 __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const float* __restrict__ rates,
                                                   const double* __restrict__ cup, const double* __restrict__ cdn,
                                                   const double* __restrict__ ntot, double* __restrict__ pops,
-                                                  unsigned long long* __restrict__ max_change)
+                                                  unsigned long long* __restrict__ max_change,
+                                                  double* __restrict__ ne)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double change = 0.0;
@@ -705,6 +706,9 @@ __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const
                 if (l != m) s += G[l][m];
             G[m][m] = -s;
         }
+        double G0[NL][NL];  // Gamma before the conservation row (charge step)
+        for (int l = 0; l < NL; ++l)
+            for (int m = 0; m < NL; ++m) G0[l][m] = G[l][m];
         int r = 0;
         for (int l = 1; l < NL; ++l)
             if (n[l] > n[r]) r = l;
@@ -732,6 +736,82 @@ __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const
             double s = G[l][NL];
             for (int m = l + 1; m < NL; ++m) s -= G[l][m] * x[m];
             x[l] = s / G[l][l];
+        }
+        if (ne) {
+            // charge conservation (Sec. 3.3): one Newton-Raphson step on
+            // (n, n_e) with n_e = n_c (the continuum level, hydrogen the
+            // only donor). dGamma/dn_e holds the rates proportional to n_e:
+            // collisional downward, bound-bound collisional upward and
+            // radiative recombination, divided by n_e.
+            const double e = ne[c];
+            constexpr int cl = NL - 1;
+            double D[NL];
+            for (int l = 0; l < NL; ++l) D[l] = 0.0;
+            for (int k = 0; k < A.nt; ++k) {
+                const Trans& tr = A.t[k];
+                const double upE = tr.kind == 0 ? cup[(int64_t)k * ncell + c] / e : 0.0;
+                const double dnE =
+                    (cdn[(int64_t)k * ncell + c] + (tr.kind == 1 ? (double)rates[((int64_t)k * 2 + 1) * ncell + c] : 0.0)) /
+                    e;
+                D[tr.j] += upE * x[tr.i];
+                D[tr.i] -= upE * x[tr.i];
+                D[tr.i] += dnE * x[tr.j];
+                D[tr.j] -= dnE * x[tr.j];
+            }
+            int r2 = 0;
+            for (int l = 1; l < NL; ++l)
+                if (x[l] > x[r2]) r2 = l;
+            double M[NL + 1][NL + 2];
+            double sx = 0.0;
+            for (int l = 0; l < NL; ++l) sx += x[l];
+            for (int l = 0; l < NL; ++l) {
+                double gx = 0.0;
+                for (int m = 0; m < NL; ++m) {
+                    M[l][m] = G0[l][m];
+                    gx += G0[l][m] * x[m];
+                }
+                M[l][NL] = D[l];
+                M[l][NL + 1] = -gx;
+            }
+            for (int m = 0; m < NL; ++m) M[r2][m] = 1.0;
+            M[r2][NL] = 0.0;
+            M[r2][NL + 1] = ntot[c] - sx;
+            for (int m = 0; m < NL; ++m) M[NL][m] = 0.0;
+            M[NL][cl] = -1.0;
+            M[NL][NL] = 1.0;
+            M[NL][NL + 1] = x[cl] - e;
+            for (int col = 0; col <= NL; ++col) {
+                int piv = col;
+                for (int l = col + 1; l <= NL; ++l)
+                    if (fabs(M[l][col]) > fabs(M[piv][col])) piv = l;
+                if (piv != col)
+                    for (int m = 0; m <= NL + 1; ++m) {
+                        const double t = M[col][m];
+                        M[col][m] = M[piv][m];
+                        M[piv][m] = t;
+                    }
+                const double inv = 1.0 / M[col][col];
+                for (int l = col + 1; l <= NL; ++l) {
+                    const double f = M[l][col] * inv;
+                    for (int m = col; m <= NL + 1; ++m) M[l][m] -= f * M[col][m];
+                }
+            }
+            double d[NL + 1];
+            for (int l = NL; l >= 0; --l) {
+                double s = M[l][NL + 1];
+                for (int m = l + 1; m <= NL; ++m) s -= M[l][m] * d[m];
+                d[l] = s / M[l][l];
+            }
+            // the step is taken only if it keeps every population and n_e
+            // positive
+            bool ok = e + d[NL] > 0.0;
+            for (int l = 0; l < NL; ++l) ok = ok && x[l] + d[l] > 0.0;
+            if (ok) {
+                for (int l = 0; l < NL; ++l) x[l] += d[l];
+                const double e1 = e + d[NL];
+                change = fmax(change, fabs(e1 - e) / e1);
+                ne[c] = e1;
+            }
         }
         for (int l = 0; l < NL; ++l) {
             change = fmax(change, fabs(x[l] - n[l]) / fabs(x[l]));
@@ -878,6 +958,9 @@ struct rcx_nlte {
     // Ng acceleration: order M (0 = off), first after ng_delay iterations,
     // then every ng_period; ring of the last M + 2 iterates
     int32_t ng_order = 0, ng_delay = 0, ng_period = 1;
+    // charge conservation: a Newton-Raphson step after each equilibrium
+    // step updates ne_copy, and the n_e-dependent static data follow
+    int32_t charge = 0;
     int32_t ng_count = 0, ng_head = 0, ng_iter = 0;
     double* ng_hist = nullptr;   // [M + 2][nl][ncell]
     double* ng_part = nullptr;   // [kNgBlocks][kNgSums] partial sums
@@ -954,7 +1037,7 @@ template <int NL>
 hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t st)
 {
     hipLaunchKernelGGL(k_stat_eq<NL>, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->atom, s->ncell, rates,
-                       s->cup, s->cdn, s->ntot, pops, s->d_max);
+                       s->cup, s->cdn, s->ntot, pops, s->d_max, s->charge ? s->ne_copy : nullptr);
     return hipGetLastError();
 }
 
@@ -1158,6 +1241,21 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
         return rcx::hip_fail(e, "rcx_nlte_create: hipMemcpy");
     }
     *out = s;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_charge_conservation: null solver");
+    s->charge = enable != 0;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_get_ne(rcx_nlte* s, double* ne, hipStream_t st)
+{
+    if (!s || !ne) return nlte_fail(RCX_E_INVALID, "rcx_nlte_get_ne: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_get_ne: set the atmosphere first");
+    RCX_HIP_TRY(hipMemcpyAsync(ne, s->ne_copy, sizeof(double) * s->ncell, hipMemcpyDeviceToDevice, st));
     return RCX_OK;
 }
 
@@ -1507,6 +1605,14 @@ static int32_t stat_eq(rcx_nlte* s, const float* rates, double* pops, double* ch
     default: return nlte_fail(RCX_E_UNSUPPORTED, "stat_eq: level count");
     }
     RCX_HIP_TRY(e);
+    if (s->charge) {
+        // LTE populations, collisional rates and continuum LTE ratios at the
+        // new n_e (the damping maximum does not depend on n_e)
+        StaticOut o{s->lte, s->cup, s->cdn, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->d_amax};
+        hipLaunchKernelGGL(k_static, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->atom, s->ncell, s->T,
+                           s->ne_copy, s->ntot, o);
+        RCX_HIP_TRY(hipGetLastError());
+    }
     unsigned long long bits = 0;
     RCX_HIP_TRY(hipMemcpyAsync(&bits, s->d_max, sizeof(bits), hipMemcpyDeviceToHost, st));
     RCX_HIP_TRY(hipStreamSynchronize(st));

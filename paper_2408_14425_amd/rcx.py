@@ -305,6 +305,8 @@ def _load_nlte():
     L.rcx_nlte_set_atmosphere.argtypes = [vp, vp, vp, vp, vp, vp]
     L.rcx_nlte_set_line_profile.argtypes = [vp, i32]
     L.rcx_nlte_set_acceleration.argtypes = [vp, i32, i32, i32]
+    L.rcx_nlte_set_charge_conservation.argtypes = [vp, i32]
+    L.rcx_nlte_get_ne.argtypes = [vp, vp, vp]
     L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
     L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -316,7 +318,8 @@ def _load_nlte():
     L.rcx_nlte_features.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
-    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start"):
+    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start",
+              "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne"):
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
@@ -341,6 +344,16 @@ def rcx_nlte_create(grid: rcx_grid, params: rcx_params, atom: rcx_atom, lambda_n
 def rcx_nlte_set_acceleration(s: int, order: int, delay: int, period: int) -> int:
     return _check(_load_nlte().rcx_nlte_set_acceleration(s, int(order), int(delay), int(period)),
                   "rcx_nlte_set_acceleration")
+
+
+def rcx_nlte_set_charge_conservation(s: int, enable: bool) -> int:
+    return _check(_load_nlte().rcx_nlte_set_charge_conservation(s, int(bool(enable))),
+                  "rcx_nlte_set_charge_conservation")
+
+
+def rcx_nlte_get_ne(s: int, ne, stream=None) -> int:
+    return _check(_load_nlte().rcx_nlte_get_ne(s, _dev_ptr(ne, "torch.float64", "ne"), _stream_ptr(stream)),
+                  "rcx_nlte_get_ne")
 
 
 def rcx_nlte_set_line_profile(s: int, mode: int) -> int:
@@ -443,6 +456,18 @@ class Nlte:
     def set_acceleration(self, order: int, delay: int = 0, period: int = 1):
         """Ng acceleration of iterate() (order 0 = off)."""
         rcx_nlte_set_acceleration(self.handle, order, delay, period)
+
+    def set_charge_conservation(self, enable: bool = True):
+        """One Newton-Raphson charge-conservation step after each
+        equilibrium step (n_e updated on the device)."""
+        rcx_nlte_set_charge_conservation(self.handle, enable)
+
+    def electron_density(self):
+        """The solver's current electron density [ncell], FP64 on the GPU."""
+        import torch
+        out = torch.empty(self.inp.nx * self.inp.nz, dtype=torch.float64, device="cuda")
+        rcx_nlte_get_ne(self.handle, out)
+        return out
 
     def voigt(self, a, x, march: bool = False):
         """H(a, x) from the solver's tables: the full table (features), or

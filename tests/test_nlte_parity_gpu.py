@@ -242,3 +242,36 @@ def test_converged_64_at_oracle_iteration_count():
           f"max rel {relp.max():.3e}")
     assert it == K
     assert relp.max() < 1e-3
+
+
+def test_charge_conservation_matches_oracle(case32):
+    """Charge conservation (Sec. 3.3): one Newton-Raphson step on the
+    populations and n_e after each equilibrium step. After 5 iterations the
+    GPU's populations and electron density agree with the oracle's to 1e-3,
+    and the converged run stops within one iteration of the oracle's
+    count."""
+    torch = _torch()
+    inp, P = case32
+    po, changes = P.iterate(P.lte.copy(), 5, charge=True)
+    ne_o = P.last_ne.copy()
+    pc, ch_c = P.iterate(P.lte.copy(), 200, tol=1e-3, charge=True)
+    K = len(ch_c)
+    s = _solver(inp)
+    s.set_charge_conservation(True)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, 5, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    ne_g = s.electron_density().cpu().numpy()
+    s.close()
+    s = _solver(inp)
+    s.set_charge_conservation(True)
+    pops2 = s.lte()
+    rc2, it2, ch2 = s.iterate(pops2, K + 2, 1e-3)
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    rele = np.abs(ne_g - ne_o) / ne_o
+    print(f"charge: after 5 iterations pops max rel {relp.max():.3e}, n_e max rel {rele.max():.3e}, "
+          f"n_e moved {np.abs(ne_o / P.ne - 1).max():.3e}; oracle converges in {K}, gpu rc {rc2} at {it2}")
+    assert it == 5
+    assert relp.max() < 1e-3 and rele.max() < 1e-3
+    assert rc2 == 0 and abs(it2 - K) <= 1
