@@ -40,6 +40,13 @@ Readings (listed in the design notes):
     is proportional to n_e); dGamma/dn_e = (those rates) / n_e, all other
     rates held fixed. The step is taken only if it leaves every population
     and n_e positive. The change metric includes |dn_e| / n_e.
+  - Pressure conservation (needs charge conservation): the gas pressure
+    P = (A_tot n_Htot + n_e) k T of the starting atmosphere is held, with
+    A_tot = 1 (this atom is the only species); after the charge step n_Htot
+    becomes P/(kT) - n_e and every population is scaled by its ratio to the
+    old n_Htot; the change metric includes |dn_Htot| / n_Htot.
+  - Starting n_e from the collisional rates alone: equilibrium and charge
+    steps with the radiative rates set to zero, from the given n_e.
 """
 from __future__ import annotations
 
@@ -327,14 +334,17 @@ class Problem:
             G[:, l, l] = -(G.sum(axis=1)[:, l] - G[:, l, l])
         return G
 
-    def with_ne(self, ne):
-        """A copy of the problem at electron density ne: the LTE populations,
-        collisional rates and continuum coefficients follow n_e."""
+    def with_ne(self, ne, ntot=None):
+        """A copy of the problem at electron density ne (and hydrogen
+        density ntot): the LTE populations, collisional rates and continuum
+        coefficients follow them."""
         import copy
         P = copy.copy(self)
         P.ne = np.asarray(ne, np.float64).copy()
-        P.lte = lte_populations(self.atom, self.T, P.ne, self.ntot)
-        P.Cdown = np.array([P.ne * t.q * (self.T / 1e4) ** -0.5 for t in self.atom.trans])
+        if ntot is not None:
+            P.ntot = np.asarray(ntot, np.float64).copy()
+        P.lte = lte_populations(self.atom, self.T, P.ne, P.ntot)
+        P.Cdown = np.array([P.ne * t.q * (P.T / 1e4) ** -0.5 for t in self.atom.trans])
         P.Cup = np.array([cd * P.lte[t.j] / P.lte[t.i] for cd, t in zip(P.Cdown, self.atom.trans)])
         return P
 
@@ -391,18 +401,34 @@ class Problem:
         change = float(np.max(np.abs(new - pops) / np.abs(new)))
         return new, change
 
+    def collisional_ne(self, n_iter: int = 20):
+        """Starting n_e from the collisional rates alone (radiative rates
+        zero): n_iter equilibrium + charge steps from the given n_e, LTE
+        start. Returns the problem at that n_e."""
+        zero = np.zeros((len(self.atom.trans), self.ncell))
+        P = self
+        pops = P.lte
+        for _ in range(n_iter):
+            pops, _ = P.stat_eq(pops, zero, zero)
+            pops, ne = P.charge_step(pops, zero, zero)
+            P = self.with_ne(ne)
+        return P
+
     def iterate(self, pops, n_iter: int, tol: float | None = None, ng: tuple | None = None,
-                charge: bool = False):
+                charge: bool = False, pressure: bool = False):
         """The iteration of Sec. 3.3: formal solution with rates, then the
         equilibrium step. Stops after n_iter iterations or once the max
         relative change drops below tol. ng = (order M, delay, period) adds Ng
         acceleration after the equilibrium step (not used by the paper).
         charge: one Newton-Raphson charge-conservation step after each
         equilibrium step, n_e carried from iteration to iteration (the final
-        n_e is left in ``self.last_ne``)."""
+        n_e is left in ``self.last_ne``); pressure (with charge): n_Htot
+        rescaled to hold the starting pressure after each charge step (the
+        final n_Htot in ``self.last_ntot``)."""
         changes = []
         hist = []  # newest last
         P = self
+        p_kt = self.ntot + self.ne  # P / (k T), A_tot = 1
         for it in range(1, n_iter + 1):
             J, I0, chi_loc, H_loc, _ = P.formal_solve(pops)
             Rup, Rdn = P.rates(pops, I0, chi_loc, H_loc)
@@ -410,10 +436,18 @@ class Problem:
             pops, ch = P.stat_eq(pops, Rup, Rdn)
             if charge:
                 pops, ne_new = P.charge_step(pops, Rup, Rdn)
+                nt_new = P.ntot
+                if pressure:
+                    nt_new = p_kt - ne_new
+                    ok = nt_new > 0
+                    nt_new = np.where(ok, nt_new, P.ntot)
+                    pops = pops * (nt_new / P.ntot)[None, :]
                 ch = max(float(np.max(np.abs(pops - old) / np.abs(pops))),
-                         float(np.max(np.abs(ne_new - P.ne) / ne_new)))
-                P = self.with_ne(ne_new)
+                         float(np.max(np.abs(ne_new - P.ne) / ne_new)),
+                         float(np.max(np.abs(nt_new - P.ntot) / nt_new)))
+                P = self.with_ne(ne_new, nt_new)
                 self.last_ne = P.ne
+                self.last_ntot = P.ntot
             changes.append(ch)
             if tol is not None and ch < tol:
                 break

@@ -273,3 +273,53 @@ def test_charge_conserving_iteration_converges_with_n_e_equal_n_c():
     cl = P.atom.n_levels - 1
     assert ch[-1] < 1e-3 and len(ch) < 3 * len(plain)
     np.testing.assert_allclose(P.last_ne, pops[cl], rtol=5e-3)
+
+
+def test_collisional_starting_n_e_is_saha():
+    """Sec. 3.3: the starting n_e from the collisional rates alone is the
+    Saha n_e of the pure plasma (the same closed form as above)."""
+    from oracle.nlte import H_PLANCK, K_BOLTZ, M_ELEC
+    inp = W.nlte_atmosphere(8, seed=4, n_line=8, n_cont=4)
+    P = nlte.Problem(inp)
+    A = P.atom
+    kT = K_BOLTZ * P.T
+    cl = A.n_levels - 1
+    U = sum(A.g[l] / A.g[0] * np.exp(-(A.E[l] - A.E[0]) / kT) for l in range(cl))
+    Pp = A.g[cl] / A.g[0] * 2.0 * (2.0 * np.pi * M_ELEC * kT / H_PLANCK ** 2) ** 1.5 \
+        * np.exp(-(A.E[cl] - A.E[0]) / kT) / U
+    ne_true = 0.5 * (-Pp + np.sqrt(Pp * Pp + 4.0 * Pp * P.ntot))
+    Q = P.collisional_ne(20)
+    np.testing.assert_allclose(Q.ne, ne_true, rtol=1e-10)
+
+
+def test_pressure_conservation_holds_the_starting_pressure():
+    """Sec. 3.3 (pressure conservation, with charge conservation): every
+    iteration leaves n_Htot + n_e at its starting value (A_tot = 1) and the
+    iteration converges; with radiation off its fixed point is the Saha
+    solution under that pressure, n_e = -Phi' + sqrt(Phi'^2 + Phi' P/kT)."""
+    from oracle.nlte import H_PLANCK, K_BOLTZ, M_ELEC
+    inp = W.nlte_atmosphere(16, seed=3, n_line=16, n_cont=8)
+    P = nlte.Problem(inp)
+    p_kt = P.ntot + P.ne
+    pops, ch = P.iterate(P.lte.copy(), 200, tol=1e-3, charge=True, pressure=True)
+    assert ch[-1] < 1e-3
+    np.testing.assert_allclose(P.last_ntot + P.last_ne, p_kt, rtol=1e-12)
+    np.testing.assert_allclose(pops.sum(axis=0), P.last_ntot, rtol=1e-9)
+    # collisional limit under constant pressure
+    A = P.atom
+    kT = K_BOLTZ * P.T
+    cl = A.n_levels - 1
+    U = sum(A.g[l] / A.g[0] * np.exp(-(A.E[l] - A.E[0]) / kT) for l in range(cl))
+    Pp = A.g[cl] / A.g[0] * 2.0 * (2.0 * np.pi * M_ELEC * kT / H_PLANCK ** 2) ** 1.5 \
+        * np.exp(-(A.E[cl] - A.E[0]) / kT) / U
+    ne_true = -Pp + np.sqrt(Pp * Pp + Pp * p_kt)
+    zero = np.zeros((len(A.trans), P.ncell))
+    Q = P
+    pops = Q.lte
+    for _ in range(30):
+        pops, _ = Q.stat_eq(pops, zero, zero)
+        pops, ne = Q.charge_step(pops, zero, zero)
+        nt = p_kt - ne
+        pops = pops * (nt / Q.ntot)[None, :]
+        Q = P.with_ne(ne, nt)
+    np.testing.assert_allclose(Q.ne, ne_true, rtol=1e-9)
