@@ -349,6 +349,22 @@ int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int
  * atmosphere again restores the given n_e. */
 int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable);
 
+/* Pressure conservation (Sec. 3.3; needs charge conservation, else
+ * RCX_E_INVALID): after each charge step the hydrogen density becomes
+ * n_Htot = P/(kT) - n_e, holding the gas pressure (A_tot n_Htot + n_e) k T
+ * of the atmosphere as set (A_tot = 1: this atom is the only species), and
+ * every population is scaled with it; the change includes |dn_Htot| /
+ * n_Htot. */
+int32_t rcx_nlte_set_pressure_conservation(rcx_nlte* s, int32_t enable);
+
+/* Starting n_e from the collisional rates alone (Sec. 3.3): n_iter
+ * equilibrium + charge steps with the radiative rates set to zero, from LTE
+ * at the current n_e; leaves the solver's n_e (and the LTE populations,
+ * collisional rates and the held pressure) at the result. Synchronous;
+ * allocates and frees one populations-sized temporary. RCX_E_INVALID for a
+ * null solver, n_iter < 1, or before rcx_nlte_set_atmosphere. */
+int32_t rcx_nlte_collisional_ne(rcx_nlte* s, int32_t n_iter, hipStream_t stream);
+
 /* The solver's current electron density [ncell] (device, FP64) into ne
  * (device, caller-owned), enqueued on the stream. RCX_E_INVALID for a null
  * argument or before rcx_nlte_set_atmosphere. */

@@ -354,6 +354,13 @@ __global__ void k_static(AtomDev A, int64_t ncell, const double* __restrict__ T,
     if (threadIdx.x == 0) atomicMax(o.amax_bits, __float_as_uint(red[0]));
 }
 
+// out = a + b per cell (the pressure P / (k T) = n_Htot + n_e, A_tot = 1).
+__global__ void k_sum2(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a[i] + b[i];
+}
+
 // -------------------------------------------------------------- synthesis
 // Lines: rec[line][c] = {kappa (optical depth per cell at H = 1, log2 units),
 // S_line, a in Voigt-table units (a / da), 1/v_th}, with kappa = sigma/(sqrt(pi) dnu_D) (n_i - g_i/g_j n_j)
@@ -681,9 +688,9 @@ __global__ void k_rates_sum(int64_t ncell, int32_t nt, const int32_t* __restrict
 template <int NL>
 __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const float* __restrict__ rates,
                                                   const double* __restrict__ cup, const double* __restrict__ cdn,
-                                                  const double* __restrict__ ntot, double* __restrict__ pops,
+                                                  double* __restrict__ ntot, double* __restrict__ pops,
                                                   unsigned long long* __restrict__ max_change,
-                                                  double* __restrict__ ne)
+                                                  double* __restrict__ ne, const double* __restrict__ p_kt)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double change = 0.0;
@@ -811,6 +818,17 @@ __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const
                 const double e1 = e + d[NL];
                 change = fmax(change, fabs(e1 - e) / e1);
                 ne[c] = e1;
+            }
+            if (p_kt) {
+                // pressure conservation: n_Htot + n_e held at P / (k T)
+                // (A_tot = 1), every population scaled with n_Htot
+                const double nt0 = ntot[c], nt1 = p_kt[c] - ne[c];
+                if (nt1 > 0.0) {
+                    const double f = nt1 / nt0;
+                    for (int l = 0; l < NL; ++l) x[l] *= f;
+                    ntot[c] = nt1;
+                    change = fmax(change, fabs(nt1 - nt0) / nt1);
+                }
             }
         }
         for (int l = 0; l < NL; ++l) {
@@ -961,6 +979,9 @@ struct rcx_nlte {
     // charge conservation: a Newton-Raphson step after each equilibrium
     // step updates ne_copy, and the n_e-dependent static data follow
     int32_t charge = 0;
+    // pressure conservation (with charge): n_Htot + n_e held at p_kt
+    int32_t pressure = 0;
+    double* p_kt = nullptr;  // [ncell] P / (k T) of the atmosphere as set
     int32_t ng_count = 0, ng_head = 0, ng_iter = 0;
     double* ng_hist = nullptr;   // [M + 2][nl][ncell]
     double* ng_part = nullptr;   // [kNgBlocks][kNgSums] partial sums
@@ -1037,7 +1058,8 @@ template <int NL>
 hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t st)
 {
     hipLaunchKernelGGL(k_stat_eq<NL>, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->atom, s->ncell, rates,
-                       s->cup, s->cdn, s->ntot, pops, s->d_max, s->charge ? s->ne_copy : nullptr);
+                       s->cup, s->cdn, s->ntot, pops, s->d_max, s->charge ? s->ne_copy : nullptr,
+                       s->charge && s->pressure ? s->p_kt : nullptr);
     return hipGetLastError();
 }
 
@@ -1190,6 +1212,7 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->T, sizeof(double) * nc));
     chk(dmalloc(s, &s->ntot, sizeof(double) * nc));
     chk(dmalloc(s, &s->ne_copy, sizeof(double) * nc));
+    chk(dmalloc(s, &s->p_kt, sizeof(double) * nc));
     chk(dmalloc(s, &s->inv_vth, sizeof(float) * nc));
     chk(dmalloc(s, &s->adamp, sizeof(float) * std::max(1, A.n_lines) * nc));
     chk(dmalloc(s, &s->sphi, sizeof(float) * std::max(1, A.n_lines) * nc));
@@ -1251,6 +1274,54 @@ int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable)
     return RCX_OK;
 }
 
+int32_t rcx_nlte_set_pressure_conservation(rcx_nlte* s, int32_t enable)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_pressure_conservation: null solver");
+    if (enable && !s->charge)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_pressure_conservation: needs charge conservation");
+    s->pressure = enable != 0;
+    return RCX_OK;
+}
+
+static int32_t stat_eq(rcx_nlte* s, const float* rates, double* pops, double* change_host, hipStream_t st);
+
+int32_t rcx_nlte_collisional_ne(rcx_nlte* s, int32_t n_iter, hipStream_t st)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_collisional_ne: null solver");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_collisional_ne: set the atmosphere first");
+    if (n_iter < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_collisional_ne: n_iter must be >= 1");
+    // radiative rates zero; populations from LTE at the current n_e, then
+    // equilibrium + charge steps on a temporary copy
+    double* pops = nullptr;
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    RCX_HIP_TRY(hipMalloc((void**)&pops, sizeof(double) * s->atom.nl * s->ncell));
+    const int64_t nr = (int64_t)s->atom.nt * 2 * s->ncell;
+    hipLaunchKernelGGL(k_zero_u32n, dim3(blocks_for(nr, 256)), dim3(256), 0, st, (unsigned int*)s->rates,
+                       (int32_t)nr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(pops, s->lte, sizeof(double) * s->atom.nl * s->ncell,
+                                             hipMemcpyDeviceToDevice, st);
+    const int32_t charge = s->charge, pressure = s->pressure;
+    s->charge = 1;
+    s->pressure = 0;
+    int32_t rc = e == hipSuccess ? RCX_OK : rcx::hip_fail(e, "rcx_nlte_collisional_ne");
+    for (int32_t it = 0; it < n_iter && rc == RCX_OK; ++it) {
+        double ch = 0.0;
+        rc = stat_eq(s, s->rates, pops, &ch, st);
+    }
+    s->charge = charge;
+    s->pressure = pressure;
+    const hipError_t es = hipStreamSynchronize(st);
+    (void)hipFree(pops);
+    if (rc != RCX_OK) return rc;
+    RCX_HIP_TRY(es);
+    // the pressure held from here on is that of the atmosphere at this n_e
+    hipLaunchKernelGGL(k_sum2, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, s->ntot, s->ne_copy,
+                       s->p_kt);
+    RCX_HIP_TRY(hipGetLastError());
+    return RCX_OK;
+}
+
 int32_t rcx_nlte_get_ne(rcx_nlte* s, double* ne, hipStream_t st)
 {
     if (!s || !ne) return nlte_fail(RCX_E_INVALID, "rcx_nlte_get_ne: null argument");
@@ -1277,6 +1348,8 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
     RCX_HIP_TRY(hipMemcpyAsync(s->ntot, ntot, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     RCX_HIP_TRY(hipMemcpyAsync(s->ne_copy, ne, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(k_pack_vel, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, vel, s->vel);
+    RCX_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_sum2, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, ntot, ne, s->p_kt);
     RCX_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, s->d_amax);
     RCX_HIP_TRY(hipGetLastError());

@@ -307,6 +307,8 @@ def _load_nlte():
     L.rcx_nlte_set_acceleration.argtypes = [vp, i32, i32, i32]
     L.rcx_nlte_set_charge_conservation.argtypes = [vp, i32]
     L.rcx_nlte_get_ne.argtypes = [vp, vp, vp]
+    L.rcx_nlte_set_pressure_conservation.argtypes = [vp, i32]
+    L.rcx_nlte_collisional_ne.argtypes = [vp, i32, vp]
     L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
     L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -319,7 +321,8 @@ def _load_nlte():
     L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
     for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start",
-              "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne"):
+              "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_set_pressure_conservation",
+              "rcx_nlte_collisional_ne"):
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
@@ -461,6 +464,17 @@ class Nlte:
         """One Newton-Raphson charge-conservation step after each
         equilibrium step (n_e updated on the device)."""
         rcx_nlte_set_charge_conservation(self.handle, enable)
+
+    def set_pressure_conservation(self, enable: bool = True):
+        """Hold the atmosphere's gas pressure by rescaling n_Htot after each
+        charge step (needs charge conservation)."""
+        _check(_load_nlte().rcx_nlte_set_pressure_conservation(self.handle, int(bool(enable))),
+               "rcx_nlte_set_pressure_conservation")
+
+    def collisional_ne(self, n_iter: int = 20):
+        """Starting n_e from the collisional rates alone."""
+        _check(_load_nlte().rcx_nlte_collisional_ne(self.handle, int(n_iter), _stream_ptr(None)),
+               "rcx_nlte_collisional_ne")
 
     def electron_density(self):
         """The solver's current electron density [ncell], FP64 on the GPU."""

@@ -60,6 +60,16 @@ def test_plan_create_rejects_bad_flags(flags, n_incl, code):
     assert e.value.code == getattr(rcx, code)
 
 
+def test_nlte_conservation_calls_reject_null():
+    """The charge/pressure conservation and collisional n_e calls reject a
+    null solver before touching the device."""
+    L = rcx._load_nlte()
+    assert L.rcx_nlte_set_charge_conservation(None, 1) == rcx.RCX_E_INVALID
+    assert L.rcx_nlte_set_pressure_conservation(None, 1) == rcx.RCX_E_INVALID
+    assert L.rcx_nlte_collisional_ne(None, 5, None) == rcx.RCX_E_INVALID
+    assert L.rcx_nlte_get_ne(None, None, None) == rcx.RCX_E_INVALID
+
+
 def test_host_radau_rule_matches_oracle_and_is_exact(tmp_path):
     """The library's inclination rule (host C++, Newton on Legendre
     polynomials) against the oracle's (numpy's Legendre roots), and its

@@ -275,3 +275,45 @@ def test_charge_conservation_matches_oracle(case32):
     assert it == 5
     assert relp.max() < 1e-3 and rele.max() < 1e-3
     assert rc2 == 0 and abs(it2 - K) <= 1
+
+
+def test_pressure_conservation_matches_oracle(case32):
+    """Pressure conservation with charge conservation (Sec. 3.3): n_Htot
+    rescaled after each charge step to hold the starting pressure; after 5
+    iterations the populations (and so n_Htot, their sum) and n_e agree with
+    the oracle's to 1e-3."""
+    _torch()
+    inp, P = case32
+    po, _ = P.iterate(P.lte.copy(), 5, charge=True, pressure=True)
+    ne_o = P.last_ne.copy()
+    s = _solver(inp)
+    s.set_charge_conservation(True)
+    s.set_pressure_conservation(True)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, 5, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    ne_g = s.electron_density().cpu().numpy()
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    rele = np.abs(ne_g - ne_o) / ne_o
+    print(f"pressure: pops max rel {relp.max():.3e}, n_e max rel {rele.max():.3e}, "
+          f"n_Htot moved {np.abs(po.sum(axis=0) / P.ntot - 1).max():.3e}")
+    assert relp.max() < 1e-3 and rele.max() < 1e-3
+    np.testing.assert_allclose(pg.sum(axis=0) + ne_g, P.ntot + P.ne, rtol=1e-12)
+
+
+def test_collisional_starting_n_e_matches_oracle(case32):
+    """The starting n_e from the collisional rates alone (Sec. 3.3): 20
+    equilibrium + charge steps with the radiative rates off, FP64 on both
+    sides: n_e and the LTE populations at it agree to 1e-10."""
+    _torch()
+    inp, P = case32
+    Q = P.collisional_ne(20)
+    s = _solver(inp)
+    s.collisional_ne(20)
+    ne_g = s.electron_density().cpu().numpy()
+    lte_g = s.lte().cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    print(f"collisional n_e: max rel {np.abs(ne_g / Q.ne - 1).max():.3e}, moved {np.abs(Q.ne / P.ne - 1).max():.3e}")
+    np.testing.assert_allclose(ne_g, Q.ne, rtol=1e-10)
+    np.testing.assert_allclose(lte_g, Q.lte, rtol=1e-10)
