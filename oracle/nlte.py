@@ -47,6 +47,11 @@ Readings (listed in the design notes):
     old n_Htot; the change metric includes |dn_Htot| / n_Htot.
   - Starting n_e from the collisional rates alone: equilibrium and charge
     steps with the radiative rates set to zero, from the given n_e.
+  - Sparsity (Sec. 3.5): with a temperature cut, cells at or above it are
+    not flagged: transparent with no emission in the formal solution, and
+    their populations (and n_e) are held; the change metric covers the
+    flagged cells. The formal solution here is the dense one of the medium
+    with those cells emptied, which at flagged cells equals the sparse one.
 """
 from __future__ import annotations
 
@@ -187,7 +192,7 @@ def ng_extrapolate(xs, M: int):
 class Problem:
     """Static (population-independent) data of one non-LTE problem."""
 
-    def __init__(self, inp, n_casc: int | None = None):
+    def __init__(self, inp, n_casc: int | None = None, t_cut: float | None = None):
         from paper_2408_14425_amd.workloads import n_cascades_for
         self.inp = inp
         self.atom = Atom(inp.atom)
@@ -196,6 +201,8 @@ class Problem:
         self.T = inp.T.reshape(-1).astype(np.float64)
         self.ne = inp.ne.reshape(-1).astype(np.float64)
         self.ntot = inp.ntot.reshape(-1).astype(np.float64)
+        # sparsity: flagged cells (None = all)
+        self.active = None if t_cut is None else self.T < t_cut
         self.vx = inp.vel[0].reshape(-1).astype(np.float64)
         self.vz = inp.vel[1].reshape(-1).astype(np.float64)
         self.nu = C_LIGHT / (inp.lambda_nm.astype(np.float64) * 1e-9)
@@ -266,6 +273,10 @@ class Problem:
             gr = self.atom.g[tr.i] / self.atom.g[tr.j]
             kappa[li] = norm * (pops[tr.i] - gr * pops[tr.j])
             eps[li] = norm * gr * pops[tr.j] * 2.0 * H_PLANCK * tr.nu0 ** 3 / C_LIGHT ** 2
+        if self.active is not None:
+            off = ~self.active
+            for a in (chi_c, eta_c, kappa, eps):
+                a[:, off] = 0.0
         return chi_c, eta_c, kappa, eps
 
     def _cfields(self, chi_c, eta_c, kappa, eps):
@@ -309,7 +320,9 @@ class Problem:
             t = self.trans_of[lam]
             tr = self.atom.trans[t]
             chi = chi_loc[lam]                                   # [cells][k]
-            psi = -np.expm1(-chi * self.ell[None, :]) / chi      # Psi* = (1 - e^{-chi l}) / chi
+            # Psi* = (1 - e^{-chi l}) / chi, and its limit l where chi = 0
+            with np.errstate(invalid="ignore", divide="ignore"):
+                psi = np.where(chi > 0, -np.expm1(-chi * self.ell[None, :]) / chi, self.ell[None, :])
             if tr.kind == "line":
                 _, Vij, Vji, Uji = self.line_coeffs(lam, H_loc[lam])
             else:
@@ -383,6 +396,8 @@ class Problem:
         new = pops + d[:, :nlv].T
         ne_new = ne + d[:, nlv]
         ok = np.all(new > 0, axis=0) & (ne_new > 0)
+        if self.active is not None:
+            ok &= self.active
         new = np.where(ok[None, :], new, pops)
         ne_new = np.where(ok, ne_new, ne)
         return new, ne_new
@@ -398,6 +413,8 @@ class Problem:
         A[np.arange(self.ncell), r, :] = 1.0
         b[np.arange(self.ncell), r] = self.ntot
         new = np.linalg.solve(A, b[..., None])[..., 0].T
+        if self.active is not None:
+            new[:, ~self.active] = pops[:, ~self.active]
         change = float(np.max(np.abs(new - pops) / np.abs(new)))
         return new, change
 

@@ -265,7 +265,8 @@ def nlte_wavelength_grid(atom: dict, n_line: int = 64, n_cont: int = 32, vmax: f
 
 
 def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 32,
-                    n0: float = 5e16, voxel: float = 1e3, nz: int | None = None) -> NlteInput:
+                    n0: float = 5e16, voxel: float = 1e3, nz: int | None = None,
+                    corona_frac: float = 0.0) -> NlteInput:
     """Synthetic prominence-like atmosphere: a hot (1e5 K), tenuous
     background with cool blobs, log10 T = 5 - sum_b (5 - log10 T_b)
     exp(-r^2 / 2 sigma_b^2) clipped to [log10 5e3, 5], 24 blobs per 1024^2
@@ -276,7 +277,10 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
     x(T) = 1e-4 + (1 - 1e-4) / (1 + (6540 K / T)^16) (shaped like a hydrogen
     ionisation curve at these densities: about 1% at 5000 K, 75% at 7000 K),
     ne = x ntot; velocities
-    uniform in +-20 km/s on a 32 x 32 coarse grid, bilinearly upsampled."""
+    uniform in +-20 km/s on a 32 x 32 coarse grid, bilinearly upsampled.
+    corona_frac > 0: that fraction of the cells, the hottest (the background
+    farthest from the blobs), becomes 1e6 K corona (density and ionisation
+    follow T as above), so a 250 kK cut flags the rest."""
     nz = n if nz is None else nz
     rng = np.random.default_rng(seed)
     zc, xc = np.meshgrid(np.arange(nz) + 0.5, np.arange(n) + 0.5, indexing="ij")
@@ -288,6 +292,8 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
         tb = 10 ** rng.uniform(np.log10(5e3), np.log10(3e4))
         logt -= (5.0 - np.log10(tb)) * np.exp(-((xc - cx) ** 2 + (zc - cz) ** 2) / (2 * sig * sig))
     T = 10 ** np.clip(logt, np.log10(5e3), 5.0)
+    if corona_frac > 0.0:
+        T = np.where(T > np.quantile(T, 1.0 - corona_frac), 1e6, T)
     ntot = n0 * (1e4 / T)
     xion = 1e-4 + (1.0 - 1e-4) / (1.0 + (6540.0 / T) ** 16)
     ne = xion * ntot
@@ -300,7 +306,7 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
         vel[d] = np.array([np.interp(gz, np.arange(32), rows[:, i]) for i in range(n)]).T
     lam, trans, dnu = nlte_wavelength_grid(SYNTH_ATOM, n_line, n_cont)
     return NlteInput(T, ne, ntot, vel.astype(np.float32), lam, trans, dnu, voxel, SYNTH_ATOM,
-                     f"nlte{n}x{nz}_w{len(lam)}_s{seed}")
+                     f"nlte{n}x{nz}_w{len(lam)}_s{seed}" + (f"_corona{corona_frac:g}" if corona_frac > 0 else ""))
 
 
 def mlp_init_params(n_in: int = 6, width: int = 128, depth: int = 4, n_out: int = 4, seed: int = 0):

@@ -323,3 +323,33 @@ def test_pressure_conservation_holds_the_starting_pressure():
         pops = pops * (nt / Q.ntot)[None, :]
         Q = P.with_ne(ne, nt)
     np.testing.assert_allclose(Q.ne, ne_true, rtol=1e-9)
+
+
+# ------------------------------------------------------------ sparsity
+
+
+def test_sparse_nlte_cut_above_every_cell_is_dense():
+    """Sec. 3.5: a temperature cut above every cell flags everything."""
+    inp = W.nlte_atmosphere(16, seed=3, n_line=8, n_cont=4)
+    P, Ps = nlte.Problem(inp), nlte.Problem(inp, t_cut=2.5e5)
+    a, _ = P.iterate(P.lte.copy(), 3)
+    b, _ = Ps.iterate(Ps.lte.copy(), 3)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_sparse_nlte_ignores_coronal_cells():
+    """Sec. 3.5: with a 250 kK cut the coronal cells are transparent, empty
+    and held: the flagged cells' populations after a few iterations do not
+    depend on the corona's temperature or density, and the coronal
+    populations stay at their starting values."""
+    import dataclasses
+    inp = W.nlte_atmosphere(48, seed=3, n_line=8, n_cont=4, corona_frac=0.6)
+    hot = inp.T >= 2.5e5
+    assert 0.5 < hot.mean() < 0.7
+    inp2 = dataclasses.replace(inp, T=np.where(hot, 3e6, inp.T), ntot=np.where(hot, 7.0 * inp.ntot, inp.ntot))
+    P, P2 = nlte.Problem(inp, t_cut=2.5e5), nlte.Problem(inp2, t_cut=2.5e5)
+    a, ch = P.iterate(P.lte.copy(), 4)
+    b, _ = P2.iterate(P2.lte.copy(), 4)
+    act = ~hot.reshape(-1)
+    np.testing.assert_allclose(a[:, act], b[:, act], rtol=1e-12)
+    np.testing.assert_array_equal(a[:, ~act], P.lte[:, ~act])
