@@ -349,6 +349,18 @@ int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int
  * atmosphere again restores the given n_e. */
 int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable);
 
+/* Sparse non-LTE solve (Sec. 3.5): cells with T < t_cut (the paper's
+ * temperature flag, typically 250 kK) are flagged, and the solver's plan is
+ * given them as by rcx_plan_set_active_host (their bilinear parents flagged
+ * up to the top cascade; only flagged probes' rays are marched). Unflagged
+ * cells are transparent with no emission, their rates (and J) are 0 and
+ * their populations and n_e are held by the equilibrium and conservation
+ * steps; the change covers the flagged cells. t_cut <= 0 clears the flags.
+ * Uses the atmosphere as set (call again after setting a new one); copies T
+ * to the host (synchronous). level_active_host (nullable) receives the
+ * flagged probes per cascade. */
+int32_t rcx_nlte_set_temperature_cut(rcx_nlte* s, double t_cut, int64_t* level_active_host);
+
 /* Pressure conservation (Sec. 3.3; needs charge conservation, else
  * RCX_E_INVALID): after each charge step the hydrogen density becomes
  * n_Htot = P/(kT) - n_e, holding the gas pressure (A_tot n_Htot + n_e) k T

@@ -464,6 +464,18 @@ __global__ void k_synth_cont(AtomDev A, int64_t ncell, const double* __restrict_
     }
 }
 
+// Sparse: zero the opacity scale and source function of the line records
+// ([n_lines][ncell] float4 {kappa, S, ...}) at unflagged cells.
+__global__ void k_mask_line_rec(float4* __restrict__ rec, const uint8_t* __restrict__ mask, int64_t ncell,
+                                int32_t n_lines)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)n_lines * ncell && !mask[i % ncell]) {
+        rec[i].x = 0.0f;
+        rec[i].y = 0.0f;
+    }
+}
+
 // Max over cells of a line's source function (every wavelength of a line
 // batch shares S_line), into all 16 entries of the batch's smax.
 __global__ void k_smax_line(int64_t ncell, const float4* __restrict__ rec, unsigned int* __restrict__ smax_b)
@@ -690,11 +702,13 @@ __global__ __launch_bounds__(256) void k_stat_eq(AtomDev A, int64_t ncell, const
                                                   const double* __restrict__ cup, const double* __restrict__ cdn,
                                                   double* __restrict__ ntot, double* __restrict__ pops,
                                                   unsigned long long* __restrict__ max_change,
-                                                  double* __restrict__ ne, const double* __restrict__ p_kt)
+                                                  double* __restrict__ ne, const double* __restrict__ p_kt,
+                                                  const uint8_t* __restrict__ active)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double change = 0.0;
-    if (c < ncell) {
+    // sparse: unflagged cells are held (Sec. 3.5)
+    if (c < ncell && (!active || active[c])) {
         double n[NL], G[NL][NL + 1];
         for (int l = 0; l < NL; ++l) {
             n[l] = pops[(int64_t)l * ncell + c];
@@ -1059,7 +1073,7 @@ hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t 
 {
     hipLaunchKernelGGL(k_stat_eq<NL>, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->atom, s->ncell, rates,
                        s->cup, s->cdn, s->ntot, pops, s->d_max, s->charge ? s->ne_copy : nullptr,
-                       s->charge && s->pressure ? s->p_kt : nullptr);
+                       s->charge && s->pressure ? s->p_kt : nullptr, s->plan->mask_dev);
     return hipGetLastError();
 }
 
@@ -1274,6 +1288,18 @@ int32_t rcx_nlte_set_charge_conservation(rcx_nlte* s, int32_t enable)
     return RCX_OK;
 }
 
+int32_t rcx_nlte_set_temperature_cut(rcx_nlte* s, double t_cut, int64_t* level_active_host)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_temperature_cut: null solver");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_temperature_cut: set the atmosphere first");
+    if (!(t_cut > 0.0)) return rcx_plan_set_active_host(s->plan, nullptr, level_active_host);
+    std::vector<double> T((size_t)s->ncell);
+    RCX_HIP_TRY(hipMemcpy(T.data(), s->T, sizeof(double) * s->ncell, hipMemcpyDeviceToHost));
+    std::vector<uint8_t> flag((size_t)s->ncell);
+    for (size_t c = 0; c < flag.size(); ++c) flag[c] = T[c] < t_cut ? 1 : 0;
+    return rcx_plan_set_active_host(s->plan, flag.data(), level_active_host);
+}
+
 int32_t rcx_nlte_set_pressure_conservation(rcx_nlte* s, int32_t enable)
 {
     if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_pressure_conservation: null solver");
@@ -1406,6 +1432,12 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
                  s->small_a ? 1.0f : (float)(1.0 / s->da_c), s->small_a ? (1 << 24) : s->n_ac};
     hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
     RCX_HIP_TRY(hipGetLastError());
+    if (P->mask_dev && A.n_lines > 0) {
+        // sparse (Sec. 3.5): unflagged cells transparent, no emission
+        hipLaunchKernelGGL(k_mask_line_rec, dim3(blocks_for((int64_t)A.n_lines * nc, 256)), dim3(256), 0, st,
+                           s->line_rec, P->mask_dev, nc, A.n_lines);
+        RCX_HIP_TRY(hipGetLastError());
+    }
     const int32_t nb = (int32_t)s->batches.size();
     if (s->f16) {
         hipLaunchKernelGGL(k_zero_u32n, dim3(blocks_for((int64_t)nb * kLB, 256)), dim3(256), 0, st, s->smax, nb * kLB);
@@ -1425,6 +1457,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             hipLaunchKernelGGL(k_synth_cont, dim3(blocks_for(nc * kLB, 256)), dim3(256), 0, st, A, nc, pops, s->T, cb,
                                s->lratio, s->voxel, Fb, smax_b);
             RCX_HIP_TRY(hipGetLastError());
+            if (P->mask_dev) RCX_HIP_TRY(launch_mask_fields(Fb, P->mask_dev, nc, 1, st));
         } else if (smax_b) {
             hipLaunchKernelGGL(k_smax_line, dim3(std::min<unsigned>(blocks_for(nc, 256), 1024u)), dim3(256), 0, st, nc,
                                s->line_rec + (size_t)tr.line * nc, smax_b);
@@ -1500,6 +1533,12 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
     hipLaunchKernelGGL(k_rates_sum, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, A.nt, s->d_tb, s->d_tb + A.nt,
                        s->part, rates);
     RCX_HIP_TRY(hipGetLastError());
+    if (P->mask_dev) {
+        // sparse: no rays reach the unflagged cells' partial sums; their
+        // rates and J are 0
+        RCX_HIP_TRY(launch_mask_j(rates, P->mask_dev, nc, 2 * A.nt, st));
+        if (J) RCX_HIP_TRY(launch_mask_j(J, P->mask_dev, nc, s->n_wave, st));
+    }
     return RCX_OK;
 }
 

@@ -309,6 +309,7 @@ def _load_nlte():
     L.rcx_nlte_get_ne.argtypes = [vp, vp, vp]
     L.rcx_nlte_set_pressure_conservation.argtypes = [vp, i32]
     L.rcx_nlte_collisional_ne.argtypes = [vp, i32, vp]
+    L.rcx_nlte_set_temperature_cut.argtypes = [vp, C.c_double, C.POINTER(C.c_int64)]
     L.rcx_nlte_lte_populations.argtypes = [vp, vp, vp]
     L.rcx_nlte_formal_solve_rates.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_stat_eq.argtypes = [vp, vp, vp, C.POINTER(C.c_double), vp]
@@ -322,7 +323,7 @@ def _load_nlte():
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
     for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start",
               "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_set_pressure_conservation",
-              "rcx_nlte_collisional_ne"):
+              "rcx_nlte_collisional_ne", "rcx_nlte_set_temperature_cut"):
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
               "rcx_nlte_formal_solve_rates", "rcx_nlte_stat_eq", "rcx_nlte_iterate", "rcx_nlte_voigt_eval",
@@ -470,6 +471,15 @@ class Nlte:
         charge step (needs charge conservation)."""
         _check(_load_nlte().rcx_nlte_set_pressure_conservation(self.handle, int(bool(enable))),
                "rcx_nlte_set_pressure_conservation")
+
+    def set_temperature_cut(self, t_cut: float):
+        """Sparse solve: flag the cells with T < t_cut (0 clears); returns
+        the flagged probes per cascade."""
+        n = 16
+        counts = (C.c_int64 * n)()
+        _check(_load_nlte().rcx_nlte_set_temperature_cut(self.handle, float(t_cut), counts),
+               "rcx_nlte_set_temperature_cut")
+        return [c for c in counts if c > 0]
 
     def collisional_ne(self, n_iter: int = 20):
         """Starting n_e from the collisional rates alone."""
