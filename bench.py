@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--nlte-variants", default="plain_fp32,learned_fp16,ng_fp32,learned_ng_fp16",
                     help="comma-separated subset of the non-LTE runs")
     ap.add_argument("--nlte-n", type=int, default=1024)
+    ap.add_argument("--nlte-corona", type=float, default=0.0,
+                    help="fraction of the non-LTE atmosphere turned into 1e6 K corona (for sparse_fp32)")
     ap.add_argument("--nlte-max-iter", type=int, default=300)
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "warmstart_mlp.npz"),
                     help="trained warm-start network (skipped when absent)")
@@ -162,16 +164,18 @@ def nlte_solves(args):
     import torch
 
     from paper_2408_14425_amd import rcx, warmstart, workloads
-    inp = workloads.nlte_atmosphere(args.nlte_n, seed=3, n_line=64, n_cont=32)
+    inp = workloads.nlte_atmosphere(args.nlte_n, seed=3, n_line=64, n_cont=32, corona_frac=args.nlte_corona)
+    corona = f", {args.nlte_corona:.0%} of the cells 1e6 K corona" if args.nlte_corona > 0 else ""
     out = {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz} grid, {inp.n_wave} wavelengths "
-                       f"(2 lines x 64 + 32 continuum), synthetic 3-level + continuum atom, seed 3, "
+                       f"(2 lines x 64 + 32 continuum), synthetic 3-level + continuum atom, seed 3{corona}, "
                        f"stop at max relative change < 1e-3",
            "tol": 1e-3}
     net = None
     if os.path.exists(args.weights):
         net, fn, tn = warmstart.load(args.weights)
     runs = [("plain_fp32", rcx.RCX_STORE_F32, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False),
-            ("ng_fp32", rcx.RCX_STORE_F32, False), ("charge_fp32", rcx.RCX_STORE_F32, False)]
+            ("ng_fp32", rcx.RCX_STORE_F32, False), ("charge_fp32", rcx.RCX_STORE_F32, False),
+            ("sparse_fp32", rcx.RCX_STORE_F32, False)]
     if net is not None:
         runs += [("learned_fp32", rcx.RCX_STORE_F32, True), ("learned_fp16", rcx.RCX_STORE_F16_SCALED, True),
                  ("learned_ng_fp16", rcx.RCX_STORE_F16_SCALED, True)]
@@ -188,6 +192,9 @@ def nlte_solves(args):
             # Ng acceleration (not in the paper): order 2, first after 4
             # iterations, then every 4
             s.set_acceleration(2, 4, 4)
+        if "sparse" in name:
+            # sparsity: cells below 250 kK flagged, the corona left out
+            out.setdefault("flagged_probes_per_cascade", s.set_temperature_cut(2.5e5))
         if "charge" in name:
             # charge conservation: a Newton-Raphson step on the populations
             # and n_e after each equilibrium step
