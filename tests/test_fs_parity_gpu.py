@@ -332,8 +332,13 @@ def test_sparse_matches_oracle(case):
         act = W.active_cells(64, 64, seed=5, frac=0.3)
     Jg, counts, _, _ = _gpu_sparse(inp, act, storage=st, bilinear_fix=fix, n_incl=ni)
     if ni == 1:
-        Jo = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act, voxel=inp.voxel_scale,
-                                        bilinear_fix=fix)["J"]
+        ref = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act, voxel=inp.voxel_scale,
+                                         bilinear_fix=fix)
+        Jo = ref["J"]
+        # the library's flagged probes per cascade give the oracle's ray count
+        top = inp.n_cascades - 1
+        rays = sum(c * (4 << (2 * i)) * (4 if fix and i < top else 1) for i, c in enumerate(counts))
+        assert rays * inp.n_wave == ref["rays"], (counts, ref["rays"])
     else:
         mu, wt = oracle.radau_inclinations(ni)
         Jo = sum(wt[m] * oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act,
@@ -406,3 +411,24 @@ def test_bilinear_fix_interval_rule_and_directions(t_rule, c0_dirs):
     plan.close()
     Jo = oracle.formal_solve(chi, eta, ncas, t_rule=t_rule, c0_dirs=c0_dirs, bilinear_fix=True)["J"]
     print(f"fix t_rule={t_rule} c0_dirs={c0_dirs}: max rel {_assert_rel(Jg, Jo):.3e}")
+
+
+def test_sparse_nothing_flagged_gives_zero_then_dense_again():
+    """No flagged cell: J is 0 everywhere and nothing is marched; clearing
+    the flags restores the dense result."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.blobs_medium(32, seed=8)
+    print("[gpu] sparse formal solve, nothing flagged", flush=True)
+    plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
+    chi = torch.from_numpy(inp.chi).cuda()
+    eta = torch.from_numpy(inp.eta).cuda()
+    dense = plan.formal_solve(chi, eta).cpu().numpy()
+    counts = plan.set_active(np.zeros((32, 32), bool))
+    J0 = plan.formal_solve(chi, eta).cpu().numpy()
+    plan.set_active(None)
+    J1 = plan.formal_solve(chi, eta).cpu().numpy()
+    plan.close()
+    assert all(c == 0 for c in counts)
+    assert np.all(J0 == 0.0)
+    assert np.array_equal(J1, dense)
