@@ -422,7 +422,7 @@ int32_t rcx_nlte_destroy(rcx_nlte* s);
  * Linear -> y [B][n_out], trained by Adam on an MSE loss with BF16 MFMA
  * products (FP32 accumulation) and FP32 master weights. It predicts
  * warm-start level populations for the non-LTE iteration; the plain
- * iteration from its prediction remains the judge of convergence.
+ * iteration from its prediction still decides convergence.
  * Parameters are one flat FP32 array, layer by layer: W [fan_in][fan_out]
  * row-major, then b [fan_out]. Initial values come from the caller. */
 typedef struct rcx_mlp rcx_mlp;
@@ -467,7 +467,7 @@ int32_t rcx_nlte_log_departures(rcx_nlte* s, const double* pops, const float* no
  * network inference, and populations n_l = ntot b_l n_l^LTE / sum_m b_m n_m^LTE
  * with log10 b the de-standardised prediction (targ_norm_host[2][n_levels]);
  * pops_out [n_levels][nz][nx] device FP64. The plain iteration started
- * from it remains the judge of convergence. Synchronises. */
+ * from it still decides convergence. Synchronises. */
 int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_host, const float* targ_norm_host,
                             double* pops_out, hipStream_t stream);
 
