@@ -191,6 +191,12 @@ typedef struct rcx_batch rcx_batch;
  * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
 int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
                          rcx_batch** out);
+/* Sparse atmosphere atm of the batch (Sec. 3.5): its plan flags the cells
+ * as rcx_plan_set_active_host does (NULL = dense again); the batched solve
+ * then marches only its flagged probes' rays, empties its unflagged cells
+ * and writes J = 0 there. Rebuilds the task list (and the graph) on the next
+ * solve. RCX_E_INVALID for a null batch or atm outside [0, n_atm). */
+int32_t rcx_batch_set_active_host(rcx_batch* s, int32_t atm, const uint8_t* active_host);
 /* Launch order of the cascades with >= 256 directions: groups of
  * tile_probes x tile_probes probes x 32 directions (default 4), or 0 for
  * probe-major order. Results do not depend on it. */

@@ -89,23 +89,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ t
         const Task T = tasks[lo];  // by value: kept in registers for the march
         const int64_t rr = wbase - T.ray0 + c.row;  // < T.n_rays
         const LevelDesc L = T.L;
+        // probe and direction in the task's launch order (dense, tiled, or
+        // the flagged-probe list of a sparse atmosphere)
         int32_t k, u, v;
-        if (L.tile_p <= 0) {
-            k = (int32_t)(rr % L.nd);
-            const int32_t p = (int32_t)(rr / L.nd);
-            u = p % L.px;
-            v = p / L.px;
-        } else {
-            const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
-            const int64_t g = rr / per, r_in = rr % per;
-            const int32_t nw = L.nd / L.tile_d;
-            const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
-            const int32_t pl = (int32_t)(r_in / L.tile_d);
-            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
-            u = (t % ntx) * L.tile_p + pl % L.tile_p;
-            v = (t / ntx) * L.tile_p + pl / L.tile_p;
-        }
-        const bool active = u < L.px && v < L.pz;
+        bool active;
+        march::ray_coords(L, rr, T.n_rays, k, u, v, active);
         const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;
         march::FieldOp op{};
         op.Fb = T.Fb;
@@ -326,6 +314,8 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
         hipError_t e = launch_prep(chi[a], eta[a], s->F[a], s->n_wave[a], ncell, (float)P->grid.voxel_scale,
                                    s->f16 ? s->smax[a] : nullptr, st);
         if (e == hipSuccess && s->f16) e = launch_scales(s->n_batch[a] * kLB, s->smax[a], s->scale[a], s->inv_scale[a], st);
+        // sparse atmosphere: unflagged cells transparent and empty
+        if (e == hipSuccess && P->mask_dev) e = launch_mask_fields(s->F[a], P->mask_dev, ncell, s->n_batch[a], st);
         if (e != hipSuccess) return e;
     }
     for (size_t g = 0; g + 1 < s->gen_task.size(); ++g) {
@@ -338,6 +328,13 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
             hipLaunchKernelGGL(k_batch_gen<false>, grid, dim3(kBlock), 0, st, s->tasks_d, t0, nt, total);
         hipError_t r = hipGetLastError();
         if (r != hipSuccess) return r;
+    }
+    // sparse atmospheres: J = 0 at unflagged cells
+    for (int32_t a = 0; a < s->n_atm; ++a) {
+        const rcx_plan* P = s->plans[a];
+        if (!P->mask_dev) continue;
+        hipError_t e = launch_mask_j(s->J_bound[a], P->mask_dev, (int64_t)P->grid.nx * P->grid.nz, s->n_wave[a], st);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -434,6 +431,15 @@ int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes)
     return RCX_OK;
 }
 
+int32_t rcx_batch_set_active_host(rcx_batch* s, int32_t atm, const uint8_t* active_host)
+{
+    if (!s || atm < 0 || atm >= s->n_atm) return bfail(RCX_E_INVALID, "rcx_batch_set_active_host: bad argument");
+    const int32_t rc = rcx_plan_set_active_host(s->plans[atm], active_host, nullptr);
+    s->J_bound.clear();  // ray counts changed: rebuild the task list on the next solve
+    drop_graph(s);
+    return rc;
+}
+
 int32_t rcx_batch_set_graph(rcx_batch* s, int32_t enable)
 {
     if (!s) return bfail(RCX_E_INVALID, "rcx_batch_set_graph: null batch");
@@ -507,6 +513,8 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
     // cache key: the batch's shapes
     std::ostringstream key;
     key << (s->f16 ? "f16" : "f32");
+    for (int32_t a = 0; a < s->n_atm; ++a)
+        if (s->plans[a]->mask_dev) key << "_sparse" << a << "_" << s->plans[a]->levels[0].n_active;
     for (int32_t a = 0; a < s->n_atm; ++a)
         key << "_" << s->plans[a]->grid.nx << "x" << s->plans[a]->grid.nz << "w" << s->n_wave[a];
     const std::string k = key.str();

@@ -652,11 +652,13 @@ def _load_batch():
     L.rcx_batch_create.argtypes = [i32, C.POINTER(rcx_grid), C.POINTER(i32), C.POINTER(rcx_params), C.POINTER(vp)]
     L.rcx_batch_set_order.argtypes = [vp, i32]
     L.rcx_batch_set_graph.argtypes = [vp, i32]
+    L.rcx_batch_set_active_host.argtypes = [vp, i32, vp]
     L.rcx_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.rcx_batch_work.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     L.rcx_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_char_p, C.POINTER(i32), vp]
     L.rcx_batch_destroy.argtypes = [vp]
-    for n in ("rcx_batch_create", "rcx_batch_set_order", "rcx_batch_set_graph", "rcx_batch_solve",
+    for n in ("rcx_batch_create", "rcx_batch_set_order", "rcx_batch_set_graph", "rcx_batch_set_active_host",
+              "rcx_batch_solve",
               "rcx_batch_work", "rcx_batch_autotune", "rcx_batch_destroy"):
         getattr(L, n).restype = i32
     L._batch_bound = True
@@ -695,6 +697,20 @@ class Batch:
 
     def set_graph(self, enable: bool):
         _check(_load_batch().rcx_batch_set_graph(self.handle, int(bool(enable))), "rcx_batch_set_graph")
+
+    def set_active(self, atm: int, active):
+        """Sparse atmosphere: flag its cells ([nz][nx], non-zero = active)
+        or None for dense."""
+        import numpy as np
+        L = _load_batch()
+        if active is None:
+            _check(L.rcx_batch_set_active_host(self.handle, int(atm), None), "rcx_batch_set_active_host")
+            return
+        nx, nz = self.shapes[atm]
+        a = np.ascontiguousarray(np.asarray(active) != 0, dtype=np.uint8)
+        if a.shape != (nz, nx):
+            raise ValueError(f"active must have shape ({nz}, {nx})")
+        _check(L.rcx_batch_set_active_host(self.handle, int(atm), a.ctypes.data), "rcx_batch_set_active_host")
 
     def work(self):
         r, c = C.c_int64(), C.c_int64()

@@ -162,3 +162,41 @@ def test_line_medium_batch_sampled_against_oracle():
             Jo = oracle.formal_solve(inp.chi[lam:lam + 1], inp.eta[lam:lam + 1], inp.n_cascades, need=need)["J"][0]
             for x, z in cells:
                 assert abs(float(Jg[lam, z, x]) - Jo[z, x]) <= RTOL * Jo[z, x], (inp.name, lam, x, z)
+
+
+def test_sparse_atmospheres_in_a_batch():
+    """Sparse atmospheres inside a batch (Sec. 3.5): two of four atmospheres
+    flagged (one with nothing flagged), solved under the graph twice (the
+    second a replay); flagged cells against the oracle's sparse solve to
+    1e-4, J = 0 at unflagged cells, the dense atmospheres as before; then
+    flags cleared, the batch is dense again."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    cases = [(64, 64, 3, 1), (37, 53, 20, 2), (128, 96, 17, 3), (40, 40, 2, 6)]
+    print("[gpu] batch sparse", cases, flush=True)
+    host, chi, eta = _inputs(cases)
+    act = {0: W.active_cells(64, 64, seed=3, frac=0.3), 2: W.active_cells(128, 96, seed=4, frac=0.25),
+           3: np.zeros((40, 40), bool)}
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in cases], [nw for _, _, nw, _ in cases])
+    dense = [j.cpu().numpy() for j in B.solve(chi, eta)]
+    for a, m in act.items():
+        B.set_active(a, m)
+    for rep in range(2):
+        J = [j.cpu().numpy().astype(np.float64) for j in B.solve(chi, eta)]
+        for a, (nx, nz, nw, _) in enumerate(cases):
+            if a not in act:
+                assert np.array_equal(J[a], dense[a]), a
+                continue
+            m = act[a]
+            assert np.all(J[a][:, ~m] == 0.0), a
+            if m.any():
+                Jo = oracle.formal_solve_sparse(host[a][0], host[a][1], W.n_cascades_for(nx, nz), m)["J"]
+                r = _rel(J[a][:, m], Jo[:, m])
+                print(f"replay {rep} atm {a}: flagged {m.mean():.2f}, vs oracle {r:.2e}")
+                assert r <= RTOL
+    for a in act:
+        B.set_active(a, None)
+    again = [j.cpu().numpy() for j in B.solve(chi, eta)]
+    B.close()
+    for a in range(len(cases)):
+        assert np.array_equal(again[a], dense[a]), a
