@@ -191,6 +191,22 @@ typedef struct rcx_batch rcx_batch;
  * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
 int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
                          rcx_batch** out);
+/* Emergent intensity along parallel long characteristics (Sec. 3.9, the
+ * post-processing formal solver): a beam of n_rays rays of light direction
+ * (wx, wz) (any non-zero vector; normalised), one cell apart across the beam
+ * and centred on the domain (ray j at offset j + 1/2 - n_rays/2 cells along
+ * (-wz, wx) from the domain centre), each traced front to back from outside
+ * the domain on the observer's side through isotropic chi, eta
+ * [n_wave][nz][nx] (device, float32, as for rcx_formal_solve) with the same
+ * cell walk and piecewise-constant update as the cascade march; nothing
+ * enters from behind (free-space boundary). I [n_wave][n_rays] (device,
+ * float32, caller-owned). Uses the plan's own workspace (the field batches),
+ * so it must not overlap another call on the plan; a sparse plan's
+ * unflagged cells are empty. Errors: RCX_E_INVALID (null arrays, n_wave
+ * outside [1, max_wave], n_rays <= 0, zero or non-finite direction). */
+int32_t rcx_emergent(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta, double wx, double wz,
+                     int32_t n_rays, float* I, hipStream_t stream);
+
 /* Sparse atmosphere atm of the batch (Sec. 3.5): its plan flags the cells
  * as rcx_plan_set_active_host does (NULL = dense again); the batched solve
  * then marches only its flagged probes' rays, empties its unflagged cells

@@ -82,6 +82,9 @@ def lib():
         L.ora_lc_points.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, C.c_int32, dp, dp,
                                     C.c_int32, ip, ip, ip, dp, C.c_int32]
         L.ora_num_threads.restype = C.c_int32
+        L.ora_emergent.restype = C.c_int32
+        L.ora_emergent.argtypes = [C.c_int32, C.c_int32, C.c_double, C.c_int32, dp, dp, C.c_double, C.c_double,
+                                   C.c_int32, dp, C.c_int32]
         _lib = L
     return _lib
 
@@ -276,6 +279,21 @@ def lc_points(chi, eta, M: int, pts, voxel: float = 1.0, n_threads: int = 0):
                         px.ctypes.data_as(ip), pz.ctypes.data_as(ip), pl.ctypes.data_as(ip),
                         _dp(J), n_threads)
     return J
+
+
+def emergent(chi, eta, wx: float, wz: float, n_rays: int, voxel: float = 1.0, n_threads: int = 0):
+    """Emergent intensity [n_wave][n_rays] of a beam of parallel long
+    characteristics of light direction (wx, wz) (Sec. 3.9), ray j at offset
+    j + 1/2 - n_rays/2 cells across the beam from the domain centre."""
+    chi, eta = _f64(chi), _f64(eta)
+    if chi.ndim == 2:
+        chi, eta = chi[None], eta[None]
+    nw, nz, nx = chi.shape
+    I = np.zeros((nw, n_rays))
+    rc = lib().ora_emergent(nx, nz, voxel, nw, _dp(chi), _dp(eta), wx, wz, n_rays, _dp(I), n_threads)
+    if rc != 0:
+        raise RuntimeError("ora_emergent failed")
+    return I
 
 
 def num_threads() -> int:

@@ -586,6 +586,57 @@ int32_t ora_lc_solve(int32_t nx, int32_t nz, double voxel, int32_t M, int32_t n_
     return 0;
 }
 
+/* Emergent intensity along parallel long characteristics (Sec. 3.9): a beam
+ * of n_rays rays of light direction (wx, wz) (normalised here), one cell
+ * apart across the beam and centred on the domain, ray j at offset
+ * j + 1/2 - n_rays/2 cells along (-wz, wx); each is traced from outside the
+ * domain on the observer's side back along -w through the whole domain,
+ * nothing entering from behind. I: [n_wave][n_rays]. */
+int32_t ora_emergent(int32_t nx, int32_t nz, double voxel, int32_t n_wave, const double* chi, const double* eta,
+                     double wx, double wz, int32_t n_rays, double* I, int32_t n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    double wn = hypot(wx, wz);
+    if (!(wn > 0.0)) return -1;
+    wx /= wn;
+    wz /= wn;
+    ora_geom g;
+    memset(&g, 0, sizeof(g));
+    g.nx = nx;
+    g.nz = nz;
+    g.n_casc = 1;
+    g.c0_dirs = 4;
+    g.voxel = voxel;
+    ora_given_fields f = {chi, eta, nx, nz};
+    int32_t max_seg = nx + nz + 8;
+    double R = 0.5 * hypot((double)nx, (double)nz) + 2.0;
+#pragma omp parallel
+    {
+        int32_t* sx = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+        int32_t* sz = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+        double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)max_seg);
+        double *sdt = buf, *schi = buf + max_seg, *seta = buf + 2 * max_seg, *sds = buf + 3 * max_seg;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t q = 0; q < (int64_t)n_wave * n_rays; ++q) {
+            int32_t lam = (int32_t)(q / n_rays), j = (int32_t)(q % n_rays);
+            double s = j + 0.5 - 0.5 * n_rays;
+            double ox = 0.5 * nx + s * (-wz) + R * wx, oz = 0.5 * nz + s * wx + R * wz;
+            double In, tau;
+            march_ray(&g, given_opac, &f, lam, ox, oz, -wx, -wz, 0.0, INFINITY, sx, sz, sdt, schi, seta, sds,
+                      max_seg, &In, &tau);
+            I[q] = In;
+        }
+        free(sx);
+        free(sz);
+        free(buf);
+    }
+    return 0;
+}
+
 /* Long characteristics at selected cells only: J at (px[q], pz[q], lam[q]). */
 int32_t ora_lc_points(int32_t nx, int32_t nz, double voxel, int32_t M, int32_t n_wave,
                       const double* chi, const double* eta, int32_t n_pts, const int32_t* px,

@@ -70,6 +70,7 @@ def load() -> C.CDLL:
     L.rcx_plan_workspace_bytes.argtypes = [vp, i32, C.POINTER(sz)]
     L.rcx_plan_work.argtypes = [vp, C.POINTER(rcx_work)]
     L.rcx_plan_set_active_host.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+    L.rcx_emergent.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, i32, vp, vp]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.rcx_plan_destroy.argtypes = [vp]
     L.rcx_plan_set_timing.argtypes = [vp, i32]
@@ -80,7 +81,7 @@ def load() -> C.CDLL:
     L.rcx_last_error.argtypes = [C.c_char_p, sz]
     for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
                  "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error", "rcx_plan_set_timing",
-                 "rcx_plan_get_timing", "rcx_plan_set_active_host"):
+                 "rcx_plan_get_timing", "rcx_plan_set_active_host", "rcx_emergent"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -224,6 +225,18 @@ class Plan:
         n = w.n_cascades
         return Work(n, bool(w.top_skipped), w.rays_all, w.rays_nonempty, w.cell_steps,
                     list(w.level_rays[:n]), list(w.level_steps[:n]))
+
+    def emergent(self, chi, eta, wx: float, wz: float, n_rays: int, I=None, stream=None):
+        """Emergent intensity [n_wave][n_rays] of a beam of parallel long
+        characteristics of light direction (wx, wz)."""
+        import torch
+        n_wave = chi.shape[0]
+        if I is None:
+            I = torch.empty((n_wave, n_rays), dtype=torch.float32, device=chi.device)
+        _check(load().rcx_emergent(self.handle, int(n_wave), _dev_ptr(chi, "torch.float32", "chi"),
+                                   _dev_ptr(eta, "torch.float32", "eta"), float(wx), float(wz), int(n_rays),
+                                   _dev_ptr(I, "torch.float32", "I"), _stream_ptr(stream)), "rcx_emergent")
+        return I
 
     def set_active(self, active):
         """Sparse solve: flag the cells of interest ([nz][nx], non-zero =

@@ -5,6 +5,8 @@ march and merge is non-negative once 1 - e^{-x} is evaluated stably, so FP32
 error grows at most linearly in the number of steps: ~1e-5 for the longest
 rays here).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -432,3 +434,31 @@ def test_sparse_nothing_flagged_gives_zero_then_dense_again():
     assert all(c == 0 for c in counts)
     assert np.all(J0 == 0.0)
     assert np.array_equal(J1, dense)
+
+
+@pytest.mark.parametrize("case, wx, wz", [("blobs64", 0.8, 0.6), ("blobs64", -0.26, 0.97), ("blobs64", -0.6, -0.8),
+                                          ("ragged_w20", 0.5, -0.866), ("line96_w40", 0.9, 0.3)])
+def test_emergent_matches_oracle(case, wx, wz):
+    """Emergent intensity of a beam of parallel long characteristics (Sec.
+    3.9) against the oracle's, ray by ray; rays that miss the domain are 0
+    on both sides."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    if case == "blobs64":
+        inp = W.blobs_medium(64, seed=1)
+    elif case == "ragged_w20":
+        inp = _ragged_w20()
+    else:
+        inp = W.line_medium(96, 64, seed=5, wave_subset=np.arange(0, 40))
+    n = math.hypot(wx, wz)
+    n_rays = int(math.ceil(abs(inp.nx * wz / n) + abs(inp.nz * wx / n))) + 6
+    print(f"[gpu] emergent {inp.name} w=({wx}, {wz}) rays {n_rays}", flush=True)
+    plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave, voxel_scale=inp.voxel_scale)
+    I = plan.emergent(torch.from_numpy(inp.chi).cuda(), torch.from_numpy(inp.eta).cuda(), wx, wz, n_rays)
+    torch.cuda.synchronize()
+    Ig = I.cpu().numpy().astype(np.float64)
+    plan.close()
+    Io = oracle.emergent(inp.chi, inp.eta, wx, wz, n_rays, voxel=inp.voxel_scale)
+    hit = Io > 0
+    assert np.all(Ig[~hit] == 0.0) and hit.sum() > 0
+    print(f"emergent {case}: {hit[0].sum()} of {n_rays} rays hit, max rel {_assert_rel(Ig[hit], Io[hit]):.3e}")

@@ -619,3 +619,60 @@ def test_sparse_computes_fewer_rays():
     sparse = oracle.formal_solve_sparse(inp.chi, inp.eta, inp.n_cascades, act)
     share = sparse["rays"] / dense["rays"]
     assert 0.25 <= share < 0.8, share
+
+
+# ------------------------------------------------------------ emergent rays
+
+
+def _chords(nx, nz, wx, wz, n_rays):
+    """Length of each beam ray inside the box [0, nx] x [0, nz] (slab
+    clipping of the full line), for the ray layout of the emergent solver."""
+    n = math.hypot(wx, wz)
+    wx, wz = wx / n, wz / n
+    out = []
+    for j in range(n_rays):
+        s = j + 0.5 - 0.5 * n_rays
+        ox, oz = 0.5 * nx - s * wz, 0.5 * nz + s * wx
+        lo, hi = -np.inf, np.inf
+        for o, w, size in ((ox, wx, nx), (oz, wz, nz)):
+            if abs(w) < 1e-15:
+                if not (0.0 <= o <= size):
+                    lo, hi = 1.0, 0.0
+                continue
+            a, b = (0.0 - o) / w, (size - o) / w
+            lo, hi = max(lo, min(a, b)), min(hi, max(a, b))
+        out.append(max(hi - lo, 0.0))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("wx, wz", [(0.8, 0.6), (-0.3, 0.95), (-0.7, -0.7)])
+def test_emergent_homogeneous_box_closed_form(wx, wz):
+    """Sec. 3.9: through a homogeneous box the emergent intensity of each
+    ray is S (1 - e^{-chi L}) with L its chord through the box (and
+    eta L in the optically thin limit)."""
+    nx, nz, n_rays = 40, 28, 60
+    chi = np.full((2, nz, nx), 0.07)
+    chi[1] = 1e-9
+    eta = chi * 1.7
+    I = oracle.emergent(chi, eta, wx, wz, n_rays, voxel=1.0)
+    L = _chords(nx, nz, wx, wz, n_rays)
+    np.testing.assert_allclose(I[0], 1.7 * -np.expm1(-0.07 * L), rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(I[1], 1.7e-9 * L, rtol=1e-6, atol=1e-300)
+    assert (L > 0).sum() > 10 and (L == 0).sum() > 0
+
+
+def test_emergent_along_a_grid_row_is_the_direct_sum():
+    """Sec. 3.9: light travelling along +x, one ray per grid row (the beam
+    offsets run along z, ray j through z = j + 1/2): each emergent intensity
+    is the front-to-back sum over the row from its far end, written out
+    cell by cell."""
+    inp = W.blobs_medium(32, seed=2)
+    I = oracle.emergent(inp.chi, inp.eta, 1.0, 0.0, 32)
+    for j in (3, 16, 29):
+        chi, eta = inp.chi[0, j].astype(np.float64), inp.eta[0, j].astype(np.float64)
+        Iexp, T = 0.0, 1.0
+        for x in range(31, -1, -1):
+            t = math.exp(-chi[x])
+            Iexp += T * eta[x] / chi[x] * (1 - t)
+            T *= t
+        assert abs(I[0, j] / Iexp - 1) < 1e-12, (j, I[0, j], Iexp)
