@@ -93,6 +93,9 @@ def _bind():
         L.ora_nlte_formal_solve.restype = C.c_int32
         L.ora_nlte_local.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_void_p, C.c_void_p]
         L.ora_nlte_local.restype = None
+        L.ora_nlte_emergent.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_double, C.c_double, C.c_int32,
+                                        C.c_void_p]
+        L.ora_nlte_emergent.restype = C.c_int32
         L._nlte_bound = True
     return L
 
@@ -308,6 +311,20 @@ class Problem:
         L.ora_nlte_local(C.byref(self.geom), C.byref(f), chi_loc.ctypes.data, H_loc.ctypes.data)
         del keep
         return J, I0, chi_loc, H_loc, st
+
+    def emergent(self, pops, wx: float, wz: float, n_rays: int):
+        """Emergent intensity [n_wave][n_rays] at populations pops along the
+        beam of parallel long characteristics of light direction (wx, wz)
+        (Sec. 3.9; the ray layout of ``oracle.emergent``), line profiles
+        Doppler-shifted along the rays."""
+        f, keep = self._cfields(*self.fields(pops))
+        I = np.zeros((len(self.nu), n_rays))
+        L = _bind()
+        rc = L.ora_nlte_emergent(C.byref(self.geom), C.byref(f), wx, wz, n_rays, I.ctypes.data)
+        del keep
+        if rc != 0:
+            raise RuntimeError("ora_nlte_emergent failed")
+        return I
 
     def rates(self, pops, I0, chi_loc, H_loc):
         """Preconditioned radiative rate coefficients per transition and cell:

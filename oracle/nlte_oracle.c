@@ -126,6 +126,32 @@ int32_t ora_nlte_formal_solve(const ora_geom* g, const ora_nlte_fields* f, doubl
     return ora_rc_solve(g, f->n_wave, nlte_opac, f, NULL, J, I0, stats);
 }
 
+/* Emergent intensity through the non-LTE fields (Sec. 3.9): the beam of
+ * ora_emergent (light direction (wx, wz), normalised here, ray j at offset
+ * j + 1/2 - n_rays/2 cells along (-wz, wx) from the domain centre), each ray
+ * traced from outside the domain back along -w with the line profiles
+ * shifted for that march direction. I_out[n_wave][n_rays]. */
+int32_t ora_nlte_emergent(const ora_geom* g, const ora_nlte_fields* f, double wx, double wz, int32_t n_rays,
+                          double* I_out)
+{
+    if (!wei_ready) wei_init();
+    double wn = hypot(wx, wz);
+    if (!(wn > 0.0)) return -1;
+    wx /= wn;
+    wz /= wn;
+    double R = 0.5 * hypot((double)g->nx, (double)g->nz) + 2.0;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < (int64_t)f->n_wave * n_rays; ++q) {
+        int32_t lam = (int32_t)(q / n_rays), j = (int32_t)(q % n_rays);
+        double s = j + 0.5 - 0.5 * n_rays;
+        double ox = 0.5 * g->nx + s * (-wz) + R * wx, oz = 0.5 * g->nz + s * wx + R * wz;
+        double In, tau;
+        ora_ray(g, nlte_opac, f, lam, ox, oz, -wx, -wz, 0.0, INFINITY, &In, &tau);
+        I_out[q] = In;
+    }
+    return 0;
+}
+
 /* Directional opacity at the cell itself (for the cascade-0 operator):
  * out_chi[l][c][k] and the line profile H at the cell, out_H[l][c][k]
  * (0 for continuum wavelengths), for the N_0 cascade-0 directions. */

@@ -239,6 +239,24 @@ static int32_t march_ray(const ora_geom* g, ora_opac_fn opac, const void* ctx, i
     return n;
 }
 
+/* One ray with any opacity provider (scratch allocated here): the segments
+ * of [ta, tb) from (cx, cz) along (wx, wz), solved back to front. Returns the
+ * number of segments. */
+int32_t ora_ray(const ora_geom* g, ora_opac_fn opac, const void* ctx, int32_t lam, double cx, double cz, double wx,
+                double wz, double ta, double tb, double* I, double* tau)
+{
+    int32_t max_seg = g->nx + g->nz + 8;
+    int32_t* sx = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+    int32_t* sz = (int32_t*)malloc(sizeof(int32_t) * max_seg);
+    double* buf = (double*)malloc(sizeof(double) * 4 * (size_t)max_seg);
+    int32_t n = march_ray(g, opac, ctx, lam, cx, cz, wx, wz, ta, tb, sx, sz, buf, buf + max_seg, buf + 2 * max_seg,
+                          buf + 3 * max_seg, max_seg, I, tau);
+    free(sx);
+    free(sz);
+    free(buf);
+    return n;
+}
+
 /* ------------------------------------------------------------------ merge */
 
 /* Bilinear taps of probe coordinate c (cells) on the probe grid of cascade

@@ -20,4 +20,6 @@ typedef void (*ora_opac_fn)(const void* ctx, int32_t lam, int32_t cx, int32_t cz
 int32_t ora_rc_solve(const ora_geom* g, int32_t n_wave, ora_opac_fn opac, const void* ctx,
                      const uint8_t* need_c0, double* J, double* I0, int64_t* stats);
 void ora_direction(const ora_geom* g, int32_t i, int32_t k, double* wx, double* wz);
+int32_t ora_ray(const ora_geom* g, ora_opac_fn opac, const void* ctx, int32_t lam, double cx, double cz, double wx,
+                double wz, double ta, double tb, double* I_out, double* tau_out);
 #endif

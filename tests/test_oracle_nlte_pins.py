@@ -353,3 +353,48 @@ def test_sparse_nlte_ignores_coronal_cells():
     act = ~hot.reshape(-1)
     np.testing.assert_allclose(a[:, act], b[:, act], rtol=1e-12)
     np.testing.assert_array_equal(a[:, ~act], P.lte[:, ~act])
+
+
+# -------------------------------------------------------- emergent spectra
+
+
+def test_nlte_emergent_without_lines_is_the_given_fields_solver():
+    """Sec. 3.9: at continuum wavelengths the non-LTE emergent intensity is
+    the given-fields beam solver's on the synthesised continuum opacity and
+    emissivity (the two share only the ray layout)."""
+    inp = W.nlte_atmosphere(24, seed=3, n_line=8, n_cont=4)
+    P = nlte.Problem(inp)
+    chi_c, eta_c, _, _ = P.fields(P.lte)
+    I = P.emergent(P.lte, 0.6, -0.8, 40)
+    cont = np.nonzero(P.line_index < 0)[0]
+    ref = oracle.emergent(chi_c[cont].reshape(-1, 24, 24), eta_c[cont].reshape(-1, 24, 24), 0.6, -0.8, 40,
+                          voxel=inp.voxel)
+    np.testing.assert_allclose(I[cont], ref, rtol=1e-12, atol=0)
+
+
+def test_nlte_emergent_line_follows_the_flow():
+    """Sec. 3.9 with Sec. 3.2's Doppler shifts: a uniform flow of 20 km/s
+    along +x shifts the emergent line to the blue for an observer on the +x
+    side and to the red for one on the -x side (the intensity-weighted
+    velocity centroid of the line against the same atmosphere at rest; on
+    the coarse, non-uniform wavelength grid the centroid moves by 0.4-1 x
+    the flow speed, so the bound is loose and the sign is the pin)."""
+    import dataclasses
+    inp = W.nlte_atmosphere(24, seed=3, n_line=32, n_cont=4)
+    v0 = 20e3
+    still = dataclasses.replace(inp, vel=np.zeros_like(inp.vel))
+    vel = np.zeros_like(inp.vel)
+    vel[0] = v0
+    flow = dataclasses.replace(inp, vel=vel)
+    P0, P1 = nlte.Problem(still), nlte.Problem(flow)
+    line0 = np.nonzero(P0.line_index == 0)[0]
+    u = P0.u[line0]
+
+    def centroid(P, wx):
+        I = P.emergent(P0.lte, wx, 0.0, 24)[line0].mean(axis=1)
+        e = I - I.min()
+        return float(np.sum(u * e) / np.sum(e))
+
+    for wx, sign in ((1.0, 1.0), (-1.0, -1.0)):
+        shift = centroid(P1, wx) - centroid(P0, wx)
+        assert 0.2 * v0 < sign * shift < 1.5 * v0, (wx, shift)
