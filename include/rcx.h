@@ -355,6 +355,19 @@ int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, doub
  * or period < 1. */
 int32_t rcx_nlte_set_acceleration(rcx_nlte* s, int32_t order, int32_t delay, int32_t period);
 
+/* Emergent spectra (Sec. 3.9) at populations pops [n_levels][nz][nx]
+ * (device, FP64): the beam of rcx_emergent (light direction (wx, wz), ray j
+ * at offset j + 1/2 - n_rays/2 cells along (-wz, wx) from the domain
+ * centre), traced through the opacities and emissivities synthesised from
+ * pops, with the line profiles Doppler-shifted along the rays as in the
+ * formal solution. I [n_wave][n_rays] (device, float32, caller-owned);
+ * unflagged cells of a sparse solver are empty. Uses the solver's field
+ * buffers (not concurrently with another call on it). RCX_E_INVALID for
+ * null arguments, n_rays <= 0, a zero direction or before
+ * rcx_nlte_set_atmosphere. */
+int32_t rcx_nlte_emergent(rcx_nlte* s, const double* pops, double wx, double wz, int32_t n_rays, float* I,
+                          hipStream_t stream);
+
 /* Charge conservation (Sec. 3.3; off by default): after each equilibrium
  * step of rcx_nlte_stat_eq / rcx_nlte_iterate, one Newton-Raphson step per
  * cell on the populations and the electron density, with the equations

@@ -1068,6 +1068,47 @@ hipError_t launch_level_op(int32_t kind, bool small_a, const LevelDesc& L, int32
     return launch_level(L, nx, nz, lop, epi, dirs, up, st);
 }
 
+// Emergent intensity along a beam of parallel long characteristics (Sec.
+// 3.9) through the synthesised fields: 4 rays x 16 wavelengths of one batch
+// per wavefront, ray j from o0 + s_j p (s_j = j + 1/2 - n_rays/2) along d,
+// the op's per-step opacity (the line op's Doppler shift follows d).
+template <class Op>
+__global__ __launch_bounds__(march::kBlock) void k_emergent_op(int32_t nx, int32_t nz, Op op, double ox0, double oz0,
+                                                               double px, double pz, double4 d, int32_t n_rays,
+                                                               float* __restrict__ out, int32_t lam0, int32_t n_valid)
+{
+    using march::kBlock;
+    __shared__ uint4 seg[kBlock / 64][4][march::kSegRow];
+    __shared__ typename Op::Stage stg[Op::kStaged ? kBlock / 64 : 1][4][march::kStgRow];
+    __shared__ float2 op_smem[Op::kSmemBytes > 0 ? Op::kSmemBytes / 8 : 2];
+    if constexpr (Op::kSmemBytes > 0) {
+        op.init_shared(op_smem);
+        __syncthreads();
+    }
+    const march::RowCtx c = march::row_ctx();
+    op.init(c.l);
+    seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (Op::kStaged) {
+        uint4* gw = reinterpret_cast<uint4*>(&stg[c.w][0][0]);
+        constexpr int n16 = 4 * march::kStgRow * (int)sizeof(typename Op::Stage) / 16;
+        for (int i = c.lane; i < n16; i += 64) gw[i] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    march::wave_sync();
+    LevelDesc L{};
+    L.ds_scale = 1.0;
+    const int64_t stride = (int64_t)gridDim.x * march::kRaysPerBlock;
+    for (int64_t base = ((int64_t)blockIdx.x * (kBlock / 64) + c.w) * 4; base < n_rays; base += stride) {
+        const int64_t j = base + c.row;
+        const bool active = j < n_rays;
+        const double sj = (double)(active ? j : 0) + 0.5 - 0.5 * (double)n_rays;
+        op.begin_ray(d.x, d.y);
+        float I[1], T[1];
+        march::walk_ray(L, nx, nz, op, ox0 + sj * px, oz0 + sj * pz, d, 0.0, INFINITY, active, seg[c.w],
+                        stg[Op::kStaged ? c.w : 0], c, I, T);
+        if (active && c.l < n_valid) out[(int64_t)(lam0 + c.l) * n_rays + j] = I[0];
+    }
+}
+
 template <int NL>
 hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t st)
 {
@@ -1538,6 +1579,92 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         // rates and J are 0
         RCX_HIP_TRY(launch_mask_j(rates, P->mask_dev, nc, 2 * A.nt, st));
         if (J) RCX_HIP_TRY(launch_mask_j(J, P->mask_dev, nc, s->n_wave, st));
+    }
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_emergent(rcx_nlte* s, const double* pops, double wx, double wz, int32_t n_rays, float* I,
+                          hipStream_t st)
+{
+    if (!s || !pops || !I) return nlte_fail(RCX_E_INVALID, "rcx_nlte_emergent: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_emergent: set the atmosphere first");
+    if (n_rays <= 0) return nlte_fail(RCX_E_INVALID, "rcx_nlte_emergent: n_rays must be positive");
+    const double wn = std::hypot(wx, wz);
+    if (!(wn > 0.0) || !std::isfinite(wn)) return nlte_fail(RCX_E_INVALID, "rcx_nlte_emergent: zero direction");
+    wx /= wn;
+    wz /= wn;
+    const rcx_plan* P = s->plan;
+    const int32_t nx = P->grid.nx, nz = P->grid.nz;
+    const int64_t nc = s->ncell;
+    const AtomDev& A = s->atom;
+    // the fields of the populations, as for the formal solve
+    SynthArgs sa{pops, s->inv_vth, s->adamp, s->sphi, s->lratio, s->hkt2, s->line_rec, s->epi_rec, s->voxel,
+                 s->small_a ? 1.0f : (float)(1.0 / s->da_c), s->small_a ? (1 << 24) : s->n_ac};
+    hipLaunchKernelGGL(k_synth, dim3(blocks_for(nc, 256)), dim3(256), 0, st, A, nc, sa);
+    RCX_HIP_TRY(hipGetLastError());
+    if (P->mask_dev && A.n_lines > 0) {
+        hipLaunchKernelGGL(k_mask_line_rec, dim3(blocks_for((int64_t)A.n_lines * nc, 256)), dim3(256), 0, st,
+                           s->line_rec, P->mask_dev, nc, A.n_lines);
+        RCX_HIP_TRY(hipGetLastError());
+    }
+    const int32_t nb = (int32_t)s->batches.size();
+    for (int32_t b = 0; b < nb; ++b) {
+        const auto& B = s->batches[b];
+        const Trans& tr = A.t[B.trans];
+        if (tr.kind != 1) continue;
+        ContBatch cb{};
+        cb.trans = B.trans;
+        cb.n = B.n;
+        for (int q = 0; q < B.n; ++q) cb.nu[q] = kC / (s->lam_nm[B.lam0 + q] * 1e-9);
+        float2* Fb = s->Fcont + (size_t)B.cont_slot * nc * kLB;
+        hipLaunchKernelGGL(k_synth_cont, dim3(blocks_for(nc * kLB, 256)), dim3(256), 0, st, A, nc, pops, s->T, cb,
+                           s->lratio, s->voxel, Fb, nullptr);
+        RCX_HIP_TRY(hipGetLastError());
+        if (P->mask_dev) RCX_HIP_TRY(launch_mask_fields(Fb, P->mask_dev, nc, 1, st));
+    }
+    // the beam (as rcx_emergent): from outside the domain on the observer's
+    // side, march direction -w
+    const double R = 0.5 * std::hypot((double)nx, (double)nz) + 2.0;
+    const double ox0 = 0.5 * nx + R * wx, oz0 = 0.5 * nz + R * wz;
+    double dx = -wx, dz = -wz;
+    if (std::fabs(dx) < 1e-12) dx = dx < 0.0 ? -1e-12 : 1e-12;
+    if (std::fabs(dz) < 1e-12) dz = dz < 0.0 ? -1e-12 : 1e-12;
+    const double4 d = make_double4(dx, dz, 1.0 / dx, 1.0 / dz);
+    const dim3 grid = march_grid(n_rays);
+    for (int32_t b = 0; b < nb; ++b) {
+        const auto& B = s->batches[b];
+        const Trans& tr = A.t[B.trans];
+        const float* bc = s->bconst + b * 5 * kLB;
+        if (tr.kind == 1) {
+            march::FieldOp fop{};
+            fop.Fb = s->Fcont + (size_t)B.cont_slot * nc * kLB;
+            fop.fb_bytes = (uint32_t)(nc * kLB * sizeof(float2));
+            hipLaunchKernelGGL(k_emergent_op<march::FieldOp>, grid, dim3(march::kBlock), 0, st, nx, nz, fop, ox0, oz0,
+                               -wz, wx, d, n_rays, I, B.lam0, B.n);
+        } else if (s->small_a) {
+            LineOpSmallA sop{};
+            sop.rec = s->line_rec + (size_t)tr.line * nc;
+            sop.vel = s->vel;
+            sop.tabc = s->vtabc;
+            sop.n_a = s->n_ac;
+            sop.u_b = bc + 1 * kLB;
+            sop.ncell = (uint32_t)nc;
+            sop.da_sqrtpi = (float)(s->da_c / std::sqrt(kPi));
+            hipLaunchKernelGGL(k_emergent_op<LineOpSmallA>, grid, dim3(march::kBlock), 0, st, nx, nz, sop, ox0, oz0,
+                               -wz, wx, d, n_rays, I, B.lam0, B.n);
+        } else {
+            LineOp lop{};
+            lop.rec = s->line_rec + (size_t)tr.line * nc;
+            lop.vel = s->vel;
+            lop.tabc = s->vtabc;
+            lop.n_a = s->n_ac;
+            lop.u_b = bc + 1 * kLB;
+            lop.ncell = (uint32_t)nc;
+            lop.da_sqrtpi = (float)(s->da_c / std::sqrt(kPi));
+            hipLaunchKernelGGL(k_emergent_op<LineOp>, grid, dim3(march::kBlock), 0, st, nx, nz, lop, ox0, oz0, -wz,
+                               wx, d, n_rays, I, B.lam0, B.n);
+        }
+        RCX_HIP_TRY(hipGetLastError());
     }
     return RCX_OK;
 }

@@ -319,6 +319,7 @@ def _load_nlte():
     L.rcx_nlte_set_line_profile.argtypes = [vp, i32]
     L.rcx_nlte_set_acceleration.argtypes = [vp, i32, i32, i32]
     L.rcx_nlte_set_charge_conservation.argtypes = [vp, i32]
+    L.rcx_nlte_emergent.argtypes = [vp, vp, C.c_double, C.c_double, i32, vp, vp]
     L.rcx_nlte_get_ne.argtypes = [vp, vp, vp]
     L.rcx_nlte_set_pressure_conservation.argtypes = [vp, i32]
     L.rcx_nlte_collisional_ne.argtypes = [vp, i32, vp]
@@ -335,7 +336,7 @@ def _load_nlte():
     L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
     for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start",
-              "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_set_pressure_conservation",
+              "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_emergent", "rcx_nlte_set_pressure_conservation",
               "rcx_nlte_collisional_ne", "rcx_nlte_set_temperature_cut"):
         getattr(L, n).restype = i32
     for n in ("rcx_nlte_create", "rcx_nlte_set_atmosphere", "rcx_nlte_lte_populations",
@@ -473,6 +474,16 @@ class Nlte:
     def set_acceleration(self, order: int, delay: int = 0, period: int = 1):
         """Ng acceleration of iterate() (order 0 = off)."""
         rcx_nlte_set_acceleration(self.handle, order, delay, period)
+
+    def emergent(self, pops, wx: float, wz: float, n_rays: int):
+        """Emergent spectra [n_wave][n_rays] at populations pops along the
+        beam of parallel long characteristics of light direction (wx, wz)."""
+        import torch
+        I = torch.empty((self.inp.n_wave, n_rays), dtype=torch.float32, device="cuda")
+        _check(_load_nlte().rcx_nlte_emergent(self.handle, _dev_ptr(pops, "torch.float64", "pops"), float(wx),
+                                              float(wz), int(n_rays), _dev_ptr(I, "torch.float32", "I"),
+                                              _stream_ptr(None)), "rcx_nlte_emergent")
+        return I
 
     def set_charge_conservation(self, enable: bool = True):
         """One Newton-Raphson charge-conservation step after each

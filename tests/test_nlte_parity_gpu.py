@@ -4,6 +4,8 @@ Tolerances: populations 1e-3 relative (compared after the same number of
 iterations, the oracle's stopping count for converged runs); J 5e-4 relative
 (the FP32 march plus the device Voigt table's interpolation error, below
 5e-5 relative); LTE populations 1e-12 (same FP64 formula)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -357,3 +359,28 @@ def test_sparse_nlte_matches_oracle():
     assert np.array_equal(pg[:, ~act], l0[:, ~act])
     assert np.all(rg.reshape(rg.shape[0], 2, -1)[:, :, ~act] == 0.0)
     assert rc2 == 0 and abs(it2 - K) <= 1
+
+
+@pytest.mark.parametrize("wx, wz", [(0.8, 0.6), (-0.45, -0.9)])
+def test_emergent_spectra_match_oracle(case32, wx, wz):
+    """Emergent spectra (Sec. 3.9) along a beam of parallel long
+    characteristics at the populations after two GPU iterations, against
+    the oracle at the same populations: 5e-4 relative (the FP32 march and
+    the march's Voigt profile, as for J)."""
+    torch = _torch()
+    inp, P = case32
+    s = _solver(inp)
+    pops = s.lte()
+    s.iterate(pops, 2, 0.0)
+    n_rays = int(math.ceil(abs(inp.nx * wz) + abs(inp.nz * wx))) + 4
+    I = s.emergent(pops, wx, wz, n_rays)
+    torch.cuda.synchronize()
+    Ig = I.cpu().numpy().astype(np.float64)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    Io = P.emergent(pg, wx, wz, n_rays)
+    hit = Io > 0
+    rel = np.abs(Ig[hit] - Io[hit]) / Io[hit]
+    print(f"emergent spectra w=({wx}, {wz}): {hit[0].sum()} of {n_rays} rays hit, max rel {rel.max():.3e}")
+    assert np.all(Ig[~hit] == 0.0)
+    assert rel.max() < 5e-4
