@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -213,6 +214,18 @@ def nlte_solves(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         final[name] = p
+        if name == "plain_fp32":
+            # emergent spectra of the converged atmosphere along a beam of
+            # parallel long characteristics
+            n_em = int(math.ceil(inp.nx * 0.6 + inp.nz * 0.8)) + 2
+            s.emergent(p, 0.8, 0.6, n_em)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                s.emergent(p, 0.8, 0.6, n_em)
+            torch.cuda.synchronize()
+            out["emergent_spectra"] = {"direction": [0.8, 0.6], "rays": n_em,
+                                       "ms_per_image": (time.perf_counter() - t1) / 5 * 1e3}
         s.close()
         out[name] = {"seconds": dt, "iterations": it, "last_change": ch, "converged": rc == 0,
                      "s_per_iteration": dt / max(it, 1)}
@@ -409,6 +422,19 @@ def main():
             "steps": stepsS,
         }
 
+    # emergent intensity along a beam of parallel long characteristics (light
+    # direction (0.8, 0.6), one ray per cell across the beam)
+    planE = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
+    n_em = int(math.ceil(inp.nx * 0.6 + inp.nz * 0.8)) + 2
+    planE.emergent(chi, eta, 0.8, 0.6, n_em)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        planE.emergent(chi, eta, 0.8, 0.6, n_em)
+    torch.cuda.synchronize()
+    emergent = {"direction": [0.8, 0.6], "rays": n_em, "ms_per_image": (time.perf_counter() - t0) / 10 * 1e3}
+    planE.close()
+
     ms_step = dt / args.steps * 1e3
     rays = work.rays_nonempty * inp.n_wave
     value = rays / (dt / args.steps)
@@ -451,6 +477,7 @@ def main():
         "inclined": incl,
         "bilinear_fix": fix,
         "sparse": sparse,
+        "emergent": emergent,
         "roofline": {
             "bound": "alu",
             "kernel": "k_march_rows",
