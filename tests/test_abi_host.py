@@ -60,6 +60,19 @@ def test_plan_create_rejects_bad_flags(flags, n_incl, code):
     assert e.value.code == getattr(rcx, code)
 
 
+def test_sparse_and_emergent_calls_reject_bad_arguments():
+    """The sparse, emergent and batch-flag calls validate their arguments
+    before touching the device."""
+    L = rcx.load()
+    assert L.rcx_plan_set_active_host(None, None, None) == rcx.RCX_E_INVALID
+    assert L.rcx_emergent(None, 1, None, None, 1.0, 0.0, 4, None, None) == rcx.RCX_E_INVALID
+    N = rcx._load_nlte()
+    assert N.rcx_nlte_emergent(None, None, 1.0, 0.0, 4, None, None) == rcx.RCX_E_INVALID
+    assert N.rcx_nlte_set_temperature_cut(None, 2.5e5, None) == rcx.RCX_E_INVALID
+    B = rcx._load_batch()
+    assert B.rcx_batch_set_active_host(None, 0, None) == rcx.RCX_E_INVALID
+
+
 def test_nlte_conservation_calls_reject_null():
     """The charge/pressure conservation and collisional n_e calls reject a
     null solver before touching the device."""
