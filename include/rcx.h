@@ -83,9 +83,9 @@ typedef struct {
  *               q of the cascade above, from its start p + t_i w_k to the
  *               start q + t_{i+1} w_k of the child cone on q, merges it with
  *               q's children and sums the four results with the bilinear
- *               weights (4 x the rays below the top cascade). Flatland only
- *               (n_incl = 1), formal solve only: batches and the non-LTE
- *               solver return RCX_E_UNSUPPORTED for it. */
+ *               weights (4 x the rays below the top cascade). Formal solve
+ *               only (with any n_incl): batches and the non-LTE solver
+ *               return RCX_E_UNSUPPORTED for it. */
 typedef struct {
     int32_t n_cascades;
     int32_t c0_dirs;
@@ -120,9 +120,10 @@ int32_t rcx_params_default(rcx_params* p);
  * direction tables on the device and allocates the plan-owned workspace
  * used when a call passes workspace == NULL.
  * Errors: RCX_E_INVALID (null, nx/nz/max_wave <= 0, c0_dirs <= 0,
- * c0_t1 <= 0, n_cascades outside [1, 16], unknown flags); RCX_E_UNSUPPORTED
- * (RCX_FLAG_BILINEAR_FIX with n_incl != 1,
- * unknown storage); RCX_E_NOMEM; RCX_E_HIP. On error *out is NULL. */
+ * c0_t1 <= 0, n_cascades outside [1, 16], n_incl outside [1, 16], unknown
+ * flags); RCX_E_UNSUPPORTED (unknown storage, too many top-cascade
+ * directions, more than 2^24 cells); RCX_E_NOMEM; RCX_E_HIP. On error *out
+ * is NULL. */
 int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* p, int32_t max_wave, rcx_plan** out);
 
 /* Sparse solve (Sec. 3.5). active_host [nz][nx] (host, caller-owned, read

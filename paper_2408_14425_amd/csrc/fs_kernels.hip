@@ -99,9 +99,6 @@ __global__ void k_fill_u32(unsigned int* p, int32_t n, unsigned int v)
     if (i < n) p[i] = v;
 }
 
-// ---------------------------------------------------------------- J
-// J[lam0 + l][c] = (1/N_0) sum_k Itilde_0[(c * N_0 + k)][l] for one batch,
-// through a 64-cell x 16-wavelength LDS tile.
 // Sparse solve: cells with mask 0 are transparent and emit nothing
 // (F = {0, 0} in every batch), and their J is 0. Grid-stride over
 // (batch or wavelength) x cell; F is written as 16 float2 per cell.
@@ -123,6 +120,9 @@ __global__ __launch_bounds__(256) void k_mask_j(float* __restrict__ J, const uin
         if (!mask[i % ncell]) J[i] = 0.0f;
 }
 
+// ---------------------------------------------------------------- J
+// J[lam0 + l][c] = (1/N_0) sum_k Itilde_0[(c * N_0 + k)][l] for one batch,
+// through a 64-cell x 16-wavelength LDS tile.
 __global__ __launch_bounds__(256) void k_j(const float* __restrict__ I0, float* __restrict__ J,
                                            int32_t lam0, int32_t n_valid, int64_t ncell, int32_t n0, float w,
                                            int32_t acc_j)
@@ -309,6 +309,18 @@ hipError_t launch_march_merge_incl(const LevelDesc& L, int32_t nx, int32_t nz, c
     op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
     for (int w = 0; w < kInclSlots; ++w) op.sc[w] = sc[w];
     return launch_fs_up(L, nx, nz, op, march::StoreEpiSlots<kInclSlots>{(float*)io.out, io.slot_stride}, dirs, io, st);
+}
+
+hipError_t launch_march_fix_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                 const CascIO& io, const float* sc, hipStream_t st)
+{
+    march::FieldOpIncl<kInclSlots> op{};
+    op.Fb = Fb;
+    op.fb_bytes = (uint32_t)((int64_t)nx * nz * kLB * sizeof(float2));
+    for (int w = 0; w < kInclSlots; ++w) op.sc[w] = sc[w];
+    march::UpF32 up{(const float*)io.up};
+    up.stride = io.slot_stride;
+    return launch_fix_k(L, nx, nz, op, march::StoreEpiSlots<kInclSlots>{(float*)io.out, io.slot_stride}, dirs, up, st);
 }
 
 hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,

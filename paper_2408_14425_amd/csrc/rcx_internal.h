@@ -104,6 +104,9 @@ hipError_t launch_march_fix(const LevelDesc& L, int32_t nx, int32_t nz, const fl
 constexpr int kInclSlots = 8;
 hipError_t launch_march_merge_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
                                    const CascIO& io, const float* sc, hipStream_t st);
+// The bilinear fix with the kInclSlots inclinations as slots (FP32).
+hipError_t launch_march_fix_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
+                                 const CascIO& io, const float* sc, hipStream_t st);
 hipError_t launch_march_merge_j_incl(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb,
                                      const double4* dirs, const CascIO& io, float* J, int32_t lam0, int32_t n_valid,
                                      const float* sc, const float* wt, hipStream_t st);

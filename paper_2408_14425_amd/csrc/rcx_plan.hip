@@ -203,9 +203,55 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
     const bool fuse_j = p->prm.c0_dirs == 4;
     if (p->prm.flags & RCX_FLAG_BILINEAR_FIX) {
         // bilinear fix: the cascades below the top trace each interval once
-        // per bilinear probe; batches b and b+1 share the walks on the
-        // cascades with at most kPairMaxDirs directions (as in the basic
-        // solve); cascade 0 is stored, then averaged into J
+        // per bilinear probe; cascade 0 is stored, then averaged into J
+        if (incl_slots(p)) {
+            // the 8 inclinations as slots (one batch at a time)
+            float sc[kInclSlots], wt[kInclSlots];
+            for (int m = 0; m < kInclSlots; ++m) {
+                sc[m] = (float)p->incl_scale[m];
+                wt[m] = (float)p->incl_w[m];
+            }
+            for (int32_t b = 0; b < n_batch; ++b) {
+                const float2* Fb = F + (size_t)b * ncell * lb;
+                const int32_t nvalid = std::min(lb, n_wave - b * lb);
+                int cur = 0;
+                const void* up = nullptr;
+                for (int32_t i = p->n_casc - 1; i >= 0; --i) {
+                    if (p->top_skipped && i == p->n_casc - 1) continue;
+                    const LevelDesc& L = p->levels[i];
+                    CascIO io;
+                    io.up = L.has_up ? up : nullptr;
+                    io.up_f16 = false;
+                    io.out = bufs[cur];
+                    io.out_f16 = false;
+                    io.scale_b = scale + (size_t)b * lb;
+                    io.inv_scale_b = inv_scale + (size_t)b * lb;
+                    io.slot_stride = w.casc_slot;
+                    const double4* dirs = p->dirs_dev + p->dir_off[i];
+                    const bool fix = i + 1 < p->n_casc;
+                    RCX_HIP_TRY(timed(p, i, st, [&] {
+                        return fix ? launch_march_fix_incl(L, nx, nz, Fb, dirs, io, sc, st)
+                                   : launch_march_merge_incl(L, nx, nz, Fb, dirs, io, sc, st);
+                    }));
+                    up = bufs[cur];
+                    cur ^= 1;
+                }
+                RCX_HIP_TRY(timed(p, -1, st, [&] {
+                    hipError_t e = hipSuccess;
+                    for (int m = 0; m < kInclSlots && e == hipSuccess; ++m)
+                        e = launch_j((const float*)up + m * w.casc_slot, J, b * lb, nvalid, ncell, p->prm.c0_dirs,
+                                     wt[m], m > 0, st);
+                    return e;
+                }));
+            }
+            return ok();
+        }
+        // one pass per inclination (flatland: one pass); batches b and b+1
+        // share the walks on the cascades with at most kPairMaxDirs
+        // directions (as in the basic solve)
+        for (int32_t m = 0; m < p->prm.n_incl; ++m) {
+        const float jw = (float)p->incl_w[m];
+        const bool jacc = m > 0;
         for (int32_t b = 0; b < n_batch;) {
             const bool pair = b + 1 < n_batch;
             const float2* Fb = F + (size_t)b * ncell * lb;
@@ -216,7 +262,8 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
             bool up_f16 = false;
             for (int32_t i = p->n_casc - 1; i >= 0; --i) {
                 if (p->top_skipped && i == p->n_casc - 1) continue;
-                const LevelDesc& L = p->levels[i];
+                LevelDesc L = p->levels[i];
+                L.ds_scale = p->incl_scale[m];
                 CascIO io;
                 io.up = L.has_up ? up : nullptr;
                 io.up_f16 = up_f16;
@@ -252,13 +299,14 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                 cur ^= 1;
             }
             RCX_HIP_TRY(timed(p, -1, st, [&] {
-                hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, 1.0f, false, st);
+                hipError_t e = launch_j((const float*)up, J, b * lb, nvalid, ncell, p->prm.c0_dirs, jw, jacc, st);
                 if (e == hipSuccess && pair)
-                    e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, 1.0f,
-                                 false, st);
+                    e = launch_j((const float*)up + w.casc_slot, J, (b + 1) * lb, nvalid1, ncell, p->prm.c0_dirs, jw,
+                                 jacc, st);
                 return e;
             }));
             b += pair ? 2 : 1;
+        }
         }
         return ok();
     }
@@ -424,8 +472,6 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
     if (prm->n_incl < 1 || prm->n_incl > 16)
         return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
     if ((prm->flags & ~RCX_FLAG_BILINEAR_FIX) != 0) return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
-    if ((prm->flags & RCX_FLAG_BILINEAR_FIX) && prm->n_incl != 1)
-        return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: the bilinear fix is flatland only (n_incl = 1)");
     int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
     if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
     if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))

@@ -49,9 +49,9 @@ def test_plan_create_rejects_bad_inclination_counts(n_incl):
 
 
 @pytest.mark.parametrize("flags, n_incl, code", [(2, 1, "RCX_E_INVALID"), (0x80000000, 1, "RCX_E_INVALID"),
-                                                 (1, 8, "RCX_E_UNSUPPORTED")])
+                                                 (3, 8, "RCX_E_INVALID")])
 def test_plan_create_rejects_bad_flags(flags, n_incl, code):
-    """Unknown flag bits are invalid; the bilinear fix is flatland only."""
+    """Unknown flag bits are invalid (with or without the bilinear fix)."""
     p = rcx.rcx_params_default()
     p.flags = flags
     p.n_incl = n_incl

@@ -204,7 +204,7 @@ def _ragged_w20():
 
 
 @pytest.mark.parametrize("case", ["blobs64", "ragged_w20", "blobs32_nc2", "blobs32_nc3", "disc128",
-                                  "line96_w40_fp16"])
+                                  "line96_w40_fp16", "blobs64_incl8", "ragged_w20_incl3"])
 def test_bilinear_fix_matches_oracle(case):
     """Bilinear fix (Sec. 2.5): each interval of the cascades below the top
     traced once per bilinear probe, to the start of that probe's child cone.
@@ -213,20 +213,30 @@ def test_bilinear_fix_matches_oracle(case):
     so the cascade below traces its four rays with nothing above); 2 and 3
     cascades (the top cascade marched and merged); the opaque disc in vacuum
     (zero-opacity cells); FP16 cascade storage (bounded as in the FP16
-    test)."""
-    tol, nc, st = RTOL, 0, 0
+    test); the 8 inclinations as slots, and 3 inclinations as passes over a
+    pair of batches."""
+    tol, nc, st, ni = RTOL, 0, 0, 1
     if case == "blobs64":
         inp = W.blobs_medium(64, seed=1)
     elif case == "ragged_w20":
         inp = _ragged_w20()
+    elif case == "blobs64_incl8":
+        inp, ni = W.blobs_medium(64, seed=1), 8
+    elif case == "ragged_w20_incl3":
+        inp, ni = _ragged_w20(), 3
     elif case.startswith("blobs32_nc"):
         inp, nc = W.blobs_medium(32, seed=8), int(case[-1])
     elif case == "disc128":
         inp = W.disc_in_vacuum(128, 4.0)
     else:
         inp, st, tol = W.line_medium(96, 64, seed=5, wave_subset=np.arange(0, 40)), 1, 2e-3
-    Jg = _gpu_solve(inp, n_cascades=nc, storage=st, bilinear_fix=True)
-    Jo = oracle.formal_solve(inp.chi, inp.eta, nc or inp.n_cascades, voxel=inp.voxel_scale, bilinear_fix=True)["J"]
+    Jg = _gpu_solve(inp, n_cascades=nc, storage=st, bilinear_fix=True, n_incl=ni)
+    if ni > 1:
+        Jo = oracle.formal_solve_inclined(inp.chi, inp.eta, inp.n_cascades, ni, voxel=inp.voxel_scale,
+                                          bilinear_fix=True)
+    else:
+        Jo = oracle.formal_solve(inp.chi, inp.eta, nc or inp.n_cascades, voxel=inp.voxel_scale,
+                                 bilinear_fix=True)["J"]
     if case == "disc128":
         # cells no ray of any cascade reaches from the disc are exactly 0 on both sides
         assert np.array_equal(Jg == 0, Jo == 0)
