@@ -472,3 +472,23 @@ def test_emergent_matches_oracle(case, wx, wz):
     hit = Io > 0
     assert np.all(Ig[~hit] == 0.0) and hit.sum() > 0
     print(f"emergent {case}: {hit[0].sum()} of {n_rays} rays hit, max rel {_assert_rel(Ig[hit], Io[hit]):.3e}")
+
+
+def test_emergent_on_a_sparse_plan_sees_the_emptied_medium():
+    """A sparse plan's emergent image treats unflagged cells as empty: it
+    equals the oracle's image of the medium with those cells emptied."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.blobs_medium(64, seed=1)
+    act = W.active_cells(64, 64, seed=9, frac=0.35)
+    print("[gpu] emergent on a sparse plan", flush=True)
+    plan = rcx.Plan(64, 64, inp.n_wave)
+    plan.set_active(act)
+    I = plan.emergent(torch.from_numpy(inp.chi).cuda(), torch.from_numpy(inp.eta).cuda(), 0.6, 0.8, 96)
+    torch.cuda.synchronize()
+    Ig = I.cpu().numpy().astype(np.float64)
+    plan.close()
+    Io = oracle.emergent(np.where(act, inp.chi, 0.0), np.where(act, inp.eta, 0.0), 0.6, 0.8, 96)
+    hit = Io > 0
+    assert np.all(Ig[~hit] == 0.0)
+    print(f"sparse emergent: max rel {_assert_rel(Ig[hit], Io[hit]):.3e}")

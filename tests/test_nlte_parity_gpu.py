@@ -384,3 +384,27 @@ def test_emergent_spectra_match_oracle(case32, wx, wz):
     print(f"emergent spectra w=({wx}, {wz}): {hit[0].sum()} of {n_rays} rays hit, max rel {rel.max():.3e}")
     assert np.all(Ig[~hit] == 0.0)
     assert rel.max() < 5e-4
+
+
+def test_emergent_spectra_of_a_sparse_solver():
+    """With a temperature cut the emergent spectra see the corona as empty:
+    they equal the oracle's for the sparse problem (the coronal fields
+    emptied) at the same populations."""
+    torch = _torch()
+    from oracle import nlte
+    inp = W.nlte_atmosphere(32, seed=3, n_line=16, n_cont=8, corona_frac=0.45)
+    P = nlte.Problem(inp, t_cut=2.5e5)
+    s = _solver(inp)
+    s.set_temperature_cut(2.5e5)
+    pops = s.lte()
+    I = s.emergent(pops, 0.8, -0.6, 48)
+    torch.cuda.synchronize()
+    Ig = I.cpu().numpy().astype(np.float64)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    Io = P.emergent(pg, 0.8, -0.6, 48)
+    hit = Io > 0
+    rel = np.abs(Ig[hit] - Io[hit]) / Io[hit]
+    print(f"sparse emergent spectra: max rel {rel.max():.3e}")
+    assert np.all(Ig[~hit] == 0.0)
+    assert rel.max() < 5e-4
