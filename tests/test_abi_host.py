@@ -39,6 +39,27 @@ def test_plan_create_rejects_bad_sizes(nx, nz, mw):
     assert e.value.code == rcx.RCX_E_INVALID
 
 
+@pytest.mark.parametrize("nx,nz", [(4097, 4096), (1 << 24, 2), (65536, 65536), (2147483647, 2147483647)])
+def test_plan_create_rejects_grids_beyond_the_cell_maximum(nx, nz):
+    """More than 2^24 cells (the march keeps cell indices in 24-bit products)
+    is unsupported, also where nx * nz overflows 32 bits; the check comes
+    before any device call, so it runs without a GPU."""
+    p = rcx.rcx_params_default()
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(nx, nz, 1.0), p, 1)
+    assert e.value.code == rcx.RCX_E_UNSUPPORTED
+    code, msg = rcx.rcx_last_error()
+    assert code == rcx.RCX_E_UNSUPPORTED and "2^24" in msg
+
+
+@pytest.mark.parametrize("scale", [0.0, -1.0, float("nan")])
+def test_plan_create_rejects_non_positive_voxel_scale(scale):
+    p = rcx.rcx_params_default()
+    with pytest.raises(rcx.RcxError) as e:
+        rcx.rcx_plan_create(rcx.rcx_grid(8, 8, scale), p, 1)
+    assert e.value.code == rcx.RCX_E_INVALID
+
+
 @pytest.mark.parametrize("n_incl", [0, 17])
 def test_plan_create_rejects_bad_inclination_counts(n_incl):
     p = rcx.rcx_params_default()
