@@ -638,8 +638,9 @@ struct FieldOp {
         lane_off = (uint32_t)l * 8u;
     }
     __device__ __forceinline__ void begin_ray(double, double) {}
-    // key of a cell: the byte offset of its 16 wavelengths (cell < 2^24, so
-    // below 2^28); the null key lies beyond every buffer and reads zeros
+    // key of a cell: the byte offset of its 16 wavelengths, cell * 128 B
+    // (cell < 2^24, so at most 2^31 - 128, and key + lane offset < 2^31);
+    // the null key 2^31 lies at or beyond every buffer's size and reads zeros
     static constexpr uint32_t kNullKey = 0x80000000u;
     __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell * (uint32_t)(kLB * 8); }
     __device__ __forceinline__ void fetch_key(uint32_t k, Raw (&r)[kW]) const
