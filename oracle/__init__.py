@@ -97,6 +97,19 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def default_cascades(nx: int, nz: int) -> int:
+    """Cascade count of a grid when none is given: the smallest k with
+    4^k >= max(nx, nz), plus 2. With alpha = 2 the interval starts grow
+    as 4^i (Eq. RcScalingLaw, cascade-0 interval 1.5 cells, Sec. 4.5), so
+    this is the count at which the top cascade's interval starts at or
+    beyond the domain's diagonal: 5 cascades at 64^2, 7 at 1024^2."""
+    m = max(int(nx), int(nz))
+    k = 0
+    while 4 ** k < m:
+        k += 1
+    return k + 2
+
+
 def make_geom(nx: int, nz: int, n_casc: int, c0_dirs: int = 4, t1: float = 1.5,
               t_rule: int = 0, voxel: float = 1.0, bilinear_fix: bool = False) -> Geom:
     return Geom(nx, nz, n_casc, c0_dirs, t1, t_rule, int(bool(bilinear_fix)), voxel)

@@ -61,7 +61,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import _dp, lib, make_geom
+from . import _dp, default_cascades, lib, make_geom
 
 # CODATA 2018, SI
 H_PLANCK = 6.62607015e-34
@@ -196,7 +196,6 @@ class Problem:
     """Static (population-independent) data of one non-LTE problem."""
 
     def __init__(self, inp, n_casc: int | None = None, t_cut: float | None = None):
-        from paper_2408_14425_amd.workloads import n_cascades_for
         self.inp = inp
         self.atom = Atom(inp.atom)
         self.nx, self.nz = inp.nx, inp.nz
@@ -211,7 +210,7 @@ class Problem:
         self.nu = C_LIGHT / (inp.lambda_nm.astype(np.float64) * 1e-9)
         self.trans_of = inp.trans.astype(np.int32)
         self.W = 4.0 * math.pi * inp.dnu / (H_PLANCK * self.nu)
-        self.n_casc = n_cascades_for(self.nx, self.nz) if n_casc is None else n_casc
+        self.n_casc = default_cascades(self.nx, self.nz) if n_casc is None else n_casc
         self.geom = make_geom(self.nx, self.nz, self.n_casc, voxel=inp.voxel)
         self.n0 = 4
         self.lte = lte_populations(self.atom, self.T, self.ne, self.ntot)

@@ -31,6 +31,7 @@ def test_ray_counts_match_paper_identity():
     for case in _golden("ray_counts.json")["cases"]:
         n, I = case["n"], case["n_cascades"]
         assert W.n_cascades_for(n, n) == I
+        assert oracle.default_cascades(n, n) == I
         g = oracle.make_geom(n, n, I)
         counts = [np.prod(oracle.level_shape(g, i)) for i in range(I)]
         assert all(c == case["N_C0"] for c in counts)

@@ -105,6 +105,70 @@ def test_rates_vanish_at_lte_for_planck_field(small):
     assert ch < 1e-7
 
 
+def _planck(nu, T):
+    """B_nu(T) = (2 h nu^3 / c^2) / (e^{h nu / k T} - 1)."""
+    return 2 * nlte.H_PLANCK * nu ** 3 / nlte.C_LIGHT ** 2 / np.expm1(nlte.H_PLANCK * nu / (nlte.K_BOLTZ * T))
+
+
+def test_line_source_function_is_planck_at_lte(small):
+    """Kirchhoff for the synthesised line fields: at LTE populations the
+    line's emissivity over its opacity (the same profile multiplies both
+    under complete redistribution) is B_nu(nu0, T) in every cell. A
+    dropped g_i/g_j or a wrong population index fails this."""
+    P = small
+    _, _, kappa, eps = P.fields(P.lte)
+    for li, tr in enumerate(P.atom.lines):
+        np.testing.assert_allclose(eps[li] / kappa[li], _planck(tr.nu0, P.T), rtol=1e-10)
+
+
+def test_continuum_source_function_is_planck_at_lte(small):
+    """At LTE the continuum's emissivity over its opacity (stimulated
+    emission included) is B_nu(nu, T) at every continuum wavelength."""
+    P = small
+    chi_c, eta_c, _, _ = P.fields(P.lte)
+    for lam, t in enumerate(P.trans_of):
+        if P.atom.trans[t].kind == "cont":
+            assert np.all(chi_c[lam] > 0)
+            np.testing.assert_allclose(eta_c[lam] / chi_c[lam], _planck(P.nu[lam], P.T), rtol=1e-10)
+
+
+def test_thick_isothermal_atmosphere_has_planck_mean_intensity():
+    """A homogeneous isothermal atmosphere at rest at LTE populations, dense
+    enough that every cell is optically thick at the Lyman-alpha core and
+    across the Lyman continuum: the formal solution gives J = B_nu(T) (at
+    the line's rest frequency for line wavelengths) wherever the medium is
+    thick, the cells more than 8 cells from the edge."""
+    n = 32
+    inp = W.nlte_atmosphere(n, seed=9, n_line=16, n_cont=8)
+    T = np.full((n, n), 6000.0)
+    ntot = np.full((n, n), 5e19)
+    inp = W.NlteInput(T, 0.2 * ntot, ntot, np.zeros((2, n, n), np.float32), inp.lambda_nm, inp.trans, inp.dnu,
+                      inp.voxel, inp.atom, "isothermal")
+    P = nlte.Problem(inp)
+    chi_c, _, kappa, _ = P.fields(P.lte)
+    J = P.formal_solve(P.lte)[0]
+    inner = np.zeros((n, n), bool)
+    inner[8:-8, 8:-8] = True
+    inner = inner.ravel()
+    checked = 0
+    for lam, t in enumerate(P.trans_of):
+        tr = P.atom.trans[t]
+        if tr.kind == "line":
+            li = P.line_index[lam]
+            H = nlte.voigt_H(P.adamp[li], np.abs(P.u[lam]) / P.vth)
+            tau_cell = kappa[li] * H * inp.voxel
+            B = _planck(tr.nu0, P.T)
+        else:
+            tau_cell = chi_c[lam] * inp.voxel
+            B = _planck(P.nu[lam], P.T)
+        if tau_cell.min() < 5.0:
+            continue
+        checked += 1
+        np.testing.assert_allclose(J[lam][inner], B[inner], rtol=1e-10)
+    # the Lyman-alpha core and every Lyman-continuum wavelength are checked
+    assert checked >= 8 + 2
+
+
 def test_collision_dominated_limit_is_lte():
     """Collisions far above radiative rates force Saha-Boltzmann populations."""
     d = dict(W.SYNTH_ATOM)
