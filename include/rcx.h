@@ -37,19 +37,33 @@ extern "C" {
 #define RCX_E_NOMEM (-3)       /* device or host allocation failed              */
 #define RCX_E_HIP (-4)         /* a HIP runtime call failed (see last error)    */
 #define RCX_E_WORKSPACE (-5)   /* caller workspace too small                    */
+#define RCX_E_NONFINITE (-6)   /* an input value is not finite or out of range
+                                  (only with RCX_FLAG_CHECK_INPUT)              */
 
 /* Cascade interval rule (Eq. RcScalingLaw, alpha = 2). */
 #define RCX_T_GEOMETRIC 0  /* t_0 = 0, t_i = c0_t1 * 4^(i-1)                    */
 #define RCX_T_LENGTH_X4 1  /* t_i = c0_t1 * (4^i - 1) / 3 (lengths x4)          */
 
 /* Storage of merged cascade radiance between levels. F16_SCALED stores
- * cascades >= 1 as FP16 with a per-wavelength power-of-two scale
- * 2^(15 - ceil(log2 max S)), valid because no merged radiance exceeds the
- * largest source function along its path; cascade 0 stays FP32. */
+ * cascades >= 1 as 16-bit codes with FP16's precision and a per-wavelength
+ * exponent offset: the FP32 radiance rounded to a 10-bit significand (to
+ * nearest, ties to even; relative rounding 2^-11) with its exponent rebased
+ * into 6 bits below 2 x the wavelength's largest source function (FP16's
+ * sign bit spent on range, radiances being non-negative), so 63 binades
+ * keep that precision; smaller values flush to 0. Valid because no merged
+ * radiance exceeds the largest source function along its path. Cascade 0
+ * stays FP32. */
 #define RCX_STORE_F32 0
 #define RCX_STORE_F16_SCALED 1
 /* rcx_params.flags */
 #define RCX_FLAG_BILINEAR_FIX 1u
+/* Check the inputs of every call before computing (formal solves, batches,
+ * emergent intensity: chi and eta finite and >= 0; non-LTE atmospheres: T,
+ * n_e and ntot finite and > 0, velocities finite). One extra pass over the
+ * inputs and one stream synchronisation per call; a failed check returns
+ * RCX_E_NONFINITE (rcx_last_error names the array and the kind of value)
+ * before anything else is enqueued. */
+#define RCX_FLAG_CHECK_INPUT 2u
 
 /* Uniform 2D grid. chi is per unit of voxel_scale length: the optical depth
  * of a path of dt cells is chi * dt * voxel_scale (Sec. 3.2). */
@@ -76,7 +90,8 @@ typedef struct {
  *               the formal solve
  *               (rcx_formal_solve) supports n_incl > 1; batches and the
  *               non-LTE solver return RCX_E_UNSUPPORTED for it.
- *   flags:      RCX_FLAG_BILINEAR_FIX or 0 (other bits must be 0).
+ *   flags:      RCX_FLAG_BILINEAR_FIX, RCX_FLAG_CHECK_INPUT or their OR, or 0
+ *               (other bits must be 0).
  *               RCX_FLAG_BILINEAR_FIX (Sec. 2.5, the remedy for ringing and
  *               for light leaking through thin occluders): every cascade
  *               below the top traces each interval once per bilinear probe
@@ -158,9 +173,27 @@ int32_t rcx_plan_work(rcx_plan* plan, rcx_work* out_host);
  * workspace: device buffer of at least rcx_plan_workspace_bytes(n_wave)
  * bytes, or NULL to use the plan's own.
  * Errors: RCX_E_INVALID (null arrays, n_wave <= 0 or > max_wave);
- * RCX_E_WORKSPACE; RCX_E_HIP. */
+ * RCX_E_WORKSPACE; RCX_E_NONFINITE (with RCX_FLAG_CHECK_INPUT: a chi or eta
+ * value not finite or negative; nothing is computed); RCX_E_HIP. */
 int32_t rcx_formal_solve(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta,
                          float* J, void* workspace, size_t ws_bytes, hipStream_t stream);
+
+/* Emergent intensity along parallel long characteristics (Sec. 3.9, the
+ * post-processing formal solver): a beam of n_rays rays of light direction
+ * (wx, wz) (any non-zero vector; normalised), one cell apart across the beam
+ * and centred on the domain (ray j at offset j + 1/2 - n_rays/2 cells along
+ * (-wz, wx) from the domain centre), each traced front to back from outside
+ * the domain on the observer's side through isotropic chi, eta
+ * [n_wave][nz][nx] (device, float32, as for rcx_formal_solve) with the same
+ * cell walk and piecewise-constant update as the cascade march; nothing
+ * enters from behind (free-space boundary). I [n_wave][n_rays] (device,
+ * float32, caller-owned). Uses the plan's own workspace (the field batches),
+ * so it must not overlap another call on the plan; a sparse plan's
+ * unflagged cells are empty. Errors: RCX_E_INVALID (null arrays, n_wave
+ * outside [1, max_wave], n_rays <= 0, zero or non-finite direction);
+ * RCX_E_NONFINITE (with RCX_FLAG_CHECK_INPUT). */
+int32_t rcx_emergent(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta, double wx, double wz,
+                     int32_t n_rays, float* I, hipStream_t stream);
 
 /* Kernel timing for measurement: when enabled, every solve records HIP
  * events on its stream around each cascade's march+merge launch and around
@@ -188,26 +221,11 @@ int32_t rcx_plan_destroy(rcx_plan* plan);
 typedef struct rcx_batch rcx_batch;
 
 /* n_atm atmospheres with grids[a] and n_wave[a] wavelengths. p as for
- * rcx_plan_create, with n_cascades = 0 (automatic per atmosphere) and
- * c0_dirs = 4 (RCX_E_UNSUPPORTED otherwise). Allocates every buffer. */
+ * rcx_plan_create, with n_cascades = 0 (automatic per atmosphere), c0_dirs =
+ * 4, n_incl = 1 and no flag but RCX_FLAG_CHECK_INPUT (RCX_E_UNSUPPORTED
+ * otherwise). Allocates every buffer. */
 int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_wave, const rcx_params* p,
                          rcx_batch** out);
-/* Emergent intensity along parallel long characteristics (Sec. 3.9, the
- * post-processing formal solver): a beam of n_rays rays of light direction
- * (wx, wz) (any non-zero vector; normalised), one cell apart across the beam
- * and centred on the domain (ray j at offset j + 1/2 - n_rays/2 cells along
- * (-wz, wx) from the domain centre), each traced front to back from outside
- * the domain on the observer's side through isotropic chi, eta
- * [n_wave][nz][nx] (device, float32, as for rcx_formal_solve) with the same
- * cell walk and piecewise-constant update as the cascade march; nothing
- * enters from behind (free-space boundary). I [n_wave][n_rays] (device,
- * float32, caller-owned). Uses the plan's own workspace (the field batches),
- * so it must not overlap another call on the plan; a sparse plan's
- * unflagged cells are empty. Errors: RCX_E_INVALID (null arrays, n_wave
- * outside [1, max_wave], n_rays <= 0, zero or non-finite direction). */
-int32_t rcx_emergent(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta, double wx, double wz,
-                     int32_t n_rays, float* I, hipStream_t stream);
-
 /* Sparse atmosphere atm of the batch (Sec. 3.5): its plan flags the cells
  * as rcx_plan_set_active_host does (NULL = dense again); the batched solve
  * then marches only its flagged probes' rays, empties its unflagged cells
@@ -223,8 +241,13 @@ int32_t rcx_batch_set_graph(rcx_batch* b, int32_t enable);
 /* chi_host[a], eta_host[a], J_host[a]: host arrays of n_atm device pointers
  * to [n_wave[a]][nz][nx] float32, as for rcx_formal_solve; the pointers are
  * recorded in the graph and must stay valid while they are in use.
- * Synchronises the stream. Errors: RCX_E_INVALID (null arguments);
- * RCX_E_HIP. */
+ * Enqueues on the stream without synchronising when the pointers are those
+ * of the previous call (a replay of the captured graph); new pointers first
+ * synchronise the stream (the work list and the graph that a solve still in
+ * flight reads are then rebuilt). rcx_batch_set_order, _set_graph,
+ * _set_active_host and _destroy wait for the device to finish. With
+ * RCX_FLAG_CHECK_INPUT every call checks chi and eta first (synchronising).
+ * Errors: RCX_E_INVALID (null arguments); RCX_E_NONFINITE; RCX_E_HIP. */
 int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
                         float* const* J_host, hipStream_t stream);
 /* Work summed over atmospheres and wavelengths (rcx_work semantics). */
@@ -284,9 +307,11 @@ typedef struct rcx_nlte rcx_nlte;
  * ordered as described above) and dnu_host[n_wave] (frequency quadrature
  * weights of the rate integrals, Hz). All host arrays are copied.
  * p->storage = RCX_STORE_F16_SCALED stores cascades >= 1 of every
- * formal solution as FP16 with a per-wavelength power-of-two scale from the
- * largest source function of that wavelength (lines: S_line; continua:
- * eta/chi); cascade 0, the rates and the rate matrix stay FP32/FP64.
+ * formal solution as the 16-bit codes of RCX_STORE_F16_SCALED, the exponent
+ * offset of each wavelength from its largest source function (lines:
+ * S_line; continua: eta/chi); cascade 0, the rates and the rate matrix stay
+ * FP32/FP64.
+ * p: c0_dirs = 4, n_incl = 1, flags 0 or RCX_FLAG_CHECK_INPUT.
  * Errors: RCX_E_INVALID (nulls, sizes, ungrouped or out-of-range
  * transitions, a wavelength outside its continuum's edge);
  * RCX_E_UNSUPPORTED (more levels/lines/continua than the maxima);
@@ -301,7 +326,10 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
  * on the device in FP64 the Saha-Boltzmann populations, collisional rates,
  * thermal widths and damping, and fills the Voigt table H(a, x) in FP64
  * (Fourier-integral form of the Voigt function, Gauss-Legendre panels) for
- * the damping range present. Synchronises the stream once (damping range). */
+ * the damping range present. Synchronises the stream once (damping range).
+ * With RCX_FLAG_CHECK_INPUT (given to rcx_nlte_create) T, ne and ntot must
+ * be finite and positive and vel finite, else RCX_E_NONFINITE and nothing
+ * changes. */
 int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, const double* ntot,
                                 const float* vel, hipStream_t stream);
 
@@ -499,6 +527,17 @@ int32_t rcx_nlte_features(rcx_nlte* s, const double* pops, const float* norm_hos
  * norm_host[2][n_levels] (NULL: none). Synchronises. */
 int32_t rcx_nlte_log_departures(rcx_nlte* s, const double* pops, const float* norm_host, float* out,
                                 hipStream_t stream);
+/* Populations from a prediction of the warm start's targets:
+ * y [nz*nx][n_levels] (device FP32, standardised log10 departure
+ * coefficients), targ_norm_host[2][n_levels] = {means, stds} (host, stds
+ * positive); pops_out [n_levels][nz][nx] (device FP64) receives
+ * n_l = ntot b_l n_l^LTE / sum_m b_m n_m^LTE, log10 b_l = y_l std_l + mean_l
+ * (exponents above 30 are clamped), n^LTE the Saha-Boltzmann populations at
+ * the solver's current n_e. The last step of rcx_nlte_warm_start.
+ * Synchronises. RCX_E_INVALID for null arguments, non-finite norms or
+ * non-positive stds, or before rcx_nlte_set_atmosphere. */
+int32_t rcx_nlte_pops_from_prediction(rcx_nlte* s, const float* y, const float* targ_norm_host, double* pops_out,
+                                      hipStream_t stream);
 /* Learned warm start: LTE populations, one formal solution, features,
  * network inference, and populations n_l = ntot b_l n_l^LTE / sum_m b_m n_m^LTE
  * with log10 b the de-standardised prediction (targ_norm_host[2][n_levels]);

@@ -89,7 +89,7 @@ def _bind():
         L.ora_voigt_H_vec.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.ora_voigt_H_vec.restype = None
         L.ora_nlte_formal_solve.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_void_p, C.c_void_p,
-                                            C.c_void_p, C.c_int32]
+                                            C.c_void_p, C.c_void_p, C.c_int32]
         L.ora_nlte_formal_solve.restype = C.c_int32
         L.ora_nlte_local.argtypes = [C.c_void_p, C.POINTER(NlteFields), C.c_void_p, C.c_void_p]
         L.ora_nlte_local.restype = None
@@ -256,20 +256,24 @@ class Problem:
         Uji = 2.0 * H_PLANCK * tr.nu0 ** 3 / C_LIGHT ** 2 * Vji
         return tr, Vij, Vji, Uji
 
-    def fields(self, pops):
-        """Opacity fields for the formal solve at populations pops [levels][cells]."""
-        nw = len(self.nu)
+    def fields(self, pops, lams=None):
+        """Opacity fields for the formal solve at populations pops [levels][cells]:
+        continuum chi, eta [wavelengths][cells] of the wavelength indices lams
+        (all if None), and the line opacity and emissivity per unit profile
+        [lines][cells]."""
+        lams = np.arange(len(self.nu)) if lams is None else np.asarray(lams)
+        nw = len(lams)
         chi_c = np.zeros((nw, self.ncell))
         eta_c = np.zeros((nw, self.ncell))
         nl = len(self.atom.lines)
         kappa = np.zeros((nl, self.ncell))
         eps = np.zeros((nl, self.ncell))
-        for lam in range(nw):
+        for q, lam in enumerate(lams):
             tr = self.atom.trans[self.trans_of[lam]]
             if tr.kind == "cont":
                 _, Vic, Vci, Uci = self.cont_coeffs(lam)
-                chi_c[lam] = pops[tr.i] * Vic - pops[tr.j] * Vci
-                eta_c[lam] = pops[tr.j] * Uci
+                chi_c[q] = pops[tr.i] * Vic - pops[tr.j] * Vci
+                eta_c[q] = pops[tr.j] * Uci
         for li, tr in enumerate(self.atom.lines):
             norm = tr.sigma / (math.sqrt(math.pi) * self.dnuD[li])
             gr = self.atom.g[tr.i] / self.atom.g[tr.j]
@@ -281,28 +285,34 @@ class Problem:
                 a[:, off] = 0.0
         return chi_c, eta_c, kappa, eps
 
-    def _cfields(self, chi_c, eta_c, kappa, eps):
+    def _cfields(self, chi_c, eta_c, kappa, eps, lams=None):
+        lams = np.arange(len(self.nu)) if lams is None else np.asarray(lams)
         keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
-                (self.u, chi_c, eta_c, kappa, eps, self.adamp, 1.0 / self.vth, self.vx, self.vz)]
-        line = np.ascontiguousarray(self.line_index, dtype=np.int32)
+                (self.u[lams], chi_c, eta_c, kappa, eps, self.adamp, 1.0 / self.vth, self.vx, self.vz)]
+        line = np.ascontiguousarray(self.line_index[lams], dtype=np.int32)
         keep.append(line)
-        f = NlteFields(self.nx, self.nz, len(self.nu), len(self.atom.lines), line.ctypes.data,
+        f = NlteFields(self.nx, self.nz, len(lams), len(self.atom.lines), line.ctypes.data,
                        *[k.ctypes.data for k in keep[:9]])
         return f, keep
 
-    def formal_solve(self, pops):
+    def formal_solve(self, pops, lams=None, need=None):
         """J [n_wave][cells] and merged cascade-0 radiance I0 [n_wave][cells][N_0],
         plus the local directional opacity chi [n_wave][cells][N_0] and line
-        profile H at each cell."""
-        chi_c, eta_c, kappa, eps = self.fields(pops)
-        f, keep = self._cfields(chi_c, eta_c, kappa, eps)
-        nw = len(self.nu)
+        profile H at each cell. lams: wavelength indices to solve (all if
+        None; the outputs then cover those only); need: [cells] mask of the
+        cells whose J is wanted (only their dependency cone is solved, the
+        other cells' J and I0 are 0)."""
+        lams = np.arange(len(self.nu)) if lams is None else np.asarray(lams)
+        chi_c, eta_c, kappa, eps = self.fields(pops, lams)
+        f, keep = self._cfields(chi_c, eta_c, kappa, eps, lams)
+        nw = len(lams)
         J = np.zeros((nw, self.ncell))
         I0 = np.zeros((nw, self.ncell, self.n0))
         st = np.zeros(3, np.int64)
         L = _bind()
-        rc = L.ora_nlte_formal_solve(C.byref(self.geom), C.byref(f), J.ctypes.data, I0.ctypes.data,
-                                     st.ctypes.data, 0)
+        nm = None if need is None else np.ascontiguousarray(np.asarray(need).reshape(-1), dtype=np.uint8)
+        rc = L.ora_nlte_formal_solve(C.byref(self.geom), C.byref(f), None if nm is None else nm.ctypes.data,
+                                     J.ctypes.data, I0.ctypes.data, st.ctypes.data, 0)
         if rc != 0:
             raise RuntimeError("ora_nlte_formal_solve failed")
         chi_loc = np.zeros((nw, self.ncell, self.n0))
@@ -351,6 +361,34 @@ class Problem:
             Rdn[t] += self.W[lam] * w * np.sum(Vji * Ieff + Uji * (1.0 - chi_t * psi), axis=1)
         return Rup, Rdn
 
+    def rate_magnitudes(self, pops, I0, chi_loc, H_loc):
+        """The sums of ``rates`` with every term replaced by its magnitude,
+        sum W w |V_ij| (|I| + |Psi* eta_t|) and
+        sum W w [|V_ji| (|I| + |Psi* eta_t|) + |U_ji| (1 + |chi_t Psi*|)]: the
+        scale against which rounding in the rate sums is measured (the
+        preconditioned sums cancel where a cell is optically thick)."""
+        nt = len(self.atom.trans)
+        Aup = np.zeros((nt, self.ncell))
+        Adn = np.zeros((nt, self.ncell))
+        w = 1.0 / self.n0
+        for lam in range(len(self.nu)):
+            t = self.trans_of[lam]
+            tr = self.atom.trans[t]
+            chi = chi_loc[lam]
+            with np.errstate(invalid="ignore", divide="ignore"):
+                psi = np.where(chi > 0, -np.expm1(-chi * self.ell[None, :]) / chi, self.ell[None, :])
+            if tr.kind == "line":
+                _, Vij, Vji, Uji = self.line_coeffs(lam, H_loc[lam])
+            else:
+                _, Vic, Vci, Uci = self.cont_coeffs(lam)
+                Vij, Vji, Uji = Vic[:, None], Vci[:, None], Uci[:, None]
+            eta_t = pops[tr.j][:, None] * Uji
+            chi_t = pops[tr.i][:, None] * Vij - pops[tr.j][:, None] * Vji
+            mag = np.abs(I0[lam]) + np.abs(psi * eta_t)
+            Aup[t] += self.W[lam] * w * np.sum(np.abs(Vij) * mag, axis=1)
+            Adn[t] += self.W[lam] * w * np.sum(np.abs(Vji) * mag + np.abs(Uji) * (1.0 + np.abs(chi_t * psi)), axis=1)
+        return Aup, Adn
+
     def gamma(self, Rup, Rdn):
         """Rate matrix [cells][levels][levels]: Gamma[j][i] = rate i -> j
         (i != j), diagonal = minus the column sum (conservation)."""
@@ -362,6 +400,25 @@ class Problem:
         for l in range(nlv):
             G[:, l, l] = -(G.sum(axis=1)[:, l] - G[:, l, l])
         return G
+
+    def at_cells(self, idx):
+        """The cell-local part of the problem restricted to the cells idx
+        (the rates, the rate matrix and the equilibrium solve of those cells
+        only; no formal solve on the result)."""
+        import copy
+        idx = np.asarray(idx)
+        P = copy.copy(self)
+        P.ncell = len(idx)
+        for name in ("T", "ne", "ntot", "vx", "vz", "vth"):
+            setattr(P, name, getattr(self, name)[idx].copy())
+        P.lte = self.lte[:, idx].copy()
+        P.Cdown = self.Cdown[:, idx].copy()
+        P.Cup = self.Cup[:, idx].copy()
+        P.dnuD = [d[idx].copy() for d in self.dnuD]
+        P.adamp = self.adamp[:, idx].copy()
+        P.active = None if self.active is None else self.active[idx].copy()
+        P.geom = None
+        return P
 
     def with_ne(self, ne, ntot=None):
         """A copy of the problem at electron density ne (and hydrogen

@@ -113,9 +113,11 @@ static void nlte_opac(const void* ctx, int32_t lam, int32_t x, int32_t z, double
 }
 
 /* Formal solve with direction-dependent line opacity. Outputs J and the
- * merged cascade-0 radiance per direction, I0[n_wave][nz][nx][N_0]. */
-int32_t ora_nlte_formal_solve(const ora_geom* g, const ora_nlte_fields* f, double* J, double* I0,
-                              int64_t* stats, int32_t n_threads)
+ * merged cascade-0 radiance per direction, I0[n_wave][nz][nx][N_0].
+ * need_c0 (nullable): [nz][nx] mask of the cells whose J is wanted; only
+ * their dependency cone is solved (J and I0 elsewhere are left 0). */
+int32_t ora_nlte_formal_solve(const ora_geom* g, const ora_nlte_fields* f, const uint8_t* need_c0, double* J,
+                              double* I0, int64_t* stats, int32_t n_threads)
 {
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -123,7 +125,7 @@ int32_t ora_nlte_formal_solve(const ora_geom* g, const ora_nlte_fields* f, doubl
     (void)n_threads;
 #endif
     if (!wei_ready) wei_init();
-    return ora_rc_solve(g, f->n_wave, nlte_opac, f, NULL, J, I0, stats);
+    return ora_rc_solve(g, f->n_wave, nlte_opac, f, need_c0, J, I0, stats);
 }
 
 /* Emergent intensity through the non-LTE fields (Sec. 3.9): the beam of

@@ -46,8 +46,7 @@ struct Task {
     uint32_t fb_bytes;
     const void* up;
     void* out;
-    const float* scale_b;
-    const float* inv_scale_b;
+    const int32_t* ebias_b;
     float* J;
     int32_t lam0, n_valid;
     int64_t ncell;
@@ -100,13 +99,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_gen(const Task* __restrict__ t
         op.fb_bytes = T.fb_bytes;
         op.init(c.l);
         if (F16) {
-            march::UpF16 up{(const __half*)T.up, T.inv_scale_b, 0.0f};
+            march::UpF16 up{(const uint16_t*)T.up, T.ebias_b};
             up.init(c.l);
             if (T.level == 0) {
                 march::JEpi epi{T.J, T.lam0, T.n_valid, T.ncell};
                 march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
             } else {
-                march::StoreF16Epi epi{(__half*)T.out, T.scale_b, 0.0f};
+                march::StoreF16Epi epi{(uint16_t*)T.out, T.ebias_b};
                 epi.init(c.l);
                 march::march_ray(L, T.nx, T.nz, op, epi, T.dirs, up, seg[c.w], nullptr, c, ray, u, v, k, active);
             }
@@ -136,7 +135,7 @@ struct rcx_batch {
     std::vector<int32_t> n_wave, n_batch;
     std::vector<float2*> F;        // per atmosphere [n_batch][ncell][16]
     std::vector<unsigned int*> smax;
-    std::vector<float*> scale, inv_scale;
+    std::vector<int32_t*> ebias;
     std::vector<void*> casc;          // per (atmosphere, slot): 2 buffers back to back
     std::vector<size_t> casc_half;     // bytes of one of the two buffers
     std::vector<int32_t> casc_index;   // first slot of atmosphere a
@@ -154,6 +153,8 @@ struct rcx_batch {
     hipStream_t cap = nullptr;  // capture stream (the legacy default stream cannot be captured)
     hipGraphExec_t gexec = nullptr;
     std::vector<const float*> g_chi, g_eta;
+    unsigned int* flag = nullptr;  // input check (RCX_FLAG_CHECK_INPUT)
+    bool check_input = false;
     std::vector<void*> allocs;
 };
 
@@ -206,8 +207,7 @@ bool build_work(rcx_batch* s, float* const* J)
                 T.fb_bytes = (uint32_t)(ncell * kLB * sizeof(float2));
                 T.up = T.L.has_up ? up : nullptr;
                 T.out = bufs[cur];
-                T.scale_b = s->f16 ? s->scale[a] + b * kLB : nullptr;
-                T.inv_scale_b = s->f16 ? s->inv_scale[a] + b * kLB : nullptr;
+                T.ebias_b = s->f16 ? s->ebias[a] + b * kLB : nullptr;
                 T.J = J ? J[a] : nullptr;
                 T.lam0 = b * kLB;
                 T.n_valid = std::min(kLB, s->n_wave[a] - b * kLB);
@@ -313,7 +313,7 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
         const int64_t ncell = (int64_t)P->grid.nx * P->grid.nz;
         hipError_t e = launch_prep(chi[a], eta[a], s->F[a], s->n_wave[a], ncell, (float)P->grid.voxel_scale,
                                    s->f16 ? s->smax[a] : nullptr, st);
-        if (e == hipSuccess && s->f16) e = launch_scales(s->n_batch[a] * kLB, s->smax[a], s->scale[a], s->inv_scale[a], st);
+        if (e == hipSuccess && s->f16) e = launch_ebias(s->n_batch[a] * kLB, s->smax[a], s->ebias[a], st);
         // sparse atmosphere: unflagged cells transparent and empty
         if (e == hipSuccess && P->mask_dev) e = launch_mask_fields(s->F[a], P->mask_dev, ncell, s->n_batch[a], st);
         if (e != hipSuccess) return e;
@@ -339,9 +339,14 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
     return hipSuccess;
 }
 
+// Solves run asynchronously: before the work list, the graph or a plan's
+// lists change, the device must have finished any solve still reading them.
 void drop_graph(rcx_batch* s)
 {
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->gexec) {
+        (void)hipDeviceSynchronize();
+        (void)hipGraphExecDestroy(s->gexec);
+    }
     s->gexec = nullptr;
 }
 
@@ -357,11 +362,13 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
     if (p->c0_dirs != 4) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: the fused J epilogue needs c0_dirs = 4");
     if (p->n_cascades != 0) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: cascades are chosen per atmosphere");
     if (p->n_incl != 1) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: flatland only (n_incl = 1)");
-    if (p->flags != 0) return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: no flags (basic merge only)");
+    if ((p->flags & ~RCX_FLAG_CHECK_INPUT) != 0)
+        return bfail(RCX_E_UNSUPPORTED, "rcx_batch_create: only RCX_FLAG_CHECK_INPUT (basic merge only)");
     rcx_batch* s = new (std::nothrow) rcx_batch();
     if (!s) return bfail(RCX_E_NOMEM, "rcx_batch_create: host allocation");
     s->n_atm = n_atm;
     s->f16 = p->storage == RCX_STORE_F16_SCALED;
+    s->check_input = (p->flags & RCX_FLAG_CHECK_INPUT) != 0;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) {
         if (r != hipSuccess && e == hipSuccess) e = r;
@@ -392,13 +399,11 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
         chk(balloc(s, &F, sizeof(float2) * ncell * nb * kLB));
         s->F.push_back(F);
         unsigned int* sm = nullptr;
-        float *sc = nullptr, *isc = nullptr;
+        int32_t* eb = nullptr;
         chk(balloc(s, &sm, sizeof(unsigned int) * nb * kLB));
-        chk(balloc(s, &sc, sizeof(float) * nb * kLB));
-        chk(balloc(s, &isc, sizeof(float) * nb * kLB));
+        chk(balloc(s, &eb, sizeof(int32_t) * nb * kLB));
         s->smax.push_back(sm);
-        s->scale.push_back(sc);
-        s->inv_scale.push_back(isc);
+        s->ebias.push_back(eb);
         int64_t max_entries = 0;
         for (const auto& L : P->levels) max_entries = std::max<int64_t>(max_entries, (int64_t)L.px * L.pz * L.nd);
         s->casc_index.push_back((int32_t)s->casc.size());
@@ -413,6 +418,7 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
         }
         if (e != hipSuccess) break;
     }
+    if (s->check_input) chk(balloc(s, &s->flag, sizeof(unsigned int)));
     chk(hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking));
     if (e != hipSuccess) {
         rcx_batch_destroy(s);
@@ -426,7 +432,7 @@ int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes)
 {
     if (!s || tile_probes < 0 || tile_probes > 64) return bfail(RCX_E_INVALID, "rcx_batch_set_order: bad argument");
     s->tile_probes = tile_probes;
-    s->J_bound.clear();  // rebuild the task list on the next solve
+    s->J_bound.clear();  // rebuild the task list on the next solve (after the stream has finished)
     drop_graph(s);
     return RCX_OK;
 }
@@ -434,6 +440,7 @@ int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes)
 int32_t rcx_batch_set_active_host(rcx_batch* s, int32_t atm, const uint8_t* active_host)
 {
     if (!s || atm < 0 || atm >= s->n_atm) return bfail(RCX_E_INVALID, "rcx_batch_set_active_host: bad argument");
+    RCX_HIP_TRY(hipDeviceSynchronize());  // a solve in flight reads the plan's lists
     const int32_t rc = rcx_plan_set_active_host(s->plans[atm], active_host, nullptr);
     s->J_bound.clear();  // ray counts changed: rebuild the task list on the next solve
     drop_graph(s);
@@ -454,8 +461,26 @@ int32_t rcx_batch_solve(rcx_batch* s, const float* const* chi_host, const float*
     if (!s || !chi_host || !eta_host || !J_host) return bfail(RCX_E_INVALID, "rcx_batch_solve: null argument");
     for (int32_t a = 0; a < s->n_atm; ++a)
         if (!chi_host[a] || !eta_host[a] || !J_host[a]) return bfail(RCX_E_INVALID, "rcx_batch_solve: null array");
+    if (s->check_input) {
+        // every atmosphere's chi and eta finite and non-negative (synchronises)
+        RCX_HIP_TRY(launch_zero_flag(s->flag, st));
+        for (int32_t a = 0; a < s->n_atm; ++a) {
+            const int64_t n = (int64_t)s->n_wave[a] * s->plans[a]->grid.nx * s->plans[a]->grid.nz;
+            RCX_HIP_TRY(launch_check_f32(chi_host[a], n, kCheckNonNegative, s->flag, st));
+            RCX_HIP_TRY(launch_check_f32(eta_host[a], n, kCheckNonNegative, s->flag, st));
+        }
+        const int32_t rc = check_flag_result(s->flag, "rcx_batch_solve: chi or eta", st);
+        if (rc != RCX_OK) return rc;
+    }
     const bool same_J = (int32_t)s->J_bound.size() == s->n_atm &&
                         std::equal(s->J_bound.begin(), s->J_bound.end(), J_host);
+    const bool same_in = s->gexec && std::equal(s->g_chi.begin(), s->g_chi.end(), chi_host) &&
+                         std::equal(s->g_eta.begin(), s->g_eta.end(), eta_host);
+    if (!same_J || (s->use_graph && !same_in)) {
+        // the work list or the graph changes: a solve still in flight reads
+        // them, so it must end first
+        RCX_HIP_TRY(hipStreamSynchronize(st));
+    }
     if (!same_J) {
         if (!build_work(s, J_host)) return bfail(RCX_E_INVALID, "rcx_batch_solve: internal: work queue out of order");
         RCX_HIP_TRY(upload_work(s));
@@ -463,9 +488,7 @@ int32_t rcx_batch_solve(rcx_batch* s, const float* const* chi_host, const float*
         drop_graph(s);
     }
     if (s->use_graph) {
-        const bool same_in = s->gexec && std::equal(s->g_chi.begin(), s->g_chi.end(), chi_host) &&
-                             std::equal(s->g_eta.begin(), s->g_eta.end(), eta_host);
-        if (!same_in) {
+        if (!s->gexec || !same_in) {
             drop_graph(s);
             hipGraph_t g = nullptr;
             RCX_HIP_TRY(hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal));
@@ -486,7 +509,6 @@ int32_t rcx_batch_solve(rcx_batch* s, const float* const* chi_host, const float*
     } else {
         RCX_HIP_TRY(enqueue(s, chi_host, eta_host, st));
     }
-    RCX_HIP_TRY(hipStreamSynchronize(st));
     return RCX_OK;
 }
 
@@ -543,9 +565,11 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
         if (rc != RCX_OK) return rc;
         rc = rcx_batch_solve(s, chi, eta, J, st);  // warm-up and work-list build
         if (rc != RCX_OK) return rc;
+        RCX_HIP_TRY(hipStreamSynchronize(st));
         const auto t0 = std::chrono::steady_clock::now();
         rc = rcx_batch_solve(s, chi, eta, J, st);
         if (rc != RCX_OK) return rc;
+        RCX_HIP_TRY(hipStreamSynchronize(st));
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         if (ms < best_ms) {
             best_ms = ms;

@@ -67,6 +67,16 @@ extern "C" int32_t rcx_emergent(rcx_plan* p, int32_t n_wave, const float* chi, c
     // the field batches at the start of the plan's own workspace (sized for
     // max_wave wavelengths)
     float2* F = (float2*)p->ws_own;
+    if (p->prm.flags & RCX_FLAG_CHECK_INPUT) {
+        // the flag word after the field batches of n_wave wavelengths (the
+        // workspace holds at least that much)
+        unsigned int* flag = (unsigned int*)((char*)p->ws_own + sizeof(float2) * (size_t)ncell * n_batch * kLB);
+        RCX_HIP_TRY(launch_zero_flag(flag, st));
+        RCX_HIP_TRY(launch_check_f32(chi, (int64_t)n_wave * ncell, kCheckNonNegative, flag, st));
+        RCX_HIP_TRY(launch_check_f32(eta, (int64_t)n_wave * ncell, kCheckNonNegative, flag, st));
+        const int32_t rc = check_flag_result(flag, "rcx_emergent: chi or eta", st);
+        if (rc != RCX_OK) return rc;
+    }
     RCX_HIP_TRY(launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, nullptr, st));
     if (p->mask_dev) RCX_HIP_TRY(launch_mask_fields(F, p->mask_dev, ncell, n_batch, st));
     // beam: centred on the domain, starting outside it on the observer's

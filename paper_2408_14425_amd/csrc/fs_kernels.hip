@@ -78,19 +78,33 @@ __global__ __launch_bounds__(256) void k_prep(const float* __restrict__ chi,
     }
 }
 
-// Per-wavelength storage scale 2^(15 - e) with max S < 2^e, so every stored
-// value (bounded by max S) stays below 2^15 in FP16.
-__global__ void k_scales(int32_t n, const unsigned int* __restrict__ smax_bits, float* __restrict__ scale,
-                         float* __restrict__ inv_scale)
+// Per-wavelength exponent bias of the 16-bit cascade storage: the FP32
+// exponent field of max S less 62, so the codes cover 2 max S downwards
+// (march_rows.h, enc_h16). max S is non-negative and finite.
+__global__ void k_ebias(int32_t n, const unsigned int* __restrict__ smax_bits, int32_t* __restrict__ ebias)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float m = __uint_as_float(smax_bits[i]);
-    int e = 0;
-    if (m > 0.0f && m < 3.0e38f) (void)frexpf(m, &e);
-    const int sh = min(max(15 - e, -126), 126);
-    scale[i] = ldexpf(1.0f, sh);
-    inv_scale[i] = ldexpf(1.0f, -sh);
+    ebias[i] = (int32_t)((smax_bits[i] & 0x7FFFFFFFu) >> 23) - 62;
+}
+
+// Input check (RCX_FLAG_CHECK_INPUT): *flag |= 1 if a value is not finite,
+// 2 if a finite value is out of range: below 0 (range kNonNegative), not
+// above 0 (kPositive), never (kFinite). One atomic per wavefront.
+template <class T>
+__global__ void k_check_values(const T* __restrict__ a, int64_t n, int32_t range, unsigned int* __restrict__ flag)
+{
+    unsigned int bits = 0u;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T v = a[i];
+        if (!isfinite(v))
+            bits |= 1u;
+        else if ((range == kCheckNonNegative && v < T(0)) || (range == kCheckPositive && !(v > T(0))))
+            bits |= 2u;
+    }
+    const unsigned int any1 = __ballot(bits & 1u) != 0ull ? 1u : 0u;
+    const unsigned int any2 = __ballot(bits & 2u) != 0ull ? 2u : 0u;
+    if ((threadIdx.x & 63) == 0 && (any1 | any2)) atomicOr(flag, any1 | any2);
 }
 
 __global__ void k_fill_u32(unsigned int* p, int32_t n, unsigned int v)
@@ -181,9 +195,31 @@ hipError_t launch_prep(const float* chi, const float* eta, float2* F, int32_t n_
     return hipGetLastError();
 }
 
-hipError_t launch_scales(int32_t n, const unsigned int* smax_bits, float* scale, float* inv_scale, hipStream_t st)
+hipError_t launch_zero_flag(unsigned int* flag, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scales, dim3((n + 255) / 256), dim3(256), 0, st, n, smax_bits, scale, inv_scale);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, flag, 1, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_f32(const float* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_check_values<float>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, a, n,
+                       range, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_f64(const double* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st)
+{
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_check_values<double>, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, a, n,
+                       range, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_ebias(int32_t n, const unsigned int* smax_bits, int32_t* ebias, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ebias, dim3((n + 255) / 256), dim3(256), 0, st, n, smax_bits, ebias);
     return hipGetLastError();
 }
 
@@ -208,7 +244,7 @@ hipError_t launch_fs_up(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op
         up.stride = io.slot_stride;
         return launch_fs(L, nx, nz, op, epi, dirs, up, st);
     }
-    march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+    march::UpF16 up{(const uint16_t*)io.up, io.ebias_b};
     up.stride = io.slot_stride;
     return launch_fs(L, nx, nz, op, epi, dirs, up, st);
 }
@@ -241,14 +277,14 @@ hipError_t launch_march_fix(const LevelDesc& L, int32_t nx, int32_t nz, const fl
             if (!io.out_f16)
                 return launch_fix_k(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, up, st);
             return launch_fix_k(L, nx, nz, op,
-                                march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f}, dirs,
+                                march::StoreF16Epi2{(uint16_t*)io.out, io.slot_stride, io.ebias_b}, dirs,
                                 up, st);
         }
-        march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+        march::UpF16 up{(const uint16_t*)io.up, io.ebias_b};
         up.stride = io.slot_stride;
         if (!io.out_f16)
             return launch_fix_k(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, up, st);
-        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f},
+        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi2{(uint16_t*)io.out, io.slot_stride, io.ebias_b},
                             dirs, up, st);
     }
     march::FieldOp op{};
@@ -257,11 +293,11 @@ hipError_t launch_march_fix(const LevelDesc& L, int32_t nx, int32_t nz, const fl
     if (!io.up_f16) {
         const march::UpF32 up{(const float*)io.up};
         if (!io.out_f16) return launch_fix_k(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
-        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
+        return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(uint16_t*)io.out, io.ebias_b}, dirs, up, st);
     }
-    march::UpF16 up{(const __half*)io.up, io.inv_scale_b, 0.0f};
+    march::UpF16 up{(const uint16_t*)io.up, io.ebias_b};
     if (!io.out_f16) return launch_fix_k(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, up, st);
-    return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, up, st);
+    return launch_fix_k(L, nx, nz, op, march::StoreF16Epi{(uint16_t*)io.out, io.ebias_b}, dirs, up, st);
 }
 
 hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,
@@ -273,14 +309,14 @@ hipError_t launch_march_merge(const LevelDesc& L, int32_t nx, int32_t nz, const 
         op.Fb = Fb;
         op.fb_bytes = fb_bytes;
         if (!io.out_f16) return launch_fs_up(L, nx, nz, op, march::StoreEpi2{(float*)io.out, io.slot_stride}, dirs, io, st);
-        return launch_fs_up(L, nx, nz, op, march::StoreF16Epi2{(__half*)io.out, io.slot_stride, io.scale_b, 0.0f, 0.0f},
+        return launch_fs_up(L, nx, nz, op, march::StoreF16Epi2{(uint16_t*)io.out, io.slot_stride, io.ebias_b},
                             dirs, io, st);
     }
     march::FieldOp op{};
     op.Fb = Fb;
     op.fb_bytes = fb_bytes;
     if (!io.out_f16) return launch_fs_up(L, nx, nz, op, march::StoreEpi{(float*)io.out}, dirs, io, st);
-    return launch_fs_up(L, nx, nz, op, march::StoreF16Epi{(__half*)io.out, io.scale_b, 0.0f}, dirs, io, st);
+    return launch_fs_up(L, nx, nz, op, march::StoreF16Epi{(uint16_t*)io.out, io.ebias_b}, dirs, io, st);
 }
 
 hipError_t launch_march_merge_j(const LevelDesc& L, int32_t nx, int32_t nz, const float2* Fb, const double4* dirs,

@@ -16,8 +16,6 @@
 //   Itilde = I + T * sum_taps w_x w_z (1/4) sum_j Itilde_up(tap, 4k + j).
 #pragma once
 
-#include <hip/hip_fp16.h>
-
 #include "rcx_internal.h"
 
 namespace rcx {
@@ -72,10 +70,30 @@ struct RayInfo {
     bool active;
 };
 
-// Readers of the merged cascade above: FP32, or FP16 with a per-wavelength
-// power-of-two scale (value = stored * inv_scale). Slot w = 1 (a second
-// wavelength batch marched by the same lanes) lies `stride` elements after
-// slot 0, with the next batch's scales.
+// 16-bit cascade storage (RCX_STORE_F16_SCALED) of a non-negative
+// radiance: FP32 rounded to FP16's 10-bit significand (to nearest, ties to
+// even), its 8-bit exponent E rebased by the wavelength's bias eb into 6
+// bits, code = (E - eb) 2^10 + significand. FP16's sign bit is spent on
+// range (radiances are never negative): with eb = E(max S) - 62 the codes
+// cover the 63 binades below 2^(E(max S) + 2 - 127) > 2 max S, every value
+// there with FP16's relative rounding 2^-11; code 0 is 0, and values more
+// than ~2^62 below max S flush to it. eb1024 = eb * 2^10.
+__device__ __forceinline__ uint16_t enc_h16(float x, int32_t eb1024)
+{
+    const uint32_t u = __float_as_uint(x) & 0x7FFFFFFFu;
+    const int32_t r = (int32_t)((u + 0x0FFFu + ((u >> 13) & 1u)) >> 13) - eb1024;
+    return (uint16_t)min(max(r, 0), 0xFFFF);
+}
+__device__ __forceinline__ float dec_h16(uint32_t c, int32_t eb1024)
+{
+    const float v = __uint_as_float((uint32_t)((int32_t)c + eb1024) << 13);
+    return c != 0u ? v : 0.0f;
+}
+
+// Readers of the merged cascade above: FP32, or the 16-bit codes with a
+// per-wavelength exponent bias. Slot w = 1 (a second wavelength batch
+// marched by the same lanes) lies `stride` elements after slot 0, with the
+// next batch's biases.
 struct UpF32 {
     const float* p;
     int64_t stride = 0;
@@ -83,20 +101,16 @@ struct UpF32 {
     __device__ __forceinline__ float get(int64_t i, int w) const { return p[i + w * stride]; }
 };
 struct UpF16 {
-    const __half* p;
-    const float* inv_scale_b;  // [16] of this batch (then [16] of the next when stride != 0)
-    float inv;
+    const uint16_t* p;
+    const int32_t* ebias_b;  // [16] of this batch (then [16] of the next when stride != 0)
     int64_t stride = 0;
-    float inv2 = 0.0f;
+    int32_t B = 0, B2 = 0;   // the lane's biases * 2^10
     __device__ __forceinline__ void init(int l)
     {
-        inv = inv_scale_b[l];
-        if (stride != 0) inv2 = inv_scale_b[l + kLB];
+        B = ebias_b[l] * 1024;
+        if (stride != 0) B2 = ebias_b[l + kLB] * 1024;
     }
-    __device__ __forceinline__ float get(int64_t i, int w) const
-    {
-        return __half2float(p[i + w * stride]) * (w ? inv2 : inv);
-    }
+    __device__ __forceinline__ float get(int64_t i, int w) const { return dec_h16(p[i + w * stride], w ? B2 : B); }
 };
 
 // Lane state shared by the kernels that march rows of rays.
@@ -574,19 +588,19 @@ struct StoreEpi {
     }
 };
 
-// Epilogue storing FP16 with a per-wavelength power-of-two scale
-// (stored = value * scale; the scale keeps the largest source function of
-// the wavelength below 2^15, and no merged radiance exceeds it).
+// Epilogue storing the 16-bit codes with the wavelength's exponent bias
+// (enc_h16; no merged radiance exceeds the largest source function of its
+// wavelength, which sets the bias).
 struct StoreF16Epi {
-    __half* out;
-    const float* scale_b;  // [16] of this batch
-    float sc;
-    __device__ __forceinline__ void init(int l) { sc = scale_b[l]; }
+    uint16_t* out;
+    const int32_t* ebias_b;  // [16] of this batch
+    int32_t B = 0;
+    __device__ __forceinline__ void init(int l) { B = ebias_b[l] * 1024; }
     template <class Op>
     __device__ __forceinline__ void finish(const RayInfo& ri, int l, int lane, float I, const Op&)
     {
         (void)lane;
-        if (ri.active) out[ri.ray * kLB + l] = __float2half_rn(I * sc);
+        if (ri.active) out[ri.ray * kLB + l] = enc_h16(I, B);
     }
 };
 
@@ -682,7 +696,7 @@ struct FieldOp2 {
 };
 
 // Epilogues for two batches per lane: slot 1 is stored `stride` elements
-// after slot 0 (FP16 with the next batch's scales).
+// after slot 0 (16-bit codes with the next batch's biases).
 struct StoreEpi2 {
     float* out;
     int64_t stride;
@@ -697,21 +711,21 @@ struct StoreEpi2 {
     }
 };
 struct StoreF16Epi2 {
-    __half* out;
+    uint16_t* out;
     int64_t stride;
-    const float* scale_b;  // [32]: this batch's scales, then the next batch's
-    float sc0, sc1;
+    const int32_t* ebias_b;  // [32]: this batch's biases, then the next batch's
+    int32_t B0 = 0, B1 = 0;
     __device__ __forceinline__ void init(int l)
     {
-        sc0 = scale_b[l];
-        sc1 = scale_b[l + kLB];
+        B0 = ebias_b[l] * 1024;
+        B1 = ebias_b[l + kLB] * 1024;
     }
     template <class Op>
     __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int, const float (&I)[2], const Op&)
     {
         if (ri.active) {
-            out[ri.ray * kLB + l] = __float2half_rn(I[0] * sc0);
-            out[stride + ri.ray * kLB + l] = __float2half_rn(I[1] * sc1);
+            out[ri.ray * kLB + l] = enc_h16(I[0], B0);
+            out[stride + ri.ray * kLB + l] = enc_h16(I[1], B1);
         }
     }
 };

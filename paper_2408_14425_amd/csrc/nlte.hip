@@ -975,11 +975,13 @@ struct rcx_nlte {
     float* casc[2] = {nullptr, nullptr};
     bool f16 = false;                 // cascades >= 1 stored as scaled FP16
     unsigned int* smax = nullptr;     // [n_batch][16] max S (float bits)
-    float *scale = nullptr, *inv_scale = nullptr;  // [n_batch][16]
+    int32_t* ebias = nullptr;         // [n_batch][16] exponent biases of the 16-bit codes
     float2* part = nullptr;
     float* rates = nullptr;
     unsigned long long* d_max = nullptr;
     unsigned int* d_amax = nullptr;
+    unsigned int* d_check = nullptr;  // input check flag (RCX_FLAG_CHECK_INPUT)
+    bool check_input = false;
     float2* vtab = nullptr;
     float v_inv_da = 0.0f;
     float2* vtabc = nullptr;  // profile table of the line march
@@ -1134,7 +1136,8 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
         return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: atom exceeds the supported sizes");
     if (p->c0_dirs != 4) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: the rate epilogue needs c0_dirs = 4");
     if (p->n_incl != 1) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: flatland only (n_incl = 1)");
-    if (p->flags != 0) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: no flags (basic merge only)");
+    if ((p->flags & ~RCX_FLAG_CHECK_INPUT) != 0)
+        return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: only RCX_FLAG_CHECK_INPUT (basic merge only)");
     const int32_t nt = atom->n_lines + atom->n_conts;
     if (nt < 1) return nlte_fail(RCX_E_INVALID, "rcx_nlte_create: no transitions");
     for (int32_t k = 0; k < atom->n_lines; ++k)
@@ -1283,15 +1286,16 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->rates, sizeof(float) * 2 * nt * nc));
     chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
     chk(dmalloc(s, &s->d_amax, sizeof(unsigned int)));
+    chk(dmalloc(s, &s->d_check, sizeof(unsigned int)));
     chk(dmalloc(s, &s->vtab, sizeof(float2) * kNa * kNx));
     chk(dmalloc(s, &s->vtabc, sizeof(float2) * kNacMax * kNxc));
     chk(dmalloc(s, &s->u_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->dnu_all, sizeof(float) * n_wave));
     chk(dmalloc(s, &s->norms, sizeof(float) * (12 + 2 * kMaxL)));
     s->f16 = p->storage == RCX_STORE_F16_SCALED;
+    s->check_input = (p->flags & RCX_FLAG_CHECK_INPUT) != 0;
     chk(dmalloc(s, &s->smax, sizeof(unsigned int) * nb * kLB));
-    chk(dmalloc(s, &s->scale, sizeof(float) * nb * kLB));
-    chk(dmalloc(s, &s->inv_scale, sizeof(float) * nb * kLB));
+    chk(dmalloc(s, &s->ebias, sizeof(int32_t) * nb * kLB));
     if (e != hipSuccess) {
         rcx_nlte_destroy(s);
         return nlte_fail(RCX_E_NOMEM, std::string("rcx_nlte_create: hipMalloc: ") + hipGetErrorName(e));
@@ -1411,6 +1415,22 @@ int32_t rcx_nlte_set_atmosphere(rcx_nlte* s, const double* T, const double* ne, 
 {
     if (!s || !T || !ne || !ntot || !vel) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_atmosphere: null argument");
     const int64_t nc = s->ncell;
+    if (s->check_input) {
+        // T, n_e, ntot finite and positive, velocities finite (synchronises)
+        const double* pos[3] = {T, ne, ntot};
+        const char* names[3] = {"rcx_nlte_set_atmosphere: T", "rcx_nlte_set_atmosphere: ne",
+                                "rcx_nlte_set_atmosphere: ntot"};
+        for (int q = 0; q < 3; ++q) {
+            RCX_HIP_TRY(launch_zero_flag(s->d_check, st));
+            RCX_HIP_TRY(launch_check_f64(pos[q], nc, kCheckPositive, s->d_check, st));
+            const int32_t rc = check_flag_result(s->d_check, names[q], st);
+            if (rc != RCX_OK) return rc;
+        }
+        RCX_HIP_TRY(launch_zero_flag(s->d_check, st));
+        RCX_HIP_TRY(launch_check_f32(vel, 2 * nc, kCheckFinite, s->d_check, st));
+        const int32_t rc = check_flag_result(s->d_check, "rcx_nlte_set_atmosphere: vel", st);
+        if (rc != RCX_OK) return rc;
+    }
     RCX_HIP_TRY(hipMemcpyAsync(s->T, T, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     RCX_HIP_TRY(hipMemcpyAsync(s->ntot, ntot, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
     RCX_HIP_TRY(hipMemcpyAsync(s->ne_copy, ne, sizeof(double) * nc, hipMemcpyDeviceToDevice, st));
@@ -1505,7 +1525,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             RCX_HIP_TRY(hipGetLastError());
         }
     }
-    if (s->f16) RCX_HIP_TRY(launch_scales(nb * kLB, s->smax, s->scale, s->inv_scale, st));
+    if (s->f16) RCX_HIP_TRY(launch_ebias(nb * kLB, s->smax, s->ebias, st));
     for (int32_t b = 0; b < nb; ++b) {
         const auto& B = s->batches[b];
         const Trans& tr = A.t[B.trans];
@@ -1535,8 +1555,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         re.ell_cells = (float)std::sqrt(0.5);
         re.voxel = (float)s->voxel;
         re.kind = tr.kind;
-        const float* sc_b = s->scale + (size_t)b * kLB;
-        const float* isc_b = s->inv_scale + (size_t)b * kLB;
+        const int32_t* eb_b = s->ebias + (size_t)b * kLB;
         int cur = 0;
         const void* up = nullptr;
         for (int32_t i = P->n_casc - 1; i >= 0; --i) {
@@ -1548,9 +1567,9 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             hipError_t e;
             if (s->f16) {
                 // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
-                const march::UpF16 u16{(const __half*)upl, isc_b, 0.0f};
+                const march::UpF16 u16{(const uint16_t*)upl, eb_b};
                 if (i > 0) {
-                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, march::StoreF16Epi{(__half*)outb, sc_b, 0.0f},
+                    e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, march::StoreF16Epi{(uint16_t*)outb, eb_b},
                                         dirs, u16, st);
                 } else {
                     re.out = outb;
@@ -2008,6 +2027,34 @@ int32_t rcx_nlte_log_departures(rcx_nlte* s, const double* pops, const float* no
     return RCX_OK;
 }
 
+// Populations from standardised predicted targets y [ncell][n_levels] on
+// the stream (norms copied to the solver's device buffer first).
+static int32_t pops_from_prediction(rcx_nlte* s, const float* y, const float* targ_norm_host, double* pops_out,
+                                    hipStream_t st)
+{
+    const int nl = s->atom.nl;
+    RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, targ_norm_host, sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_pops_from_pred, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, y,
+                       s->norms + 12, s->lte, s->ntot, pops_out);
+    RCX_HIP_TRY(hipGetLastError());
+    // the norms buffer must not be overwritten before the kernel has read it
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_pops_from_prediction(rcx_nlte* s, const float* y, const float* targ_norm_host, double* pops_out,
+                                      hipStream_t st)
+{
+    if (!s || !y || !targ_norm_host || !pops_out)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_pops_from_prediction: null argument");
+    if (!s->atm_set) return nlte_fail(RCX_E_INVALID, "rcx_nlte_pops_from_prediction: set the atmosphere first");
+    const int nl = s->atom.nl;
+    for (int q = nl; q < 2 * nl; ++q)
+        if (!(targ_norm_host[q] > 0.0f) || !std::isfinite(targ_norm_host[q]) || !std::isfinite(targ_norm_host[q - nl]))
+            return nlte_fail(RCX_E_INVALID, "rcx_nlte_pops_from_prediction: norms must be finite, stds positive");
+    return pops_from_prediction(s, y, targ_norm_host, pops_out, st);
+}
+
 int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_host, const float* targ_norm_host,
                             double* pops_out, hipStream_t st)
 {
@@ -2024,12 +2071,7 @@ int32_t rcx_nlte_warm_start(rcx_nlte* s, rcx_mlp* net, const float* feat_norm_ho
     if (rc != RCX_OK) return rc;
     rc = rcx_mlp_forward(net, s->feat, s->pred, (int32_t)s->ncell, st);
     if (rc != RCX_OK) return rc;
-    RCX_HIP_TRY(hipMemcpyAsync(s->norms + 12, targ_norm_host, sizeof(float) * 2 * nl, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_pops_from_pred, dim3(blocks_for(s->ncell, 256)), dim3(256), 0, st, s->ncell, nl, s->pred,
-                       s->norms + 12, s->lte, s->ntot, pops_out);
-    RCX_HIP_TRY(hipGetLastError());
-    RCX_HIP_TRY(hipStreamSynchronize(st));
-    return RCX_OK;
+    return pops_from_prediction(s, s->pred, targ_norm_host, pops_out, st);
 }
 
 }  // extern "C"

@@ -62,17 +62,28 @@ int32_t hip_fail(hipError_t e, const char* what);
 // smax_bits (nullable): [n_batch * batch_width] per-wavelength max of S (float bits).
 hipError_t launch_prep(const float* chi, const float* eta, float2* F, int32_t n_wave, int64_t ncell,
                        float voxel, unsigned int* smax_bits, hipStream_t st);
-// FP16 storage scales from the per-wavelength max S.
-hipError_t launch_scales(int32_t n, const unsigned int* smax_bits, float* scale, float* inv_scale, hipStream_t st);
+// Input checks (RCX_FLAG_CHECK_INPUT): zero *flag, then OR into it 1 for a
+// non-finite value and 2 for a finite one out of the range among a[0..n).
+constexpr int32_t kCheckNonNegative = 0;  // v >= 0
+constexpr int32_t kCheckPositive = 1;     // v > 0
+constexpr int32_t kCheckFinite = 2;       // any finite v
+hipError_t launch_zero_flag(unsigned int* flag, hipStream_t st);
+hipError_t launch_check_f32(const float* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st);
+hipError_t launch_check_f64(const double* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st);
+// Read the flag back (synchronises st): RCX_OK if 0, else RCX_E_NONFINITE
+// with a message naming `what`.
+int32_t check_flag_result(const unsigned int* flag, const char* what, hipStream_t st);
+// Exponent biases of the 16-bit cascade storage from the per-wavelength
+// max S: ebias = E(max S) - 62, E the FP32 exponent field.
+hipError_t launch_ebias(int32_t n, const unsigned int* smax_bits, int32_t* ebias, hipStream_t st);
 
 // Cascade buffers of one march launch: the merged cascade above (read) and
-// this cascade (written), each FP32 or FP16-with-scale.
+// this cascade (written), each FP32 or 16-bit codes with exponent biases.
 struct CascIO {
     const void* up;
     void* out;
     bool up_f16, out_f16;
-    const float* scale_b;      // [batch_width] stored = value * scale (2 x with pairs)
-    const float* inv_scale_b;  // [batch_width] (2 x with pairs)
+    const int32_t* ebias_b;    // [batch_width] exponent biases of the 16-bit codes (2 x with pairs)
     int64_t slot_stride = 0;   // pairs of batches: elements from batch b's cascade to b+1's
 };
 // Wavelengths per batch of the field and cascade layouts.

@@ -47,6 +47,18 @@ static int32_t ok()
     return RCX_OK;
 }
 
+int32_t check_flag_result(const unsigned int* flag, const char* what, hipStream_t st)
+{
+    unsigned int h = 0u;
+    RCX_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, st));
+    RCX_HIP_TRY(hipStreamSynchronize(st));
+    if (h == 0u) return RCX_OK;
+    std::string m = std::string(what) + ":";
+    if (h & 1u) m += " a value is not finite";
+    if (h & 2u) m += (h & 1u) ? "; a value is out of range" : " a value is out of range";
+    return fail(RCX_E_NONFINITE, m);
+}
+
 }  // namespace rcx
 
 using namespace rcx;
@@ -89,7 +101,7 @@ double max_probe_corner_distance(const rcx_grid& g, const LevelDesc& L)
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct WsLayout {
-    size_t F, casc_a, casc_b, smax, scale, inv_scale, total;
+    size_t F, casc_a, casc_b, smax, ebias, flag, total;
     int64_t casc_slot;  // elements of one batch's slot in a cascade buffer
 };
 
@@ -114,9 +126,9 @@ WsLayout ws_layout(const rcx_plan* p, int32_t n_wave)
     w.casc_a = align256(sizeof(float2) * (size_t)ncell * n_batch * lb);
     w.casc_b = w.casc_a + align256(sizeof(float) * (size_t)max_entries * lb * slots);
     w.smax = w.casc_b + align256(sizeof(float) * (size_t)max_entries * lb * slots);
-    w.scale = w.smax + align256(sizeof(float) * (size_t)n_batch * lb);
-    w.inv_scale = w.scale + align256(sizeof(float) * (size_t)n_batch * lb);
-    w.total = w.inv_scale + align256(sizeof(float) * (size_t)n_batch * lb);
+    w.ebias = w.smax + align256(sizeof(float) * (size_t)n_batch * lb);
+    w.flag = w.ebias + align256(sizeof(int32_t) * (size_t)n_batch * lb);
+    w.total = w.flag + align256(sizeof(unsigned int));
     return w;
 }
 
@@ -196,8 +208,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
     float2* F = (float2*)(ws + w.F);
     float* bufs[2] = {(float*)(ws + w.casc_a), (float*)(ws + w.casc_b)};
     const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
-    float* scale = (float*)(ws + w.scale);
-    float* inv_scale = (float*)(ws + w.inv_scale);
+    int32_t* ebias = (int32_t*)(ws + w.ebias);
     const int32_t lb = batch_width();
     const int32_t n_batch = (n_wave + lb - 1) / lb;
     const bool fuse_j = p->prm.c0_dirs == 4;
@@ -224,8 +235,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                     io.up_f16 = false;
                     io.out = bufs[cur];
                     io.out_f16 = false;
-                    io.scale_b = scale + (size_t)b * lb;
-                    io.inv_scale_b = inv_scale + (size_t)b * lb;
+                    io.ebias_b = ebias + (size_t)b * lb;
                     io.slot_stride = w.casc_slot;
                     const double4* dirs = p->dirs_dev + p->dir_off[i];
                     const bool fix = i + 1 < p->n_casc;
@@ -269,8 +279,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                 io.up_f16 = up_f16;
                 io.out = bufs[cur];
                 io.out_f16 = f16 && i > 0;
-                io.scale_b = scale + (size_t)b * lb;
-                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                io.ebias_b = ebias + (size_t)b * lb;
                 const bool together = pair && L.nd <= kPairMaxDirs;
                 io.slot_stride = together ? w.casc_slot : 0;
                 const bool fix = i + 1 < p->n_casc;
@@ -286,8 +295,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                     const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
                     io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
                     io1.out = (void*)((char*)io.out + out_off);
-                    io1.scale_b = io.scale_b + lb;
-                    io1.inv_scale_b = io.inv_scale_b + lb;
+                    io1.ebias_b = io.ebias_b + lb;
                     const float2* Fb1 = Fb + (size_t)ncell * lb;
                     RCX_HIP_TRY(timed(p, i, st, [&] {
                         return fix ? launch_march_fix(L, nx, nz, Fb1, dirs, io1, st)
@@ -331,8 +339,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                 io.up_f16 = false;
                 io.out = bufs[cur];
                 io.out_f16 = false;
-                io.scale_b = scale + (size_t)b * lb;
-                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                io.ebias_b = ebias + (size_t)b * lb;
                 io.slot_stride = w.casc_slot;
                 if (i == 0 && fuse_j) {
                     RCX_HIP_TRY(timed(p, i, st, [&] {
@@ -388,8 +395,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                 io.up_f16 = up_f16;
                 io.out = bufs[cur];
                 io.out_f16 = f16 && i > 0;  // cascade 0 feeds J: kept in FP32
-                io.scale_b = scale + (size_t)b * lb;
-                io.inv_scale_b = inv_scale + (size_t)b * lb;
+                io.ebias_b = ebias + (size_t)b * lb;
                 const bool together = pair && L.nd <= kPairMaxDirs;
                 io.slot_stride = together ? w.casc_slot : 0;
                 if (i == 0 && fuse_j) {
@@ -411,8 +417,7 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
                     const size_t out_off = (size_t)w.casc_slot * (io.out_f16 ? (size_t)2 : sizeof(float));
                     io1.up = io.up ? (const void*)((const char*)io.up + up_off) : nullptr;
                     io1.out = (void*)((char*)io.out + out_off);
-                    io1.scale_b = io.scale_b + lb;
-                    io1.inv_scale_b = io.inv_scale_b + lb;
+                    io1.ebias_b = io.ebias_b + lb;
                     RCX_HIP_TRY(timed(p, i, st, [&] {
                         return launch_march_merge(L, nx, nz, Fb + (size_t)ncell * lb, p->dirs_dev + p->dir_off[i], io1,
                                                   st);
@@ -471,7 +476,8 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
         return fail(RCX_E_UNSUPPORTED, "rcx_plan_create: unknown storage");
     if (prm->n_incl < 1 || prm->n_incl > 16)
         return fail(RCX_E_INVALID, "rcx_plan_create: n_incl must be in [1, 16] (1 = flatland)");
-    if ((prm->flags & ~RCX_FLAG_BILINEAR_FIX) != 0) return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
+    if ((prm->flags & ~(RCX_FLAG_BILINEAR_FIX | RCX_FLAG_CHECK_INPUT)) != 0)
+        return fail(RCX_E_INVALID, "rcx_plan_create: unknown flags");
     int32_t n_casc = prm->n_cascades == 0 ? auto_cascades(g->nx, g->nz) : prm->n_cascades;
     if (n_casc < 1 || n_casc > 16) return fail(RCX_E_INVALID, "rcx_plan_create: n_cascades must be in [1, 16]");
     if ((int64_t)prm->c0_dirs << (2 * (n_casc - 1)) > (int64_t(1) << 26))
@@ -679,10 +685,19 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     if (p->timing) ++p->n_solves;
     const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
     unsigned int* smax = (unsigned int*)(ws + w.smax);
-    float* scale = (float*)(ws + w.scale);
-    float* inv_scale = (float*)(ws + w.inv_scale);
+    int32_t* ebias = (int32_t*)(ws + w.ebias);
     const int32_t lb = batch_width();
     const int32_t n_batch = (n_wave + lb - 1) / lb;
+    if (p->prm.flags & RCX_FLAG_CHECK_INPUT) {
+        // chi and eta finite and non-negative (synchronises the stream)
+        unsigned int* flag = (unsigned int*)(ws + w.flag);
+        const int64_t n = (int64_t)n_wave * ncell;
+        RCX_HIP_TRY(launch_zero_flag(flag, st));
+        RCX_HIP_TRY(launch_check_f32(chi, n, kCheckNonNegative, flag, st));
+        RCX_HIP_TRY(launch_check_f32(eta, n, kCheckNonNegative, flag, st));
+        const int32_t rc = check_flag_result(flag, "rcx_formal_solve: chi or eta", st);
+        if (rc != RCX_OK) return rc;
+    }
     if (p->mask_dev && p->levels[0].n_active == 0) {
         // sparse with nothing flagged: J = 0
         RCX_HIP_TRY(launch_mask_j(J, p->mask_dev, ncell, n_wave, st));
@@ -690,7 +705,7 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     }
     RCX_HIP_TRY(timed(p, -1, st, [&] {
         hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
-        if (e == hipSuccess && f16) e = launch_scales(n_batch * lb, smax, scale, inv_scale, st);
+        if (e == hipSuccess && f16) e = launch_ebias(n_batch * lb, smax, ebias, st);
         // sparse: unflagged cells transparent and empty (Sec. 3.5)
         if (e == hipSuccess && p->mask_dev) e = launch_mask_fields(F, p->mask_dev, ncell, n_batch, st);
         return e;
@@ -763,6 +778,7 @@ const char* rcx_error_string(int32_t code)
     case RCX_E_NOMEM: return "out of memory";
     case RCX_E_HIP: return "HIP runtime error";
     case RCX_E_WORKSPACE: return "workspace too small";
+    case RCX_E_NONFINITE: return "input value not finite or out of range";
     default: return "unknown status code";
     }
 }

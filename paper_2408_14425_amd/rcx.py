@@ -22,11 +22,13 @@ RCX_E_UNSUPPORTED = -2
 RCX_E_NOMEM = -3
 RCX_E_HIP = -4
 RCX_E_WORKSPACE = -5
+RCX_E_NONFINITE = -6
 RCX_T_GEOMETRIC = 0
 RCX_T_LENGTH_X4 = 1
 RCX_STORE_F32 = 0
 RCX_STORE_F16_SCALED = 1
 RCX_FLAG_BILINEAR_FIX = 1
+RCX_FLAG_CHECK_INPUT = 2
 RCX_PROFILE_AUTO = 0
 RCX_PROFILE_TABLE = 1
 
@@ -212,11 +214,11 @@ class Plan:
     def __init__(self, nx: int, nz: int, max_wave: int, voxel_scale: float = 1.0,
                  n_cascades: int = 0, c0_dirs: int = 4, c0_t1: float = 1.5,
                  t_rule: int = RCX_T_GEOMETRIC, storage: int = RCX_STORE_F32, n_incl: int = 1,
-                 bilinear_fix: bool = False):
+                 bilinear_fix: bool = False, check_input: bool = False):
         p = rcx_params_default()
         p.n_cascades, p.c0_dirs, p.c0_t1, p.t_rule, p.storage = n_cascades, c0_dirs, c0_t1, t_rule, storage
         p.n_incl = n_incl
-        p.flags = RCX_FLAG_BILINEAR_FIX if bilinear_fix else 0
+        p.flags = (RCX_FLAG_BILINEAR_FIX if bilinear_fix else 0) | (RCX_FLAG_CHECK_INPUT if check_input else 0)
         self.nx, self.nz, self.max_wave = nx, nz, max_wave
         self.handle = rcx_plan_create(rcx_grid(nx, nz, voxel_scale), p, max_wave)
 
@@ -335,7 +337,8 @@ def _load_nlte():
     L.rcx_nlte_features.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
-    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start",
+    L.rcx_nlte_pops_from_prediction.argtypes = [vp, vp, vp, vp, vp]
+    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start", "rcx_nlte_pops_from_prediction",
               "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_emergent", "rcx_nlte_set_pressure_conservation",
               "rcx_nlte_collisional_ne", "rcx_nlte_set_temperature_cut"):
         getattr(L, n).restype = i32
@@ -434,11 +437,12 @@ class Nlte:
     ``workloads.NlteInput``); arrays live on ``cuda:0``."""
 
     def __init__(self, inp, n_cascades: int = 0, storage: int = RCX_STORE_F32,
-                 line_profile: int = RCX_PROFILE_AUTO):
+                 line_profile: int = RCX_PROFILE_AUTO, check_input: bool = False, set_atmosphere: bool = True):
         import torch
         p = rcx_params_default()
         p.n_cascades = n_cascades
         p.storage = storage
+        p.flags = RCX_FLAG_CHECK_INPUT if check_input else 0
         self.inp = inp
         self.handle = rcx_nlte_create(rcx_grid(inp.nx, inp.nz, inp.voxel), p, atom_from_dict(inp.atom),
                                       inp.lambda_nm, inp.trans, inp.dnu)
@@ -449,7 +453,13 @@ class Nlte:
         self.ne = torch.from_numpy(inp.ne.astype("float64")).to(dev)
         self.ntot = torch.from_numpy(inp.ntot.astype("float64")).to(dev)
         self.vel = torch.from_numpy(inp.vel.astype("float32")).to(dev).contiguous()
-        rcx_nlte_set_atmosphere(self.handle, self.T, self.ne, self.ntot, self.vel)
+        if set_atmosphere:
+            rcx_nlte_set_atmosphere(self.handle, self.T, self.ne, self.ntot, self.vel)
+
+    def set_atmosphere(self, T, ne, ntot, vel):
+        """Set the atmosphere from device arrays (T, ne, ntot FP64 [nz][nx],
+        vel FP32 [2][nz][nx])."""
+        rcx_nlte_set_atmosphere(self.handle, T, ne, ntot, vel)
 
     def lte(self):
         import torch
@@ -564,6 +574,19 @@ class Nlte:
         _check(_load_nlte().rcx_nlte_warm_start(self.handle, net.handle, fn.ctypes.data, tn.ctypes.data,
                                                 _dev_ptr(pops, "torch.float64", "pops"), _stream_ptr(None)),
                "rcx_nlte_warm_start")
+        return pops
+
+    def pops_from_prediction(self, y, targ_norm):
+        """Populations (device FP64 [levels][nz][nx]) from standardised
+        predicted targets y [cells][levels] (device FP32)."""
+        import numpy as np
+        import torch
+        pops = torch.empty((self.n_levels, self.inp.nz, self.inp.nx), dtype=torch.float64, device="cuda:0")
+        tn = np.ascontiguousarray(targ_norm, np.float32)
+        _check(_load_nlte().rcx_nlte_pops_from_prediction(self.handle, _dev_ptr(y, "torch.float32", "y"),
+                                                          tn.ctypes.data, _dev_ptr(pops, "torch.float64", "pops"),
+                                                          _stream_ptr(None)),
+               "rcx_nlte_pops_from_prediction")
         return pops
 
     def close(self):
@@ -698,11 +721,11 @@ def _ptr_array(ts, what: str):
 
 class Batch:
     """Owns an ``rcx_batch``: formal solutions of several atmospheres (grids
-    ``shapes[a] = (nx, nz)``, ``n_wave[a]`` wavelengths) in one persistent
-    launch."""
+    ``shapes[a] = (nx, nz)``, ``n_wave[a]`` wavelengths) as one captured
+    graph of list-scheduled launches."""
 
     def __init__(self, shapes, n_wave, voxel_scale=1.0, storage: int = RCX_STORE_F32, c0_t1: float = 1.5,
-                 t_rule: int = RCX_T_GEOMETRIC):
+                 t_rule: int = RCX_T_GEOMETRIC, check_input: bool = False):
         n = len(shapes)
         if len(n_wave) != n:
             raise ValueError("shapes and n_wave differ in length")
@@ -711,6 +734,7 @@ class Batch:
         nw = (C.c_int32 * n)(*[int(w) for w in n_wave])
         p = rcx_params_default()
         p.storage, p.c0_t1, p.t_rule = storage, c0_t1, t_rule
+        p.flags = RCX_FLAG_CHECK_INPUT if check_input else 0
         h = C.c_void_p()
         _check(_load_batch().rcx_batch_create(n, grids, nw, C.byref(p), C.byref(h)), "rcx_batch_create")
         self.handle = h.value

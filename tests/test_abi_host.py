@@ -28,7 +28,19 @@ def test_library_exports_every_declared_symbol():
 def test_error_strings():
     assert rcx.rcx_error_string(0) == "ok"
     assert "invalid" in rcx.rcx_error_string(rcx.RCX_E_INVALID)
+    assert "not finite" in rcx.rcx_error_string(rcx.RCX_E_NONFINITE)
     assert rcx.rcx_error_string(-99) == "unknown status code"
+
+
+def test_header_constants_match_the_binding():
+    """The status codes and flags the binding uses are the header's."""
+    text = open(rcx.HEADER).read()
+    for name in ("RCX_E_INVALID", "RCX_E_UNSUPPORTED", "RCX_E_NOMEM", "RCX_E_HIP", "RCX_E_WORKSPACE",
+                 "RCX_E_NONFINITE", "RCX_FLAG_BILINEAR_FIX", "RCX_FLAG_CHECK_INPUT", "RCX_STORE_F32",
+                 "RCX_STORE_F16_SCALED"):
+        m = re.search(r"#define\s+" + name + r"\s+\(?(-?\d+)u?\)?", text)
+        assert m, name
+        assert int(m.group(1)) == getattr(rcx, name), name
 
 
 @pytest.mark.parametrize("nx,nz,mw", [(0, 8, 1), (8, -1, 1), (8, 8, 0)])
@@ -69,10 +81,11 @@ def test_plan_create_rejects_bad_inclination_counts(n_incl):
     assert e.value.code == rcx.RCX_E_INVALID
 
 
-@pytest.mark.parametrize("flags, n_incl, code", [(2, 1, "RCX_E_INVALID"), (0x80000000, 1, "RCX_E_INVALID"),
-                                                 (3, 8, "RCX_E_INVALID")])
+@pytest.mark.parametrize("flags, n_incl, code", [(4, 1, "RCX_E_INVALID"), (0x80000000, 1, "RCX_E_INVALID"),
+                                                 (5, 8, "RCX_E_INVALID"), (7, 1, "RCX_E_INVALID")])
 def test_plan_create_rejects_bad_flags(flags, n_incl, code):
-    """Unknown flag bits are invalid (with or without the bilinear fix)."""
+    """Unknown flag bits are invalid (with or without the bilinear fix and
+    the input check)."""
     p = rcx.rcx_params_default()
     p.flags = flags
     p.n_incl = n_incl
@@ -201,6 +214,9 @@ def test_batch_create_rejects_bad_arguments():
     assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
     p = rcx.rcx_params_default()
     p.n_cascades = 3
+    assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
+    p = rcx.rcx_params_default()
+    p.flags = rcx.RCX_FLAG_BILINEAR_FIX | rcx.RCX_FLAG_CHECK_INPUT
     assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
     assert h.value is None
     assert L.rcx_batch_solve(None, None, None, None, None) == rcx.RCX_E_INVALID

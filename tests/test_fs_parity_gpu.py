@@ -145,10 +145,11 @@ def test_full_size_1024_64_wavelengths_sampled():
 
 @pytest.mark.parametrize("which", ["blobs64", "line256", "line96_w40"])
 def test_fp16_storage_error_is_bounded(which):
-    """FP16 cascade storage with per-wavelength power-of-two scaling: each
-    stored value carries at most 2^-12 relative rounding error within range,
-    accumulated over at most 6 stored cascades; the error against the FP64
-    oracle is reported and bounded by 2e-3."""
+    """16-bit cascade storage (FP16's 10-bit significand, the exponent
+    rebased per wavelength below its largest source function): each stored
+    value carries at most 2^-11 relative rounding error, accumulated over at
+    most 6 stored cascades and averaged over taps and directions; the error
+    against the FP64 oracle is reported and bounded by 1e-3."""
     torch = _torch()
     from paper_2408_14425_amd import rcx
     if which == "blobs64":
@@ -167,7 +168,7 @@ def test_fp16_storage_error_is_bounded(which):
     Jo = oracle.formal_solve(inp.chi, inp.eta, inp.n_cascades)["J"]
     rel = np.abs(Jg - Jo) / Jo
     print(f"fp16 storage {which}: max rel {rel.max():.3e} mean {rel.mean():.3e}")
-    assert rel.max() < 2e-3
+    assert rel.max() < 1e-3
 
 
 @pytest.mark.parametrize("case", ["blobs64_incl8", "ragged_w20_incl3", "ragged_w20_incl8", "line96_w40_incl8_fp16"])

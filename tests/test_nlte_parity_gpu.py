@@ -1,10 +1,19 @@
 """GPU non-LTE iteration vs the FP64 oracle, through the C ABI.
 
 Tolerances: populations 1e-3 relative (compared after the same number of
-iterations, the oracle's stopping count for converged runs); J 5e-4 relative
-(the FP32 march plus the device Voigt table's interpolation error, below
-5e-5 relative); LTE populations 1e-12 (same FP64 formula)."""
+iterations, the oracle's stopping count for converged runs); J 1e-4
+relative (the FP32 march, whose rounding is ~1e-6 to 1e-5 over these path
+lengths, plus the march's Voigt profile, within 2e-5 of the oracle's);
+rate coefficients 1e-4 of the sum of the magnitudes of their terms (the
+preconditioned sums cancel in optically thick cells, so their relative
+error is measured against the scale the FP32 terms carry); LTE populations
+1e-12 (FP64 on both sides). Stored oracle results (tests/golden, written by
+make_nlte_goldens.py from the oracle alone) stand in where the oracle would
+need minutes: the converged 128^2 run and the sampled cells of the 1024^2,
+160-wavelength atmosphere."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -105,11 +114,131 @@ def test_formal_solve_J_and_first_update(case32):
     new, cho = P.stat_eq(po, Rup, Rdn)
     relJ = np.abs(Jg - Jo) / np.abs(Jo)
     print("J max rel", relJ.max(), "first change gpu/oracle", ch, cho)
-    assert relJ.max() < 5e-4
+    assert relJ.max() < 1e-4
     relp = np.abs(pg - new) / np.abs(new)
     print("pops after one update max rel", relp.max())
     assert relp.max() < 1e-3
     assert abs(ch / cho - 1) < 1e-3
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rates_vs_oracle(rg, P, pops, I0, chi_loc, H_loc):
+    """Max over transitions and cells of |R_gpu - R_oracle| / (magnitude
+    sum), for the upward and downward coefficients."""
+    Rup, Rdn = P.rates(pops, I0, chi_loc, H_loc)
+    Aup, Adn = P.rate_magnitudes(pops, I0, chi_loc, H_loc)
+    rg = rg.reshape(len(P.atom.trans), 2, -1).astype(np.float64)
+    return float(np.max(np.abs(rg[:, 0] - Rup) / Aup)), float(np.max(np.abs(rg[:, 1] - Rdn) / Adn))
+
+
+@pytest.mark.parametrize("profile", PROFILES)
+def test_rates_elementwise(case32, profile):
+    """The preconditioned rate coefficients of one formal solution at LTE,
+    cell by cell and transition by transition, against the oracle's."""
+    torch = _torch()
+    inp, P = case32
+    s = _solver(inp, profile)
+    pops = s.lte()
+    rates, _ = s.formal_solve_rates(pops)
+    torch.cuda.synchronize()
+    rg = rates.cpu().numpy()
+    s.close()
+    _, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    eu, ed = _rates_vs_oracle(rg, P, P.lte, I0, chi_loc, H_loc)
+    print(f"rates vs oracle ({profile}): up {eu:.3e}, down {ed:.3e} of the magnitude sums")
+    assert eu < 1e-4 and ed < 1e-4
+
+
+def test_two_continuum_batches():
+    """32 continuum wavelengths: two continuum batches, which the march pairs
+    per lane on the cascades with at most 256 directions. J to 1e-4, the
+    rates to 1e-4 of their magnitude sums, populations after 3 iterations
+    to 1e-3."""
+    torch = _torch()
+    from oracle import nlte
+    inp = W.nlte_atmosphere(32, seed=6, n_line=16, n_cont=32)
+    P = nlte.Problem(inp)
+    s = _solver(inp)
+    pops = s.lte()
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64)
+    rg = rates.cpu().numpy()
+    rc, it, ch = s.iterate(pops, 3, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    relJ = np.abs(Jg - Jo) / np.abs(Jo)
+    eu, ed = _rates_vs_oracle(rg, P, P.lte, I0, chi_loc, H_loc)
+    po, _ = P.iterate(P.lte.copy(), 3)
+    relp = np.abs(pg - po) / np.abs(po)
+    cont = inp.trans == inp.trans.max()
+    print(f"two continuum batches: J max rel {relJ.max():.3e} (continuum {relJ[cont].max():.3e}), "
+          f"rates {eu:.3e} / {ed:.3e}, pops after 3 iterations {relp.max():.3e}")
+    assert cont.sum() == 32
+    assert relJ.max() < 1e-4
+    assert eu < 1e-4 and ed < 1e-4
+    assert relp.max() < 1e-3
+
+
+def test_converged_128_at_oracle_iteration_count():
+    """The 128^2 atmosphere (6 cascades) iterated for the oracle's count K
+    (stored: the oracle needs minutes for it) agrees with the oracle's
+    populations to 1e-3, and the GPU's own stopping test fires within one
+    iteration of K."""
+    _torch()
+    g = np.load(os.path.join(GOLDEN, "nlte128_s4.npz"))
+    K = int(g["K"])
+    inp = W.nlte_atmosphere(128, seed=4, n_line=32, n_cont=16)
+    s = _solver(inp)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, K, 0.0)
+    pg = pops.cpu().numpy().reshape(g["pops"].shape)
+    pops2 = s.lte()
+    rc2, it2, ch2 = s.iterate(pops2, K + 2, 1e-3)
+    s.close()
+    relp = np.abs(pg - g["pops"]) / np.abs(g["pops"])
+    print(f"128^2 converged: oracle {K} iterations (last change {g['changes'][-1]:.3e}); gpu after {it} "
+          f"({ch:.3e}): max rel {relp.max():.3e}; gpu stopping test rc {rc2} at {it2}")
+    assert it == K
+    assert relp.max() < 1e-3
+    assert rc2 == 0 and abs(it2 - K) <= 1
+
+
+def test_full_size_atmosphere_sampled_cells():
+    """The 1024^2, 160-wavelength atmosphere (7 cascades, two continuum
+    batches, the tiled launch order and XCD-chunked workgroups of the full
+    size) at LTE: J at four sampled cells for every wavelength to 1e-4, the
+    rate coefficients there to 1e-4 of their magnitude sums, and the
+    populations after one equilibrium step to 1e-3, against the oracle's
+    dependency-cone solve of those cells (stored)."""
+    torch = _torch()
+    with open(os.path.join(GOLDEN, "nlte1024_s3_cells.json")) as f:
+        g = json.load(f)
+    cells = np.array(g["cells"])
+    inp = W.nlte_atmosphere(1024, seed=3, n_line=64, n_cont=32)
+    s = _solver(inp)
+    pops = s.lte()
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    lte = pops.cpu().numpy().reshape(4, -1)[:, cells]
+    s.stat_eq(rates, pops)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1)[:, cells].astype(np.float64)
+    rg = rates.cpu().numpy().reshape(3, 2, -1)[:, :, cells].astype(np.float64)
+    pg = pops.cpu().numpy().reshape(4, -1)[:, cells]
+    s.close()
+    relJ = np.abs(Jg - np.array(g["J"])) / np.abs(np.array(g["J"]))
+    eu = np.max(np.abs(rg[:, 0] - np.array(g["Rup"])) / np.array(g["Aup"]))
+    ed = np.max(np.abs(rg[:, 1] - np.array(g["Rdn"])) / np.array(g["Adn"]))
+    relp = np.abs(pg - np.array(g["pops1"])) / np.abs(np.array(g["pops1"]))
+    print(f"1024^2 sampled cells {cells.tolist()}: J max rel {relJ.max():.3e}, rates {eu:.3e} / {ed:.3e}, "
+          f"pops after one step {relp.max():.3e}")
+    np.testing.assert_allclose(lte, np.array(g["lte"]), rtol=1e-12)
+    assert relJ.max() < 1e-4
+    assert eu < 1e-4 and ed < 1e-4
+    assert relp.max() < 1e-3
 
 
 @pytest.mark.parametrize("profile", PROFILES)
@@ -184,15 +313,17 @@ def test_ng_accelerated_iteration_matches_oracle(case32):
 
 
 def test_fp16_storage_converged_populations(case32):
-    """FP16 scaled cascade storage inside the non-LTE iteration. The storage
-    is linear FP16 with one power-of-two scale per wavelength, set by the
-    largest source function of the wavelength (a bound no radiance
-    exceeds). Where the hottest cells are optically thin (the continuum,
-    the line wings) the radiances stay decades below that bound and lose
-    precision, so J's error is reported per transition, not gated; the rate
-    coefficients (dominated by cascade 0, which is FP32) must agree with the
-    FP32 path to 1e-4 of their maximum and the converged populations (same
-    iteration count as the oracle) with the oracle to 1e-3."""
+    """16-bit cascade storage inside the non-LTE iteration: cascades >= 1
+    stored as FP16-precision codes (10-bit significand, relative rounding
+    2^-11) whose 6-bit exponent is rebased per wavelength below its largest
+    source function, so the 2^43 dynamic range of the Lyman continuum
+    between hot and cool cells stays inside the format. J of every
+    transition agrees with the FP64 oracle to 1e-3 relative, element by
+    element (at most ~6 stored cascades of 2^-11 each, averaged over taps
+    and directions); the rate coefficients (cascade 0 is FP32, but its
+    merged radiance carries the stored cascades' rounding) agree with the
+    oracle to 1e-3 of their magnitude sums, the bound of J; the converged
+    populations (same iteration count as the oracle) to 1e-3."""
     torch = _torch()
     from paper_2408_14425_amd import rcx
     inp, P = case32
@@ -205,24 +336,26 @@ def test_fp16_storage_converged_populations(case32):
         pops = s.lte()
         r, J = s.formal_solve_rates(pops, want_J=True)
         torch.cuda.synchronize()
-        res[st] = (r.cpu().numpy(), J.cpu().numpy().reshape(inp.n_wave, -1))
+        res[st] = (r.cpu().numpy(), J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64))
         if st == rcx.RCX_STORE_F16_SCALED:
             rc, it, ch = s.iterate(pops, K, 1e-3)
             pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
         s.close()
-    Jo = P.formal_solve(P.lte.copy())[0]
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte.copy())
     J16 = res[rcx.RCX_STORE_F16_SCALED][1]
-    scaled = np.abs(J16 - Jo) / np.abs(Jo).max(axis=1, keepdims=True)
+    rel = np.abs(J16 - Jo) / np.abs(Jo)
+    worst = 0.0
     for t in range(int(inp.trans.max()) + 1):
         sel = inp.trans == t
-        print(f"fp16 J, transition {t}: max error / per-wavelength max {scaled[sel].max():.3e}, "
-              f"median relative {np.median(np.abs(J16[sel] - Jo[sel]) / Jo[sel]):.3e}")
-    r32, r16 = res[rcx.RCX_STORE_F32][0], res[rcx.RCX_STORE_F16_SCALED][0]
-    rdiff = float(np.abs(r16 - r32).max() / np.abs(r32).max())
+        print(f"fp16 J, transition {t}: max rel {rel[sel].max():.3e}, median {np.median(rel[sel]):.3e}")
+        worst = max(worst, float(rel[sel].max()))
+    eu, ed = _rates_vs_oracle(res[rcx.RCX_STORE_F16_SCALED][0], P, P.lte, I0, chi_loc, H_loc)
     relp = np.abs(pg - po) / np.abs(po)
-    print(f"fp16: rates vs fp32 {rdiff:.3e}; after {it} iterations pops max rel {relp.max():.3e}")
+    print(f"fp16: rates vs oracle {eu:.3e} / {ed:.3e} of the magnitude sums; after {it} iterations pops max rel "
+          f"{relp.max():.3e}")
     assert np.all(np.isfinite(J16))
-    assert rdiff < 1e-4
+    assert worst < 1e-3
+    assert eu < 1e-3 and ed < 1e-3
     assert relp.max() < 1e-3
 
 
@@ -364,26 +497,25 @@ def test_sparse_nlte_matches_oracle():
 @pytest.mark.parametrize("wx, wz", [(0.8, 0.6), (-0.45, -0.9)])
 def test_emergent_spectra_match_oracle(case32, wx, wz):
     """Emergent spectra (Sec. 3.9) along a beam of parallel long
-    characteristics at the populations after two GPU iterations, against
-    the oracle at the same populations: 5e-4 relative (the FP32 march and
-    the march's Voigt profile, as for J)."""
+    characteristics at the oracle's populations after two iterations (given
+    to both sides): 1e-4 relative (the FP32 march and the march's Voigt
+    profile, as for J)."""
     torch = _torch()
     inp, P = case32
+    po, _ = P.iterate(P.lte.copy(), 2)
     s = _solver(inp)
-    pops = s.lte()
-    s.iterate(pops, 2, 0.0)
+    pops = torch.from_numpy(np.ascontiguousarray(po).reshape(P.atom.n_levels, inp.nz, inp.nx)).to("cuda:0")
     n_rays = int(math.ceil(abs(inp.nx * wz) + abs(inp.nz * wx))) + 4
     I = s.emergent(pops, wx, wz, n_rays)
     torch.cuda.synchronize()
     Ig = I.cpu().numpy().astype(np.float64)
-    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
     s.close()
-    Io = P.emergent(pg, wx, wz, n_rays)
+    Io = P.emergent(po, wx, wz, n_rays)
     hit = Io > 0
     rel = np.abs(Ig[hit] - Io[hit]) / Io[hit]
     print(f"emergent spectra w=({wx}, {wz}): {hit[0].sum()} of {n_rays} rays hit, max rel {rel.max():.3e}")
     assert np.all(Ig[~hit] == 0.0)
-    assert rel.max() < 5e-4
+    assert rel.max() < 1e-4
 
 
 def test_emergent_spectra_of_a_sparse_solver():
@@ -400,11 +532,10 @@ def test_emergent_spectra_of_a_sparse_solver():
     I = s.emergent(pops, 0.8, -0.6, 48)
     torch.cuda.synchronize()
     Ig = I.cpu().numpy().astype(np.float64)
-    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
     s.close()
-    Io = P.emergent(pg, 0.8, -0.6, 48)
+    Io = P.emergent(P.lte, 0.8, -0.6, 48)
     hit = Io > 0
     rel = np.abs(Ig[hit] - Io[hit]) / Io[hit]
     print(f"sparse emergent spectra: max rel {rel.max():.3e}")
     assert np.all(Ig[~hit] == 0.0)
-    assert rel.max() < 5e-4
+    assert rel.max() < 1e-4
