@@ -178,6 +178,24 @@ int32_t rcx_plan_work(rcx_plan* plan, rcx_work* out_host);
 int32_t rcx_formal_solve(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta,
                          float* J, void* workspace, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * formal solve of rcx_formal_solve with no allocation at all. Its workspace
+ * is the library's scratch, a 64 MiB array held on each GPU the library
+ * runs on until the process ends (its address on the device is looked up
+ * once, by rcx_plan_create). Every call on a GPU shares that GPU's scratch:
+ * calls that overlap on one GPU (two streams, two threads) race and must
+ * be ordered by the caller; the scratch keeps the last call's contents and
+ * every value a solve reads from it is written first by that solve. Calls
+ * no hipMalloc, hipFree or allocating library routine; the plan must not
+ * have kernel timing enabled (it records events).
+ * Errors: RCX_E_INVALID (null arrays, n_wave outside [1, max_wave], timing
+ * enabled); RCX_E_WORKSPACE when rcx_plan_workspace_bytes(n_wave) exceeds
+ * the 64 MiB (e.g. more than about 256^2 cells x 16 wavelengths: use
+ * rcx_formal_solve); RCX_E_NONFINITE; RCX_E_HIP. */
+int32_t rcx_formal_solve_noalloc(rcx_plan* plan, int32_t n_wave, const float* chi, const float* eta, float* J,
+                                 hipStream_t stream);
+
 /* Emergent intensity along parallel long characteristics (Sec. 3.9, the
  * post-processing formal solver): a beam of n_rays rays of light direction
  * (wx, wz) (any non-zero vector; normalised), one cell apart across the beam

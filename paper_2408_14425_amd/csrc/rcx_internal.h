@@ -155,6 +155,7 @@ struct rcx_plan {
     int32_t* plist_dev = nullptr;
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
+    void* scratch = nullptr;  // the library's scratch on the plan's device (rcx_formal_solve_noalloc)
     bool work_done = false;
     rcx_work work;
     // measurement: events recorded around launches when timing is enabled

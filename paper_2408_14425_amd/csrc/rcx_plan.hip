@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -21,6 +22,14 @@ constexpr int32_t kTileMinDirs = 256;
 constexpr int32_t kPairMaxDirs = 256;
 constexpr int32_t kTileProbes = 4;
 constexpr int32_t kTileDirs = 32;
+
+// The allocation-free formal solve's scratch (rcx_formal_solve_noalloc):
+// a file-scope device array, one copy per GPU, held until the process ends.
+// Host code uses only the device address that hipGetSymbolAddress returns
+// for the current device (kept per device in g_scratch), never the array's
+// name.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 thread_local int32_t g_last_code = RCX_OK;
@@ -44,6 +53,32 @@ static int32_t ok()
 {
     g_last_code = RCX_OK;
     g_last_msg[0] = 0;
+    return RCX_OK;
+}
+
+// Device address of the scratch array on the current device, looked up
+// once per device (at plan creation: rcx_plan_create calls this with the
+// plan's device current).
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+int32_t scratch_address(void** out)
+{
+    *out = nullptr;
+    int dev = 0;
+    RCX_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RCX_E_UNSUPPORTED, "scratch: device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
     return RCX_OK;
 }
 
@@ -561,8 +596,31 @@ int32_t rcx_plan_create(const rcx_grid* g, const rcx_params* prm, int32_t max_wa
         rcx_plan_destroy(p);
         return fail(RCX_E_NOMEM, std::string("rcx_plan_create: workspace hipMalloc: ") + hipGetErrorName(e));
     }
+    // the allocation-free solve's scratch on this device (looked up once)
+    const int32_t rc = scratch_address(&p->scratch);
+    if (rc != RCX_OK) {
+        rcx_plan_destroy(p);
+        return rc;
+    }
     *out = p;
     return ok();
+}
+
+int32_t rcx_formal_solve_noalloc(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                                 hipStream_t st)
+{
+    if (!p || !chi || !eta || !J) return fail(RCX_E_INVALID, "rcx_formal_solve_noalloc: null argument");
+    if (n_wave <= 0 || n_wave > p->max_wave)
+        return fail(RCX_E_INVALID, "rcx_formal_solve_noalloc: n_wave must be in [1, max_wave]");
+    if (p->timing)
+        return fail(RCX_E_INVALID, "rcx_formal_solve_noalloc: kernel timing creates events; disable it first");
+    const size_t need = ws_layout(p, n_wave).total;
+    if (need > kScratchBytes)
+        return fail(RCX_E_WORKSPACE, "rcx_formal_solve_noalloc: the solve needs " + std::to_string(need) +
+                                         " bytes of scratch, more than the library's " +
+                                         std::to_string(kScratchBytes) + " (use rcx_formal_solve)");
+    if (!p->scratch) return fail(RCX_E_HIP, "rcx_formal_solve_noalloc: no scratch address for the plan's device");
+    return rcx_formal_solve(p, n_wave, chi, eta, J, p->scratch, kScratchBytes, st);
 }
 
 int32_t rcx_plan_set_active_host(rcx_plan* p, const uint8_t* active_host, int64_t* level_active_host)

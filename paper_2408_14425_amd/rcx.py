@@ -74,6 +74,7 @@ def load() -> C.CDLL:
     L.rcx_plan_set_active_host.argtypes = [vp, vp, C.POINTER(C.c_int64)]
     L.rcx_emergent.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, i32, vp, vp]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
+    L.rcx_formal_solve_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
     L.rcx_plan_destroy.argtypes = [vp]
     L.rcx_plan_set_timing.argtypes = [vp, i32]
     L.rcx_plan_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -83,7 +84,7 @@ def load() -> C.CDLL:
     L.rcx_last_error.argtypes = [C.c_char_p, sz]
     for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
                  "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error", "rcx_plan_set_timing",
-                 "rcx_plan_get_timing", "rcx_plan_set_active_host", "rcx_emergent"):
+                 "rcx_plan_get_timing", "rcx_plan_set_active_host", "rcx_emergent", "rcx_formal_solve_noalloc"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -263,6 +264,15 @@ class Plan:
         if J is None:
             J = torch.empty_like(chi)
         rcx_formal_solve(self.handle, n_wave, chi, eta, J, workspace, stream)
+        return J
+
+    def formal_solve_noalloc(self, chi, eta, J, stream=None):
+        """rcx_formal_solve_noalloc: the solve in the library's scratch (no
+        allocation; J must be given)."""
+        _check(load().rcx_formal_solve_noalloc(self.handle, int(chi.shape[0]), _dev_ptr(chi, "torch.float32", "chi"),
+                                               _dev_ptr(eta, "torch.float32", "eta"),
+                                               _dev_ptr(J, "torch.float32", "J"), _stream_ptr(stream)),
+               "rcx_formal_solve_noalloc")
         return J
 
     def close(self):
