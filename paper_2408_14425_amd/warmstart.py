@@ -18,26 +18,38 @@ import numpy as np
 from . import rcx, workloads as W
 
 
-def converged_run(n: int, seed: int, n_line: int, n_cont: int, tol: float, max_iter: int):
-    """Features at LTE and converged log departure coefficients of one seeded atmosphere."""
+def converged_run(n: int, seed: int, n_line: int, n_cont: int, tol: float, max_iter: int, ng: bool = False,
+                  keep: int = 1):
+    """Features at LTE and converged log departure coefficients of one seeded
+    atmosphere; ng: iterate with Ng acceleration (order 2, first after 4
+    iterations, then every 4; the same fixed point, reached in fewer
+    iterations); keep: every keep-th cell (a seeded random subset) only."""
     inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
     s = rcx.Nlte(inp)
+    if ng:
+        s.set_acceleration(2, 4, 4)
     pops = s.lte()
     feat = s.features(pops).cpu().numpy()
     rc, it, ch = s.iterate(pops, max_iter, tol)
     targ = s.log_departures(pops).cpu().numpy()
     s.close()
+    if keep > 1:
+        sel = np.sort(np.random.default_rng(seed).choice(len(feat), len(feat) // keep, replace=False))
+        feat, targ = feat[sel], targ[sel]
     return feat, targ, it, ch
 
 
-def dataset(n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 500):
+def dataset(n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 500, ng: bool = False,
+            keep: int = 1):
     X, Y, info = [], [], []
+    t0 = time.perf_counter()
     for seed in seeds:
-        f, t, it, ch = converged_run(n, seed, n_line, n_cont, tol, max_iter)
+        f, t, it, ch = converged_run(n, seed, n_line, n_cont, tol, max_iter, ng=ng, keep=keep)
         X.append(f)
         Y.append(t)
         info.append({"seed": int(seed), "iterations": it, "last_change": ch})
-        print(f"converged run {n}^2 seed {seed}: {it} iterations (change {ch:.2e})", flush=True)
+        print(f"converged run {n}^2 seed {seed}: {it} iterations (change {ch:.2e}), "
+              f"{time.perf_counter() - t0:.0f} s", flush=True)
     return np.concatenate(X), np.concatenate(Y), info
 
 
@@ -154,9 +166,14 @@ def main():
     ap.add_argument("--out", default=None)
     ap.add_argument("--save", default=None, help="write the trained network (npz)")
     ap.add_argument("--ref-max-iter", type=int, default=300)
+    ap.add_argument("--tol", type=float, default=1e-3, help="stopping change of the training runs")
+    ap.add_argument("--ng", action="store_true", help="training runs with Ng acceleration")
+    ap.add_argument("--keep", type=int, default=1, help="keep every keep-th cell of each training run")
+    ap.add_argument("--no-eval", action="store_true")
     a = ap.parse_args()
     t0 = time.perf_counter()
-    X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont)
+    X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont, tol=a.tol, ng=a.ng,
+                         keep=a.keep)
     if a.train_n2 > 0 and a.train_runs2 > 0:
         X2, Y2, info2 = dataset(a.train_n2, range(5100, 5100 + a.train_runs2), a.n_line, a.n_cont)
         X, Y = np.concatenate([X, X2]), np.concatenate([Y, Y2])
@@ -169,9 +186,11 @@ def main():
     print(f"trained on {len(X)} samples in {t_train:.1f} s, loss {losses[0]:.4g} -> {losses[-1]:.4g}", flush=True)
     if a.save:
         save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "train_n2": a.train_n2,
-                                   "train_runs2": a.train_runs2, "epochs": a.epochs,
+                                   "train_runs2": a.train_runs2, "epochs": a.epochs, "tol": a.tol, "ng": a.ng,
+                                   "keep": a.keep, "samples": len(X),
                                    "n_line": a.n_line, "n_cont": a.n_cont, "loss_last": losses[-1]})
-    ev = evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont, ref_max_iter=a.ref_max_iter)
+    ev = [] if a.no_eval else evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont,
+                                       ref_max_iter=a.ref_max_iter)
     for e in ev:
         print(json.dumps(e), flush=True)
     rep = {"train": {"n": a.train_n, "runs": a.train_runs, "n2": a.train_n2, "runs2": a.train_runs2,
