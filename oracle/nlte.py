@@ -61,7 +61,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import _dp, default_cascades, lib, make_geom
+from . import _dp, default_cascades, lib, make_geom, radau_inclinations
 
 # CODATA 2018, SI
 H_PLANCK = 6.62607015e-34
@@ -79,7 +79,7 @@ class NlteFields(C.Structure):
         ("nx", C.c_int32), ("nz", C.c_int32), ("n_wave", C.c_int32), ("n_lines", C.c_int32),
         ("line", C.c_void_p), ("u", C.c_void_p), ("chi_c", C.c_void_p), ("eta_c", C.c_void_p),
         ("kappa", C.c_void_p), ("eps", C.c_void_p), ("adamp", C.c_void_p), ("inv_vth", C.c_void_p),
-        ("vx", C.c_void_p), ("vz", C.c_void_p),
+        ("vx", C.c_void_p), ("vz", C.c_void_p), ("vscale", C.c_double),
     ]
 
 
@@ -195,7 +195,7 @@ def ng_extrapolate(xs, M: int):
 class Problem:
     """Static (population-independent) data of one non-LTE problem."""
 
-    def __init__(self, inp, n_casc: int | None = None, t_cut: float | None = None):
+    def __init__(self, inp, n_casc: int | None = None, t_cut: float | None = None, n_incl: int = 1):
         self.inp = inp
         self.atom = Atom(inp.atom)
         self.nx, self.nz = inp.nx, inp.nz
@@ -212,6 +212,17 @@ class Problem:
         self.W = 4.0 * math.pi * inp.dnu / (H_PLANCK * self.nu)
         self.n_casc = default_cascades(self.nx, self.nz) if n_casc is None else n_casc
         self.geom = make_geom(self.nx, self.nz, self.n_casc, voxel=inp.voxel)
+        # 2D invariance (Sec. 3.1): n_incl rays per flatland ray, inclined to
+        # the invariant y axis at mu = cos(theta) on the Gauss-Radau rule
+        # with the in-plane node mu = 0 fixed; ray m has the flatland ray's
+        # projection, a path sin(theta_m)^-1 times longer per projected cell
+        # and sin(theta_m) of the in-plane velocity along it; J and the
+        # rates are the weighted sums over m. n_incl = 1 is flatland.
+        self.n_incl = n_incl
+        mu, wmu = radau_inclinations(n_incl)
+        self.incl_sin = np.sqrt(1.0 - mu ** 2)
+        self.incl_w = wmu
+        self.incl_geom = [make_geom(self.nx, self.nz, self.n_casc, voxel=inp.voxel / sm) for sm in self.incl_sin]
         self.n0 = 4
         self.lte = lte_populations(self.atom, self.T, self.ne, self.ntot)
         # thermal speed and line quantities per cell
@@ -285,14 +296,14 @@ class Problem:
                 a[:, off] = 0.0
         return chi_c, eta_c, kappa, eps
 
-    def _cfields(self, chi_c, eta_c, kappa, eps, lams=None):
+    def _cfields(self, chi_c, eta_c, kappa, eps, lams=None, vscale: float = 1.0):
         lams = np.arange(len(self.nu)) if lams is None else np.asarray(lams)
         keep = [np.ascontiguousarray(a, dtype=np.float64) for a in
                 (self.u[lams], chi_c, eta_c, kappa, eps, self.adamp, 1.0 / self.vth, self.vx, self.vz)]
         line = np.ascontiguousarray(self.line_index[lams], dtype=np.int32)
         keep.append(line)
         f = NlteFields(self.nx, self.nz, len(lams), len(self.atom.lines), line.ctypes.data,
-                       *[k.ctypes.data for k in keep[:9]])
+                       *[k.ctypes.data for k in keep[:9]], vscale)
         return f, keep
 
     def formal_solve(self, pops, lams=None, need=None):
@@ -301,25 +312,36 @@ class Problem:
         profile H at each cell. lams: wavelength indices to solve (all if
         None; the outputs then cover those only); need: [cells] mask of the
         cells whose J is wanted (only their dependency cone is solved, the
-        other cells' J and I0 are 0)."""
+        other cells' J and I0 are 0). With inclinations J is the weighted sum
+        over them, and I0, chi and H carry a leading inclination axis."""
         lams = np.arange(len(self.nu)) if lams is None else np.asarray(lams)
         chi_c, eta_c, kappa, eps = self.fields(pops, lams)
-        f, keep = self._cfields(chi_c, eta_c, kappa, eps, lams)
         nw = len(lams)
-        J = np.zeros((nw, self.ncell))
-        I0 = np.zeros((nw, self.ncell, self.n0))
-        st = np.zeros(3, np.int64)
         L = _bind()
         nm = None if need is None else np.ascontiguousarray(np.asarray(need).reshape(-1), dtype=np.uint8)
-        rc = L.ora_nlte_formal_solve(C.byref(self.geom), C.byref(f), None if nm is None else nm.ctypes.data,
-                                     J.ctypes.data, I0.ctypes.data, st.ctypes.data, 0)
-        if rc != 0:
-            raise RuntimeError("ora_nlte_formal_solve failed")
-        chi_loc = np.zeros((nw, self.ncell, self.n0))
-        H_loc = np.zeros((nw, self.ncell, self.n0))
-        L.ora_nlte_local(C.byref(self.geom), C.byref(f), chi_loc.ctypes.data, H_loc.ctypes.data)
-        del keep
-        return J, I0, chi_loc, H_loc, st
+        Js, I0s, chis, Hs = [], [], [], []
+        st = np.zeros(3, np.int64)
+        for m in range(self.n_incl):
+            f, keep = self._cfields(chi_c, eta_c, kappa, eps, lams, float(self.incl_sin[m]))
+            J = np.zeros((nw, self.ncell))
+            I0 = np.zeros((nw, self.ncell, self.n0))
+            rc = L.ora_nlte_formal_solve(C.byref(self.incl_geom[m]), C.byref(f),
+                                         None if nm is None else nm.ctypes.data, J.ctypes.data, I0.ctypes.data,
+                                         st.ctypes.data, 0)
+            if rc != 0:
+                raise RuntimeError("ora_nlte_formal_solve failed")
+            chi_loc = np.zeros((nw, self.ncell, self.n0))
+            H_loc = np.zeros((nw, self.ncell, self.n0))
+            L.ora_nlte_local(C.byref(self.incl_geom[m]), C.byref(f), chi_loc.ctypes.data, H_loc.ctypes.data)
+            del keep
+            Js.append(J)
+            I0s.append(I0)
+            chis.append(chi_loc)
+            Hs.append(H_loc)
+        if self.n_incl == 1:
+            return Js[0], I0s[0], chis[0], Hs[0], st
+        J = sum(w * Jm for w, Jm in zip(self.incl_w, Js))
+        return J, np.array(I0s), np.array(chis), np.array(Hs), st
 
     def emergent(self, pops, wx: float, wz: float, n_rays: int):
         """Emergent intensity [n_wave][n_rays] at populations pops along the
@@ -335,9 +357,27 @@ class Problem:
             raise RuntimeError("ora_nlte_emergent failed")
         return I
 
+    def _incl_parts(self, I0, chi_loc, H_loc):
+        """(weight, path factor 1/sin, I0, chi, H) per inclination."""
+        if self.n_incl == 1:
+            return [(1.0, 1.0, I0, chi_loc, H_loc)]
+        return [(self.incl_w[m], 1.0 / self.incl_sin[m], I0[m], chi_loc[m], H_loc[m]) for m in range(self.n_incl)]
+
     def rates(self, pops, I0, chi_loc, H_loc):
         """Preconditioned radiative rate coefficients per transition and cell:
-        Rup (multiplies n_i) and Rdown (multiplies n_j)."""
+        Rup (multiplies n_i) and Rdown (multiplies n_j); with inclinations
+        the weighted sum over them, each with its longer path through the
+        cell (l / sin theta) in Psi*."""
+        nt = len(self.atom.trans)
+        Rup = np.zeros((nt, self.ncell))
+        Rdn = np.zeros((nt, self.ncell))
+        for wm, pf, I0m, chim, Hm in self._incl_parts(I0, chi_loc, H_loc):
+            u, d = self._rates_one(pops, I0m, chim, Hm, self.ell * pf)
+            Rup += wm * u
+            Rdn += wm * d
+        return Rup, Rdn
+
+    def _rates_one(self, pops, I0, chi_loc, H_loc, ell):
         nt = len(self.atom.trans)
         Rup = np.zeros((nt, self.ncell))
         Rdn = np.zeros((nt, self.ncell))
@@ -348,7 +388,7 @@ class Problem:
             chi = chi_loc[lam]                                   # [cells][k]
             # Psi* = (1 - e^{-chi l}) / chi, and its limit l where chi = 0
             with np.errstate(invalid="ignore", divide="ignore"):
-                psi = np.where(chi > 0, -np.expm1(-chi * self.ell[None, :]) / chi, self.ell[None, :])
+                psi = np.where(chi > 0, -np.expm1(-chi * ell[None, :]) / chi, ell[None, :])
             if tr.kind == "line":
                 _, Vij, Vji, Uji = self.line_coeffs(lam, H_loc[lam])
             else:
@@ -370,13 +410,23 @@ class Problem:
         nt = len(self.atom.trans)
         Aup = np.zeros((nt, self.ncell))
         Adn = np.zeros((nt, self.ncell))
+        for wm, pf, I0m, chim, Hm in self._incl_parts(I0, chi_loc, H_loc):
+            u, d = self._rate_magnitudes_one(pops, I0m, chim, Hm, self.ell * pf)
+            Aup += wm * u
+            Adn += wm * d
+        return Aup, Adn
+
+    def _rate_magnitudes_one(self, pops, I0, chi_loc, H_loc, ell):
+        nt = len(self.atom.trans)
+        Aup = np.zeros((nt, self.ncell))
+        Adn = np.zeros((nt, self.ncell))
         w = 1.0 / self.n0
         for lam in range(len(self.nu)):
             t = self.trans_of[lam]
             tr = self.atom.trans[t]
             chi = chi_loc[lam]
             with np.errstate(invalid="ignore", divide="ignore"):
-                psi = np.where(chi > 0, -np.expm1(-chi * self.ell[None, :]) / chi, self.ell[None, :])
+                psi = np.where(chi > 0, -np.expm1(-chi * ell[None, :]) / chi, ell[None, :])
             if tr.kind == "line":
                 _, Vij, Vji, Uji = self.line_coeffs(lam, H_loc[lam])
             else:

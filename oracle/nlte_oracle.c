@@ -75,10 +75,12 @@ void ora_voigt_H_vec(int64_t n, const double* a, const double* x, double* out)
 /* Opacity fields of one non-LTE formal solve. For wavelength index l:
  *   chi(l, c, w) = chi_c[l][c] + (line[l] >= 0 ? kappa[t][c] H(a[t][c], x) : 0)
  *   eta(l, c, w) = eta_c[l][c] + (line[l] >= 0 ? eps[t][c]   H(a[t][c], x) : 0)
- * with t = line[l] and x = (u[l] + w . v[c]) / v_th[c]: u[l] = c (nu_l - nu_0)/nu_0
+ * with t = line[l] and x = (u[l] + vscale w . v[c]) / v_th[c]: u[l] = c (nu_l - nu_0)/nu_0
  * is the wavelength's velocity offset from the line centre, and the profile
  * of a ray looking along w (photons travelling along -w) is shifted by the
- * projected plasma velocity. */
+ * projected plasma velocity. A ray inclined at theta to the invariant axis
+ * (Sec. 3.1) has the in-plane direction w of its projection and sees
+ * sin(theta) of the in-plane velocity: vscale = sin(theta). */
 typedef struct {
     int32_t nx, nz, n_wave, n_lines;
     const int32_t* line;   /* [n_wave] line index or -1 */
@@ -91,6 +93,8 @@ typedef struct {
     const double* inv_vth; /* [ncell] s/m */
     const double* vx;      /* [ncell] m/s */
     const double* vz;      /* [ncell] m/s */
+    double vscale;         /* velocity projection of the rays: 1 in the plane, sin(theta)
+                              for rays inclined at theta to the invariant y axis */
 } ora_nlte_fields;
 
 static void nlte_opac(const void* ctx, int32_t lam, int32_t x, int32_t z, double wx, double wz,
@@ -103,7 +107,7 @@ static void nlte_opac(const void* ctx, int32_t lam, int32_t x, int32_t z, double
     double et = f->eta_c[(size_t)lam * ncell + c];
     int32_t t = f->line[lam];
     if (t >= 0) {
-        double xx = (f->u[lam] + wx * f->vx[c] + wz * f->vz[c]) * f->inv_vth[c];
+        double xx = (f->u[lam] + f->vscale * (wx * f->vx[c] + wz * f->vz[c])) * f->inv_vth[c];
         double H = ora_voigt_H(f->adamp[(size_t)t * ncell + c], xx);
         ch += f->kappa[(size_t)t * ncell + c] * H;
         et += f->eps[(size_t)t * ncell + c] * H;
@@ -176,7 +180,7 @@ void ora_nlte_local(const ora_geom* g, const ora_nlte_fields* f, double* out_chi
             double H = 0.0;
             int32_t t = f->line[lam];
             if (t >= 0) {
-                double xx = (f->u[lam] + wxs[k] * f->vx[c] + wzs[k] * f->vz[c]) * f->inv_vth[c];
+                double xx = (f->u[lam] + f->vscale * (wxs[k] * f->vx[c] + wzs[k] * f->vz[c])) * f->inv_vth[c];
                 H = ora_voigt_H(f->adamp[(size_t)t * ncell + c], xx);
             }
             out_H[(size_t)lc * n0 + k] = H;

@@ -169,6 +169,83 @@ def test_thick_isothermal_atmosphere_has_planck_mean_intensity():
     assert checked >= 8 + 2
 
 
+def test_inclined_static_atmosphere_matches_the_inclined_formal_solve():
+    """2D invariance in the non-LTE oracle (Sec. 3.1): in an atmosphere at
+    rest the fields are isotropic, so its J with 3 inclinations equals the
+    formal-solve oracle's inclined solve (a separate code path: isotropic
+    chi and eta arrays, the path scaled through the voxel size) of the same
+    fields, wavelength by wavelength."""
+    inp = W.nlte_atmosphere(24, seed=7, n_line=12, n_cont=8)
+    inp.vel[...] = 0.0
+    P = nlte.Problem(inp, n_incl=3)
+    J = P.formal_solve(P.lte)[0]
+    chi_c, eta_c, kappa, eps = P.fields(P.lte)
+    chi = chi_c.copy()
+    eta = eta_c.copy()
+    for lam in range(len(P.nu)):
+        li = P.line_index[lam]
+        if li >= 0:
+            H = nlte.voigt_H(P.adamp[li], np.abs(P.u[lam]) / P.vth)
+            chi[lam] += kappa[li] * H
+            eta[lam] += eps[li] * H
+    ref = oracle.formal_solve_inclined(chi.reshape(-1, 24, 24), eta.reshape(-1, 24, 24), P.n_casc, 3,
+                                       voxel=inp.voxel).reshape(len(P.nu), -1)
+    np.testing.assert_allclose(J, ref, rtol=1e-11)
+
+
+def test_inclined_rays_are_flatland_rays_with_projected_velocity_and_longer_paths():
+    """Inclination m of the non-LTE oracle equals the flatland problem whose
+    cells are 1/sin(theta_m) longer and whose velocities are sin(theta_m)
+    times the in-plane ones: the cascade-0 radiances, the local opacities and
+    profiles, and the rates summed with the Gauss-Radau weights."""
+    inp = W.nlte_atmosphere(16, seed=8, n_line=12, n_cont=8)
+    P = nlte.Problem(inp, n_incl=3)
+    J, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    Rup, Rdn = P.rates(P.lte, I0, chi_loc, H_loc)
+    mu, w = oracle.radau_inclinations(3)
+    Jsum = np.zeros_like(J)
+    Usum = np.zeros_like(Rup)
+    Dsum = np.zeros_like(Rdn)
+    for m in range(3):
+        sm = math.sqrt(1.0 - mu[m] ** 2)
+        q = W.NlteInput(inp.T, inp.ne, inp.ntot, (inp.vel.astype(np.float64) * sm).astype(np.float32),
+                        inp.lambda_nm, inp.trans, inp.dnu, inp.voxel / sm, inp.atom, "scaled")
+        Q = nlte.Problem(q)
+        # the velocity is rounded to FP32 again after scaling: compare the
+        # opacities at the precision that leaves
+        Jm, I0m, chim, Hm, _ = Q.formal_solve(Q.lte)
+        np.testing.assert_allclose(I0[m], I0m, rtol=1e-6)
+        np.testing.assert_allclose(chi_loc[m], chim, rtol=1e-6)
+        u, d = Q.rates(Q.lte, I0m, chim, Hm)
+        Jsum += w[m] * Jm
+        Usum += w[m] * u
+        Dsum += w[m] * d
+    np.testing.assert_allclose(J, Jsum, rtol=1e-6)
+    np.testing.assert_allclose(Rup, Usum, rtol=1e-5, atol=1e-6 * np.abs(Rup).max())
+    np.testing.assert_allclose(Rdn, Dsum, rtol=1e-5, atol=1e-6 * np.abs(Rdn).max())
+
+
+def test_thick_isothermal_atmosphere_with_inclinations_has_planck_mean_intensity():
+    """J = B_nu(T) deep in a thick isothermal atmosphere for any quadrature
+    of inclinations (every inclined ray sees the same source function)."""
+    n = 24
+    base = W.nlte_atmosphere(n, seed=9, n_line=12, n_cont=8)
+    T = np.full((n, n), 6000.0)
+    ntot = np.full((n, n), 5e19)
+    inp = W.NlteInput(T, 0.2 * ntot, ntot, np.zeros((2, n, n), np.float32), base.lambda_nm, base.trans, base.dnu,
+                      base.voxel, base.atom, "isothermal")
+    P = nlte.Problem(inp, n_incl=8)
+    chi_c, _, _, _ = P.fields(P.lte)
+    J = P.formal_solve(P.lte)[0]
+    inner = np.zeros((n, n), bool)
+    inner[6:-6, 6:-6] = True
+    inner = inner.ravel()
+    for lam, t in enumerate(P.trans_of):
+        tr = P.atom.trans[t]
+        if tr.kind == "cont":
+            np.testing.assert_allclose(J[lam][inner], _planck(P.nu[lam], P.T)[inner], rtol=1e-10)
+
+
 def test_collision_dominated_limit_is_lte():
     """Collisions far above radiative rates force Saha-Boltzmann populations."""
     d = dict(W.SYNTH_ATOM)
