@@ -66,17 +66,26 @@ def parse():
                     help="also run the batched formal solve of 16 uneven atmospheres (256^2..2048^2, "
                          "32..256 wavelengths; ~190 GB of device memory, a few minutes)")
     ap.add_argument("--nlte-only", action="store_true",
-                    help="only the converged non-LTE solves (for profiling; prints their object)")
+                    help="only the converged non-LTE solves (prints their object)")
+    ap.add_argument("--nlte-profile", type=int, default=0,
+                    help="only this many plain FP32 non-LTE iterations from LTE (for profiling the line march)")
+    ap.add_argument("--mlp-profile", type=int, default=0,
+                    help="only this many warm-start network training steps and forward passes on seeded data "
+                         "(batch 65536; for profiling the BF16 MFMA products)")
     ap.add_argument("--nlte-variants", default="plain_fp32,plain_fp16,learned_fp32,learned_fp16",
                     help="comma-separated subset of the non-LTE runs (also ng_fp32, learned_ng_fp16, "
                          "charge_fp32, sparse_fp32)")
     ap.add_argument("--nlte-n", type=int, default=1024)
+    ap.add_argument("--nlte-seed", type=int, default=3, help="seed of the non-LTE atmosphere")
     ap.add_argument("--nlte-corona", type=float, default=0.0,
                     help="fraction of the non-LTE atmosphere turned into 1e6 K corona (for sparse_fp32)")
     ap.add_argument("--nlte-max-iter", type=int, default=300)
     ap.add_argument("--nlte-ref-max-iter", type=int, default=200)
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "warmstart_mlp.npz"),
                     help="trained warm-start network (skipped when absent)")
+    ap.add_argument("--orders", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "launch_orders.jsonl"),
+                    help="launch-order cache of the autotuner (rcx_autotune); a miss tunes and appends")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch orders")
     return ap.parse_args()
 
 
@@ -211,10 +220,12 @@ def nlte_solves(args):
     import torch
 
     from paper_2408_14425_amd import rcx, warmstart, workloads
-    inp = workloads.nlte_atmosphere(args.nlte_n, seed=3, n_line=64, n_cont=32, corona_frac=args.nlte_corona)
+    inp = workloads.nlte_atmosphere(args.nlte_n, seed=args.nlte_seed, n_line=64, n_cont=32,
+                                    corona_frac=args.nlte_corona)
     corona = f", {args.nlte_corona:.0%} of the cells 1e6 K corona" if args.nlte_corona > 0 else ""
     out = {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz} grid, {inp.n_wave} wavelengths "
-                       f"(2 lines x 64 + 32 continuum), synthetic 3-level + continuum atom, seed 3{corona}",
+                       f"(2 lines x 64 + 32 continuum), synthetic 3-level + continuum atom, seed {args.nlte_seed}"
+                       f"{corona}",
            "criterion": "max relative change < 1e-3 (Sec. 4.2); equal accuracy: true error <= 1e-3 against "
                         "the reference"}
     net = None
@@ -310,6 +321,61 @@ def nlte_solves(args):
     return out
 
 
+def nlte_profile(args):
+    """Plain FP32 non-LTE iterations from LTE (one untimed first), with the
+    seconds per iteration: the command the line march's profiles run."""
+    import torch
+
+    from paper_2408_14425_amd import rcx, workloads
+    inp = workloads.nlte_atmosphere(args.nlte_n, seed=args.nlte_seed, n_line=64, n_cont=32)
+    s = rcx.Nlte(inp)
+    p = s.lte()
+    s.iterate(p, 1, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, ch = s.iterate(p, args.nlte_profile, 0.0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s.close()
+    return {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz}, {inp.n_wave} wavelengths, seed {args.nlte_seed}",
+            "iterations": it, "s_per_iteration": dt / max(it, 1), "last_change": ch}
+
+
+def mlp_profile(args):
+    """Training steps and forward passes of the warm-start network
+    (6 -> 4 x 128 -> 4, BF16 MFMA) on seeded data, batch 65536: the command
+    the MLP kernels' profiles run. FLOP per sample: 2 x 50,432 multiply-adds
+    forward, 3 x that for a training step (forward, input and weight
+    gradients)."""
+    import numpy as np
+    import torch
+
+    from paper_2408_14425_amd import rcx, workloads
+    batch = 65536
+    rng = np.random.default_rng(0)
+    x = torch.from_numpy(rng.standard_normal((batch, 6)).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.standard_normal((batch, 4)).astype(np.float32)).cuda()
+    net = rcx.Mlp(6, 128, 4, 4, max_batch=batch)
+    net.set_params(workloads.mlp_init_params(6, 128, 4, 4, seed=0))
+    net.train_step(x, y, 1e-3)
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.mlp_profile):
+        net.train_step(x, y, 1e-3)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / args.mlp_profile
+    t0 = time.perf_counter()
+    for _ in range(args.mlp_profile):
+        net.forward(x)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / args.mlp_profile
+    net.close()
+    macs = 6 * 128 + 3 * 128 * 128 + 128 * 4
+    return {"batch": batch, "ms_per_train_step": t_train * 1e3, "ms_per_forward": t_fwd * 1e3,
+            "train_TFLOPs": 3 * 2 * macs * batch / t_train / 1e12, "forward_TFLOPs": 2 * macs * batch / t_fwd / 1e12}
+
+
 def c4_batched(args):
     """The 16-atmosphere uneven batch in one batched solve (HIP graph), FP32
     and FP16 cascade storage: time per solve, ray intervals per second, and
@@ -397,14 +463,27 @@ def main():
     if args.nlte_only:
         print(json.dumps(nlte_solves(args)), flush=True)
         return
+    if args.nlte_profile:
+        print(json.dumps(nlte_profile(args)), flush=True)
+        return
+    if args.mlp_profile:
+        print(json.dumps(mlp_profile(args)), flush=True)
+        return
 
     inp = workloads.line_medium(args.n, args.waves, seed=2)
     dev = torch.device("cuda:0")
     chi = torch.from_numpy(inp.chi).to(dev)
     eta = torch.from_numpy(inp.eta).to(dev)
     J = torch.empty_like(chi)
-    plan = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
+    def tuned(plan):
+        """The plan with its launch orders from the autotuner (cached)."""
+        if not args.no_autotune:
+            plan.autotune(args.orders)
+        return plan
+
+    plan = tuned(rcx.Plan(inp.nx, inp.nz, inp.n_wave))
     work = plan.work()
+    orders = [plan.get_order(i) for i in range(work.n_cascades)]
     dt, (ms_level, ms_other, n_launch, n_solves) = time_solves(plan, chi, eta, J, args.steps, args.warmup)
     ok = bool(torch.isfinite(J).all().item())
     plan.close()
@@ -412,7 +491,7 @@ def main():
     fp16 = None
     if not args.no_fp16:
         # the same solve with FP16 cascade storage
-        plan16 = rcx.Plan(inp.nx, inp.nz, inp.n_wave, storage=rcx.RCX_STORE_F16_SCALED)
+        plan16 = tuned(rcx.Plan(inp.nx, inp.nz, inp.n_wave, storage=rcx.RCX_STORE_F16_SCALED))
         J16 = torch.empty_like(chi)
         dt16, _ = time_solves(plan16, chi, eta, J16, args.steps, args.warmup)
         plan16.close()
@@ -426,7 +505,7 @@ def main():
     if not args.no_incl:
         # the same solve with the paper's 8 inclinations per flatland ray
         # (2D invariance): 8 x the ray intervals, J the hemisphere average
-        planI = rcx.Plan(inp.nx, inp.nz, inp.n_wave, n_incl=8)
+        planI = tuned(rcx.Plan(inp.nx, inp.nz, inp.n_wave, n_incl=8))
         workI = planI.work()
         JI = torch.empty_like(chi)
         stepsI = max(1, min(args.steps, 3))
@@ -445,7 +524,7 @@ def main():
     if not args.no_fix:
         # the same solve with the bilinear fix: 4 traced rays per interval on
         # every cascade below the top
-        planF = rcx.Plan(inp.nx, inp.nz, inp.n_wave, bilinear_fix=True)
+        planF = tuned(rcx.Plan(inp.nx, inp.nz, inp.n_wave, bilinear_fix=True))
         JF = torch.empty_like(chi)
         stepsF = max(1, min(args.steps, 5))
         dtF, (msF, _, _, nF) = time_solves(planF, chi, eta, JF, stepsF, 1)
@@ -468,6 +547,7 @@ def main():
         act = workloads.active_cells(inp.nx, inp.nz, seed=7, frac=0.25)
         planS = rcx.Plan(inp.nx, inp.nz, inp.n_wave)
         counts = planS.set_active(act)
+        tuned(planS)
         JS = torch.empty_like(chi)
         stepsS = max(1, min(args.steps, 5))
         dtS, (msS, _, _, nS) = time_solves(planS, chi, eta, JS, stepsS, 1)
@@ -530,6 +610,8 @@ def main():
             "cell_steps_per_step": work.cell_steps * inp.n_wave,
             "cell_steps_per_s": work.cell_steps * inp.n_wave / (dt / args.steps),
             "kernel_ms_per_cascade": [m / max(n_solves, 1) for m in ms_level],
+            "launch_orders": {"per_cascade_tile_p_tile_d_xcd_chunk": orders,
+                              "source": "defaults" if args.no_autotune else os.path.relpath(args.orders, ROOT)},
             "kernel_ms_prep_and_J": ms_other / max(n_solves, 1),
             "finite": ok,
         },

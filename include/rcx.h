@@ -86,10 +86,10 @@ typedef struct {
  *               fixed; J = sum_m w_m J_m, J_m the flatland J with the path
  *               per projected cell scaled by 1/sqrt(1 - mu_m^2). 1 = flatland
  *               (the default); the paper uses 8 (with FP32 cascades the 8
- *               run as slots of one march: 8 x the cascade workspace). Only
- *               the formal solve
- *               (rcx_formal_solve) supports n_incl > 1; batches and the
- *               non-LTE solver return RCX_E_UNSUPPORTED for it.
+ *               run as slots of one march: 8 x the cascade workspace).
+ *               The formal solve and the non-LTE solver support n_incl > 1
+ *               (the non-LTE solver marches one pass per inclination);
+ *               batches return RCX_E_UNSUPPORTED for it.
  *   flags:      RCX_FLAG_BILINEAR_FIX, RCX_FLAG_CHECK_INPUT or their OR, or 0
  *               (other bits must be 0).
  *               RCX_FLAG_BILINEAR_FIX (Sec. 2.5, the remedy for ringing and
@@ -223,6 +223,33 @@ int32_t rcx_plan_set_timing(rcx_plan* plan, int32_t enable);
 int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_other_host,
                             int64_t* n_march_launches_host, int64_t* n_solves_host);
 
+/* Launch order of cascade `level`'s march (the rays of a launch run in
+ * this order; results do not depend on it): tile_p = 0 for probe-major
+ * order (directions of a probe consecutive), else groups of tile_p x tile_p
+ * probes x tile_d directions (tile_d a multiple of 4 dividing the cascade's
+ * directions), and workgroups given to the 8 XCDs in chunks of xcd_chunk
+ * consecutive ones. Defaults: 4 x 4 x 32, chunk 128, on cascades with at
+ * least 256 directions; probe-major, chunk 128, below. A sparse plan's
+ * flagged-probe lists are rebuilt to follow the order (synchronous).
+ * RCX_E_INVALID for a bad level or order. */
+int32_t rcx_plan_set_order(rcx_plan* plan, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk);
+/* order3_host = {tile_p, tile_d, xcd_chunk} of cascade `level`. */
+int32_t rcx_plan_get_order(const rcx_plan* plan, int32_t level, int32_t* order3_host);
+
+/* Autotuner of the launch order (growth pattern (2)): for every cascade
+ * with at least 256 directions, times the plan's formal solve of up to 32
+ * wavelengths on uniform fields (the march's work and memory traffic do not
+ * depend on the values) for each candidate order, tile_p in {0, 2, 4, 8} x
+ * tile_d in {16, 32, 64} x xcd_chunk in {32, 128, 512}, with the plan's
+ * kernel timing, and keeps the fastest per cascade. cache_path (nullable): a
+ * text file of JSON lines keyed by the device (architecture, compute units)
+ * and the plan's geometry, storage, flags and sparsity; a hit applies the
+ * stored orders without timing, a miss appends the result. Allocates its
+ * temporary fields (and a workspace when the plan has none) and
+ * synchronises the stream; pending timing records are consumed. Errors:
+ * RCX_E_INVALID; RCX_E_NOMEM; RCX_E_HIP. */
+int32_t rcx_autotune(rcx_plan* plan, const char* cache_path, hipStream_t stream);
+
 /* Release a plan and its device memory. NULL is accepted. */
 int32_t rcx_plan_destroy(rcx_plan* plan);
 
@@ -250,10 +277,11 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
  * and writes J = 0 there. Rebuilds the task list (and the graph) on the next
  * solve. RCX_E_INVALID for a null batch or atm outside [0, n_atm). */
 int32_t rcx_batch_set_active_host(rcx_batch* s, int32_t atm, const uint8_t* active_host);
-/* Launch order of the cascades with >= 256 directions: groups of
- * tile_probes x tile_probes probes x 32 directions (default 4), or 0 for
- * probe-major order. Results do not depend on it. */
-int32_t rcx_batch_set_order(rcx_batch* b, int32_t tile_probes);
+/* Launch order of every atmosphere's cascades with >= 256 directions, as
+ * rcx_plan_set_order: groups of tile_probes x tile_probes probes x
+ * tile_dirs directions (default 4 x 4 x 32), or tile_probes = 0 for
+ * probe-major order. Results do not depend on it. Waits for the device. */
+int32_t rcx_batch_set_order(rcx_batch* b, int32_t tile_probes, int32_t tile_dirs);
 /* Enqueue through the captured graph (1, default) or by direct launches (0). */
 int32_t rcx_batch_set_graph(rcx_batch* b, int32_t enable);
 /* chi_host[a], eta_host[a], J_host[a]: host arrays of n_atm device pointers
@@ -270,10 +298,11 @@ int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float*
                         float* const* J_host, hipStream_t stream);
 /* Work summed over atmospheres and wavelengths (rcx_work semantics). */
 int32_t rcx_batch_work(const rcx_batch* b, int64_t* rays_nonempty_host, int64_t* cell_steps_host);
-/* Time each candidate launch order {0, 2, 4, 8} (rcx_batch_set_order) on
- * these inputs and keep the fastest (*best_host). cache_path (or NULL): a
- * text file of JSON lines keyed by the batch's shapes; a hit skips timing,
- * a miss appends the result. */
+/* Time each candidate launch order (tile_probes, tile_dirs) in {(0, -),
+ * (2, 32), (4, 16), (4, 32), (4, 64), (8, 32)} (rcx_batch_set_order) on
+ * these inputs and keep the fastest: *best_host = tile_probes * 1000 +
+ * tile_dirs. cache_path (or NULL): a text file of JSON lines keyed by the
+ * batch's shapes; a hit skips timing, a miss appends the result. */
 int32_t rcx_batch_autotune(rcx_batch* b, const float* const* chi_host, const float* const* eta_host,
                            float* const* J_host, const char* cache_path, int32_t* best_host, hipStream_t stream);
 int32_t rcx_batch_destroy(rcx_batch* b);
@@ -289,8 +318,10 @@ int32_t rcx_batch_destroy(rcx_batch* b);
  * Model: one atom, levels 0..n_levels-1 with the last level the continuum
  * (ionised stage); every wavelength belongs to exactly one transition (its
  * governing transition, Sec. 3.3), wavelengths are grouped by transition in
- * the order lines then continua; no background opacity; flatland angular
- * quadrature (weights 1/N_0); free-space boundary; electron density fixed. */
+ * the order lines then continua; no background opacity; angular
+ * quadrature 1/N_0 per cascade-0 direction, flatland or with the
+ * inclinations of rcx_params.n_incl; free-space boundary; electron density
+ * fixed unless charge conservation is on. */
 
 #define RCX_NLTE_MAX_LEVELS 6
 #define RCX_NLTE_MAX_LINES 8
@@ -329,7 +360,12 @@ typedef struct rcx_nlte rcx_nlte;
  * offset of each wavelength from its largest source function (lines:
  * S_line; continua: eta/chi); cascade 0, the rates and the rate matrix stay
  * FP32/FP64.
- * p: c0_dirs = 4, n_incl = 1, flags 0 or RCX_FLAG_CHECK_INPUT.
+ * p: c0_dirs = 4, flags 0 or RCX_FLAG_CHECK_INPUT; n_incl as for
+ * rcx_plan_create (Sec. 3.1: every inclination m marches the flatland rays
+ * with the path per projected cell 1/sin(theta_m) and sin(theta_m) of the
+ * in-plane velocity along them, in Psi* the path through the cell
+ * l / sin(theta_m); J and the rate coefficients are the sums over m with the
+ * Gauss-Radau weights; the paper iterates with 8).
  * Errors: RCX_E_INVALID (nulls, sizes, ungrouped or out-of-range
  * transitions, a wavelength outside its continuum's edge);
  * RCX_E_UNSUPPORTED (more levels/lines/continua than the maxima);

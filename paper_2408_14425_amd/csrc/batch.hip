@@ -140,7 +140,6 @@ struct rcx_batch {
     std::vector<size_t> casc_half;     // bytes of one of the two buffers
     std::vector<int32_t> casc_index;   // first slot of atmosphere a
     std::vector<int32_t> n_slots;      // slots of atmosphere a
-    int32_t tile_probes = 4;          // launch order of the upper cascades (0: probe-major)
     int64_t fill_rays = 1 << 19;      // rays a launch gathers before it stops activating chains
     std::vector<Task> tasks_h;        // grouped by generation, each group sorted by ray0
     Task* tasks_d = nullptr;
@@ -161,6 +160,9 @@ struct rcx_batch {
 namespace {
 
 int32_t bfail(int32_t c, const std::string& m) { return rcx::fail(c, m); }
+
+// Cascades whose launch order rcx_batch_set_order sets (the tiled ones).
+constexpr int32_t kWideDirs = 256;
 
 template <class P>
 hipError_t balloc(rcx_batch* s, P** p, size_t bytes)
@@ -198,8 +200,7 @@ bool build_work(rcx_batch* s, float* const* J)
             for (int32_t i = P->n_casc - 1; i >= 0; --i) {
                 if (P->top_skipped && i == P->n_casc - 1) continue;
                 Task T{};
-                T.L = P->levels[i];
-                if (T.L.tile_p > 0) T.L.tile_p = s->tile_probes;  // 0: probe-major
+                T.L = P->levels[i];  // the plan's launch order (rcx_batch_set_order sets it)
                 T.nx = P->grid.nx;
                 T.nz = P->grid.nz;
                 T.dirs = P->dirs_dev + P->dir_off[i];
@@ -428,10 +429,16 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
     return RCX_OK;
 }
 
-int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes)
+int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes, int32_t tile_dirs)
 {
     if (!s || tile_probes < 0 || tile_probes > 64) return bfail(RCX_E_INVALID, "rcx_batch_set_order: bad argument");
-    s->tile_probes = tile_probes;
+    RCX_HIP_TRY(hipDeviceSynchronize());  // a solve in flight reads the plans' lists
+    for (rcx_plan* P : s->plans)
+        for (int32_t i = 0; i < P->n_casc; ++i) {
+            if (P->levels[i].nd < kWideDirs) continue;
+            const int32_t rc = rcx_plan_set_order(P, i, tile_probes, tile_dirs, P->levels[i].xcd_chunk);
+            if (rc != RCX_OK) return rc;
+        }
     s->J_bound.clear();  // rebuild the task list on the next solve (after the stream has finished)
     drop_graph(s);
     return RCX_OK;
@@ -534,7 +541,7 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
     if (!s || !chi || !eta || !J || !best_rays_host) return bfail(RCX_E_INVALID, "rcx_batch_autotune: null argument");
     // cache key: the batch's shapes
     std::ostringstream key;
-    key << (s->f16 ? "f16" : "f32");
+    key << "v2_" << (s->f16 ? "f16" : "f32");
     for (int32_t a = 0; a < s->n_atm; ++a)
         if (s->plans[a]->mask_dev) key << "_sparse" << a << "_" << s->plans[a]->levels[0].n_active;
     for (int32_t a = 0; a < s->n_atm; ++a)
@@ -548,20 +555,21 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
             const size_t pos = line.find(pre);
             if (pos != std::string::npos) {
                 const int32_t r = std::atoi(line.c_str() + pos + pre.size());
-                if (r >= 0 && r <= 64) {
+                if (r >= 0 && r <= 64064) {
                     *best_rays_host = r;
-                    return rcx_batch_set_order(s, r);
+                    return rcx_batch_set_order(s, r / 1000, r % 1000);
                 }
             }
         }
     }
-    const int32_t cands[] = {0, 2, 4, 8};
+    // candidate (tile_probes, tile_dirs), coded tile_probes * 1000 + tile_dirs
+    const int32_t cands[] = {0, 2032, 4016, 4032, 4064, 8032};
     double best_ms = 1e300;
     int32_t best = cands[0];
     const bool g = s->use_graph;
     s->use_graph = false;
     for (int32_t cnd : cands) {
-        int32_t rc = rcx_batch_set_order(s, cnd);
+        int32_t rc = rcx_batch_set_order(s, cnd / 1000, cnd % 1000);
         if (rc != RCX_OK) return rc;
         rc = rcx_batch_solve(s, chi, eta, J, st);  // warm-up and work-list build
         if (rc != RCX_OK) return rc;
@@ -582,7 +590,7 @@ int32_t rcx_batch_autotune(rcx_batch* s, const float* const* chi, const float* c
         f << "{\"" << k << "\": " << best << ", \"ms\": " << best_ms << "}\n";
     }
     *best_rays_host = best;
-    return rcx_batch_set_order(s, best);
+    return rcx_batch_set_order(s, best / 1000, best % 1000);
 }
 
 int32_t rcx_batch_destroy(rcx_batch* s)

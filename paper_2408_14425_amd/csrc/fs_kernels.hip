@@ -107,6 +107,12 @@ __global__ void k_check_values(const T* __restrict__ a, int64_t n, int32_t range
     if ((threadIdx.x & 63) == 0 && (any1 | any2)) atomicOr(flag, any1 | any2);
 }
 
+__global__ void k_fill_f32(float* p, int64_t n, float v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 __global__ void k_fill_u32(unsigned int* p, int32_t n, unsigned int v)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,6 +198,13 @@ hipError_t launch_prep(const float* chi, const float* eta, float2* F, int32_t n_
     }
     dim3 grid((unsigned)((ncell + 63) / 64), (unsigned)nb);
     hipLaunchKernelGGL(k_prep, grid, dim3(256), 0, st, chi, eta, F, n_wave, ncell, voxel, smax_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st)
+{
+    const int64_t blocks = std::max<int64_t>(std::min<int64_t>((n + 255) / 256, 16384), 1);
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 

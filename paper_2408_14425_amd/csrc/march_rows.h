@@ -29,18 +29,19 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
 // Workgroups are dispatched round-robin over the 8 XCDs. XCD x takes
-// chunks of kXcdChunk consecutive logical blocks, chunk i on XCD i mod 8:
+// chunks of `chunk` consecutive logical blocks, chunk i on XCD i mod 8:
 // all XCDs advance through the ray order together (they share the field data
 // in the Infinity Cache) while each works on compact groups of rays (shared
 // in its own L2). The tail that does not fill 8 whole chunks keeps the
-// identity order.
+// identity order. The chunk is a launch parameter (LevelDesc::xcd_chunk,
+// chosen by the autotuner; 128 by default).
 constexpr unsigned kXcdChunk = 128;
-__device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb)
+__device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb, unsigned chunk = kXcdChunk)
 {
-    const unsigned full = nb / (kXcds * kXcdChunk) * (kXcds * kXcdChunk);
+    const unsigned full = nb / (kXcds * chunk) * (kXcds * chunk);
     if (b >= full) return b;
     const unsigned x = b % kXcds, slot = b / kXcds;
-    return (slot / kXcdChunk) * (kXcds * kXcdChunk) + x * kXcdChunk + slot % kXcdChunk;
+    return (slot / chunk) * (kXcds * chunk) + x * chunk + slot % chunk;
 }
 
 // 1 - 2^{-y} for y >= 0 (y = optical depth in log2 units) without
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t n
         }
         wave_sync();
     }
-    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, (unsigned)L.xcd_chunk);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
     for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
         int32_t k, u, v;
@@ -565,7 +566,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_fix(LevelDesc L, int32_t nx
     up.init(c.l);
     seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
     wave_sync();
-    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, (unsigned)L.xcd_chunk);
     const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t r = (int64_t)lb * (kBlock / 64) + c.w; r < total; r += stride) {
         int32_t k, u, v;

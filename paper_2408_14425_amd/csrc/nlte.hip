@@ -515,6 +515,7 @@ struct LineOpT {
     uint32_t ncell;
     float da_sqrtpi;    // damping step of the table / sqrt(pi)
     float u, wx, wz;
+    float vscale = 1.0f;  // velocity projection: sin(theta) of an inclined ray (Sec. 3.1), 1 in the plane
     const float2* tab;  // the LDS copy
     // the cell record and velocity are the same for all wavelength lanes;
     // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)} and holds
@@ -555,8 +556,8 @@ struct LineOpT {
     __device__ __forceinline__ void init(int l) { u = u_b[l]; }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
-        wx = (float)dwx;
-        wz = (float)dwz;
+        wx = (float)dwx * vscale;
+        wz = (float)dwz * vscale;
     }
     // H(a, |x|), x = (u + w . v) / v_th, from a record and a velocity
     __device__ __forceinline__ float profile(const float4& r, const float2& v) const
@@ -613,7 +614,9 @@ using LineOpSmallA = LineOpT<true>;
 //   I_eff = I - Psi* eta_t
 //   up   = W V_ij I_eff,   down = W (V_ji I_eff + U_ji (1 - chi_t Psi*))
 // (W = 4 pi dnu/(h nu) / N_0 per lane, 0 on padding lanes); the wavefront sum
-// goes to part[c] = {up, down}.
+// goes to part[c] = {up, down}. An inclined ray (Sec. 3.1) crosses the cell
+// on a path `path` = 1/sin(theta) times longer, its terms are weighted by
+// its quadrature weight `wgt`, and inclinations after the first add to part.
 struct RatesEpi {
     float* out;             // merged cascade 0 [rays][16] (for J)
     float2* part;           // [ncell] this batch's rate contributions
@@ -625,13 +628,21 @@ struct RatesEpi {
     float gr, U0;           // line: g_i/g_j, 2 h nu0^3 / c^2
     float ell_cells, voxel; // l in cells (the same for all N_0 directions), cell size [m]
     int32_t kind;           // 0 line, 1 continuum
+    float path = 1.0f, wgt = 1.0f;
+    bool acc = false;
 
     __device__ __forceinline__ void init(int) {}
 
+    // I is the merged radiance of the ray beyond its own cell: the launch
+    // marches [l, t_1) (l the distance from the cell centre to its edge
+    // along the ray, where the ray leaves the cell through a corner), and
+    // the cell's own part, Psi* eta_t = S (1 - e^{-tau}), is added here.
+    // Then I_eff = I_full - Psi* eta_t = e^{-tau} I is formed without the
+    // cancellation of two nearly equal FP32 numbers in optically thick
+    // cells, and 1 - chi_t Psi* = e^{-tau} likewise.
     template <class Op>
     __device__ __forceinline__ void finish(const march::RayInfo& ri, int l, int lane, float I, const Op& op)
     {
-        if (ri.active) out[ri.ray * kLB + l] = I;
         const int64_t cell = ri.ray / 4;  // cascade 0: ray = cell * 4 + direction
         float up = 0.0f, dn = 0.0f;
         if (ri.active) {
@@ -649,23 +660,33 @@ struct RatesEpi {
             }
             const float eta_t = e.y * Uji;
             const float chi_t = e.x * Vij - e.y * Vji;   // [1/m]
-            const float ellm = ell_cells * voxel;
+            const float ellm = ell_cells * voxel * path;
             const float tau = fmaxf(chi_t * ellm, 0.0f);
+            const float T1 = __builtin_amdgcn_exp2f(-tau * march::kLog2e);
             // phi1 = (1 - e^{-tau}) / tau: series below 1/64, direct above
             const float ser = 1.0f - tau * (0.5f - tau * (1.0f / 6.0f - tau * (1.0f / 24.0f)));
-            const float phi1 = tau < (1.0f / 64.0f) ? ser : (1.0f - __builtin_amdgcn_exp2f(-tau * march::kLog2e)) / tau;
+            const float phi1 = tau < (1.0f / 64.0f) ? ser : (1.0f - T1) / tau;
             const float psi = ellm * phi1;
-            const float ieff = I - psi * eta_t;
-            const float wv = W[l];
+            const float ieff = T1 * I;
+            out[ri.ray * kLB + l] = fmaf(psi, eta_t, ieff);
+            const float stim = chi_t > 0.0f ? T1 : 1.0f - chi_t * psi;
+            const float wv = W[l] * wgt;
             up = (wv * Vij) * ieff;
-            dn = (wv * Vji) * ieff + (wv * Uji) * (1.0f - chi_t * psi);
+            dn = (wv * Vji) * ieff + (wv * Uji) * stim;
         }
         // wavefront sum (fixed butterfly order: deterministic)
         for (int m = 32; m >= 1; m >>= 1) {
             up += __shfl_xor(up, m);
             dn += __shfl_xor(dn, m);
         }
-        if (lane == 0 && ri.active) part[cell] = make_float2(up, dn);
+        if (lane == 0 && ri.active) {
+            if (acc) {
+                const float2 o = part[cell];
+                part[cell] = make_float2(o.x + up, o.y + dn);
+            } else {
+                part[cell] = make_float2(up, dn);
+            }
+        }
     }
 
     // H at the cell itself along the ray (only a line op has a profile).
@@ -1065,6 +1086,7 @@ hipError_t launch_level_op(int32_t kind, bool small_a, const LevelDesc& L, int32
         sop.u_b = lop.u_b;
         sop.ncell = lop.ncell;
         sop.da_sqrtpi = lop.da_sqrtpi;
+        sop.vscale = lop.vscale;
         return launch_level(L, nx, nz, sop, epi, dirs, up, st);
     }
     return launch_level(L, nx, nz, lop, epi, dirs, up, st);
@@ -1135,7 +1157,6 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
         atom->n_lines > RCX_NLTE_MAX_LINES || atom->n_conts < 0 || atom->n_conts > RCX_NLTE_MAX_CONTS)
         return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: atom exceeds the supported sizes");
     if (p->c0_dirs != 4) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: the rate epilogue needs c0_dirs = 4");
-    if (p->n_incl != 1) return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: flatland only (n_incl = 1)");
     if ((p->flags & ~RCX_FLAG_CHECK_INPUT) != 0)
         return nlte_fail(RCX_E_UNSUPPORTED, "rcx_nlte_create: only RCX_FLAG_CHECK_INPUT (basic merge only)");
     const int32_t nt = atom->n_lines + atom->n_conts;
@@ -1166,6 +1187,12 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     if (rc != RCX_OK) {
         delete s;
         return rc;
+    }
+    // the solver keeps its own field and cascade buffers: the plan's
+    // workspace (sized for its inclination slots) is not needed
+    if (s->plan->ws_own) {
+        (void)hipFree(s->plan->ws_own);
+        s->plan->ws_own = nullptr;
     }
     s->n_wave = n_wave;
     s->ncell = (int64_t)g->nx * g->nz;
@@ -1526,6 +1553,11 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         }
     }
     if (s->f16) RCX_HIP_TRY(launch_ebias(nb * kLB, s->smax, s->ebias, st));
+    // 2D invariance (Sec. 3.1): every inclination m marches the flatland
+    // rays with its path per projected cell 1/sin(theta_m) and sin(theta_m)
+    // of the in-plane velocity; J and the rates sum w_m times its share
+    for (int32_t m = 0; m < P->prm.n_incl; ++m) {
+    const double path = P->incl_scale[m], wm = P->incl_w[m];
     for (int32_t b = 0; b < nb; ++b) {
         const auto& B = s->batches[b];
         const Trans& tr = A.t[B.trans];
@@ -1542,6 +1574,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             lop.u_b = bc + 1 * kLB;
             lop.ncell = (uint32_t)nc;
             lop.da_sqrtpi = (float)(s->da_c / std::sqrt(kPi));
+            lop.vscale = (float)(1.0 / path);
         }
         RatesEpi re{};
         re.part = s->part + b * nc;
@@ -1555,12 +1588,19 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         re.ell_cells = (float)std::sqrt(0.5);
         re.voxel = (float)s->voxel;
         re.kind = tr.kind;
+        re.path = (float)path;
+        re.wgt = (float)wm;
+        re.acc = m > 0;
         const int32_t* eb_b = s->ebias + (size_t)b * kLB;
         int cur = 0;
         const void* up = nullptr;
         for (int32_t i = P->n_casc - 1; i >= 0; --i) {
             if (P->top_skipped && i == P->n_casc - 1) continue;
-            const LevelDesc& L = P->levels[i];
+            LevelDesc L = P->levels[i];
+            L.ds_scale = path;
+            // cascade 0 (the rate epilogue): the cell's own part of the
+            // interval is added analytically by RatesEpi
+            if (i == 0) L.ta = std::sqrt(0.5);
             const double4* dirs = P->dirs_dev + P->dir_off[i];
             float* outb = s->casc[cur];
             const void* upl = L.has_up ? up : nullptr;
@@ -1588,7 +1628,8 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             up = outb;
             cur ^= 1;
         }
-        if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, 1.0f, false, st));
+        if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, (float)wm, m > 0, st));
+    }
     }
     hipLaunchKernelGGL(k_rates_sum, dim3(blocks_for(nc, 256)), dim3(256), 0, st, nc, A.nt, s->d_tb, s->d_tb + A.nt,
                        s->part, rates);

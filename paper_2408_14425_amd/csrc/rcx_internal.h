@@ -24,6 +24,9 @@ struct LevelDesc {
     // groups of tile_p x tile_p probes x tile_d directions, so the rays a
     // launch runs at one time cross a compact band of cells.
     int32_t tile_p, tile_d;
+    // workgroups are given to the 8 XCDs in chunks of xcd_chunk consecutive
+    // ones (march_rows.h, xcd_block_chunked)
+    int32_t xcd_chunk = 128;
     // path length per unit of projected (x-z) length: 1 / sin(theta) for a
     // ray inclined at theta to the invariant y axis; 1 in flatland
     double ds_scale = 1.0;
@@ -68,6 +71,8 @@ constexpr int32_t kCheckNonNegative = 0;  // v >= 0
 constexpr int32_t kCheckPositive = 1;     // v > 0
 constexpr int32_t kCheckFinite = 2;       // any finite v
 hipError_t launch_zero_flag(unsigned int* flag, hipStream_t st);
+// p[0..n) = v.
+hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t st);
 hipError_t launch_check_f32(const float* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st);
 hipError_t launch_check_f64(const double* a, int64_t n, int32_t range, unsigned int* flag, hipStream_t st);
 // Read the flag back (synchronises st): RCX_OK if 0, else RCX_E_NONFINITE
@@ -153,6 +158,7 @@ struct rcx_plan {
     // flagged probe lists of every cascade (levels[i].plist points here)
     uint8_t* mask_dev = nullptr;
     int32_t* plist_dev = nullptr;
+    std::vector<uint8_t> active_host;  // the flags last given (the lists follow the launch order)
     void* ws_own = nullptr;
     size_t ws_own_bytes = 0;
     void* scratch = nullptr;  // the library's scratch on the plan's device (rcx_formal_solve_noalloc)

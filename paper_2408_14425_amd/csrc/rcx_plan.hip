@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -627,6 +629,11 @@ int32_t rcx_plan_set_active_host(rcx_plan* p, const uint8_t* active_host, int64_
 {
     if (!p) return fail(RCX_E_INVALID, "rcx_plan_set_active_host: null plan");
     const int32_t nx = p->grid.nx, nz = p->grid.nz;
+    // keep the flags: a change of launch order rebuilds the lists from them
+    if (active_host && active_host != p->active_host.data())
+        p->active_host.assign(active_host, active_host + (size_t)nx * nz);
+    else if (!active_host)
+        p->active_host.clear();
     // drop any previous flags: every probe active
     hipError_t e = hipSuccess;
     if (p->mask_dev) e = hipFree(p->mask_dev);
@@ -809,6 +816,151 @@ int32_t rcx_plan_get_timing(rcx_plan* p, double* ms_level, double* ms_other, int
     *n_solves = p->n_solves;
     p->n_solves = 0;
     return rc == RCX_OK ? ok() : rc;
+}
+
+int32_t rcx_plan_set_order(rcx_plan* p, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk)
+{
+    if (!p || level < 0 || level >= p->n_casc) return fail(RCX_E_INVALID, "rcx_plan_set_order: bad plan or level");
+    LevelDesc& L = p->levels[level];
+    if (tile_p < 0 || tile_p > 64 || xcd_chunk < 1 || xcd_chunk > (1 << 16))
+        return fail(RCX_E_INVALID, "rcx_plan_set_order: tile_p must be in [0, 64], xcd_chunk in [1, 65536]");
+    if (tile_p > 0 && (tile_d < 4 || tile_d % 4 != 0 || L.nd % tile_d != 0))
+        return fail(RCX_E_INVALID, "rcx_plan_set_order: tile_d must be a multiple of 4 dividing the directions");
+    L.tile_p = tile_p;
+    L.tile_d = tile_p > 0 ? tile_d : 0;
+    L.xcd_chunk = xcd_chunk;
+    if (p->mask_dev) {
+        // the flagged-probe lists follow the launch order: rebuild them
+        const std::vector<uint8_t> flags = p->active_host;
+        return rcx_plan_set_active_host(p, flags.data(), nullptr);
+    }
+    return ok();
+}
+
+int32_t rcx_plan_get_order(const rcx_plan* p, int32_t level, int32_t* order3_host)
+{
+    if (!p || !order3_host || level < 0 || level >= p->n_casc)
+        return fail(RCX_E_INVALID, "rcx_plan_get_order: bad argument");
+    const LevelDesc& L = p->levels[level];
+    order3_host[0] = L.tile_p;
+    order3_host[1] = L.tile_d;
+    order3_host[2] = L.xcd_chunk;
+    return ok();
+}
+
+int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
+{
+    if (!p) return fail(RCX_E_INVALID, "rcx_autotune: null plan");
+    const int32_t nx = p->grid.nx, nz = p->grid.nz;
+    const int64_t ncell = (int64_t)nx * nz;
+    const int32_t n_wave = std::min(p->max_wave, 2 * batch_width());
+    std::vector<int32_t> tun;  // the cascades whose launch order is tuned
+    for (int32_t i = 0; i < p->n_casc; ++i)
+        if (p->levels[i].nd >= kTileMinDirs && !(p->top_skipped && i == p->n_casc - 1)) tun.push_back(i);
+    if (tun.empty()) return ok();
+    int dev = 0;
+    RCX_HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    RCX_HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    std::ostringstream key;
+    key << prop.gcnArchName << "/" << prop.multiProcessorCount << "cu/" << nx << "x" << nz << "/c" << p->n_casc
+        << "/d" << p->prm.c0_dirs << "/t1=" << p->prm.c0_t1 << "/r" << p->prm.t_rule << "/s" << p->prm.storage
+        << "/i" << p->prm.n_incl << "/f" << (p->prm.flags & RCX_FLAG_BILINEAR_FIX) << "/w" << n_wave;
+    if (p->mask_dev) key << "/sparse" << p->levels[0].n_active;
+    const std::string k = key.str();
+    const std::string pre = "{\"key\": \"" + k + "\", \"orders\": \"";
+    if (cache_path) {
+        std::ifstream f(cache_path);
+        std::string line;
+        while (std::getline(f, line)) {
+            if (line.compare(0, pre.size(), pre) != 0) continue;
+            // "level:tile_p:tile_d:chunk,..." up to the closing quote
+            std::istringstream in(line.substr(pre.size(), line.find('"', pre.size()) - pre.size()));
+            std::string item;
+            int32_t rc = RCX_OK;
+            while (rc == RCX_OK && std::getline(in, item, ',')) {
+                int lv = -1, tp = 0, td = 0, ch = 0;
+                if (std::sscanf(item.c_str(), "%d:%d:%d:%d", &lv, &tp, &td, &ch) == 4)
+                    rc = rcx_plan_set_order(p, lv, tp, td, ch);
+            }
+            return rc;
+        }
+    }
+    // time candidate orders on uniform fields (the march's work and memory
+    // traffic do not depend on the values)
+    struct Cand {
+        int32_t tp, td, ch;
+    };
+    std::vector<Cand> cands;
+    for (int32_t ch : {32, 128, 512}) {
+        cands.push_back({0, 0, ch});
+        for (int32_t tp : {2, 4, 8})
+            for (int32_t td : {16, 32, 64}) cands.push_back({tp, td, ch});
+    }
+    std::vector<LevelDesc> saved = p->levels;
+    const bool timing = p->timing;
+    float* buf = nullptr;
+    void* ws = nullptr;
+    const size_t nfield = (size_t)n_wave * ncell;
+    hipError_t e = hipMalloc(&buf, sizeof(float) * 3 * nfield);
+    const size_t ws_bytes = ws_layout(p, n_wave).total;
+    if (e == hipSuccess && !p->ws_own) e = hipMalloc(&ws, ws_bytes);
+    if (e != hipSuccess) {
+        if (buf) (void)hipFree(buf);
+        return fail(RCX_E_NOMEM, "rcx_autotune: temporary fields");
+    }
+    int32_t rc = RCX_OK;
+    e = launch_fill_f32(buf, (int64_t)2 * nfield, 1.0f, st);
+    std::vector<std::vector<double>> ms(cands.size(), std::vector<double>(p->n_casc, 0.0));
+    std::vector<double> lvl(p->n_casc);
+    double other = 0.0;
+    int64_t nl = 0, ns = 0;
+    for (size_t c = 0; c < cands.size() && rc == RCX_OK && e == hipSuccess; ++c) {
+        for (int32_t i : tun) {
+            const int32_t td = cands[c].tp > 0 && p->levels[i].nd % cands[c].td != 0 ? 4 : cands[c].td;
+            rc = rcx_plan_set_order(p, i, cands[c].tp, td, cands[c].ch);
+            if (rc != RCX_OK) break;
+        }
+        if (rc != RCX_OK) break;
+        p->timing = false;
+        rc = rcx_formal_solve(p, n_wave, buf, buf + nfield, buf + 2 * nfield, ws, ws_bytes, st);
+        if (rc != RCX_OK) break;
+        p->timing = true;
+        for (int r = 0; r < 2 && rc == RCX_OK; ++r)
+            rc = rcx_formal_solve(p, n_wave, buf, buf + nfield, buf + 2 * nfield, ws, ws_bytes, st);
+        if (rc == RCX_OK) rc = rcx_plan_get_timing(p, lvl.data(), &other, &nl, &ns);
+        ms[c] = lvl;
+    }
+    p->timing = timing;
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (ws) (void)hipFree(ws);
+    if (e != hipSuccess && rc == RCX_OK) rc = hip_fail(e, "rcx_autotune");
+    if (rc != RCX_OK) {
+        p->levels = saved;
+        if (p->mask_dev) {
+            const std::vector<uint8_t> flags = p->active_host;
+            (void)rcx_plan_set_active_host(p, flags.data(), nullptr);
+        }
+        return rc;
+    }
+    std::ostringstream orders, times;
+    for (size_t q = 0; q < tun.size(); ++q) {
+        const int32_t i = tun[q];
+        size_t best = 0;
+        for (size_t c = 1; c < cands.size(); ++c)
+            if (ms[c][i] < ms[best][i]) best = c;
+        const int32_t td = cands[best].tp > 0 && p->levels[i].nd % cands[best].td != 0 ? 4 : cands[best].td;
+        rc = rcx_plan_set_order(p, i, cands[best].tp, td, cands[best].ch);
+        if (rc != RCX_OK) return rc;
+        orders << (q ? "," : "") << i << ":" << cands[best].tp << ":" << p->levels[i].tile_d << ":" << cands[best].ch;
+        times << (q ? "," : "") << i << ":" << ms[best][i] / 2.0 << "/" << ms[0][i] / 2.0;
+    }
+    if (cache_path) {
+        std::ofstream f(cache_path, std::ios::app);
+        f << pre << orders.str() << "\", \"ms_best_vs_first\": \"" << times.str() << "\"}\n";
+    }
+    return ok();
 }
 
 int32_t rcx_plan_destroy(rcx_plan* p)

@@ -75,6 +75,9 @@ def load() -> C.CDLL:
     L.rcx_emergent.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, i32, vp, vp]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.rcx_formal_solve_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.rcx_plan_set_order.argtypes = [vp, i32, i32, i32, i32]
+    L.rcx_plan_get_order.argtypes = [vp, i32, C.POINTER(i32)]
+    L.rcx_autotune.argtypes = [vp, C.c_char_p, vp]
     L.rcx_plan_destroy.argtypes = [vp]
     L.rcx_plan_set_timing.argtypes = [vp, i32]
     L.rcx_plan_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -84,7 +87,8 @@ def load() -> C.CDLL:
     L.rcx_last_error.argtypes = [C.c_char_p, sz]
     for name in ("rcx_params_default", "rcx_plan_create", "rcx_plan_workspace_bytes", "rcx_plan_work",
                  "rcx_formal_solve", "rcx_plan_destroy", "rcx_last_error", "rcx_plan_set_timing",
-                 "rcx_plan_get_timing", "rcx_plan_set_active_host", "rcx_emergent", "rcx_formal_solve_noalloc"):
+                 "rcx_plan_get_timing", "rcx_plan_set_active_host", "rcx_emergent", "rcx_formal_solve_noalloc",
+                 "rcx_plan_set_order", "rcx_plan_get_order", "rcx_autotune"):
         getattr(L, name).restype = i32
     _lib = L
     return L
@@ -265,6 +269,23 @@ class Plan:
             J = torch.empty_like(chi)
         rcx_formal_solve(self.handle, n_wave, chi, eta, J, workspace, stream)
         return J
+
+    def set_order(self, level: int, tile_p: int, tile_d: int = 32, xcd_chunk: int = 128):
+        """Launch order of cascade `level` (tile_p = 0: probe-major)."""
+        _check(load().rcx_plan_set_order(self.handle, int(level), int(tile_p), int(tile_d), int(xcd_chunk)),
+               "rcx_plan_set_order")
+
+    def get_order(self, level: int):
+        out = (C.c_int32 * 3)()
+        _check(load().rcx_plan_get_order(self.handle, int(level), out), "rcx_plan_get_order")
+        return tuple(out)
+
+    def autotune(self, cache_path=None, stream=None):
+        """Tune the launch order of the wide cascades (cached per device and
+        geometry in cache_path); returns the orders per cascade."""
+        _check(load().rcx_autotune(self.handle, None if cache_path is None else str(cache_path).encode(),
+                                   _stream_ptr(stream)), "rcx_autotune")
+        return [self.get_order(i) for i in range(self.work().n_cascades)]
 
     def formal_solve_noalloc(self, chi, eta, J, stream=None):
         """rcx_formal_solve_noalloc: the solve in the library's scratch (no
@@ -447,11 +468,13 @@ class Nlte:
     ``workloads.NlteInput``); arrays live on ``cuda:0``."""
 
     def __init__(self, inp, n_cascades: int = 0, storage: int = RCX_STORE_F32,
-                 line_profile: int = RCX_PROFILE_AUTO, check_input: bool = False, set_atmosphere: bool = True):
+                 line_profile: int = RCX_PROFILE_AUTO, check_input: bool = False, set_atmosphere: bool = True,
+                 n_incl: int = 1):
         import torch
         p = rcx_params_default()
         p.n_cascades = n_cascades
         p.storage = storage
+        p.n_incl = n_incl
         p.flags = RCX_FLAG_CHECK_INPUT if check_input else 0
         self.inp = inp
         self.handle = rcx_nlte_create(rcx_grid(inp.nx, inp.nz, inp.voxel), p, atom_from_dict(inp.atom),
@@ -707,7 +730,7 @@ def _load_batch():
         return L
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.rcx_batch_create.argtypes = [i32, C.POINTER(rcx_grid), C.POINTER(i32), C.POINTER(rcx_params), C.POINTER(vp)]
-    L.rcx_batch_set_order.argtypes = [vp, i32]
+    L.rcx_batch_set_order.argtypes = [vp, i32, i32]
     L.rcx_batch_set_graph.argtypes = [vp, i32]
     L.rcx_batch_set_active_host.argtypes = [vp, i32, vp]
     L.rcx_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
@@ -750,8 +773,9 @@ class Batch:
         self.handle = h.value
         self.shapes, self.n_wave = [tuple(s) for s in shapes], list(n_wave)
 
-    def set_order(self, tile_probes: int):
-        _check(_load_batch().rcx_batch_set_order(self.handle, int(tile_probes)), "rcx_batch_set_order")
+    def set_order(self, tile_probes: int, tile_dirs: int = 32):
+        _check(_load_batch().rcx_batch_set_order(self.handle, int(tile_probes), int(tile_dirs)),
+               "rcx_batch_set_order")
 
     def set_graph(self, enable: bool):
         _check(_load_batch().rcx_batch_set_graph(self.handle, int(bool(enable))), "rcx_batch_set_graph")

@@ -170,10 +170,11 @@ def main():
     ap.add_argument("--ng", action="store_true", help="training runs with Ng acceleration")
     ap.add_argument("--keep", type=int, default=1, help="keep every keep-th cell of each training run")
     ap.add_argument("--no-eval", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=500, help="iteration cap of the training runs")
     a = ap.parse_args()
     t0 = time.perf_counter()
     X, Y, info = dataset(a.train_n, range(5000, 5000 + a.train_runs), a.n_line, a.n_cont, tol=a.tol, ng=a.ng,
-                         keep=a.keep)
+                         keep=a.keep, max_iter=a.max_iter)
     if a.train_n2 > 0 and a.train_runs2 > 0:
         X2, Y2, info2 = dataset(a.train_n2, range(5100, 5100 + a.train_runs2), a.n_line, a.n_cont)
         X, Y = np.concatenate([X, X2]), np.concatenate([Y, Y2])
@@ -187,7 +188,7 @@ def main():
     if a.save:
         save(net, fn, tn, a.save, {"train_n": a.train_n, "train_runs": a.train_runs, "train_n2": a.train_n2,
                                    "train_runs2": a.train_runs2, "epochs": a.epochs, "tol": a.tol, "ng": a.ng,
-                                   "keep": a.keep, "samples": len(X),
+                                   "keep": a.keep, "samples": len(X), "max_iter": a.max_iter,
                                    "n_line": a.n_line, "n_cont": a.n_cont, "loss_last": losses[-1]})
     ev = [] if a.no_eval else evaluate(net, fn, tn, a.eval_n, a.eval_seeds, a.n_line, a.n_cont,
                                        ref_max_iter=a.ref_max_iter)

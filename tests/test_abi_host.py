@@ -220,5 +220,5 @@ def test_batch_create_rejects_bad_arguments():
     assert L.rcx_batch_create(1, g, nw, C.byref(p), C.byref(h)) == rcx.RCX_E_UNSUPPORTED
     assert h.value is None
     assert L.rcx_batch_solve(None, None, None, None, None) == rcx.RCX_E_INVALID
-    assert L.rcx_batch_set_order(None, 4) == rcx.RCX_E_INVALID
+    assert L.rcx_batch_set_order(None, 4, 32) == rcx.RCX_E_INVALID
     assert L.rcx_batch_destroy(None) == rcx.RCX_OK

@@ -80,10 +80,10 @@ def test_launch_order_and_graph_do_not_change_results():
     B = rcx.Batch([(nx, nz) for nx, nz, _, _ in CASES], [nw for _, _, nw, _ in CASES])
     ref = [j.cpu().numpy() for j in B.solve(chi, eta)]
     J = [torch.empty_like(c) for c in chi]
-    for order in (0, 2, 8):
+    for order, dirs in ((0, 32), (2, 32), (8, 32), (4, 16), (4, 64)):
         for graph in (False, True):
-            print(f"[gpu] batch order {order} graph {graph}", flush=True)
-            B.set_order(order)
+            print(f"[gpu] batch order {order} x {dirs} graph {graph}", flush=True)
+            B.set_order(order, dirs)
             B.set_graph(graph)
             for rep in range(3):  # graph replays with eager work in between
                 for j in J:
@@ -91,7 +91,7 @@ def test_launch_order_and_graph_do_not_change_results():
                 B.solve(chi, eta, J)
                 torch.cuda.synchronize()
                 for a in range(len(CASES)):
-                    assert np.array_equal(J[a].cpu().numpy(), ref[a]), (order, graph, rep, a)
+                    assert np.array_equal(J[a].cpu().numpy(), ref[a]), (order, dirs, graph, rep, a)
                 _ = (chi[0] * 2.0).sum().item()
     B.close()
 
@@ -112,7 +112,7 @@ def test_fp16_batch_error_is_bounded():
         Jo = oracle.formal_solve(host[a][0][lam], host[a][1][lam], W.n_cascades_for(nx, nz))["J"]
         r = _rel(Jg[lam], Jo)
         print(f"fp16 batch atm {a}: max rel {r:.3e}")
-        assert r < 2e-3
+        assert r < 1e-3
     B.close()
 
 
@@ -126,7 +126,7 @@ def test_autotune_and_cache(tmp_path):
     path = str(tmp_path / "tiles.jsonl")
     print("[gpu] batch autotune", flush=True)
     best = B.autotune(chi, eta, cache_path=path)
-    assert best in (0, 2, 4, 8)
+    assert best in (0, 2032, 4016, 4032, 4064, 8032)
     assert open(path).read().count("\n") == 1
     assert B.autotune(chi, eta, cache_path=path) == best  # cache hit: no new line
     assert open(path).read().count("\n") == 1

@@ -241,6 +241,63 @@ def test_full_size_atmosphere_sampled_cells():
     assert relp.max() < 1e-3
 
 
+@pytest.mark.parametrize("n_incl", [2, 8])
+def test_inclinations(case32, n_incl):
+    """2D invariance in the non-LTE iteration (Sec. 3.1; the paper iterates
+    with 8 inclinations): J (the Gauss-Radau sum over inclinations) to 1e-4,
+    the rate coefficients to 1e-4 of their magnitude sums, and the
+    populations after 3 iterations to 1e-3, against the oracle with the same
+    inclinations."""
+    torch = _torch()
+    from oracle import nlte
+    from paper_2408_14425_amd import rcx
+    inp, _ = case32
+    P = nlte.Problem(inp, n_incl=n_incl)
+    print(f"[gpu] nlte {inp.name} with {n_incl} inclinations", flush=True)
+    s = rcx.Nlte(inp, n_incl=n_incl)
+    pops = s.lte()
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64)
+    rg = rates.cpu().numpy()
+    rc, it, ch = s.iterate(pops, 3, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    relJ = np.abs(Jg - Jo) / np.abs(Jo)
+    eu, ed = _rates_vs_oracle(rg, P, P.lte, I0, chi_loc, H_loc)
+    po, _ = P.iterate(P.lte.copy(), 3)
+    relp = np.abs(pg - po) / np.abs(po)
+    Jflat = nlte.Problem(inp).formal_solve(P.lte)[0]
+    print(f"{n_incl} inclinations: J max rel {relJ.max():.3e} (differs from flatland by up to "
+          f"{np.max(np.abs(Jo - Jflat) / Jflat):.2e}), rates {eu:.3e} / {ed:.3e}, pops after 3 iterations "
+          f"{relp.max():.3e}")
+    assert relJ.max() < 1e-4
+    assert eu < 1e-4 and ed < 1e-4
+    assert relp.max() < 1e-3
+
+
+def test_inclinations_converged_at_oracle_iteration_count(case32):
+    """With 3 inclinations the GPU iterated for the oracle's stopping count
+    agrees with the oracle's populations to 1e-3."""
+    _torch()
+    from oracle import nlte
+    from paper_2408_14425_amd import rcx
+    inp, _ = case32
+    P = nlte.Problem(inp, n_incl=3)
+    po, changes = P.iterate(P.lte.copy(), 200, tol=1e-3)
+    K = len(changes)
+    s = rcx.Nlte(inp, n_incl=3)
+    pops = s.lte()
+    rc, it, ch = s.iterate(pops, K, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"3 inclinations converged: oracle {K} iterations; gpu max rel {relp.max():.3e}")
+    assert it == K
+    assert relp.max() < 1e-3
+
+
 @pytest.mark.parametrize("profile", PROFILES)
 def test_three_iterations(case32, profile):
     _torch()
