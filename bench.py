@@ -39,6 +39,14 @@ VALU_SLOTS = 78.6e12
 ALU_OPS_PER_STEP = 8
 # Algorithmic bytes per cell step and wavelength: chi and S, FP32 each.
 BYTES_PER_STEP = 8
+# The non-LTE line march adds the line profile per step (expansion in the
+# damping parameter a): x = |u w + v| (1), x^2 (1), e^{-x^2} (1 + 4), the
+# Dawson term from its table (4: scale, clamp, fraction, interpolation),
+# H = e (1 + a^2 (1 - 2x^2)) - (2a/sqrt(pi)) g (4) and chi = chi_0 H (1):
+# 16 slots, plus the radiative update's 8.
+LINE_OPS_PER_STEP = 24
+# Dense BF16 MFMA peak of MI355X (FLOP/s).
+MFMA_BF16_PEAK = 2.5e15
 
 
 def parse():
@@ -62,9 +70,12 @@ def parse():
                     help="skip the formal solve with the bilinear fix")
     ap.add_argument("--no-incl", action="store_true",
                     help="skip the 2D-invariant formal solve with 8 inclinations per flatland ray")
-    ap.add_argument("--c4", action="store_true",
-                    help="also run the batched formal solve of 16 uneven atmospheres (256^2..2048^2, "
-                         "32..256 wavelengths; ~190 GB of device memory, a few minutes)")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the batched formal solve of 16 uneven atmospheres (256^2..2048^2, "
+                         "32..256 wavelengths; ~190 GB of device memory, about two minutes)")
+    ap.add_argument("--c4-reps", type=int, default=1, help="timed batched solves per storage")
+    ap.add_argument("--c4-per-plan", action="store_true",
+                    help="also time the 16 atmospheres one plan after another (FP32)")
     ap.add_argument("--nlte-only", action="store_true",
                     help="only the converged non-LTE solves (prints their object)")
     ap.add_argument("--nlte-profile", type=int, default=0,
@@ -81,6 +92,10 @@ def parse():
                     help="fraction of the non-LTE atmosphere turned into 1e6 K corona (for sparse_fp32)")
     ap.add_argument("--nlte-max-iter", type=int, default=300)
     ap.add_argument("--nlte-ref-max-iter", type=int, default=200)
+    ap.add_argument("--nlte-ref-tol", type=float, default=1e-7,
+                    help="the reference stops when its max relative change drops below this")
+    ap.add_argument("--nlte-ref-start", choices=("lte", "learned"), default="lte",
+                    help="start of the reference iteration (the same fixed point either way)")
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "warmstart_mlp.npz"),
                     help="trained warm-start network (skipped when absent)")
     ap.add_argument("--orders", default=os.path.join(ROOT, "paper_2408_14425_amd", "data", "launch_orders.jsonl"),
@@ -150,7 +165,7 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(inp, n_waves: int):
-    """The FP64 oracle (C, OpenMP, -O3 -march=native) on the host: the full
+    """The FP64 oracle (C, OpenMP, -O3 for x86-64-v3) on the host: the full
     formal solve of n_waves of the workload's wavelengths on all host
     threads, and the dependency cone of a central 64 x 64 block of cells of
     one wavelength on one thread."""
@@ -180,7 +195,42 @@ def cpu_baseline(inp, n_waves: int):
         "one_thread": {"value": r1["nonempty"] / dt1, "unit": "ray-intervals/s",
                        "sample": f"dependency cone of the central 64x64 cells, 1 wavelength: {r1['nonempty']} "
                                  f"non-empty ray intervals in {dt1:.1f} s on 1 thread"},
+        "nonlte_iteration": nlte_cpu_baseline(r["steps"] // max(n_waves, 1)),
     }
+
+
+def nlte_cpu_baseline(steps_per_wave: int):
+    """One iteration of the FP64 non-LTE oracle on the 1024^2, 160-wavelength
+    atmosphere, estimated from a bounded sample: the dependency cones of the
+    central 64 x 64 and 192 x 192 cells at one line-core wavelength (formal
+    solution with the cascade-0 radiance, local opacities and profiles) on
+    all host threads; the straight line through (cell steps, seconds)
+    extrapolated to the full grid (the formal solve's steps per wavelength
+    on the same grid) and multiplied by the 160 wavelengths."""
+    import numpy as np
+
+    import oracle
+    from oracle import nlte
+    from paper_2408_14425_amd import workloads
+    inp = workloads.nlte_atmosphere(1024, seed=3, n_line=64, n_cont=32)
+    P = nlte.Problem(inp)
+    pts = []
+    for h in (32, 96):
+        need = np.zeros((inp.nz, inp.nx), np.uint8)
+        need[inp.nz // 2 - h:inp.nz // 2 + h, inp.nx // 2 - h:inp.nx // 2 + h] = 1
+        t0 = time.perf_counter()
+        st = P.formal_solve(P.lte, lams=[32], need=need)[4]
+        pts.append((int(st[2]), time.perf_counter() - t0))
+    # seconds = a + b steps (a: the per-wavelength work on every cell)
+    (s0, t0_), (s1, t1_) = pts
+    b = (t1_ - t0_) / max(s1 - s0, 1)
+    a = max(t0_ - b * s0, 0.0)
+    est = (a + b * steps_per_wave) * inp.n_wave
+    return {"seconds_per_iteration_estimated": est, "unit": "s per iteration", "cores": oracle.num_threads(),
+            "sample": f"dependency cones of the central 64x64 and 192x192 cells at 1 line-core wavelength: "
+                      f"{s0} and {s1} cell steps in {t0_:.1f} and {t1_:.1f} s on {oracle.num_threads()} threads; "
+                      f"the line through them extrapolated to {steps_per_wave} cell steps per wavelength, times "
+                      f"{inp.n_wave} wavelengths"}
 
 
 def time_solves(plan, chi, eta, J, steps: int, warmup: int):
@@ -208,7 +258,7 @@ def nlte_solves(args):
 
     The reference is the plain FP32 iteration with Ng acceleration from the
     LTE start, iterated until its max relative change stops falling (the
-    FP32 floor) or drops below 1e-7. Each variant then iterates one step at
+    FP32 floor) or drops below --nlte-ref-tol (1e-7). Each variant then iterates one step at
     a time from its start (LTE, or the learned warm start: features, network
     inference and populations inside the timed region) with FP32 or 16-bit
     cascade storage; after each step its true error, the max relative
@@ -239,9 +289,9 @@ def nlte_solves(args):
     t0 = time.perf_counter()
     s = rcx.Nlte(inp)
     s.set_acceleration(2, 4, 4)
-    ref = s.lte()
+    ref = s.warm_start(net, fn, tn) if args.nlte_ref_start == "learned" and net is not None else s.lte()
     it_r, best, since, ch = 0, float("inf"), 0, float("inf")
-    while it_r < args.nlte_ref_max_iter and ch > 1e-7 and since < 12:
+    while it_r < args.nlte_ref_max_iter and ch > args.nlte_ref_tol and since < 12:
         _, k, ch = s.iterate(ref, 1, 0.0)
         it_r += k
         if ch < 0.9 * best:
@@ -253,6 +303,7 @@ def nlte_solves(args):
     torch.cuda.synchronize()
     s.close()
     out["reference"] = {"iterations": it_r, "last_change": ch, "best_change": best, "ng": [2, 4, 4],
+                        "tolerance": args.nlte_ref_tol, "start": args.nlte_ref_start,
                         "seconds": time.perf_counter() - t0}
 
     runs = [("plain_fp32", rcx.RCX_STORE_F32, False, False), ("plain_fp16", rcx.RCX_STORE_F16_SCALED, False, False),
@@ -315,9 +366,40 @@ def nlte_solves(args):
         ea = out[name].get("equal_accuracy")
         if base and ea and name != "plain_fp32":
             out[name]["speedup_vs_plain_fp32_at_equal_accuracy"] = base["seconds"] / ea["seconds"]
+    # the march kernels' ALU rooflines (2 plain FP32 iterations with timing)
+    s = rcx.Nlte(inp)
+    out["roofline"] = line_march_roofline(s, 2)
+    s.close()
     if net is not None:
         out["network"] = {"weights": os.path.relpath(args.weights, ROOT)}
         net.close()
+    return out
+
+
+def line_march_roofline(s, iters: int):
+    """ALU roofline of the non-LTE march from `iters` iterations with kernel
+    timing: algorithmic slots (LINE_OPS_PER_STEP per line cell step and
+    wavelength, ALU_OPS_PER_STEP per continuum one) over the summed event
+    time of the launches."""
+    p = s.lte()
+    s.iterate(p, 1, 0.0)
+    s.get_timing()
+    s.set_timing(True)
+    s.iterate(p, iters, 0.0)
+    t = s.get_timing()
+    s.set_timing(False)
+    out = {}
+    for kind, ops in (("line", LINE_OPS_PER_STEP), ("continuum", ALU_OPS_PER_STEP)):
+        ms, n, steps = t[kind]
+        if n == 0:
+            continue
+        achieved = ops * steps / (ms / 1e3) / 1e12
+        out[kind] = {"bound": "alu", "kernel": "k_march_rows<LineOpT>" if kind == "line" else "k_march_rows<FieldOp>",
+                     "achieved": achieved, "peak": VALU_SLOTS / 1e12,
+                     "unit": "T VALU lane slots/s (FP32 FMA = 1, v_exp_f32 = 4)",
+                     "frac": achieved / (VALU_SLOTS / 1e12), "ops_per_cell_step": ops,
+                     "launches": n, "avg_launch_ms": ms / n, "cell_steps_x_wavelengths": steps,
+                     "iterations": iters}
     return out
 
 
@@ -336,9 +418,10 @@ def nlte_profile(args):
     _, it, ch = s.iterate(p, args.nlte_profile, 0.0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    roof = line_march_roofline(s, 2)
     s.close()
     return {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz}, {inp.n_wave} wavelengths, seed {args.nlte_seed}",
-            "iterations": it, "s_per_iteration": dt / max(it, 1), "last_change": ch}
+            "iterations": it, "s_per_iteration": dt / max(it, 1), "last_change": ch, "roofline": roof}
 
 
 def mlp_profile(args):
@@ -372,8 +455,14 @@ def mlp_profile(args):
     t_fwd = (time.perf_counter() - t0) / args.mlp_profile
     net.close()
     macs = 6 * 128 + 3 * 128 * 128 + 128 * 4
-    return {"batch": batch, "ms_per_train_step": t_train * 1e3, "ms_per_forward": t_fwd * 1e3,
-            "train_TFLOPs": 3 * 2 * macs * batch / t_train / 1e12, "forward_TFLOPs": 2 * macs * batch / t_fwd / 1e12}
+    train = 3 * 2 * macs * batch / t_train / 1e12
+    fwd = 2 * macs * batch / t_fwd / 1e12
+    return {"batch": batch, "steps": args.mlp_profile, "ms_per_train_step": t_train * 1e3,
+            "ms_per_forward": t_fwd * 1e3, "train_TFLOPs": train, "forward_TFLOPs": fwd,
+            # whole training step (every kernel of it) against the dense BF16 MFMA peak
+            "roofline": {"bound": "mfma", "kernel": "training step (k_gemm_nt and its epilogues)",
+                         "achieved": train, "peak": MFMA_BF16_PEAK / 1e12, "unit": "TFLOP/s",
+                         "frac": train / (MFMA_BF16_PEAK / 1e12)}}
 
 
 def c4_batched(args):
@@ -409,17 +498,34 @@ def c4_batched(args):
         B = rcx.Batch([(s_[0], s_[0]) for s_ in specs], [s_[1] for s_ in specs], storage=storage)
         B.solve(chi, eta, J)  # builds the schedule and captures the graph
         torch.cuda.synchronize()
-        reps = 2
+        reps = max(args.c4_reps, 1)
         t1 = time.perf_counter()
         for _ in range(reps):
             B.solve(chi, eta, J)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / reps
         rays, steps = B.work()
+        n_march, n_all = B.launches()
         B.close()
         got[name] = [[J[a][l, z, x].item() for l in smp[2] for (x, z) in smp[3]] for a, smp in enumerate(samples)]
-        out[name] = {"s_per_solve": dt, "ray_intervals_per_s": rays / dt, "cell_steps_per_s": steps / dt}
+        out[name] = {"s_per_solve": dt, "ray_intervals_per_s": rays / dt, "cell_steps_per_s": steps / dt,
+                     "march_launches": n_march, "launches": n_all}
         print(f"[bench] c4 {name}: {dt:.2f} s per batched solve", file=sys.stderr, flush=True)
+    if args.c4_per_plan:
+        # the same atmospheres one plan after another (FP32, one untimed solve each first)
+        t_pp = 0.0
+        for a, (side, nw, _) in enumerate(specs):
+            P = rcx.Plan(side, side, nw)
+            P.formal_solve(chi[a], eta[a], J[a])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P.formal_solve(chi[a], eta[a], J[a])
+            torch.cuda.synchronize()
+            t_pp += time.perf_counter() - t1
+            P.close()
+        out["fp32"]["per_plan_s"] = t_pp
+        out["fp32"]["batched_speedup_vs_per_plan"] = t_pp / out["fp32"]["s_per_solve"]
+        print(f"[bench] c4 per plan: {t_pp:.2f} s", file=sys.stderr, flush=True)
     del chi, eta, J
     torch.cuda.empty_cache()
     ref = []
@@ -638,7 +744,10 @@ def main():
     }
     if not args.no_nlte:
         out["nonlte"] = nlte_solves(args)
-    if args.c4:
+        # the warm-start network's training step (20 steps, batch 65536)
+        args.mlp_profile = 20
+        out["mlp"] = mlp_profile(args)
+    if not args.no_c4:
         out["batched"] = c4_batched(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, args.cpu_waves)

@@ -298,6 +298,11 @@ int32_t rcx_batch_solve(rcx_batch* b, const float* const* chi_host, const float*
                         float* const* J_host, hipStream_t stream);
 /* Work summed over atmospheres and wavelengths (rcx_work semantics). */
 int32_t rcx_batch_work(const rcx_batch* b, int64_t* rays_nonempty_host, int64_t* cell_steps_host);
+/* Kernel launches one solve enqueues, from the work list the last solve
+ * built (both 0 before the first solve): *march_host march launches (each
+ * the next cascade of every active chain), *all_host those plus the field
+ * preparation and masking launches (the input check not counted). */
+int32_t rcx_batch_launches(const rcx_batch* b, int32_t* march_host, int32_t* all_host);
 /* Time each candidate launch order (tile_probes, tile_dirs) in {(0, -),
  * (2, 32), (4, 16), (4, 32), (4, 64), (8, 32)} (rcx_batch_set_order) on
  * these inputs and keep the fastest: *best_host = tile_probes * 1000 +
@@ -426,6 +431,18 @@ int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops_inout,
  * Ng step. */
 int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, double tol,
                          int32_t* iters_host, double* last_change_host, hipStream_t stream);
+
+/* Kernel timing for measurement: when enabled, every march launch of the
+ * formal solution (rcx_nlte_formal_solve_rates, rcx_nlte_iterate) records
+ * two HIP events on its stream. rcx_nlte_get_timing synchronises on them
+ * and returns, for the line batches [0] and the continuum batches [1]: the
+ * summed kernel time in ms, the launch count, and the cell steps x
+ * wavelengths those launches marched (the dense per-cascade counts of
+ * rcx_plan_work; per inclination); it then drops the records. Enabling
+ * counts the plan's work first (host loop over every ray). Errors:
+ * RCX_E_INVALID (null arguments); RCX_E_HIP. */
+int32_t rcx_nlte_set_timing(rcx_nlte* s, int32_t enable);
+int32_t rcx_nlte_get_timing(rcx_nlte* s, double* ms_host, int64_t* launches_host, int64_t* steps_host);
 
 /* Ng acceleration of rcx_nlte_iterate (not used by the paper; off by
  * default): order M in [1, 3] (0 = off) extrapolates from the last M + 2

@@ -201,6 +201,7 @@ bool build_work(rcx_batch* s, float* const* J)
                 if (P->top_skipped && i == P->n_casc - 1) continue;
                 Task T{};
                 T.L = P->levels[i];  // the plan's launch order (rcx_batch_set_order sets it)
+                if (!set_decode(T.L)) return false;
                 T.nx = P->grid.nx;
                 T.nz = P->grid.nz;
                 T.dirs = P->dirs_dev + P->dir_off[i];
@@ -532,6 +533,21 @@ int32_t rcx_batch_work(const rcx_batch* s, int64_t* rays_nonempty_host, int64_t*
     }
     *rays_nonempty_host = r;
     *cell_steps_host = c;
+    return RCX_OK;
+}
+
+int32_t rcx_batch_launches(const rcx_batch* s, int32_t* march_host, int32_t* all_host)
+{
+    if (!s || !march_host || !all_host) return bfail(RCX_E_INVALID, "rcx_batch_launches: null argument");
+    const int32_t march = s->gen_task.empty() ? 0 : (int32_t)s->gen_task.size() - 1;
+    int32_t other = 0;
+    if (march > 0)
+        for (int32_t a = 0; a < s->n_atm; ++a) {
+            other += 1 + (s->f16 ? 1 : 0);              // field prep (+ exponent bias)
+            if (s->plans[a]->mask_dev) other += 2;      // masked fields, masked J
+        }
+    *march_host = march;
+    *all_host = march + other;
     return RCX_OK;
 }
 

@@ -238,9 +238,11 @@ hipError_t launch_ebias(int32_t n, const unsigned int* smax_bits, int32_t* ebias
 
 namespace {
 template <class Op, class Epi, class Up>
-hipError_t launch_fs(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+hipError_t launch_fs(const LevelDesc& L0, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
                      const Up& up, hipStream_t st)
 {
+    LevelDesc L = L0;
+    if (!set_decode(L)) return hipErrorInvalidValue;  // more rays than 31-bit indices
     const int64_t total = level_launch_rays(L);
     hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
                        dirs, up, total);
@@ -265,9 +267,11 @@ hipError_t launch_fs_up(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op
 // The bilinear-fix kernel: one interval per wavefront, so 4 x the
 // intervals' rows.
 template <class Op, class Epi, class Up>
-hipError_t launch_fix_k(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+hipError_t launch_fix_k(const LevelDesc& L0, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
                         const Up& up, hipStream_t st)
 {
+    LevelDesc L = L0;
+    if (!set_decode(L)) return hipErrorInvalidValue;  // more rays than 31-bit indices
     const int64_t total = level_launch_rays(L);
     hipLaunchKernelGGL((march::k_march_fix<Op, Epi, Up>), march_grid(4 * total), dim3(kBlock), 0, st, L, nx, nz, op,
                        epi, dirs, up, total);

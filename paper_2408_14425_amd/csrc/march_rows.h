@@ -43,6 +43,16 @@ __device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb, u
     const unsigned x = b % kXcds, slot = b / kXcds;
     return (slot / chunk) * (kXcds * chunk) + x * chunk + slot % chunk;
 }
+// The same with the chunk a launch constant of the cascade (its divisions
+// precomputed in LevelDesc::dec).
+__device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb, const LevelDesc::Decode& D)
+{
+    const unsigned c8 = D.chunk8.d, full = D.chunk8.div(nb) * c8;
+    if (b >= full) return b;
+    const unsigned x = b % kXcds, slot = b / kXcds;
+    const unsigned q = D.chunk.div(slot);
+    return q * c8 + x * D.chunk.d + (slot - q * D.chunk.d);
+}
 
 // 1 - 2^{-y} for y >= 0 (y = optical depth in log2 units) without
 // cancellation: with x = y ln2, the series x - x^2/2 + x^3/6 below x = 1/64
@@ -388,50 +398,54 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
 
 // Probe and direction of launch-order ray r (of total): probe-major, or
 // the tiled order of LevelDesc; active false past the end and on padding.
-__device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t r, int64_t total, int32_t& k, int32_t& u,
-                                           int32_t& v, bool& active)
+__host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t r, int64_t total, int32_t& k,
+                                                    int32_t& u, int32_t& v, bool& active)
 {
-    active = r < total;
-    const int64_t rr = active ? r : total - 1;
+    // 32-bit decode with the launch's divisors precomputed (set_decode
+    // checks that its ray indices fit); a launch without them marches nothing
+    const LevelDesc::Decode& D = L.dec;
+    active = r < total && D.ready == kDecodeReady;
+    const uint32_t rr = (uint32_t)(r < total ? r : total - 1);
+    uint32_t kk, p;
     if (L.plist) {
         // sparse: entry i of the flagged-probe list stands for probe i of
         // the dense order (groups of tile_p^2 list entries when tiled)
-        int64_t i;
+        uint32_t i;
         if (L.tile_p <= 0) {
-            k = (int32_t)(rr % L.nd);
-            i = rr / L.nd;
+            i = D.nd.div(rr);
+            kk = rr - i * D.nd.d;
         } else {
-            const int64_t tp2 = (int64_t)L.tile_p * L.tile_p;
-            const int64_t per = tp2 * L.tile_d;
-            const int64_t g = rr / per, r_in = rr % per;
-            const int32_t nw = L.nd / L.tile_d;
-            k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
-            i = (g / nw) * tp2 + r_in / L.tile_d;
+            const uint32_t g = D.per.div(rr), r_in = rr - g * D.per.d;
+            const uint32_t t = D.nw.div(g), pl = D.tile_d.div(r_in);
+            kk = (g - t * D.nw.d) * D.tile_d.d + (r_in - pl * D.tile_d.d);
+            i = t * D.tp2.d + pl;
         }
-        active = active && i < L.n_active;
-        const int32_t p = L.plist[i < L.n_active ? i : L.n_active - 1];
-        u = p % L.px;
-        v = p / L.px;
+        active = active && i < (uint32_t)L.n_active;
+        p = (uint32_t)L.plist[i < (uint32_t)L.n_active ? i : L.n_active - 1];
+        const uint32_t pv = D.px.div(p);
+        u = (int32_t)(p - pv * D.px.d);
+        v = (int32_t)pv;
+        k = (int32_t)kk;
         return;
     }
     if (L.tile_p <= 0) {
-        k = (int32_t)(rr % L.nd);
-        const int32_t p = (int32_t)(rr / L.nd);
-        u = p % L.px;
-        v = p / L.px;
+        p = D.nd.div(rr);
+        k = (int32_t)(rr - p * D.nd.d);
+        const uint32_t pv = D.px.div(p);
+        u = (int32_t)(p - pv * D.px.d);
+        v = (int32_t)pv;
     } else {
         // group g = (probe tile, direction wedge), wedge fastest; within
         // a group, direction fastest
-        const int64_t per = (int64_t)L.tile_p * L.tile_p * L.tile_d;
-        const int64_t g = rr / per, r_in = rr % per;
-        const int32_t nw = L.nd / L.tile_d;
-        const int32_t t = (int32_t)(g / nw), ntx = (L.px + L.tile_p - 1) / L.tile_p;
-        const int32_t pl = (int32_t)(r_in / L.tile_d);
-        k = (int32_t)(g % nw) * L.tile_d + (int32_t)(r_in % L.tile_d);
-        u = (t % ntx) * L.tile_p + pl % L.tile_p;
-        v = (t / ntx) * L.tile_p + pl / L.tile_p;
+        const uint32_t g = D.per.div(rr), r_in = rr - g * D.per.d;
+        const uint32_t t = D.nw.div(g), pl = D.tile_d.div(r_in);
+        k = (int32_t)((g - t * D.nw.d) * D.tile_d.d + (r_in - pl * D.tile_d.d));
+        const uint32_t ty = D.ntx.div(t), py = D.tile_p.div(pl);
+        u = (int32_t)((t - ty * D.ntx.d) * D.tile_p.d + (pl - py * D.tile_p.d));
+        v = (int32_t)(ty * D.tile_p.d + py);
         active = active && u < L.px && v < L.pz;
     }
+    if (D.ready != kDecodeReady) k = u = v = 0;
 }
 
 template <class Op, class Epi, class Up>
@@ -463,7 +477,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t n
         }
         wave_sync();
     }
-    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, (unsigned)L.xcd_chunk);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, L.dec);
     const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
     for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
         int32_t k, u, v;
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_march_fix(LevelDesc L, int32_t nx
     up.init(c.l);
     seg[c.w][c.row][c.l] = make_uint4(0u, 0u, 0u, 0u);
     wave_sync();
-    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, (unsigned)L.xcd_chunk);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, L.dec);
     const int64_t stride = (int64_t)gridDim.x * (kBlock / 64);
     for (int64_t r = (int64_t)lb * (kBlock / 64) + c.w; r < total; r += stride) {
         int32_t k, u, v;

@@ -157,14 +157,32 @@ __global__ void k_wgrad_reduce(const float* __restrict__ P, int32_t splits, int3
     gW[i] = s;
 }
 
-__global__ void k_bias_grad(const __bf16* __restrict__ dZt, int32_t Bp, int32_t n_valid, float* __restrict__ gb)
+// Bias gradient: gb[n] = sum over the batch of dZ^T[n][.]. One block of 256
+// threads per output; each thread sums 8 consecutive values per 16-byte load
+// (rows are 128-byte aligned: Bp is a multiple of 64), the block reduces in
+// a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_bias_grad(const __bf16* __restrict__ dZt, int32_t Bp, int32_t n_valid,
+                                                   float* __restrict__ gb)
 {
+    __shared__ float part[4];
     const int n = blockIdx.x;
     if (n >= n_valid) return;
+    const uint4* row = reinterpret_cast<const uint4*>(dZt + (int64_t)n * Bp);
+    const int n8 = Bp / 8;
     float s = 0.0f;
-    for (int64_t b = threadIdx.x; b < Bp; b += 64) s += (float)dZt[(int64_t)n * Bp + b];
+    for (int i = threadIdx.x; i < n8; i += 256) {
+        const uint4 q = row[i];
+        const uint32_t wv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            s += __uint_as_float(wv[h] << 16);
+            s += __uint_as_float(wv[h] & 0xFFFF0000u);
+        }
+    }
     for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
-    if (threadIdx.x == 0) gb[n] = s;
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) gb[n] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 // Adam on the flat FP32 parameters, then refresh the bf16 copies W [Kp][Np]
@@ -332,7 +350,7 @@ hipError_t backward(rcx_mlp* s, const float* yref, int32_t B, int32_t Bp, int* n
                            splits, s->Kp[l], s->Np[l], s->fin[l], s->fout[l], gW);
         e = hipGetLastError();
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL(k_bias_grad, dim3(s->fout[l]), dim3(64), 0, st, dZt, Bp, s->fout[l], gb);
+        hipLaunchKernelGGL(k_bias_grad, dim3(s->fout[l]), dim3(256), 0, st, dZt, Bp, s->fout[l], gb);
         e = hipGetLastError();
         if (e != hipSuccess || l == 0) break;
         // backward data: dZ_{l-1} = (dZ_l W_l^T) * silu'(Z_{l-1})

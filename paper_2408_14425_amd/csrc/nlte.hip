@@ -1030,6 +1030,14 @@ struct rcx_nlte {
     float* feat = nullptr;     // [ncell][6]
     float* pred = nullptr;     // [ncell][n_levels]
     float* norms = nullptr;    // [12 + 2 n_levels]
+    // measurement: events around every march launch when timing is enabled
+    struct Timed {
+        int32_t kind;   // 0 line, 1 continuum
+        int64_t steps;  // cell steps x wavelengths the launch marches (dense count)
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<Timed> pending;
     std::vector<void*> allocs;
 };
 
@@ -1060,9 +1068,11 @@ __global__ void k_pack_vel(int64_t ncell, const float* __restrict__ v, float2* _
 unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <class Op, class Epi, class Up>
-hipError_t launch_level(const LevelDesc& L, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
+hipError_t launch_level(const LevelDesc& L0, int32_t nx, int32_t nz, const Op& op, const Epi& epi, const double4* dirs,
                         const Up& up, hipStream_t st)
 {
+    LevelDesc L = L0;
+    if (!set_decode(L)) return hipErrorInvalidValue;  // more rays than 31-bit indices
     const int64_t total = level_launch_rays(L);
     hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
                        dirs, up, total);
@@ -1604,6 +1614,17 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             const double4* dirs = P->dirs_dev + P->dir_off[i];
             float* outb = s->casc[cur];
             const void* upl = L.has_up ? up : nullptr;
+            rcx_nlte::Timed tm{tr.kind, 0, nullptr, nullptr};
+            if (s->timing) {
+                tm.steps = P->work.level_steps[i] / P->prm.n_incl * B.n;
+                RCX_HIP_TRY(hipEventCreate(&tm.a));
+                hipError_t ee = hipEventCreate(&tm.b);
+                if (ee != hipSuccess) {
+                    (void)hipEventDestroy(tm.a);
+                    return rcx::hip_fail(ee, "rcx_nlte timing");
+                }
+                (void)hipEventRecord(tm.a, st);
+            }
             hipError_t e;
             if (s->f16) {
                 // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
@@ -1623,6 +1644,10 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
                     re.out = outb;
                     e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lop, fop, re, dirs, u32, st);
                 }
+            }
+            if (s->timing) {
+                (void)hipEventRecord(tm.b, st);
+                s->pending.push_back(tm);
             }
             RCX_HIP_TRY(e);
             up = outb;
@@ -1984,9 +2009,51 @@ int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* nl, int32_t* nt)
     return RCX_OK;
 }
 
+int32_t rcx_nlte_set_timing(rcx_nlte* s, int32_t enable)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_timing: null solver");
+    if (enable) {
+        rcx_work w;  // per-cascade step counts for the records
+        const int32_t rc = rcx_plan_work(s->plan, &w);
+        if (rc != RCX_OK) return rc;
+    }
+    s->timing = enable != 0;
+    return RCX_OK;
+}
+
+int32_t rcx_nlte_get_timing(rcx_nlte* s, double* ms_host, int64_t* launches_host, int64_t* steps_host)
+{
+    if (!s || !ms_host || !launches_host || !steps_host)
+        return nlte_fail(RCX_E_INVALID, "rcx_nlte_get_timing: null argument");
+    for (int k = 0; k < 2; ++k) {
+        ms_host[k] = 0.0;
+        launches_host[k] = 0;
+        steps_host[k] = 0;
+    }
+    int32_t rc = RCX_OK;
+    for (auto& t : s->pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(t.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+        if (e != hipSuccess && rc == RCX_OK) rc = rcx::hip_fail(e, "rcx_nlte_get_timing");
+        const int k = t.kind == 0 ? 0 : 1;
+        ms_host[k] += ms;
+        ++launches_host[k];
+        steps_host[k] += t.steps;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    s->pending.clear();
+    return rc;
+}
+
 int32_t rcx_nlte_destroy(rcx_nlte* s)
 {
     if (!s) return RCX_OK;
+    for (auto& t : s->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
     for (void* p : s->allocs) (void)hipFree(p);
     if (s->plan) rcx_plan_destroy(s->plan);
     delete s;

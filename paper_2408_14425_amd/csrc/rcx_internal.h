@@ -10,6 +10,32 @@
 
 namespace rcx {
 
+// Unsigned division by a launch constant d >= 1: q = n / d for every 32-bit
+// n with one high multiply, two shifts and two adds (Granlund and
+// Montgomery 1994, the round-up method; the 33-bit multiplier is 2^32 + m).
+struct FastDiv {
+    uint32_t d = 1, m = 1, s1 = 0, s2 = 0;
+    __host__ __device__ uint32_t div(uint32_t n) const
+    {
+        const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+        return (t + ((n - t) >> s1)) >> s2;
+    }
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f;
+    f.d = d < 1 ? 1 : d;
+    uint32_t l = 0;
+    while ((1ull << l) < f.d) ++l;  // ceil(log2 d)
+    f.m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << l) - f.d)) / f.d + 1);
+    f.s1 = l > 0 ? 1 : 0;
+    f.s2 = l > 0 ? l - 1 : 0;
+    return f;
+}
+
+constexpr uint32_t kDecodeReady = 0x52435844u;
+
 // Geometry of one cascade as the march/merge kernel sees it.
 struct LevelDesc {
     int32_t px, pz;     // probes per axis
@@ -35,6 +61,12 @@ struct LevelDesc {
     // tile_p > 0); nullptr = every probe
     const int32_t* plist = nullptr;
     int32_t n_active = 0;
+    // Divisors of the ray-index decode (march_rows.h, ray_coords) and of the
+    // XCD order, set by set_decode() on the host before every launch.
+    struct Decode {
+        FastDiv nd, px, per, nw, tile_d, tile_p, ntx, tp2, chunk, chunk8;
+        uint32_t ready = 0;
+    } dec;
 };
 
 // Rays a march launch covers (the tiled order pads the probe grid to whole
@@ -48,6 +80,29 @@ inline int64_t level_launch_rays(const LevelDesc& L)
     if (L.tile_p <= 0) return (int64_t)L.px * L.pz * L.nd;
     const int64_t tx = (L.px + L.tile_p - 1) / L.tile_p, tz = (L.pz + L.tile_p - 1) / L.tile_p;
     return tx * tz * L.tile_p * L.tile_p * L.nd;
+}
+
+// Fill L.dec from the launch order and the XCD chunk. False (and L.dec not
+// ready) when the launch's ray indices would not fit in 31 bits.
+inline bool set_decode(LevelDesc& L)
+{
+    LevelDesc::Decode& D = L.dec;
+    D.ready = 0;
+    if (level_launch_rays(L) >= ((int64_t)1 << 31) || L.nd < 1 || L.px < 1 || L.xcd_chunk < 1) return false;
+    D.nd = make_fastdiv((uint32_t)L.nd);
+    D.px = make_fastdiv((uint32_t)L.px);
+    if (L.tile_p > 0) {
+        D.per = make_fastdiv((uint32_t)(L.tile_p * L.tile_p * L.tile_d));
+        D.nw = make_fastdiv((uint32_t)(L.nd / L.tile_d));
+        D.tile_d = make_fastdiv((uint32_t)L.tile_d);
+        D.tile_p = make_fastdiv((uint32_t)L.tile_p);
+        D.ntx = make_fastdiv((uint32_t)((L.px + L.tile_p - 1) / L.tile_p));
+        D.tp2 = make_fastdiv((uint32_t)(L.tile_p * L.tile_p));
+    }
+    D.chunk = make_fastdiv((uint32_t)L.xcd_chunk);
+    D.chunk8 = make_fastdiv((uint32_t)L.xcd_chunk * 8u);
+    D.ready = kDecodeReady;
+    return true;
 }
 
 // Error plumbing: set the thread-local message and return the code.

@@ -369,7 +369,9 @@ def _load_nlte():
     L.rcx_nlte_log_departures.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
     L.rcx_nlte_pops_from_prediction.argtypes = [vp, vp, vp, vp, vp]
-    for n in ("rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start", "rcx_nlte_pops_from_prediction",
+    L.rcx_nlte_set_timing.argtypes = [vp, i32]
+    L.rcx_nlte_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    for n in ("rcx_nlte_set_timing", "rcx_nlte_get_timing", "rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start", "rcx_nlte_pops_from_prediction",
               "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_emergent", "rcx_nlte_set_pressure_conservation",
               "rcx_nlte_collisional_ne", "rcx_nlte_set_temperature_cut"):
         getattr(L, n).restype = i32
@@ -517,6 +519,20 @@ class Nlte:
     def set_acceleration(self, order: int, delay: int = 0, period: int = 1):
         """Ng acceleration of iterate() (order 0 = off)."""
         rcx_nlte_set_acceleration(self.handle, order, delay, period)
+
+    def set_timing(self, enable: bool):
+        """Record HIP events around every march launch (measurement)."""
+        _check(_load_nlte().rcx_nlte_set_timing(self.handle, int(bool(enable))), "rcx_nlte_set_timing")
+
+    def get_timing(self):
+        """{'line': (ms, launches, cell steps x wavelengths), 'continuum':
+        (...)} of the march launches recorded since timing was enabled or
+        the last call; synchronises on the events."""
+        ms = (C.c_double * 2)()
+        n = (C.c_int64 * 2)()
+        st = (C.c_int64 * 2)()
+        _check(_load_nlte().rcx_nlte_get_timing(self.handle, ms, n, st), "rcx_nlte_get_timing")
+        return {"line": (ms[0], n[0], st[0]), "continuum": (ms[1], n[1], st[1])}
 
     def emergent(self, pops, wx: float, wz: float, n_rays: int):
         """Emergent spectra [n_wave][n_rays] at populations pops along the
@@ -735,11 +751,12 @@ def _load_batch():
     L.rcx_batch_set_active_host.argtypes = [vp, i32, vp]
     L.rcx_batch_solve.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.rcx_batch_work.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+    L.rcx_batch_launches.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.rcx_batch_autotune.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.c_char_p, C.POINTER(i32), vp]
     L.rcx_batch_destroy.argtypes = [vp]
     for n in ("rcx_batch_create", "rcx_batch_set_order", "rcx_batch_set_graph", "rcx_batch_set_active_host",
               "rcx_batch_solve",
-              "rcx_batch_work", "rcx_batch_autotune", "rcx_batch_destroy"):
+              "rcx_batch_work", "rcx_batch_launches", "rcx_batch_autotune", "rcx_batch_destroy"):
         getattr(L, n).restype = i32
     L._batch_bound = True
     return L
@@ -798,6 +815,13 @@ class Batch:
         r, c = C.c_int64(), C.c_int64()
         _check(_load_batch().rcx_batch_work(self.handle, C.byref(r), C.byref(c)), "rcx_batch_work")
         return r.value, c.value
+
+    def launches(self):
+        """(march launches, all launches) one solve enqueues; (0, 0) before
+        the first solve."""
+        m, a = C.c_int32(), C.c_int32()
+        _check(_load_batch().rcx_batch_launches(self.handle, C.byref(m), C.byref(a)), "rcx_batch_launches")
+        return m.value, a.value
 
     def _arrays(self, chi, eta, J):
         import torch

@@ -56,9 +56,16 @@ def test_uneven_batch_matches_oracle_and_plans():
     host, chi, eta = _inputs(CASES)
     B = rcx.Batch([(nx, nz) for nx, nz, _, _ in CASES], [nw for _, _, nw, _ in CASES])
     B.set_graph(False)
+    assert B.launches() == (0, 0)
     J = B.solve(chi, eta)
     torch.cuda.synchronize()
     print("[gpu] batch solve done (direct launch)", flush=True)
+    # one march launch advances every active chain by a cascade: at least the
+    # longest chain, at most every (atmosphere, 16-wavelength batch) chain in turn
+    n_march, n_all = B.launches()
+    chains = [(-(-nw // 16), W.n_cascades_for(nx, nz)) for nx, nz, nw, _ in CASES]
+    assert max(nc for _, nc in chains) - 1 <= n_march <= sum(nb * nc for nb, nc in chains)
+    assert n_all == n_march + len(CASES)
     for a, (nx, nz, nw, _) in enumerate(CASES):
         Jg = J[a].cpu().numpy().astype(np.float64)
         plan = rcx.Plan(nx, nz, nw)

@@ -277,6 +277,47 @@ def test_inclinations(case32, n_incl):
     assert relp.max() < 1e-3
 
 
+def test_march_timing_counts(case32):
+    """Kernel timing of the non-LTE march: one formal solution with 2
+    inclinations records one launch per (batch, marched cascade,
+    inclination), and the cell steps x wavelengths of the line and continuum
+    launches equal the plan's dense per-cascade counts times the batches'
+    wavelengths; the records are dropped after reading."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp, _ = case32
+    print(f"[gpu] nlte timing {inp.name}", flush=True)
+    s = rcx.Nlte(inp, n_incl=2)
+    pops = s.lte()
+    s.set_timing(True)
+    s.formal_solve_rates(pops)
+    t = s.get_timing()
+    s.set_timing(False)
+    s.formal_solve_rates(pops)
+    torch.cuda.synchronize()
+    t2 = s.get_timing()
+    s.close()
+    plan = rcx.Plan(inp.nx, inp.nz, 1)
+    w = plan.work()
+    plan.close()
+    marched = w.n_cascades - (1 if w.top_skipped else 0)
+    # batches of <= 16 wavelengths per transition; transitions below the
+    # number of lines are lines, the rest continua
+    n_lines = len(inp.atom["lines"])
+    counts = np.bincount(inp.trans)
+    line_batches = sum(-(-int(c) // 16) for c in counts[:n_lines])
+    cont_batches = sum(-(-int(c) // 16) for c in counts[n_lines:])
+    n_lw = int(counts[:n_lines].sum())
+    n_cont = int(counts[n_lines:].sum())
+    assert line_batches > 0 and cont_batches > 0
+    assert t["line"][1] == line_batches * marched * 2
+    assert t["continuum"][1] == cont_batches * marched * 2
+    assert t["line"][2] == n_lw * w.cell_steps * 2
+    assert t["continuum"][2] == n_cont * w.cell_steps * 2
+    assert t["line"][0] > 0 and t["continuum"][0] > 0
+    assert t2 == {"line": (0.0, 0, 0), "continuum": (0.0, 0, 0)}
+
+
 def test_inclinations_converged_at_oracle_iteration_count(case32):
     """With 3 inclinations the GPU iterated for the oracle's stopping count
     agrees with the oracle's populations to 1e-3."""
