@@ -270,8 +270,11 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
     """Synthetic prominence-like atmosphere: a hot (1e5 K), tenuous
     background with cool blobs, log10 T = 5 - sum_b (5 - log10 T_b)
     exp(-r^2 / 2 sigma_b^2) clipped to [log10 5e3, 5], 24 blobs per 1024^2
-    (count scaled by area, at least 3), widths uniform in [20, 80] x
-    max(n, 256)/1024 cells, blob temperatures log-uniform in [5e3, 3e4] K;
+    (count scaled by area, at least 3), widths sigma uniform in [20, 80]
+    cells from 512^2 up (the cells keep their size, so a larger grid is a
+    larger patch of the same kind of atmosphere) and in [5, 20] cells on
+    smaller grids (several blobs in view), blob temperatures log-uniform in
+    [5e3, 3e4] K;
     hydrogen density
     ntot = n0 (1e4 K / T); a prescribed ionisation fraction
     x(T) = 1e-4 + (1 - 1e-4) / (1 + (6540 K / T)^16) (shaped like a hydrogen
@@ -288,7 +291,7 @@ def nlte_atmosphere(n: int = 64, seed: int = 3, n_line: int = 64, n_cont: int = 
     logt = np.full((nz, n), 5.0)
     for _ in range(n_blobs):
         cx, cz = rng.uniform(0, n), rng.uniform(0, nz)
-        sig = rng.uniform(20.0, 80.0) * max(n, 256) / 1024.0
+        sig = rng.uniform(20.0, 80.0) * (1.0 if max(n, nz) >= 512 else 0.25)
         tb = 10 ** rng.uniform(np.log10(5e3), np.log10(3e4))
         logt -= (5.0 - np.log10(tb)) * np.exp(-((xc - cx) ** 2 + (zc - cz) ** 2) / (2 * sig * sig))
     T = 10 ** np.clip(logt, np.log10(5e3), 5.0)
