@@ -106,25 +106,39 @@ def load(path: str, max_batch: int = 65536):
 
 
 def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 1e-3, max_iter: int = 1000,
-             ref_tol: float = 1e-5, ref_max_iter: int = 2000, storage: int = rcx.RCX_STORE_F32):
+             ref_tol: float = 1e-6, ref_max_iter: int = 2000, storage: int = rcx.RCX_STORE_F32,
+             accuracy: float = 1e-3):
     """For each seed: iterations and wall time to max change < tol from the
     LTE start and from the warm start, the largest relative difference of
     the starting guesses and of both converged results from a reference
-    iterated further (to ref_tol, or ref_max_iter iterations: the FP32 rates
-    put a floor of a few 1e-4 under the attainable change), and the
-    difference between the two converged results."""
+    iterated further (with Ng acceleration to a change below ref_tol, or
+    ref_max_iter iterations), the difference between the two converged
+    results, and the iterations each start needs until its largest relative
+    difference from the reference first drops to `accuracy` (equal
+    accuracy)."""
     import torch
     out = []
+    err = lambda p, r: float(((p - r).abs() / r.abs()).max())
     for seed in seeds:
         inp = W.nlte_atmosphere(n, seed=seed, n_line=n_line, n_cont=n_cont)
         s = rcx.Nlte(inp, storage=storage)
+        s.set_acceleration(2, 4, 4)
         ref = s.lte()
         it_r, rc_r, ch_r = 0, 1, float("inf")
         while rc_r != 0 and it_r < ref_max_iter:
             rc_r, k, ch_r = s.iterate(ref, min(50, ref_max_iter - it_r), ref_tol)
             it_r += k
             print(f"reference {n}^2 seed {seed}: {it_r} iterations, change {ch_r:.2e}", flush=True)
+        s.set_acceleration(0)
         torch.cuda.synchronize()
+        to_acc = {}
+        for name in ("lte", "warm"):
+            p = s.lte() if name == "lte" else s.warm_start(net, fn, tn)
+            k = 0
+            while k < max_iter and err(p, ref) > accuracy:
+                s.iterate(p, 1, 0.0)
+                k += 1
+            to_acc[name] = (k, err(p, ref))
         t0 = time.perf_counter()
         p_lte = s.lte()
         rc0, it0, ch0 = s.iterate(p_lte, max_iter, tol)
@@ -136,17 +150,19 @@ def evaluate(net, fn, tn, n: int, seeds, n_line: int, n_cont: int, tol: float = 
         rc1, it1, ch1 = s.iterate(p_ws, max_iter, tol)
         torch.cuda.synchronize()
         t_ws = time.perf_counter() - t0
-        err = lambda p, r=ref: float(((p - r).abs() / r.abs()).max())
         med = lambda p, r=ref: float(((p - r).abs() / r.abs()).median())
         p_lte0 = s.lte()
         out.append({
             "seed": int(seed), "n": n, "reference_iterations": it_r, "reference_change": ch_r,
-            "lte_iterations": it0, "lte_seconds": t_lte, "lte_error_vs_reference": err(p_lte),
-            "warm_iterations": it1, "warm_seconds": t_ws, "warm_error_vs_reference": err(p_ws),
-            "lte_start_error_vs_reference": err(p_lte0), "lte_start_median_error": med(p_lte0),
-            "prediction_error_vs_reference": err(p_pred), "prediction_median_error": med(p_pred),
+            "lte_iterations": it0, "lte_seconds": t_lte, "lte_error_vs_reference": err(p_lte, ref),
+            "warm_iterations": it1, "warm_seconds": t_ws, "warm_error_vs_reference": err(p_ws, ref),
+            "lte_start_error_vs_reference": err(p_lte0, ref), "lte_start_median_error": med(p_lte0),
+            "prediction_error_vs_reference": err(p_pred, ref), "prediction_median_error": med(p_pred),
             "warm_vs_lte_converged": err(p_ws, p_lte),
             "converged": bool(rc0 == 0 and rc1 == 0),
+            "accuracy": accuracy,
+            "lte_iterations_to_accuracy": to_acc["lte"][0], "lte_error_at_accuracy": to_acc["lte"][1],
+            "warm_iterations_to_accuracy": to_acc["warm"][0], "warm_error_at_accuracy": to_acc["warm"][1],
         })
         s.close()
     return out
