@@ -448,8 +448,22 @@ __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t 
     if (D.ready != kDecodeReady) k = u = v = 0;
 }
 
+// Waves per SIMD the march kernels are compiled for (their register
+// budget): 4, except the one-batch bilinear fix, held to 5 (96 VGPRs; at
+// the 99-102 it takes otherwise it runs 4 waves per SIMD and 10% slower).
+// Holding the one-batch march to 7 spills and is slower than its 6.
+template <class Op>
+struct MarchWaves {
+    static constexpr int rows = 4, fix = 4;
+};
+struct FieldOp;
+template <>
+struct MarchWaves<FieldOp> {
+    static constexpr int rows = 4, fix = 5;
+};
+
 template <class Op, class Epi, class Up>
-__global__ __launch_bounds__(kBlock, 4) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
+__global__ __launch_bounds__(kBlock, MarchWaves<Op>::rows) void k_march_rows(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                         const double4* __restrict__ dirs, Up up, int64_t total)
 {
     // per wave, per row: (cell index, ds) entries, and staged step data
@@ -568,7 +582,7 @@ __device__ __forceinline__ void march_fix_ray(const LevelDesc& L, int32_t nx, in
 // One interval per wavefront (its 4 taps on the 4 rows); total = intervals
 // of the launch (the tiled order of LevelDesc applies to intervals).
 template <class Op, class Epi, class Up>
-__global__ __launch_bounds__(kBlock, 4) void k_march_fix(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
+__global__ __launch_bounds__(kBlock, MarchWaves<Op>::fix) void k_march_fix(LevelDesc L, int32_t nx, int32_t nz, Op op, Epi epi,
                                                        const double4* __restrict__ dirs, Up up, int64_t total)
 {
     static_assert(!Op::kStaged && Op::kSmemBytes == 0, "the fix takes per-lane field ops");
