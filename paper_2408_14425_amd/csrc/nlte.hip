@@ -647,19 +647,25 @@ struct RatesEpi {
         float up = 0.0f, dn = 0.0f;
         if (ri.active) {
             const float4 e = epi_rec[cell];
-            float Vij, Vji, Uji;
+            // V_ji = A S2 is never formed on its own: for a far-UV continuum
+            // in cool gas alpha (n_i*/n_c*) e^{-h nu/kT} falls below FP32's
+            // range (2.5e-48 at 5000 K and half the Lyman edge) while each
+            // product with n_c, U0 or W, taken before S2, stays inside it
+            float Vij, A, S2, U0x;
             if (kind == 0) {
                 const float H = line_profile(op, (uint32_t)cell);
                 Vij = e.z * H;
-                Vji = gr * Vij;
-                Uji = U0 * Vji;
+                A = gr * Vij;
+                S2 = 1.0f;
+                U0x = U0;
             } else {
                 Vij = alpha[l];
-                Vji = Vij * __builtin_amdgcn_exp2f(fminf(e.z - nu[l] * e.w, 126.0f));
-                Uji = U0c[l] * Vji;
+                A = Vij;
+                S2 = __builtin_amdgcn_exp2f(fminf(e.z - nu[l] * e.w, 126.0f));
+                U0x = U0c[l];
             }
-            const float eta_t = e.y * Uji;
-            const float chi_t = e.x * Vij - e.y * Vji;   // [1/m]
+            const float eta_t = ((e.y * U0x) * A) * S2;
+            const float chi_t = e.x * Vij - (e.y * A) * S2;  // [1/m]
             const float ellm = ell_cells * voxel * path;
             const float tau = fmaxf(chi_t * ellm, 0.0f);
             const float T1 = __builtin_amdgcn_exp2f(-tau * march::kLog2e);
@@ -672,7 +678,7 @@ struct RatesEpi {
             const float stim = chi_t > 0.0f ? T1 : 1.0f - chi_t * psi;
             const float wv = W[l] * wgt;
             up = (wv * Vij) * ieff;
-            dn = (wv * Vji) * ieff + (wv * Uji) * stim;
+            dn = ((wv * A) * S2) * ieff + (((wv * U0x) * A) * S2) * stim;
         }
         // wavefront sum (fixed butterfly order: deterministic)
         for (int m = 32; m >= 1; m >>= 1) {

@@ -151,6 +151,42 @@ def test_rates_elementwise(case32, profile):
     assert eu < 1e-4 and ed < 1e-4
 
 
+def test_cool_atmosphere_far_uv_continuum():
+    """An atmosphere at 5000 K everywhere (16^2: its blobs cover the grid),
+    whose Lyman continuum at half the edge wavelength has J ~ 1e-31 (17
+    orders below the lines): 2 h nu^3 / c^2 alpha e^{-h nu / kT} is then
+    below FP32's normal range, so the rate epilogue must not form it on its
+    own. J at LTE for every wavelength to 1e-4, the rates to 1e-4 of their
+    magnitude sums, the populations after one iteration to 1e-3; a
+    continuum batch of 8 wavelengths (half a batch)."""
+    torch = _torch()
+    from oracle import nlte
+    from paper_2408_14425_amd import rcx
+    inp = W.nlte_atmosphere(16, seed=5, n_line=16, n_cont=8)
+    assert inp.T.max() <= 5000.0 + 1e-9
+    P = nlte.Problem(inp)
+    print(f"[gpu] nlte cool atmosphere {inp.name}", flush=True)
+    s = rcx.Nlte(inp)
+    pops = s.lte()
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64)
+    rg = rates.cpu().numpy()
+    s.iterate(pops, 1, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    relJ = np.abs(Jg - Jo) / np.abs(Jo)
+    eu, ed = _rates_vs_oracle(rg, P, P.lte, I0, chi_loc, H_loc)
+    po, _ = P.iterate(P.lte.copy(), 1)
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"J max rel {relJ.max():.3e} (smallest J {Jo.min():.2e}), rates {eu:.3e} / {ed:.3e}, "
+          f"pops {relp.max():.3e}")
+    assert relJ.max() < 1e-4
+    assert eu < 1e-4 and ed < 1e-4
+    assert relp.max() < 1e-3
+
+
 def test_two_continuum_batches():
     """32 continuum wavelengths: two continuum batches, which the march pairs
     per lane on the cascades with at most 256 directions. J to 1e-4, the
