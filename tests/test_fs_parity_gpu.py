@@ -7,6 +7,8 @@ rays here).
 """
 import math
 
+import os
+
 import numpy as np
 import pytest
 
@@ -115,15 +117,23 @@ def test_deterministic_bitwise():
     assert np.array_equal(a, b)
 
 
-def test_full_size_1024_64_wavelengths_sampled():
+def test_full_size_1024_64_wavelengths_sampled(tmp_path):
     """The benchmark workload (1024^2, 64 wavelengths, 7 cascades) in the
-    benchmark's launch configuration; J compared at sampled (cell, wavelength)
-    points that the oracle computes through their dependency cones."""
+    benchmark's launch configuration (the launch orders of the committed
+    autotuner cache, read from a copy); J compared at sampled (cell,
+    wavelength) points that the oracle computes through their dependency
+    cones."""
+    import shutil
     torch = _torch()
     from paper_2408_14425_amd import rcx
     inp = W.line_medium(1024, 64, seed=2)
     print("[gpu] full-size 1024^2 x 64 formal solve", flush=True)
     plan = rcx.Plan(1024, 1024, 64)
+    cache = tmp_path / "launch_orders.jsonl"
+    shutil.copy(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2408_14425_amd",
+                             "data", "launch_orders.jsonl"), cache)
+    plan.autotune(str(cache))
+    print("launch orders:", [plan.get_order(i) for i in range(7)], flush=True)
     chi = torch.from_numpy(inp.chi).cuda()
     eta = torch.from_numpy(inp.eta).cuda()
     J = plan.formal_solve(chi, eta)
