@@ -260,9 +260,11 @@ int32_t rcx_plan_destroy(rcx_plan* plan);
  * into generations by their distance from the atmosphere's top cascade;
  * each generation is one launch that sweeps the rays of all its tasks, and
  * stream order provides every dependency, so no workgroup waits on another.
- * Cascade 0 writes J directly. The sequence of launches is captured into a
- * HIP graph and replayed, re-captured when the input or output pointers
- * change. */
+ * An atmosphere whose every cascade holds at least 2^19 rays (about 512^2
+ * and up) fills the GPU alone: it runs through its plan's own solve (the
+ * per-cascade launches of rcx_formal_solve) in the same sequence. Cascade 0
+ * writes J directly. The sequence of launches is captured into a HIP graph
+ * and replayed, re-captured when the input or output pointers change. */
 typedef struct rcx_batch rcx_batch;
 
 /* n_atm atmospheres with grids[a] and n_wave[a] wavelengths. p as for

@@ -8,9 +8,11 @@
 // b uses slot b mod K. Launches are formed by a list schedule: a set of
 // active chains advances one cascade per launch, and chains are activated
 // (in order, at most K per atmosphere) until a launch holds enough rays to
-// fill the GPU. A large atmosphere then runs one chain at a time, so its
-// batch's field data stays in the Infinity Cache across its cascades as in
-// the per-cascade path, while small atmospheres share launches. Every
+// fill the GPU, so small atmospheres share launches. An atmosphere whose
+// every cascade fills the GPU alone gains nothing from sharing and runs
+// through its plan's own solve instead (the per-cascade path, with two
+// wavelength batches per lane below 256 directions), inside the same
+// captured sequence. Every
 // dependency (the cascade above in the same chain, or the chain that used
 // the slot before) lies in an earlier launch, and stream order provides it:
 // no workgroup waits on another. A launch sweeps the concatenated rays of
@@ -147,6 +149,12 @@ struct rcx_batch {
     std::vector<int32_t> gen_task;    // task range of each generation: [gen_task[g], gen_task[g + 1])
     std::vector<int64_t> gen_rays;    // rays of each generation
     std::vector<float*> J_bound;  // J pointers the tasks were built for
+    // atmospheres large enough to fill the GPU with every one of their
+    // launches run through their plan's own solve (rcx::plan_enqueue_solve:
+    // the per-cascade path, two wavelength batches per lane below 256
+    // directions); the rest are list-scheduled
+    std::vector<char> solo;
+    int64_t solo_march = 0;  // march launches the solo atmospheres enqueued in the last solve
     // graph
     bool use_graph = true;
     hipStream_t cap = nullptr;  // capture stream (the legacy default stream cannot be captured)
@@ -186,6 +194,7 @@ bool build_work(rcx_batch* s, float* const* J)
     };
     std::vector<Chain> chains;
     for (int32_t a = 0; a < s->n_atm; ++a) {
+        if (s->solo[a]) continue;
         const rcx_plan* P = s->plans[a];
         const int64_t ncell = (int64_t)P->grid.nx * P->grid.nz;
         const int32_t K = s->n_slots[a];
@@ -297,6 +306,7 @@ bool build_work(rcx_batch* s, float* const* J)
 
 hipError_t upload_work(rcx_batch* s)
 {
+    if (s->tasks_h.empty()) return hipSuccess;  // every atmosphere runs through its plan
     if (s->tasks_h.size() > s->tasks_cap) {
         if (s->tasks_d) (void)hipFree(s->tasks_d);
         s->tasks_d = nullptr;
@@ -310,7 +320,16 @@ hipError_t upload_work(rcx_batch* s)
 // Enqueue one batch solve (no synchronisation).
 hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* eta, hipStream_t st)
 {
+    s->solo_march = 0;
     for (int32_t a = 0; a < s->n_atm; ++a) {
+        if (!s->solo[a]) continue;
+        int64_t n = 0;
+        if (plan_enqueue_solve(s->plans[a], s->n_wave[a], chi[a], eta[a], s->J_bound[a], st, &n) != RCX_OK)
+            return hipErrorInvalidValue;
+        s->solo_march += n;
+    }
+    for (int32_t a = 0; a < s->n_atm; ++a) {
+        if (s->solo[a]) continue;
         const rcx_plan* P = s->plans[a];
         const int64_t ncell = (int64_t)P->grid.nx * P->grid.nz;
         hipError_t e = launch_prep(chi[a], eta[a], s->F[a], s->n_wave[a], ncell, (float)P->grid.voxel_scale,
@@ -334,7 +353,7 @@ hipError_t enqueue(rcx_batch* s, const float* const* chi, const float* const* et
     // sparse atmospheres: J = 0 at unflagged cells
     for (int32_t a = 0; a < s->n_atm; ++a) {
         const rcx_plan* P = s->plans[a];
-        if (!P->mask_dev) continue;
+        if (s->solo[a] || !P->mask_dev) continue;
         hipError_t e = launch_mask_j(s->J_bound[a], P->mask_dev, (int64_t)P->grid.nx * P->grid.nz, s->n_wave[a], st);
         if (e != hipSuccess) return e;
     }
@@ -376,26 +395,44 @@ int32_t rcx_batch_create(int32_t n_atm, const rcx_grid* grids, const int32_t* n_
         if (r != hipSuccess && e == hipSuccess) e = r;
     };
     for (int32_t a = 0; a < n_atm; ++a) {
-        rcx_plan* P = nullptr;
-        rcx_params pa = *p;
-        int32_t rc = rcx_plan_create(&grids[a], &pa, kLB, &P);
-        if (rc != RCX_OK) {
-            rcx_batch_destroy(s);
-            return rc;
-        }
-        // the batch keeps its own buffers; the plan's own workspace is not needed
-        if (P->ws_own) {
-            (void)hipFree(P->ws_own);
-            P->ws_own = nullptr;
-        }
-        s->plans.push_back(P);
         if (n_wave[a] < 1) {
             rcx_batch_destroy(s);
             return bfail(RCX_E_INVALID, "rcx_batch_create: n_wave must be positive");
         }
+        rcx_plan* P = nullptr;
+        rcx_params pa = *p;
+        pa.flags &= ~RCX_FLAG_CHECK_INPUT;  // the batch checks its inputs itself
+        int32_t rc = rcx_plan_create(&grids[a], &pa, n_wave[a], &P);
+        if (rc != RCX_OK) {
+            rcx_batch_destroy(s);
+            return rc;
+        }
+        s->plans.push_back(P);
         s->n_wave.push_back(n_wave[a]);
         const int32_t nb = (n_wave[a] + kLB - 1) / kLB;
         s->n_batch.push_back(nb);
+        // every launch of this atmosphere fills the GPU on its own: its
+        // plan's solve, with the plan's workspace
+        bool solo = true;
+        for (int32_t i = 0; i < P->n_casc; ++i) {
+            if (P->top_skipped && i == P->n_casc - 1) continue;
+            const LevelDesc& L = P->levels[i];
+            if ((int64_t)L.px * L.pz * L.nd < s->fill_rays) solo = false;
+        }
+        s->solo.push_back(solo ? 1 : 0);
+        if (solo) {
+            s->F.push_back(nullptr);
+            s->smax.push_back(nullptr);
+            s->ebias.push_back(nullptr);
+            s->casc_index.push_back((int32_t)s->casc.size());
+            s->n_slots.push_back(0);
+            continue;
+        }
+        // list-scheduled: the batch keeps its own buffers
+        if (P->ws_own) {
+            (void)hipFree(P->ws_own);
+            P->ws_own = nullptr;
+        }
         const int64_t ncell = (int64_t)grids[a].nx * grids[a].nz;
         float2* F = nullptr;
         chk(balloc(s, &F, sizeof(float2) * ncell * nb * kLB));
@@ -539,7 +576,7 @@ int32_t rcx_batch_work(const rcx_batch* s, int64_t* rays_nonempty_host, int64_t*
 int32_t rcx_batch_launches(const rcx_batch* s, int32_t* march_host, int32_t* all_host)
 {
     if (!s || !march_host || !all_host) return bfail(RCX_E_INVALID, "rcx_batch_launches: null argument");
-    const int32_t march = s->gen_task.empty() ? 0 : (int32_t)s->gen_task.size() - 1;
+    const int32_t march = (s->gen_task.empty() ? 0 : (int32_t)s->gen_task.size() - 1) + (int32_t)s->solo_march;
     int32_t other = 0;
     if (march > 0)
         for (int32_t a = 0; a < s->n_atm; ++a) {

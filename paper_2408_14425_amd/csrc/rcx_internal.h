@@ -227,6 +227,17 @@ struct rcx_plan {
     bool timing = false;
     std::vector<Timed> pending;
     int64_t n_solves = 0;
+    int64_t n_march_enqueued = 0;  // march launches enqueued since plan_enqueue_solve began
 };
+
+namespace rcx {
+// The formal solve of rcx_formal_solve on the plan's own workspace, enqueue
+// only: no argument or input check and no synchronisation, so a stream
+// capture may record it (the batched path runs its large atmospheres
+// through it). *march_launches (nullable) receives the march launches it
+// enqueued.
+int32_t plan_enqueue_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                           hipStream_t st, int64_t* march_launches);
+}  // namespace rcx
 
 

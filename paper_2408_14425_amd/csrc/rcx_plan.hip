@@ -221,6 +221,7 @@ void count_work(rcx_plan* p)
 template <class F>
 hipError_t timed(rcx_plan* p, int32_t level, hipStream_t st, F&& launch)
 {
+    if (level >= 0) ++p->n_march_enqueued;
     if (!p->timing) return launch();
     rcx_plan::Timed t{level, nullptr, nullptr};
     hipError_t e = hipEventCreate(&t.a);
@@ -476,6 +477,38 @@ int32_t solve_batches(rcx_plan* p, int32_t n_wave, float* J, const WsLayout& w, 
             b += pair ? 2 : 1;
         }
     }
+    return ok();
+}
+
+
+// The launches of one formal solve (after any input check).
+int32_t enqueue_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                             const WsLayout& w, char* ws, hipStream_t st)
+{
+    const int64_t ncell = (int64_t)p->grid.nx * p->grid.nz;
+    float2* F = (float2*)(ws + w.F);
+    if (p->timing) ++p->n_solves;
+    const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
+    unsigned int* smax = (unsigned int*)(ws + w.smax);
+    int32_t* ebias = (int32_t*)(ws + w.ebias);
+    const int32_t lb = batch_width();
+    const int32_t n_batch = (n_wave + lb - 1) / lb;
+    if (p->mask_dev && p->levels[0].n_active == 0) {
+        // sparse with nothing flagged: J = 0
+        RCX_HIP_TRY(launch_mask_j(J, p->mask_dev, ncell, n_wave, st));
+        return ok();
+    }
+    RCX_HIP_TRY(timed(p, -1, st, [&] {
+        hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
+        if (e == hipSuccess && f16) e = launch_ebias(n_batch * lb, smax, ebias, st);
+        // sparse: unflagged cells transparent and empty (Sec. 3.5)
+        if (e == hipSuccess && p->mask_dev) e = launch_mask_fields(F, p->mask_dev, ncell, n_batch, st);
+        return e;
+    }));
+    const int32_t rc = solve_batches(p, n_wave, J, w, ws, st);
+    if (rc != RCX_OK || !p->mask_dev) return rc;
+    // sparse: J = 0 at unflagged cells
+    RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_mask_j(J, p->mask_dev, ncell, n_wave, st); }));
     return ok();
 }
 
@@ -744,42 +777,17 @@ int32_t rcx_formal_solve(rcx_plan* p, int32_t n_wave, const float* chi, const fl
     } else if (ws_bytes < w.total) {
         return fail(RCX_E_WORKSPACE, "rcx_formal_solve: workspace smaller than rcx_plan_workspace_bytes");
     }
-    const int64_t ncell = (int64_t)p->grid.nx * p->grid.nz;
-    float2* F = (float2*)(ws + w.F);
-
-    if (p->timing) ++p->n_solves;
-    const bool f16 = p->prm.storage == RCX_STORE_F16_SCALED;
-    unsigned int* smax = (unsigned int*)(ws + w.smax);
-    int32_t* ebias = (int32_t*)(ws + w.ebias);
-    const int32_t lb = batch_width();
-    const int32_t n_batch = (n_wave + lb - 1) / lb;
     if (p->prm.flags & RCX_FLAG_CHECK_INPUT) {
         // chi and eta finite and non-negative (synchronises the stream)
         unsigned int* flag = (unsigned int*)(ws + w.flag);
-        const int64_t n = (int64_t)n_wave * ncell;
+        const int64_t n = (int64_t)n_wave * p->grid.nx * p->grid.nz;
         RCX_HIP_TRY(launch_zero_flag(flag, st));
         RCX_HIP_TRY(launch_check_f32(chi, n, kCheckNonNegative, flag, st));
         RCX_HIP_TRY(launch_check_f32(eta, n, kCheckNonNegative, flag, st));
         const int32_t rc = check_flag_result(flag, "rcx_formal_solve: chi or eta", st);
         if (rc != RCX_OK) return rc;
     }
-    if (p->mask_dev && p->levels[0].n_active == 0) {
-        // sparse with nothing flagged: J = 0
-        RCX_HIP_TRY(launch_mask_j(J, p->mask_dev, ncell, n_wave, st));
-        return ok();
-    }
-    RCX_HIP_TRY(timed(p, -1, st, [&] {
-        hipError_t e = launch_prep(chi, eta, F, n_wave, ncell, (float)p->grid.voxel_scale, f16 ? smax : nullptr, st);
-        if (e == hipSuccess && f16) e = launch_ebias(n_batch * lb, smax, ebias, st);
-        // sparse: unflagged cells transparent and empty (Sec. 3.5)
-        if (e == hipSuccess && p->mask_dev) e = launch_mask_fields(F, p->mask_dev, ncell, n_batch, st);
-        return e;
-    }));
-    const int32_t rc = solve_batches(p, n_wave, J, w, ws, st);
-    if (rc != RCX_OK || !p->mask_dev) return rc;
-    // sparse: J = 0 at unflagged cells
-    RCX_HIP_TRY(timed(p, -1, st, [&] { return launch_mask_j(J, p->mask_dev, ncell, n_wave, st); }));
-    return ok();
+    return enqueue_solve(p, n_wave, chi, eta, J, w, ws, st);
 }
 
 int32_t rcx_plan_set_timing(rcx_plan* p, int32_t enable)
@@ -1000,3 +1008,17 @@ int32_t rcx_last_error(char* buf, size_t n)
 }
 
 }  // extern "C"
+
+namespace rcx {
+int32_t plan_enqueue_solve(rcx_plan* p, int32_t n_wave, const float* chi, const float* eta, float* J,
+                           hipStream_t st, int64_t* march_launches)
+{
+    if (!p || !p->ws_own || n_wave <= 0 || n_wave > p->max_wave)
+        return fail(RCX_E_INVALID, "plan_enqueue_solve: no own workspace or n_wave outside [1, max_wave]");
+    p->n_march_enqueued = 0;
+    const int32_t rc = enqueue_solve(p, n_wave, chi, eta, J, ws_layout(p, n_wave), (char*)p->ws_own, st);
+    if (march_launches) *march_launches = p->n_march_enqueued;
+    return rc;
+}
+}  // namespace rcx
+

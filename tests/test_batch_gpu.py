@@ -207,3 +207,53 @@ def test_sparse_atmospheres_in_a_batch():
     B.close()
     for a in range(len(cases)):
         assert np.array_equal(again[a], dense[a]), a
+
+
+def test_large_atmosphere_runs_through_its_plan_inside_the_batch():
+    """An atmosphere whose every cascade holds at least 2^19 rays (512^2)
+    runs through its plan's own solve inside the batch's captured sequence:
+    its J equals a separate plan's bit for bit (the same launches) and
+    stays so over graph replays, next to list-scheduled small atmospheres;
+    sampled cells of it agree with the FP64 oracle. 20 wavelengths: a
+    pair of batches (the second partly filled) shares the walks on the
+    cascades with at most 256 directions."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    cases = [(512, 512, 20, 11), (40, 24, 5, 12), (32, 32, 18, 13)]
+    print("[gpu] batch with a 512^2 atmosphere", cases, flush=True)
+    host, chi, eta = _inputs(cases)
+    B = rcx.Batch([(nx, nz) for nx, nz, _, _ in cases], [nw for _, _, nw, _ in cases])
+    J = B.solve(chi, eta)
+    torch.cuda.synchronize()
+    first = [j.cpu().numpy() for j in J]
+    n_march, n_all = B.launches()
+    for _ in range(2):
+        B.solve(chi, eta, J)  # graph replays
+    torch.cuda.synchronize()
+    again = [j.cpu().numpy() for j in J]
+    B.close()
+    for a in range(len(cases)):
+        assert np.array_equal(first[a], again[a])
+    plan = rcx.Plan(512, 512, 20)
+    Jp = plan.formal_solve(chi[0], eta[0]).cpu().numpy()
+    w = plan.work()
+    plan.close()
+    assert np.array_equal(first[0], Jp)
+    # the plan's launches (cascades of two batches, paired below 256
+    # directions) plus at least one per small atmosphere's cascade
+    assert n_march > w.n_cascades and n_all == n_march + len(cases)
+    for a, (nx, nz, nw, _) in enumerate(cases[1:], start=1):
+        plan = rcx.Plan(nx, nz, nw)
+        Jq = plan.formal_solve(chi[a], eta[a]).cpu().numpy().astype(np.float64)
+        plan.close()
+        assert _rel(first[a].astype(np.float64), Jq) <= 1e-6
+    rng = np.random.default_rng(5)
+    cells = [(0, 0), (511, 511)] + [tuple(int(c) for c in rng.integers(0, 512, 2)) for _ in range(2)]
+    need = np.zeros((512, 512), np.uint8)
+    for x, z in cells:
+        need[z, x] = 1
+    for lam in (0, 19):
+        Jo = oracle.formal_solve(host[0][0][lam:lam + 1], host[0][1][lam:lam + 1], W.n_cascades_for(512, 512),
+                                 need=need)["J"][0]
+        for x, z in cells:
+            assert abs(float(first[0][lam, z, x]) - Jo[z, x]) <= RTOL * Jo[z, x], (lam, x, z)
