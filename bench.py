@@ -719,7 +719,7 @@ def main():
             "cell_steps_per_step": work.cell_steps * inp.n_wave,
             "cell_steps_per_s": work.cell_steps * inp.n_wave / (dt / args.steps),
             "kernel_ms_per_cascade": [m / max(n_solves, 1) for m in ms_level],
-            "launch_orders": {"per_cascade_tile_p_tile_d_xcd_chunk": orders,
+            "launch_orders": {"per_cascade_tile_p_tile_d_xcd_chunk_shared_walk": orders,
                               "source": "defaults" if args.no_autotune else os.path.relpath(args.orders, ROOT)},
             "kernel_ms_prep_and_J": ms_other / max(n_solves, 1),
             "finite": ok,
@@ -731,7 +731,7 @@ def main():
         "emergent": emergent,
         "roofline": {
             "bound": "alu",
-            "kernel": "k_march_rows",
+            "kernel": "k_march_rows and k_march_shared (every march launch of the solve)",
             "achieved": alu_achieved,
             "peak": VALU_SLOTS / 1e12,
             "unit": "T VALU lane slots/s (FP32 FMA = 1, v_exp_f32 = 4)",

@@ -224,23 +224,30 @@ int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_ot
                             int64_t* n_march_launches_host, int64_t* n_solves_host);
 
 /* Launch order of cascade `level`'s march (the rays of a launch run in
- * this order; results do not depend on it): tile_p = 0 for probe-major
- * order (directions of a probe consecutive), else groups of tile_p x tile_p
- * probes x tile_d directions (tile_d a multiple of 4 dividing the cascade's
- * directions), and workgroups given to the 8 XCDs in chunks of xcd_chunk
- * consecutive ones. Defaults: 4 x 4 x 32, chunk 128, on cascades with at
- * least 256 directions; probe-major, chunk 128, below. A sparse plan's
- * flagged-probe lists are rebuilt to follow the order (synchronous).
- * RCX_E_INVALID for a bad level or order. */
-int32_t rcx_plan_set_order(rcx_plan* plan, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk);
-/* order3_host = {tile_p, tile_d, xcd_chunk} of cascade `level`. */
-int32_t rcx_plan_get_order(const rcx_plan* plan, int32_t level, int32_t* order3_host);
+ * this order; results do not depend on it, bit for bit): tile_p = 0 for
+ * probe-major order (directions of a probe consecutive), else groups of
+ * tile_p x tile_p probes x tile_d directions (tile_d a multiple of 4
+ * dividing the cascade's directions), and workgroups given to the 8 XCDs in
+ * chunks of xcd_chunk consecutive ones. shared_walk = 1 (0 or 1): with an
+ * even tile_p, on a dense plan, the field march (not the cascade-0 J
+ * launch) takes the rays of a group probe-fastest, so the 4 rays of a
+ * wavefront are 4 probes of one direction, and walks their cells once for
+ * all 4 (their probe centres lie whole cells apart; every ray still
+ * marches exactly its own segments). Defaults: 4 x 4 x 32, chunk 128, row
+ * walks, on cascades with at least 256 directions; probe-major, chunk 128,
+ * below. A sparse plan's flagged-probe lists are rebuilt to follow the
+ * order (synchronous). RCX_E_INVALID for a bad level or order. */
+int32_t rcx_plan_set_order(rcx_plan* plan, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk,
+                           int32_t shared_walk);
+/* order4_host = {tile_p, tile_d, xcd_chunk, shared_walk} of cascade `level`. */
+int32_t rcx_plan_get_order(const rcx_plan* plan, int32_t level, int32_t* order4_host);
 
 /* Autotuner of the launch order (growth pattern (2)): for every cascade
  * with at least 256 directions, times the plan's formal solve of up to 32
  * wavelengths on uniform fields (the march's work and memory traffic do not
  * depend on the values) for each candidate order, tile_p in {0, 2, 4, 8} x
- * tile_d in {16, 32, 64} x xcd_chunk in {32, 128, 512}, with the plan's
+ * tile_d in {16, 32, 64} x xcd_chunk in {32, 128, 512} x shared_walk in
+ * {0, 1} (for tile_p > 0), with the plan's
  * kernel timing, and keeps the fastest per cascade. cache_path (nullable): a
  * text file of JSON lines keyed by the device (architecture, compute units)
  * and the plan's geometry, storage, flags and sparsity; a hit applies the

@@ -474,7 +474,8 @@ int32_t rcx_batch_set_order(rcx_batch* s, int32_t tile_probes, int32_t tile_dirs
     for (rcx_plan* P : s->plans)
         for (int32_t i = 0; i < P->n_casc; ++i) {
             if (P->levels[i].nd < kWideDirs) continue;
-            const int32_t rc = rcx_plan_set_order(P, i, tile_probes, tile_dirs, P->levels[i].xcd_chunk);
+            const int32_t rc =
+                rcx_plan_set_order(P, i, tile_probes, tile_dirs, P->levels[i].xcd_chunk, P->levels[i].shared_walk);
             if (rc != RCX_OK) return rc;
         }
     s->J_bound.clear();  // rebuild the task list on the next solve (after the stream has finished)

@@ -17,6 +17,7 @@
 #include "march_rows.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 namespace rcx {
@@ -242,8 +243,24 @@ hipError_t launch_fs(const LevelDesc& L0, int32_t nx, int32_t nz, const Op& op, 
                      const Up& up, hipStream_t st)
 {
     LevelDesc L = L0;
+    // dense tiled orders of the field ops with an even tile and whole-cell
+    // probe spacing run the 4 rows of a wavefront on one direction and
+    // share its cell walk (bitwise the same results); the J epilogues sum
+    // the 4 rows as the 4 directions of one probe and keep the row walk
+    constexpr bool kShareable =
+        (std::is_same<Op, march::FieldOp>::value || std::is_same<Op, march::FieldOp2>::value) &&
+        !std::is_same<Epi, march::JEpi>::value && !std::is_same<Epi, march::JEpi2>::value;
+    const bool shared =
+        kShareable && L.shared_walk && L.tile_p > 0 && L.tile_p % 2 == 0 && !L.plist && L.s == std::floor(L.s);
     if (!set_decode(L)) return hipErrorInvalidValue;  // more rays than 31-bit indices
     const int64_t total = level_launch_rays(L);
+    if constexpr (kShareable) {
+        if (shared) {
+            hipLaunchKernelGGL((march::k_march_shared<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz,
+                               op, epi, dirs, up, total);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((march::k_march_rows<Op, Epi, Up>), march_grid(total), dim3(kBlock), 0, st, L, nx, nz, op, epi,
                        dirs, up, total);
     return hipGetLastError();

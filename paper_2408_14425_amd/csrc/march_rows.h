@@ -14,6 +14,8 @@
 // front to back, which equals the back-to-front piecewise-constant solution
 // of Sec. 3.2. The merge with the cascade above (Sec. 2.3.1) follows:
 //   Itilde = I + T * sum_taps w_x w_z (1/4) sum_j Itilde_up(tap, 4k + j).
+// In k_march_shared the 4 rows are 4 probes of one direction and one walk
+// of 64 columns serves all four (walk_ray_shared), with the same segments.
 #pragma once
 
 #include "rcx_internal.h"
@@ -161,6 +163,18 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
     T *= e;
 }
 
+// Plane crossings. A ray line from c = k + f per axis (k = floor(c), f =
+// c - k, both exact) meets plane X at t = ((X - k) - f) / w: X - k is an
+// exact integer and, for probe centres (f = 0 or 1/2), so is its difference
+// with f, so t takes one rounding and is the same for every start point
+// moved by whole cells. Walks from probes whole cells apart therefore find
+// bitwise the same segments (walk_ray_shared relies on it), and the
+// crossing of the domain's exit plane equals the clip bound exactly.
+__device__ __forceinline__ double plane_t(double X, double k, double f, double inv_w)
+{
+    return ((X - k) - f) * inv_w;
+}
+
 // Walk one ray per row: the segments of the line (cx, cz) + t (wx, wz),
 // t in [t_lo, t_hi), that lie in the domain (d = {wx, wz, 1/wx, 1/wz}),
 // stepped front to back into I and T (Op::kW slots per lane). Rows with walk
@@ -181,11 +195,9 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
 {
     const int row = cx_.row, l = cx_.l;
     const uint64_t row_bits = cx_.row_bits, lt_bits = cx_.lt_bits;
-    // Plane crossings t(X) = X / w - c / w, evaluated with one FMA so the
-    // crossing of the domain's exit plane equals the clip bound exactly.
-    const double offx = -cx * d.z, offz = -cz * d.w;
-    const double ax = offx, bx = fma((double)nx, d.z, offx);
-    const double az = offz, bz = fma((double)nz, d.w, offz);
+    const double kx = floor(cx), kz = floor(cz), fx = cx - kx, fz = cz - kz;
+    const double ax = plane_t(0.0, kx, fx, d.z), bx = plane_t((double)nx, kx, fx, d.z);
+    const double az = plane_t(0.0, kz, fz, d.w), bz = plane_t((double)nz, kz, fz, d.w);
     double lo = fmax(t_lo, fmax(fmin(ax, bx), fmin(az, bz)));
     double hi = fmin(t_hi, fmin(fmax(ax, bx), fmax(az, bz)));
     if (!walk) {
@@ -196,15 +208,16 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
     // Major axis m (the one crossed at least as often), minor axis n.
     const bool xmaj = fabs(d.x) >= fabs(d.y);
     const double wm = xmaj ? d.x : d.y, wn = xmaj ? d.y : d.x;
-    const double cm = xmaj ? cx : cz, cn = xmaj ? cz : cx;
+    const double km = xmaj ? kx : kz, kn = xmaj ? kz : kx, fm = xmaj ? fx : fz, fn = xmaj ? fz : fx;
     const double im_ = xmaj ? d.z : d.w, in_ = xmaj ? d.w : d.z;
-    const double offm = xmaj ? offx : offz, offn = xmaj ? offz : offx;
     const int nm = xmaj ? nx : nz, nn = xmaj ? nz : nx;
     const int strm = xmaj ? 1 : nx, strn = xmaj ? nx : 1;
     const int sm = wm > 0.0 ? 1 : -1, sn = wn > 0.0 ? 1 : -1;
+    const int ikm = (int)km, ikn = (int)kn;
 
-    const double pm0 = cm + lo * wm;
-    int im0 = wm > 0.0 ? (int)floor(pm0) : (int)ceil(pm0) - 1;
+    // major-axis position at lo relative to km
+    const double qm0 = fm + lo * wm;
+    int im0 = ikm + (wm > 0.0 ? (int)floor(qm0) : (int)ceil(qm0) - 1);
     im0 = min(max(im0, 0), nm - 1);
     const int mfirst = wm > 0.0 ? im0 + 1 : im0;  // first m-plane crossed
 
@@ -218,24 +231,25 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
         T[w] = 1.0f;
     }
     const int max_chunks = (nm + 2 + 15) / 16 + 1;
-    // Minor-axis cell of a crossing at pn: floor(pn) if sn > 0, else
-    // ceil(pn) - 1 = ~floor(-pn); both as floor(sn * pn) ^ nflip (sn * pn is
-    // exact). The products below stay within 24 bits (cell < 2^24).
+    // Minor-axis cell of a crossing at kn + qn: kn + floor(qn) if sn > 0,
+    // else kn + ceil(qn) - 1 = kn + ~floor(-qn); both as kn + (floor(sn * qn)
+    // ^ nflip) (sn * qn is exact). The products below stay within 24 bits
+    // (cell < 2^24).
     const double snd = (double)sn;
     const int nflip = sn > 0 ? 0 : -1, nadd = sn > 0 ? 1 : 0;
     for (int chunk = 0; chunk < max_chunks; ++chunk) {
         // ---- column j of this row's ray: one or two segments
         const int j = chunk * 16 + l;
         const int pj = mfirst + __mul24(j - 1, sm);  // m-plane entering column j
-        const double ta = (j == 0) ? lo : fma((double)pj, im_, offm);
-        const double tb_ = fmin(fma((double)(pj + sm), im_, offm), hi);
+        const double ta = (j == 0) ? lo : plane_t((double)(pj - ikm), 0.0, fm, im_);
+        const double tb_ = fmin(plane_t((double)(pj + sm - ikm), 0.0, fm, im_), hi);
         const bool valid = ta < hi;
         const int im = min(max(im0 + __mul24(j, sm), 0), nm - 1);
-        const double pn = cn + ta * wn;
-        int in0 = (int)floor(snd * pn) ^ nflip;
+        const double qn = fn + ta * wn;
+        int in0 = ikn + ((int)floor(snd * qn) ^ nflip);
         in0 = min(max(in0, 0), nn - 1);
         const int nnext = in0 + nadd;
-        const double tn = fma((double)nnext, in_, offn);
+        const double tn = plane_t((double)(nnext - ikn), 0.0, fn, in_);
         const bool two = valid && tn < tb_;
         const double tmid = fmax(tn, ta);
         const int in1 = min(max(in0 + sn, 0), nn - 1);
@@ -334,6 +348,208 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
     }
 }
 
+// Shared-direction walk (k_march_shared): the 4 rows of the
+// wavefront march one direction from 4 probes whose centres lie whole cells
+// apart (integral probe spacing). One cooperative walk, 64 columns per chunk
+// in the frame of row 0's probe on an unbounded grid, serves all four: row
+// r's cell of a segment is the reference cell moved by r's probe offset, a
+// constant step of the cell key. The domain's planes are grid planes of that
+// frame and plane_t gives their crossings bitwise as row r's own walk would,
+// so each segment lies wholly inside or outside row r's clip range
+// [lo_r, hi_r]; the inside ones are a contiguous run of the list, found per
+// chunk from ballots, and the rest step with the null key (no opacity, no
+// emission). Row r thus steps the segments walk_ray would give it, with the
+// same lengths, in the same order (up to zero-length ones, which change
+// nothing): the results are bitwise those of walk_ray. The walk covers the
+// union of the four ranges; the per-row walk runs 4 walks of 16 columns in
+// its place.
+constexpr int kSegShared = 128;  // entries per wavefront and chunk: 64 columns, <= 2 each
+
+__device__ __forceinline__ double uniform_d(double x)
+{
+    const uint64_t b = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <class Op>
+__device__ __forceinline__ void walk_ray_shared(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, int32_t u,
+                                                int32_t v, const double4 d, bool walk, uint2* seg,
+                                                const RowCtx& cx_, float (&I)[Op::kW], float (&T)[Op::kW])
+{
+    static_assert(!Op::kStaged, "the shared walk takes per-lane field ops");
+    constexpr int W = Op::kW;
+    const int lane = cx_.lane, row = cx_.row;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        I[w] = 0.0f;
+        T[w] = 1.0f;
+    }
+    // this row's clip range, as in walk_ray; +inf/-inf when it walks nothing
+    const double cx = (u + 0.5) * L.s, cz = (v + 0.5) * L.s;
+    double lo, hi;
+    {
+        const double kx = floor(cx), kz = floor(cz), fx = cx - kx, fz = cz - kz;
+        const double ax = plane_t(0.0, kx, fx, d.z), bx = plane_t((double)nx, kx, fx, d.z);
+        const double az = plane_t(0.0, kz, fz, d.w), bz = plane_t((double)nz, kz, fz, d.w);
+        lo = fmax(L.ta, fmax(fmin(ax, bx), fmin(az, bz)));
+        hi = fmin(L.tb, fmin(fmax(ax, bx), fmax(az, bz)));
+        if (!walk || !(lo < hi)) {
+            lo = INFINITY;
+            hi = -INFINITY;
+        }
+    }
+    double lo_q[4], hi_q[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        lo_q[q] = uniform_d(__shfl(lo, 16 * q));
+        hi_q[q] = uniform_d(__shfl(hi, 16 * q));
+    }
+    const double T0 = fmin(fmin(lo_q[0], lo_q[1]), fmin(lo_q[2], lo_q[3]));
+    const double T1 = fmax(fmax(hi_q[0], hi_q[1]), fmax(hi_q[2], hi_q[3]));
+    if (!(T0 < T1)) return;  // no row walks anything
+
+    // reference frame: row 0's probe; row offsets in whole cells
+    const int32_t u0 = __builtin_amdgcn_readfirstlane(u), v0 = __builtin_amdgcn_readfirstlane(v);
+    const int32_t is = (int32_t)L.s;
+    const double c0x = (u0 + 0.5) * L.s, c0z = (v0 + 0.5) * L.s;
+    // row r's cell key = reference key + dkey (mod 2^32; exact for cells in the domain)
+    const uint32_t dkey =
+        ((uint32_t)((v - v0) * is) * (uint32_t)nx + (uint32_t)((u - u0) * is)) * (uint32_t)(kLB * 8);
+
+    const double k0x = floor(c0x), k0z = floor(c0z), fx = c0x - k0x, fz = c0z - k0z;
+    const bool xmaj = fabs(d.x) >= fabs(d.y);
+    const double wm = xmaj ? d.x : d.y, wn = xmaj ? d.y : d.x;
+    const double fm = xmaj ? fx : fz, fn = xmaj ? fz : fx;
+    const int ikm = (int)(xmaj ? k0x : k0z), ikn = (int)(xmaj ? k0z : k0x);
+    const double im_ = xmaj ? d.z : d.w, in_ = xmaj ? d.w : d.z;
+    const uint32_t kstrm = xmaj ? (uint32_t)(kLB * 8) : (uint32_t)nx * (kLB * 8);
+    const uint32_t kstrn = xmaj ? (uint32_t)nx * (kLB * 8) : (uint32_t)(kLB * 8);
+    const int sm = wm > 0.0 ? 1 : -1, sn = wn > 0.0 ? 1 : -1;
+    // the same arithmetic as walk_ray, unclamped (cells outside the domain
+    // belong to no row's range)
+    const double qm0 = fm + T0 * wm;
+    const int im0 = ikm + (wm > 0.0 ? (int)floor(qm0) : (int)ceil(qm0) - 1);
+    const int mfirst = wm > 0.0 ? im0 + 1 : im0;
+    const double snd = (double)sn;
+    const int nflip = sn > 0 ? 0 : -1, nadd = sn > 0 ? 1 : 0;
+    // columns crossed: at most (T1 - T0) |wm| + 2
+    const int max_chunks = (int)((T1 - T0) * fabs(wm) * (1.0 / 64.0)) + 2;
+
+    for (int chunk = 0; chunk < max_chunks; ++chunk) {
+        const int j = chunk * 64 + lane;
+        const int pj = mfirst + (j - 1) * sm;
+        const double ta = (j == 0) ? T0 : plane_t((double)(pj - ikm), 0.0, fm, im_);
+        const double tb_ = fmin(plane_t((double)(pj + sm - ikm), 0.0, fm, im_), T1);
+        const bool valid = ta < T1;
+        const int im = im0 + j * sm;
+        const double qn = fn + ta * wn;
+        const int in0 = ikn + ((int)floor(snd * qn) ^ nflip);
+        const double tn = plane_t((double)(in0 + nadd - ikn), 0.0, fn, in_);
+        const bool two = valid && tn < tb_;
+        const double tmid = fmax(tn, ta);
+        const double tend1 = two ? tmid : tb_;
+        const uint32_t key1 = (uint32_t)im * kstrm + (uint32_t)in0 * kstrn;
+        const uint32_t key2 = key1 + (sn > 0 ? kstrn : 0u - kstrn);
+        const float ds1 = (float)(fmax(tend1 - ta, 0.0) * L.ds_scale);
+        const float ds2 = (float)(fmax(tb_ - tmid, 0.0) * L.ds_scale);
+
+        const uint64_t b1 = __ballot(valid);
+        if (b1 == 0) break;
+        const uint64_t b2 = __ballot(two);
+        const int pos = (int)__popcll(b1 & cx_.lt_bits) + (int)__popcll(b2 & cx_.lt_bits);
+        const int n = (int)__builtin_amdgcn_readfirstlane((int)__popcll(b1) + (int)__popcll(b2));
+        // each row's run [a_q, e_q) of the list: a_q entries start before
+        // lo_q, e_q end at or before hi_q (row q's clip bounds are crossings
+        // of this walk, bitwise, so no segment straddles them)
+        int a_q[4], e_q[4];
+        bool full = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a_q[q] = (int)__popcll(__ballot(valid && ta < lo_q[q])) + (int)__popcll(__ballot(two && tmid < lo_q[q]));
+            e_q[q] = (int)__popcll(__ballot(valid && tend1 <= hi_q[q])) + (int)__popcll(__ballot(two && tb_ <= hi_q[q]));
+            full = full && a_q[q] == 0 && e_q[q] == n;
+        }
+        const int a = row == 0 ? a_q[0] : row == 1 ? a_q[1] : row == 2 ? a_q[2] : a_q[3];
+        const int e = row == 0 ? e_q[0] : row == 1 ? e_q[1] : row == 2 ? e_q[2] : e_q[3];
+        const uint32_t len = (uint32_t)max(e - a, 0);
+        // null entries first, then the list (one wavefront's LDS writes
+        // execute in issue order)
+        seg[lane] = make_uint2(Op::kNullKey, 0u);
+        seg[lane + 64] = make_uint2(Op::kNullKey, 0u);
+        if (valid) seg[pos] = make_uint2(key1, __float_as_uint(ds1));
+        if (two) seg[pos + 1] = make_uint2(key2, __float_as_uint(ds2));
+        wave_sync();
+
+        const uint4* seg4 = reinterpret_cast<const uint4*>(seg);
+        for (int s = 0; s < n; s += 4) {
+            const uint4 e01 = seg4[s >> 1];
+            const uint4 e23 = seg4[(s >> 1) + 1];
+            const uint32_t keys[4] = {e01.x, e01.z, e23.x, e23.z};
+            const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
+                                  __uint_as_float(e23.w)};
+            typename Op::Raw raw[4][W];
+            if (full && s + 4 <= n) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) op.fetch_key(keys[q] + dkey, raw[q]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    op.fetch_key((uint32_t)(s + q - a) < len ? keys[q] + dkey : Op::kNullKey, raw[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int w = 0; w < W; ++w) step(op.resolve(raw[q][w]), dsv[q], I[w], T[w]);
+        }
+        wave_sync();
+    }
+}
+
+// Merge the marched (I, T) of one row's ray with the cascade above and
+// hand it to the epilogue.
+template <class Op, class Epi, class Up>
+__device__ __forceinline__ void merge_finish(const LevelDesc& L, Op& op, Epi& epi, const Up& up, const RayInfo& ri,
+                                             int l, int lane, float (&I)[Op::kW], const float (&T)[Op::kW])
+{
+    constexpr int W = Op::kW;
+    if (ri.active && L.has_up) {
+        // Bilinear taps on the cascade above: q = (u + 1/2)/2 - 1/2, so
+        // even u -> taps (u/2 - 1, u/2) with weights (1/4, 3/4), odd u ->
+        // taps ((u-1)/2, (u+1)/2) with weights (3/4, 1/4); clamped.
+        const int bx0 = (ri.u - 1) >> 1, bz0 = (ri.v - 1) >> 1;
+        const float fx = (ri.u & 1) ? 0.25f : 0.75f;
+        const float fz = (ri.v & 1) ? 0.25f : 0.75f;
+        const int txs[2] = {min(max(bx0, 0), L.qx - 1), min(max(bx0 + 1, 0), L.qx - 1)};
+        const int tzs[2] = {min(max(bz0, 0), L.qz - 1), min(max(bz0 + 1, 0), L.qz - 1)};
+        const float wxs[2] = {1.0f - fx, fx};
+        const float wzs[2] = {1.0f - fz, fz};
+        float far[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) far[w] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) {
+                const int64_t bi = (((int64_t)tzs[a] * L.qx + txs[bb]) * L.nd_up + 4 * (int64_t)ri.k) * kLB + l;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const float c4 =
+                        up.get(bi, w) + up.get(bi + kLB, w) + up.get(bi + 2 * kLB, w) + up.get(bi + 3 * kLB, w);
+                    far[w] = fmaf(wzs[a] * wxs[bb], 0.25f * c4, far[w]);
+                }
+            }
+#pragma unroll
+        for (int w = 0; w < W; ++w) I[w] = fmaf(T[w], far[w], I[w]);
+    }
+    if constexpr (W == 1) {
+        epi.finish(ri, l, lane, I[0], op);
+    } else {
+        epi.finish_slots(ri, l, lane, I, op);
+    }
+}
+
 // March, merge and finish one ray per row. ray = output index of the ray
 // in its cascade, (u, v, k) its probe and direction; active false for rows
 // past the end (they still take part in the wavefront-wide ballots).
@@ -396,8 +612,32 @@ __device__ __forceinline__ void march_ray(const LevelDesc& L, int32_t nx, int32_
     }
 }
 
+// march_ray with the shared-direction walk (the 4 rows hold one direction).
+template <class Op, class Epi, class Up>
+__device__ __forceinline__ void march_ray_shared(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, Epi& epi,
+                                                 const double4* __restrict__ dirs, const Up& up, uint2* seg,
+                                                 const RowCtx& cx_, int64_t ray, int32_t u, int32_t v, int32_t k,
+                                                 bool active)
+{
+    RayInfo ri;
+    ri.ray = ray;
+    ri.active = active;
+    ri.k = k;
+    ri.u = u;
+    ri.v = v;
+    const double4 d = dirs[__builtin_amdgcn_readfirstlane(k)];
+    ri.wx = d.x;
+    ri.wz = d.y;
+    op.begin_ray(d.x, d.y);
+    constexpr int W = Op::kW;
+    float I[W], T[W];
+    walk_ray_shared(L, nx, nz, op, u, v, d, active, seg, cx_, I, T);
+    merge_finish(L, op, epi, up, ri, cx_.l, cx_.lane, I, T);
+}
+
 // Probe and direction of launch-order ray r (of total): probe-major, or
 // the tiled order of LevelDesc; active false past the end and on padding.
+template <bool kShared = false>
 __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t r, int64_t total, int32_t& k,
                                                     int32_t& u, int32_t& v, bool& active)
 {
@@ -436,12 +676,33 @@ __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t 
         v = (int32_t)pv;
     } else {
         // group g = (probe tile, direction wedge), wedge fastest; within
-        // a group, direction fastest
+        // a group, direction fastest (kShared: probe fastest)
         const uint32_t g = D.per.div(rr), r_in = rr - g * D.per.d;
-        const uint32_t t = D.nw.div(g), pl = D.tile_d.div(r_in);
-        k = (int32_t)((g - t * D.nw.d) * D.tile_d.d + (r_in - pl * D.tile_d.d));
-        const uint32_t ty = D.ntx.div(t), py = D.tile_p.div(pl);
-        u = (int32_t)((t - ty * D.ntx.d) * D.tile_p.d + (pl - py * D.tile_p.d));
+        const uint32_t t = D.nw.div(g);
+        uint32_t pl, kd;
+        if (kShared) {
+            kd = D.tp2.div(r_in);
+            pl = r_in - kd * D.tp2.d;
+        } else {
+            pl = D.tile_d.div(r_in);
+            kd = r_in - pl * D.tile_d.d;
+        }
+        k = (int32_t)((g - t * D.nw.d) * D.tile_d.d + kd);
+        const uint32_t ty = D.ntx.div(t);
+        uint32_t py = D.tile_p.div(pl), pxl = pl - py * D.tile_p.d;
+        if (kShared) {
+            // consecutive probes of a tile row run along the direction's
+            // major axis: theta_k = (2k + 1) pi / nd is x-major when
+            // (2k + 1) mod nd lies within nd / 4 of 0 or nd
+            const uint32_t m = 2u * (uint32_t)k + 1u, mm = m >= (uint32_t)L.nd ? m - (uint32_t)L.nd : m;
+            const bool xmaj = 4u * mm <= (uint32_t)L.nd || 4u * mm >= 3u * (uint32_t)L.nd;
+            if (xmaj) {
+                const uint32_t tmp = py;
+                py = pxl;
+                pxl = tmp;
+            }
+        }
+        u = (int32_t)((t - ty * D.ntx.d) * D.tile_p.d + pxl);
         v = (int32_t)(ty * D.tile_p.d + py);
         active = active && u < L.px && v < L.pz;
     }
@@ -454,12 +715,12 @@ __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t 
 // Holding the one-batch march to 7 spills and is slower than its 6.
 template <class Op>
 struct MarchWaves {
-    static constexpr int rows = 4, fix = 4;
+    static constexpr int rows = 4, fix = 4, shared = 8;
 };
 struct FieldOp;
 template <>
 struct MarchWaves<FieldOp> {
-    static constexpr int rows = 4, fix = 5;
+    static constexpr int rows = 4, fix = 5, shared = 8;
 };
 
 template <class Op, class Epi, class Up>
@@ -499,6 +760,31 @@ __global__ __launch_bounds__(kBlock, MarchWaves<Op>::rows) void k_march_rows(Lev
         ray_coords(L, base + c.row, total, k, u, v, active);
         const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;  // output index
         march_ray(L, nx, nz, op, epi, dirs, up, seg[c.w], stg[Op::kStaged ? c.w : 0], c, ray, u, v, k, active);
+    }
+}
+
+// The march with the shared-direction walk, for tiled launch orders with an
+// even tile_p and an integral probe spacing: the rays of a tile run probe
+// fastest (ray_coords<true>), so the 4 rows of every wavefront are 4 probes
+// of one direction (total is a multiple of 4: whole tiles).
+template <class Op, class Epi, class Up>
+__global__ __launch_bounds__(kBlock, MarchWaves<Op>::shared) void k_march_shared(LevelDesc L, int32_t nx, int32_t nz, Op op,
+                                                                             Epi epi, const double4* __restrict__ dirs,
+                                                                             Up up, int64_t total)
+{
+    __shared__ uint2 seg[kBlock / 64][kSegShared];
+    const RowCtx c = row_ctx();
+    op.init(c.l);
+    epi.init(c.l);
+    up.init(c.l);
+    const unsigned lb = xcd_block_chunked(blockIdx.x, gridDim.x, L.dec);
+    const int64_t stride = (int64_t)gridDim.x * kRaysPerBlock;
+    for (int64_t base = ((int64_t)lb * (kBlock / 64) + c.w) * 4; base < total; base += stride) {
+        int32_t k, u, v;
+        bool active;
+        ray_coords<true>(L, base + c.row, total, k, u, v, active);
+        const int64_t ray = ((int64_t)v * L.px + u) * L.nd + k;  // output index
+        march_ray_shared(L, nx, nz, op, epi, dirs, up, seg[c.w], c, ray, u, v, k, active);
     }
 }
 

@@ -50,6 +50,11 @@ struct LevelDesc {
     // groups of tile_p x tile_p probes x tile_d directions, so the rays a
     // launch runs at one time cross a compact band of cells.
     int32_t tile_p, tile_d;
+    // 1: the field march of a tiled order with an even tile_p runs the 4
+    // rows of a wavefront on one direction and shares their cell walk
+    // (march_rows.h, k_march_shared; bitwise the same results), else one
+    // walk per row
+    int32_t shared_walk = 0;
     // workgroups are given to the 8 XCDs in chunks of xcd_chunk consecutive
     // ones (march_rows.h, xcd_block_chunked)
     int32_t xcd_chunk = 128;

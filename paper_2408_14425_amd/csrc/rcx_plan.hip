@@ -826,17 +826,20 @@ int32_t rcx_plan_get_timing(rcx_plan* p, double* ms_level, double* ms_other, int
     return rc == RCX_OK ? ok() : rc;
 }
 
-int32_t rcx_plan_set_order(rcx_plan* p, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk)
+int32_t rcx_plan_set_order(rcx_plan* p, int32_t level, int32_t tile_p, int32_t tile_d, int32_t xcd_chunk,
+                           int32_t shared_walk)
 {
     if (!p || level < 0 || level >= p->n_casc) return fail(RCX_E_INVALID, "rcx_plan_set_order: bad plan or level");
     LevelDesc& L = p->levels[level];
-    if (tile_p < 0 || tile_p > 64 || xcd_chunk < 1 || xcd_chunk > (1 << 16))
-        return fail(RCX_E_INVALID, "rcx_plan_set_order: tile_p must be in [0, 64], xcd_chunk in [1, 65536]");
+    if (tile_p < 0 || tile_p > 64 || xcd_chunk < 1 || xcd_chunk > (1 << 16) || (shared_walk != 0 && shared_walk != 1))
+        return fail(RCX_E_INVALID,
+                    "rcx_plan_set_order: tile_p must be in [0, 64], xcd_chunk in [1, 65536], shared_walk 0 or 1");
     if (tile_p > 0 && (tile_d < 4 || tile_d % 4 != 0 || L.nd % tile_d != 0))
         return fail(RCX_E_INVALID, "rcx_plan_set_order: tile_d must be a multiple of 4 dividing the directions");
     L.tile_p = tile_p;
     L.tile_d = tile_p > 0 ? tile_d : 0;
     L.xcd_chunk = xcd_chunk;
+    L.shared_walk = shared_walk;
     if (p->mask_dev) {
         // the flagged-probe lists follow the launch order: rebuild them
         const std::vector<uint8_t> flags = p->active_host;
@@ -845,14 +848,15 @@ int32_t rcx_plan_set_order(rcx_plan* p, int32_t level, int32_t tile_p, int32_t t
     return ok();
 }
 
-int32_t rcx_plan_get_order(const rcx_plan* p, int32_t level, int32_t* order3_host)
+int32_t rcx_plan_get_order(const rcx_plan* p, int32_t level, int32_t* order4_host)
 {
-    if (!p || !order3_host || level < 0 || level >= p->n_casc)
+    if (!p || !order4_host || level < 0 || level >= p->n_casc)
         return fail(RCX_E_INVALID, "rcx_plan_get_order: bad argument");
     const LevelDesc& L = p->levels[level];
-    order3_host[0] = L.tile_p;
-    order3_host[1] = L.tile_d;
-    order3_host[2] = L.xcd_chunk;
+    order4_host[0] = L.tile_p;
+    order4_host[1] = L.tile_d;
+    order4_host[2] = L.xcd_chunk;
+    order4_host[3] = L.shared_walk;
     return ok();
 }
 
@@ -873,7 +877,8 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
     std::ostringstream key;
     key << prop.gcnArchName << "/" << prop.multiProcessorCount << "cu/" << nx << "x" << nz << "/c" << p->n_casc
         << "/d" << p->prm.c0_dirs << "/t1=" << p->prm.c0_t1 << "/r" << p->prm.t_rule << "/s" << p->prm.storage
-        << "/i" << p->prm.n_incl << "/f" << (p->prm.flags & RCX_FLAG_BILINEAR_FIX) << "/w" << n_wave;
+        << "/i" << p->prm.n_incl << "/f" << (p->prm.flags & RCX_FLAG_BILINEAR_FIX) << "/w" << n_wave
+        << "/walk2";  // orders with the walk mode (a fifth field)
     if (p->mask_dev) key << "/sparse" << p->levels[0].n_active;
     const std::string k = key.str();
     const std::string pre = "{\"key\": \"" + k + "\", \"orders\": \"";
@@ -882,14 +887,14 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
         std::string line;
         while (std::getline(f, line)) {
             if (line.compare(0, pre.size(), pre) != 0) continue;
-            // "level:tile_p:tile_d:chunk,..." up to the closing quote
+            // "level:tile_p:tile_d:chunk:walk,..." up to the closing quote
             std::istringstream in(line.substr(pre.size(), line.find('"', pre.size()) - pre.size()));
             std::string item;
             int32_t rc = RCX_OK;
             while (rc == RCX_OK && std::getline(in, item, ',')) {
-                int lv = -1, tp = 0, td = 0, ch = 0;
-                if (std::sscanf(item.c_str(), "%d:%d:%d:%d", &lv, &tp, &td, &ch) == 4)
-                    rc = rcx_plan_set_order(p, lv, tp, td, ch);
+                int lv = -1, tp = 0, td = 0, ch = 0, sw = 0;
+                if (std::sscanf(item.c_str(), "%d:%d:%d:%d:%d", &lv, &tp, &td, &ch, &sw) == 5)
+                    rc = rcx_plan_set_order(p, lv, tp, td, ch, sw);
             }
             return rc;
         }
@@ -897,13 +902,14 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
     // time candidate orders on uniform fields (the march's work and memory
     // traffic do not depend on the values)
     struct Cand {
-        int32_t tp, td, ch;
+        int32_t tp, td, ch, sw;
     };
     std::vector<Cand> cands;
     for (int32_t ch : {32, 128, 512}) {
-        cands.push_back({0, 0, ch});
+        cands.push_back({0, 0, ch, 0});
         for (int32_t tp : {2, 4, 8})
-            for (int32_t td : {16, 32, 64}) cands.push_back({tp, td, ch});
+            for (int32_t td : {16, 32, 64})
+                for (int32_t sw : {0, 1}) cands.push_back({tp, td, ch, sw});
     }
     std::vector<LevelDesc> saved = p->levels;
     const bool timing = p->timing;
@@ -926,7 +932,7 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
     for (size_t c = 0; c < cands.size() && rc == RCX_OK && e == hipSuccess; ++c) {
         for (int32_t i : tun) {
             const int32_t td = cands[c].tp > 0 && p->levels[i].nd % cands[c].td != 0 ? 4 : cands[c].td;
-            rc = rcx_plan_set_order(p, i, cands[c].tp, td, cands[c].ch);
+            rc = rcx_plan_set_order(p, i, cands[c].tp, td, cands[c].ch, cands[c].sw);
             if (rc != RCX_OK) break;
         }
         if (rc != RCX_OK) break;
@@ -959,9 +965,10 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
         for (size_t c = 1; c < cands.size(); ++c)
             if (ms[c][i] < ms[best][i]) best = c;
         const int32_t td = cands[best].tp > 0 && p->levels[i].nd % cands[best].td != 0 ? 4 : cands[best].td;
-        rc = rcx_plan_set_order(p, i, cands[best].tp, td, cands[best].ch);
+        rc = rcx_plan_set_order(p, i, cands[best].tp, td, cands[best].ch, cands[best].sw);
         if (rc != RCX_OK) return rc;
-        orders << (q ? "," : "") << i << ":" << cands[best].tp << ":" << p->levels[i].tile_d << ":" << cands[best].ch;
+        orders << (q ? "," : "") << i << ":" << cands[best].tp << ":" << p->levels[i].tile_d << ":" << cands[best].ch
+               << ":" << cands[best].sw;
         times << (q ? "," : "") << i << ":" << ms[best][i] / 2.0 << "/" << ms[0][i] / 2.0;
     }
     if (cache_path) {

@@ -75,7 +75,7 @@ def load() -> C.CDLL:
     L.rcx_emergent.argtypes = [vp, i32, vp, vp, C.c_double, C.c_double, i32, vp, vp]
     L.rcx_formal_solve.argtypes = [vp, i32, vp, vp, vp, vp, sz, vp]
     L.rcx_formal_solve_noalloc.argtypes = [vp, i32, vp, vp, vp, vp]
-    L.rcx_plan_set_order.argtypes = [vp, i32, i32, i32, i32]
+    L.rcx_plan_set_order.argtypes = [vp, i32, i32, i32, i32, i32]
     L.rcx_plan_get_order.argtypes = [vp, i32, C.POINTER(i32)]
     L.rcx_autotune.argtypes = [vp, C.c_char_p, vp]
     L.rcx_plan_destroy.argtypes = [vp]
@@ -270,13 +270,16 @@ class Plan:
         rcx_formal_solve(self.handle, n_wave, chi, eta, J, workspace, stream)
         return J
 
-    def set_order(self, level: int, tile_p: int, tile_d: int = 32, xcd_chunk: int = 128):
-        """Launch order of cascade `level` (tile_p = 0: probe-major)."""
-        _check(load().rcx_plan_set_order(self.handle, int(level), int(tile_p), int(tile_d), int(xcd_chunk)),
+    def set_order(self, level: int, tile_p: int, tile_d: int = 32, xcd_chunk: int = 128, shared_walk: int = 0):
+        """Launch order of cascade `level` (tile_p = 0: probe-major;
+        shared_walk = 1: one cell walk for the 4 rays of a wavefront)."""
+        _check(load().rcx_plan_set_order(self.handle, int(level), int(tile_p), int(tile_d), int(xcd_chunk),
+                                         int(shared_walk)),
                "rcx_plan_set_order")
 
     def get_order(self, level: int):
-        out = (C.c_int32 * 3)()
+        """(tile_p, tile_d, xcd_chunk, shared_walk) of cascade `level`."""
+        out = (C.c_int32 * 4)()
         _check(load().rcx_plan_get_order(self.handle, int(level), out), "rcx_plan_get_order")
         return tuple(out)
 
