@@ -229,8 +229,10 @@ int32_t rcx_plan_get_timing(rcx_plan* plan, double* ms_level_host, double* ms_ot
  * tile_p x tile_p probes x tile_d directions (tile_d a multiple of 4
  * dividing the cascade's directions), and workgroups given to the 8 XCDs in
  * chunks of xcd_chunk consecutive ones. shared_walk = 1 (0 or 1): with an
- * even tile_p, on a dense plan, the field march (not the cascade-0 J
- * launch) takes the rays of a group probe-fastest, so the 4 rays of a
+ * even tile_p, in the basic march of a dense plan with one inclination (not
+ * the bilinear-fix kernel, not the cascade-0 J launch; elsewhere the
+ * setting is kept but changes nothing), the march takes the rays of a group
+ * probe-fastest, so the 4 rays of a
  * wavefront are 4 probes of one direction, and walks their cells once for
  * all 4 (their probe centres lie whole cells apart; every ray still
  * marches exactly its own segments). Defaults: 4 x 4 x 32, chunk 128, row
@@ -247,7 +249,7 @@ int32_t rcx_plan_get_order(const rcx_plan* plan, int32_t level, int32_t* order4_
  * wavelengths on uniform fields (the march's work and memory traffic do not
  * depend on the values) for each candidate order, tile_p in {0, 2, 4, 8} x
  * tile_d in {16, 32, 64} x xcd_chunk in {32, 128, 512} x shared_walk in
- * {0, 1} (for tile_p > 0), with the plan's
+ * {0, 1} (for tile_p > 0, where the walk applies), with the plan's
  * kernel timing, and keeps the fastest per cascade. cache_path (nullable): a
  * text file of JSON lines keyed by the device (architecture, compute units)
  * and the plan's geometry, storage, flags and sparsity; a hit applies the

@@ -691,9 +691,10 @@ __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t 
         const uint32_t ty = D.ntx.div(t);
         uint32_t py = D.tile_p.div(pl), pxl = pl - py * D.tile_p.d;
         if (kShared) {
-            // consecutive probes of a tile row run along the direction's
-            // major axis: theta_k = (2k + 1) pi / nd is x-major when
-            // (2k + 1) mod nd lies within nd / 4 of 0 or nd
+            // 4 consecutive probes (a wavefront's rows) run along the
+            // direction's minor axis, where their clip ranges differ least:
+            // theta_k = (2k + 1) pi / nd is x-major when (2k + 1) mod nd
+            // lies within nd / 4 of 0 or nd
             const uint32_t m = 2u * (uint32_t)k + 1u, mm = m >= (uint32_t)L.nd ? m - (uint32_t)L.nd : m;
             const bool xmaj = 4u * mm <= (uint32_t)L.nd || 4u * mm >= 3u * (uint32_t)L.nd;
             if (xmaj) {
@@ -715,12 +716,12 @@ __host__ __device__ __forceinline__ void ray_coords(const LevelDesc& L, int64_t 
 // Holding the one-batch march to 7 spills and is slower than its 6.
 template <class Op>
 struct MarchWaves {
-    static constexpr int rows = 4, fix = 4, shared = 8;
+    static constexpr int rows = 4, fix = 4, shared = 4;
 };
 struct FieldOp;
 template <>
 struct MarchWaves<FieldOp> {
-    static constexpr int rows = 4, fix = 5, shared = 8;
+    static constexpr int rows = 4, fix = 5, shared = 4;
 };
 
 template <class Op, class Epi, class Up>

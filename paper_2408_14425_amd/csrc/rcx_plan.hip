@@ -904,12 +904,22 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
     struct Cand {
         int32_t tp, td, ch, sw;
     };
+    // the shared walk serves the basic march of a dense plan with one
+    // inclination (with the bilinear fix, only its top marched cascade);
+    // elsewhere its setting changes nothing and is kept 0
+    auto walk_applies = [p](int32_t i) {
+        return !p->mask_dev && p->prm.n_incl == 1 &&
+               (!(p->prm.flags & RCX_FLAG_BILINEAR_FIX) || !p->levels[i].has_up);
+    };
+    bool walk_cands = false;
+    for (int32_t i : tun) walk_cands = walk_cands || walk_applies(i);
     std::vector<Cand> cands;
     for (int32_t ch : {32, 128, 512}) {
         cands.push_back({0, 0, ch, 0});
         for (int32_t tp : {2, 4, 8})
             for (int32_t td : {16, 32, 64})
-                for (int32_t sw : {0, 1}) cands.push_back({tp, td, ch, sw});
+                for (int32_t sw : {0, 1})
+                    if (sw == 0 || walk_cands) cands.push_back({tp, td, ch, sw});
     }
     std::vector<LevelDesc> saved = p->levels;
     const bool timing = p->timing;
@@ -932,7 +942,7 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
     for (size_t c = 0; c < cands.size() && rc == RCX_OK && e == hipSuccess; ++c) {
         for (int32_t i : tun) {
             const int32_t td = cands[c].tp > 0 && p->levels[i].nd % cands[c].td != 0 ? 4 : cands[c].td;
-            rc = rcx_plan_set_order(p, i, cands[c].tp, td, cands[c].ch, cands[c].sw);
+            rc = rcx_plan_set_order(p, i, cands[c].tp, td, cands[c].ch, walk_applies(i) ? cands[c].sw : 0);
             if (rc != RCX_OK) break;
         }
         if (rc != RCX_OK) break;
@@ -965,10 +975,11 @@ int32_t rcx_autotune(rcx_plan* p, const char* cache_path, hipStream_t st)
         for (size_t c = 1; c < cands.size(); ++c)
             if (ms[c][i] < ms[best][i]) best = c;
         const int32_t td = cands[best].tp > 0 && p->levels[i].nd % cands[best].td != 0 ? 4 : cands[best].td;
-        rc = rcx_plan_set_order(p, i, cands[best].tp, td, cands[best].ch, cands[best].sw);
+        const int32_t sw = walk_applies(i) ? cands[best].sw : 0;
+        rc = rcx_plan_set_order(p, i, cands[best].tp, td, cands[best].ch, sw);
         if (rc != RCX_OK) return rc;
         orders << (q ? "," : "") << i << ":" << cands[best].tp << ":" << p->levels[i].tile_d << ":" << cands[best].ch
-               << ":" << cands[best].sw;
+               << ":" << sw;
         times << (q ? "," : "") << i << ":" << ms[best][i] / 2.0 << "/" << ms[0][i] / 2.0;
     }
     if (cache_path) {
