@@ -443,6 +443,14 @@ int32_t rcx_nlte_stat_eq(rcx_nlte* s, const float* rates, double* pops_inout,
 int32_t rcx_nlte_iterate(rcx_nlte* s, double* pops_inout, int32_t max_iter, double tol,
                          int32_t* iters_host, double* last_change_host, hipStream_t stream);
 
+/* Launch orders of the solver's marches: rcx_autotune on the solver's own
+ * plan (its formal solve of 16 wavelengths timed for each candidate order,
+ * cache_path as there). The line and continuum marches take the chosen
+ * orders too; every result is bitwise the same under any order (each ray's
+ * arithmetic does not depend on where it runs). Synchronises the stream.
+ * Errors: as rcx_autotune. */
+int32_t rcx_nlte_autotune(rcx_nlte* s, const char* cache_path, hipStream_t stream);
+
 /* Kernel timing for measurement: when enabled, every march launch of the
  * formal solution (rcx_nlte_formal_solve_rates, rcx_nlte_iterate) records
  * two HIP events on its stream. rcx_nlte_get_timing synchronises on them

@@ -2015,6 +2015,14 @@ int32_t rcx_nlte_dims(const rcx_nlte* s, int32_t* nl, int32_t* nt)
     return RCX_OK;
 }
 
+int32_t rcx_nlte_autotune(rcx_nlte* s, const char* cache_path, hipStream_t stream)
+{
+    if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_autotune: null solver");
+    // the solver marches with its plan's launch orders (results do not
+    // depend on them): tune them on the plan's own formal solve
+    return rcx_autotune(s->plan, cache_path, stream);
+}
+
 int32_t rcx_nlte_set_timing(rcx_nlte* s, int32_t enable)
 {
     if (!s) return nlte_fail(RCX_E_INVALID, "rcx_nlte_set_timing: null solver");

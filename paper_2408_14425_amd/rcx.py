@@ -373,8 +373,9 @@ def _load_nlte():
     L.rcx_nlte_warm_start.argtypes = [vp, vp, vp, vp, vp, vp]
     L.rcx_nlte_pops_from_prediction.argtypes = [vp, vp, vp, vp, vp]
     L.rcx_nlte_set_timing.argtypes = [vp, i32]
+    L.rcx_nlte_autotune.argtypes = [vp, C.c_char_p, vp]
     L.rcx_nlte_get_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
-    for n in ("rcx_nlte_set_timing", "rcx_nlte_get_timing", "rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start", "rcx_nlte_pops_from_prediction",
+    for n in ("rcx_nlte_set_timing", "rcx_nlte_get_timing", "rcx_nlte_autotune", "rcx_nlte_features", "rcx_nlte_log_departures", "rcx_nlte_warm_start", "rcx_nlte_pops_from_prediction",
               "rcx_nlte_set_charge_conservation", "rcx_nlte_get_ne", "rcx_nlte_emergent", "rcx_nlte_set_pressure_conservation",
               "rcx_nlte_collisional_ne", "rcx_nlte_set_temperature_cut"):
         getattr(L, n).restype = i32
@@ -526,6 +527,12 @@ class Nlte:
     def set_timing(self, enable: bool):
         """Record HIP events around every march launch (measurement)."""
         _check(_load_nlte().rcx_nlte_set_timing(self.handle, int(bool(enable))), "rcx_nlte_set_timing")
+
+    def autotune(self, cache_path=None, stream=None):
+        """rcx_nlte_autotune: tune the launch orders of the solver's marches
+        (cached per device and geometry in cache_path)."""
+        _check(_load_nlte().rcx_nlte_autotune(self.handle, None if cache_path is None else str(cache_path).encode(),
+                                              _stream_ptr(stream)), "rcx_nlte_autotune")
 
     def get_timing(self):
         """{'line': (ms, launches, cell steps x wavelengths), 'continuum':

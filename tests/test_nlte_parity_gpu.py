@@ -675,3 +675,26 @@ def test_emergent_spectra_of_a_sparse_solver():
     print(f"sparse emergent spectra: max rel {rel.max():.3e}")
     assert np.all(Ig[~hit] == 0.0)
     assert rel.max() < 1e-4
+
+
+def test_autotune_keeps_the_iteration_bitwise(tmp_path):
+    """rcx_nlte_autotune changes only the launch orders of the solver's
+    marches (each ray's arithmetic does not depend on where it runs): one
+    iteration from LTE gives bitwise the same populations with the tuned
+    orders as with the defaults, and the tuner appends one cache line."""
+    torch = _torch()
+    from paper_2408_14425_amd import rcx
+    inp = W.nlte_atmosphere(64, seed=4, n_line=16, n_cont=8)
+    print(f"[gpu] nlte autotune {inp.name}", flush=True)
+    out = []
+    for tuned in (False, True):
+        s = rcx.Nlte(inp)
+        if tuned:
+            s.autotune(tmp_path / "orders.jsonl")
+        p = s.lte()
+        s.iterate(p, 1, 0.0)
+        torch.cuda.synchronize()
+        out.append(p.clone())
+        s.close()
+    assert (tmp_path / "orders.jsonl").read_text().count("\n") == 1
+    assert torch.equal(out[0], out[1])
