@@ -245,7 +245,9 @@ __device__ __forceinline__ float voigt_small_a(const float2* __restrict__ gtab, 
 {
     const float x2 = ax * ax;
     const float e = __builtin_amdgcn_exp2f(-x2 * march::kLog2e);
-    const float fx = fminf(ax * kInvDg, (float)(kNg - 1) - 1e-3f);
+    // with ax < kXTab (kCore) ax * kInvDg (a power of two: exact) is below
+    // kNg - 1, so the index needs no clamp
+    const float fx = kCore ? ax * kInvDg : fminf(ax * kInvDg, (float)(kNg - 1) - 1e-3f);
     const float2 q = gtab[(int)fx];
     const float gt = fmaf(__builtin_amdgcn_fractf(fx), q.y, q.x);
     const float g = (!kCore && ax >= (float)kXTab) ? -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2)) : gt;
@@ -581,13 +583,12 @@ struct LineOpT {
     {
         if constexpr (kSmallA) {
             float ax[4];
-            bool wing = false;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ax[q] = fabsf(fmaf(u, raw[q].r.w, raw[q].v.x));
-                wing = wing || ax[q] >= (float)kXTab;
-            }
-            if (__ballot(wing) != 0) {
+            for (int q = 0; q < 4; ++q) ax[q] = fabsf(fmaf(u, raw[q].r.w, raw[q].v.x));
+            // one compare of the group's largest |x| (a NaN lane takes the
+            // core path, whose index conversion maps it to entry 0)
+            const float ax_max = fmaxf(fmaxf(ax[0], ax[1]), fmaxf(ax[2], ax[3]));
+            if (__ballot(ax_max >= (float)kXTab) != 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     f[q] = make_float2(raw[q].r.x * voigt_small_a(tab, raw[q].p.x, raw[q].p.y, ax[q]), raw[q].r.y);
