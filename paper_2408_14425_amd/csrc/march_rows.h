@@ -183,10 +183,11 @@ __device__ __forceinline__ double plane_t(double X, double k, double f, double i
 // An Op whose step data depends on the cell only (the same for all 16
 // wavelength lanes of a row) sets kStaged: the lane that finds a segment
 // loads that data once (Op::stage_load, then Op::stage_make forms the
-// entry) while the row's segment list is built,
-// and the step loop reads it back from LDS (stg, this wavefront's
+// entry with the segment's length folded in) in place of a segment-list
+// entry, and the step loop reads it back from LDS (stg, this wavefront's
 // [4 rows][kSegs] entries) instead of issuing a dependent global load per
-// step; Op::resolve4 turns a group of 4 staged steps into {chi, S}.
+// step; Op::resolve4 turns a group of 4 staged steps into {optical depth
+// of the step, S}.
 template <class Op>
 __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t nz, Op& op, double cx, double cz,
                                          const double4 d, double t_lo, double t_hi, bool walk,
@@ -277,40 +278,41 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
             n_max = max(n_max, (int)__popcll(b1 & rb) + (int)__popcll(b2 & rb));
         }
         n_max = __builtin_amdgcn_readfirstlane(n_max);
-        uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
-        // entries: the Op's key of the cell (a byte offset for per-lane
-        // fields) and ds; positions past the row's count hold a null entry
-        // (no data, ds = 0), so the step loop needs no bounds test. Null
-        // entries are written everywhere first and the row's segments over
-        // them (the LDS executes one wavefront's writes in issue order).
-        srow[l] = make_uint2(Op::kNullKey, 0u);
-        srow[l + 16] = make_uint2(Op::kNullKey, 0u);
-        if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
-        if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
+        // Null entries are written everywhere first and the row's segments
+        // over them (the LDS executes one wavefront's writes in issue order),
+        // so the step loop needs no bounds test.
         if constexpr (Op::kStaged) {
-            // staged entries past the row's count keep an earlier record (or
-            // the zeros of the kernel's start): finite, and met with ds = 0
-            if (valid) stg[row][pos] = op.stage_make(st1);
-            if (two) stg[row][pos + 1] = op.stage_make(st2);
+            // staged records with their segment length folded in
+            // (Op::stage_make); a null record (zeros) is a step with no
+            // opacity and no emission. No segment list is needed.
+            stg[row][l] = typename Op::Stage{};
+            stg[row][l + 16] = typename Op::Stage{};
+            if (valid) stg[row][pos] = op.stage_make(st1, ds1);
+            if (two) stg[row][pos + 1] = op.stage_make(st2, ds2);
+        } else {
+            // entries: the Op's key of the cell (a byte offset for per-lane
+            // fields) and ds; a null entry has no data and ds = 0
+            uint2* srow = reinterpret_cast<uint2*>(&seg[row][0]);
+            srow[l] = make_uint2(Op::kNullKey, 0u);
+            srow[l + 16] = make_uint2(Op::kNullKey, 0u);
+            if (valid) srow[pos] = make_uint2(op.key(cell1), __float_as_uint(ds1));
+            if (two) srow[pos + 1] = make_uint2(op.key(cell2), __float_as_uint(ds2));
         }
         wave_sync();
 
         // ---- step through the row's segments, 4 at a time. Positions past
         // the row's count are steps with no opacity and no emission.
         if constexpr (Op::kStaged) {
-            // step data in LDS: no global loads to overlap
+            // step data in LDS (no global loads to overlap), optical depths
+            // per step already (f.x includes ds)
             for (int s = 0; s < n_max; s += 4) {
-                const uint4 e01 = seg[row][s >> 1];
-                const uint4 e23 = seg[row][(s >> 1) + 1];
-                const float dsv[4] = {__uint_as_float(e01.y), __uint_as_float(e01.w), __uint_as_float(e23.y),
-                                      __uint_as_float(e23.w)};
                 typename Op::Raw raw[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) raw[q] = stg[row][s + q];
                 float2 f[4];
                 op.resolve4(raw, f);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step(f[q], dsv[q], I[0], T[0]);
+                for (int q = 0; q < 4; ++q) step(f[q], 1.0f, I[0], T[0]);
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a

@@ -546,10 +546,13 @@ struct LineOpT {
     static constexpr uint32_t kNullKey = 0u;
     __device__ __forceinline__ uint32_t key(uint32_t cell) const { return cell; }
     __device__ __forceinline__ StageIn stage_load(uint32_t cell) const { return StageIn{rec[cell], vel[cell]}; }
-    __device__ __forceinline__ Stage stage_make(const StageIn& in) const
+    // the entry of a segment of length ds: its opacity scale times ds, so
+    // the profile times it is the step's optical depth
+    __device__ __forceinline__ Stage stage_make(const StageIn& in, float ds) const
     {
         Stage st;
         st.r = in.r;
+        st.r.x = in.r.x * ds;
         st.v = in.v;
         st.p = kSmallA ? make_float2(in.r.z * in.r.z, (float)(2.0 / sqrt(kPi)) * in.r.z) : make_float2(0.0f, 0.0f);
         if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
