@@ -175,6 +175,24 @@ __device__ __forceinline__ double plane_t(double X, double k, double f, double i
     return ((X - k) - f) * inv_w;
 }
 
+// A step of known optical depth y = f.x (log2 units), for the staged
+// marches, whose time goes to VALU issue: 1 - 2^{-y} as the smaller of the
+// three-term series (an upper bound of it for every y >= 0: the remainder's
+// derivative is non-negative) and (1 + 2^-22) - 2^{-y} (the offset keeps the
+// cancelling form above the series where the series is the better one), with
+// no compare and select: at most 6e-6 relative, 0 at y = 0.
+__device__ __forceinline__ void step_unit(float2 f, float& I, float& T)
+{
+    constexpr float c1 = 0.6931471805599453f;  // ln 2
+    constexpr float c2 = 0.2402265069591007f;  // (ln 2)^2 / 2
+    constexpr float c3 = 0.0555041086648216f;  // (ln 2)^3 / 6
+    const float y = f.x;
+    const float e = __builtin_amdgcn_exp2f(-y);
+    const float ser = y * (c1 - y * (c2 - y * c3));
+    I = fmaf(T * f.y, fminf(ser, (1.0f + 0x1p-22f) - e), I);
+    T *= e;
+}
+
 // Walk one ray per row: the segments of the line (cx, cz) + t (wx, wz),
 // t in [t_lo, t_hi), that lie in the domain (d = {wx, wz, 1/wx, 1/wz}),
 // stepped front to back into I and T (Op::kW slots per lane). Rows with walk
@@ -312,7 +330,7 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
                 float2 f[4];
                 op.resolve4(raw, f);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step(f[q], 1.0f, I[0], T[0]);
+                for (int q = 0; q < 4; ++q) step_unit(f[q], I[0], T[0]);
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a
