@@ -254,6 +254,23 @@ __device__ __forceinline__ float voigt_small_a(const float2* __restrict__ gtab, 
     return fmaf(e, fmaf(a2, fmaf(-2.0f, x2, 1.0f), 1.0f), -ca * g);
 }
 
+// rx H(a, x) from a staged record's coefficients rx, rx a^2 and rx 2a/sqrt(pi)
+// (rx = the step's opacity scale times its length): e^{-x^2} (rx + rx a^2 (1
+// - 2 x^2)) - rx (2a / sqrt(pi)) g(x), the products with rx taken once per
+// segment when the record is staged.
+template <bool kCore = false>
+__device__ __forceinline__ float voigt_small_a_rx(const float2* __restrict__ gtab, float rx, float rxa2, float rxca,
+                                                  float ax)
+{
+    const float x2 = ax * ax;
+    const float e = __builtin_amdgcn_exp2f(-x2 * march::kLog2e);
+    const float fx = kCore ? ax * kInvDg : fminf(ax * kInvDg, (float)(kNg - 1) - 1e-3f);
+    const float2 q = gtab[(int)fx];
+    const float gt = fmaf(__builtin_amdgcn_fractf(fx), q.y, q.x);
+    const float g = (!kCore && ax >= (float)kXTab) ? -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2)) : gt;
+    return fmaf(e, fmaf(rxa2, fmaf(-2.0f, x2, 1.0f), rx), -rxca * g);
+}
+
 // g(x) = 1 - 2x F(x), with L(0, x) = (2 / sqrt(pi)) F(x) from the Fourier integral.
 __device__ double dawson_g(double x)
 {
@@ -554,7 +571,9 @@ struct LineOpT {
         st.r = in.r;
         st.r.x = in.r.x * ds;
         st.v = in.v;
-        st.p = kSmallA ? make_float2(in.r.z * in.r.z, (float)(2.0 / sqrt(kPi)) * in.r.z) : make_float2(0.0f, 0.0f);
+        // with the expansion in a: {rx a^2, rx 2a / sqrt(pi)} (voigt_small_a_rx)
+        st.p = kSmallA ? make_float2(st.r.x * (in.r.z * in.r.z), st.r.x * ((float)(2.0 / sqrt(kPi)) * in.r.z))
+                       : make_float2(0.0f, 0.0f);
         if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
         return st;
     }
@@ -575,7 +594,7 @@ struct LineOpT {
     {
         if constexpr (kSmallA) {
             const float ax = fabsf(fmaf(u, raw.r.w, raw.v.x));
-            return make_float2(raw.r.x * voigt_small_a(tab, raw.p.x, raw.p.y, ax), raw.r.y);
+            return make_float2(voigt_small_a_rx(tab, raw.r.x, raw.p.x, raw.p.y, ax), raw.r.y);
         }
         return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);
     }
@@ -594,11 +613,11 @@ struct LineOpT {
             if (__ballot(ax_max >= (float)kXTab) != 0) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    f[q] = make_float2(raw[q].r.x * voigt_small_a(tab, raw[q].p.x, raw[q].p.y, ax[q]), raw[q].r.y);
+                    f[q] = make_float2(voigt_small_a_rx(tab, raw[q].r.x, raw[q].p.x, raw[q].p.y, ax[q]), raw[q].r.y);
             } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    f[q] = make_float2(raw[q].r.x * voigt_small_a<true>(tab, raw[q].p.x, raw[q].p.y, ax[q]),
+                    f[q] = make_float2(voigt_small_a_rx<true>(tab, raw[q].r.x, raw[q].p.x, raw[q].p.y, ax[q]),
                                        raw[q].r.y);
             }
         } else {
