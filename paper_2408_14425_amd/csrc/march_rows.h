@@ -243,7 +243,6 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
     // kW wavelength batches per lane (slot w of lane l is wavelength l of
     // batch w): the walk and the segment list serve all of them
     constexpr int W = Op::kW;
-    static_assert(!Op::kStaged || W == 1, "staged ops march one batch");
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         I[w] = 0.0f;
@@ -327,10 +326,13 @@ __device__ __forceinline__ void walk_ray(const LevelDesc& L, int32_t nx, int32_t
                 typename Op::Raw raw[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) raw[q] = stg[row][s + q];
-                float2 f[4];
-                op.resolve4(raw, f);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) step_unit(f[q], I[0], T[0]);
+                for (int w = 0; w < W; ++w) {
+                    float2 f[4];
+                    op.resolve4(raw, f, w);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) step_unit(f[q], I[w], T[w]);
+                }
             }
         } else {
             // per-lane data: the 4 loads of a group are issued together (a

@@ -524,22 +524,27 @@ __global__ void k_zero_u32n(unsigned int* p, int32_t n)
 // observer's frame), chi = kappa H(a, |x|), S = S_line. kSmallA selects the
 // profile: the expansion in a (voigt_small_a, record z = a) or the compact
 // table in (a, x) (voigt_compact, record z = a / da).
-template <bool kSmallA>
+//
+// kPair: each lane marches wavelength l of two batches of the same line (u_b
+// and u_b2): one walk and one staged record per segment serve both, and the
+// cascades hold two slots (StoreEpi2 / StoreF16Epi2).
+template <bool kSmallA, bool kPair = false>
 struct LineOpT {
     const float4* rec;  // [ncell]
     const float2* vel;  // [ncell]
     const float2* tabc; // profile table [n_a][kNxc] (global; copied to LDS)
     int32_t n_a;
     const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
+    const float* u_b2 = nullptr;  // kPair: [16] of the second batch
     uint32_t ncell;
     float da_sqrtpi;    // damping step of the table / sqrt(pi)
-    float u, wx, wz;
+    float u, u2, wx, wz;
     float vscale = 1.0f;  // velocity projection: sin(theta) of an inclined ray (Sec. 3.1), 1 in the plane
     const float2* tab;  // the LDS copy
     // the cell record and velocity are the same for all wavelength lanes;
     // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)} and holds
     // (w . v) / v_th in place of the velocity's x component
-    static constexpr int kW = 1;
+    static constexpr int kW = kPair ? 2 : 1;
     static constexpr bool kStaged = true;
     struct Stage {
         float4 r;
@@ -577,7 +582,11 @@ struct LineOpT {
         if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
         return st;
     }
-    __device__ __forceinline__ void init(int l) { u = u_b[l]; }
+    __device__ __forceinline__ void init(int l)
+    {
+        u = u_b[l];
+        u2 = kPair ? u_b2[l] : u;
+    }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
         wx = (float)dwx * vscale;
@@ -590,23 +599,26 @@ struct LineOpT {
         if constexpr (kSmallA) return voigt_small_a(tab, r.z * r.z, (float)(2.0 / sqrt(kPi)) * r.z, ax);
         return voigt_compact(tab, r.z, r.z * da_sqrtpi, ax);
     }
-    __device__ __forceinline__ float2 resolve(const Raw& raw) const
+    __device__ __forceinline__ float2 resolve(const Raw& raw, float uw) const
     {
         if constexpr (kSmallA) {
-            const float ax = fabsf(fmaf(u, raw.r.w, raw.v.x));
+            const float ax = fabsf(fmaf(uw, raw.r.w, raw.v.x));
             return make_float2(voigt_small_a_rx(tab, raw.r.x, raw.p.x, raw.p.y, ax), raw.r.y);
         }
-        return make_float2(raw.r.x * profile(raw.r, raw.v), raw.r.y);
+        const float ax = fabsf((uw + wx * raw.v.x + wz * raw.v.y) * raw.r.w);
+        return make_float2(raw.r.x * voigt_compact(tab, raw.r.z, raw.r.z * da_sqrtpi, ax), raw.r.y);
     }
-    // {chi, S} of a group of 4 staged steps. With the expansion in a, the
-    // series beyond kXTab is evaluated only when a lane of the wavefront
-    // needs it (the line-core batches never do).
-    __device__ __forceinline__ void resolve4(const Raw (&raw)[4], float2 (&f)[4]) const
+    // {chi, S} of a group of 4 staged steps for slot w (the batch of u, or
+    // with kPair of u2). With the expansion in a, the series beyond kXTab is
+    // evaluated only when a lane of the wavefront needs it (the line-core
+    // batches never do).
+    __device__ __forceinline__ void resolve4(const Raw (&raw)[4], float2 (&f)[4], int w) const
     {
+        const float uw = w == 0 ? u : u2;
         if constexpr (kSmallA) {
             float ax[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) ax[q] = fabsf(fmaf(u, raw[q].r.w, raw[q].v.x));
+            for (int q = 0; q < 4; ++q) ax[q] = fabsf(fmaf(uw, raw[q].r.w, raw[q].v.x));
             // one compare of the group's largest |x| (a NaN lane takes the
             // core path, whose index conversion maps it to entry 0)
             const float ax_max = fmaxf(fmaxf(ax[0], ax[1]), fmaxf(ax[2], ax[3]));
@@ -622,7 +634,7 @@ struct LineOpT {
             }
         } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) f[q] = resolve(raw[q]);
+            for (int q = 0; q < 4; ++q) f[q] = resolve(raw[q], uw);
         }
     }
 };
@@ -1023,6 +1035,11 @@ struct rcx_nlte {
     float4* epi_rec = nullptr;
     float2* Fcont = nullptr;
     float* casc[2] = {nullptr, nullptr};
+    // two consecutive batches of one line march their cascades >= 1 in one
+    // pass (LineOpT kPair); the cascade buffers then hold two slots of
+    // casc_slot elements
+    bool pair = false;
+    int64_t casc_slot = 0;
     bool f16 = false;                 // cascades >= 1 stored as scaled FP16
     unsigned int* smax = nullptr;     // [n_batch][16] max S (float bits)
     int32_t* ebias = nullptr;         // [n_batch][16] exponent biases of the 16-bit codes
@@ -1129,6 +1146,33 @@ hipError_t launch_level_op(int32_t kind, bool small_a, const LevelDesc& L, int32
         return launch_level(L, nx, nz, sop, epi, dirs, up, st);
     }
     return launch_level(L, nx, nz, lop, epi, dirs, up, st);
+}
+
+// Cascades >= 1 of two batches of one line in one launch (LineOpT kPair:
+// u_b2 the second batch's velocity offsets; two-slot epilogue and reader).
+template <class Epi, class Up>
+hipError_t launch_level_pair(bool small_a, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
+                             const float* u_b2, const Epi& epi, const double4* dirs, const Up& up, hipStream_t st)
+{
+    auto fill = [&](auto& op) {
+        op.rec = lop.rec;
+        op.vel = lop.vel;
+        op.tabc = lop.tabc;
+        op.n_a = lop.n_a;
+        op.u_b = lop.u_b;
+        op.u_b2 = u_b2;
+        op.ncell = lop.ncell;
+        op.da_sqrtpi = lop.da_sqrtpi;
+        op.vscale = lop.vscale;
+    };
+    if (small_a) {
+        LineOpT<true, true> pop{};
+        fill(pop);
+        return launch_level(L, nx, nz, pop, epi, dirs, up, st);
+    }
+    LineOpT<false, true> pop{};
+    fill(pop);
+    return launch_level(L, nx, nz, pop, epi, dirs, up, st);
 }
 
 // Emergent intensity along a beam of parallel long characteristics (Sec.
@@ -1346,8 +1390,13 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->line_rec, sizeof(float4) * std::max(1, A.n_lines) * nc));
     chk(dmalloc(s, &s->epi_rec, sizeof(float4) * nt * nc));
     chk(dmalloc(s, &s->Fcont, sizeof(float2) * std::max(1, s->n_cont_batches) * nc * kLB));
-    chk(dmalloc(s, &s->casc[0], sizeof(float) * max_entries * kLB));
-    chk(dmalloc(s, &s->casc[1], sizeof(float) * max_entries * kLB));
+    // line pairs need a second slot (and at least one cascade above 0)
+    for (int32_t b = 0; b + 1 < nb; ++b)
+        if (A.t[s->batches[b].trans].kind == 0 && s->batches[b + 1].trans == s->batches[b].trans) s->pair = true;
+    s->pair = s->pair && s->plan->n_casc >= 2 && !(s->plan->top_skipped && s->plan->n_casc == 2);
+    s->casc_slot = max_entries * kLB;
+    chk(dmalloc(s, &s->casc[0], sizeof(float) * s->casc_slot * (s->pair ? 2 : 1)));
+    chk(dmalloc(s, &s->casc[1], sizeof(float) * s->casc_slot * (s->pair ? 2 : 1)));
     chk(dmalloc(s, &s->part, sizeof(float2) * nb * nc));
     chk(dmalloc(s, &s->rates, sizeof(float) * 2 * nt * nc));
     chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
@@ -1631,6 +1680,10 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         re.wgt = (float)wm;
         re.acc = m > 0;
         const int32_t* eb_b = s->ebias + (size_t)b * kLB;
+        // this batch and the next of the same line: cascades >= 1 in one
+        // pass for both, cascade 0 per batch from its slot
+        const bool pair = s->pair && tr.kind == 0 && b + 1 < nb && s->batches[b + 1].trans == B.trans;
+        const int64_t slot = s->casc_slot;
         int cur = 0;
         const void* up = nullptr;
         for (int32_t i = P->n_casc - 1; i >= 0; --i) {
@@ -1643,9 +1696,8 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             const double4* dirs = P->dirs_dev + P->dir_off[i];
             float* outb = s->casc[cur];
             const void* upl = L.has_up ? up : nullptr;
-            rcx_nlte::Timed tm{tr.kind, 0, nullptr, nullptr};
-            if (s->timing) {
-                tm.steps = P->work.level_steps[i] / P->prm.n_incl * B.n;
+            auto timed_begin = [&](rcx_nlte::Timed& tm, int32_t n_wl) -> int32_t {
+                tm.steps = P->work.level_steps[i] / P->prm.n_incl * n_wl;
                 RCX_HIP_TRY(hipEventCreate(&tm.a));
                 hipError_t ee = hipEventCreate(&tm.b);
                 if (ee != hipSuccess) {
@@ -1653,9 +1705,68 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
                     return rcx::hip_fail(ee, "rcx_nlte timing");
                 }
                 (void)hipEventRecord(tm.a, st);
+                return RCX_OK;
+            };
+            if (pair && i == 0) {
+                // cascade 0 of each batch of the pair, reading its slot of
+                // cascade 1 and writing its own slot of outb
+                for (int32_t k = 0; k < 2; ++k) {
+                    const int32_t bk = b + k;
+                    const auto& Bk = s->batches[bk];
+                    const float* bck = s->bconst + bk * 5 * kLB;
+                    const int32_t* eb_k = s->ebias + (size_t)bk * kLB;
+                    LineOp lk = lop;
+                    lk.u_b = bck + 1 * kLB;
+                    RatesEpi rk = re;
+                    rk.part = s->part + bk * nc;
+                    rk.W = bck;
+                    rk.nu = bck + 2 * kLB;
+                    rk.alpha = bck + 3 * kLB;
+                    rk.U0c = bck + 4 * kLB;
+                    rk.out = outb + k * slot;
+                    rcx_nlte::Timed tm{tr.kind, 0, nullptr, nullptr};
+                    if (s->timing) {
+                        const int32_t rt = timed_begin(tm, Bk.n);
+                        if (rt != RCX_OK) return rt;
+                    }
+                    hipError_t e;
+                    if (s->f16) {
+                        const march::UpF16 u16{upl ? (const uint16_t*)upl + k * slot : nullptr, eb_k};
+                        e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lk, fop, rk, dirs, u16, st);
+                    } else {
+                        const march::UpF32 u32{upl ? (const float*)upl + k * slot : nullptr};
+                        e = launch_level_op(tr.kind, s->small_a, L, nx, nz, lk, fop, rk, dirs, u32, st);
+                    }
+                    if (s->timing) {
+                        (void)hipEventRecord(tm.b, st);
+                        s->pending.push_back(tm);
+                    }
+                    RCX_HIP_TRY(e);
+                    if (J) RCX_HIP_TRY(launch_j(outb + k * slot, J, Bk.lam0, Bk.n, nc, 4, (float)wm, m > 0, st));
+                }
+                up = nullptr;
+                break;
+            }
+            rcx_nlte::Timed tm{tr.kind, 0, nullptr, nullptr};
+            if (s->timing) {
+                const int32_t rt = timed_begin(tm, pair ? B.n + s->batches[b + 1].n : B.n);
+                if (rt != RCX_OK) return rt;
             }
             hipError_t e;
-            if (s->f16) {
+            if (pair) {
+                // cascades >= 1 of both batches (slot 1: the next batch)
+                if (s->f16) {
+                    march::UpF16 u16{(const uint16_t*)upl, eb_b};
+                    u16.stride = slot;
+                    e = launch_level_pair(s->small_a, L, nx, nz, lop, bc + 5 * kLB + 1 * kLB,
+                                          march::StoreF16Epi2{(uint16_t*)outb, slot, eb_b}, dirs, u16, st);
+                } else {
+                    march::UpF32 u32{(const float*)upl};
+                    u32.stride = slot;
+                    e = launch_level_pair(s->small_a, L, nx, nz, lop, bc + 5 * kLB + 1 * kLB,
+                                          march::StoreEpi2{outb, slot}, dirs, u32, st);
+                }
+            } else if (s->f16) {
                 // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
                 const march::UpF16 u16{(const uint16_t*)upl, eb_b};
                 if (i > 0) {
@@ -1681,6 +1792,10 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             RCX_HIP_TRY(e);
             up = outb;
             cur ^= 1;
+        }
+        if (pair) {
+            ++b;  // the next batch was marched with this one (and its J written)
+            continue;
         }
         if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, (float)wm, m > 0, st));
     }
