@@ -126,6 +126,23 @@ struct UpF16 {
     __device__ __forceinline__ float get(int64_t i, int w) const { return dec_h16(p[i + w * stride], w ? B2 : B); }
 };
 
+// W slots `stride` elements apart, slot w with the biases of batch b + w
+// (ebias_b[w * 16 + l]): the cascades of W batches of one line marched
+// together.
+// The biases are read where a merge needs them (entry i belongs to lane
+// i mod 16), so no register holds them during the march.
+template <int W>
+struct UpF16Slots {
+    const uint16_t* p;
+    const int32_t* ebias_b;  // [W][16]
+    int64_t stride = 0;
+    __device__ __forceinline__ void init(int) {}
+    __device__ __forceinline__ float get(int64_t i, int w) const
+    {
+        return dec_h16(p[i + w * stride], ebias_b[(int)(i & (kLB - 1)) + w * kLB] * 1024);
+    }
+};
+
 // Lane state shared by the kernels that march rows of rays.
 struct RowCtx {
     int lane, w, row, l;
@@ -1146,6 +1163,25 @@ struct StoreEpiSlots {
         if (ri.active) {
 #pragma unroll
             for (int w = 0; w < W; ++w) out[w * stride + ri.ray * kLB + l] = I[w];
+        }
+    }
+};
+
+// 16-bit codes of W slots `stride` elements apart, slot w with the biases
+// of batch b + w (ebias_b[w * 16 + l]).
+template <int W>
+struct StoreF16EpiSlots {
+    uint16_t* out;
+    int64_t stride;
+    const int32_t* ebias_b;  // [W][16]
+    __device__ __forceinline__ void init(int) {}
+    template <class Op>
+    __device__ __forceinline__ void finish_slots(const RayInfo& ri, int l, int, const float (&I)[W], const Op&)
+    {
+        if (ri.active) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                out[w * stride + ri.ray * kLB + l] = enc_h16(I[w], ebias_b[l + w * kLB] * 1024);
         }
     }
 };

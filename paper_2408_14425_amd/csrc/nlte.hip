@@ -525,26 +525,27 @@ __global__ void k_zero_u32n(unsigned int* p, int32_t n)
 // profile: the expansion in a (voigt_small_a, record z = a) or the compact
 // table in (a, x) (voigt_compact, record z = a / da).
 //
-// kPair: each lane marches wavelength l of two batches of the same line (u_b
-// and u_b2): one walk and one staged record per segment serve both, and the
-// cascades hold two slots (StoreEpi2 / StoreF16Epi2).
-template <bool kSmallA, bool kPair = false>
+// kG > 1: each lane marches wavelength l of kG consecutive batches of the
+// same line (slot w's velocity offsets at u_b + w u_stride): one walk and one
+// staged record per segment serve all of them, and the cascades hold kG
+// slots (StoreEpiSlots / StoreF16EpiSlots).
+template <bool kSmallA, int kG = 1>
 struct LineOpT {
     const float4* rec;  // [ncell]
     const float2* vel;  // [ncell]
     const float2* tabc; // profile table [n_a][kNxc] (global; copied to LDS)
     int32_t n_a;
     const float* u_b;   // [16] velocity offsets of the batch's wavelengths [m/s]
-    const float* u_b2 = nullptr;  // kPair: [16] of the second batch
+    int32_t u_stride = 0;  // kG > 1: elements from one slot's offsets to the next's
     uint32_t ncell;
     float da_sqrtpi;    // damping step of the table / sqrt(pi)
-    float u, u2, wx, wz;
+    float u[kG], wx, wz;
     float vscale = 1.0f;  // velocity projection: sin(theta) of an inclined ray (Sec. 3.1), 1 in the plane
     const float2* tab;  // the LDS copy
     // the cell record and velocity are the same for all wavelength lanes;
     // with kSmallA the entry also carries {a^2, 2a / sqrt(pi)} and holds
     // (w . v) / v_th in place of the velocity's x component
-    static constexpr int kW = kPair ? 2 : 1;
+    static constexpr int kW = kG;
     static constexpr bool kStaged = true;
     struct Stage {
         float4 r;
@@ -584,8 +585,8 @@ struct LineOpT {
     }
     __device__ __forceinline__ void init(int l)
     {
-        u = u_b[l];
-        u2 = kPair ? u_b2[l] : u;
+#pragma unroll
+        for (int w = 0; w < kG; ++w) u[w] = u_b[l + w * u_stride];
     }
     __device__ __forceinline__ void begin_ray(double dwx, double dwz)
     {
@@ -595,7 +596,7 @@ struct LineOpT {
     // H(a, |x|), x = (u + w . v) / v_th, from a record and a velocity
     __device__ __forceinline__ float profile(const float4& r, const float2& v) const
     {
-        const float ax = fabsf((u + wx * v.x + wz * v.y) * r.w);
+        const float ax = fabsf((u[0] + wx * v.x + wz * v.y) * r.w);
         if constexpr (kSmallA) return voigt_small_a(tab, r.z * r.z, (float)(2.0 / sqrt(kPi)) * r.z, ax);
         return voigt_compact(tab, r.z, r.z * da_sqrtpi, ax);
     }
@@ -608,13 +609,12 @@ struct LineOpT {
         const float ax = fabsf((uw + wx * raw.v.x + wz * raw.v.y) * raw.r.w);
         return make_float2(raw.r.x * voigt_compact(tab, raw.r.z, raw.r.z * da_sqrtpi, ax), raw.r.y);
     }
-    // {chi, S} of a group of 4 staged steps for slot w (the batch of u, or
-    // with kPair of u2). With the expansion in a, the series beyond kXTab is
-    // evaluated only when a lane of the wavefront needs it (the line-core
-    // batches never do).
+    // {chi, S} of a group of 4 staged steps for slot w (the batch of u[w]).
+    // With the expansion in a, the series beyond kXTab is evaluated only when
+    // a lane of the wavefront needs it (the line-core batches never do).
     __device__ __forceinline__ void resolve4(const Raw (&raw)[4], float2 (&f)[4], int w) const
     {
-        const float uw = w == 0 ? u : u2;
+        const float uw = u[w];
         if constexpr (kSmallA) {
             float ax[4];
 #pragma unroll
@@ -1035,10 +1035,10 @@ struct rcx_nlte {
     float4* epi_rec = nullptr;
     float2* Fcont = nullptr;
     float* casc[2] = {nullptr, nullptr};
-    // two consecutive batches of one line march their cascades >= 1 in one
-    // pass (LineOpT kPair); the cascade buffers then hold two slots of
-    // casc_slot elements
-    bool pair = false;
+    // up to `group` consecutive batches of one line march their cascades
+    // >= 1 in one pass (LineOpT<_, G>, G = 4 or 2); the cascade buffers then
+    // hold `group` slots of casc_slot elements
+    int32_t group = 1;
     int64_t casc_slot = 0;
     bool f16 = false;                 // cascades >= 1 stored as scaled FP16
     unsigned int* smax = nullptr;     // [n_batch][16] max S (float bits)
@@ -1148,11 +1148,12 @@ hipError_t launch_level_op(int32_t kind, bool small_a, const LevelDesc& L, int32
     return launch_level(L, nx, nz, lop, epi, dirs, up, st);
 }
 
-// Cascades >= 1 of two batches of one line in one launch (LineOpT kPair:
-// u_b2 the second batch's velocity offsets; two-slot epilogue and reader).
-template <class Epi, class Up>
-hipError_t launch_level_pair(bool small_a, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
-                             const float* u_b2, const Epi& epi, const double4* dirs, const Up& up, hipStream_t st)
+// Cascades >= 1 of G batches of one line in one launch (LineOpT<_, G>:
+// slot w's velocity offsets u_stride elements after slot w - 1's; G-slot
+// epilogue and reader).
+template <int G, class Epi, class Up>
+hipError_t launch_level_group(bool small_a, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
+                              int32_t u_stride, const Epi& epi, const double4* dirs, const Up& up, hipStream_t st)
 {
     auto fill = [&](auto& op) {
         op.rec = lop.rec;
@@ -1160,19 +1161,41 @@ hipError_t launch_level_pair(bool small_a, const LevelDesc& L, int32_t nx, int32
         op.tabc = lop.tabc;
         op.n_a = lop.n_a;
         op.u_b = lop.u_b;
-        op.u_b2 = u_b2;
+        op.u_stride = u_stride;
         op.ncell = lop.ncell;
         op.da_sqrtpi = lop.da_sqrtpi;
         op.vscale = lop.vscale;
     };
     if (small_a) {
-        LineOpT<true, true> pop{};
-        fill(pop);
-        return launch_level(L, nx, nz, pop, epi, dirs, up, st);
+        LineOpT<true, G> gop{};
+        fill(gop);
+        return launch_level(L, nx, nz, gop, epi, dirs, up, st);
     }
-    LineOpT<false, true> pop{};
-    fill(pop);
-    return launch_level(L, nx, nz, pop, epi, dirs, up, st);
+    LineOpT<false, G> gop{};
+    fill(gop);
+    return launch_level(L, nx, nz, gop, epi, dirs, up, st);
+}
+
+template <int G>
+hipError_t launch_group_casc(bool f16, bool small_a, const LevelDesc& L, int32_t nx, int32_t nz, const LineOp& lop,
+                             int32_t u_stride, void* outb, const void* upl, int64_t slot, const int32_t* eb_b,
+                             const double4* dirs, hipStream_t st)
+{
+    if (f16) {
+        // 16-bit cascades march at most 2 batches together (4 spill registers)
+        if constexpr (G > 2) {
+            return hipErrorInvalidValue;
+        } else {
+            march::UpF16Slots<G> u16{(const uint16_t*)upl, eb_b};
+            u16.stride = slot;
+            return launch_level_group<G>(small_a, L, nx, nz, lop, u_stride,
+                                         march::StoreF16EpiSlots<G>{(uint16_t*)outb, slot, eb_b}, dirs, u16, st);
+        }
+    }
+    march::UpF32 u32{(const float*)upl};
+    u32.stride = slot;
+    return launch_level_group<G>(small_a, L, nx, nz, lop, u_stride, march::StoreEpiSlots<G>{(float*)outb, slot},
+                                 dirs, u32, st);
 }
 
 // Emergent intensity along a beam of parallel long characteristics (Sec.
@@ -1228,6 +1251,20 @@ hipError_t launch_se(rcx_nlte* s, const float* rates, double* pops, hipStream_t 
 }  // namespace
 
 extern "C" {
+
+// Batches b .. b + G - 1 march their cascades >= 1 together: the largest G
+// in {4, 2} (at most gmax) whose batches all belong to batch b's line, else 1.
+static int32_t line_group(const rcx_nlte* s, int32_t b, int32_t gmax)
+{
+    const int32_t nb = (int32_t)s->batches.size();
+    if (s->atom.t[s->batches[b].trans].kind != 0) return 1;
+    for (int32_t G = gmax; G >= 2; G /= 2) {
+        bool same = b + G <= nb;
+        for (int32_t k = 1; same && k < G; ++k) same = s->batches[b + k].trans == s->batches[b].trans;
+        if (same) return G;
+    }
+    return 1;
+}
 
 int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* atom, int32_t n_wave,
                         const double* lambda_nm_host, const int32_t* trans_host, const double* dnu_host, rcx_nlte** out)
@@ -1390,13 +1427,12 @@ int32_t rcx_nlte_create(const rcx_grid* g, const rcx_params* p, const rcx_atom* 
     chk(dmalloc(s, &s->line_rec, sizeof(float4) * std::max(1, A.n_lines) * nc));
     chk(dmalloc(s, &s->epi_rec, sizeof(float4) * nt * nc));
     chk(dmalloc(s, &s->Fcont, sizeof(float2) * std::max(1, s->n_cont_batches) * nc * kLB));
-    // line pairs need a second slot (and at least one cascade above 0)
-    for (int32_t b = 0; b + 1 < nb; ++b)
-        if (A.t[s->batches[b].trans].kind == 0 && s->batches[b + 1].trans == s->batches[b].trans) s->pair = true;
-    s->pair = s->pair && s->plan->n_casc >= 2 && !(s->plan->top_skipped && s->plan->n_casc == 2);
+    // line groups need a slot per batch (and at least one cascade above 0)
+    if (s->plan->n_casc >= 2 && !(s->plan->top_skipped && s->plan->n_casc == 2))
+        for (int32_t b = 0; b < nb; ++b) s->group = std::max(s->group, line_group(s, b, 4));
     s->casc_slot = max_entries * kLB;
-    chk(dmalloc(s, &s->casc[0], sizeof(float) * s->casc_slot * (s->pair ? 2 : 1)));
-    chk(dmalloc(s, &s->casc[1], sizeof(float) * s->casc_slot * (s->pair ? 2 : 1)));
+    chk(dmalloc(s, &s->casc[0], sizeof(float) * s->casc_slot * s->group));
+    chk(dmalloc(s, &s->casc[1], sizeof(float) * s->casc_slot * s->group));
     chk(dmalloc(s, &s->part, sizeof(float2) * nb * nc));
     chk(dmalloc(s, &s->rates, sizeof(float) * 2 * nt * nc));
     chk(dmalloc(s, &s->d_max, sizeof(unsigned long long)));
@@ -1680,9 +1716,9 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         re.wgt = (float)wm;
         re.acc = m > 0;
         const int32_t* eb_b = s->ebias + (size_t)b * kLB;
-        // this batch and the next of the same line: cascades >= 1 in one
-        // pass for both, cascade 0 per batch from its slot
-        const bool pair = s->pair && tr.kind == 0 && b + 1 < nb && s->batches[b + 1].trans == B.trans;
+        // this batch and the next G - 1 of the same line: cascades >= 1 in
+        // one pass for all, cascade 0 per batch from its slot
+        const int32_t G = s->group > 1 ? line_group(s, b, s->f16 ? std::min(s->group, 2) : s->group) : 1;
         const int64_t slot = s->casc_slot;
         int cur = 0;
         const void* up = nullptr;
@@ -1707,10 +1743,10 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
                 (void)hipEventRecord(tm.a, st);
                 return RCX_OK;
             };
-            if (pair && i == 0) {
-                // cascade 0 of each batch of the pair, reading its slot of
+            if (G > 1 && i == 0) {
+                // cascade 0 of each batch of the group, reading its slot of
                 // cascade 1 and writing its own slot of outb
-                for (int32_t k = 0; k < 2; ++k) {
+                for (int32_t k = 0; k < G; ++k) {
                     const int32_t bk = b + k;
                     const auto& Bk = s->batches[bk];
                     const float* bck = s->bconst + bk * 5 * kLB;
@@ -1749,23 +1785,17 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             }
             rcx_nlte::Timed tm{tr.kind, 0, nullptr, nullptr};
             if (s->timing) {
-                const int32_t rt = timed_begin(tm, pair ? B.n + s->batches[b + 1].n : B.n);
+                int32_t n_wl = 0;
+                for (int32_t k = 0; k < G; ++k) n_wl += s->batches[b + k].n;
+                const int32_t rt = timed_begin(tm, n_wl);
                 if (rt != RCX_OK) return rt;
             }
             hipError_t e;
-            if (pair) {
-                // cascades >= 1 of both batches (slot 1: the next batch)
-                if (s->f16) {
-                    march::UpF16 u16{(const uint16_t*)upl, eb_b};
-                    u16.stride = slot;
-                    e = launch_level_pair(s->small_a, L, nx, nz, lop, bc + 5 * kLB + 1 * kLB,
-                                          march::StoreF16Epi2{(uint16_t*)outb, slot, eb_b}, dirs, u16, st);
-                } else {
-                    march::UpF32 u32{(const float*)upl};
-                    u32.stride = slot;
-                    e = launch_level_pair(s->small_a, L, nx, nz, lop, bc + 5 * kLB + 1 * kLB,
-                                          march::StoreEpi2{outb, slot}, dirs, u32, st);
-                }
+            if (G == 4) {
+                // cascades >= 1 of the 4 batches (slot w: batch b + w)
+                e = launch_group_casc<4>(s->f16, s->small_a, L, nx, nz, lop, 5 * kLB, outb, upl, slot, eb_b, dirs, st);
+            } else if (G == 2) {
+                e = launch_group_casc<2>(s->f16, s->small_a, L, nx, nz, lop, 5 * kLB, outb, upl, slot, eb_b, dirs, st);
             } else if (s->f16) {
                 // cascades >= 1 stored in FP16; cascade 0 (rates, J) in FP32
                 const march::UpF16 u16{(const uint16_t*)upl, eb_b};
@@ -1793,8 +1823,8 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
             up = outb;
             cur ^= 1;
         }
-        if (pair) {
-            ++b;  // the next batch was marched with this one (and its J written)
+        if (G > 1) {
+            b += G - 1;  // the group's batches were marched with this one (and their J written)
             continue;
         }
         if (J) RCX_HIP_TRY(launch_j((const float*)up, J, B.lam0, B.n, nc, 4, (float)wm, m > 0, st));

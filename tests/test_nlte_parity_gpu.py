@@ -318,8 +318,8 @@ def test_inclinations(case32, n_incl):
 def test_march_timing_counts(case32):
     """Kernel timing of the non-LTE march: one formal solution with 2
     inclinations records one launch per (batch, marched cascade,
-    inclination), except that two batches of one line share their launches
-    of the cascades above 0; the cell steps x wavelengths of the line and
+    inclination), except that 4 (or 2) consecutive batches of one line share
+    their launches of the cascades above 0; the cell steps x wavelengths of the line and
     continuum launches equal the plan's dense per-cascade counts times the
     batches' wavelengths; the records are dropped after reading."""
     torch = _torch()
@@ -349,13 +349,16 @@ def test_march_timing_counts(case32):
     n_lw = int(counts[:n_lines].sum())
     n_cont = int(counts[n_lines:].sum())
     assert line_batches > 0 and cont_batches > 0
-    # a line's batches march in pairs (when a cascade above 0 is marched):
-    # a pair takes one launch per cascade above 0 and one per batch at 0
+    # a line's batches march in groups of 4, then 2 (when a cascade above 0
+    # is marched): a group of G takes one launch per cascade above 0 and one
+    # per batch at 0
     line_launches = 0
     for c in counts[:n_lines]:
-        nb = -(-int(c) // 16)
-        pairs = nb // 2 if marched >= 2 else 0
-        line_launches += pairs * (marched + 1) + (nb - 2 * pairs) * marched
+        nb, b = -(-int(c) // 16), 0
+        while b < nb:
+            G = next(g for g in (4, 2, 1) if nb - b >= g) if marched >= 2 else 1
+            line_launches += (marched - 1 + G) if G > 1 else marched
+            b += G
     assert t["line"][1] == line_launches * 2
     assert t["continuum"][1] == cont_batches * marched * 2
     assert t["line"][2] == n_lw * w.cell_steps * 2
