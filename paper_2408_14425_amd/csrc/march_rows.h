@@ -56,16 +56,18 @@ __device__ __forceinline__ unsigned xcd_block_chunked(unsigned b, unsigned nb, c
     return q * c8 + x * D.chunk.d + (slot - q * D.chunk.d);
 }
 
-// 1 - 2^{-y} for y >= 0 (y = optical depth in log2 units) without
-// cancellation: with x = y ln2, the series x - x^2/2 + x^3/6 below x = 1/64
-// (truncation < 2e-7 relative), the direct form above (< 4e-6 relative).
-__device__ __forceinline__ float one_minus_exp2_neg(float y, float e)
+// 1 - 2^{-y} (e = 2^{-y}) as the smaller of the three-term series (an upper
+// bound of it for every y >= 0: the remainder's derivative is non-negative)
+// and (1 + 2^-22) - 2^{-y} (the offset keeps the cancelling form above the
+// series where the series is the better one), with no compare and select:
+// at most 6e-6 relative, 0 at y = 0.
+__device__ __forceinline__ float one_minus_exp2_neg_min(float y, float e)
 {
     constexpr float c1 = 0.6931471805599453f;  // ln 2
     constexpr float c2 = 0.2402265069591007f;  // (ln 2)^2 / 2
     constexpr float c3 = 0.0555041086648216f;  // (ln 2)^3 / 6
     const float ser = y * (c1 - y * (c2 - y * c3));
-    return y < (1.0f / 64.0f) / c1 ? ser : 1.0f - e;
+    return fminf(ser, (1.0f + 0x1p-22f) - e);
 }
 
 __device__ __forceinline__ void wave_sync()
@@ -176,7 +178,7 @@ __device__ __forceinline__ void step(float2 f, float ds, float& I, float& T)
 {
     const float y = f.x * ds;
     const float e = __builtin_amdgcn_exp2f(-y);
-    I = fmaf(T * f.y, one_minus_exp2_neg(y, e), I);
+    I = fmaf(T * f.y, one_minus_exp2_neg_min(y, e), I);
     T *= e;
 }
 
@@ -193,20 +195,12 @@ __device__ __forceinline__ double plane_t(double X, double k, double f, double i
 }
 
 // A step of known optical depth y = f.x (log2 units), for the staged
-// marches, whose time goes to VALU issue: 1 - 2^{-y} as the smaller of the
-// three-term series (an upper bound of it for every y >= 0: the remainder's
-// derivative is non-negative) and (1 + 2^-22) - 2^{-y} (the offset keeps the
-// cancelling form above the series where the series is the better one), with
-// no compare and select: at most 6e-6 relative, 0 at y = 0.
+// marches (the segment length is folded into their records).
 __device__ __forceinline__ void step_unit(float2 f, float& I, float& T)
 {
-    constexpr float c1 = 0.6931471805599453f;  // ln 2
-    constexpr float c2 = 0.2402265069591007f;  // (ln 2)^2 / 2
-    constexpr float c3 = 0.0555041086648216f;  // (ln 2)^3 / 6
     const float y = f.x;
     const float e = __builtin_amdgcn_exp2f(-y);
-    const float ser = y * (c1 - y * (c2 - y * c3));
-    I = fmaf(T * f.y, fminf(ser, (1.0f + 0x1p-22f) - e), I);
+    I = fmaf(T * f.y, one_minus_exp2_neg_min(y, e), I);
     T *= e;
 }
 
