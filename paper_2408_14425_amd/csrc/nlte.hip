@@ -1182,15 +1182,10 @@ hipError_t launch_group_casc(bool f16, bool small_a, const LevelDesc& L, int32_t
                              const double4* dirs, hipStream_t st)
 {
     if (f16) {
-        // 16-bit cascades march at most 2 batches together (4 spill registers)
-        if constexpr (G > 2) {
-            return hipErrorInvalidValue;
-        } else {
-            march::UpF16Slots<G> u16{(const uint16_t*)upl, eb_b};
-            u16.stride = slot;
-            return launch_level_group<G>(small_a, L, nx, nz, lop, u_stride,
-                                         march::StoreF16EpiSlots<G>{(uint16_t*)outb, slot, eb_b}, dirs, u16, st);
-        }
+        march::UpF16Slots<G> u16{(const uint16_t*)upl, eb_b};
+        u16.stride = slot;
+        return launch_level_group<G>(small_a, L, nx, nz, lop, u_stride,
+                                     march::StoreF16EpiSlots<G>{(uint16_t*)outb, slot, eb_b}, dirs, u16, st);
     }
     march::UpF32 u32{(const float*)upl};
     u32.stride = slot;
@@ -1718,7 +1713,7 @@ static int32_t formal_solve_rates(rcx_nlte* s, const double* pops, float* rates,
         const int32_t* eb_b = s->ebias + (size_t)b * kLB;
         // this batch and the next G - 1 of the same line: cascades >= 1 in
         // one pass for all, cascade 0 per batch from its slot
-        const int32_t G = s->group > 1 ? line_group(s, b, s->f16 ? std::min(s->group, 2) : s->group) : 1;
+        const int32_t G = s->group > 1 ? line_group(s, b, s->group) : 1;
         const int64_t slot = s->casc_slot;
         int cur = 0;
         const void* up = nullptr;
