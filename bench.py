@@ -438,6 +438,31 @@ def nlte_profile(args):
             "iterations": it, "s_per_iteration": dt / max(it, 1), "last_change": ch, "roofline": roof}
 
 
+def nlte_inclined(args, n_incl: int = 8, iters: int = 2):
+    """The non-LTE iteration with the paper's 8 Gauss-Radau inclinations per
+    flatland ray (Sec. 3.1; Sec. 4.5 iterates with 8): one pass per
+    inclination, velocities projected; one untimed iteration from LTE, then
+    `iters` timed, and the march rooflines of one more (default launch
+    orders)."""
+    import torch
+
+    from paper_2408_14425_amd import rcx, workloads
+    inp = workloads.nlte_atmosphere(args.nlte_n, seed=args.nlte_seed, n_line=64, n_cont=32)
+    s = rcx.Nlte(inp, n_incl=n_incl)
+    p = s.lte()
+    s.iterate(p, 1, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, ch = s.iterate(p, iters, 0.0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    roof = line_march_roofline(s, 1)
+    s.close()
+    return {"workload": f"non-LTE iteration, {inp.nx}x{inp.nz}, {inp.n_wave} wavelengths, seed {args.nlte_seed}, "
+                        f"{n_incl} inclinations", "n_incl": n_incl,
+            "iterations": it, "s_per_iteration": dt / max(it, 1), "last_change": ch, "roofline": roof}
+
+
 def mlp_profile(args):
     """Training steps and forward passes of the warm-start network
     (6 -> 4 x 128 -> 4, BF16 MFMA) on seeded data, batch 65536: the command
@@ -758,6 +783,7 @@ def main():
     }
     if not args.no_nlte:
         out["nonlte"] = nlte_solves(args)
+        out["nonlte_inclined"] = nlte_inclined(args)
         # the warm-start network's training step (20 steps, batch 65536)
         args.mlp_profile = 20
         out["mlp"] = mlp_profile(args)

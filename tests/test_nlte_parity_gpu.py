@@ -221,6 +221,53 @@ def test_two_continuum_batches():
     assert relp.max() < 1e-3
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_line_batch_groups(storage):
+    """112 wavelengths per line: 7 batches, which the march groups as 4 + 2
+    + 1 (the 4 and the 2 share their cascades above 0, each batch takes its
+    own cascade 0). One launch per group and marched cascade above 0 and one
+    per batch at cascade 0; J to 1e-4 (16-bit cascades 1e-3), the rates to
+    the same bar of their magnitude sums, the populations after one
+    iteration to 1e-3."""
+    torch = _torch()
+    from oracle import nlte
+    from paper_2408_14425_amd import rcx
+    inp = W.nlte_atmosphere(32, seed=4, n_line=112, n_cont=16)
+    P = nlte.Problem(inp)
+    print(f"[gpu] nlte line batch groups {inp.name} {storage}", flush=True)
+    s = rcx.Nlte(inp, storage=rcx.RCX_STORE_F32 if storage == "f32" else rcx.RCX_STORE_F16_SCALED)
+    pops = s.lte()
+    s.set_timing(True)
+    rates, J = s.formal_solve_rates(pops, want_J=True)
+    torch.cuda.synchronize()
+    t = s.get_timing()
+    s.set_timing(False)
+    Jg = J.cpu().numpy().reshape(inp.n_wave, -1).astype(np.float64)
+    rg = rates.cpu().numpy()
+    s.iterate(pops, 1, 0.0)
+    pg = pops.cpu().numpy().reshape(P.atom.n_levels, -1)
+    s.close()
+    plan = rcx.Plan(inp.nx, inp.nz, 1)
+    w = plan.work()
+    plan.close()
+    marched = w.n_cascades - (1 if w.top_skipped else 0)
+    assert marched >= 2
+    n_lines = len(inp.atom["lines"])
+    assert list(np.bincount(inp.trans)[:n_lines]) == [112] * n_lines
+    assert t["line"][1] == n_lines * ((marched - 1 + 4) + (marched - 1 + 2) + marched)
+    Jo, I0, chi_loc, H_loc, _ = P.formal_solve(P.lte)
+    relJ = np.abs(Jg - Jo) / np.abs(Jo)
+    eu, ed = _rates_vs_oracle(rg, P, P.lte, I0, chi_loc, H_loc)
+    po, _ = P.iterate(P.lte.copy(), 1)
+    relp = np.abs(pg - po) / np.abs(po)
+    print(f"line batch groups {storage}: J max rel {relJ.max():.3e}, rates {eu:.3e} / {ed:.3e}, "
+          f"pops {relp.max():.3e}")
+    tol = 1e-4 if storage == "f32" else 1e-3
+    assert relJ.max() < tol
+    assert eu < tol and ed < tol
+    assert relp.max() < 1e-3
+
+
 def test_converged_128_at_oracle_iteration_count():
     """The 128^2 atmosphere (6 cascades) iterated for the oracle's count K
     (stored: the oracle needs minutes for it) agrees with the oracle's
