@@ -254,13 +254,12 @@ __device__ __forceinline__ float voigt_small_a(const float2* __restrict__ gtab, 
     return fmaf(e, fmaf(a2, fmaf(-2.0f, x2, 1.0f), 1.0f), -ca * g);
 }
 
-// rx H(a, x) from a staged record's coefficients rx, rx a^2 and rx 2a/sqrt(pi)
-// (rx = the step's opacity scale times its length): e^{-x^2} (rx + rx a^2 (1
-// - 2 x^2)) - rx (2a / sqrt(pi)) g(x), the products with rx taken once per
-// segment when the record is staged.
+// rx H(a, x) from a staged record's coefficients A = rx (1 + a^2), B = -2 rx
+// a^2 and C = rx 2a/sqrt(pi) (rx = the step's opacity scale times its
+// length): e^{-x^2} (A + B x^2) - C g(x), the products with rx taken once
+// per segment when the record is staged.
 template <bool kCore = false>
-__device__ __forceinline__ float voigt_small_a_rx(const float2* __restrict__ gtab, float rx, float rxa2, float rxca,
-                                                  float ax)
+__device__ __forceinline__ float voigt_small_a_rx(const float2* __restrict__ gtab, float A, float B, float C, float ax)
 {
     const float x2 = ax * ax;
     const float e = __builtin_amdgcn_exp2f(-x2 * march::kLog2e);
@@ -268,7 +267,7 @@ __device__ __forceinline__ float voigt_small_a_rx(const float2* __restrict__ gta
     const float2 q = gtab[(int)fx];
     const float gt = fmaf(__builtin_amdgcn_fractf(fx), q.y, q.x);
     const float g = (!kCore && ax >= (float)kXTab) ? -0.5f * voigt_wing_series(__builtin_amdgcn_rcpf(x2)) : gt;
-    return fmaf(e, fmaf(rxa2, fmaf(-2.0f, x2, 1.0f), rx), -rxca * g);
+    return fmaf(e, fmaf(B, x2, A), -C * g);
 }
 
 // g(x) = 1 - 2x F(x), with L(0, x) = (2 / sqrt(pi)) F(x) from the Fourier integral.
@@ -577,9 +576,15 @@ struct LineOpT {
         st.r = in.r;
         st.r.x = in.r.x * ds;
         st.v = in.v;
-        // with the expansion in a: {rx a^2, rx 2a / sqrt(pi)} (voigt_small_a_rx)
-        st.p = kSmallA ? make_float2(st.r.x * (in.r.z * in.r.z), st.r.x * ((float)(2.0 / sqrt(kPi)) * in.r.z))
-                       : make_float2(0.0f, 0.0f);
+        // with the expansion in a: r.x = rx (1 + a^2), p = {-2 rx a^2, rx 2a /
+        // sqrt(pi)} (voigt_small_a_rx)
+        if constexpr (kSmallA) {
+            const float rx = st.r.x, rxa2 = rx * (in.r.z * in.r.z);
+            st.r.x = rx + rxa2;
+            st.p = make_float2(-2.0f * rxa2, rx * ((float)(2.0 / sqrt(kPi)) * in.r.z));
+        } else {
+            st.p = make_float2(0.0f, 0.0f);
+        }
         if constexpr (kSmallA) st.v.x = (wx * in.v.x + wz * in.v.y) * in.r.w;  // (w . v) / v_th
         return st;
     }
