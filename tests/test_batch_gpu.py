@@ -1,4 +1,4 @@
-"""Batched persistent formal solve vs the FP64 oracle and vs per-atmosphere
+"""Batched formal solve (list-scheduled launches in a HIP graph) vs the FP64 oracle and vs per-atmosphere
 plan solves, through the C ABI.
 
 Tolerances: 1e-4 relative on J against the oracle (FP32 path, as for the
